@@ -1,0 +1,176 @@
+#!/usr/bin/env python3
+"""Benchmark of the BDDC-PCG solve on one MI355X.
+
+A step is one complete ``bddc_solve`` (Algorithm "BDDC method": coarse step,
+subdomain step, preconditioned CG on the interface correction to rtol 1e-8,
+post-correction of interiors) of a resident problem whose source already sits
+in device memory.  The setup (factorizations, face eigenproblems, coarse
+problem) runs once before the timed region and is reported separately.
+
+Prints one JSON line.  ``value`` is solves per second of the mixed form (FP32
+local operators inside the FP64 CG); the FP64 form is reported beside it.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "BDDC-PCG solve time & served solves/s (p50/p99), mixed vs FP64, rtol 1e-8"
+HBM_PEAK_GBS = 8000.0
+
+
+def make_workload(name):
+    import workloads as W
+    if name == "layer":
+        pr = W.layer_60x220(0, tau=10.0)
+        desc = {"workload": "SPE10-shaped channelised layer 60x220 (20x10 ft cells), 10x10-cell boxes (N=132), "
+                            "five-spot wells, adaptive tau=10, rtol 1e-8",
+                "n": list(pr.n), "subdomains": 132, "tau": 10.0, "rtol": 1e-8}
+    elif name == "square":
+        pr = W.unit_square_16(0)
+        pr.rtol = 1e-10
+        desc = {"workload": "unit square 16x16, GRF permeability, 4x4 boxes, no adaptivity, rtol 1e-10",
+                "n": list(pr.n), "subdomains": 16, "tau": None, "rtol": 1e-10}
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    return pr, desc
+
+
+def time_gpu(pr, precision, steps, warmup):
+    import torch
+    from paper_1901_02090_amd import Solver
+    t0 = time.perf_counter()
+    s = Solver(pr.n, pr.h, pr.perm, pr.cuts, tau=pr.tau, precision=precision)
+    setup_s = time.perf_counter() - t0
+    stream = torch.cuda.current_stream()
+    s.set_stream(stream.cuda_stream)
+    src = torch.tensor(pr.source, dtype=torch.float64, device="cuda")
+    flux = torch.empty(s.n_faces_all, dtype=torch.float64, device="cuda")
+    pres = torch.empty(s.n_cells, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    for _ in range(warmup):
+        s.solve_device(src.data_ptr(), pr.rtol, flux.data_ptr(), pres.data_ptr())
+    torch.cuda.synchronize()
+    lat = []
+    t_start = time.perf_counter()
+    for _ in range(steps):
+        a = time.perf_counter()
+        s.solve_device(src.data_ptr(), pr.rtol, flux.data_ptr(), pres.data_ptr())
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - a)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t_start
+    st = s.stats()
+    return s, dict(setup_s=setup_s, total_s=total, lat=np.array(lat), stats=st,
+                   flux=flux.cpu().numpy(), pres=pres.cpu().numpy())
+
+
+def cpu_baseline(pr, seconds):
+    """The oracle (plain CPU FP64 BDDC) solving the same problem, setup excluded."""
+    try:
+        from threadpoolctl import threadpool_limits
+    except Exception:  # pragma: no cover
+        threadpool_limits = None
+    from oracle import bddc as ob, rt0
+    ctx = threadpool_limits(1) if threadpool_limits else None
+    try:
+        g = rt0.Grid(pr.n, pr.h)
+        o = ob.BDDC(g, pr.perm, pr.cuts, tau=pr.tau)
+        n = 0
+        t0 = time.perf_counter()
+        while True:
+            o.solve(pr.source, rtol=pr.rtol, maxit=5000)
+            n += 1
+            el = time.perf_counter() - t0
+            if el >= seconds or n >= 1000:
+                break
+    finally:
+        if ctx is not None:
+            ctx.__exit__(None, None, None)
+    return {"value": n / el, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n} complete oracle solves of the same workload (setup excluded), {el:.1f} s, "
+                      f"one BLAS thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="layer", choices=["layer", "square"])
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("this benchmark runs on exactly one GPU: the solver is a single-GPU build "
+              "(--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+
+    from paper_1901_02090_amd.bddc import K_SCHUR_APPLY, K_PRECOND_APPLY
+    pr, desc = make_workload(args.workload)
+
+    s64, r64 = time_gpu(pr, "fp64", args.steps, args.warmup)
+    smx, rmx = time_gpu(pr, "mixed", args.steps, args.warmup)
+
+    # dominant kernel of an iteration: the local S^i products (FP64 in both forms)
+    reps = 200
+    ms_s, by_s = smx.time_kernel(K_SCHUR_APPLY, reps)
+    ms_t, by_t = smx.time_kernel(K_PRECOND_APPLY, reps)
+    kern = ("k_symv<double,false> (S^i apply, step H1)", ms_s, by_s)
+    if by_t / ms_t > by_s / ms_s and ms_t > ms_s:
+        kern = ("k_symv<float,true> (T^i and Psi^iT apply, steps H3-H4)", ms_t, by_t)
+    achieved = kern[2] / (kern[1] * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": kern[0],
+            "bytes_per_launch": kern[2], "avg_launch_us": kern[1] * 1e3}
+
+    st = rmx["stats"]
+    lat = rmx["lat"] * 1e3
+    value = args.steps / rmx["total_s"]
+    ref_u, ref_p = r64["flux"], r64["pres"]
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": rmx["total_s"] / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64+f32",
+        "data": "synthetic",
+        "config": desc,
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+        "iterations": st["it"],
+        "kappa": st["kappa"],
+        "n_coarse": st["n_coarse"],
+        "omega_tilde": st["omega_tilde"],
+        "setup_ms": rmx["setup_s"] * 1e3,
+        "pcg_ms": st["t_pcg_ms"],
+        "fp64": {"value": args.steps / r64["total_s"], "unit": "solves/s",
+                 "ms_per_step": r64["total_s"] / args.steps * 1e3,
+                 "latency_ms": {"p50": float(np.percentile(r64["lat"] * 1e3, 50)),
+                                "p99": float(np.percentile(r64["lat"] * 1e3, 99))},
+                 "iterations": r64["stats"]["it"], "setup_ms": r64["setup_s"] * 1e3},
+        "mixed_vs_fp64": {"flux_relerr": float(np.linalg.norm(rmx["flux"] - ref_u) / np.linalg.norm(ref_u)),
+                          "pressure_relerr": float(np.linalg.norm(rmx["pres"] - ref_p) / np.linalg.norm(ref_p))},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(pr, args.cpu_seconds)
+    smx.close()
+    s64.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

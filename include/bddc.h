@@ -1,0 +1,207 @@
+/*
+ * bddc.h -- C ABI of the MI355X (gfx950) adaptive BDDC solver for the mixed
+ * RT0/P0 Darcy problem.
+ *
+ * Method: B. Sousedik, "On adaptive BDDC for the flow in heterogeneous porous
+ * media".  The library solves the saddle-point system of Section 2
+ * (eqs. variational-1/2; matrix form eq. system, rescaled as eq. system-scaled)
+ * by Algorithm "BDDC method": a coarse solve (step 1), independent subdomain
+ * solves (step 2) and conjugate gradients on the divergence-free correction
+ * (step 3) preconditioned by Algorithm "BDDC preconditioner", with the flux
+ * coarse space enriched by Algorithm "Adaptive BDDC" (Section 4, eqs.
+ * eigenvalue-problem-local-matrix and constraints).
+ *
+ * Data conventions (all entry points):
+ *   - cells are numbered x-fastest: c = ix + nx*(iy + ny*iz);
+ *   - a flux unknown is the total normal flux through one grid face, oriented
+ *     along +x/+y/+z.  Faces are numbered direction by direction (all x-faces,
+ *     then y-faces, then z-faces); inside direction d the face with integer
+ *     position (i0,i1,i2), i_d in [0, n_d], has index i0 + s0*(i1 + s1*i2)
+ *     with s_e = n_e + (e == d).  Boundary faces are included and carry zero
+ *     flux (no-flow boundary, Section 2);
+ *   - the source is cell integrated (injection > 0) and must sum to zero
+ *     (eq. compatibility with g_E = 0).
+ *
+ * Ownership: input arrays are read during the call only.  The handle owns all
+ * device memory it allocates; it is released by bddc_destroy.  A handle is not
+ * thread safe; distinct handles are independent.
+ *
+ * Errors: every entry point returns BDDC_OK (0) or a negative code; the
+ * message of the last failure on the calling thread is bddc_last_error().
+ * No C++ exception crosses this interface.
+ */
+#ifndef BDDC_H
+#define BDDC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BDDC_OK          0
+#define BDDC_EINVAL     -1   /* bad shape, partition, permeability or source   */
+#define BDDC_ENOMEM     -2   /* device memory could not be obtained            */
+#define BDDC_ENOCONV    -3   /* max_it reached; outputs hold the last iterate  */
+#define BDDC_EBREAKDOWN -4   /* CG breakdown: p^T S p <= 0 or not finite       */
+#define BDDC_EFACTOR    -5   /* a local or coarse factorization lost definiteness */
+#define BDDC_EDEVICE    -6   /* HIP runtime error                              */
+
+/* precision of the preconditioner (the CG recurrences and S are always FP64) */
+#define BDDC_FP64  0
+#define BDDC_MIXED 1         /* T^i and Psi^i stored and streamed in FP32      */
+
+/* bddc_options.flags */
+#define BDDC_ALL_CONSTRAINED 1u  /* diagnostic: every interface dof is a coarse dof */
+
+/* bddc_solve flags */
+#define BDDC_DEVICE_PTRS 1u      /* rhs, flux and pressure are device pointers   */
+
+typedef struct bddc_problem *bddc_handle;
+
+/* Cartesian grid: dim 2 or 3, cells per axis n[0..dim), cell size h[0..dim). */
+typedef struct {
+  int32_t dim;
+  int32_t n[3];
+  double h[3];
+} bddc_grid;
+
+/* Box partition by axis cut planes: cuts[d] has nsub[d]+1 increasing entries,
+ * cuts[d][0] = 0 and cuts[d][nsub[d]] = n[d] (Section 6, regular partitions). */
+typedef struct {
+  int32_t nsub[3];
+  const int32_t *cuts[3];
+} bddc_partition;
+
+typedef struct {
+  int32_t precision;   /* BDDC_FP64 or BDDC_MIXED                   */
+  int32_t max_it;      /* CG iteration cap (<= 0: 10000)             */
+  uint32_t flags;      /* BDDC_ALL_CONSTRAINED (diagnostic)          */
+  int32_t reserved;
+} bddc_options;
+
+typedef struct {
+  int32_t it;               /* CG iterations of the last solve                  */
+  int32_t converged;        /* 1 if ||r|| <= rtol ||r_0||                        */
+  double relres;            /* final ||r|| / ||r_0||                             */
+  double kappa;             /* Lanczos condition estimate (Section 6)            */
+  double lambda_min, lambda_max;
+  double omega_tilde;       /* eq. indicator (0 without adaptivity)              */
+  int32_t n_adaptive;       /* adaptive flux constraints added                   */
+  int32_t n_coarse_flux;    /* flux coarse dofs                                  */
+  int32_t n_coarse;         /* n_c = flux coarse dofs + N (Table 1 column n_c)   */
+  int32_t n_sub;            /* N                                                 */
+  int32_t n_gamma;          /* interface flux dofs                               */
+  int32_t n_faces;          /* subdomain faces                                   */
+  int32_t precision;
+  int32_t reserved;
+  double t_setup_ms;        /* wall time of bddc_setup                           */
+  double t_solve_ms;        /* wall time of the last bddc_solve                  */
+  double t_pcg_ms;          /* device time of the CG loop of the last solve      */
+  double bytes_per_iter;    /* algorithmic HBM bytes of one CG iteration         */
+  double bytes_prec;        /* ... of which the preconditioner (steps H3-H7)     */
+  double device_bytes;      /* device memory held by the handle                  */
+} bddc_stats_t;
+
+/*
+ * Build everything the solve needs, on the device: local RT0 coefficients and
+ * the rescaling D (Section 5), the interface Schur complements S^i and the
+ * pressure operators of every subdomain, the pair eigenproblems and adaptive
+ * constraints of every face (Section 4, threshold tau; tau <= 0 or infinite
+ * disables adaptivity), the local coarse bases Psi^i, the substructure
+ * operators T^i and the coarse saddle point (Section 3, Algorithm "BDDC
+ * preconditioner").
+ *   g     : grid (dim 2|3, n[d] >= 1, h[d] > 0)
+ *   perm  : host array [n_cells][dim], diagonal permeability, finite and > 0
+ *   part  : box partition; every axis interval must be non-empty
+ *   opt   : NULL for defaults (FP64, max_it 10000)
+ *   out   : receives the handle on success
+ * Returns BDDC_EINVAL on bad input, BDDC_ENOMEM, BDDC_EFACTOR, BDDC_EDEVICE.
+ */
+int bddc_setup(const bddc_grid *g, const double *perm, const bddc_partition *part,
+               double tau, const bddc_options *opt, bddc_handle *out);
+
+/*
+ * Solve with the given source (Algorithm "BDDC method", steps 1-3 and the
+ * post-correction of interiors).  CG stops when ||r||_2 <= rtol ||r_0||_2.
+ *   rhs      : [n_cells] cell-integrated source, sum within 1e-12 sum|rhs| of 0
+ *   flux     : [n_faces_all] output, global orientation, boundary faces = 0
+ *   pressure : [n_cells] output, zero volume-weighted mean
+ *   flags    : BDDC_DEVICE_PTRS if the three arrays live in device memory
+ *              (then the call is asynchronous on the handle's stream except for
+ *              the convergence checks of the CG loop)
+ * Returns BDDC_OK, BDDC_ENOCONV (outputs hold the last iterate),
+ * BDDC_EBREAKDOWN, BDDC_EINVAL, BDDC_EDEVICE.
+ */
+int bddc_solve(bddc_handle h, const double *rhs, double rtol, double *flux, double *pressure,
+               uint32_t flags);
+
+/* Statistics of the setup and of the last solve. */
+int bddc_stats(bddc_handle h, bddc_stats_t *out);
+
+/* Run all later work of this handle on the given hipStream_t (NULL: the
+ * handle's own stream).  The stream must outlive its use by the handle. */
+int bddc_set_stream(bddc_handle h, void *hip_stream);
+
+/* Release all device memory of the handle.  NULL is accepted. */
+int bddc_destroy(bddc_handle h);
+
+/* Thread-local message describing the last non-zero return on this thread. */
+const char *bddc_last_error(void);
+
+/* ---- diagnostics used by the parity tests ----------------------------------
+ * Sizes of the problem: out[0..8) = {N, n_gamma, n_faces, n_coarse_flux,
+ * n_cells, n_faces_all, n_adaptive, max n_gamma^i}. */
+int bddc_sizes(bddc_handle h, int64_t *out);
+
+/* Copy an internal array to host memory (FP64 unless stated).
+ *   what = BDDC_X_SCHUR     : S^i of subdomain `index`, dense n x n column major
+ *          BDDC_X_FACE_EIG  : eigenvalues (descending) of face `index`'s
+ *                             reduced pair problem, n_F - 1 values
+ *          BDDC_X_FACE_K    : int32 adaptive row count of every face
+ *          BDDC_X_DSCALE    : rescaling d_i of every subdomain
+ *          BDDC_X_GAMMA     : int32 global face index of every interface dof
+ *          BDDC_X_OMEGA     : omega^F of every face
+ *          BDDC_X_T         : T^i of subdomain `index` (FP64 form), dense n x n
+ *          BDDC_X_PSI       : Psi^i of subdomain `index`, n_gamma^i x n_c^i column major
+ *          BDDC_X_COARSE_INV: flux-flux block of the coarse saddle-point
+ *                             inverse, n_coarse_flux^2 column major
+ * `cap` is the capacity of dst in elements; returns the element count or a
+ * negative code. */
+#define BDDC_X_SCHUR    1
+#define BDDC_X_FACE_EIG 2
+#define BDDC_X_FACE_K   3
+#define BDDC_X_DSCALE   4
+#define BDDC_X_GAMMA    5
+#define BDDC_X_OMEGA    6
+#define BDDC_X_T        7
+#define BDDC_X_PSI      8
+#define BDDC_X_COARSE_INV 9
+int64_t bddc_export(bddc_handle h, int32_t what, int32_t index, void *dst, int64_t cap);
+
+/* Apply one operator of the CG iteration to host vectors of the interface
+ * problem (eqs. corr-reduced-1/2):
+ *   which = BDDC_OP_SYSTEM : (y_u, y_p) = (S x_u + B_0^T x_p, B_0 x_u)
+ *           BDDC_OP_PRECOND: (y_u, y_p) = BDDC preconditioner applied to (x_u, 0)
+ * x_u, y_u: [n_gamma]; x_p, y_p: [N] (pressures in the rescaled variable). */
+#define BDDC_OP_SYSTEM  1
+#define BDDC_OP_PRECOND 2
+int bddc_apply(bddc_handle h, int32_t which, const double *x_u, const double *x_p, double *y_u,
+               double *y_p);
+
+/* Time one kernel of the CG iteration on the handle's stream with HIP events:
+ * `reps` back-to-back launches on the vectors of the last solve, bracketed by
+ * two events.  which = BDDC_K_SCHUR_APPLY (local S^i products, step H1) or
+ * BDDC_K_PRECOND_APPLY (local T^i and Psi^iT products, steps H3-H4).
+ * avg_ms receives the mean duration of one launch, bytes the algorithmic HBM
+ * bytes of one launch (operator entries read once, vectors gathered and
+ * written once).  Call after a bddc_solve. */
+#define BDDC_K_SCHUR_APPLY   1
+#define BDDC_K_PRECOND_APPLY 2
+int bddc_time_kernel(bddc_handle h, int32_t which, int32_t reps, double *avg_ms, double *bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BDDC_H */

@@ -1,0 +1,6 @@
+"""MI355X-native adaptive BDDC for RT0/P0 flow in heterogeneous porous media.
+
+The numerical work runs in the HIP library ``libbddc.so`` (C ABI declared in
+``include/bddc.h``); this package only marshals arguments.
+"""
+from .bddc import Solver, BddcError, load_library, LIB_PATH  # noqa: F401

@@ -1,0 +1,219 @@
+"""ctypes binding of the C ABI in include/bddc.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libbddc.so")
+
+BDDC_OK, BDDC_EINVAL, BDDC_ENOMEM, BDDC_ENOCONV, BDDC_EBREAKDOWN, BDDC_EFACTOR, BDDC_EDEVICE = 0, -1, -2, -3, -4, -5, -6
+BDDC_FP64, BDDC_MIXED = 0, 1
+BDDC_ALL_CONSTRAINED = 1
+BDDC_DEVICE_PTRS = 1
+X_SCHUR, X_FACE_EIG, X_FACE_K, X_DSCALE, X_GAMMA, X_OMEGA, X_T, X_PSI, X_COARSE_INV = 1, 2, 3, 4, 5, 6, 7, 8, 9
+OP_SYSTEM, OP_PRECOND = 1, 2
+
+EXPORTED = ["bddc_setup", "bddc_solve", "bddc_stats", "bddc_set_stream", "bddc_destroy", "bddc_last_error",
+            "bddc_sizes", "bddc_export", "bddc_apply", "bddc_time_kernel"]
+K_SCHUR_APPLY, K_PRECOND_APPLY = 1, 2
+
+
+class Grid(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("n", C.c_int32 * 3), ("h", C.c_double * 3)]
+
+
+class Partition(C.Structure):
+    _fields_ = [("nsub", C.c_int32 * 3), ("cuts", C.POINTER(C.c_int32) * 3)]
+
+
+class Options(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("max_it", C.c_int32), ("flags", C.c_uint32), ("reserved", C.c_int32)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("it", C.c_int32), ("converged", C.c_int32), ("relres", C.c_double), ("kappa", C.c_double),
+                ("lambda_min", C.c_double), ("lambda_max", C.c_double), ("omega_tilde", C.c_double),
+                ("n_adaptive", C.c_int32), ("n_coarse_flux", C.c_int32), ("n_coarse", C.c_int32),
+                ("n_sub", C.c_int32), ("n_gamma", C.c_int32), ("n_faces", C.c_int32), ("precision", C.c_int32),
+                ("reserved", C.c_int32), ("t_setup_ms", C.c_double), ("t_solve_ms", C.c_double),
+                ("t_pcg_ms", C.c_double), ("bytes_per_iter", C.c_double), ("bytes_prec", C.c_double),
+                ("device_bytes", C.c_double)]
+
+
+class BddcError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"bddc error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load_library(path=LIB_PATH):
+    """Load libbddc.so; raises if it was not built (there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FileNotFoundError(f"{path} is missing: build it with paper_1901_02090_amd.build.build()")
+    lib = C.CDLL(path)
+    P = C.c_void_p
+    dp = C.POINTER(C.c_double)
+    lib.bddc_setup.argtypes = [C.POINTER(Grid), dp, C.POINTER(Partition), C.c_double, C.POINTER(Options),
+                               C.POINTER(P)]
+    lib.bddc_setup.restype = C.c_int
+    lib.bddc_solve.argtypes = [P, P, C.c_double, P, P, C.c_uint32]
+    lib.bddc_solve.restype = C.c_int
+    lib.bddc_stats.argtypes = [P, C.POINTER(Stats)]
+    lib.bddc_stats.restype = C.c_int
+    lib.bddc_set_stream.argtypes = [P, P]
+    lib.bddc_set_stream.restype = C.c_int
+    lib.bddc_destroy.argtypes = [P]
+    lib.bddc_destroy.restype = C.c_int
+    lib.bddc_last_error.argtypes = []
+    lib.bddc_last_error.restype = C.c_char_p
+    lib.bddc_sizes.argtypes = [P, C.POINTER(C.c_int64)]
+    lib.bddc_sizes.restype = C.c_int
+    lib.bddc_export.argtypes = [P, C.c_int32, C.c_int32, P, C.c_int64]
+    lib.bddc_export.restype = C.c_int64
+    lib.bddc_apply.argtypes = [P, C.c_int32, dp, dp, dp, dp]
+    lib.bddc_apply.restype = C.c_int
+    lib.bddc_time_kernel.argtypes = [P, C.c_int32, C.c_int32, dp, dp]
+    lib.bddc_time_kernel.restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def _check(lib, rc, allow=()):
+    if rc != BDDC_OK and rc not in allow:
+        raise BddcError(rc, lib.bddc_last_error().decode())
+    return rc
+
+
+def _dptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+class Solver:
+    """One problem resident on the GPU: setup once, solve many right-hand sides."""
+
+    def __init__(self, n, h, perm, cuts, tau=math.inf, precision="fp64", max_it=10000, all_constrained=False):
+        self.lib = lib = load_library()
+        dim = len(n)
+        self.n = tuple(int(v) for v in n)
+        g = Grid(dim, (C.c_int32 * 3)(*(list(self.n) + [1] * (3 - dim))),
+                 (C.c_double * 3)(*(list(map(float, h)) + [1.0] * (3 - dim))))
+        self._cuts = [np.ascontiguousarray(c, dtype=np.int32) for c in cuts]
+        cp = (C.POINTER(C.c_int32) * 3)(*[c.ctypes.data_as(C.POINTER(C.c_int32)) for c in self._cuts] +
+                                        [C.POINTER(C.c_int32)()] * (3 - dim))
+        part = Partition((C.c_int32 * 3)(*([len(c) - 1 for c in self._cuts] + [1] * (3 - dim))), cp)
+        opt = Options(BDDC_MIXED if precision == "mixed" else BDDC_FP64, int(max_it),
+                      BDDC_ALL_CONSTRAINED if all_constrained else 0, 0)
+        perm = np.ascontiguousarray(perm, dtype=np.float64).reshape(-1)
+        t = float(tau) if (tau is not None and math.isfinite(tau)) else 0.0
+        self.h = C.c_void_p()
+        _check(lib, lib.bddc_setup(C.byref(g), _dptr(perm), C.byref(part), t, C.byref(opt), C.byref(self.h)))
+        sz = (C.c_int64 * 8)()
+        _check(lib, lib.bddc_sizes(self.h, sz))
+        (self.N, self.n_gamma, self.n_faces, self.n_coarse_flux, self.n_cells, self.n_faces_all,
+         self.n_adaptive, self.max_gamma_local) = [int(v) for v in sz]
+        self._sub_nG = [self.schur(i).shape[0] for i in range(self.N)] if self.N <= 4096 else None
+
+    # -- solves ----------------------------------------------------------------
+    def solve(self, source, rtol=1e-8, allow_noconv=False):
+        src = np.ascontiguousarray(source, dtype=np.float64)
+        flux = np.empty(self.n_faces_all)
+        pres = np.empty(self.n_cells)
+        rc = self.lib.bddc_solve(self.h, src.ctypes.data, float(rtol), flux.ctypes.data, pres.ctypes.data, 0)
+        _check(self.lib, rc, allow=(BDDC_ENOCONV,) if allow_noconv else ())
+        return flux, pres
+
+    def solve_device(self, src_ptr, rtol, flux_ptr, pres_ptr):
+        """Device-pointer solve (e.g. torch tensor data_ptr()); no host copies."""
+        rc = self.lib.bddc_solve(self.h, C.c_void_p(src_ptr), float(rtol), C.c_void_p(flux_ptr),
+                                 C.c_void_p(pres_ptr), BDDC_DEVICE_PTRS)
+        return _check(self.lib, rc, allow=(BDDC_ENOCONV,))
+
+    def set_stream(self, stream_ptr):
+        _check(self.lib, self.lib.bddc_set_stream(self.h, C.c_void_p(stream_ptr)))
+
+    def stats(self):
+        s = Stats()
+        _check(self.lib, self.lib.bddc_stats(self.h, C.byref(s)))
+        return {k: getattr(s, k) for k, _ in Stats._fields_}
+
+    # -- diagnostics -------------------------------------------------------------
+    def _export(self, what, index, count, dtype):
+        out = np.empty(max(count, 1), dtype=dtype)
+        rc = self.lib.bddc_export(self.h, what, index, out.ctypes.data, out.size)
+        if rc < 0:
+            _check(self.lib, int(rc))
+        return out[:rc]
+
+    def schur(self, i):
+        n = self._export(X_SCHUR, i, self.max_gamma_local ** 2, np.float64)
+        m = int(round(math.sqrt(len(n))))
+        return n.reshape(m, m, order="F")
+
+    def T(self, i):
+        n = self._export(X_T, i, self.max_gamma_local ** 2, np.float64)
+        m = int(round(math.sqrt(len(n))))
+        return n.reshape(m, m, order="F")
+
+    def psi(self, i):
+        out = self._export(X_PSI, i, self.max_gamma_local * 1024, np.float64)
+        nG = int(self._sub_nG[i])
+        return out.reshape(nG, -1, order="F")
+
+    def coarse_inverse(self):
+        n = self._export(X_COARSE_INV, 0, self.n_coarse_flux ** 2, np.float64)
+        return n.reshape(self.n_coarse_flux, self.n_coarse_flux, order="F")
+
+    def face_eigs(self, f):
+        return self._export(X_FACE_EIG, f, 4096, np.float64)
+
+    def face_k(self):
+        return self._export(X_FACE_K, 0, self.n_faces, np.int32)
+
+    def face_omega(self):
+        return self._export(X_OMEGA, 0, self.n_faces, np.float64)
+
+    def dscale(self):
+        return self._export(X_DSCALE, 0, self.N, np.float64)
+
+    def gamma(self):
+        return self._export(X_GAMMA, 0, self.n_gamma, np.int32)
+
+    def apply(self, which, xu, xp=None):
+        xu = np.ascontiguousarray(xu, dtype=np.float64)
+        xp = np.zeros(self.N) if xp is None else np.ascontiguousarray(xp, dtype=np.float64)
+        yu = np.empty(self.n_gamma)
+        yp = np.empty(self.N)
+        _check(self.lib, self.lib.bddc_apply(self.h, which, _dptr(xu), _dptr(xp), _dptr(yu), _dptr(yp)))
+        return yu, yp
+
+    def apply_system(self, xu, xp):
+        return self.apply(OP_SYSTEM, xu, xp)
+
+    def apply_precond(self, xu):
+        return self.apply(OP_PRECOND, xu)
+
+    def time_kernel(self, which, reps=50):
+        """Mean launch duration (ms) and algorithmic bytes of one CG kernel."""
+        ms, by = C.c_double(), C.c_double()
+        _check(self.lib, self.lib.bddc_time_kernel(self.h, which, int(reps), C.byref(ms), C.byref(by)))
+        return ms.value, by.value
+
+    def close(self):
+        if getattr(self, "h", None) and self.h.value:
+            self.lib.bddc_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

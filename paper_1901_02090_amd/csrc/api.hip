@@ -1,0 +1,895 @@
+// C ABI of the BDDC library: handle, setup orchestration, CG driver,
+// diagnostics.  All numerical work runs in the kernels of setup.hip and
+// solve.hip (compiled into this translation unit).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <string.h>
+
+#include <chrono>
+#include <cstdio>
+#include <new>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/bddc.h"
+#include "common.hpp"
+#include "layout.hpp"
+#include "setup.hip"
+#include "solve.hip"
+
+using namespace bddc;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct Error {
+  int code;
+  std::string msg;
+};
+
+#define HIPCHK(x)                                                                         \
+  do {                                                                                    \
+    hipError_t e_ = (x);                                                                  \
+    if (e_ != hipSuccess)                                                                 \
+      throw Error{e_ == hipErrorOutOfMemory ? BDDC_ENOMEM : BDDC_EDEVICE,                 \
+                  std::string(#x) + ": " + hipGetErrorString(e_)};                        \
+  } while (0)
+
+inline unsigned nblk(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+struct bddc_problem {
+  Layout L;
+  hipStream_t stream = nullptr;
+  hipStream_t own_stream = nullptr;
+  int precision = BDDC_FP64;
+  int max_it = 10000;
+  uint32_t flags = 0;
+  double tau = 0.0;
+  std::vector<void *> allocs;
+  double device_bytes = 0;
+
+  DevGeom g{};
+  DevCoarse cs{};
+  int ncu = 0, nk = 0, n_adaptive = 0;
+  double omega_tilde = 0.0;
+  std::vector<int> face_k;
+  std::vector<double> face_omega, face_eig;
+  std::vector<int64_t> eig_off_h;
+  std::vector<int64_t> pk_h, psi_off_h;
+  std::vector<int> sub_coff_h;
+
+  double *mcoef = nullptr, *dscale = nullptr;
+  double *Spk = nullptr, *T64 = nullptr, *Psi64 = nullptr, *Xmat = nullptr, *Kinv64 = nullptr;
+  float *T32 = nullptr, *Psi32 = nullptr, *Kinv32 = nullptr;
+  int64_t *d_pk = nullptr, *d_psi_off = nullptr, *d_Xoff = nullptr, *d_gamma_face = nullptr;
+
+  double *xu = nullptr, *ru = nullptr, *pu = nullptr, *zu = nullptr, *qu = nullptr, *u0 = nullptr, *uG = nullptr;
+  double *xp = nullptr, *pp = nullptr, *yloc = nullptr, *wloc = nullptr, *gloc = nullptr, *bc = nullptr,
+         *csol = nullptr;
+  double *part_g = nullptr, *part_r = nullptr, *part_z = nullptr, *part_p = nullptr;
+  double *d_src = nullptr, *d_flux = nullptr, *d_pres = nullptr;
+  double *alpha_h = nullptr, *beta_h = nullptr;
+  CgState *st = nullptr;
+  CgState *st_host = nullptr;
+  int *d_err = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+
+  bddc_stats_t stats{};
+
+  template <typename T>
+  T *alloc(int64_t count) {
+    if (count <= 0) count = 1;
+    void *p = nullptr;
+    HIPCHK(hipMalloc(&p, (size_t)count * sizeof(T)));
+    allocs.push_back(p);
+    device_bytes += (double)count * sizeof(T);
+    return (T *)p;
+  }
+  void release(void *p) {
+    for (auto &a : allocs)
+      if (a == p) {
+        (void)hipFree(a);
+        a = nullptr;
+      }
+  }
+  template <typename T>
+  T *upload(const std::vector<T> &v) {
+    T *d = alloc<T>((int64_t)v.size());
+    if (!v.empty()) HIPCHK(hipMemcpy(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return d;
+  }
+  ~bddc_problem() {
+    for (void *p : allocs)
+      if (p) (void)hipFree(p);
+    if (st_host) (void)hipHostFree(st_host);
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+    if (own_stream) (void)hipStreamDestroy(own_stream);
+  }
+};
+
+namespace {
+
+void check_err(bddc_problem *h, const char *stage) {
+  int e = 0;
+  HIPCHK(hipMemcpy(&e, h->d_err, sizeof(int), hipMemcpyDeviceToHost));
+  if (e & 1) throw Error{BDDC_EINVAL, "permeability must be finite and > 0"};
+  if (e) throw Error{BDDC_EFACTOR, std::string("factorization lost definiteness in ") + stage +
+                                       " (code " + std::to_string(e) + ")"};
+}
+
+void fill(bddc_problem *h, double *x, int64_t n, double v) {
+  if (n > 0) k_fill<<<nblk(n), 256, 0, h->stream>>>(n, x, v);
+}
+
+void do_setup(bddc_problem *h, const bddc_grid *gr, const double *perm, const bddc_partition *part) {
+  Layout &L = h->L;
+  int n[3] = {gr->n[0], gr->n[1], gr->n[2]};
+  double hh[3] = {gr->h[0], gr->h[1], gr->h[2]};
+  const int *cuts[3] = {part->cuts[0], part->cuts[1], part->cuts[2]};
+  for (int d = 0; d < gr->dim; ++d)
+    if (!cuts[d]) throw Error{BDDC_EINVAL, "partition cuts missing"};
+  try {
+    L.build(gr->dim, n, hh, part->nsub, cuts);
+  } catch (const std::exception &e) {
+    throw Error{BDDC_EINVAL, e.what()};
+  }
+  for (int i = 0; i < L.N; ++i)
+    for (int d = 0; d < L.dim; ++d)
+      if (L.ext[d][i] > MAXLINE) throw Error{BDDC_EINVAL, "subdomain extent exceeds 32 cells"};
+  const int dim = L.dim;
+  for (int64_t c = 0; c < L.ncells * dim; ++c)
+    if (!(perm[c] > 0.0) || !isfinite(perm[c])) throw Error{BDDC_EINVAL, "permeability must be finite and > 0"};
+  const int N = L.N;
+  hipStream_t s = h->stream;
+
+  // index data
+  DevGeom &g = h->g;
+  g.dim = dim;
+  double vol = 1.0;
+  for (int d = 0; d < 3; ++d) {
+    g.n[d] = L.n[d];
+    g.h[d] = L.h[d];
+    if (d < dim) vol *= L.h[d];
+    for (int e = 0; e < 3; ++e) g.fshape[d][e] = L.fshape[d][e];
+  }
+  for (int d = 0; d < 4; ++d) g.face_off[d] = L.face_off[d];
+  g.vol = vol;
+  g.N = N;
+  g.nGamma = L.nGamma;
+  g.nF = L.nF;
+  std::vector<int> lo3(3 * N), ext3(3 * N);
+  for (int i = 0; i < N; ++i)
+    for (int d = 0; d < 3; ++d) {
+      lo3[3 * i + d] = L.lo[d][i];
+      ext3[3 * i + d] = L.ext[d][i];
+    }
+  g.lo = h->upload(lo3);
+  g.ext = h->upload(ext3);
+  g.nc = h->upload(L.nc);
+  g.nG = h->upload(L.nG);
+  g.cell_off = h->upload(L.cell_off);
+  g.g_off = h->upload(L.g_off);
+  g.lcell_global = h->upload(L.lcell_global);
+  g.lg_dir = h->upload(L.lg_dir);
+  g.lg_cell = h->upload(L.lg_cell);
+  g.lg_end = h->upload(L.lg_end);
+  g.lg_partner = h->upload(L.lg_partner);
+  g.Rmap = h->upload(L.Rmap);
+  g.own_minus = h->upload(L.own_minus);
+  g.own_plus = h->upload(L.own_plus);
+  g.sub_minus = h->upload(L.sub_minus);
+  g.sub_plus = h->upload(L.sub_plus);
+  g.f_minus = h->upload(L.f_minus);
+  g.f_plus = h->upload(L.f_plus);
+  g.f_n = h->upload(L.f_n);
+  g.f_loffm = h->upload(L.f_loff_minus);
+  g.f_loffp = h->upload(L.f_loff_plus);
+  g.sub_face_off = h->upload(L.sub_face_off);
+  g.sub_faces = h->upload(L.sub_faces);
+  g.line_off = h->upload(L.line_off);
+  g.line_g = h->upload(L.line_g);
+  h->d_gamma_face = h->upload(L.gamma_face);
+  h->d_err = h->alloc<int>(1);
+  {
+    const int zero = 0;
+    HIPCHK(hipMemcpy(h->d_err, &zero, sizeof(int), hipMemcpyHostToDevice));
+  }
+
+  // S1: cell coefficients
+  std::vector<double> permv(perm, perm + L.ncells * dim);
+  double *d_perm = h->upload(permv);
+  h->mcoef = h->alloc<double>(L.ncells * 3);
+  k_cell_coef<<<nblk(L.ncells), 256, 0, s>>>(g, d_perm, L.ncells, h->mcoef, h->d_err);
+  HIPCHK(hipGetLastError());
+  h->dscale = h->alloc<double>(N);
+
+  // S2: local dense setup
+  std::vector<int64_t> oP(N), oV(N), oH(N), oS(N), oL(N), oW(N), oX(N), opk(N);
+  int64_t ws = 0, xs = 0, pks = 0;
+  for (int i = 0; i < N; ++i) {
+    const int64_t nc = L.nc[i], nG = L.nG[i];
+    oP[i] = ws; ws += nc * nc;
+    oV[i] = ws; ws += nc * nc;
+    oH[i] = ws; ws += nc * (nG + 1);
+    oS[i] = ws; ws += nG * nG;
+    oL[i] = ws; ws += nG * nG;
+    oW[i] = ws; ws += nG * nG;
+    oX[i] = xs; xs += nc * nc;
+    opk[i] = pks; pks += nG * (nG + 1) / 2;
+  }
+  double *wsb = h->alloc<double>(ws);
+  SetupWs sw;
+  sw.base = wsb;
+  sw.P = h->upload(oP);
+  sw.V = h->upload(oV);
+  sw.H = h->upload(oH);
+  sw.S = h->upload(oS);
+  sw.L = h->upload(oL);
+  sw.W = h->upload(oW);
+  sw.X = h->d_Xoff = h->upload(oX);
+  sw.Xmat = h->Xmat = h->alloc<double>(xs);
+  sw.pk = h->d_pk = h->upload(opk);
+  sw.Spk = h->Spk = h->alloc<double>(pks);
+  h->pk_h = opk;
+  k_local_setup<<<N, 256, 0, s>>>(g, h->mcoef, sw, h->dscale, h->d_err);
+  HIPCHK(hipGetLastError());
+  k_schur_factor<<<N, 256, 0, s>>>(g, sw, h->d_err);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  check_err(h, "the subdomain setup");
+
+  // S4: face eigenproblems
+  const int nF = L.nF;
+  h->face_k.assign(nF, 0);
+  h->face_omega.assign(nF, 0.0);
+  std::vector<int64_t> foff(nF), eoff(nF), roff(nF);
+  int64_t fws = 0, es = 0, rs = 0;
+  for (int f = 0; f < nF; ++f) {
+    const int64_t fn = L.f_n[f];
+    foff[f] = fws; fws += 6 * fn * fn + fn;
+    eoff[f] = es; es += fn - 1;
+    roff[f] = rs; rs += fn * fn;
+  }
+  h->eig_off_h = eoff;
+  h->face_eig.assign(es, 0.0);
+  const bool adaptive = (h->tau > 0.0 && isfinite(h->tau));
+  const bool allc = (h->flags & BDDC_ALL_CONSTRAINED) != 0;
+  if ((adaptive || allc) && L.maxFn > 256)
+    throw Error{BDDC_EINVAL, "adaptive constraints need faces of at most 256 dofs"};
+  double *d_rows = h->alloc<double>(rs);
+  double *d_fws = nullptr;
+  if (nF > 0 && (adaptive || allc)) {
+    d_fws = h->alloc<double>(fws);
+    double *d_eig = h->alloc<double>(es);
+    int *d_k = h->alloc<int>(nF);
+    double *d_om = h->alloc<double>(nF);
+    int64_t *d_foff = h->upload(foff), *d_eoff = h->upload(eoff), *d_roff = h->upload(roff);
+    k_face_eig<<<nF, 256, 0, s>>>(g, sw, d_fws, d_foff, adaptive ? h->tau : 0.0, allc ? 1 : 0, d_eig, d_eoff,
+                                  d_k, d_om, d_rows, d_roff, h->d_err);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
+    check_err(h, "the face eigenproblems");
+    HIPCHK(hipMemcpy(h->face_k.data(), d_k, nF * sizeof(int), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(h->face_omega.data(), d_om, nF * sizeof(double), hipMemcpyDeviceToHost));
+    if (es > 0) HIPCHK(hipMemcpy(h->face_eig.data(), d_eig, es * sizeof(double), hipMemcpyDeviceToHost));
+    h->release(d_fws);
+  }
+  h->n_adaptive = 0;
+  h->omega_tilde = 0.0;
+  for (int f = 0; f < nF; ++f) {
+    h->n_adaptive += h->face_k[f];
+    h->omega_tilde = std::max(h->omega_tilde, h->face_omega[f]);
+  }
+
+  // coarse numbering: face by face, zero-net-flux row first
+  std::vector<int> face_cofs(nF), sub_coff(N + 1, 0), sub_cmap;
+  int ncu = 0;
+  for (int f = 0; f < nF; ++f) {
+    face_cofs[f] = ncu;
+    ncu += 1 + h->face_k[f];
+  }
+  std::vector<int> co_minus(ncu), co_plus(ncu);
+  for (int i = 0; i < N; ++i) {
+    for (int t = L.sub_face_off[i]; t < L.sub_face_off[i + 1]; ++t) {
+      const int f = L.sub_faces[t];
+      for (int l = 0; l <= h->face_k[f]; ++l) {
+        const int gdof = face_cofs[f] + l;
+        const int flat = (int)sub_cmap.size();
+        sub_cmap.push_back(gdof);
+        if (L.f_minus[f] == i) co_minus[gdof] = flat;
+        else co_plus[gdof] = flat;
+      }
+    }
+    sub_coff[i + 1] = (int)sub_cmap.size();
+    if (sub_coff[i + 1] - sub_coff[i] > 1024)
+      throw Error{BDDC_EINVAL, "more than 1024 coarse dofs on one subdomain"};
+  }
+  h->ncu = ncu;
+  h->nk = ncu + N - 1;
+  h->sub_coff_h = sub_coff;
+  DevCoarse &cs = h->cs;
+  cs.ncu = ncu;
+  cs.nk = h->nk;
+  cs.face_cofs = h->upload(face_cofs);
+  cs.face_k = h->upload(h->face_k);
+  cs.face_rows_off = h->upload(roff);
+  cs.face_rows = d_rows;
+  cs.sub_coff = h->upload(sub_coff);
+  cs.sub_cmap = h->upload(sub_cmap);
+  cs.co_minus = h->upload(co_minus);
+  cs.co_plus = h->upload(co_plus);
+
+  // S5: local coarse spaces
+  std::vector<int64_t> cwoff(N), acoff(N), psioff(N);
+  int64_t cws = 0, acs = 0, pss = 0;
+  for (int i = 0; i < N; ++i) {
+    const int64_t nci = sub_coff[i + 1] - sub_coff[i], nG = L.nG[i];
+    cwoff[i] = cws; cws += 4 * nci * nG + 2 * nci * nci;
+    acoff[i] = acs; acs += nci * nci;
+    psioff[i] = pss; pss += nG * nci;
+  }
+  h->psi_off_h = psioff;
+  CoarseLocalWs cw;
+  cw.base = h->alloc<double>(cws);
+  cw.off = h->upload(cwoff);
+  cw.Ac = h->alloc<double>(acs);
+  cw.ac_off = h->upload(acoff);
+  cw.psi64 = h->Psi64 = h->alloc<double>(pss);
+  cw.psi32 = h->Psi32 = h->alloc<float>(pss);
+  cw.psi_off = h->d_psi_off = h->upload(psioff);
+  cw.t64 = h->T64 = h->alloc<double>(pks);
+  cw.t32 = h->T32 = h->alloc<float>(pks);
+  cw.pk = h->d_pk;
+  k_coarse_local<<<N, 256, 0, s>>>(g, sw, cs, cw, h->d_err);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  check_err(h, "the local coarse spaces");
+
+  // S6: coarse saddle point
+  const int nk = h->nk;
+  if (nk > 0) {
+    double *K = h->alloc<double>((int64_t)nk * nk);
+    double *Wb = h->alloc<double>((int64_t)nk * nk);
+    double *sgn = h->alloc<double>(nk);
+    h->Kinv64 = h->alloc<double>((int64_t)nk * nk);
+    h->Kinv32 = h->alloc<float>((int64_t)nk * nk);
+    fill(h, K, (int64_t)nk * nk, 0.0);
+    k_coarse_assemble<<<N, 256, 0, s>>>(g, cs, cw.Ac, cw.ac_off, h->dscale, K);
+    HIPCHK(hipGetLastError());
+    k_coarse_factor<<<1, 256, 0, s>>>(nk, ncu, K, Wb, h->Kinv64, h->Kinv32, sgn, h->d_err);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
+    check_err(h, "the coarse problem");
+    h->release(K);
+    h->release(Wb);
+  }
+  h->release(wsb);
+  h->release(cw.base);
+  h->release(cw.Ac);
+  h->release(d_perm);
+
+  // solve work arrays
+  const int nGm = L.nGamma;
+  const int64_t totG = L.g_off[N];
+  h->xu = h->alloc<double>(nGm);
+  h->ru = h->alloc<double>(nGm);
+  h->pu = h->alloc<double>(nGm);
+  h->zu = h->alloc<double>(nGm);
+  h->qu = h->alloc<double>(nGm);
+  h->u0 = h->alloc<double>(nGm);
+  h->uG = h->alloc<double>(nGm);
+  h->xp = h->alloc<double>(N);
+  h->pp = h->alloc<double>(N);
+  h->yloc = h->alloc<double>(totG);
+  h->wloc = h->alloc<double>(totG);
+  h->gloc = h->alloc<double>(sub_coff[N]);
+  h->bc = h->alloc<double>(nk + 1);
+  h->csol = h->alloc<double>(nk + 1);
+  h->part_g = h->alloc<double>(nblk(nGm) + 1);
+  h->part_r = h->alloc<double>(nblk(nGm) + 1);
+  h->part_z = h->alloc<double>(nF + 1);
+  h->part_p = h->alloc<double>(1024);
+  h->d_src = h->alloc<double>(L.ncells);
+  h->d_flux = h->alloc<double>(L.nfaces_all);
+  h->d_pres = h->alloc<double>(L.ncells);
+  h->alpha_h = h->alloc<double>(h->max_it + 2);
+  h->beta_h = h->alloc<double>(h->max_it + 2);
+  h->st = h->alloc<CgState>(1);
+  HIPCHK(hipHostMalloc((void **)&h->st_host, sizeof(CgState), hipHostMallocDefault));
+  HIPCHK(hipEventCreate(&h->ev0));
+  HIPCHK(hipEventCreate(&h->ev1));
+  HIPCHK(hipStreamSynchronize(s));
+
+  // statistics of the operators streamed per iteration
+  double sumpk = (double)pks, sumpsi = (double)pss;
+  const double sT = h->precision == BDDC_MIXED ? 4.0 : 8.0;
+  h->stats.bytes_prec = sumpk * sT + 2.0 * sumpsi * sT + (double)nk * ncu * 8.0 + 6.0 * totG * 8.0 + 4.0 * nGm * 8.0;
+  h->stats.bytes_per_iter = h->stats.bytes_prec + sumpk * 8.0 + 2.0 * totG * 8.0 + 8.0 * nGm * 8.0;
+}
+
+// Preconditioner on r (FP64 or mixed operators) -> zu (and csol for the pressures).
+void launch_precond(bddc_problem *h, const double *r, double *z, double *zpart, bool check) {
+  const Layout &L = h->L;
+  hipStream_t s = h->stream;
+  const int N = L.N, nF = L.nF;
+  const size_t shm = (size_t)5 * L.maxG * sizeof(double);
+  CgState *st = check ? h->st : nullptr;
+  const double *rp = check ? h->part_r : nullptr;
+  const int nrp = (int)nblk(L.nGamma);
+  if (h->precision == BDDC_MIXED) {
+    k_symv<float, true><<<N, 256, shm, s>>>(h->g, h->T32, h->d_pk, r, 0.5, h->yloc, h->Psi32, h->d_psi_off,
+                                            h->cs.sub_coff, h->gloc, st, rp, nrp);
+  } else {
+    k_symv<double, true><<<N, 256, shm, s>>>(h->g, h->T64, h->d_pk, r, 0.5, h->yloc, h->Psi64, h->d_psi_off,
+                                             h->cs.sub_coff, h->gloc, st, rp, nrp);
+  }
+  if (h->ncu > 0) k_coarse_rhs<<<nblk(h->ncu), 256, 0, s>>>(h->cs, h->gloc, h->bc, st);
+  // The coarse solve stays FP64 in both forms: the CG runs in the balanced
+  // subspace, so the face-average coarse fluxes must satisfy B_c alpha = 0 to
+  // FP64 accuracy (the FP32 local operators are corrected by the balance step).
+  if (h->nk > 0)
+    k_coarse_gemv<double><<<nblk(h->nk, 4), 256, 0, s>>>(h->nk, h->ncu, h->Kinv64, h->bc, h->csol, st);
+  if (h->precision == BDDC_MIXED)
+    k_psi_correct<float><<<N, 256, 0, s>>>(h->g, h->cs, h->Psi32, h->d_psi_off, h->yloc, h->csol, h->wloc, st);
+  else
+    k_psi_correct<double><<<N, 256, 0, s>>>(h->g, h->cs, h->Psi64, h->d_psi_off, h->yloc, h->csol, h->wloc, st);
+  if (nF > 0) k_average_balance<<<nF, 256, 0, s>>>(h->g, h->cs, h->wloc, h->csol, z, r, zpart, st);
+}
+
+void launch_iteration(bddc_problem *h) {
+  const Layout &L = h->L;
+  hipStream_t s = h->stream;
+  const int N = L.N, nGm = L.nGamma;
+  const size_t shm = (size_t)5 * L.maxG * sizeof(double);
+  const int nb = (int)nblk(nGm);
+  k_symv<double, false><<<N, 256, shm, s>>>(h->g, h->Spk, h->d_pk, h->pu, 1.0, h->yloc, nullptr, nullptr,
+                                            nullptr, nullptr, h->st, nullptr, 0);
+  k_sys_assemble<<<nb, 256, 0, s>>>(h->g, h->yloc, h->pp, h->dscale, h->pu, h->qu, h->part_g, h->st);
+  k_update_xr<<<nb, 256, 0, s>>>(nGm, N, h->part_g, nb, h->pu, h->qu, h->pp, h->xu, h->ru, h->xp, h->part_r,
+                                 h->st, h->alpha_h);
+  launch_precond(h, h->ru, h->zu, h->part_z, true);
+  k_update_p<<<nb, 256, 0, s>>>(nGm, N, h->ncu, h->part_z, L.nF, h->zu, h->csol, h->pu, h->pp, h->st, h->beta_h);
+  k_advance<<<1, 1, 0, s>>>(h->st);
+}
+
+double lanczos_kappa(const std::vector<double> &a, const std::vector<double> &b, double *lmin, double *lmax) {
+  int k = (int)a.size();
+  for (int j = 0; j + 1 < k && j < (int)b.size(); ++j)
+    if (!(b[j] > 0.0)) { k = j + 1; break; }
+  if (k == 0) { *lmin = *lmax = 1.0; return 1.0; }
+  // symmetric tridiagonal: bisection on the Sturm sequence for the extremes
+  std::vector<double> d(k), e(k, 0.0);
+  for (int j = 0; j < k; ++j) {
+    d[j] = 1.0 / a[j] + (j > 0 ? b[j - 1] / a[j - 1] : 0.0);
+    if (j + 1 < k) e[j] = sqrt(b[j]) / a[j];
+  }
+  double lo = d[0], hi = d[0];
+  for (int j = 0; j < k; ++j) {
+    const double r = (j > 0 ? fabs(e[j - 1]) : 0.0) + (j + 1 < k ? fabs(e[j]) : 0.0);
+    lo = std::min(lo, d[j] - r);
+    hi = std::max(hi, d[j] + r);
+  }
+  auto count_below = [&](double x) {
+    int c = 0;
+    double q = d[0] - x;
+    if (q < 0) ++c;
+    for (int j = 1; j < k; ++j) {
+      if (q == 0.0) q = 1e-300;
+      q = d[j] - x - e[j - 1] * e[j - 1] / q;
+      if (q < 0) ++c;
+    }
+    return c;
+  };
+  auto kth = [&](int idx) {
+    double a0 = lo, b0 = hi;
+    for (int it = 0; it < 200; ++it) {
+      const double m = 0.5 * (a0 + b0);
+      if (count_below(m) > idx) b0 = m; else a0 = m;
+      if (b0 - a0 <= 1e-15 * std::max(fabs(a0), fabs(b0))) break;
+    }
+    return 0.5 * (a0 + b0);
+  };
+  *lmin = kth(0);
+  *lmax = kth(k - 1);
+  return *lmax / *lmin;
+}
+
+int do_solve(bddc_problem *h, const double *rhs, double rtol, double *flux, double *pressure, uint32_t flags) {
+  const Layout &L = h->L;
+  hipStream_t s = h->stream;
+  const int N = L.N, nF = L.nF, nGm = L.nGamma;
+  const bool dev = (flags & BDDC_DEVICE_PTRS) != 0;
+  auto t0 = std::chrono::steady_clock::now();
+  if (!(rtol > 0.0)) throw Error{BDDC_EINVAL, "rtol must be > 0"};
+  const double *src = rhs;
+  if (!dev) {
+    double sum = 0.0, asum = 0.0;
+    for (int64_t c = 0; c < L.ncells; ++c) {
+      if (!isfinite(rhs[c])) throw Error{BDDC_EINVAL, "source must be finite"};
+      sum += rhs[c];
+      asum += fabs(rhs[c]);
+    }
+    if (fabs(sum) > 1e-12 * asum) throw Error{BDDC_EINVAL, "source must sum to zero (no-flow compatibility)"};
+    HIPCHK(hipMemcpyAsync(h->d_src, rhs, L.ncells * sizeof(double), hipMemcpyHostToDevice, s));
+    src = h->d_src;
+  }
+  double *fl = dev ? flux : h->d_flux;
+  double *pr = dev ? pressure : h->d_pres;
+  const size_t shm = (size_t)5 * L.maxG * sizeof(double);
+  const int nb = (int)nblk(nGm);
+
+  int iters = 0, converged = 1, fail = 0;
+  double relres = 0.0;
+  float pcg_ms = 0.f;
+  if (N > 1) {
+    // step 1: coarse solve with (0, D F_0), u0 = E Psi alpha
+    k_step1_rhs<<<N, 256, 0, s>>>(h->g, h->ncu, h->nk, src, h->dscale, h->bc);
+    k_coarse_gemv<double><<<nblk(h->nk, 4), 256, 0, s>>>(h->nk, h->nk, h->Kinv64, h->bc, h->csol, nullptr);
+    k_psi_correct<double><<<N, 256, 0, s>>>(h->g, h->cs, h->Psi64, h->d_psi_off, nullptr, h->csol, h->wloc,
+                                            nullptr);
+    k_average_balance<<<nF, 256, 0, s>>>(h->g, h->cs, h->wloc, h->csol, h->u0, nullptr, nullptr, nullptr);
+    // steps 2-3 right-hand side: f* = -S u0 + H^T X F
+    k_symv<double, false><<<N, 256, shm, s>>>(h->g, h->Spk, h->d_pk, h->u0, 1.0, h->yloc, nullptr, nullptr,
+                                              nullptr, nullptr, nullptr, nullptr, 0);
+    k_source_term<<<N, 256, (size_t)2 * L.maxC * sizeof(double), s>>>(h->g, h->mcoef, h->Xmat, h->d_Xoff, src,
+                                                                       h->wloc);
+    k_fstar<<<nblk(nGm), 256, 0, s>>>(h->g, h->yloc, h->wloc, h->ru);
+    fill(h, h->xu, nGm, 0.0);
+    fill(h, h->xp, N, 0.0);
+    k_norm2_partial<<<nb, 256, 0, s>>>(nGm, h->ru, h->part_r);
+    launch_precond(h, h->ru, h->zu, h->part_z, false);
+    k_init_p<<<nb, 256, 0, s>>>(nGm, N, h->ncu, h->part_z, nF, h->part_r, nb, h->zu, h->csol, h->pu, h->pp, h->st,
+                                rtol, h->max_it);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipEventRecord(h->ev0, s));
+    const int chunk = 8;
+    for (int rounds = 0;; ++rounds) {
+      if (rounds > h->max_it / chunk + 2) throw Error{BDDC_EDEVICE, "CG loop did not report completion"};
+      for (int k = 0; k < chunk; ++k) launch_iteration(h);
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipMemcpyAsync(h->st_host, h->st, sizeof(CgState), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      if (h->st_host->done) break;
+    }
+    HIPCHK(hipEventRecord(h->ev1, s));
+    HIPCHK(hipEventSynchronize(h->ev1));
+    HIPCHK(hipEventElapsedTime(&pcg_ms, h->ev0, h->ev1));
+    iters = h->st_host->nupd;
+    converged = h->st_host->converged;
+    fail = h->st_host->fail;
+    relres = h->st_host->relres;
+    // Lanczos estimate from the CG coefficients
+    std::vector<double> a(iters), b(iters > 0 ? iters - 1 : 0);
+    if (iters > 0) HIPCHK(hipMemcpy(a.data(), h->alpha_h, iters * sizeof(double), hipMemcpyDeviceToHost));
+    if (iters > 1) HIPCHK(hipMemcpy(b.data(), h->beta_h, (iters - 1) * sizeof(double), hipMemcpyDeviceToHost));
+    double lmin = 1, lmax = 1;
+    h->stats.kappa = lanczos_kappa(a, b, &lmin, &lmax);
+    h->stats.lambda_min = lmin;
+    h->stats.lambda_max = lmax;
+    // final interface flux
+    k_axpby<<<nblk(nGm), 256, 0, s>>>(nGm, 1.0, h->u0, 1.0, h->xu, h->uG);
+  }
+  // post-correction: interior fluxes and pressures
+  fill(h, fl, L.nfaces_all, 0.0);
+  if (nGm > 0) k_scatter_iface<<<nblk(nGm), 256, 0, s>>>(nGm, h->d_gamma_face, h->uG, fl);
+  if (N == 1) fill(h, h->xp, 1, 0.0);
+  k_recover<<<N, 256, (size_t)(L.maxG + 2 * L.maxC) * sizeof(double), s>>>(h->g, h->mcoef, h->Xmat, h->d_Xoff,
+                                                                            src, h->uG, h->xp, h->dscale, fl, pr);
+  k_sum_partial<<<256, 256, 0, s>>>(L.ncells, pr, h->part_p);
+  k_sub_mean<<<256, 256, 0, s>>>(L.ncells, pr, h->part_p, 256);
+  HIPCHK(hipGetLastError());
+  if (!dev) {
+    HIPCHK(hipMemcpyAsync(flux, fl, L.nfaces_all * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(pressure, pr, L.ncells * sizeof(double), hipMemcpyDeviceToHost, s));
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  h->stats.it = iters;
+  h->stats.converged = converged;
+  h->stats.relres = relres;
+  h->stats.t_pcg_ms = pcg_ms;
+  h->stats.t_solve_ms =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (fail) throw Error{BDDC_EBREAKDOWN, "CG breakdown (p^T S p <= 0 or not finite)"};
+  if (!converged) return BDDC_ENOCONV;
+  return BDDC_OK;
+}
+
+template <typename F>
+int guarded(F &&fn) {
+  try {
+    return fn();
+  } catch (const Error &e) {
+    g_last_error = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc &) {
+    g_last_error = "host out of memory";
+    return BDDC_ENOMEM;
+  } catch (const std::exception &e) {
+    g_last_error = e.what();
+    return BDDC_EDEVICE;
+  } catch (...) {
+    g_last_error = "unknown error";
+    return BDDC_EDEVICE;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int bddc_setup(const bddc_grid *g, const double *perm, const bddc_partition *part, double tau,
+               const bddc_options *opt, bddc_handle *out) {
+  return guarded([&]() -> int {
+    if (!g || !perm || !part || !out) throw Error{BDDC_EINVAL, "null argument"};
+    *out = nullptr;
+    auto t0 = std::chrono::steady_clock::now();
+    bddc_problem *h = new bddc_problem();
+    try {
+      if (opt) {
+        h->precision = opt->precision;
+        if (opt->max_it > 0) h->max_it = opt->max_it;
+        h->flags = opt->flags;
+      }
+      if (h->precision != BDDC_FP64 && h->precision != BDDC_MIXED) throw Error{BDDC_EINVAL, "bad precision"};
+      h->tau = tau;
+      HIPCHK(hipStreamCreateWithFlags(&h->own_stream, hipStreamNonBlocking));
+      h->stream = h->own_stream;
+      do_setup(h, g, perm, part);
+    } catch (...) {
+      delete h;
+      throw;
+    }
+    h->stats.t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    *out = h;
+    return BDDC_OK;
+  });
+}
+
+int bddc_solve(bddc_handle h, const double *rhs, double rtol, double *flux, double *pressure, uint32_t flags) {
+  return guarded([&]() -> int {
+    if (!h || !rhs || !flux || !pressure) throw Error{BDDC_EINVAL, "null argument"};
+    const int rc = do_solve(h, rhs, rtol, flux, pressure, flags);
+    if (rc == BDDC_ENOCONV) g_last_error = "maximum number of CG iterations reached";
+    return rc;
+  });
+}
+
+int bddc_stats(bddc_handle h, bddc_stats_t *out) {
+  return guarded([&]() -> int {
+    if (!h || !out) throw Error{BDDC_EINVAL, "null argument"};
+    bddc_stats_t s = h->stats;
+    s.omega_tilde = h->omega_tilde;
+    s.n_adaptive = h->n_adaptive;
+    s.n_coarse_flux = h->ncu;
+    s.n_coarse = h->ncu + h->L.N;
+    s.n_sub = h->L.N;
+    s.n_gamma = h->L.nGamma;
+    s.n_faces = h->L.nF;
+    s.precision = h->precision;
+    s.device_bytes = h->device_bytes;
+    *out = s;
+    return BDDC_OK;
+  });
+}
+
+int bddc_set_stream(bddc_handle h, void *stream) {
+  return guarded([&]() -> int {
+    if (!h) throw Error{BDDC_EINVAL, "null handle"};
+    HIPCHK(hipStreamSynchronize(h->stream));
+    h->stream = stream ? (hipStream_t)stream : h->own_stream;
+    return BDDC_OK;
+  });
+}
+
+int bddc_destroy(bddc_handle h) {
+  return guarded([&]() -> int {
+    if (h) {
+      (void)hipStreamSynchronize(h->stream);
+      delete h;
+    }
+    return BDDC_OK;
+  });
+}
+
+const char *bddc_last_error(void) { return g_last_error.c_str(); }
+
+int bddc_sizes(bddc_handle h, int64_t *out) {
+  return guarded([&]() -> int {
+    if (!h || !out) throw Error{BDDC_EINVAL, "null argument"};
+    out[0] = h->L.N;
+    out[1] = h->L.nGamma;
+    out[2] = h->L.nF;
+    out[3] = h->ncu;
+    out[4] = h->L.ncells;
+    out[5] = h->L.nfaces_all;
+    out[6] = h->n_adaptive;
+    out[7] = h->L.maxG;
+    return BDDC_OK;
+  });
+}
+
+int64_t bddc_export(bddc_handle h, int32_t what, int32_t index, void *dst, int64_t cap) {
+  int64_t count = 0;
+  const int rc = guarded([&]() -> int {
+    if (!h || !dst) throw Error{BDDC_EINVAL, "null argument"};
+    const Layout &L = h->L;
+    switch (what) {
+      case BDDC_X_SCHUR: {
+        if (index < 0 || index >= L.N) throw Error{BDDC_EINVAL, "bad subdomain index"};
+        const int n = L.nG[index];
+        count = (int64_t)n * n;
+        if (cap < count) throw Error{BDDC_EINVAL, "capacity too small"};
+        std::vector<double> pk((size_t)n * (n + 1) / 2);
+        if (!pk.empty())
+          HIPCHK(hipMemcpy(pk.data(), h->Spk + h->pk_h[index], pk.size() * sizeof(double), hipMemcpyDeviceToHost));
+        double *o = (double *)dst;
+        for (int c = 0; c < n; ++c)
+          for (int r = c; r < n; ++r) {
+            const double v = pk[(size_t)c * n - (size_t)c * (c - 1) / 2 + (r - c)];
+            o[r + (size_t)c * n] = v;
+            o[c + (size_t)r * n] = v;
+          }
+        break;
+      }
+      case BDDC_X_T: {
+        if (index < 0 || index >= L.N) throw Error{BDDC_EINVAL, "bad subdomain index"};
+        const int n = L.nG[index];
+        count = (int64_t)n * n;
+        if (cap < count) throw Error{BDDC_EINVAL, "capacity too small"};
+        std::vector<double> pk((size_t)n * (n + 1) / 2);
+        if (!pk.empty())
+          HIPCHK(hipMemcpy(pk.data(), h->T64 + h->pk_h[index], pk.size() * sizeof(double), hipMemcpyDeviceToHost));
+        double *o = (double *)dst;
+        for (int c = 0; c < n; ++c)
+          for (int r = c; r < n; ++r) {
+            const double v = pk[(size_t)c * n - (size_t)c * (c - 1) / 2 + (r - c)];
+            o[r + (size_t)c * n] = v;
+            o[c + (size_t)r * n] = v;
+          }
+        break;
+      }
+      case BDDC_X_PSI: {
+        if (index < 0 || index >= L.N) throw Error{BDDC_EINVAL, "bad subdomain index"};
+        const int64_t nci = h->sub_coff_h[index + 1] - h->sub_coff_h[index];
+        count = (int64_t)L.nG[index] * nci;
+        if (cap < count) throw Error{BDDC_EINVAL, "capacity too small"};
+        if (count > 0)
+          HIPCHK(hipMemcpy(dst, h->Psi64 + h->psi_off_h[index], count * sizeof(double), hipMemcpyDeviceToHost));
+        break;
+      }
+      case BDDC_X_COARSE_INV: {
+        const int nk = h->nk, ncu = h->ncu;
+        count = (int64_t)ncu * ncu;
+        if (cap < count) throw Error{BDDC_EINVAL, "capacity too small"};
+        std::vector<double> full((size_t)nk * nk);
+        if (nk > 0) HIPCHK(hipMemcpy(full.data(), h->Kinv64, full.size() * sizeof(double), hipMemcpyDeviceToHost));
+        double *o = (double *)dst;
+        for (int c = 0; c < ncu; ++c)
+          for (int r = 0; r < ncu; ++r) o[r + (size_t)c * ncu] = full[r + (size_t)c * nk];
+        break;
+      }
+      case BDDC_X_FACE_EIG: {
+        if (index < 0 || index >= L.nF) throw Error{BDDC_EINVAL, "bad face index"};
+        count = L.f_n[index] - 1;
+        if (cap < count) throw Error{BDDC_EINVAL, "capacity too small"};
+        memcpy(dst, h->face_eig.data() + h->eig_off_h[index], count * sizeof(double));
+        break;
+      }
+      case BDDC_X_FACE_K:
+        count = L.nF;
+        if (cap < count) throw Error{BDDC_EINVAL, "capacity too small"};
+        memcpy(dst, h->face_k.data(), count * sizeof(int));
+        break;
+      case BDDC_X_OMEGA:
+        count = L.nF;
+        if (cap < count) throw Error{BDDC_EINVAL, "capacity too small"};
+        memcpy(dst, h->face_omega.data(), count * sizeof(double));
+        break;
+      case BDDC_X_DSCALE:
+        count = L.N;
+        if (cap < count) throw Error{BDDC_EINVAL, "capacity too small"};
+        HIPCHK(hipMemcpy(dst, h->dscale, count * sizeof(double), hipMemcpyDeviceToHost));
+        break;
+      case BDDC_X_GAMMA: {
+        count = L.nGamma;
+        if (cap < count) throw Error{BDDC_EINVAL, "capacity too small"};
+        int *o = (int *)dst;
+        for (int g = 0; g < L.nGamma; ++g) o[g] = (int)L.gamma_face[g];
+        break;
+      }
+      default:
+        throw Error{BDDC_EINVAL, "unknown export"};
+    }
+    return BDDC_OK;
+  });
+  return rc == BDDC_OK ? count : rc;
+}
+
+int bddc_apply(bddc_handle h, int32_t which, const double *x_u, const double *x_p, double *y_u, double *y_p) {
+  return guarded([&]() -> int {
+    if (!h || !x_u || !y_u || !y_p) throw Error{BDDC_EINVAL, "null argument"};
+    const Layout &L = h->L;
+    hipStream_t s = h->stream;
+    const int N = L.N, nGm = L.nGamma;
+    if (nGm == 0) throw Error{BDDC_EINVAL, "no interface"};
+    HIPCHK(hipMemcpyAsync(h->ru, x_u, nGm * sizeof(double), hipMemcpyHostToDevice, s));
+    if (which == BDDC_OP_SYSTEM) {
+      if (!x_p) throw Error{BDDC_EINVAL, "x_p required"};
+      HIPCHK(hipMemcpyAsync(h->pp, x_p, N * sizeof(double), hipMemcpyHostToDevice, s));
+      const size_t shm = (size_t)5 * L.maxG * sizeof(double);
+      k_symv<double, false><<<N, 256, shm, s>>>(h->g, h->Spk, h->d_pk, h->ru, 1.0, h->yloc, nullptr, nullptr,
+                                                nullptr, nullptr, nullptr, nullptr, 0);
+      k_sys_assemble<<<nblk(nGm), 256, 0, s>>>(h->g, h->yloc, h->pp, h->dscale, nullptr, h->qu, nullptr, nullptr);
+      k_b0<<<N, 256, 0, s>>>(h->g, h->ru, h->dscale, h->xp);
+      HIPCHK(hipMemcpyAsync(y_u, h->qu, nGm * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(y_p, h->xp, N * sizeof(double), hipMemcpyDeviceToHost, s));
+    } else if (which == BDDC_OP_PRECOND) {
+      launch_precond(h, h->ru, h->zu, nullptr, false);
+      HIPCHK(hipMemcpyAsync(y_u, h->zu, nGm * sizeof(double), hipMemcpyDeviceToHost, s));
+      std::vector<double> c(h->nk + 1, 0.0);
+      if (h->nk > 0) HIPCHK(hipMemcpyAsync(c.data(), h->csol, h->nk * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      for (int i = 0; i < N; ++i) y_p[i] = (i < N - 1) ? c[h->ncu + i] : 0.0;
+    } else {
+      throw Error{BDDC_EINVAL, "unknown operator"};
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
+    return BDDC_OK;
+  });
+}
+
+int bddc_time_kernel(bddc_handle h, int32_t which, int32_t reps, double *avg_ms, double *bytes) {
+  return guarded([&]() -> int {
+    if (!h || !avg_ms || !bytes || reps <= 0) throw Error{BDDC_EINVAL, "bad argument"};
+    const Layout &L = h->L;
+    hipStream_t s = h->stream;
+    const int N = L.N;
+    if (L.nGamma == 0) throw Error{BDDC_EINVAL, "no interface"};
+    const size_t shm = (size_t)5 * L.maxG * sizeof(double);
+    double pk = 0.0, psi = 0.0;
+    for (int i = 0; i < N; ++i) {
+      pk += (double)L.nG[i] * (L.nG[i] + 1) / 2;
+      psi += (double)L.nG[i] * (h->sub_coff_h[i + 1] - h->sub_coff_h[i]);
+    }
+    const double totG = (double)L.g_off[N];
+    const double sT = h->precision == BDDC_MIXED ? 4.0 : 8.0;
+    double b = 0.0;
+    auto launch = [&]() {
+      if (which == BDDC_K_SCHUR_APPLY) {
+        k_symv<double, false><<<N, 256, shm, s>>>(h->g, h->Spk, h->d_pk, h->pu, 1.0, h->yloc, nullptr, nullptr,
+                                                  nullptr, nullptr, nullptr, nullptr, 0);
+      } else if (h->precision == BDDC_MIXED) {
+        k_symv<float, true><<<N, 256, shm, s>>>(h->g, h->T32, h->d_pk, h->ru, 0.5, h->yloc, h->Psi32,
+                                                h->d_psi_off, h->cs.sub_coff, h->gloc, nullptr, nullptr, 0);
+      } else {
+        k_symv<double, true><<<N, 256, shm, s>>>(h->g, h->T64, h->d_pk, h->ru, 0.5, h->yloc, h->Psi64,
+                                                 h->d_psi_off, h->cs.sub_coff, h->gloc, nullptr, nullptr, 0);
+      }
+    };
+    if (which == BDDC_K_SCHUR_APPLY)
+      b = pk * 8.0 + totG * (4.0 + 8.0) + totG * 8.0;   // S^i, Rmap + gathered x, y
+    else if (which == BDDC_K_PRECOND_APPLY)
+      b = pk * sT + psi * sT + totG * (4.0 + 8.0) + totG * 8.0 + (double)h->sub_coff_h[N] * 8.0;
+    else
+      throw Error{BDDC_EINVAL, "unknown kernel"};
+    launch();
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipEventRecord(h->ev0, s));
+    for (int r = 0; r < reps; ++r) launch();
+    HIPCHK(hipEventRecord(h->ev1, s));
+    HIPCHK(hipEventSynchronize(h->ev1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+    *avg_ms = ms / reps;
+    *bytes = b;
+    return BDDC_OK;
+  });
+}
+
+}  // extern "C"

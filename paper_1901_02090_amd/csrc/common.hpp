@@ -1,0 +1,55 @@
+// Device-visible descriptions shared by the setup and solve kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bddc {
+
+constexpr int MAXLINE = 32;   // longest subdomain extent along one axis
+
+// Read-only index data of the partition (device pointers).
+struct DevGeom {
+  int dim;
+  int n[3];
+  double h[3];
+  double vol;                 // cell volume (C_Q^i entries)
+  int N, nGamma, nF;
+  int fshape[3][3];
+  int64_t face_off[4];
+  const int *lo, *ext;        // [N][3]
+  const int *nc, *nG;         // [N]
+  const int64_t *cell_off, *g_off;  // [N+1]
+  const int *lcell_global;    // [sum nc]
+  const int *lg_dir, *lg_cell, *lg_end, *lg_partner;  // [sum nG]
+  const int *Rmap;            // [sum nG] -> interface index
+  const int *own_minus, *own_plus, *sub_minus, *sub_plus;  // [nGamma]
+  const int *f_minus, *f_plus, *f_n, *f_loffm, *f_loffp;   // [nF]
+  const int *sub_face_off, *sub_faces;
+  const int64_t *line_off;    // [N+1] offsets into line_g
+  const int *line_g;          // per subdomain, direction d, line l, end e: local interface index or -1
+};
+
+// Per-subdomain dense setup workspace (FP64, column major).
+struct SetupWs {
+  double *base;
+  const int64_t *P, *V, *H, *S, *L, *W;   // offsets per subdomain
+  const int64_t *X;                        // offsets into Xmat
+  double *Xmat;                            // persistent pressure operators X^i
+  const int64_t *pk;                       // packed offsets (S, T)
+  double *Spk;                             // persistent packed S^i (FP64)
+};
+
+// Coarse-space description built after the eigenproblems.
+struct DevCoarse {
+  int ncu;                     // flux coarse dofs
+  int nk;                      // size of the coarse saddle point (ncu + N - 1)
+  const int *face_cofs;        // [nF] first coarse dof of each face (its zero-net-flux row)
+  const int *face_k;           // [nF] adaptive rows per face
+  const int64_t *face_rows_off;  // [nF] offset of the adaptive rows (k x n_F, row major)
+  const double *face_rows;
+  const int *sub_coff;         // [N+1] offsets of local coarse dofs
+  const int *sub_cmap;         // [sum nc_i] -> global coarse dof
+  const int *co_minus, *co_plus;  // [ncu] flat local coarse index in the two subdomains
+};
+
+}  // namespace bddc

@@ -1,0 +1,625 @@
+// Setup kernels: everything the CG loop of step 3 consumes.
+//
+// Per subdomain (one 256-thread workgroup each):
+//   * the RT0 coefficients m_d = h_d / (k_d prod_{e != d} h_e) of every cell and
+//     direction (the exact mass matrix of a rectangle with diagonal k decouples
+//     by direction, Section 2 eq. a) and the rescaling d_i (Section 5);
+//   * the interface Schur complement S^i of the Stokes-harmonic extension
+//     (Section 3, mapping P; Section 4, S^{ij}) by structured elimination: the
+//     interior mass matrix is tridiagonal along every grid line, so
+//     G = A_II^{-1} is applied line by line; the cell-pressure system
+//     P = B_I G B_I^T is dense per subdomain and has the constants as kernel,
+//     which the zero-mean condition C_Q^i p = 0 (eq. Qi-def) removes;
+//     S^i = (A_GG - A_GI G A_IG) + H^T X H with H = B_G - B_I G A_IG and X the
+//     generalized inverse of P on the zero-mean subspace;
+//   * the pair eigenproblems of every face (eq. eigenvalue-problem-local-matrix)
+//     in reduced form (see k_face_eig) and the adaptive rows (eq. constraints,
+//     Algorithm "Adaptive BDDC");
+//   * the coarse basis Psi^i, the coarse matrix block A_c^i and the substructure
+//     operator T^i of Algorithm "BDDC preconditioner" from one Cholesky factor
+//     of S^i;
+//   * the coarse saddle point and its inverse.
+#include "common.hpp"
+#include "dense.hpp"
+
+namespace bddc {
+
+// ---------------------------------------------------------------------------
+// line helpers
+// ---------------------------------------------------------------------------
+
+// Local cells of line `l` along direction d: start + t * st[d], t in [0, ext[d]).
+__device__ __forceinline__ int line_start(int d, int l, const int *ext, const int *st) {
+  int a0 = -1, a1 = -1;
+  for (int e = 0; e < 3; ++e)
+    if (e != d) { if (a0 < 0) a0 = e; else a1 = e; }
+  const int v0 = l % ext[a0], v1 = l / ext[a0];
+  return v0 * st[a0] + v1 * st[a1];
+}
+
+// Solve the interior-face system of one line of n cells: faces j = 1..n-1,
+// diagonal (m[j-1] + m[j]) / 3, coupling of faces j and j+1 through cell j:
+// m[j] / 6.  y[1..n-1] holds the right-hand side on entry, the solution on exit.
+__device__ __forceinline__ void line_solve(int n, const double *m, double *y) {
+  double cp[MAXLINE];
+  if (n < 2) return;
+  double den = (m[0] + m[1]) / 3.0;
+  cp[1] = (n > 2) ? (m[1] / 6.0) / den : 0.0;
+  y[1] = y[1] / den;
+  for (int j = 2; j <= n - 1; ++j) {
+    const double e = m[j - 1] / 6.0;
+    den = (m[j - 1] + m[j]) / 3.0 - e * cp[j - 1];
+    cp[j] = (j <= n - 2) ? (m[j] / 6.0) / den : 0.0;
+    y[j] = (y[j] - e * y[j - 1]) / den;
+  }
+  for (int j = n - 2; j >= 1; --j) y[j] -= cp[j] * y[j + 1];
+}
+
+// (B_l y)[c] for the line's cells: cell c has -d face c (B = +1) and +d face
+// c+1 (B = -1); only interior faces 1..n-1 carry y.
+__device__ __forceinline__ double line_B(int n, const double *y, int c) {
+  double v = 0.0;
+  if (c >= 1) v += y[c];
+  if (c + 1 <= n - 1) v -= y[c + 1];
+  return v;
+}
+
+__global__ void k_cell_coef(DevGeom g, const double *__restrict__ perm, int64_t ncells,
+                            double *__restrict__ mcoef, int *err) {
+  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= ncells) return;
+  for (int d = 0; d < 3; ++d) {
+    double m = 0.0;
+    if (d < g.dim) {
+      const double k = perm[c * g.dim + d];
+      if (!(k > 0.0) || !isfinite(k)) atomicOr(err, 1);
+      double other = 1.0;
+      for (int e = 0; e < g.dim; ++e)
+        if (e != d) other *= g.h[e];
+      m = g.h[d] / (k * other);
+    }
+    mcoef[c * 3 + d] = m;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// per-subdomain: d_i, P, H, S_A, L_P, S^i, X^i
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_local_setup(DevGeom g, const double *__restrict__ mcoef,
+                                                     SetupWs ws, double *dscale, int *err) {
+  __shared__ double lds[LDS_DOUBLES];
+  __shared__ double red[8];
+  const int i = blockIdx.x;
+  const int tid = threadIdx.x;
+  int ext[3], lo[3], st[3];
+  for (int d = 0; d < 3; ++d) {
+    ext[d] = g.ext[3 * i + d];
+    lo[d] = g.lo[3 * i + d];
+  }
+  st[0] = 1;
+  st[1] = ext[0];
+  st[2] = ext[0] * ext[1];
+  const int nc = g.nc[i], nG = g.nG[i];
+  const int *lcg = g.lcell_global + g.cell_off[i];
+  double *P = ws.base + ws.P[i];
+  double *V = ws.base + ws.V[i];
+  double *H = ws.base + ws.H[i];
+  double *S = ws.base + ws.S[i];
+  double *X = ws.Xmat + ws.X[i];
+  const int64_t goff = g.g_off[i];
+  auto mloc = [&](int lc, int d) { return mcoef[(int64_t)lcg[lc] * 3 + d]; };
+
+  // (1) rescaling: mean of the subdomain's assembled diag(A) over its flux dofs
+  double acc = 0.0;
+  int nI = 0;
+  for (int d = 0; d < g.dim; ++d) {
+    const int n = ext[d], lines = nc / n;
+    nI += lines * (n - 1);
+    for (int l = tid; l < lines; l += WG) {
+      const int s0 = line_start(d, l, ext, st);
+      for (int j = 1; j <= n - 1; ++j)
+        acc += (mloc(s0 + (j - 1) * st[d], d) + mloc(s0 + j * st[d], d)) / 3.0;
+      if (lo[d] > 0) acc += mloc(s0, d) / 3.0;
+      if (lo[d] + n < g.n[d]) acc += mloc(s0 + (n - 1) * st[d], d) / 3.0;
+    }
+  }
+  const double tot = wg_sum(acc, red);
+  if (tid == 0) dscale[i] = tot / (double)(nI + nG);
+
+  // (2) P = sum over lines of B_l G_l B_l^T
+  for (int e = tid; e < nc * nc; e += WG) P[e] = 0.0;
+  __syncthreads();
+  for (int d = 0; d < g.dim; ++d) {
+    const int n = ext[d], lines = nc / n;
+    if (n >= 2) {
+      for (int it = tid; it < lines * n; it += WG) {
+        const int l = it / n, c = it % n;
+        const int s0 = line_start(d, l, ext, st);
+        double m[MAXLINE], y[MAXLINE + 1];
+        for (int t = 0; t < n; ++t) m[t] = mloc(s0 + t * st[d], d);
+        for (int j = 0; j <= n; ++j) y[j] = 0.0;
+        if (c >= 1) y[c] += 1.0;
+        if (c + 1 <= n - 1) y[c + 1] -= 1.0;
+        line_solve(n, m, y);
+        const int colc = s0 + c * st[d];
+        for (int cp = 0; cp < n; ++cp) P[(s0 + cp * st[d]) + (size_t)colc * nc] += line_B(n, y, cp);
+      }
+    }
+    __syncthreads();
+  }
+
+  // (3) H = B_G - B_I G A_IG (line supported columns), S_A into S, c into H[:, nG]
+  const int ldh = nc;
+  for (int e = tid; e < nc * (nG + 1); e += WG) H[e] = (e >= nc * nG) ? g.vol : 0.0;
+  for (int e = tid; e < nG * nG; e += WG) S[e] = 0.0;
+  __syncthreads();
+  for (int t = tid; t < nG; t += WG) {
+    const int64_t fl = goff + t;
+    const int d = g.lg_dir[fl], lc = g.lg_cell[fl], end = g.lg_end[fl];
+    const int n = ext[d];
+    const int cd = (lc / st[d]) % n;
+    const int s0 = lc - cd * st[d];
+    double m[MAXLINE], y[MAXLINE + 1];
+    for (int u = 0; u < n; ++u) m[u] = mloc(s0 + u * st[d], d);
+    const int eidx = end ? n - 1 : 0;
+    const double mend = m[eidx];
+    H[(s0 + eidx * st[d]) + (size_t)t * ldh] += end ? -1.0 : 1.0;
+    const int p = g.lg_partner[fl];
+    if (n >= 2) {
+      const int adj = end ? n - 1 : 1, oadj = end ? 1 : n - 1;
+      for (int j = 0; j <= n; ++j) y[j] = 0.0;
+      y[adj] = 1.0;
+      line_solve(n, m, y);
+      for (int cp = 0; cp < n; ++cp)
+        H[(s0 + cp * st[d]) + (size_t)t * ldh] -= (mend / 6.0) * line_B(n, y, cp);
+      S[t + (size_t)t * nG] += mend / 3.0 - (mend / 6.0) * (mend / 6.0) * y[adj];
+      if (p >= 0) {
+        const double moth = m[end ? 0 : n - 1];
+        S[t + (size_t)p * nG] += -(mend / 6.0) * (moth / 6.0) * y[oadj];
+      }
+    } else {
+      S[t + (size_t)t * nG] += mend / 3.0;
+      if (p >= 0) S[t + (size_t)p * nG] += mend / 6.0;
+    }
+  }
+  __syncthreads();
+
+  // (4) P~ = P + (tr P / nc^2) 1 1^T is positive definite (kernel of P = constants)
+  double tr = 0.0;
+  for (int a = tid; a < nc; a += WG) tr += P[a + (size_t)a * nc];
+  tr = wg_sum(tr, red);
+  const double shift = (tr > 0.0) ? tr / ((double)nc * nc) : 1.0;
+  for (int e = tid; e < nc * nc; e += WG) P[e] += shift;
+  __syncthreads();
+  if (wg_potrf(nc, P, nc, lds)) {
+    if (tid == 0) atomicOr(err, 2);
+  }
+  // (5) Y = L_P^{-1} [H c]
+  wg_trsm_lower(nc, nG + 1, P, nc, H, ldh, lds);
+  double *zc = H + (size_t)nG * ldh;
+  double zz = 0.0;
+  for (int a = tid; a < nc; a += WG) zz += zc[a] * zc[a];
+  zz = wg_sum(zz, red);
+  const double zinv = 1.0 / sqrt(zz);
+  for (int a = tid; a < nc; a += WG) zc[a] *= zinv;
+  __syncthreads();
+  // Y' = (I - z z^T) Y  (the projection realises the zero-mean constraint)
+  for (int t = tid; t < nG; t += WG) {
+    double *col = H + (size_t)t * ldh;
+    double dot = 0.0;
+    for (int a = 0; a < nc; ++a) dot += zc[a] * col[a];
+    for (int a = 0; a < nc; ++a) col[a] -= dot * zc[a];
+  }
+  __syncthreads();
+  // (6) S = S_A + Y'^T Y'
+  wg_gemm<true, false, true>(nG, nG, nc, 1.0, H, ldh, H, ldh, 1.0, S, nG, lds);
+  wg_symmetrize_lower(nG, S, nG);
+  // (7) X = V'^T V' with V' = (I - z z^T) L_P^{-1}
+  wg_set_identity(nc, V, nc);
+  wg_trsm_lower(nc, nc, P, nc, V, nc, lds);
+  for (int t = tid; t < nc; t += WG) {
+    double *col = V + (size_t)t * nc;
+    double dot = 0.0;
+    for (int a = 0; a < nc; ++a) dot += zc[a] * col[a];
+    for (int a = 0; a < nc; ++a) col[a] -= dot * zc[a];
+  }
+  __syncthreads();
+  wg_gemm<true, false, true>(nc, nc, nc, 1.0, V, nc, V, nc, 0.0, X, nc, lds);
+  wg_symmetrize_lower(nc, X, nc);
+}
+
+// Cholesky of S^i and W_S = L_S^{-1}; packed copy of S^i for the CG operator.
+__global__ __launch_bounds__(256) void k_schur_factor(DevGeom g, SetupWs ws, int *err) {
+  __shared__ double lds[LDS_DOUBLES];
+  const int i = blockIdx.x;
+  const int nG = g.nG[i];
+  double *S = ws.base + ws.S[i];
+  double *L = ws.base + ws.L[i];
+  double *W = ws.base + ws.W[i];
+  for (int e = threadIdx.x; e < nG * nG; e += WG) L[e] = S[e];
+  double *pk = ws.Spk + ws.pk[i];
+  for (int e = threadIdx.x; e < nG * nG; e += WG) {
+    const int r = e % nG, c = e / nG;
+    if (r >= c) pk[(int64_t)c * nG - (int64_t)c * (c - 1) / 2 + (r - c)] = S[e];
+  }
+  __syncthreads();
+  if (wg_potrf(nG, L, nG, lds)) {
+    if (threadIdx.x == 0) atomicOr(err, 4);
+  }
+  wg_zero_upper(nG, L, nG);
+  wg_set_identity(nG, W, nG);
+  wg_trsm_lower(nG, nG, L, nG, W, nG, lds);
+}
+
+// ---------------------------------------------------------------------------
+// face eigenproblems
+// ---------------------------------------------------------------------------
+// For the face F shared by subdomains i and j the pair problem of eq.
+// eigenvalue-problem-local-matrix has, besides zeros, the eigenvalues of the
+// reduced problem on the jump d = w^i_F - w^j_F restricted to 1^T d = 0:
+//     1/4 Z^T (S^i_FF + S^j_FF) Z y = lambda Z^T ((S^i)^{-1}_FF + (S^j)^{-1}_FF)^{-1} Z y,
+// since (I - E^{ij}) only sees the jump on F and minimising the pair energy for
+// a fixed jump yields the parallel sum of the two face Schur complements.  Z is
+// an orthonormal basis of 1^perp (a Householder reflector).  The row of eq.
+// constraints for eigenvector y is, up to scale and within span{1}, X_F Z y.
+__global__ __launch_bounds__(256) void k_face_eig(DevGeom g, SetupWs ws, double *fbase,
+                                                  const int64_t *foff, double tau, int all_constrained,
+                                                  double *eig_out, const int64_t *eig_off, int *kout,
+                                                  double *omega_out, double *rows_out,
+                                                  const int64_t *rows_off, int *err) {
+  __shared__ double lds[LDS_DOUBLES];
+  __shared__ double jac[512];
+  __shared__ int perm[256];
+  __shared__ double red[8];
+  const int f = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int i = g.f_minus[f], j = g.f_plus[f], n = g.f_n[f];
+  const int oi = g.f_loffm[f], oj = g.f_loffp[f];
+  const int ni = g.nG[i], nj = g.nG[j];
+  const int m = n - 1;
+  double *w = fbase + foff[f];
+  double *XF = w, *XH = w + n * n, *YF = w + 2 * n * n, *T1 = w + 3 * n * n, *T2 = w + 4 * n * n,
+         *U = w + 5 * n * n, *v = w + 6 * n * n;
+  double *rows = rows_out + rows_off[f];
+  double *eig = eig_out + eig_off[f];
+  const double beta = 2.0 / ((1.0 + sqrt((double)n)) * (1.0 + sqrt((double)n)) + (double)(n - 1));
+  for (int a = tid; a < n; a += WG) v[a] = (a == 0) ? 1.0 + sqrt((double)n) : 1.0;
+  __syncthreads();
+  if (m == 0) {
+    if (tid == 0) { kout[f] = 0; omega_out[f] = 0.0; }
+    return;
+  }
+  if (all_constrained) {
+    // every interface dof constrained: rows = the reflector basis of 1^perp
+    for (int e = tid; e < m * n; e += WG) {
+      const int l = e / n, a = e % n;
+      rows[e] = ((a == l + 1) ? 1.0 : 0.0) - beta * v[a] * v[l + 1];
+    }
+    for (int a = tid; a < m; a += WG) eig[a] = 0.0;
+    if (tid == 0) { kout[f] = m; omega_out[f] = 0.0; }
+    return;
+  }
+  const double *Si = ws.base + ws.S[i], *Sj = ws.base + ws.S[j];
+  const double *Wi = ws.base + ws.W[i], *Wj = ws.base + ws.W[j];
+  // X_F = S^i_FF + S^j_FF
+  for (int e = tid; e < n * n; e += WG) {
+    const int a = e % n, b = e / n;
+    XF[e] = Si[(oi + a) + (size_t)(oi + b) * ni] + Sj[(oj + a) + (size_t)(oj + b) * nj];
+  }
+  // (S^{-1})_FF = W[:,F]^T W[:,F], summed over the two sides
+  wg_gemm<true, false>(n, n, ni, 1.0, Wi + (size_t)oi * ni, ni, Wi + (size_t)oi * ni, ni, 0.0, T1, n, lds);
+  wg_gemm<true, false>(n, n, nj, 1.0, Wj + (size_t)oj * nj, nj, Wj + (size_t)oj * nj, nj, 1.0, T1, n, lds);
+  // Y_F = T1^{-1} via Cholesky
+  if (wg_potrf(n, T1, n, lds)) {
+    if (tid == 0) atomicOr(err, 8);
+  }
+  wg_zero_upper(n, T1, n);
+  wg_set_identity(n, T2, n);
+  wg_trsm_lower(n, n, T1, n, T2, n, lds);
+  wg_gemm<true, false>(n, n, n, 1.0, T2, n, T2, n, 0.0, YF, n, lds);
+  // two-sided reflector on copies: M <- H M H
+  for (int e = tid; e < n * n; e += WG) XH[e] = XF[e];
+  __syncthreads();
+  for (int pass = 0; pass < 2; ++pass) {
+    double *M = pass ? YF : XH;
+    // p = beta M v (into U[:,0]), Kc = beta v.p / 2, wv = p - Kc v (into U[:,1])
+    for (int r = tid; r < n; r += WG) {
+      double s = 0.0;
+      for (int c = 0; c < n; ++c) s += M[r + (size_t)c * n] * v[c];
+      U[r] = beta * s;
+    }
+    __syncthreads();
+    double vp = 0.0;
+    for (int r = tid; r < n; r += WG) vp += v[r] * U[r];
+    vp = wg_sum(vp, red);
+    const double Kc = beta * vp / 2.0;
+    for (int r = tid; r < n; r += WG) U[n + r] = U[r] - Kc * v[r];
+    __syncthreads();
+    for (int e = tid; e < n * n; e += WG) {
+      const int r = e % n, c = e / n;
+      M[e] -= v[r] * U[n + c] + U[n + r] * v[c];
+    }
+    __syncthreads();
+  }
+  // reduced m x m problems: T1 = Yr, T2 = Xr / 4
+  for (int e = tid; e < m * m; e += WG) {
+    const int r = e % m, c = e / m;
+    T1[e] = YF[(r + 1) + (size_t)(c + 1) * n];
+    T2[e] = 0.25 * XH[(r + 1) + (size_t)(c + 1) * n];
+  }
+  __syncthreads();
+  if (wg_potrf(m, T1, m, lds)) {
+    if (tid == 0) atomicOr(err, 16);
+  }
+  wg_zero_upper(m, T1, m);
+  wg_trsm_lower(m, m, T1, m, T2, m, lds);           // B1 = L^{-1} Xr
+  for (int e = tid; e < m * m; e += WG) {
+    const int r = e % m, c = e / m;
+    U[e] = T2[c + (size_t)r * m];                    // U = B1^T
+  }
+  __syncthreads();
+  wg_trsm_lower(m, m, T1, m, U, m, lds);             // C = L^{-1} Xr L^{-T}
+  for (int e = tid; e < m * m; e += WG) {
+    const int r = e % m, c = e / m;
+    if (r > c) {
+      const double s = 0.5 * (U[e] + U[c + (size_t)r * m]);
+      U[e] = s;
+      U[c + (size_t)r * m] = s;
+    }
+  }
+  __syncthreads();
+  wg_jacobi(m, U, m, T2, m, jac, perm);
+  // sort eigenvalues descending (rank by count, ties by index)
+  for (int t = tid; t < m; t += WG) {
+    const double lt = U[t + (size_t)t * m];
+    int rank = 0;
+    for (int s = 0; s < m; ++s) {
+      const double ls = U[s + (size_t)s * m];
+      if (ls > lt || (ls == lt && s < t)) ++rank;
+    }
+    eig[rank] = lt;
+    perm[rank] = t;
+  }
+  __syncthreads();
+  int k = 0;
+  if (tau > 0.0 && isfinite(tau)) {
+    for (int t = 0; t < m; ++t)
+      if (eig[t] > tau) ++k;
+  }
+  if (tid == 0) {
+    kout[f] = k;
+    omega_out[f] = (k < m) ? eig[k] : 0.0;
+  }
+  if (k == 0) return;
+  // eigenvectors of the generalized problem: y = L^{-T} u  (gathered into YF, ld m)
+  for (int e = tid; e < m * k; e += WG) {
+    const int r = e % m, l = e / m;
+    YF[r + (size_t)l * m] = T2[r + (size_t)perm[l] * m];
+  }
+  __syncthreads();
+  wg_trsm_lower_t(m, k, T1, m, YF, m, lds);
+  // delta = H [0; y]  (into XH, ld n)
+  for (int l = 0; l < k; ++l) {
+    double s = 0.0;
+    for (int r = tid; r < m; r += WG) s += v[r + 1] * YF[r + (size_t)l * m];
+    s = wg_sum(s, red);
+    for (int a = tid; a < n; a += WG)
+      XH[a + (size_t)l * n] = ((a > 0) ? YF[(a - 1) + (size_t)l * m] : 0.0) - beta * v[a] * s;
+    __syncthreads();
+  }
+  // rows = X_F delta, projected onto 1^perp and orthonormalised (two Gram-Schmidt passes)
+  wg_gemm<false, false>(n, k, n, 1.0, XF, n, XH, n, 0.0, T2, n, lds);
+  for (int l = 0; l < k; ++l) {
+    double *r = T2 + (size_t)l * n;
+    double mean = 0.0;
+    for (int a = tid; a < n; a += WG) mean += r[a];
+    mean = wg_sum(mean, red) / n;
+    for (int a = tid; a < n; a += WG) r[a] -= mean;
+    __syncthreads();
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int q = 0; q < l; ++q) {
+        const double *rq = T2 + (size_t)q * n;
+        double dot = 0.0;
+        for (int a = tid; a < n; a += WG) dot += rq[a] * r[a];
+        dot = wg_sum(dot, red);
+        for (int a = tid; a < n; a += WG) r[a] -= dot * rq[a];
+        __syncthreads();
+      }
+    }
+    double nrm = 0.0;
+    for (int a = tid; a < n; a += WG) nrm += r[a] * r[a];
+    nrm = sqrt(wg_sum(nrm, red));
+    for (int a = tid; a < n; a += WG) {
+      r[a] /= nrm;
+      rows[(size_t)l * n + a] = r[a];
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// local coarse space: Psi^i, A_c^i, T^i
+// ---------------------------------------------------------------------------
+// With S = L L^T, W = L^{-1} and the constraint rows C of the subdomain:
+// V = W C^T = Q R,  Psi = S^{-1} C^T (C S^{-1} C^T)^{-1} = W^T Q R^{-T},
+// A_c^i = (C S^{-1} C^T)^{-1} = R^{-1} R^{-T},
+// T = S^{-1} - Psi C S^{-1} = W'^T W' with W' = (I - Q Q^T) W.
+struct CoarseLocalWs {
+  double *base;
+  const int64_t *off;     // per subdomain workspace offset
+  double *Ac;             // A_c^i blocks
+  const int64_t *ac_off;
+  double *psi64;
+  float *psi32;
+  const int64_t *psi_off;
+  double *t64;
+  float *t32;
+  const int64_t *pk;      // packed offsets (same as S)
+};
+
+__global__ __launch_bounds__(256) void k_coarse_local(DevGeom g, SetupWs ws, DevCoarse cs,
+                                                      CoarseLocalWs cw, int *err) {
+  __shared__ double lds[LDS_DOUBLES];
+  __shared__ double red[8];
+  const int i = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int nG = g.nG[i];
+  const int c0 = cs.sub_coff[i];
+  const int nci = cs.sub_coff[i + 1] - c0;
+  double *W = ws.base + ws.W[i];
+  double *Tfull = ws.base + ws.L[i];
+  double *base = cw.base + cw.off[i];
+  double *C = base;                         // nci x nG
+  double *Q = C + (size_t)nci * nG;         // nG x nci
+  double *R = Q + (size_t)nG * nci;         // nci x nci
+  double *U = R + (size_t)nci * nci;        // nG x nci
+  double *M1 = U + (size_t)nG * nci;        // nci x nG
+  double *Rinv = M1 + (size_t)nci * nG;     // nci x nci
+  double *Ac = cw.Ac + cw.ac_off[i];
+  double *Psi = cw.psi64 + cw.psi_off[i];
+
+  for (int e = tid; e < nci * nG; e += WG) C[e] = 0.0;
+  for (int e = tid; e < nci * nci; e += WG) R[e] = 0.0;
+  __syncthreads();
+  {
+    int r0 = 0;
+    for (int t = g.sub_face_off[i]; t < g.sub_face_off[i + 1]; ++t) {
+      const int f = g.sub_faces[t];
+      const int n = g.f_n[f];
+      const int off = (g.f_minus[f] == i) ? g.f_loffm[f] : g.f_loffp[f];
+      const int k = cs.face_k[f];
+      const double *rows = cs.face_rows + cs.face_rows_off[f];
+      for (int e = tid; e < (k + 1) * n; e += WG) {
+        const int l = e / n, a = e % n;
+        C[(r0 + l) + (size_t)(off + a) * nci] = (l == 0) ? 1.0 : rows[(size_t)(l - 1) * n + a];
+      }
+      r0 += k + 1;
+    }
+    __syncthreads();
+  }
+  // V = W C^T into Q
+  wg_gemm<false, true>(nG, nci, nG, 1.0, W, nG, C, nci, 0.0, Q, nG, lds);
+  // classical Gram-Schmidt, two passes per column
+  for (int jc = 0; jc < nci; ++jc) {
+    double *qj = Q + (size_t)jc * nG;
+    for (int pass = 0; pass < 2; ++pass) {
+      // d_k = q_k . q_j for k < j (thread per k)
+      for (int kk = tid; kk < jc; kk += WG) {
+        const double *qk = Q + (size_t)kk * nG;
+        double s = 0.0;
+        for (int r = 0; r < nG; ++r) s += qk[r] * qj[r];
+        lds[kk] = s;
+      }
+      __syncthreads();
+      for (int kk = tid; kk < jc; kk += WG) R[kk + (size_t)jc * nci] += lds[kk];
+      for (int r = tid; r < nG; r += WG) {
+        double s = qj[r];
+        for (int kk = 0; kk < jc; ++kk) s -= Q[r + (size_t)kk * nG] * lds[kk];
+        qj[r] = s;
+      }
+      __syncthreads();
+    }
+    double nrm = 0.0;
+    for (int r = tid; r < nG; r += WG) nrm += qj[r] * qj[r];
+    nrm = sqrt(wg_sum(nrm, red));
+    if (!(nrm > 0.0)) {
+      if (tid == 0) atomicOr(err, 32);
+      nrm = 1.0;
+    }
+    if (tid == 0) R[jc + (size_t)jc * nci] = nrm;
+    for (int r = tid; r < nG; r += WG) qj[r] /= nrm;
+    __syncthreads();
+  }
+  // U = Q R^{-T} (row-wise backward substitution)
+  for (int r = tid; r < nG; r += WG) {
+    for (int jj = nci - 1; jj >= 0; --jj) {
+      double s = Q[r + (size_t)jj * nG];
+      for (int l = jj + 1; l < nci; ++l) s -= U[r + (size_t)l * nG] * R[jj + (size_t)l * nci];
+      U[r + (size_t)jj * nG] = s / R[jj + (size_t)jj * nci];
+    }
+  }
+  __syncthreads();
+  // Psi = W^T U
+  wg_gemm<true, false>(nG, nci, nG, 1.0, W, nG, U, nG, 0.0, Psi, nG, lds);
+  for (int e = tid; e < nG * nci; e += WG) cw.psi32[cw.psi_off[i] + e] = (float)Psi[e];
+  // R^{-1} (column-wise backward substitution), A_c^i = R^{-1} R^{-T}
+  for (int c = tid; c < nci; c += WG) {
+    for (int r = nci - 1; r >= 0; --r) {
+      double s = (r == c) ? 1.0 : 0.0;
+      if (r > c) { Rinv[r + (size_t)c * nci] = 0.0; continue; }
+      for (int l = r + 1; l <= c; ++l) s -= R[r + (size_t)l * nci] * Rinv[l + (size_t)c * nci];
+      Rinv[r + (size_t)c * nci] = s / R[r + (size_t)r * nci];
+    }
+  }
+  __syncthreads();
+  wg_gemm<false, true>(nci, nci, nci, 1.0, Rinv, nci, Rinv, nci, 0.0, Ac, nci, lds);
+  // W' = W - Q (Q^T W);  T = W'^T W'
+  wg_gemm<true, false>(nci, nG, nG, 1.0, Q, nG, W, nG, 0.0, M1, nci, lds);
+  wg_gemm<false, false>(nG, nG, nci, -1.0, Q, nG, M1, nci, 1.0, W, nG, lds);
+  wg_gemm<true, false, true>(nG, nG, nG, 1.0, W, nG, W, nG, 0.0, Tfull, nG, lds);
+  const int64_t po = cw.pk[i];
+  for (int e = tid; e < nG * nG; e += WG) {
+    const int r = e % nG, c = e / nG;
+    if (r >= c) {
+      const int64_t k = po + (int64_t)c * nG - (int64_t)c * (c - 1) / 2 + (r - c);
+      const double t = Tfull[e];
+      cw.t64[k] = t;
+      cw.t32[k] = (float)t;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// coarse saddle point
+// ---------------------------------------------------------------------------
+// Unknowns: flux coarse dofs (face by face) then the rescaled subdomain
+// pressures of subdomains 0..N-2; the last pressure is pinned (the pressure
+// block of the coarse problem is singular along the constants, Q_0 has zero
+// mean; pinning changes p_0 by a constant only).  Each flux coarse dof belongs
+// to exactly two subdomains, so the two contributions to an entry commute
+// exactly and the atomic sum is deterministic.
+__global__ __launch_bounds__(256) void k_coarse_assemble(DevGeom g, DevCoarse cs, const double *Ac,
+                                                         const int64_t *ac_off, const double *dscale,
+                                                         double *K) {
+  const int i = blockIdx.x;
+  const int nk = cs.nk;
+  const int c0 = cs.sub_coff[i];
+  const int nci = cs.sub_coff[i + 1] - c0;
+  const double *A = Ac + ac_off[i];
+  for (int e = threadIdx.x; e < nci * nci; e += WG) {
+    const int a = e % nci, b = e / nci;
+    const int ga = cs.sub_cmap[c0 + a], gb = cs.sub_cmap[c0 + b];
+    atomicAdd(&K[ga + (size_t)gb * nk], A[e]);
+  }
+  if (i < g.N - 1) {
+    for (int t = g.sub_face_off[i] + threadIdx.x; t < g.sub_face_off[i + 1]; t += WG) {
+      const int f = g.sub_faces[t];
+      const double s = (g.f_minus[f] == i) ? 1.0 : -1.0;   // +1: face orientation leaves Omega^i
+      const double val = -dscale[i] * s;
+      const int jf = cs.face_cofs[f];
+      const int pi = cs.ncu + i;
+      K[pi + (size_t)jf * nk] = val;
+      K[jf + (size_t)pi * nk] = val;
+    }
+  }
+}
+
+// Signed Cholesky K = L diag(s) L^T (s = +1 on flux, -1 on pressure) and the
+// explicit inverse K^{-1} = L^{-T} diag(s) L^{-1}, FP64 and FP32 copies.
+__global__ __launch_bounds__(256) void k_coarse_factor(int nk, int ncu, double *K, double *Wb,
+                                                       double *Kinv, float *Kinv32, double *sgn,
+                                                       int *err) {
+  __shared__ double lds[LDS_DOUBLES];
+  for (int r = threadIdx.x; r < nk; r += WG) sgn[r] = (r < ncu) ? 1.0 : -1.0;
+  __syncthreads();
+  if (wg_potrf(nk, K, nk, lds, sgn)) {
+    if (threadIdx.x == 0) atomicOr(err, 64);
+  }
+  wg_zero_upper(nk, K, nk);
+  wg_set_identity(nk, Wb, nk);
+  wg_trsm_lower(nk, nk, K, nk, Wb, nk, lds);
+  wg_gemm<true, false>(nk, nk, nk, 1.0, Wb, nk, Wb, nk, 0.0, Kinv, nk, lds, sgn);
+  for (int64_t e = threadIdx.x; e < (int64_t)nk * nk; e += WG) Kinv32[e] = (float)Kinv[e];
+}
+
+}  // namespace bddc

@@ -1,0 +1,599 @@
+// Solve kernels: Algorithm "BDDC method" steps 1-3 on the device.
+//
+// Step 3 is conjugate gradients on the interface saddle point of eqs.
+// corr-reduced-1/2 in the balanced subspace: the operator is
+// (S x_u + B_0^T x_p, B_0 x_u), the preconditioner is Algorithm "BDDC
+// preconditioner" (restriction with multiplicity weights 1/2, local
+// substructure correction T^i, coarse correction through Psi^i and the coarse
+// saddle point, averaging E).  The flux iterates stay balanced, so the
+// pressure component of the residual stays zero and is not stored.
+//
+// Reductions are deterministic: every producer writes one partial per block,
+// every consumer block re-adds the partials in the same fixed order.
+#include "common.hpp"
+#include "dense.hpp"
+
+namespace bddc {
+
+struct CgState {
+  double rho, rho_next, r0sq, rtol2, relres;
+  int it;        // iterations whose updates are complete and advanced
+  int nupd;      // x/r updates performed
+  int done;      // stop flag read by every kernel of the loop
+  int converged;
+  int fail;      // 1: breakdown
+  int maxit;
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__device__ __forceinline__ double block_sum_partials(const double *__restrict__ part, int n, double *red) {
+  double s = 0.0;
+  for (int k = threadIdx.x; k < n; k += blockDim.x) s += part[k];
+  s = wave_sum(s);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) red[w] = s;
+  __syncthreads();
+  double t = 0.0;
+  for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += red[k];
+  __syncthreads();
+  return t;
+}
+
+__device__ __forceinline__ void block_write_partial(double v, double *part, double *red) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += red[k];
+    part[blockIdx.x] = t;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// local symmetric operator: y^i = M^i (xscale R^i x), M packed lower column
+// major.  Optionally also g^i = Psi^{iT} (xscale R^i x).
+// Column j of the packed matrix holds rows j..n-1 contiguously; each wave
+// streams whole columns (coalesced), accumulating the strictly-lower product
+// lane-locally in its own LDS row buffer and the transposed product by a wave
+// reduction.  If `check` is set the block first evaluates the stopping test
+// from the residual partials of the previous kernel.
+// ---------------------------------------------------------------------------
+template <typename TS, bool WITH_PSI>
+__global__ __launch_bounds__(256) void k_symv(DevGeom g, const TS *__restrict__ M, const int64_t *__restrict__ pk,
+                                              const double *__restrict__ x, double xscale,
+                                              double *__restrict__ yloc, const TS *__restrict__ Psi,
+                                              const int64_t *__restrict__ psi_off,
+                                              const int *__restrict__ sub_coff, double *__restrict__ gloc,
+                                              CgState *st, const double *__restrict__ rpart, int nrpart) {
+  extern __shared__ double sh[];
+  __shared__ double red[8];
+  if (st) {
+    if (st->done) return;
+    if (rpart) {
+      const double rn2 = block_sum_partials(rpart, nrpart, red);
+      const bool conv = rn2 <= st->rtol2 * st->r0sq;
+      const bool cap = st->nupd >= st->maxit;
+      if (conv || cap || !isfinite(rn2)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+          st->done = 1;
+          st->converged = conv ? 1 : 0;
+          st->relres = st->r0sq > 0.0 ? sqrt(rn2 / st->r0sq) : 0.0;
+          if (!isfinite(rn2)) st->fail = 1;
+        }
+        return;
+      }
+    }
+  }
+  const int i = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int n = g.nG[i];
+  const int64_t go = g.g_off[i];
+  double *xs = sh;
+  double *yw = sh + n;
+  for (int r = tid; r < n; r += 256) xs[r] = xscale * x[g.Rmap[go + r]];
+  for (int e = tid; e < 4 * n; e += 256) yw[e] = 0.0;
+  __syncthreads();
+  const TS *Mi = M + pk[i];
+  double *yme = yw + wv * n;
+  for (int j = wv; j < n; j += 4) {
+    const TS *col = Mi + (int64_t)j * n - (int64_t)j * (j - 1) / 2;
+    const int len = n - j;
+    const double xj = xs[j];
+    double dot = 0.0;
+    for (int t = lane; t < len; t += 64) {
+      const double a = (double)col[t];
+      dot = fma(a, xs[j + t], dot);
+      if (t > 0) yme[j + t] = fma(a, xj, yme[j + t]);
+    }
+    dot = wave_sum(dot);
+    if (lane == 0) yme[j] += dot;
+  }
+  __syncthreads();
+  for (int r = tid; r < n; r += 256) yloc[go + r] = yw[r] + yw[n + r] + yw[2 * n + r] + yw[3 * n + r];
+  if (WITH_PSI) {
+    const int c0 = sub_coff[i], nci = sub_coff[i + 1] - c0;
+    const TS *P = Psi + psi_off[i];
+    for (int c = wv; c < nci; c += 4) {
+      const TS *col = P + (int64_t)c * n;
+      double dot = 0.0;
+      for (int t = lane; t < n; t += 64) dot = fma((double)col[t], xs[t], dot);
+      dot = wave_sum(dot);
+      if (lane == 0) gloc[c0 + c] = dot;
+    }
+  }
+}
+
+// q = assembled local products + B_0^T x_p;  partial of p_u . q
+__global__ __launch_bounds__(256) void k_sys_assemble(DevGeom g, const double *__restrict__ yloc,
+                                                      const double *__restrict__ xp,
+                                                      const double *__restrict__ dscale,
+                                                      const double *__restrict__ pu, double *__restrict__ q,
+                                                      double *part, CgState *st) {
+  __shared__ double red[8];
+  if (st && st->done) return;
+  const int gi = blockIdx.x * 256 + threadIdx.x;
+  double v = 0.0;
+  if (gi < g.nGamma) {
+    const int sm = g.sub_minus[gi], sp = g.sub_plus[gi];
+    double b0 = 0.0;
+    if (xp) b0 = -dscale[sm] * xp[sm] + dscale[sp] * xp[sp];
+    const double qq = yloc[g.own_minus[gi]] + yloc[g.own_plus[gi]] + b0;
+    q[gi] = qq;
+    if (pu) v = pu[gi] * qq;
+  }
+  if (part) block_write_partial(v, part, red);
+}
+
+// alpha = rho / (p.q); x += alpha p; r -= alpha q; partial of r.r
+__global__ __launch_bounds__(256) void k_update_xr(int nGamma, int N, const double *__restrict__ gpart,
+                                                   int ngpart, const double *__restrict__ pu,
+                                                   const double *__restrict__ q, const double *__restrict__ pp,
+                                                   double *xu, double *ru, double *xp, double *rpart,
+                                                   CgState *st, double *alpha_hist) {
+  __shared__ double red[8];
+  if (st->done) return;
+  const double gam = block_sum_partials(gpart, ngpart, red);
+  if (!(gam > 0.0) || !isfinite(gam)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      st->fail = 1;
+      st->done = 1;
+    }
+    return;
+  }
+  const double alpha = st->rho / gam;
+  const int gi = blockIdx.x * 256 + threadIdx.x;
+  double v = 0.0;
+  if (gi < nGamma) {
+    xu[gi] = fma(alpha, pu[gi], xu[gi]);
+    const double r = fma(-alpha, q[gi], ru[gi]);
+    ru[gi] = r;
+    v = r * r;
+  }
+  if (blockIdx.x == 0) {
+    for (int k = threadIdx.x; k < N; k += 256) xp[k] = fma(alpha, pp[k], xp[k]);
+    if (threadIdx.x == 0) {
+      alpha_hist[st->it] = alpha;
+      st->nupd = st->it + 1;
+    }
+  }
+  block_write_partial(v, rpart, red);
+}
+
+// coarse right-hand side: each flux coarse dof gathers its two local values
+__global__ void k_coarse_rhs(DevCoarse cs, const double *__restrict__ gloc, double *__restrict__ b,
+                             const CgState *st) {
+  if (st && st->done) return;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < cs.ncu) b[j] = gloc[cs.co_minus[j]] + gloc[cs.co_plus[j]];
+}
+
+// x = K^{-1}[:, :ncols] b  (K^{-1} symmetric; column r read contiguously), one wave per row
+template <typename TK>
+__global__ __launch_bounds__(256) void k_coarse_gemv(int nk, int ncols, const TK *__restrict__ Kinv,
+                                                     const double *__restrict__ b, double *__restrict__ x,
+                                                     const CgState *st) {
+  if (st && st->done) return;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= nk) return;
+  const TK *col = Kinv + (int64_t)row * nk;
+  double s = 0.0;
+  for (int c = lane; c < ncols; c += 64) s = fma((double)col[c], b[c], s);
+  s = wave_sum(s);
+  if (lane == 0) x[row] = s;
+}
+
+// w^i = y^i + Psi^i alpha^(i)  (y may be null)
+template <typename TS>
+__global__ __launch_bounds__(256) void k_psi_correct(DevGeom g, DevCoarse cs, const TS *__restrict__ Psi,
+                                                     const int64_t *__restrict__ psi_off,
+                                                     const double *__restrict__ yloc,
+                                                     const double *__restrict__ csol, double *__restrict__ wloc,
+                                                     const CgState *st) {
+  __shared__ double al[1024];
+  if (st && st->done) return;
+  const int i = blockIdx.x;
+  const int n = g.nG[i];
+  const int64_t go = g.g_off[i];
+  const int c0 = cs.sub_coff[i], nci = cs.sub_coff[i + 1] - c0;
+  for (int c = threadIdx.x; c < nci; c += 256) al[c] = csol[cs.sub_cmap[c0 + c]];
+  __syncthreads();
+  const TS *P = Psi + psi_off[i];
+  for (int r = threadIdx.x; r < n; r += 256) {
+    double s = yloc ? yloc[go + r] : 0.0;
+    for (int c = 0; c < nci; ++c) s = fma((double)P[r + (int64_t)c * n], al[c], s);
+    wloc[go + r] = s;
+  }
+}
+
+// z = E w (weights 1/2), then each face total is set to the face's
+// zero-net-flux coarse dof (a no-op in exact arithmetic, since C^i T^i = 0 and
+// C^i Psi^i = I; it keeps the output balanced to rounding).  One block per
+// face; optional partial of r . z.
+__global__ __launch_bounds__(256) void k_average_balance(DevGeom g, DevCoarse cs,
+                                                         const double *__restrict__ wloc,
+                                                         const double *__restrict__ csol, double *__restrict__ z,
+                                                         const double *__restrict__ r, double *part,
+                                                         const CgState *st) {
+  __shared__ double red[8];
+  if (st && st->done) return;
+  const int f = blockIdx.x;
+  const int n = g.f_n[f];
+  const int64_t base = g.g_off[g.f_minus[f]] + g.f_loffm[f];
+  double tsum = 0.0;
+  for (int a = threadIdx.x; a < n; a += 256) {
+    const int gi = g.Rmap[base + a];
+    tsum += 0.5 * (wloc[base + a] + wloc[g.own_plus[gi]]);
+  }
+  tsum = wave_sum(tsum);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = tsum;
+  __syncthreads();
+  const double tot = red[0] + red[1] + red[2] + red[3];
+  __syncthreads();
+  const double corr = (csol[cs.face_cofs[f]] - tot) / n;
+  double v = 0.0;
+  for (int a = threadIdx.x; a < n; a += 256) {
+    const int gi = g.Rmap[base + a];
+    const double zz = 0.5 * (wloc[base + a] + wloc[g.own_plus[gi]]) + corr;
+    z[gi] = zz;
+    if (r) v += r[gi] * zz;
+  }
+  if (part) block_write_partial(v, part, red);
+}
+
+// beta = rho' / rho; p = z + beta p (flux and coarse pressure)
+__global__ __launch_bounds__(256) void k_update_p(int nGamma, int N, int ncu, const double *__restrict__ zpart,
+                                                  int nzpart, const double *__restrict__ zu,
+                                                  const double *__restrict__ csol, double *pu, double *pp,
+                                                  CgState *st, double *beta_hist) {
+  __shared__ double red[8];
+  if (st->done) return;
+  const double rn = block_sum_partials(zpart, nzpart, red);
+  const double beta = rn / st->rho;
+  const int gi = blockIdx.x * 256 + threadIdx.x;
+  if (gi < nGamma) pu[gi] = fma(beta, pu[gi], zu[gi]);
+  if (blockIdx.x == 0) {
+    for (int k = threadIdx.x; k < N; k += 256) {
+      const double zp = (k < N - 1) ? csol[ncu + k] : 0.0;
+      pp[k] = fma(beta, pp[k], zp);
+    }
+    if (threadIdx.x == 0) {
+      beta_hist[st->it] = beta;
+      st->rho_next = rn;
+    }
+  }
+}
+
+__global__ void k_advance(CgState *st) {
+  if (st->done) return;
+  st->rho = st->rho_next;
+  st->it += 1;
+}
+
+// initial direction p = z, rho = r.z, ||r_0||^2
+__global__ __launch_bounds__(256) void k_init_p(int nGamma, int N, int ncu, const double *__restrict__ zpart,
+                                                int nzpart, const double *__restrict__ rpart, int nrpart,
+                                                const double *__restrict__ zu, const double *__restrict__ csol,
+                                                double *pu, double *pp, CgState *st, double rtol, int maxit) {
+  __shared__ double red[8];
+  const double rn = block_sum_partials(zpart, nzpart, red);
+  const double r0 = block_sum_partials(rpart, nrpart, red);
+  const int gi = blockIdx.x * 256 + threadIdx.x;
+  if (gi < nGamma) pu[gi] = zu[gi];
+  if (blockIdx.x == 0) {
+    for (int k = threadIdx.x; k < N; k += 256) pp[k] = (k < N - 1) ? csol[ncu + k] : 0.0;
+    if (threadIdx.x == 0) {
+      st->rho = rn;
+      st->rho_next = rn;
+      st->r0sq = r0;
+      st->rtol2 = rtol * rtol;
+      st->relres = 1.0;
+      st->it = 0;
+      st->nupd = 0;
+      st->converged = (r0 == 0.0) ? 1 : 0;
+      st->done = (r0 == 0.0) ? 1 : 0;
+      st->fail = 0;
+      st->maxit = maxit;
+    }
+  }
+}
+
+// partial of x.x over a vector
+__global__ __launch_bounds__(256) void k_norm2_partial(int n, const double *__restrict__ x, double *part) {
+  __shared__ double red[8];
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  const double v = (k < n) ? x[k] * x[k] : 0.0;
+  block_write_partial(v, part, red);
+}
+
+__global__ void k_fill(int64_t n, double *x, double v) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k < n) x[k] = v;
+}
+
+__global__ void k_axpby(int n, double a, const double *__restrict__ x, double b, const double *__restrict__ y,
+                        double *__restrict__ out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) out[k] = a * x[k] + b * y[k];
+}
+
+// ---------------------------------------------------------------------------
+// steps 1-2 and the reduced right-hand side
+// ---------------------------------------------------------------------------
+// Coarse right-hand side of step 1: (0, D F_0), F = -source, F_0^i = sum over Omega^i.
+__global__ __launch_bounds__(256) void k_step1_rhs(DevGeom g, int ncu, int nk, const double *__restrict__ src,
+                                                   const double *__restrict__ dscale, double *b) {
+  __shared__ double red[8];
+  const int i = blockIdx.x;
+  const int nc = g.nc[i];
+  const int *lcg = g.lcell_global + g.cell_off[i];
+  double s = 0.0;
+  for (int c = threadIdx.x; c < nc; c += 256) s -= src[lcg[c]];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double t = red[0] + red[1] + red[2] + red[3];
+    if (i < g.N - 1) b[ncu + i] = dscale[i] * t;
+  }
+  if (i == 0)
+    for (int j = threadIdx.x; j < ncu; j += 256) b[j] = 0.0;
+}
+
+__device__ __forceinline__ int line_start_s(int d, int l, const int *ext, const int *st) {
+  int a0 = -1, a1 = -1;
+  for (int e = 0; e < 3; ++e)
+    if (e != d) { if (a0 < 0) a0 = e; else a1 = e; }
+  return (l % ext[a0]) * st[a0] + (l / ext[a0]) * st[a1];
+}
+
+__device__ __forceinline__ void line_solve_s(int n, const double *m, double *y) {
+  double cp[MAXLINE];
+  if (n < 2) return;
+  double den = (m[0] + m[1]) / 3.0;
+  cp[1] = (n > 2) ? (m[1] / 6.0) / den : 0.0;
+  y[1] = y[1] / den;
+  for (int j = 2; j <= n - 1; ++j) {
+    const double e = m[j - 1] / 6.0;
+    den = (m[j - 1] + m[j]) / 3.0 - e * cp[j - 1];
+    cp[j] = (j <= n - 2) ? (m[j] / 6.0) / den : 0.0;
+    y[j] = (y[j] - e * y[j - 1]) / den;
+  }
+  for (int j = n - 2; j >= 1; --j) y[j] -= cp[j] * y[j + 1];
+}
+
+// Block GEMV y = X v with X symmetric n x n column major (wave per row).
+__device__ __forceinline__ void block_symgemv(int n, const double *__restrict__ X, const double *v, double *y) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int r = wv; r < n; r += 4) {
+    const double *col = X + (int64_t)r * n;
+    double s = 0.0;
+    for (int c = lane; c < n; c += 64) s = fma(col[c], v[c], s);
+    s = wave_sum(s);
+    if (lane == 0) y[r] = s;
+  }
+  __syncthreads();
+}
+
+// h^i = H^{iT} X^i F^i: the source-dependent part of the reduced right-hand
+// side f* (zero in subdomains without source).
+__global__ __launch_bounds__(256) void k_source_term(DevGeom g, const double *__restrict__ mcoef,
+                                                     const double *__restrict__ Xmat, const int64_t *__restrict__ Xoff,
+                                                     const double *__restrict__ src, double *__restrict__ hloc) {
+  extern __shared__ double sh[];
+  __shared__ int any;
+  const int i = blockIdx.x, tid = threadIdx.x;
+  const int nc = g.nc[i], nG = g.nG[i];
+  const int64_t go = g.g_off[i];
+  const int *lcg = g.lcell_global + g.cell_off[i];
+  double *Fs = sh, *ys = sh + nc;
+  if (tid == 0) any = 0;
+  __syncthreads();
+  for (int c = tid; c < nc; c += 256) {
+    const double v = -src[lcg[c]];
+    Fs[c] = v;
+    if (v != 0.0) any = 1;
+  }
+  __syncthreads();
+  if (!any) {
+    for (int t = tid; t < nG; t += 256) hloc[go + t] = 0.0;
+    return;
+  }
+  block_symgemv(nc, Xmat + Xoff[i], Fs, ys);
+  int ext[3], st[3];
+  for (int d = 0; d < 3; ++d) ext[d] = g.ext[3 * i + d];
+  st[0] = 1; st[1] = ext[0]; st[2] = ext[0] * ext[1];
+  for (int t = tid; t < nG; t += 256) {
+    const int64_t fl = go + t;
+    const int d = g.lg_dir[fl], lc = g.lg_cell[fl], end = g.lg_end[fl];
+    const int n = ext[d];
+    const int cd = (lc / st[d]) % n;
+    const int s0 = lc - cd * st[d];
+    double m[MAXLINE], y[MAXLINE + 1];
+    for (int u = 0; u < n; ++u) m[u] = mcoef[(int64_t)lcg[s0 + u * st[d]] * 3 + d];
+    const int eidx = end ? n - 1 : 0;
+    double v = (end ? -1.0 : 1.0) * ys[s0 + eidx * st[d]];
+    if (n >= 2) {
+      // (G B_l^T y)[adj]: (B_l^T y)_j = y[c_j] - y[c_{j-1}]
+      y[0] = 0.0;
+      for (int j = 1; j <= n - 1; ++j) y[j] = ys[s0 + j * st[d]] - ys[s0 + (j - 1) * st[d]];
+      line_solve_s(n, m, y);
+      const int adj = end ? n - 1 : 1;
+      v -= (m[eidx] / 6.0) * y[adj];
+    }
+    hloc[go + t] = v;
+  }
+}
+
+// f* = -assembled S u0 + assembled h  (step-3 reduced right-hand side)
+__global__ void k_fstar(DevGeom g, const double *__restrict__ yloc, const double *__restrict__ hloc,
+                        double *__restrict__ r) {
+  const int gi = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gi >= g.nGamma) return;
+  const int a = g.own_minus[gi], b = g.own_plus[gi];
+  r[gi] = -(yloc[a] + yloc[b]) + hloc[a] + hloc[b];
+}
+
+// B_0 x per subdomain (diagnostic operator)
+__global__ __launch_bounds__(256) void k_b0(DevGeom g, const double *__restrict__ x, const double *__restrict__ dscale,
+                                            double *__restrict__ y) {
+  __shared__ double red[8];
+  const int i = blockIdx.x;
+  const int64_t go = g.g_off[i];
+  double s = 0.0;
+  for (int t = threadIdx.x; t < g.nG[i]; t += 256) {
+    const double sign = g.lg_end[go + t] ? -1.0 : 1.0;
+    s += sign * x[g.Rmap[go + t]];
+  }
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) y[i] = dscale[i] * (red[0] + red[1] + red[2] + red[3]);
+}
+
+// ---------------------------------------------------------------------------
+// post-correction: interior fluxes and pressures of every subdomain from the
+// final interface flux u_G and the source (local Dirichlet problems)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_recover(DevGeom g, const double *__restrict__ mcoef,
+                                                 const double *__restrict__ Xmat, const int64_t *__restrict__ Xoff,
+                                                 const double *__restrict__ src, const double *__restrict__ uG,
+                                                 const double *__restrict__ xp, const double *__restrict__ dscale,
+                                                 double *__restrict__ flux, double *__restrict__ pressure) {
+  extern __shared__ double sh[];
+  const int i = blockIdx.x, tid = threadIdx.x;
+  const int nc = g.nc[i], nG = g.nG[i];
+  const int64_t go = g.g_off[i];
+  const int *lcg = g.lcell_global + g.cell_off[i];
+  double *ws = sh, *ys = sh + nG, *ps = ys + nc;
+  int ext[3], lo[3], st[3];
+  for (int d = 0; d < 3; ++d) {
+    ext[d] = g.ext[3 * i + d];
+    lo[d] = g.lo[3 * i + d];
+  }
+  st[0] = 1; st[1] = ext[0]; st[2] = ext[0] * ext[1];
+  for (int t = tid; t < nG; t += 256) ws[t] = uG[g.Rmap[go + t]];
+  for (int c = tid; c < nc; c += 256) ys[c] = src[lcg[c]];   // y = H w - F = H w + source
+  __syncthreads();
+  const int *lg = g.line_g + g.line_off[i];
+  int64_t lbase = 0;
+  for (int d = 0; d < g.dim; ++d) {
+    const int n = ext[d], lines = nc / n;
+    for (int l = tid; l < lines; l += 256) {
+      const int s0 = line_start_s(d, l, ext, st);
+      const int tm = lg[lbase + 2 * l], tp = lg[lbase + 2 * l + 1];
+      const double wm = tm >= 0 ? ws[tm] : 0.0, wp = tp >= 0 ? ws[tp] : 0.0;
+      ys[s0] += wm;
+      ys[s0 + (n - 1) * st[d]] -= wp;
+      if (n >= 2 && (tm >= 0 || tp >= 0)) {
+        double m[MAXLINE], y[MAXLINE + 1];
+        for (int u = 0; u < n; ++u) m[u] = mcoef[(int64_t)lcg[s0 + u * st[d]] * 3 + d];
+        for (int j = 0; j <= n; ++j) y[j] = 0.0;
+        y[1] += (m[0] / 6.0) * wm;
+        y[n - 1] += (m[n - 1] / 6.0) * wp;
+        line_solve_s(n, m, y);
+        for (int c = 0; c < n; ++c) {
+          double v = 0.0;
+          if (c >= 1) v += y[c];
+          if (c + 1 <= n - 1) v -= y[c + 1];
+          ys[s0 + c * st[d]] -= v;
+        }
+      }
+    }
+    lbase += 2 * lines;
+    __syncthreads();
+  }
+  block_symgemv(nc, Xmat + Xoff[i], ys, ps);
+  // interior fluxes: u_I = G(-A_IG w - B_I^T p), line by line
+  lbase = 0;
+  for (int d = 0; d < g.dim; ++d) {
+    const int n = ext[d], lines = nc / n;
+    if (n >= 2) {
+      for (int l = tid; l < lines; l += 256) {
+        const int s0 = line_start_s(d, l, ext, st);
+        const int tm = lg[lbase + 2 * l], tp = lg[lbase + 2 * l + 1];
+        const double wm = tm >= 0 ? ws[tm] : 0.0, wp = tp >= 0 ? ws[tp] : 0.0;
+        double m[MAXLINE], y[MAXLINE + 1];
+        for (int u = 0; u < n; ++u) m[u] = mcoef[(int64_t)lcg[s0 + u * st[d]] * 3 + d];
+        y[0] = 0.0;
+        for (int j = 1; j <= n - 1; ++j) y[j] = -(ps[s0 + j * st[d]] - ps[s0 + (j - 1) * st[d]]);
+        y[1] -= (m[0] / 6.0) * wm;
+        y[n - 1] -= (m[n - 1] / 6.0) * wp;
+        line_solve_s(n, m, y);
+        for (int j = 1; j <= n - 1; ++j) {
+          const int lc = s0 + j * st[d];
+          int c[3] = {lo[0] + lc % ext[0], lo[1] + (lc / ext[0]) % ext[1], lo[2] + lc / (ext[0] * ext[1])};
+          const int64_t fid = g.face_off[d] + c[0] + (int64_t)g.fshape[d][0] * (c[1] + (int64_t)g.fshape[d][1] * c[2]);
+          flux[fid] = y[j];
+        }
+      }
+    }
+    lbase += 2 * lines;
+  }
+  const double p0 = (i < g.N - 1) ? dscale[i] * xp[i] : 0.0;
+  for (int c = tid; c < nc; c += 256) pressure[lcg[c]] = ps[c] + p0;
+}
+
+__global__ void k_scatter_iface(int nGamma, const int64_t *__restrict__ gamma_face, const double *__restrict__ uG,
+                                double *__restrict__ flux) {
+  const int gi = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gi < nGamma) flux[gamma_face[gi]] = uG[gi];
+}
+
+__global__ __launch_bounds__(256) void k_sum_partial(int64_t n, const double *__restrict__ x, double *part) {
+  __shared__ double red[8];
+  double s = 0.0;
+  for (int64_t k = blockIdx.x * 256 + threadIdx.x; k < n; k += (int64_t)gridDim.x * 256) s += x[k];
+  block_write_partial(s, part, red);
+}
+
+__global__ __launch_bounds__(256) void k_sub_mean(int64_t n, double *x, const double *__restrict__ part, int npart) {
+  __shared__ double red[8];
+  const double tot = block_sum_partials(part, npart, red);
+  const double mean = tot / (double)n;
+  for (int64_t k = blockIdx.x * 256 + threadIdx.x; k < n; k += (int64_t)gridDim.x * 256) x[k] -= mean;
+}
+
+// explicit instantiations used by the host code
+template __global__ void k_symv<double, false>(DevGeom, const double *, const int64_t *, const double *, double,
+                                               double *, const double *, const int64_t *, const int *, double *,
+                                               CgState *, const double *, int);
+template __global__ void k_symv<double, true>(DevGeom, const double *, const int64_t *, const double *, double,
+                                              double *, const double *, const int64_t *, const int *, double *,
+                                              CgState *, const double *, int);
+template __global__ void k_symv<float, true>(DevGeom, const float *, const int64_t *, const double *, double,
+                                             double *, const float *, const int64_t *, const int *, double *,
+                                             CgState *, const double *, int);
+template __global__ void k_coarse_gemv<double>(int, int, const double *, const double *, double *, const CgState *);
+template __global__ void k_coarse_gemv<float>(int, int, const float *, const double *, double *, const CgState *);
+template __global__ void k_psi_correct<double>(DevGeom, DevCoarse, const double *, const int64_t *, const double *,
+                                               const double *, double *, const CgState *);
+template __global__ void k_psi_correct<float>(DevGeom, DevCoarse, const float *, const int64_t *, const double *,
+                                              const double *, double *, const CgState *);
+
+}  // namespace bddc

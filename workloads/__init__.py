@@ -200,7 +200,7 @@ def unit_square_16(seed=0):
     g = gaussian_field_exact(n, h, 2.0, 0.2, seed)
     k = np.exp(g)
     perm = np.stack([k, k], axis=1)
-    return Problem("square16", n, h, perm, corner_pair(n), regular_cuts(n, (4, 4)),
+    return Problem(f"square16_s{seed}", n, h, perm, corner_pair(n), regular_cuts(n, (4, 4)),
                    tau=math.inf, rtol=1e-10)
 
 
