@@ -75,10 +75,12 @@ typedef struct {
 } bddc_partition;
 
 typedef struct {
-  int32_t precision;   /* BDDC_FP64 or BDDC_MIXED                   */
-  int32_t max_it;      /* CG iteration cap (<= 0: 10000)             */
-  uint32_t flags;      /* BDDC_ALL_CONSTRAINED (diagnostic)          */
-  int32_t reserved;
+  int32_t precision;     /* BDDC_FP64 or BDDC_MIXED                          */
+  int32_t max_it;        /* CG iteration cap (<= 0: 10000)                    */
+  uint32_t flags;        /* BDDC_ALL_CONSTRAINED (diagnostic)                 */
+  int32_t coarse_blocks; /* slab blocks of the coarse factorization; 0: chosen
+                            by a bytes-per-solve model, otherwise clamped to
+                            [1, subdomains along the longest axis]           */
 } bddc_options;
 
 typedef struct {
@@ -95,7 +97,7 @@ typedef struct {
   int32_t n_gamma;          /* interface flux dofs                               */
   int32_t n_faces;          /* subdomain faces                                   */
   int32_t precision;
-  int32_t reserved;
+  int32_t coarse_blocks;    /* slab blocks used by the coarse factorization      */
   double t_setup_ms;        /* wall time of bddc_setup                           */
   double t_solve_ms;        /* wall time of the last bddc_solve                  */
   double t_pcg_ms;          /* device time of the CG loop of the last solve      */

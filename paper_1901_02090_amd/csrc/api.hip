@@ -17,6 +17,7 @@
 #include "layout.hpp"
 #include "setup.hip"
 #include "solve.hip"
+#include "coarse.hip"
 
 using namespace bddc;
 
@@ -48,6 +49,7 @@ struct bddc_problem {
   int precision = BDDC_FP64;
   int max_it = 10000;
   uint32_t flags = 0;
+  int coarse_blocks = 0;
   double tau = 0.0;
   std::vector<void *> allocs;
   double device_bytes = 0;
@@ -63,8 +65,16 @@ struct bddc_problem {
   std::vector<int> sub_coff_h;
 
   double *mcoef = nullptr, *dscale = nullptr;
-  double *Spk = nullptr, *T64 = nullptr, *Psi64 = nullptr, *Xmat = nullptr, *Kinv64 = nullptr;
-  float *T32 = nullptr, *Psi32 = nullptr, *Kinv32 = nullptr;
+  double *Spk = nullptr, *T64 = nullptr, *Psi64 = nullptr, *Xmat = nullptr;
+  float *T32 = nullptr, *Psi32 = nullptr;
+  // coarse factorization (slab blocks)
+  int nblk_c = 0, slab_axis = 0;
+  std::vector<int> boff_h, toff_h;
+  std::vector<int64_t> lr_off, m_off, lc_off;
+  std::vector<int> pidx_h;
+  double *LinvR = nullptr, *LinvC = nullptr, *Mblk = nullptr, *Lcblk = nullptr, *csgn = nullptr, *cy = nullptr,
+         *cu = nullptr;
+  double coarse_bytes = 0.0;
   int64_t *d_pk = nullptr, *d_psi_off = nullptr, *d_Xoff = nullptr, *d_gamma_face = nullptr;
 
   double *xu = nullptr, *ru = nullptr, *pu = nullptr, *zu = nullptr, *qu = nullptr, *u0 = nullptr, *uG = nullptr;
@@ -286,14 +296,69 @@ void do_setup(bddc_problem *h, const bddc_grid *gr, const double *perm, const bd
     h->omega_tilde = std::max(h->omega_tilde, h->face_omega[f]);
   }
 
-  // coarse numbering: face by face, zero-net-flux row first
-  std::vector<int> face_cofs(nF), sub_coff(N + 1, 0), sub_cmap;
-  int ncu = 0;
-  for (int f = 0; f < nF; ++f) {
-    face_cofs[f] = ncu;
-    ncu += 1 + h->face_k[f];
+  // coarse numbering in slab-block order (see coarse.hip).  Slabs are layers of
+  // subdomains along the axis with the most subdomains, merged into G groups;
+  // G minimises the streamed bytes of one coarse solve plus a launch cost.
+  int ax = 0;
+  for (int d = 1; d < dim; ++d)
+    if (L.nsub[d] > L.nsub[ax]) ax = d;
+  const int nl = L.nsub[ax];
+  auto layer_of = [&](int i) { return (i / L.sstride[ax]) % L.nsub[ax]; };
+  auto plan = [&](int G, std::vector<int> &bsz, std::vector<int> &tsz) {
+    bsz.assign(G, 0);
+    tsz.assign(G, 0);
+    for (int f = 0; f < nF; ++f) {
+      const int ga = (int)((int64_t)layer_of(L.f_minus[f]) * G / nl), gb = (int)((int64_t)layer_of(L.f_plus[f]) * G / nl);
+      bsz[ga] += 1 + h->face_k[f];
+      if (ga != gb) tsz[ga] += 1 + h->face_k[f];
+    }
+    for (int i = 0; i < N - 1; ++i) {
+      const int gi = (int)((int64_t)layer_of(i) * G / nl);
+      bsz[gi] += 1;
+      tsz[gi] += 1;
+    }
+  };
+  int G = 1;
+  {
+    double best = 1e300;
+    std::vector<int> bsz, tsz;
+    for (int cand = 1; cand <= nl; ++cand) {
+      plan(cand, bsz, tsz);
+      double by = 0.0;
+      for (int q = 0; q < cand; ++q) {
+        by += (double)bsz[q] * bsz[q];
+        if (q > 0) by += 2.0 * bsz[q] * tsz[q - 1];
+      }
+      const double cost = by * 8.0 / 4.0e12 + (3.0 * cand - 1.0) * 6.0e-6;
+      if (cost < best * 0.999) { best = cost; G = cand; }
+    }
+    if (h->coarse_blocks > 0) G = std::min(h->coarse_blocks, nl);
   }
-  std::vector<int> co_minus(ncu), co_plus(ncu);
+  h->nblk_c = G;
+  h->slab_axis = ax;
+  std::vector<int> face_cofs(nF), sub_coff(N + 1, 0), sub_cmap, pidx(N, -1);
+  std::vector<int> boff(G + 1, 0), toff(G, 0);
+  int ncu = 0, cur = 0;
+  for (int q = 0; q < G; ++q) {
+    boff[q] = cur;
+    for (int pass = 0; pass < 2; ++pass) {     // 0: faces inside the group, 1: faces to group q+1
+      if (pass == 1) toff[q] = cur;
+      for (int f = 0; f < nF; ++f) {
+        const int ga = (int)((int64_t)layer_of(L.f_minus[f]) * G / nl), gb = (int)((int64_t)layer_of(L.f_plus[f]) * G / nl);
+        if (ga != q || (pass == 0) != (ga == gb)) continue;
+        face_cofs[f] = cur;
+        cur += 1 + h->face_k[f];
+        ncu += 1 + h->face_k[f];
+      }
+    }
+    for (int i = 0; i < N - 1; ++i)
+      if ((int)((int64_t)layer_of(i) * G / nl) == q) pidx[i] = cur++;
+  }
+  boff[G] = cur;
+  const int nkc = cur;
+  std::vector<int> co_minus(nkc, -1), co_plus(nkc, -1), blk(nkc, 0);
+  for (int q = 0; q < G; ++q)
+    for (int g2 = boff[q]; g2 < boff[q + 1]; ++g2) blk[g2] = q;
   for (int i = 0; i < N; ++i) {
     for (int t = L.sub_face_off[i]; t < L.sub_face_off[i + 1]; ++t) {
       const int f = L.sub_faces[t];
@@ -310,8 +375,11 @@ void do_setup(bddc_problem *h, const bddc_grid *gr, const double *perm, const bd
       throw Error{BDDC_EINVAL, "more than 1024 coarse dofs on one subdomain"};
   }
   h->ncu = ncu;
-  h->nk = ncu + N - 1;
+  h->nk = nkc;
   h->sub_coff_h = sub_coff;
+  h->boff_h = boff;
+  h->toff_h = toff;
+  h->pidx_h = pidx;
   DevCoarse &cs = h->cs;
   cs.ncu = ncu;
   cs.nk = h->nk;
@@ -323,6 +391,7 @@ void do_setup(bddc_problem *h, const bddc_grid *gr, const double *perm, const bd
   cs.sub_cmap = h->upload(sub_cmap);
   cs.co_minus = h->upload(co_minus);
   cs.co_plus = h->upload(co_plus);
+  cs.pidx = h->upload(pidx);
 
   // S5: local coarse spaces
   std::vector<int64_t> cwoff(N), acoff(N), psioff(N);
@@ -350,23 +419,117 @@ void do_setup(bddc_problem *h, const bddc_grid *gr, const double *perm, const bd
   HIPCHK(hipStreamSynchronize(s));
   check_err(h, "the local coarse spaces");
 
-  // S6: coarse saddle point
+  // S6: coarse saddle point, block signed Cholesky in slab order
   const int nk = h->nk;
   if (nk > 0) {
-    double *K = h->alloc<double>((int64_t)nk * nk);
-    double *Wb = h->alloc<double>((int64_t)nk * nk);
-    double *sgn = h->alloc<double>(nk);
-    h->Kinv64 = h->alloc<double>((int64_t)nk * nk);
-    h->Kinv32 = h->alloc<float>((int64_t)nk * nk);
-    fill(h, K, (int64_t)nk * nk, 0.0);
-    k_coarse_assemble<<<N, 256, 0, s>>>(g, cs, cw.Ac, cw.ac_off, h->dscale, K);
+    std::vector<int64_t> doff(G), eoff(G, 0), lroff(G), moff(G, 0), lcoff(G, 0);
+    int64_t ds = 0, es2 = 0, lrs = 0, ms = 0, lcs = 0;
+    int bmax = 0, tmax = 1;
+    for (int q = 0; q < G; ++q) {
+      const int64_t b = boff[q + 1] - boff[q];
+      const int64_t t = (q + 1 < G) ? boff[q + 1] - toff[q] : 0;
+      bmax = std::max<int>(bmax, (int)b);
+      tmax = std::max<int>(tmax, (int)t);
+      doff[q] = ds; ds += b * b;
+      lroff[q] = lrs; lrs += b * (b + 1) / 2;
+      if (q + 1 < G) {
+        const int64_t bn = boff[q + 2] - boff[q + 1];
+        eoff[q] = es2; es2 += bn * t;
+        lcoff[q] = lcs; lcs += bn * t;
+      }
+      if (q > 0) {
+        const int64_t tp = boff[q] - toff[q - 1];
+        moff[q] = ms; ms += b * tp;
+      }
+    }
+    h->lr_off = lroff;
+    h->m_off = moff;
+    h->lc_off = lcoff;
+    double *Dall = h->alloc<double>(ds);
+    double *Eall = h->alloc<double>(es2);
+    double *Wfull = h->alloc<double>((int64_t)bmax * bmax);
+    double *Mtmp = h->alloc<double>((int64_t)bmax * tmax);
+    h->LinvR = h->alloc<double>(lrs);
+    h->LinvC = h->alloc<double>(lrs);
+    h->Mblk = h->alloc<double>(ms);
+    h->Lcblk = h->alloc<double>(lcs);
+    h->cy = h->alloc<double>(nk);
+    h->cu = h->alloc<double>(tmax);
+    std::vector<double> sg(nk, 1.0);
+    for (int i = 0; i < N; ++i)
+      if (pidx[i] >= 0) sg[pidx[i]] = -1.0;
+    h->csgn = h->upload(sg);
+    fill(h, Dall, ds, 0.0);
+    fill(h, Eall, es2, 0.0);
+    BlockMap bm;
+    bm.J = G;
+    bm.blk = h->upload(blk);
+    bm.boff = h->upload(boff);
+    bm.toff = h->upload(toff);
+    bm.D = Dall;
+    bm.d_off = h->upload(doff);
+    bm.E = Eall;
+    bm.e_off = h->upload(eoff);
+    k_block_assemble<<<N, 256, 0, s>>>(g, cs, bm, cw.Ac, cw.ac_off, h->dscale);
     HIPCHK(hipGetLastError());
-    k_coarse_factor<<<1, 256, 0, s>>>(nk, ncu, K, Wb, h->Kinv64, h->Kinv32, sgn, h->d_err);
-    HIPCHK(hipGetLastError());
+    h->coarse_bytes = 0.0;
+    for (int q = 0; q < G; ++q) {
+      const int b = boff[q + 1] - boff[q];
+      double *Dq = Dall + doff[q];
+      const double *sq = h->csgn + boff[q];
+      if (q > 0) {
+        const int tp = boff[q] - toff[q - 1];
+        dim3 grid(nblk(b, TILE), nblk(b, TILE));
+        k_gemm_tiles<false, true, true><<<grid, 256, 0, s>>>(b, b, tp, -1.0, h->Lcblk + lcoff[q - 1], b,
+                                                             h->Lcblk + lcoff[q - 1], b, 1.0, Dq, b,
+                                                             h->csgn + toff[q - 1]);
+      }
+      if (b <= 512) {
+        k_potrf_one<<<1, 256, 0, s>>>(b, Dq, sq, h->d_err);
+      } else {
+        for (int k0 = 0; k0 < b; k0 += NB) {
+          const int nb = std::min(NB, b - k0);
+          k_potrf_diag<<<1, 256, 0, s>>>(b, Dq, k0, nb, sq, h->d_err);
+          const int rows = b - k0 - nb;
+          if (rows > 0) {
+            k_potrf_panel<<<nblk(rows), 256, 0, s>>>(b, Dq, k0, nb, sq);
+            dim3 grid(nblk(rows, TILE), nblk(rows, TILE));
+            k_gemm_tiles<false, true, true><<<grid, 256, 0, s>>>(rows, rows, nb, -1.0, Dq + (k0 + nb) + (size_t)k0 * b,
+                                                                 b, Dq + (k0 + nb) + (size_t)k0 * b, b, 1.0,
+                                                                 Dq + (k0 + nb) + (size_t)(k0 + nb) * b, b, sq + k0);
+          }
+        }
+      }
+      k_trtri_cols<<<nblk(b, 32), 256, 0, s>>>(b, Dq, Wfull, 32);
+      k_pack_lower<<<nblk((int64_t)b * b), 256, 0, s>>>(b, Wfull, h->LinvR + lroff[q], h->LinvC + lroff[q]);
+      h->coarse_bytes += 8.0 * (double)b * b;
+      if (q > 0) {
+        const int tp = boff[q] - toff[q - 1];
+        dim3 grid(nblk(b, TILE), nblk(tp, TILE));
+        k_gemm_tiles<false, false, false><<<grid, 256, 0, s>>>(b, tp, b, 1.0, Wfull, b, h->Lcblk + lcoff[q - 1], b,
+                                                               0.0, Mtmp, b, nullptr);
+        k_to_rowmajor<<<nblk((int64_t)b * tp), 256, 0, s>>>(b, tp, Mtmp, h->Mblk + moff[q]);
+        h->coarse_bytes += 8.0 * (double)b * tp;
+      }
+      if (q + 1 < G) {
+        const int bn = boff[q + 2] - boff[q + 1];
+        const int t = boff[q + 1] - toff[q];
+        const int ts = toff[q] - boff[q];
+        dim3 grid(nblk(bn, TILE), nblk(t, TILE));
+        k_gemm_tiles<false, true, false><<<grid, 256, 0, s>>>(bn, t, t, 1.0, Eall + eoff[q], bn,
+                                                              Wfull + ts + (size_t)ts * b, b, 0.0,
+                                                              h->Lcblk + lcoff[q], bn, nullptr);
+        k_scale_cols<<<nblk((int64_t)bn * t), 256, 0, s>>>(bn, t, h->Lcblk + lcoff[q], bn, h->csgn + toff[q]);
+        h->coarse_bytes += 8.0 * (double)bn * t;
+      }
+      HIPCHK(hipGetLastError());
+    }
     HIPCHK(hipStreamSynchronize(s));
     check_err(h, "the coarse problem");
-    h->release(K);
-    h->release(Wb);
+    h->release(Dall);
+    h->release(Eall);
+    h->release(Wfull);
+    h->release(Mtmp);
   }
   h->release(wsb);
   h->release(cw.base);
@@ -408,8 +571,31 @@ void do_setup(bddc_problem *h, const bddc_grid *gr, const double *perm, const bd
   // statistics of the operators streamed per iteration
   double sumpk = (double)pks, sumpsi = (double)pss;
   const double sT = h->precision == BDDC_MIXED ? 4.0 : 8.0;
-  h->stats.bytes_prec = sumpk * sT + 2.0 * sumpsi * sT + (double)nk * ncu * 8.0 + 6.0 * totG * 8.0 + 4.0 * nGm * 8.0;
+  h->stats.bytes_prec = sumpk * sT + 2.0 * sumpsi * sT + h->coarse_bytes + 6.0 * totG * 8.0 + 4.0 * nGm * 8.0;
   h->stats.bytes_per_iter = h->stats.bytes_prec + sumpk * 8.0 + 2.0 * totG * 8.0 + 8.0 * nGm * 8.0;
+}
+
+// Coarse solve csol = K^{-1} bc by the block forward / backward sweeps.
+void launch_coarse_solve(bddc_problem *h, const int *done) {
+  hipStream_t s = h->stream;
+  const int G = h->nblk_c;
+  const std::vector<int> &bo = h->boff_h, &to = h->toff_h;
+  for (int q = 0; q < G; ++q) {
+    const int b = bo[q + 1] - bo[q];
+    const int tp = q > 0 ? bo[q] - to[q - 1] : 0;
+    k_cfwd<<<nblk(b, 4), 256, 0, s>>>(b, h->LinvR + h->lr_off[q], h->bc + bo[q], q > 0 ? h->Mblk + h->m_off[q] : nullptr,
+                                      tp, q > 0 ? h->cy + to[q - 1] : nullptr, h->cy + bo[q], done);
+  }
+  for (int q = G - 1; q >= 0; --q) {
+    const int b = bo[q + 1] - bo[q];
+    if (q + 1 < G) {
+      const int bn = bo[q + 2] - bo[q + 1], t = bo[q + 1] - to[q];
+      k_cbwd_u<<<nblk(t, 4), 256, 0, s>>>(bn, t, h->Lcblk + h->lc_off[q], h->csol + bo[q + 1], h->cu, done);
+    }
+    k_cbwd_x<<<nblk(b, 4), 256, 0, s>>>(b, h->LinvC + h->lr_off[q], h->cy + bo[q], h->csgn + bo[q],
+                                        q + 1 < G ? h->cu : nullptr, q + 1 < G ? to[q] - bo[q] : b,
+                                        h->csol + bo[q], done);
+  }
 }
 
 // Preconditioner on r (FP64 or mixed operators) -> zu (and csol for the pressures).
@@ -428,12 +614,13 @@ void launch_precond(bddc_problem *h, const double *r, double *z, double *zpart, 
     k_symv<double, true><<<N, 256, shm, s>>>(h->g, h->T64, h->d_pk, r, 0.5, h->yloc, h->Psi64, h->d_psi_off,
                                              h->cs.sub_coff, h->gloc, st, rp, nrp);
   }
-  if (h->ncu > 0) k_coarse_rhs<<<nblk(h->ncu), 256, 0, s>>>(h->cs, h->gloc, h->bc, st);
   // The coarse solve stays FP64 in both forms: the CG runs in the balanced
   // subspace, so the face-average coarse fluxes must satisfy B_c alpha = 0 to
   // FP64 accuracy (the FP32 local operators are corrected by the balance step).
-  if (h->nk > 0)
-    k_coarse_gemv<double><<<nblk(h->nk, 4), 256, 0, s>>>(h->nk, h->ncu, h->Kinv64, h->bc, h->csol, st);
+  if (h->nk > 0) {
+    k_coarse_rhs<<<nblk(h->nk), 256, 0, s>>>(h->cs, h->gloc, h->bc, st);
+    launch_coarse_solve(h, st ? &st->done : nullptr);
+  }
   if (h->precision == BDDC_MIXED)
     k_psi_correct<float><<<N, 256, 0, s>>>(h->g, h->cs, h->Psi32, h->d_psi_off, h->yloc, h->csol, h->wloc, st);
   else
@@ -453,7 +640,7 @@ void launch_iteration(bddc_problem *h) {
   k_update_xr<<<nb, 256, 0, s>>>(nGm, N, h->part_g, nb, h->pu, h->qu, h->pp, h->xu, h->ru, h->xp, h->part_r,
                                  h->st, h->alpha_h);
   launch_precond(h, h->ru, h->zu, h->part_z, true);
-  k_update_p<<<nb, 256, 0, s>>>(nGm, N, h->ncu, h->part_z, L.nF, h->zu, h->csol, h->pu, h->pp, h->st, h->beta_h);
+  k_update_p<<<nb, 256, 0, s>>>(nGm, N, h->cs.pidx, h->part_z, L.nF, h->zu, h->csol, h->pu, h->pp, h->st, h->beta_h);
   k_advance<<<1, 1, 0, s>>>(h->st);
 }
 
@@ -528,8 +715,9 @@ int do_solve(bddc_problem *h, const double *rhs, double rtol, double *flux, doub
   float pcg_ms = 0.f;
   if (N > 1) {
     // step 1: coarse solve with (0, D F_0), u0 = E Psi alpha
-    k_step1_rhs<<<N, 256, 0, s>>>(h->g, h->ncu, h->nk, src, h->dscale, h->bc);
-    k_coarse_gemv<double><<<nblk(h->nk, 4), 256, 0, s>>>(h->nk, h->nk, h->Kinv64, h->bc, h->csol, nullptr);
+    fill(h, h->bc, h->nk, 0.0);
+    k_step1_rhs<<<N, 256, 0, s>>>(h->g, h->cs.pidx, src, h->dscale, h->bc);
+    launch_coarse_solve(h, nullptr);
     k_psi_correct<double><<<N, 256, 0, s>>>(h->g, h->cs, h->Psi64, h->d_psi_off, nullptr, h->csol, h->wloc,
                                             nullptr);
     k_average_balance<<<nF, 256, 0, s>>>(h->g, h->cs, h->wloc, h->csol, h->u0, nullptr, nullptr, nullptr);
@@ -543,8 +731,8 @@ int do_solve(bddc_problem *h, const double *rhs, double rtol, double *flux, doub
     fill(h, h->xp, N, 0.0);
     k_norm2_partial<<<nb, 256, 0, s>>>(nGm, h->ru, h->part_r);
     launch_precond(h, h->ru, h->zu, h->part_z, false);
-    k_init_p<<<nb, 256, 0, s>>>(nGm, N, h->ncu, h->part_z, nF, h->part_r, nb, h->zu, h->csol, h->pu, h->pp, h->st,
-                                rtol, h->max_it);
+    k_init_p<<<nb, 256, 0, s>>>(nGm, N, h->cs.pidx, h->part_z, nF, h->part_r, nb, h->zu, h->csol, h->pu, h->pp,
+                                h->st, rtol, h->max_it);
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(h->ev0, s));
     const int chunk = 8;
@@ -634,6 +822,7 @@ int bddc_setup(const bddc_grid *g, const double *perm, const bddc_partition *par
         h->precision = opt->precision;
         if (opt->max_it > 0) h->max_it = opt->max_it;
         h->flags = opt->flags;
+        h->coarse_blocks = opt->coarse_blocks;
       }
       if (h->precision != BDDC_FP64 && h->precision != BDDC_MIXED) throw Error{BDDC_EINVAL, "bad precision"};
       h->tau = tau;
@@ -671,6 +860,7 @@ int bddc_stats(bddc_handle h, bddc_stats_t *out) {
     s.n_gamma = h->L.nGamma;
     s.n_faces = h->L.nF;
     s.precision = h->precision;
+    s.coarse_blocks = h->nblk_c;
     s.device_bytes = h->device_bytes;
     *out = s;
     return BDDC_OK;
@@ -763,14 +953,32 @@ int64_t bddc_export(bddc_handle h, int32_t what, int32_t index, void *dst, int64
         break;
       }
       case BDDC_X_COARSE_INV: {
+        // columns of the flux-flux block of K^{-1}, in face-major flux order
         const int nk = h->nk, ncu = h->ncu;
+        if (ncu > 4096) throw Error{BDDC_EINVAL, "coarse inverse export limited to 4096 flux dofs"};
         count = (int64_t)ncu * ncu;
         if (cap < count) throw Error{BDDC_EINVAL, "capacity too small"};
-        std::vector<double> full((size_t)nk * nk);
-        if (nk > 0) HIPCHK(hipMemcpy(full.data(), h->Kinv64, full.size() * sizeof(double), hipMemcpyDeviceToHost));
+        std::vector<int> fl;   // coarse indices of the flux dofs, face by face
+        for (int f = 0; f < L.nF; ++f)
+          for (int l = 0; l <= h->face_k[f]; ++l) fl.push_back(0);
+        {
+          std::vector<int> fc(L.nF);
+          HIPCHK(hipMemcpy(fc.data(), h->cs.face_cofs, L.nF * sizeof(int), hipMemcpyDeviceToHost));
+          int t = 0;
+          for (int f = 0; f < L.nF; ++f)
+            for (int l = 0; l <= h->face_k[f]; ++l) fl[t++] = fc[f] + l;
+        }
+        std::vector<double> e(nk), x(nk);
         double *o = (double *)dst;
-        for (int c = 0; c < ncu; ++c)
-          for (int r = 0; r < ncu; ++r) o[r + (size_t)c * ncu] = full[r + (size_t)c * nk];
+        for (int c = 0; c < ncu; ++c) {
+          std::fill(e.begin(), e.end(), 0.0);
+          e[fl[c]] = 1.0;
+          HIPCHK(hipMemcpy(h->bc, e.data(), nk * sizeof(double), hipMemcpyHostToDevice));
+          launch_coarse_solve(h, nullptr);
+          HIPCHK(hipStreamSynchronize(h->stream));
+          HIPCHK(hipMemcpy(x.data(), h->csol, nk * sizeof(double), hipMemcpyDeviceToHost));
+          for (int r = 0; r < ncu; ++r) o[r + (size_t)c * ncu] = x[fl[r]];
+        }
         break;
       }
       case BDDC_X_FACE_EIG: {
@@ -834,7 +1042,7 @@ int bddc_apply(bddc_handle h, int32_t which, const double *x_u, const double *x_
       std::vector<double> c(h->nk + 1, 0.0);
       if (h->nk > 0) HIPCHK(hipMemcpyAsync(c.data(), h->csol, h->nk * sizeof(double), hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
-      for (int i = 0; i < N; ++i) y_p[i] = (i < N - 1) ? c[h->ncu + i] : 0.0;
+      for (int i = 0; i < N; ++i) y_p[i] = (h->pidx_h[i] >= 0) ? c[h->pidx_h[i]] : 0.0;
     } else {
       throw Error{BDDC_EINVAL, "unknown operator"};
     }

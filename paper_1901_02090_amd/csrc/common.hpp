@@ -39,17 +39,20 @@ struct SetupWs {
   double *Spk;                             // persistent packed S^i (FP64)
 };
 
-// Coarse-space description built after the eigenproblems.
+// Coarse-space description built after the eigenproblems.  Coarse indices
+// run over [0, nk): flux coarse dofs and rescaled subdomain pressures, in the
+// slab-block order of the coarse factorization.
 struct DevCoarse {
   int ncu;                     // flux coarse dofs
   int nk;                      // size of the coarse saddle point (ncu + N - 1)
-  const int *face_cofs;        // [nF] first coarse dof of each face (its zero-net-flux row)
+  const int *face_cofs;        // [nF] coarse index of each face's zero-net-flux row
   const int *face_k;           // [nF] adaptive rows per face
   const int64_t *face_rows_off;  // [nF] offset of the adaptive rows (k x n_F, row major)
   const double *face_rows;
   const int *sub_coff;         // [N+1] offsets of local coarse dofs
-  const int *sub_cmap;         // [sum nc_i] -> global coarse dof
-  const int *co_minus, *co_plus;  // [ncu] flat local coarse index in the two subdomains
+  const int *sub_cmap;         // [sum nc_i] -> coarse index
+  const int *co_minus, *co_plus;  // [nk] flat local index in the two subdomains (-1: pressure)
+  const int *pidx;             // [N] coarse index of each subdomain pressure (-1: pinned)
 };
 
 }  // namespace bddc

@@ -18,21 +18,18 @@ constexpr int KT = 16;      // k depth staged per LDS round
 constexpr int NB = 32;      // block size of the blocked factorizations
 constexpr int LDS_DOUBLES = 2 * KT * TILE + NB * NB + 2 * NB + 2;
 
-// C = alpha * op(A) * op(B) * [diag(kscale)] + beta * C, op = transpose if TA/TB.
-// op(A) is m x k, op(B) is k x n.  kscale (length k, may be null) multiplies
-// column kk of op(A).  If LOWER, only tiles touching the lower triangle are
-// computed and only entries with row >= column are written.
+// One TILE x TILE tile of C at (i0, j0); see wg_gemm.  No trailing barrier.
 template <bool TA, bool TB, bool LOWER = false>
-__device__ __forceinline__ void wg_gemm(int m, int n, int k, double alpha, const double *__restrict__ A, int lda,
-                        const double *__restrict__ B, int ldb, double beta, double *C, int ldc,
-                        double *lds, const double *kscale = nullptr) {
+__device__ __forceinline__ void wg_gemm_tile(int i0, int j0, int m, int n, int k, double alpha,
+                                             const double *__restrict__ A, int lda, const double *__restrict__ B,
+                                             int ldb, double beta, double *C, int ldc, double *lds,
+                                             const double *kscale) {
   double *As = lds;              // As[kk * TILE + i] = op(A)(i0 + i, k0 + kk)
   double *Bs = lds + KT * TILE;  // Bs[kk * TILE + j] = op(B)(k0 + kk, j0 + j)
   const int tid = threadIdx.x;
   const int tx = tid & 15, ty = tid >> 4;
-  for (int i0 = 0; i0 < m; i0 += TILE) {
-    for (int j0 = 0; j0 < n; j0 += TILE) {
-      if (LOWER && j0 > i0 + TILE - 1) continue;
+  {
+    {
       double acc[4][4];
 #pragma unroll
       for (int r = 0; r < 4; ++r)
@@ -88,6 +85,22 @@ __device__ __forceinline__ void wg_gemm(int m, int n, int k, double alpha, const
           *dst = (beta == 0.0) ? alpha * acc[r][c] : fma(alpha, acc[r][c], beta * (*dst));
         }
       }
+    }
+  }
+}
+
+// C = alpha * op(A) * op(B) * [diag(kscale)] + beta * C, op = transpose if TA/TB.
+// op(A) is m x k, op(B) is k x n.  kscale (length k, may be null) multiplies
+// column kk of op(A).  If LOWER, only tiles touching the lower triangle are
+// computed and only entries with row >= column are written.
+template <bool TA, bool TB, bool LOWER = false>
+__device__ __forceinline__ void wg_gemm(int m, int n, int k, double alpha, const double *__restrict__ A, int lda,
+                                        const double *__restrict__ B, int ldb, double beta, double *C, int ldc,
+                                        double *lds, const double *kscale = nullptr) {
+  for (int i0 = 0; i0 < m; i0 += TILE) {
+    for (int j0 = 0; j0 < n; j0 += TILE) {
+      if (LOWER && j0 > i0 + TILE - 1) continue;
+      wg_gemm_tile<TA, TB, LOWER>(i0, j0, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, lds, kscale);
     }
   }
   __syncthreads();

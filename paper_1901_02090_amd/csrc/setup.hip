@@ -569,57 +569,4 @@ __global__ __launch_bounds__(256) void k_coarse_local(DevGeom g, SetupWs ws, Dev
   }
 }
 
-// ---------------------------------------------------------------------------
-// coarse saddle point
-// ---------------------------------------------------------------------------
-// Unknowns: flux coarse dofs (face by face) then the rescaled subdomain
-// pressures of subdomains 0..N-2; the last pressure is pinned (the pressure
-// block of the coarse problem is singular along the constants, Q_0 has zero
-// mean; pinning changes p_0 by a constant only).  Each flux coarse dof belongs
-// to exactly two subdomains, so the two contributions to an entry commute
-// exactly and the atomic sum is deterministic.
-__global__ __launch_bounds__(256) void k_coarse_assemble(DevGeom g, DevCoarse cs, const double *Ac,
-                                                         const int64_t *ac_off, const double *dscale,
-                                                         double *K) {
-  const int i = blockIdx.x;
-  const int nk = cs.nk;
-  const int c0 = cs.sub_coff[i];
-  const int nci = cs.sub_coff[i + 1] - c0;
-  const double *A = Ac + ac_off[i];
-  for (int e = threadIdx.x; e < nci * nci; e += WG) {
-    const int a = e % nci, b = e / nci;
-    const int ga = cs.sub_cmap[c0 + a], gb = cs.sub_cmap[c0 + b];
-    atomicAdd(&K[ga + (size_t)gb * nk], A[e]);
-  }
-  if (i < g.N - 1) {
-    for (int t = g.sub_face_off[i] + threadIdx.x; t < g.sub_face_off[i + 1]; t += WG) {
-      const int f = g.sub_faces[t];
-      const double s = (g.f_minus[f] == i) ? 1.0 : -1.0;   // +1: face orientation leaves Omega^i
-      const double val = -dscale[i] * s;
-      const int jf = cs.face_cofs[f];
-      const int pi = cs.ncu + i;
-      K[pi + (size_t)jf * nk] = val;
-      K[jf + (size_t)pi * nk] = val;
-    }
-  }
-}
-
-// Signed Cholesky K = L diag(s) L^T (s = +1 on flux, -1 on pressure) and the
-// explicit inverse K^{-1} = L^{-T} diag(s) L^{-1}, FP64 and FP32 copies.
-__global__ __launch_bounds__(256) void k_coarse_factor(int nk, int ncu, double *K, double *Wb,
-                                                       double *Kinv, float *Kinv32, double *sgn,
-                                                       int *err) {
-  __shared__ double lds[LDS_DOUBLES];
-  for (int r = threadIdx.x; r < nk; r += WG) sgn[r] = (r < ncu) ? 1.0 : -1.0;
-  __syncthreads();
-  if (wg_potrf(nk, K, nk, lds, sgn)) {
-    if (threadIdx.x == 0) atomicOr(err, 64);
-  }
-  wg_zero_upper(nk, K, nk);
-  wg_set_identity(nk, Wb, nk);
-  wg_trsm_lower(nk, nk, K, nk, Wb, nk, lds);
-  wg_gemm<true, false>(nk, nk, nk, 1.0, Wb, nk, Wb, nk, 0.0, Kinv, nk, lds, sgn);
-  for (int64_t e = threadIdx.x; e < (int64_t)nk * nk; e += WG) Kinv32[e] = (float)Kinv[e];
-}
-
 }  // namespace bddc

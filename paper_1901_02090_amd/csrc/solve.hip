@@ -184,28 +184,16 @@ __global__ __launch_bounds__(256) void k_update_xr(int nGamma, int N, const doub
   block_write_partial(v, rpart, red);
 }
 
-// coarse right-hand side: each flux coarse dof gathers its two local values
+// coarse right-hand side: each flux coarse dof gathers its two local values,
+// pressure rows are zero (the preconditioner's input is (r_B, 0))
 __global__ void k_coarse_rhs(DevCoarse cs, const double *__restrict__ gloc, double *__restrict__ b,
                              const CgState *st) {
   if (st && st->done) return;
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j < cs.ncu) b[j] = gloc[cs.co_minus[j]] + gloc[cs.co_plus[j]];
-}
-
-// x = K^{-1}[:, :ncols] b  (K^{-1} symmetric; column r read contiguously), one wave per row
-template <typename TK>
-__global__ __launch_bounds__(256) void k_coarse_gemv(int nk, int ncols, const TK *__restrict__ Kinv,
-                                                     const double *__restrict__ b, double *__restrict__ x,
-                                                     const CgState *st) {
-  if (st && st->done) return;
-  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (row >= nk) return;
-  const TK *col = Kinv + (int64_t)row * nk;
-  double s = 0.0;
-  for (int c = lane; c < ncols; c += 64) s = fma((double)col[c], b[c], s);
-  s = wave_sum(s);
-  if (lane == 0) x[row] = s;
+  if (j < cs.nk) {
+    const int a = cs.co_minus[j];
+    b[j] = (a >= 0) ? gloc[a] + gloc[cs.co_plus[j]] : 0.0;
+  }
 }
 
 // w^i = y^i + Psi^i alpha^(i)  (y may be null)
@@ -267,10 +255,10 @@ __global__ __launch_bounds__(256) void k_average_balance(DevGeom g, DevCoarse cs
 }
 
 // beta = rho' / rho; p = z + beta p (flux and coarse pressure)
-__global__ __launch_bounds__(256) void k_update_p(int nGamma, int N, int ncu, const double *__restrict__ zpart,
-                                                  int nzpart, const double *__restrict__ zu,
-                                                  const double *__restrict__ csol, double *pu, double *pp,
-                                                  CgState *st, double *beta_hist) {
+__global__ __launch_bounds__(256) void k_update_p(int nGamma, int N, const int *__restrict__ pidx,
+                                                  const double *__restrict__ zpart, int nzpart,
+                                                  const double *__restrict__ zu, const double *__restrict__ csol,
+                                                  double *pu, double *pp, CgState *st, double *beta_hist) {
   __shared__ double red[8];
   if (st->done) return;
   const double rn = block_sum_partials(zpart, nzpart, red);
@@ -279,7 +267,7 @@ __global__ __launch_bounds__(256) void k_update_p(int nGamma, int N, int ncu, co
   if (gi < nGamma) pu[gi] = fma(beta, pu[gi], zu[gi]);
   if (blockIdx.x == 0) {
     for (int k = threadIdx.x; k < N; k += 256) {
-      const double zp = (k < N - 1) ? csol[ncu + k] : 0.0;
+      const double zp = (pidx[k] >= 0) ? csol[pidx[k]] : 0.0;
       pp[k] = fma(beta, pp[k], zp);
     }
     if (threadIdx.x == 0) {
@@ -296,7 +284,8 @@ __global__ void k_advance(CgState *st) {
 }
 
 // initial direction p = z, rho = r.z, ||r_0||^2
-__global__ __launch_bounds__(256) void k_init_p(int nGamma, int N, int ncu, const double *__restrict__ zpart,
+__global__ __launch_bounds__(256) void k_init_p(int nGamma, int N, const int *__restrict__ pidx,
+                                                const double *__restrict__ zpart,
                                                 int nzpart, const double *__restrict__ rpart, int nrpart,
                                                 const double *__restrict__ zu, const double *__restrict__ csol,
                                                 double *pu, double *pp, CgState *st, double rtol, int maxit) {
@@ -306,7 +295,7 @@ __global__ __launch_bounds__(256) void k_init_p(int nGamma, int N, int ncu, cons
   const int gi = blockIdx.x * 256 + threadIdx.x;
   if (gi < nGamma) pu[gi] = zu[gi];
   if (blockIdx.x == 0) {
-    for (int k = threadIdx.x; k < N; k += 256) pp[k] = (k < N - 1) ? csol[ncu + k] : 0.0;
+    for (int k = threadIdx.x; k < N; k += 256) pp[k] = (pidx[k] >= 0) ? csol[pidx[k]] : 0.0;
     if (threadIdx.x == 0) {
       st->rho = rn;
       st->rho_next = rn;
@@ -345,8 +334,10 @@ __global__ void k_axpby(int n, double a, const double *__restrict__ x, double b,
 // ---------------------------------------------------------------------------
 // steps 1-2 and the reduced right-hand side
 // ---------------------------------------------------------------------------
-// Coarse right-hand side of step 1: (0, D F_0), F = -source, F_0^i = sum over Omega^i.
-__global__ __launch_bounds__(256) void k_step1_rhs(DevGeom g, int ncu, int nk, const double *__restrict__ src,
+// Coarse right-hand side of step 1: (0, D F_0), F = -source, F_0^i = sum over
+// Omega^i.  The flux rows of b must be zero on entry.
+__global__ __launch_bounds__(256) void k_step1_rhs(DevGeom g, const int *__restrict__ pidx,
+                                                   const double *__restrict__ src,
                                                    const double *__restrict__ dscale, double *b) {
   __shared__ double red[8];
   const int i = blockIdx.x;
@@ -359,10 +350,8 @@ __global__ __launch_bounds__(256) void k_step1_rhs(DevGeom g, int ncu, int nk, c
   __syncthreads();
   if (threadIdx.x == 0) {
     const double t = red[0] + red[1] + red[2] + red[3];
-    if (i < g.N - 1) b[ncu + i] = dscale[i] * t;
+    if (pidx[i] >= 0) b[pidx[i]] = dscale[i] * t;
   }
-  if (i == 0)
-    for (int j = threadIdx.x; j < ncu; j += 256) b[j] = 0.0;
 }
 
 __device__ __forceinline__ int line_start_s(int d, int l, const int *ext, const int *st) {
@@ -589,8 +578,6 @@ template __global__ void k_symv<double, true>(DevGeom, const double *, const int
 template __global__ void k_symv<float, true>(DevGeom, const float *, const int64_t *, const double *, double,
                                              double *, const float *, const int64_t *, const int *, double *,
                                              CgState *, const double *, int);
-template __global__ void k_coarse_gemv<double>(int, int, const double *, const double *, double *, const CgState *);
-template __global__ void k_coarse_gemv<float>(int, int, const float *, const double *, double *, const CgState *);
 template __global__ void k_psi_correct<double>(DevGeom, DevCoarse, const double *, const int64_t *, const double *,
                                                const double *, double *, const CgState *);
 template __global__ void k_psi_correct<float>(DevGeom, DevCoarse, const float *, const int64_t *, const double *,
