@@ -230,7 +230,7 @@ void do_setup(bddc_problem *h, const bddc_grid *gr, const double *perm, const bd
     oL[i] = ws; ws += nG * nG;
     oW[i] = ws; ws += nG * nG;
     oX[i] = xs; xs += nc * nc;
-    opk[i] = pks; pks += nG * (nG + 1) / 2;
+    opk[i] = pks; pks += gp_size((int)nG);
   }
   double *wsb = h->alloc<double>(ws);
   SetupWs sw;
@@ -400,7 +400,7 @@ void do_setup(bddc_problem *h, const bddc_grid *gr, const double *perm, const bd
     const int64_t nci = sub_coff[i + 1] - sub_coff[i], nG = L.nG[i];
     cwoff[i] = cws; cws += 4 * nci * nG + 2 * nci * nci;
     acoff[i] = acs; acs += nci * nci;
-    psioff[i] = pss; pss += nG * nci;
+    psioff[i] = pss; pss += ld4((int)nG) * nci;
   }
   h->psi_off_h = psioff;
   CoarseLocalWs cw;
@@ -583,16 +583,16 @@ void launch_coarse_solve(bddc_problem *h, const int *done) {
   for (int q = 0; q < G; ++q) {
     const int b = bo[q + 1] - bo[q];
     const int tp = q > 0 ? bo[q] - to[q - 1] : 0;
-    k_cfwd<<<nblk(b, 4), 256, 0, s>>>(b, h->LinvR + h->lr_off[q], h->bc + bo[q], q > 0 ? h->Mblk + h->m_off[q] : nullptr,
+    k_cfwd<<<(b + 1) / 2, 256, 0, s>>>(b, h->LinvR + h->lr_off[q], h->bc + bo[q], q > 0 ? h->Mblk + h->m_off[q] : nullptr,
                                       tp, q > 0 ? h->cy + to[q - 1] : nullptr, h->cy + bo[q], done);
   }
   for (int q = G - 1; q >= 0; --q) {
     const int b = bo[q + 1] - bo[q];
     if (q + 1 < G) {
       const int bn = bo[q + 2] - bo[q + 1], t = bo[q + 1] - to[q];
-      k_cbwd_u<<<nblk(t, 4), 256, 0, s>>>(bn, t, h->Lcblk + h->lc_off[q], h->csol + bo[q + 1], h->cu, done);
+      k_cbwd_u<<<t, 256, 0, s>>>(bn, t, h->Lcblk + h->lc_off[q], h->csol + bo[q + 1], h->cu, done);
     }
-    k_cbwd_x<<<nblk(b, 4), 256, 0, s>>>(b, h->LinvC + h->lr_off[q], h->cy + bo[q], h->csgn + bo[q],
+    k_cbwd_x<<<(b + 1) / 2, 256, 0, s>>>(b, h->LinvC + h->lr_off[q], h->cy + bo[q], h->csgn + bo[q],
                                         q + 1 < G ? h->cu : nullptr, q + 1 < G ? to[q] - bo[q] : b,
                                         h->csol + bo[q], done);
   }
@@ -603,7 +603,7 @@ void launch_precond(bddc_problem *h, const double *r, double *z, double *zpart, 
   const Layout &L = h->L;
   hipStream_t s = h->stream;
   const int N = L.N, nF = L.nF;
-  const size_t shm = (size_t)5 * L.maxG * sizeof(double);
+  const size_t shm = (size_t)5 * ld4(L.maxG) * sizeof(double);
   CgState *st = check ? h->st : nullptr;
   const double *rp = check ? h->part_r : nullptr;
   const int nrp = (int)nblk(L.nGamma);
@@ -632,7 +632,7 @@ void launch_iteration(bddc_problem *h) {
   const Layout &L = h->L;
   hipStream_t s = h->stream;
   const int N = L.N, nGm = L.nGamma;
-  const size_t shm = (size_t)5 * L.maxG * sizeof(double);
+  const size_t shm = (size_t)5 * ld4(L.maxG) * sizeof(double);
   const int nb = (int)nblk(nGm);
   k_symv<double, false><<<N, 256, shm, s>>>(h->g, h->Spk, h->d_pk, h->pu, 1.0, h->yloc, nullptr, nullptr,
                                             nullptr, nullptr, h->st, nullptr, 0);
@@ -707,7 +707,7 @@ int do_solve(bddc_problem *h, const double *rhs, double rtol, double *flux, doub
   }
   double *fl = dev ? flux : h->d_flux;
   double *pr = dev ? pressure : h->d_pres;
-  const size_t shm = (size_t)5 * L.maxG * sizeof(double);
+  const size_t shm = (size_t)5 * ld4(L.maxG) * sizeof(double);
   const int nb = (int)nblk(nGm);
 
   int iters = 0, converged = 1, fail = 0;
@@ -914,13 +914,13 @@ int64_t bddc_export(bddc_handle h, int32_t what, int32_t index, void *dst, int64
         const int n = L.nG[index];
         count = (int64_t)n * n;
         if (cap < count) throw Error{BDDC_EINVAL, "capacity too small"};
-        std::vector<double> pk((size_t)n * (n + 1) / 2);
-        if (!pk.empty())
+        std::vector<double> pk(gp_size(n));
+        if (n > 0)
           HIPCHK(hipMemcpy(pk.data(), h->Spk + h->pk_h[index], pk.size() * sizeof(double), hipMemcpyDeviceToHost));
         double *o = (double *)dst;
         for (int c = 0; c < n; ++c)
           for (int r = c; r < n; ++r) {
-            const double v = pk[(size_t)c * n - (size_t)c * (c - 1) / 2 + (r - c)];
+            const double v = pk[gp_index(n, r, c)];
             o[r + (size_t)c * n] = v;
             o[c + (size_t)r * n] = v;
           }
@@ -931,13 +931,13 @@ int64_t bddc_export(bddc_handle h, int32_t what, int32_t index, void *dst, int64
         const int n = L.nG[index];
         count = (int64_t)n * n;
         if (cap < count) throw Error{BDDC_EINVAL, "capacity too small"};
-        std::vector<double> pk((size_t)n * (n + 1) / 2);
-        if (!pk.empty())
+        std::vector<double> pk(gp_size(n));
+        if (n > 0)
           HIPCHK(hipMemcpy(pk.data(), h->T64 + h->pk_h[index], pk.size() * sizeof(double), hipMemcpyDeviceToHost));
         double *o = (double *)dst;
         for (int c = 0; c < n; ++c)
           for (int r = c; r < n; ++r) {
-            const double v = pk[(size_t)c * n - (size_t)c * (c - 1) / 2 + (r - c)];
+            const double v = pk[gp_index(n, r, c)];
             o[r + (size_t)c * n] = v;
             o[c + (size_t)r * n] = v;
           }
@@ -946,10 +946,16 @@ int64_t bddc_export(bddc_handle h, int32_t what, int32_t index, void *dst, int64
       case BDDC_X_PSI: {
         if (index < 0 || index >= L.N) throw Error{BDDC_EINVAL, "bad subdomain index"};
         const int64_t nci = h->sub_coff_h[index + 1] - h->sub_coff_h[index];
-        count = (int64_t)L.nG[index] * nci;
+        const int n = L.nG[index], ldp = ld4(n);
+        count = (int64_t)n * nci;
         if (cap < count) throw Error{BDDC_EINVAL, "capacity too small"};
+        std::vector<double> full((size_t)ldp * nci);
         if (count > 0)
-          HIPCHK(hipMemcpy(dst, h->Psi64 + h->psi_off_h[index], count * sizeof(double), hipMemcpyDeviceToHost));
+          HIPCHK(hipMemcpy(full.data(), h->Psi64 + h->psi_off_h[index], full.size() * sizeof(double),
+                           hipMemcpyDeviceToHost));
+        double *o = (double *)dst;
+        for (int64_t c = 0; c < nci; ++c)
+          for (int r = 0; r < n; ++r) o[r + c * n] = full[r + c * ldp];
         break;
       }
       case BDDC_X_COARSE_INV: {
@@ -1029,7 +1035,7 @@ int bddc_apply(bddc_handle h, int32_t which, const double *x_u, const double *x_
     if (which == BDDC_OP_SYSTEM) {
       if (!x_p) throw Error{BDDC_EINVAL, "x_p required"};
       HIPCHK(hipMemcpyAsync(h->pp, x_p, N * sizeof(double), hipMemcpyHostToDevice, s));
-      const size_t shm = (size_t)5 * L.maxG * sizeof(double);
+      const size_t shm = (size_t)5 * ld4(L.maxG) * sizeof(double);
       k_symv<double, false><<<N, 256, shm, s>>>(h->g, h->Spk, h->d_pk, h->ru, 1.0, h->yloc, nullptr, nullptr,
                                                 nullptr, nullptr, nullptr, nullptr, 0);
       k_sys_assemble<<<nblk(nGm), 256, 0, s>>>(h->g, h->yloc, h->pp, h->dscale, nullptr, h->qu, nullptr, nullptr);
@@ -1059,7 +1065,7 @@ int bddc_time_kernel(bddc_handle h, int32_t which, int32_t reps, double *avg_ms,
     hipStream_t s = h->stream;
     const int N = L.N;
     if (L.nGamma == 0) throw Error{BDDC_EINVAL, "no interface"};
-    const size_t shm = (size_t)5 * L.maxG * sizeof(double);
+    const size_t shm = (size_t)5 * ld4(L.maxG) * sizeof(double);
     double pk = 0.0, psi = 0.0;
     for (int i = 0; i < N; ++i) {
       pk += (double)L.nG[i] * (L.nG[i] + 1) / 2;

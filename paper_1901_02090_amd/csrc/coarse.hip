@@ -173,57 +173,117 @@ __device__ __forceinline__ double wave_sum_c(double v) {
   return v;
 }
 
-// y[r] = sum_{c<=r} Linv[r,c] b[c] - sum_t M[r,t] yprev[t]   (one wave per row)
+// Block-wide sum over 256 threads (four waves); every thread gets the result.
+__device__ __forceinline__ double block_sum256(double v, double *red) {
+  v = wave_sum_c(v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// Each of the sweep GEMVs gives one workgroup per output entry: a row (or
+// column) of a few thousand entries is covered by 256 lanes with four
+// independent loads in flight each, so one entry costs about one memory round
+// trip instead of a chain of them.
+
+// y[r] = sum_{c<=r} Linv[r,c] b[c] - sum_t M[r,t] yprev[t].  Workgroup k
+// computes rows k and b-1-k, which together hold b+1 triangle entries, so
+// every workgroup streams the same amount.
+__device__ __forceinline__ double cfwd_row(int r, const double *__restrict__ rowp, const double *__restrict__ bvec,
+                                           const double *__restrict__ M, int tprev, const double *__restrict__ yprev,
+                                           double *red) {
+  const int tid = threadIdx.x;
+  const double *row = rowp + (int64_t)r * (r + 1) / 2;
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int c0 = tid; c0 <= r; c0 += 1024) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int c = c0 + 256 * u;
+      if (c <= r) a[u] = fma(row[c], bvec[c], a[u]);
+    }
+  }
+  if (M) {
+    const double *mr = M + (int64_t)r * tprev;
+    for (int t0 = tid; t0 < tprev; t0 += 1024) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int t = t0 + 256 * u;
+        if (t < tprev) a[u] = fma(-mr[t], yprev[t], a[u]);
+      }
+    }
+  }
+  return block_sum256((a[0] + a[1]) + (a[2] + a[3]), red);
+}
+
 __global__ __launch_bounds__(256) void k_cfwd(int bsz, const double *__restrict__ rowp, const double *__restrict__ bvec,
                                               const double *__restrict__ M, int tprev,
                                               const double *__restrict__ yprev, double *__restrict__ y,
                                               const int *done) {
+  __shared__ double red[8];
   if (done && *done) return;
-  const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (r >= bsz) return;
-  const double *row = rowp + (int64_t)r * (r + 1) / 2;
-  double s = 0.0;
-  for (int c = lane; c <= r; c += 64) s = fma(row[c], bvec[c], s);
-  if (M) {
-    const double *mr = M + (int64_t)r * tprev;
-    for (int t = lane; t < tprev; t += 64) s = fma(-mr[t], yprev[t], s);
+  const int r1 = blockIdx.x, r2 = bsz - 1 - blockIdx.x;
+  const double s1 = cfwd_row(r1, rowp, bvec, M, tprev, yprev, red);
+  if (r2 > r1) {
+    const double s2 = cfwd_row(r2, rowp, bvec, M, tprev, yprev, red + 4);
+    if (threadIdx.x == 0) y[r2] = s2;
   }
-  s = wave_sum_c(s);
-  if (lane == 0) y[r] = s;
+  if (threadIdx.x == 0) y[r1] = s1;
 }
 
-// u[t] = sum_r Lc[r,t] x[r]  (Lc: bnext x t, column major; one wave per column)
+// u[t] = sum_r Lc[r,t] x[r]  (Lc: bnext x t, column major)
 __global__ __launch_bounds__(256) void k_cbwd_u(int bnext, int tcur, const double *__restrict__ Lc,
                                                 const double *__restrict__ x, double *__restrict__ u, const int *done) {
+  __shared__ double red[4];
   if (done && *done) return;
-  const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (t >= tcur) return;
+  const int t = blockIdx.x;
+  const int tid = threadIdx.x;
   const double *col = Lc + (int64_t)t * bnext;
-  double s = 0.0;
-  for (int r = lane; r < bnext; r += 64) s = fma(col[r], x[r], s);
-  s = wave_sum_c(s);
-  if (lane == 0) u[t] = s;
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int r0 = tid; r0 < bnext; r0 += 1024) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r = r0 + 256 * q;
+      if (r < bnext) a[q] = fma(col[r], x[r], a[q]);
+    }
+  }
+  const double s = block_sum256((a[0] + a[1]) + (a[2] + a[3]), red);
+  if (tid == 0) u[t] = s;
 }
 
-// x[c] = sum_{r>=c} Linv[r,c] (s_r y[r] - u[r - ts])   (one wave per column)
+// x[c] = sum_{r>=c} Linv[r,c] (s_r y[r] - u[r - ts]); workgroup k computes
+// columns k and b-1-k.
+__device__ __forceinline__ double cbwd_col(int c, int bsz, const double *__restrict__ colp,
+                                           const double *__restrict__ y, const double *__restrict__ sg,
+                                           const double *__restrict__ u, int ts, double *red) {
+  const int tid = threadIdx.x;
+  const double *col = colp + (int64_t)c * bsz - (int64_t)c * (c - 1) / 2;
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int r0 = c + tid; r0 < bsz; r0 += 1024) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r = r0 + 256 * q;
+      if (r < bsz) {
+        double v = sg[r] * y[r];
+        if (u && r >= ts) v -= u[r - ts];
+        a[q] = fma(col[r - c], v, a[q]);
+      }
+    }
+  }
+  return block_sum256((a[0] + a[1]) + (a[2] + a[3]), red);
+}
+
 __global__ __launch_bounds__(256) void k_cbwd_x(int bsz, const double *__restrict__ colp, const double *__restrict__ y,
                                                 const double *__restrict__ sg, const double *__restrict__ u, int ts,
                                                 double *__restrict__ x, const int *done) {
+  __shared__ double red[8];
   if (done && *done) return;
-  const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (c >= bsz) return;
-  const double *col = colp + (int64_t)c * bsz - (int64_t)c * (c - 1) / 2;
-  double s = 0.0;
-  for (int r = c + lane; r < bsz; r += 64) {
-    double v = sg[r] * y[r];
-    if (u && r >= ts) v -= u[r - ts];
-    s = fma(col[r - c], v, s);
+  const int c1 = blockIdx.x, c2 = bsz - 1 - blockIdx.x;
+  const double s1 = cbwd_col(c1, bsz, colp, y, sg, u, ts, red);
+  if (c2 > c1) {
+    const double s2 = cbwd_col(c2, bsz, colp, y, sg, u, ts, red + 4);
+    if (threadIdx.x == 0) x[c2] = s2;
   }
-  s = wave_sum_c(s);
-  if (lane == 0) x[c] = s;
+  if (threadIdx.x == 0) x[c1] = s1;
 }
 
 }  // namespace bddc

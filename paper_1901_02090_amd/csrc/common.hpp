@@ -7,6 +7,29 @@ namespace bddc {
 
 constexpr int MAXLINE = 32;   // longest subdomain extent along one axis
 
+// Group-aligned packed storage of a symmetric n x n matrix (lower triangle).
+// Columns come in groups of four; group g holds its four columns over rows
+// 4g .. 4G-1 (G = ceil(n/4)), each column contiguous with length 4(G-g).
+// Entries above the diagonal inside a group and rows >= n are zero.  Every
+// column of a group starts at the same row and on a 16-byte boundary, so a
+// wavefront reads four columns with 16-byte vector loads, contiguous across
+// lanes.  Size 8 G (G+1) (n(n+1)/2 plus O(n) padding).
+__host__ __device__ inline int64_t gp_size(int n) {
+  const int64_t G = (n + 3) / 4;
+  return 8 * G * (G + 1);
+}
+__host__ __device__ inline int64_t gp_group(int n, int g) {
+  const int64_t G = (n + 3) / 4;
+  return 16 * ((int64_t)g * G - (int64_t)g * (g - 1) / 2);
+}
+__host__ __device__ inline int64_t gp_index(int n, int r, int c) {
+  const int64_t G = (n + 3) / 4;
+  const int g = c / 4, q = c % 4;
+  return gp_group(n, g) + (int64_t)q * 4 * (G - g) + (r - 4 * g);
+}
+// Leading dimension of the coarse bases Psi^i: rows padded to a multiple of 4.
+__host__ __device__ inline int ld4(int n) { return (n + 3) & ~3; }
+
 // Read-only index data of the partition (device pointers).
 struct DevGeom {
   int dim;

@@ -238,9 +238,11 @@ __global__ __launch_bounds__(256) void k_schur_factor(DevGeom g, SetupWs ws, int
   double *W = ws.base + ws.W[i];
   for (int e = threadIdx.x; e < nG * nG; e += WG) L[e] = S[e];
   double *pk = ws.Spk + ws.pk[i];
+  for (int64_t e = threadIdx.x; e < gp_size(nG); e += WG) pk[e] = 0.0;
+  __syncthreads();
   for (int e = threadIdx.x; e < nG * nG; e += WG) {
     const int r = e % nG, c = e / nG;
-    if (r >= c) pk[(int64_t)c * nG - (int64_t)c * (c - 1) / 2 + (r - c)] = S[e];
+    if (r >= c) pk[gp_index(nG, r, c)] = S[e];
   }
   __syncthreads();
   if (wg_potrf(nG, L, nG, lds)) {
@@ -539,9 +541,12 @@ __global__ __launch_bounds__(256) void k_coarse_local(DevGeom g, SetupWs ws, Dev
     }
   }
   __syncthreads();
-  // Psi = W^T U
-  wg_gemm<true, false>(nG, nci, nG, 1.0, W, nG, U, nG, 0.0, Psi, nG, lds);
-  for (int e = tid; e < nG * nci; e += WG) cw.psi32[cw.psi_off[i] + e] = (float)Psi[e];
+  // Psi = W^T U  (leading dimension ld4(nG), padding rows zero)
+  const int ldp = ld4(nG);
+  for (int e = tid; e < ldp * nci; e += WG) Psi[e] = 0.0;
+  __syncthreads();
+  wg_gemm<true, false>(nG, nci, nG, 1.0, W, nG, U, nG, 0.0, Psi, ldp, lds);
+  for (int e = tid; e < ldp * nci; e += WG) cw.psi32[cw.psi_off[i] + e] = (float)Psi[e];
   // R^{-1} (column-wise backward substitution), A_c^i = R^{-1} R^{-T}
   for (int c = tid; c < nci; c += WG) {
     for (int r = nci - 1; r >= 0; --r) {
@@ -558,10 +563,15 @@ __global__ __launch_bounds__(256) void k_coarse_local(DevGeom g, SetupWs ws, Dev
   wg_gemm<false, false>(nG, nG, nci, -1.0, Q, nG, M1, nci, 1.0, W, nG, lds);
   wg_gemm<true, false, true>(nG, nG, nG, 1.0, W, nG, W, nG, 0.0, Tfull, nG, lds);
   const int64_t po = cw.pk[i];
+  for (int64_t e = tid; e < gp_size(nG); e += WG) {
+    cw.t64[po + e] = 0.0;
+    cw.t32[po + e] = 0.0f;
+  }
+  __syncthreads();
   for (int e = tid; e < nG * nG; e += WG) {
     const int r = e % nG, c = e / nG;
     if (r >= c) {
-      const int64_t k = po + (int64_t)c * nG - (int64_t)c * (c - 1) / 2 + (r - c);
+      const int64_t k = po + gp_index(nG, r, c);
       const double t = Tfull[e];
       cw.t64[k] = t;
       cw.t32[k] = (float)t;

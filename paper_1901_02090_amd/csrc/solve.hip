@@ -30,6 +30,23 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Sum four per-lane values over the 64 lanes at once: after the exchange
+// with lane^32 and lane^16 each 16-lane group holds one of the four partial
+// sums, which four more steps finish.  Lane 16*q returns the total of d[q].
+__device__ __forceinline__ double transpose_reduce4(const double *d, int lane) {
+  const bool hi32 = (lane & 32) != 0;
+  double v0 = hi32 ? d[2] : d[0], v1 = hi32 ? d[3] : d[1];
+  const double w0 = hi32 ? d[0] : d[2], w1 = hi32 ? d[1] : d[3];
+  v0 += __shfl_xor(w0, 32, 64);
+  v1 += __shfl_xor(w1, 32, 64);
+  const bool hi16 = (lane & 16) != 0;
+  double u = hi16 ? v1 : v0;
+  const double o = hi16 ? v0 : v1;
+  u += __shfl_xor(o, 16, 64);
+  for (int off = 8; off > 0; off >>= 1) u += __shfl_xor(u, off, 64);
+  return u;
+}
+
 __device__ __forceinline__ double block_sum_partials(const double *__restrict__ part, int n, double *red) {
   double s = 0.0;
   for (int k = threadIdx.x; k < n; k += blockDim.x) s += part[k];
@@ -64,6 +81,16 @@ __device__ __forceinline__ void block_write_partial(double v, double *part, doub
 // reduction.  If `check` is set the block first evaluates the stopping test
 // from the residual partials of the previous kernel.
 // ---------------------------------------------------------------------------
+// 16-byte vector load of 16/sizeof(TS) consecutive entries, widened to FP64.
+__device__ __forceinline__ void load16(const float *p, double *o) {
+  const float4 v = *reinterpret_cast<const float4 *>(p);
+  o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+}
+__device__ __forceinline__ void load16(const double *p, double *o) {
+  const double2 v = *reinterpret_cast<const double2 *>(p);
+  o[0] = v.x; o[1] = v.y;
+}
+
 template <typename TS, bool WITH_PSI>
 __global__ __launch_bounds__(256) void k_symv(DevGeom g, const TS *__restrict__ M, const int64_t *__restrict__ pk,
                                               const double *__restrict__ x, double xscale,
@@ -90,40 +117,75 @@ __global__ __launch_bounds__(256) void k_symv(DevGeom g, const TS *__restrict__ 
       }
     }
   }
+  constexpr int VW = 16 / sizeof(TS);
   const int i = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int n = g.nG[i];
+  const int G4 = (n + 3) / 4, np = 4 * G4;
   const int64_t go = g.g_off[i];
   double *xs = sh;
-  double *yw = sh + n;
-  for (int r = tid; r < n; r += 256) xs[r] = xscale * x[g.Rmap[go + r]];
-  for (int e = tid; e < 4 * n; e += 256) yw[e] = 0.0;
+  double *yw = sh + np;
+  for (int r = tid; r < np; r += 256) xs[r] = (r < n) ? xscale * x[g.Rmap[go + r]] : 0.0;
+  for (int e = tid; e < 4 * np; e += 256) yw[e] = 0.0;
   __syncthreads();
   const TS *Mi = M + pk[i];
-  double *yme = yw + wv * n;
-  for (int j = wv; j < n; j += 4) {
-    const TS *col = Mi + (int64_t)j * n - (int64_t)j * (j - 1) / 2;
-    const int len = n - j;
-    const double xj = xs[j];
-    double dot = 0.0;
-    for (int t = lane; t < len; t += 64) {
-      const double a = (double)col[t];
-      dot = fma(a, xs[j + t], dot);
-      if (t > 0) yme[j + t] = fma(a, xj, yme[j + t]);
+  double *yme = yw + wv * np;
+  // A wave takes one column group (four columns, common first row rs) at a
+  // time: each lane loads VW consecutive rows of all four columns with 16-byte
+  // loads, folds the strictly-lower products into one LDS update per row, and
+  // the four transposed dot products are reduced together.
+  for (int gi = wv; gi < G4; gi += 4) {
+    const int rs = 4 * gi;
+    const int L = 4 * (G4 - gi);
+    const TS *base = Mi + gp_group(n, gi);
+    double xj[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) xj[q] = xs[rs + q];
+    double d[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int t = lane * VW; t < L; t += 64 * VW) {
+      double a[4][VW];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) load16(base + (int64_t)q * L + t, a[q]);
+#pragma unroll
+      for (int v = 0; v < VW; ++v) {
+        const int r = rs + t + v;
+        const double xr = xs[r];
+        double acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          d[q] = fma(a[q][v], xr, d[q]);
+          if (r > rs + q) acc = fma(a[q][v], xj[q], acc);
+        }
+        yme[r] += acc;
+      }
     }
-    dot = wave_sum(dot);
-    if (lane == 0) yme[j] += dot;
+    const double tot = transpose_reduce4(d, lane);
+    if ((lane & 15) == 0) yme[rs + (lane >> 4)] += tot;
   }
   __syncthreads();
-  for (int r = tid; r < n; r += 256) yloc[go + r] = yw[r] + yw[n + r] + yw[2 * n + r] + yw[3 * n + r];
+  for (int r = tid; r < n; r += 256) yloc[go + r] = yw[r] + yw[np + r] + yw[2 * np + r] + yw[3 * np + r];
   if (WITH_PSI) {
     const int c0 = sub_coff[i], nci = sub_coff[i + 1] - c0;
     const TS *P = Psi + psi_off[i];
-    for (int c = wv; c < nci; c += 4) {
-      const TS *col = P + (int64_t)c * n;
-      double dot = 0.0;
-      for (int t = lane; t < n; t += 64) dot = fma((double)col[t], xs[t], dot);
-      dot = wave_sum(dot);
-      if (lane == 0) gloc[c0 + c] = dot;
+    for (int cb = 4 * wv; cb < nci; cb += 16) {
+      double d[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int t = lane * VW; t < np; t += 64 * VW) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          double a[VW];
+          if (cb + q < nci) load16(P + (int64_t)(cb + q) * np + t, a);
+          else {
+#pragma unroll
+            for (int v = 0; v < VW; ++v) a[v] = 0.0;
+          }
+#pragma unroll
+          for (int v = 0; v < VW; ++v) d[q] = fma(a[v], xs[t + v], d[q]);
+        }
+      }
+      const double tot = transpose_reduce4(d, lane);
+      if ((lane & 15) == 0) {
+        const int c = cb + (lane >> 4);
+        if (c < nci) gloc[c0 + c] = tot;
+      }
     }
   }
 }
@@ -212,9 +274,10 @@ __global__ __launch_bounds__(256) void k_psi_correct(DevGeom g, DevCoarse cs, co
   for (int c = threadIdx.x; c < nci; c += 256) al[c] = csol[cs.sub_cmap[c0 + c]];
   __syncthreads();
   const TS *P = Psi + psi_off[i];
+  const int ldp = ld4(n);
   for (int r = threadIdx.x; r < n; r += 256) {
     double s = yloc ? yloc[go + r] : 0.0;
-    for (int c = 0; c < nci; ++c) s = fma((double)P[r + (int64_t)c * n], al[c], s);
+    for (int c = 0; c < nci; ++c) s = fma((double)P[r + (int64_t)c * ldp], al[c], s);
     wloc[go + r] = s;
   }
 }
