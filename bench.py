@@ -134,6 +134,34 @@ def cpu_baseline(pr, seconds, gpu_iters):
             "sample": f"{n} complete oracle solves (setup excluded, {el:.1f} s, one BLAS thread) of {what}"}
 
 
+COPY_BYTES = 1 << 30
+
+
+def kernels_only(pr, reps):
+    """Launch the local apply kernels and a 1 GiB device-to-device copy alone.
+
+    Under a hardware-counter profiler the copy gives the factor between the
+    counters' byte figures and true bytes (it reads and writes exactly
+    COPY_BYTES each).
+    """
+    import torch
+    from paper_1901_02090_amd import Solver
+    from paper_1901_02090_amd.bddc import K_SCHUR_APPLY, K_PRECOND_APPLY
+    s = Solver(pr.n, pr.h, pr.perm, pr.cuts, tau=pr.tau, precision="mixed", max_it=5000)
+    ms_s, by_s = s.time_kernel(K_SCHUR_APPLY, reps)
+    ms_t, by_t = s.time_kernel(K_PRECOND_APPLY, reps)
+    a = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    c = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        c.copy_(a)
+    torch.cuda.synchronize()
+    s.close()
+    print(json.dumps({"schur_apply": {"avg_ms": ms_s, "bytes": by_s},
+                      "precond_apply": {"avg_ms": ms_t, "bytes": by_t},
+                      "copy_bytes": COPY_BYTES, "reps": reps}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -142,6 +170,9 @@ def main():
     ap.add_argument("--workload", default="reservoir", choices=["reservoir", "layer", "square"])
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="set up the mixed form, launch the S^i and T^i apply kernels alone and a plain "
+                         "device copy of known size (for scaling hardware byte counters), then exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("this benchmark runs on exactly one GPU: the solver is a single-GPU build "
@@ -150,6 +181,9 @@ def main():
 
     from paper_1901_02090_amd.bddc import K_SCHUR_APPLY, K_PRECOND_APPLY
     pr, desc = make_workload(args.workload)
+    if args.kernels_only:
+        kernels_only(pr, args.steps)
+        return
 
     s64, r64 = time_gpu(pr, "fp64", args.steps, args.warmup)
     smx, rmx = time_gpu(pr, "mixed", args.steps, args.warmup)

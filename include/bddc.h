@@ -78,9 +78,8 @@ typedef struct {
   int32_t precision;     /* BDDC_FP64 or BDDC_MIXED                          */
   int32_t max_it;        /* CG iteration cap (<= 0: 10000)                    */
   uint32_t flags;        /* BDDC_ALL_CONSTRAINED (diagnostic)                 */
-  int32_t coarse_blocks; /* slab blocks of the coarse factorization; 0: chosen
-                            by a bytes-per-solve model, otherwise clamped to
-                            [1, subdomains along the longest axis]           */
+  int32_t coarse_leaf;   /* nested dissection of the coarse problem stops at
+                            boxes of at most this many subdomains (<= 0: 1) */
 } bddc_options;
 
 typedef struct {
@@ -97,7 +96,8 @@ typedef struct {
   int32_t n_gamma;          /* interface flux dofs                               */
   int32_t n_faces;          /* subdomain faces                                   */
   int32_t precision;
-  int32_t coarse_blocks;    /* slab blocks used by the coarse factorization      */
+  int32_t coarse_levels;    /* levels of the coarse multifrontal factorization   */
+  int32_t coarse_fronts;    /* fronts (separators and leaf boxes) of it          */
   double t_setup_ms;        /* wall time of bddc_setup                           */
   double t_solve_ms;        /* wall time of the last bddc_solve                  */
   double t_pcg_ms;          /* device time of the CG loop of the last solve      */

@@ -30,7 +30,7 @@ class Partition(C.Structure):
 
 
 class Options(C.Structure):
-    _fields_ = [("precision", C.c_int32), ("max_it", C.c_int32), ("flags", C.c_uint32), ("coarse_blocks", C.c_int32)]
+    _fields_ = [("precision", C.c_int32), ("max_it", C.c_int32), ("flags", C.c_uint32), ("coarse_leaf", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -38,7 +38,7 @@ class Stats(C.Structure):
                 ("lambda_min", C.c_double), ("lambda_max", C.c_double), ("omega_tilde", C.c_double),
                 ("n_adaptive", C.c_int32), ("n_coarse_flux", C.c_int32), ("n_coarse", C.c_int32),
                 ("n_sub", C.c_int32), ("n_gamma", C.c_int32), ("n_faces", C.c_int32), ("precision", C.c_int32),
-                ("coarse_blocks", C.c_int32), ("t_setup_ms", C.c_double), ("t_solve_ms", C.c_double),
+                ("coarse_levels", C.c_int32), ("coarse_fronts", C.c_int32), ("t_setup_ms", C.c_double), ("t_solve_ms", C.c_double),
                 ("t_pcg_ms", C.c_double), ("bytes_per_iter", C.c_double), ("bytes_prec", C.c_double),
                 ("device_bytes", C.c_double)]
 
@@ -101,7 +101,7 @@ class Solver:
     """One problem resident on the GPU: setup once, solve many right-hand sides."""
 
     def __init__(self, n, h, perm, cuts, tau=math.inf, precision="fp64", max_it=10000, all_constrained=False,
-                 coarse_blocks=0):
+                 coarse_leaf=0):
         self.lib = lib = load_library()
         dim = len(n)
         self.n = tuple(int(v) for v in n)
@@ -112,7 +112,7 @@ class Solver:
                                         [C.POINTER(C.c_int32)()] * (3 - dim))
         part = Partition((C.c_int32 * 3)(*([len(c) - 1 for c in self._cuts] + [1] * (3 - dim))), cp)
         opt = Options(BDDC_MIXED if precision == "mixed" else BDDC_FP64, int(max_it),
-                      BDDC_ALL_CONSTRAINED if all_constrained else 0, int(coarse_blocks))
+                      BDDC_ALL_CONSTRAINED if all_constrained else 0, int(coarse_leaf))
         perm = np.ascontiguousarray(perm, dtype=np.float64).reshape(-1)
         t = float(tau) if (tau is not None and math.isfinite(tau)) else 0.0
         self.h = C.c_void_p()

@@ -15,6 +15,7 @@
 #include "../../include/bddc.h"
 #include "common.hpp"
 #include "layout.hpp"
+#include "nd.hpp"
 #include "setup.hip"
 #include "solve.hip"
 #include "coarse.hip"
@@ -49,7 +50,7 @@ struct bddc_problem {
   int precision = BDDC_FP64;
   int max_it = 10000;
   uint32_t flags = 0;
-  int coarse_blocks = 0;
+  int coarse_leaf = 0;
   double tau = 0.0;
   std::vector<void *> allocs;
   double device_bytes = 0;
@@ -67,13 +68,13 @@ struct bddc_problem {
   double *mcoef = nullptr, *dscale = nullptr;
   double *Spk = nullptr, *T64 = nullptr, *Psi64 = nullptr, *Xmat = nullptr;
   float *T32 = nullptr, *Psi32 = nullptr;
-  // coarse factorization (slab blocks)
-  int nblk_c = 0, slab_axis = 0;
-  std::vector<int> boff_h, toff_h;
-  std::vector<int64_t> lr_off, m_off, lc_off;
+  // coarse factorization (nested-dissection fronts)
+  NdPlan nd;
+  DevFronts fd{};
+  DevSweep sw{};
   std::vector<int> pidx_h;
-  double *LinvR = nullptr, *LinvC = nullptr, *Mblk = nullptr, *Lcblk = nullptr, *csgn = nullptr, *cy = nullptr,
-         *cu = nullptr;
+  double *FR = nullptr, *BC = nullptr, *csgn = nullptr, *cy = nullptr, *cS0 = nullptr, *cS1 = nullptr,
+         *cXB = nullptr;
   double coarse_bytes = 0.0;
   int64_t *d_pk = nullptr, *d_psi_off = nullptr, *d_Xoff = nullptr, *d_gamma_face = nullptr;
 
@@ -296,69 +297,19 @@ void do_setup(bddc_problem *h, const bddc_grid *gr, const double *perm, const bd
     h->omega_tilde = std::max(h->omega_tilde, h->face_omega[f]);
   }
 
-  // coarse numbering in slab-block order (see coarse.hip).  Slabs are layers of
-  // subdomains along the axis with the most subdomains, merged into G groups;
-  // G minimises the streamed bytes of one coarse solve plus a launch cost.
-  int ax = 0;
-  for (int d = 1; d < dim; ++d)
-    if (L.nsub[d] > L.nsub[ax]) ax = d;
-  const int nl = L.nsub[ax];
-  auto layer_of = [&](int i) { return (i / L.sstride[ax]) % L.nsub[ax]; };
-  auto plan = [&](int G, std::vector<int> &bsz, std::vector<int> &tsz) {
-    bsz.assign(G, 0);
-    tsz.assign(G, 0);
-    for (int f = 0; f < nF; ++f) {
-      const int ga = (int)((int64_t)layer_of(L.f_minus[f]) * G / nl), gb = (int)((int64_t)layer_of(L.f_plus[f]) * G / nl);
-      bsz[ga] += 1 + h->face_k[f];
-      if (ga != gb) tsz[ga] += 1 + h->face_k[f];
-    }
-    for (int i = 0; i < N - 1; ++i) {
-      const int gi = (int)((int64_t)layer_of(i) * G / nl);
-      bsz[gi] += 1;
-      tsz[gi] += 1;
-    }
-  };
-  int G = 1;
-  {
-    double best = 1e300;
-    std::vector<int> bsz, tsz;
-    for (int cand = 1; cand <= nl; ++cand) {
-      plan(cand, bsz, tsz);
-      double by = 0.0;
-      for (int q = 0; q < cand; ++q) {
-        by += (double)bsz[q] * bsz[q];
-        if (q > 0) by += 2.0 * bsz[q] * tsz[q - 1];
-      }
-      const double cost = by * 8.0 / 4.0e12 + (3.0 * cand - 1.0) * 6.0e-6;
-      if (cost < best * 0.999) { best = cost; G = cand; }
-    }
-    if (h->coarse_blocks > 0) G = std::min(h->coarse_blocks, nl);
+  // coarse numbering: nested-dissection fronts, level by level (see nd.hpp)
+  NdPlan &P = h->nd;
+  try {
+    nd_plan(L, h->face_k, h->coarse_leaf, P);
+  } catch (const std::logic_error &e) {
+    throw Error{BDDC_EINVAL, std::string("coarse plan: ") + e.what()};
   }
-  h->nblk_c = G;
-  h->slab_axis = ax;
-  std::vector<int> face_cofs(nF), sub_coff(N + 1, 0), sub_cmap, pidx(N, -1);
-  std::vector<int> boff(G + 1, 0), toff(G, 0);
-  int ncu = 0, cur = 0;
-  for (int q = 0; q < G; ++q) {
-    boff[q] = cur;
-    for (int pass = 0; pass < 2; ++pass) {     // 0: faces inside the group, 1: faces to group q+1
-      if (pass == 1) toff[q] = cur;
-      for (int f = 0; f < nF; ++f) {
-        const int ga = (int)((int64_t)layer_of(L.f_minus[f]) * G / nl), gb = (int)((int64_t)layer_of(L.f_plus[f]) * G / nl);
-        if (ga != q || (pass == 0) != (ga == gb)) continue;
-        face_cofs[f] = cur;
-        cur += 1 + h->face_k[f];
-        ncu += 1 + h->face_k[f];
-      }
-    }
-    for (int i = 0; i < N - 1; ++i)
-      if ((int)((int64_t)layer_of(i) * G / nl) == q) pidx[i] = cur++;
-  }
-  boff[G] = cur;
-  const int nkc = cur;
-  std::vector<int> co_minus(nkc, -1), co_plus(nkc, -1), blk(nkc, 0);
-  for (int q = 0; q < G; ++q)
-    for (int g2 = boff[q]; g2 < boff[q + 1]; ++g2) blk[g2] = q;
+  const std::vector<int> &face_cofs = P.face_cofs, &pidx = P.pidx;
+  std::vector<int> sub_coff(N + 1, 0), sub_cmap;
+  int ncu = 0;
+  for (int f = 0; f < nF; ++f) ncu += 1 + h->face_k[f];
+  const int nkc = P.nk;
+  std::vector<int> co_minus(nkc, -1), co_plus(nkc, -1);
   for (int i = 0; i < N; ++i) {
     for (int t = L.sub_face_off[i]; t < L.sub_face_off[i + 1]; ++t) {
       const int f = L.sub_faces[t];
@@ -377,8 +328,6 @@ void do_setup(bddc_problem *h, const bddc_grid *gr, const double *perm, const bd
   h->ncu = ncu;
   h->nk = nkc;
   h->sub_coff_h = sub_coff;
-  h->boff_h = boff;
-  h->toff_h = toff;
   h->pidx_h = pidx;
   DevCoarse &cs = h->cs;
   cs.ncu = ncu;
@@ -419,124 +368,71 @@ void do_setup(bddc_problem *h, const bddc_grid *gr, const double *perm, const bd
   HIPCHK(hipStreamSynchronize(s));
   check_err(h, "the local coarse spaces");
 
-  // S6: coarse saddle point, block signed Cholesky in slab order
+  // S6: coarse saddle point, multifrontal signed Cholesky level by level
   const int nk = h->nk;
+  h->coarse_bytes = 0.0;
   if (nk > 0) {
-    std::vector<int64_t> doff(G), eoff(G, 0), lroff(G), moff(G, 0), lcoff(G, 0);
-    int64_t ds = 0, es2 = 0, lrs = 0, ms = 0, lcs = 0;
-    int bmax = 0, tmax = 1;
-    for (int q = 0; q < G; ++q) {
-      const int64_t b = boff[q + 1] - boff[q];
-      const int64_t t = (q + 1 < G) ? boff[q + 1] - toff[q] : 0;
-      bmax = std::max<int>(bmax, (int)b);
-      tmax = std::max<int>(tmax, (int)t);
-      doff[q] = ds; ds += b * b;
-      lroff[q] = lrs; lrs += b * (b + 1) / 2;
-      if (q + 1 < G) {
-        const int64_t bn = boff[q + 2] - boff[q + 1];
-        eoff[q] = es2; es2 += bn * t;
-        lcoff[q] = lcs; lcs += bn * t;
-      }
-      if (q > 0) {
-        const int64_t tp = boff[q] - toff[q - 1];
-        moff[q] = ms; ms += b * tp;
-      }
-    }
-    h->lr_off = lroff;
-    h->m_off = moff;
-    h->lc_off = lcoff;
-    double *Dall = h->alloc<double>(ds);
-    double *Eall = h->alloc<double>(es2);
-    double *Wfull = h->alloc<double>((int64_t)bmax * bmax);
-    double *Mtmp = h->alloc<double>((int64_t)bmax * tmax);
-    h->LinvR = h->alloc<double>(lrs);
-    h->LinvC = h->alloc<double>(lrs);
-    h->Mblk = h->alloc<double>(ms);
-    h->Lcblk = h->alloc<double>(lcs);
+    DevFronts &fd = h->fd;
+    fd.first = h->upload(P.first);
+    fd.n = h->upload(P.n);
+    fd.m = h->upload(P.m);
+    fd.ch = h->upload(P.ch);
+    fd.b_off = h->upload(P.b_off);
+    fd.bidx = h->upload(P.bidx);
+    fd.ext = h->upload(P.ext);
+    fd.touch_off = h->upload(P.touch_off);
+    fd.touch = h->upload(P.touch);
+    fd.F_off = h->upload(P.F_off);
+    fd.w_off = h->upload(P.w_off);
+    fd.q_off = h->upload(P.q_off);
+    fd.r_off = h->upload(P.r_off);
+    fd.v_off = h->upload(P.v_off);
+    const int nfr = P.nfr;
+    double *Fall = h->alloc<double>(P.F_off[nfr]);
+    double *Wall = h->alloc<double>(P.w_off[nfr]);
+    double *Qall = h->alloc<double>(P.q_off[nfr]);
+    h->FR = h->alloc<double>(P.r_off[nfr]);
+    h->BC = h->alloc<double>(P.r_off[nfr]);
     h->cy = h->alloc<double>(nk);
-    h->cu = h->alloc<double>(tmax);
+    h->cS0 = h->alloc<double>(P.v_off[nfr]);
+    h->cS1 = h->alloc<double>(P.v_off[nfr]);
+    h->cXB = h->alloc<double>(P.b_off[nfr]);
+    fill(h, h->cS0, P.v_off[nfr], 0.0);   // slots no child writes stay zero
+    fill(h, h->cS1, P.v_off[nfr], 0.0);
+    DevSweep &sv = h->sw;
+    sv.first = fd.first;
+    sv.n = fd.n;
+    sv.m = fd.m;
+    sv.gf = h->upload(P.gf);
+    sv.gb = h->upload(P.gb);
+    sv.cslot = h->upload(P.cslot);
+    sv.b_off = fd.b_off;
+    sv.wdst = h->upload(P.wdst);
+    sv.r_off = fd.r_off;
+    sv.v_off = fd.v_off;
+    sv.xsc = (const int2 *)h->upload(P.xsc);
+    sv.ftask = (const int2 *)h->upload(P.ftask);
+    sv.btask = (const int2 *)h->upload(P.btask);
+    sv.xcp = (const int2 *)h->upload(P.xcp);
     std::vector<double> sg(nk, 1.0);
     for (int i = 0; i < N; ++i)
       if (pidx[i] >= 0) sg[pidx[i]] = -1.0;
     h->csgn = h->upload(sg);
-    fill(h, Dall, ds, 0.0);
-    fill(h, Eall, es2, 0.0);
-    BlockMap bm;
-    bm.J = G;
-    bm.blk = h->upload(blk);
-    bm.boff = h->upload(boff);
-    bm.toff = h->upload(toff);
-    bm.D = Dall;
-    bm.d_off = h->upload(doff);
-    bm.E = Eall;
-    bm.e_off = h->upload(eoff);
-    k_block_assemble<<<N, 256, 0, s>>>(g, cs, bm, cw.Ac, cw.ac_off, h->dscale);
-    HIPCHK(hipGetLastError());
-    h->coarse_bytes = 0.0;
-    for (int q = 0; q < G; ++q) {
-      const int b = boff[q + 1] - boff[q];
-      double *Dq = Dall + doff[q];
-      const double *sq = h->csgn + boff[q];
-      if (q > 0) {
-        const int tp = boff[q] - toff[q - 1];
-        dim3 grid(nblk(b, TILE), nblk(b, TILE));
-        k_gemm_tiles<false, true, true><<<grid, 256, 0, s>>>(b, b, tp, -1.0, h->Lcblk + lcoff[q - 1], b,
-                                                             h->Lcblk + lcoff[q - 1], b, 1.0, Dq, b,
-                                                             h->csgn + toff[q - 1]);
-      }
-      if (b <= 512) {
-        k_potrf_one<<<1, 256, 0, s>>>(b, Dq, sq, h->d_err);
-      } else {
-        for (int k0 = 0; k0 < b; k0 += NB) {
-          const int nb = std::min(NB, b - k0);
-          k_potrf_diag<<<1, 256, 0, s>>>(b, Dq, k0, nb, sq, h->d_err);
-          const int rows = b - k0 - nb;
-          if (rows > 0) {
-            k_potrf_panel<<<nblk(rows), 256, 0, s>>>(b, Dq, k0, nb, sq);
-            dim3 grid(nblk(rows, TILE), nblk(rows, TILE));
-            k_gemm_tiles<false, true, true><<<grid, 256, 0, s>>>(rows, rows, nb, -1.0, Dq + (k0 + nb) + (size_t)k0 * b,
-                                                                 b, Dq + (k0 + nb) + (size_t)k0 * b, b, 1.0,
-                                                                 Dq + (k0 + nb) + (size_t)(k0 + nb) * b, b, sq + k0);
-          }
-        }
-      }
-      k_trtri_cols<<<nblk(b, 32), 256, 0, s>>>(b, Dq, Wfull, 32);
-      k_pack_lower<<<nblk((int64_t)b * b), 256, 0, s>>>(b, Wfull, h->LinvR + lroff[q], h->LinvC + lroff[q]);
-      h->coarse_bytes += 8.0 * (double)b * b;
-      if (q > 0) {
-        const int tp = boff[q] - toff[q - 1];
-        dim3 grid(nblk(b, TILE), nblk(tp, TILE));
-        k_gemm_tiles<false, false, false><<<grid, 256, 0, s>>>(b, tp, b, 1.0, Wfull, b, h->Lcblk + lcoff[q - 1], b,
-                                                               0.0, Mtmp, b, nullptr);
-        k_to_rowmajor<<<nblk((int64_t)b * tp), 256, 0, s>>>(b, tp, Mtmp, h->Mblk + moff[q]);
-        h->coarse_bytes += 8.0 * (double)b * tp;
-      }
-      if (q + 1 < G) {
-        const int bn = boff[q + 2] - boff[q + 1];
-        const int t = boff[q + 1] - toff[q];
-        const int ts = toff[q] - boff[q];
-        dim3 grid(nblk(bn, TILE), nblk(t, TILE));
-        k_gemm_tiles<false, true, false><<<grid, 256, 0, s>>>(bn, t, t, 1.0, Eall + eoff[q], bn,
-                                                              Wfull + ts + (size_t)ts * b, b, 0.0,
-                                                              h->Lcblk + lcoff[q], bn, nullptr);
-        k_scale_cols<<<nblk((int64_t)bn * t), 256, 0, s>>>(bn, t, h->Lcblk + lcoff[q], bn, h->csgn + toff[q]);
-        h->coarse_bytes += 8.0 * (double)bn * t;
-      }
+    for (int lv = 0; lv < P.H; ++lv) {
+      const int f0 = P.lvl_off[lv], nf = P.lvl_off[lv + 1] - f0;
+      k_front_factor<<<nf, 256, 0, s>>>(g, cs, fd, f0, cw.Ac, cw.ac_off, h->dscale, h->csgn, Fall, Wall, Qall,
+                                        h->FR, h->BC, h->d_err);
       HIPCHK(hipGetLastError());
     }
     HIPCHK(hipStreamSynchronize(s));
     check_err(h, "the coarse problem");
-    h->release(Dall);
-    h->release(Eall);
-    h->release(Wfull);
-    h->release(Mtmp);
+    h->release(Fall);
+    h->release(Wall);
+    h->release(Qall);
+    // streamed per coarse solve: R twice (rows forward, columns backward)
+    h->coarse_bytes = 2.0 * 8.0 * (double)P.r_off[nfr];
   }
-  h->release(wsb);
-  h->release(cw.base);
-  h->release(cw.Ac);
-  h->release(d_perm);
 
-  // solve work arrays
   const int nGm = L.nGamma;
   const int64_t totG = L.g_off[N];
   h->xu = h->alloc<double>(nGm);
@@ -575,26 +471,19 @@ void do_setup(bddc_problem *h, const bddc_grid *gr, const double *perm, const bd
   h->stats.bytes_per_iter = h->stats.bytes_prec + sumpk * 8.0 + 2.0 * totG * 8.0 + 8.0 * nGm * 8.0;
 }
 
-// Coarse solve csol = K^{-1} bc by the block forward / backward sweeps.
+// Coarse solve csol = K^{-1} bc by the multifrontal forward / backward sweeps.
 void launch_coarse_solve(bddc_problem *h, const int *done) {
   hipStream_t s = h->stream;
-  const int G = h->nblk_c;
-  const std::vector<int> &bo = h->boff_h, &to = h->toff_h;
-  for (int q = 0; q < G; ++q) {
-    const int b = bo[q + 1] - bo[q];
-    const int tp = q > 0 ? bo[q] - to[q - 1] : 0;
-    k_cfwd<<<(b + 1) / 2, 256, 0, s>>>(b, h->LinvR + h->lr_off[q], h->bc + bo[q], q > 0 ? h->Mblk + h->m_off[q] : nullptr,
-                                      tp, q > 0 ? h->cy + to[q - 1] : nullptr, h->cy + bo[q], done);
+  const NdPlan &P = h->nd;
+  if (h->nk == 0) return;
+  for (int lv = 0; lv < P.H; ++lv) {
+    const int t0 = P.ftask_off[lv], nt = P.ftask_off[lv + 1] - t0;
+    k_nd_fwd<<<nt, 256, 0, s>>>(t0, h->sw, h->FR, h->bc, h->cS0, h->cS1, h->cy, done);
   }
-  for (int q = G - 1; q >= 0; --q) {
-    const int b = bo[q + 1] - bo[q];
-    if (q + 1 < G) {
-      const int bn = bo[q + 2] - bo[q + 1], t = bo[q + 1] - to[q];
-      k_cbwd_u<<<t, 256, 0, s>>>(bn, t, h->Lcblk + h->lc_off[q], h->csol + bo[q + 1], h->cu, done);
-    }
-    k_cbwd_x<<<(b + 1) / 2, 256, 0, s>>>(b, h->LinvC + h->lr_off[q], h->cy + bo[q], h->csgn + bo[q],
-                                        q + 1 < G ? h->cu : nullptr, q + 1 < G ? to[q] - bo[q] : b,
-                                        h->csol + bo[q], done);
+  for (int lv = P.H - 1; lv >= 0; --lv) {
+    const int t0 = P.btask_off[lv], nt = P.btask_off[lv + 1] - t0;
+    k_nd_bwd<<<nt, 256, 0, s>>>(t0, P.xcp_off[lv], P.xcp_off[lv + 1], h->sw, h->BC, h->cy, h->csgn, h->cXB,
+                                h->csol, done);
   }
 }
 
@@ -822,7 +711,7 @@ int bddc_setup(const bddc_grid *g, const double *perm, const bddc_partition *par
         h->precision = opt->precision;
         if (opt->max_it > 0) h->max_it = opt->max_it;
         h->flags = opt->flags;
-        h->coarse_blocks = opt->coarse_blocks;
+        h->coarse_leaf = opt->coarse_leaf;
       }
       if (h->precision != BDDC_FP64 && h->precision != BDDC_MIXED) throw Error{BDDC_EINVAL, "bad precision"};
       h->tau = tau;
@@ -860,7 +749,8 @@ int bddc_stats(bddc_handle h, bddc_stats_t *out) {
     s.n_gamma = h->L.nGamma;
     s.n_faces = h->L.nF;
     s.precision = h->precision;
-    s.coarse_blocks = h->nblk_c;
+    s.coarse_levels = h->nd.H;
+    s.coarse_fronts = h->nd.nfr;
     s.device_bytes = h->device_bytes;
     *out = s;
     return BDDC_OK;

@@ -146,7 +146,12 @@ __device__ __forceinline__ int lds_sign_chol(double *L, int nb, const double *s,
 // In-place blocked signed Cholesky of the n x n lower triangle of A:
 // A = L diag(s) L^T with s = +-1 per column (s == nullptr: ordinary Cholesky).
 // Returns 0, or (index + 1) of the first pivot whose sign disagrees with s.
-__device__ __forceinline__ int wg_potrf(int n, double *A, int lda, double *lds, const double *s = nullptr) {
+// With nrows > n only the first n pivots are taken over the nrows x nrows
+// lower triangle: rows n.. receive the panel A_{2,1} L_11^{-T} diag(s) and the
+// trailing block the update A_22 - L_21 diag(s) L_21^T.
+__device__ __forceinline__ int wg_potrf(int n, double *A, int lda, double *lds, const double *s = nullptr,
+                                        int nrows = -1) {
+  const int nr = nrows < 0 ? n : nrows;
   double *Lk = lds + 2 * KT * TILE;  // NB x NB
   double *sk = Lk + NB * NB;         // NB signs
   int *flag = (int *)(sk + NB);      // pivot-failure word
@@ -168,7 +173,7 @@ __device__ __forceinline__ int wg_potrf(int n, double *A, int lda, double *lds, 
     }
     // panel: X with X diag(s_k) L_kk^T = A_panel  (row-wise forward substitution)
     const int r0 = k0 + nb;
-    for (int r = r0 + tid; r < n; r += WG) {
+    for (int r = r0 + tid; r < nr; r += WG) {
       double x[NB];
 #pragma unroll
       for (int j = 0; j < NB; ++j) {
@@ -185,9 +190,9 @@ __device__ __forceinline__ int wg_potrf(int n, double *A, int lda, double *lds, 
     }
     __syncthreads();
     // trailing: A22 -= X diag(s_k) X^T  (lower triangle only)
-    if (r0 < n) {
+    if (r0 < nr) {
       double *X = A + r0 + (size_t)k0 * lda;
-      wg_gemm<false, true, true>(n - r0, n - r0, nb, -1.0, X, lda, X, lda, 1.0,
+      wg_gemm<false, true, true>(nr - r0, nr - r0, nb, -1.0, X, lda, X, lda, 1.0,
                                  A + r0 + (size_t)r0 * lda, lda, lds, sk);
     }
   }

@@ -1,0 +1,367 @@
+// Nested-dissection plan of the coarse saddle point (host side).
+//
+// The coarse unknowns of Algorithm "BDDC preconditioner" step 1 are the face
+// averages and adaptive rows of every face (Section 4) and one rescaled
+// pressure per subdomain (the last subdomain's pressure is pinned).  A
+// subdomain's coarse dofs form a dense clique of the coarse matrix, and two
+// subdomains couple only through the dofs of a face they share, so the
+// subdomain grid dissects like a Cartesian mesh: a plane of faces splits a box
+// of subdomains into two boxes that do not couple.  Recursive bisection of the
+// box along its longest axis gives a tree of separator fronts; a leaf box (at
+// most `leaf` subdomains) keeps its interior faces as one front.
+//
+// A pressure joins the front of the separator nearest the root among those
+// that hold one of its faces, so it is eliminated after every face it couples
+// to.  Then each leading principal block of the coarse matrix is a saddle
+// point with an SPD flux block and divergence rows of full rank, so the signed
+// factorization K = L diag(s) L^T exists with s = +1 on face dofs and -1 on
+// pressures, without pivoting.
+//
+// Fronts are numbered level by level (height above the leaves, then creation
+// order) and the coarse dofs follow the front order, so the fronts of one
+// level, their dofs and their work vectors are contiguous.  For front p with
+// own dofs P (n_p) and later dofs B(p) (m_p) it couples to after elimination
+// (the boundary of its subtree, all in ancestor fronts), the plan records
+// B(p), the position of every entry of B(p) in the parent's index list
+// [P(parent), B(parent)] (extend-add map) and the storage offsets.
+#pragma once
+#include <stdint.h>
+
+#include <algorithm>
+#include <stdexcept>
+#include <vector>
+
+#include "layout.hpp"
+
+namespace bddc {
+
+struct NdPlan {
+  int H = 0;                        // levels
+  int nfr = 0;                      // fronts
+  int nk = 0;                       // coarse dofs (pinned pressure excluded)
+  std::vector<int> lvl_off;         // [H+1] fronts of level h
+  std::vector<int> lvl_dof;         // [H+1] coarse dofs of level h
+  std::vector<int> first, n, m;     // per front: first own dof, own dofs, later dofs
+  std::vector<int> ch;              // [2 nfr] children (-1: none)
+  std::vector<int> b_off, bidx;     // [nfr+1], B(p) ascending
+  std::vector<int> ext;             // aligned with bidx: position in the parent's list
+  std::vector<int> touch_off, touch;  // subdomains whose coarse dofs meet front p
+  std::vector<int> face_cofs;       // per face: its first coarse dof
+  std::vector<int> pidx;            // per subdomain: pressure dof or -1
+  std::vector<int> dfront;          // [nk] front of every dof
+  std::vector<int64_t> F_off, w_off, q_off, r_off, v_off;  // [nfr+1] storage prefix sums
+  // solve sweeps (coarse.hip): lane-group width per front, the slot (0/1) of
+  // every front among its parent's children, forward push targets of the B
+  // rows, backward scatter targets of the own dofs and the copies of the
+  // parents' B values into their children's B vectors
+  std::vector<int> gf, gb;          // [nfr] group widths, forward rows / backward columns
+  std::vector<int> cslot;           // [nfr]
+  std::vector<int> wdst;            // [sum m] forward: position of w_c[k] in the parent's vectors
+  std::vector<int> xsc;             // [2 nk] backward: positions in the children's B vectors or -1
+  std::vector<int> xcp;             // [2 ncopy] backward copies {dst, src} in B-vector positions
+  std::vector<int> xcp_off;         // [H+1] copies of level h
+  std::vector<int> ftask, btask;    // [2 ntask] {front, first row / column}
+  std::vector<int> ftask_off, btask_off;  // [H+1]
+};
+
+// `leaf`: largest number of subdomains in a leaf box (>= 1).
+inline void nd_plan(const Layout &L, const std::vector<int> &face_k, int leaf, NdPlan &P) {
+  const int N = L.N, nF = L.nF;
+  if (leaf < 1) leaf = 1;
+  struct Node {
+    int lo[3], hi[3];
+    int ch[2] = {-1, -1};
+    int depth = 0, height = 0;
+    std::vector<int> faces, press;
+  };
+  std::vector<Node> nodes;
+  std::vector<int> face_node(nF, -1);
+  std::vector<int> fpos(3 * nF);   // subdomain-grid position of every face's minus side
+  for (int f = 0; f < nF; ++f)
+    for (int e = 0; e < 3; ++e) fpos[3 * f + e] = (L.f_minus[f] / L.sstride[e]) % L.nsub[e];
+  // faces of a box interior, or of its cut plane (axis d, between layers cut-1 and cut)
+  auto collect = [&](const int *lo, const int *hi, int d, int cut, std::vector<int> &out) {
+    for (int f = 0; f < nF; ++f) {
+      const int *s = &fpos[3 * f];
+      bool in = true;
+      for (int e = 0; e < 3; ++e) in = in && s[e] >= lo[e] && s[e] < hi[e];
+      if (!in) continue;
+      const int fd = L.f_dir[f];
+      if (s[fd] + 1 >= hi[fd]) continue;      // the plus side lies outside the box
+      if (d >= 0 && (fd != d || s[d] != cut - 1)) continue;
+      out.push_back(f);
+    }
+  };
+  // coarse dofs of the +d face of every subdomain (0 where there is none)
+  std::vector<int> wface(3 * (size_t)N, 0);
+  for (int f = 0; f < nF; ++f) wface[3 * (size_t)L.f_minus[f] + L.f_dir[f]] = 1 + face_k[f];
+  // dofs of the plane between layers cut-1 and cut (axis d) inside the box
+  auto plane_weight = [&](const int *lo, const int *hi, int d, int cut) {
+    const int a = (d + 1) % 3, b = (d + 2) % 3;
+    int64_t w = 0;
+    int s[3];
+    s[d] = cut - 1;
+    for (s[a] = lo[a]; s[a] < hi[a]; ++s[a])
+      for (s[b] = lo[b]; s[b] < hi[b]; ++s[b])
+        w += wface[3 * (size_t)(s[0] * L.sstride[0] + s[1] * L.sstride[1] + s[2] * L.sstride[2]) + d];
+    return w;
+  };
+  // recursive bisection; returns the node id or -1 (box without faces).  The
+  // cut is the plane with the fewest coarse dofs among those that leave at
+  // least a quarter of the box extent on either side (ties: the more balanced
+  // cut, then the lower axis), so that faces rich in adaptive constraints end
+  // up in small fronts low in the tree.
+  auto build = [&](auto &&self, const int *lo, const int *hi, int depth) -> int {
+    int ext[3], cnt = 1;
+    for (int e = 0; e < 3; ++e) {
+      ext[e] = hi[e] - lo[e];
+      cnt *= ext[e];
+    }
+    Node nd;
+    for (int e = 0; e < 3; ++e) { nd.lo[e] = lo[e]; nd.hi[e] = hi[e]; }
+    nd.depth = depth;
+    if (cnt <= leaf) {
+      collect(lo, hi, -1, 0, nd.faces);
+      if (nd.faces.empty()) return -1;
+      nodes.push_back(nd);
+      return (int)nodes.size() - 1;
+    }
+    int d = -1, cut = 0;
+    int64_t bw = 0;
+    int bimb = 0;
+    for (int e = 0; e < 3; ++e) {
+      if (ext[e] < 2) continue;
+      const int side = std::max(1, (ext[e] + 3) / 4);
+      for (int c = lo[e] + side; c <= hi[e] - side; ++c) {
+        const int64_t w = plane_weight(lo, hi, e, c);
+        const int imb = std::abs((c - lo[e]) - (hi[e] - c));
+        if (d < 0 || w < bw || (w == bw && imb < bimb)) {
+          d = e;
+          cut = c;
+          bw = w;
+          bimb = imb;
+        }
+      }
+    }
+    int hi1[3] = {hi[0], hi[1], hi[2]}, lo2[3] = {lo[0], lo[1], lo[2]};
+    hi1[d] = cut;
+    lo2[d] = cut;
+    const int c0 = self(self, lo, hi1, depth + 1);
+    const int c1 = self(self, lo2, hi, depth + 1);
+    collect(lo, hi, d, cut, nd.faces);
+    nd.ch[0] = c0;
+    nd.ch[1] = c1;
+    nodes.push_back(nd);
+    return (int)nodes.size() - 1;
+  };
+  const int lo0[3] = {0, 0, 0}, hi0[3] = {L.nsub[0], L.nsub[1], L.nsub[2]};
+  if (N > 1) build(build, lo0, hi0, 0);
+  const int nn = (int)nodes.size();
+  for (int q = 0; q < nn; ++q)
+    for (int f : nodes[q].faces) {
+      if (face_node[f] >= 0) throw std::logic_error("coarse plan: face in two fronts");
+      face_node[f] = q;
+    }
+  for (int f = 0; f < nF; ++f)
+    if (face_node[f] < 0) throw std::logic_error("coarse plan: face in no front");
+  // pressures: the front nearest the root among those holding a face of i
+  for (int i = 0; i + 1 < N; ++i) {
+    int best = -1;
+    for (int t = L.sub_face_off[i]; t < L.sub_face_off[i + 1]; ++t) {
+      const int q = face_node[L.sub_faces[t]];
+      if (best < 0 || nodes[q].depth < nodes[best].depth) best = q;
+    }
+    if (best < 0) throw std::logic_error("coarse plan: subdomain without faces");
+    nodes[best].press.push_back(i);
+  }
+  // heights (children are created before their parent)
+  for (int q = 0; q < nn; ++q) {
+    int hq = 0;
+    for (int c : nodes[q].ch)
+      if (c >= 0) hq = std::max(hq, nodes[c].height + 1);
+    nodes[q].height = hq;
+  }
+  int H = 0;
+  for (int q = 0; q < nn; ++q) H = std::max(H, nodes[q].height + 1);
+  std::vector<int> order(nn);
+  for (int q = 0; q < nn; ++q) order[q] = q;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return nodes[a].height < nodes[b].height; });
+  std::vector<int> fid(nn);
+  for (int r = 0; r < nn; ++r) fid[order[r]] = r;
+
+  P = NdPlan();
+  P.H = H;
+  P.nfr = nn;
+  P.lvl_off.assign(H + 1, 0);
+  P.lvl_dof.assign(H + 1, 0);
+  P.first.assign(nn, 0);
+  P.n.assign(nn, 0);
+  P.m.assign(nn, 0);
+  P.ch.assign(2 * nn, -1);
+  P.face_cofs.assign(nF, -1);
+  P.pidx.assign(N, -1);
+  int cur = 0;
+  for (int r = 0; r < nn; ++r) {
+    Node &nd = nodes[order[r]];
+    std::sort(nd.faces.begin(), nd.faces.end());
+    std::sort(nd.press.begin(), nd.press.end());
+    P.first[r] = cur;
+    for (int f : nd.faces) {
+      P.face_cofs[f] = cur;
+      cur += 1 + face_k[f];
+    }
+    for (int i : nd.press) P.pidx[i] = cur++;
+    P.n[r] = cur - P.first[r];
+    for (int k = 0; k < 2; ++k) P.ch[2 * r + k] = nd.ch[k] >= 0 ? fid[nd.ch[k]] : -1;
+    if (P.ch[2 * r] < 0 && P.ch[2 * r + 1] >= 0) std::swap(P.ch[2 * r], P.ch[2 * r + 1]);
+  }
+  P.nk = cur;
+  for (int h = 0, r = 0; h <= H; ++h) {
+    while (r < nn && nodes[order[r]].height < h) ++r;
+    P.lvl_off[h] = r;
+    P.lvl_dof[h] = r < nn ? P.first[r] : cur;
+  }
+  P.dfront.assign(cur, 0);
+  for (int r = 0; r < nn; ++r)
+    for (int k = 0; k < P.n[r]; ++k) P.dfront[P.first[r] + k] = r;
+  // coarse dofs of every subdomain, and the subdomains meeting every front
+  std::vector<std::vector<int>> D(N);
+  std::vector<std::vector<int>> tch(nn);
+  for (int i = 0; i < N; ++i) {
+    for (int t = L.sub_face_off[i]; t < L.sub_face_off[i + 1]; ++t) {
+      const int f = L.sub_faces[t];
+      for (int l = 0; l <= face_k[f]; ++l) D[i].push_back(P.face_cofs[f] + l);
+      tch[fid[face_node[f]]].push_back(i);
+    }
+    if (P.pidx[i] >= 0) {
+      D[i].push_back(P.pidx[i]);
+      tch[P.dfront[P.pidx[i]]].push_back(i);
+    }
+    std::sort(D[i].begin(), D[i].end());
+  }
+  P.touch_off.assign(nn + 1, 0);
+  for (int r = 0; r < nn; ++r) {
+    std::sort(tch[r].begin(), tch[r].end());
+    tch[r].erase(std::unique(tch[r].begin(), tch[r].end()), tch[r].end());
+    P.touch_off[r + 1] = P.touch_off[r] + (int)tch[r].size();
+    P.touch.insert(P.touch.end(), tch[r].begin(), tch[r].end());
+  }
+  // B(p) = (coarse dofs of the touching subdomains and children's B) beyond p
+  std::vector<std::vector<int>> Bs(nn);
+  for (int r = 0; r < nn; ++r) {
+    const int last = P.first[r] + P.n[r] - 1;
+    std::vector<int> s;
+    for (int i : tch[r])
+      for (int v : D[i])
+        if (v > last) s.push_back(v);
+    for (int k = 0; k < 2; ++k) {
+      const int c = P.ch[2 * r + k];
+      if (c < 0) continue;
+      for (int v : Bs[c]) {
+        if (v < P.first[r]) throw std::logic_error("coarse plan: child couples outside its ancestors");
+        if (v > last) s.push_back(v);
+      }
+    }
+    std::sort(s.begin(), s.end());
+    s.erase(std::unique(s.begin(), s.end()), s.end());
+    Bs[r] = s;
+    P.m[r] = (int)s.size();
+  }
+  P.b_off.assign(nn + 1, 0);
+  for (int r = 0; r < nn; ++r) P.b_off[r + 1] = P.b_off[r] + P.m[r];
+  P.bidx.reserve(P.b_off[nn]);
+  for (int r = 0; r < nn; ++r) P.bidx.insert(P.bidx.end(), Bs[r].begin(), Bs[r].end());
+  // extend-add maps: position of B(c)[k] in [own(p), B(p)]
+  P.ext.assign(P.b_off[nn], -1);
+  std::vector<int> parent(nn, -1);
+  for (int r = 0; r < nn; ++r)
+    for (int k = 0; k < 2; ++k)
+      if (P.ch[2 * r + k] >= 0) parent[P.ch[2 * r + k]] = r;
+  for (int c = 0; c < nn; ++c) {
+    const int p = parent[c];
+    if (p < 0) {
+      if (P.m[c] != 0) throw std::logic_error("coarse plan: root with later dofs");
+      continue;
+    }
+    for (int k = 0; k < P.m[c]; ++k) {
+      const int v = Bs[c][k];
+      int pos;
+      if (v < P.first[p] + P.n[p]) {
+        pos = v - P.first[p];
+      } else {
+        auto it = std::lower_bound(Bs[p].begin(), Bs[p].end(), v);
+        if (it == Bs[p].end() || *it != v) throw std::logic_error("coarse plan: extend-add map");
+        pos = P.n[p] + (int)(it - Bs[p].begin());
+      }
+      P.ext[P.b_off[c] + k] = pos;
+    }
+  }
+  // storage offsets
+  P.F_off.assign(nn + 1, 0);
+  P.w_off.assign(nn + 1, 0);
+  P.q_off.assign(nn + 1, 0);
+  P.r_off.assign(nn + 1, 0);
+  P.v_off.assign(nn + 1, 0);
+  for (int r = 0; r < nn; ++r) {
+    const int64_t a = P.n[r], b = P.m[r];
+    P.F_off[r + 1] = P.F_off[r] + (a + b) * (a + b);
+    P.w_off[r + 1] = P.w_off[r] + a * a;
+    P.q_off[r + 1] = P.q_off[r] + a * b;
+    P.r_off[r + 1] = P.r_off[r] + a * (a + 1) / 2 + a * b;
+    P.v_off[r + 1] = P.v_off[r] + a + b;
+  }
+  // sweep maps
+  const int64_t nv = P.v_off[nn];
+  P.gf.assign(nn, 4);
+  P.gb.assign(nn, 4);
+  P.cslot.assign(nn, 0);
+  auto width = [](int len) { return len <= 24 ? 4 : (len <= 96 ? 16 : 64); };
+  for (int r = 0; r < nn; ++r) {
+    P.gf[r] = width(P.n[r]);
+    P.gb[r] = width(P.n[r] + P.m[r]);
+    for (int k = 0; k < 2; ++k)
+      if (P.ch[2 * r + k] >= 0) P.cslot[P.ch[2 * r + k]] = k;
+  }
+  P.wdst.assign(P.b_off[nn], -1);
+  P.xsc.assign(2 * (size_t)cur, -1);
+  P.xcp_off.assign(H + 1, 0);
+  std::vector<int> lvl_of(nn);
+  for (int h = 0; h < H; ++h)
+    for (int r = P.lvl_off[h]; r < P.lvl_off[h + 1]; ++r) lvl_of[r] = h;
+  std::vector<std::vector<int>> cps(H);
+  for (int c = 0; c < nn; ++c) {
+    const int p = parent[c];
+    if (p < 0) continue;
+    const int k = P.cslot[c];
+    for (int t = 0; t < P.m[c]; ++t) {
+      const int e = P.ext[P.b_off[c] + t];
+      P.wdst[P.b_off[c] + t] = (int)(P.v_off[p] + e);
+      if (e < P.n[p]) {
+        P.xsc[2 * (size_t)(P.first[p] + e) + k] = P.b_off[c] + t;
+      } else {
+        cps[lvl_of[p]].push_back(P.b_off[c] + t);
+        cps[lvl_of[p]].push_back(P.b_off[p] + e - P.n[p]);
+      }
+    }
+  }
+  for (int h = 0; h < H; ++h) {
+    P.xcp_off[h + 1] = P.xcp_off[h] + (int)cps[h].size() / 2;
+    P.xcp.insert(P.xcp.end(), cps[h].begin(), cps[h].end());
+  }
+  // tasks: one workgroup (256 lanes) per 256/g rows (forward) or columns (backward)
+  P.ftask_off.assign(H + 1, 0);
+  P.btask_off.assign(H + 1, 0);
+  for (int h = 0; h < H; ++h) {
+    for (int r = P.lvl_off[h]; r < P.lvl_off[h + 1]; ++r) {
+      const int fr = 256 / P.gf[r], br = 256 / P.gb[r];
+      for (int j = 0; j < P.n[r] + P.m[r]; j += fr) { P.ftask.push_back(r); P.ftask.push_back(j); }
+      for (int j = 0; j < P.n[r]; j += br) { P.btask.push_back(r); P.btask.push_back(j); }
+    }
+    P.ftask_off[h + 1] = (int)P.ftask.size() / 2;
+    P.btask_off[h + 1] = (int)P.btask.size() / 2;
+  }
+  if (nv > INT32_MAX) throw std::length_error("coarse plan: front vectors too long");
+}
+
+}  // namespace bddc

@@ -257,19 +257,29 @@ def test_device_pointer_solve_matches_host_solve():
     s.close()
 
 
-@pytest.mark.parametrize("blocks", [1, 2, 5, 22])
-def test_coarse_slab_blocks_agree(blocks):
-    """The block-tridiagonal coarse factorization gives the same solve for any slab grouping."""
+@pytest.mark.parametrize("leaf", [1, 2, 6, 132])
+def test_coarse_leaf_sizes_agree(leaf):
+    """The multifrontal coarse factorization gives the same solve for any dissection depth.
+
+    leaf = 132 keeps the whole 6 x 22 subdomain grid as one dense front.
+    """
     Solver = _gpu()
     pr = W.layer_60x220(0, tau=10.0)
-    s = Solver(pr.n, pr.h, pr.perm, pr.cuts, tau=10.0, coarse_blocks=blocks)
-    assert s.stats()["coarse_blocks"] == blocks
+    s = Solver(pr.n, pr.h, pr.perm, pr.cuts, tau=10.0, coarse_leaf=leaf)
+    st = s.stats()
+    if leaf == 132:
+        assert st["coarse_levels"] == 1 and st["coarse_fronts"] == 1
+    else:
+        assert st["coarse_levels"] > 1
     o = _oracle(pr, 10.0)
     rng = np.random.default_rng(2)
     xu = rng.standard_normal(o.subs.n_gamma)
     zu, zp = s.apply_precond(xu)
     ozu, ozp = o.precondition(xu)
     assert _relerr(zu, ozu) <= 1e-10
+    v = 1.0 / o.d                      # kernel of B_c^T: the constant physical pressure
+    c = (ozp - zp) @ v / (v @ v)
+    assert _relerr(zp + c * v, ozp) <= 1e-9
     u, p = s.solve(pr.source, rtol=1e-8)
     ref = o.solve(pr.source, rtol=1e-8, maxit=3000)
     assert s.stats()["it"] == ref["it"]

@@ -1,0 +1,283 @@
+"""Host logic of the coarse multifrontal solver: the nested-dissection plan.
+
+The plan (csrc/nd.hpp) is compiled into a small host driver and checked here
+without a GPU.  A random saddle point with the coarse problem's structure (one
+dense SPD clique per subdomain on its face dofs, divergence rows -d_i * (+-1)
+coupling each pressure to its face averages, last pressure pinned) is factored
+and solved by a numpy transcription of the index arithmetic of the device
+kernels (front assembly, extend-add, partial signed Cholesky, packed R storage,
+push-form forward / backward sweeps).  The result must equal a dense solve, the
+pivot signs must be +1 on face dofs and -1 on pressures, every packed entry and
+every sweep row / column must be produced exactly once, and every B-vector
+entry must be filled before it is read.
+"""
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "host", "nd_plan_dump.cpp")
+
+
+@pytest.fixture(scope="module")
+def dumper(tmp_path_factory):
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("g++ not available")
+    exe = str(tmp_path_factory.mktemp("nd") / "nd_plan_dump")
+    subprocess.run([gxx, "-O1", "-std=c++17", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+                    "-o", exe, SRC], check=True)
+    return exe
+
+
+SCALARS = ("N", "nF", "H", "nfr", "nk")
+
+
+def load(exe, args):
+    out = subprocess.run([exe] + [str(a) for a in args], capture_output=True, text=True, check=True).stdout
+    d = {}
+    for line in out.splitlines():
+        t = line.split()
+        if t[0] in SCALARS:
+            d[t[0]] = int(t[1])
+        else:
+            d[t[0]] = np.array([int(x) for x in t[2:]], dtype=np.int64)
+            assert len(d[t[0]]) == int(t[1])
+    return d
+
+
+def coarse_matrix(P, rng):
+    N, nk = P["N"], P["nk"]
+    fk, sfo, sf, fm, cof, pidx = P["face_k"], P["sub_face_off"], P["sub_faces"], P["f_minus"], P["face_cofs"], P["pidx"]
+    sub_coff, cmap = [0], []
+    for i in range(N):
+        for t in range(sfo[i], sfo[i + 1]):
+            f = sf[t]
+            cmap.extend(range(cof[f], cof[f] + fk[f] + 1))
+        sub_coff.append(len(cmap))
+    cmap = np.array(cmap, dtype=np.int64)
+    K = np.zeros((nk, nk))
+    Ac = []
+    dsc = rng.uniform(0.5, 2.0, N)
+    for i in range(N):
+        nci = sub_coff[i + 1] - sub_coff[i]
+        G = rng.standard_normal((nci, nci))
+        A = G @ G.T / max(nci, 1) + np.eye(nci)
+        Ac.append(A)
+        idx = cmap[sub_coff[i]:sub_coff[i + 1]]
+        K[np.ix_(idx, idx)] += A
+        if pidx[i] >= 0:
+            for t in range(sfo[i], sfo[i + 1]):
+                f = sf[t]
+                so = 1.0 if fm[f] == i else -1.0
+                K[pidx[i], cof[f]] += -dsc[i] * so
+                K[cof[f], pidx[i]] += -dsc[i] * so
+    sg = np.ones(nk)
+    sg[pidx[pidx >= 0]] = -1.0
+    return K, Ac, cmap, np.array(sub_coff), dsc, sg
+
+
+def factor(P, Ac, cmap, sub_coff, dsc, sg):
+    """Front assembly and partial signed factorization as k_front_factor does it."""
+    nfr = P["nfr"]
+    first, n, m, ch, b_off, bidx, ext = P["first"], P["n"], P["m"], P["ch"], P["b_off"], P["bidx"], P["ext"]
+    sfo, sf, fm, cof, pidx = P["sub_face_off"], P["sub_faces"], P["f_minus"], P["face_cofs"], P["pidx"]
+    F = np.full(P["F_off"][nfr], np.nan)
+    FR = np.full(P["r_off"][nfr], np.nan)
+    BC = np.full(P["r_off"][nfr], np.nan)
+    for lv in range(P["H"]):
+        for p in range(P["lvl_off"][lv], P["lvl_off"][lv + 1]):
+            fst, nn, mm = first[p], n[p], m[p]
+            f = nn + mm
+            Bp = bidx[b_off[p]:b_off[p] + mm]
+            assert (np.diff(Bp) > 0).all() and (mm == 0 or Bp[0] >= fst + nn)
+            fo = P["F_off"][p]
+            assert P["F_off"][p + 1] - fo == f * f
+            F[fo:fo + f * f] = 0.0
+
+            def pos(u):
+                if u < fst + nn:
+                    return u - fst
+                k = np.searchsorted(Bp, u)
+                return nn + k if (k < mm and Bp[k] == u) else -1
+
+            for t in range(P["touch_off"][p], P["touch_off"][p + 1]):
+                i = P["touch"][t]
+                idx = cmap[sub_coff[i]:sub_coff[i + 1]]
+                for a, u in enumerate(idx):
+                    for bb, v in enumerate(idx):
+                        if u < v or v < fst or v >= fst + nn:
+                            continue
+                        pu = pos(u)
+                        assert pu >= 0
+                        F[fo + pu + (v - fst) * f] += Ac[i][a, bb]
+                if pidx[i] >= 0:
+                    for t2 in range(sfo[i], sfo[i + 1]):
+                        fc = sf[t2]
+                        jf = cof[fc]
+                        if jf < fst or jf >= fst + nn:
+                            continue
+                        pp = pos(pidx[i])
+                        assert pp >= 0 and pidx[i] > jf
+                        F[fo + pp + (jf - fst) * f] += -dsc[i] * (1.0 if fm[fc] == i else -1.0)
+            for k in range(2):
+                c = ch[2 * p + k]
+                if c < 0:
+                    continue
+                nc, mc = n[c], m[c]
+                fc = nc + mc
+                uo = P["F_off"][c] + nc + nc * fc
+                ex = ext[b_off[c]:b_off[c] + mc]
+                assert (ex >= 0).all() and (ex < f).all() and (np.diff(ex) > 0).all()
+                for k2 in range(mc):
+                    for k1 in range(k2, mc):
+                        F[fo + ex[k1] + ex[k2] * f] += F[uo + k1 + k2 * fc]
+            Fm = F[fo:fo + f * f].reshape(f, f, order="F")
+            L = np.tril(Fm).copy()
+            s = sg[fst:fst + nn]
+            for j in range(nn):
+                dj = s[j] * L[j, j]
+                assert dj > 0, "pivot sign disagrees with s"
+                L[j, j] = np.sqrt(dj)
+                L[j + 1:, j] /= L[j, j] * s[j]
+                L[j + 1:, j + 1:] -= s[j] * np.outer(L[j + 1:, j], L[j + 1:, j])
+            Fm[np.tri(f, dtype=bool)] = L[np.tri(f, dtype=bool)]
+            Wp = np.linalg.inv(Fm[:nn, :nn] * np.tri(nn))
+            Qp = Fm[nn:, :nn] @ Wp
+            ro = P["r_off"][p]
+            tri = nn * (nn + 1) // 2
+            assert P["r_off"][p + 1] - ro == tri + mm * nn
+            for r in range(nn):
+                for c in range(r + 1):
+                    FR[ro + r * (r + 1) // 2 + c] = Wp[r, c]
+                    BC[ro + c * f - c * (c - 1) // 2 + (r - c)] = Wp[r, c]
+            for k in range(mm):
+                for c in range(nn):
+                    FR[ro + tri + k * nn + c] = Qp[k, c]
+                    BC[ro + c * f - c * (c - 1) // 2 + (nn - c) + k] = Qp[k, c]
+    assert not np.isnan(FR).any() and not np.isnan(BC).any()
+    return FR, BC
+
+
+def sweep(P, FR, BC, sg, b):
+    """k_nd_fwd / k_nd_bwd, level by level."""
+    nfr, nk, H = P["nfr"], P["nk"], P["H"]
+    first, n, m, b_off = P["first"], P["n"], P["m"], P["b_off"]
+    nv = P["v_off"][nfr]
+    S = [np.zeros(nv), np.zeros(nv)]
+    written = np.zeros((2, nv), bool)
+    z = np.full(nk, np.nan)
+    x = np.full(nk, np.nan)
+    XB = np.full(max(1, P["b_off"][nfr]), np.nan)
+    ft, bt = P["ftask"].reshape(-1, 2), P["btask"].reshape(-1, 2)
+    for lv in range(H):
+        done = set()
+        for task in range(P["ftask_off"][lv], P["ftask_off"][lv + 1]):
+            p, r0 = ft[task]
+            assert P["lvl_off"][lv] <= p < P["lvl_off"][lv + 1]
+            nn, mm, vo = n[p], m[p], P["v_off"][p]
+            t = b[first[p]:first[p] + nn] + S[0][vo:vo + nn] + S[1][vo:vo + nn]
+            for r in range(r0, min(r0 + 256 // P["gf"][p], nn + mm)):
+                assert (p, r) not in done
+                done.add((p, r))
+                if r < nn:
+                    o = P["r_off"][p] + r * (r + 1) // 2
+                    z[first[p] + r] = FR[o:o + r + 1] @ t[:r + 1]
+                else:
+                    o = P["r_off"][p] + nn * (nn + 1) // 2 + (r - nn) * nn
+                    dst, sl = P["wdst"][b_off[p] + r - nn], P["cslot"][p]
+                    assert not written[sl, dst]
+                    written[sl, dst] = True
+                    S[sl][dst] = S[0][vo + r] + S[1][vo + r] - FR[o:o + nn] @ t
+        assert len(done) == sum(n[p] + m[p] for p in range(P["lvl_off"][lv], P["lvl_off"][lv + 1]))
+    for lv in range(H - 1, -1, -1):
+        done = set()
+        XBn = XB.copy()
+        for task in range(P["btask_off"][lv], P["btask_off"][lv + 1]):
+            p, c0 = bt[task]
+            fst, nn, mm = first[p], n[p], m[p]
+            f = nn + mm
+            xb = XB[b_off[p]:b_off[p] + mm]
+            assert not np.isnan(xb).any(), "B vector read before it was filled"
+            for c in range(c0, min(c0 + 256 // P["gb"][p], nn)):
+                d = fst + c
+                assert d not in done
+                done.add(d)
+                o = P["r_off"][p] + c * f - c * (c - 1) // 2
+                nl = nn - c
+                val = BC[o:o + nl] @ (sg[d:d + nl] * z[d:d + nl]) - BC[o + nl:o + nl + mm] @ xb
+                x[d] = val
+                for k in range(2):
+                    q = P["xsc"][2 * d + k]
+                    if q >= 0:
+                        XBn[q] = val
+        cp = P["xcp"].reshape(-1, 2)
+        for q in range(P["xcp_off"][lv], P["xcp_off"][lv + 1]):
+            assert not np.isnan(XB[cp[q, 1]])
+            XBn[cp[q, 0]] = XB[cp[q, 1]]
+        XB = XBn
+        assert len(done) == P["lvl_dof"][lv + 1] - P["lvl_dof"][lv]
+    return x
+
+
+CASES = [
+    (3, 12, 16, 9, 3, 4, 3, 1, 0),     # 3D, single-subdomain leaves
+    (3, 12, 16, 9, 3, 4, 3, 4, 1),     # leaf boxes of up to 4 subdomains
+    (3, 12, 16, 9, 3, 4, 3, 100, 2),   # one dense front
+    (2, 20, 30, 1, 4, 5, 1, 1, 3),     # 2D
+    (2, 20, 30, 1, 4, 5, 1, 3, 4),
+    (3, 20, 10, 5, 5, 2, 1, 2, 8),     # flat 3D grid
+    (3, 6, 6, 6, 1, 1, 2, 1, 6),       # two subdomains
+]
+
+
+@pytest.mark.parametrize("args", CASES, ids=lambda a: "x".join(map(str, a[4:7])) + f"_leaf{a[7]}")
+def test_plan_factor_and_sweeps_match_dense_solve(dumper, args):
+    P = load(dumper, args)
+    rng = np.random.default_rng(args[-1])
+    # numbering covers every coarse dof once, pinned pressure excluded
+    fk, cof, pidx = P["face_k"], P["face_cofs"], P["pidx"]
+    dofs = np.concatenate([np.arange(cof[f], cof[f] + fk[f] + 1) for f in range(P["nF"])] + [pidx[pidx >= 0]])
+    assert np.array_equal(np.sort(dofs), np.arange(P["nk"]))
+    assert pidx[-1] == -1 and (pidx[:-1] >= 0).all()
+    # levels: children strictly below their parent
+    lvl = np.empty(P["nfr"], int)
+    for h in range(P["H"]):
+        lvl[P["lvl_off"][h]:P["lvl_off"][h + 1]] = h
+    for p in range(P["nfr"]):
+        for c in P["ch"][2 * p:2 * p + 2]:
+            if c >= 0:
+                assert lvl[c] < lvl[p]
+    K, Ac, cmap, sub_coff, dsc, sg = coarse_matrix(P, rng)
+    FR, BC = factor(P, Ac, cmap, sub_coff, dsc, sg)
+    b = rng.standard_normal(P["nk"])
+    x = sweep(P, FR, BC, sg, b)
+    ref = np.linalg.solve(K, b)
+    assert np.linalg.norm(x - ref) / np.linalg.norm(ref) < 1e-10
+
+
+def test_single_subdomain_has_no_coarse_dofs(dumper):
+    P = load(dumper, (3, 6, 6, 6, 1, 1, 1, 1, 0))
+    assert P["nk"] == 0 and P["nfr"] == 0 and P["H"] == 0
+
+
+def test_weighted_cut_avoids_heavy_plane(dumper):
+    """The root separator is a light plane, the heavy plane's faces go to small fronts.
+
+    4 x 4 x 4 subdomains; the z-plane between subdomain layers 1 and 2 (the
+    geometric middle) carries 20 adaptive rows per face, every other face none.
+    """
+    P = load(dumper, (3, 16, 16, 16, 4, 4, 4, 1, 0, 2, 1))
+    fk, cof = P["face_k"], P["face_cofs"]
+    root = P["nfr"] - 1
+    assert P["lvl_off"][P["H"] - 1] == root
+    own = set(range(P["first"][root], P["first"][root] + P["n"][root]))
+    heavy = [f for f in range(P["nF"]) if fk[f] == 20]
+    assert len(heavy) == 16
+    assert not any(cof[f] in own for f in heavy)
+    # root: a light 4 x 4 plane (16 face dofs) and the pressures placed on it
+    assert P["n"][root] <= 16 + 32
+    assert max(P["n"]) < 16 * 21
