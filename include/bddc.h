@@ -57,6 +57,8 @@ extern "C" {
 
 /* bddc_solve flags */
 #define BDDC_DEVICE_PTRS 1u      /* rhs, flux and pressure are device pointers   */
+#define BDDC_EAGER       2u      /* launch the CG iterations kernel by kernel
+                                    instead of replaying the captured graph     */
 
 typedef struct bddc_problem *bddc_handle;
 
@@ -102,7 +104,7 @@ typedef struct {
   double t_solve_ms;        /* wall time of the last bddc_solve                  */
   double t_pcg_ms;          /* device time of the CG loop of the last solve      */
   double bytes_per_iter;    /* algorithmic HBM bytes of one CG iteration         */
-  double bytes_prec;        /* ... of which the preconditioner (steps H3-H7)     */
+  double bytes_prec;        /* ... of which the BDDC preconditioner              */
   double device_bytes;      /* device memory held by the handle                  */
 } bddc_stats_t;
 
@@ -132,7 +134,11 @@ int bddc_setup(const bddc_grid *g, const double *perm, const bddc_partition *par
  *   pressure : [n_cells] output, zero volume-weighted mean
  *   flags    : BDDC_DEVICE_PTRS if the three arrays live in device memory
  *              (then the call is asynchronous on the handle's stream except for
- *              the convergence checks of the CG loop)
+ *              the convergence checks of the CG loop); BDDC_EAGER to launch the
+ *              CG iterations one kernel at a time.  By default the first solve
+ *              captures a chunk of eight CG iterations (both streams) into a
+ *              HIP graph that later chunks and solves replay; both ways run
+ *              the same kernels on the same data and give identical results.
  * Returns BDDC_OK, BDDC_ENOCONV (outputs hold the last iterate),
  * BDDC_EBREAKDOWN, BDDC_EINVAL, BDDC_EDEVICE.
  */
@@ -194,8 +200,9 @@ int bddc_apply(bddc_handle h, int32_t which, const double *x_u, const double *x_
 
 /* Time one kernel of the CG iteration on the handle's stream with HIP events:
  * `reps` back-to-back launches on the vectors of the last solve, bracketed by
- * two events.  which = BDDC_K_SCHUR_APPLY (local S^i products, step H1) or
- * BDDC_K_PRECOND_APPLY (local T^i and Psi^iT products, steps H3-H4).
+ * two events.  which = BDDC_K_SCHUR_APPLY (local Schur products S^i of the
+ * CG operator) or BDDC_K_PRECOND_APPLY (local substructure corrections T^i of
+ * the preconditioner).
  * avg_ms receives the mean duration of one launch, bytes the algorithmic HBM
  * bytes of one launch (operator entries read once, vectors gathered and
  * written once).  Call after a bddc_solve. */

@@ -13,6 +13,7 @@ BDDC_OK, BDDC_EINVAL, BDDC_ENOMEM, BDDC_ENOCONV, BDDC_EBREAKDOWN, BDDC_EFACTOR, 
 BDDC_FP64, BDDC_MIXED = 0, 1
 BDDC_ALL_CONSTRAINED = 1
 BDDC_DEVICE_PTRS = 1
+BDDC_EAGER = 2
 X_SCHUR, X_FACE_EIG, X_FACE_K, X_DSCALE, X_GAMMA, X_OMEGA, X_T, X_PSI, X_COARSE_INV = 1, 2, 3, 4, 5, 6, 7, 8, 9
 OP_SYSTEM, OP_PRECOND = 1, 2
 
@@ -124,18 +125,19 @@ class Solver:
         self._sub_nG = [self.schur(i).shape[0] for i in range(self.N)] if self.N <= 4096 else None
 
     # -- solves ----------------------------------------------------------------
-    def solve(self, source, rtol=1e-8, allow_noconv=False):
+    def solve(self, source, rtol=1e-8, allow_noconv=False, eager=False):
         src = np.ascontiguousarray(source, dtype=np.float64)
         flux = np.empty(self.n_faces_all)
         pres = np.empty(self.n_cells)
-        rc = self.lib.bddc_solve(self.h, src.ctypes.data, float(rtol), flux.ctypes.data, pres.ctypes.data, 0)
+        rc = self.lib.bddc_solve(self.h, src.ctypes.data, float(rtol), flux.ctypes.data, pres.ctypes.data,
+                                 BDDC_EAGER if eager else 0)
         _check(self.lib, rc, allow=(BDDC_ENOCONV,) if allow_noconv else ())
         return flux, pres
 
-    def solve_device(self, src_ptr, rtol, flux_ptr, pres_ptr):
+    def solve_device(self, src_ptr, rtol, flux_ptr, pres_ptr, eager=False):
         """Device-pointer solve (e.g. torch tensor data_ptr()); no host copies."""
         rc = self.lib.bddc_solve(self.h, C.c_void_p(src_ptr), float(rtol), C.c_void_p(flux_ptr),
-                                 C.c_void_p(pres_ptr), BDDC_DEVICE_PTRS)
+                                 C.c_void_p(pres_ptr), BDDC_DEVICE_PTRS | (BDDC_EAGER if eager else 0))
         return _check(self.lib, rc, allow=(BDDC_ENOCONV,))
 
     def set_stream(self, stream_ptr):

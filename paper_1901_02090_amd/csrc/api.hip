@@ -88,6 +88,9 @@ struct bddc_problem {
   CgState *st_host = nullptr;
   int *d_err = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipStream_t side = nullptr;                     // coarse solve of the preconditioner
+  hipGraphExec_t cg_graph = nullptr;              // CG_CHUNK iterations, captured once
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 
   bddc_stats_t stats{};
 
@@ -119,6 +122,10 @@ struct bddc_problem {
     if (st_host) (void)hipHostFree(st_host);
     if (ev0) (void)hipEventDestroy(ev0);
     if (ev1) (void)hipEventDestroy(ev1);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
+    if (cg_graph) (void)hipGraphExecDestroy(cg_graph);
+    if (side) (void)hipStreamDestroy(side);
     if (own_stream) (void)hipStreamDestroy(own_stream);
   }
 };
@@ -131,6 +138,17 @@ void check_err(bddc_problem *h, const char *stage) {
   if (e & 1) throw Error{BDDC_EINVAL, "permeability must be finite and > 0"};
   if (e) throw Error{BDDC_EFACTOR, std::string("factorization lost definiteness in ") + stage +
                                        " (code " + std::to_string(e) + ")"};
+}
+
+// Every device array the coarse kernels dereference must exist before a launch.
+void check_coarse_ptrs(const bddc_problem *h) {
+  const DevFronts &f = h->fd;
+  const DevSweep &w = h->sw;
+  const void *p[] = {f.first, f.n, f.m, f.ch, f.b_off, f.bidx, f.ext, f.touch_off, f.touch, f.F_off, f.w_off,
+                     f.q_off, f.r_off, f.v_off, w.wdst, w.xsc_off, w.xsc, w.ftask, w.btask, h->FR, h->BC, h->csgn,
+                     h->cy, h->cS0, h->cS1, h->cXB, h->bc, h->csol};
+  for (const void *q : p)
+    if (!q) throw Error{BDDC_EDEVICE, "coarse solver arrays not initialised"};
 }
 
 void fill(bddc_problem *h, double *x, int64_t n, double v) {
@@ -211,7 +229,7 @@ void do_setup(bddc_problem *h, const bddc_grid *gr, const double *perm, const bd
     HIPCHK(hipMemcpy(h->d_err, &zero, sizeof(int), hipMemcpyHostToDevice));
   }
 
-  // S1: cell coefficients
+  // cell coefficients (Section 5 rescaling)
   std::vector<double> permv(perm, perm + L.ncells * dim);
   double *d_perm = h->upload(permv);
   h->mcoef = h->alloc<double>(L.ncells * 3);
@@ -219,7 +237,7 @@ void do_setup(bddc_problem *h, const bddc_grid *gr, const double *perm, const bd
   HIPCHK(hipGetLastError());
   h->dscale = h->alloc<double>(N);
 
-  // S2: local dense setup
+  // local dense setup: Schur complements S^i and the pressure operators
   std::vector<int64_t> oP(N), oV(N), oH(N), oS(N), oL(N), oW(N), oX(N), opk(N);
   int64_t ws = 0, xs = 0, pks = 0;
   for (int i = 0; i < N; ++i) {
@@ -254,7 +272,7 @@ void do_setup(bddc_problem *h, const bddc_grid *gr, const double *perm, const bd
   HIPCHK(hipStreamSynchronize(s));
   check_err(h, "the subdomain setup");
 
-  // S4: face eigenproblems
+  // face eigenproblems of Algorithm "Adaptive BDDC"
   const int nF = L.nF;
   h->face_k.assign(nF, 0);
   h->face_omega.assign(nF, 0.0);
@@ -342,7 +360,7 @@ void do_setup(bddc_problem *h, const bddc_grid *gr, const double *perm, const bd
   cs.co_plus = h->upload(co_plus);
   cs.pidx = h->upload(pidx);
 
-  // S5: local coarse spaces
+  // local coarse spaces Psi^i, coarse matrices and substructure operators T^i
   std::vector<int64_t> cwoff(N), acoff(N), psioff(N);
   int64_t cws = 0, acs = 0, pss = 0;
   for (int i = 0; i < N; ++i) {
@@ -368,9 +386,11 @@ void do_setup(bddc_problem *h, const bddc_grid *gr, const double *perm, const bd
   HIPCHK(hipStreamSynchronize(s));
   check_err(h, "the local coarse spaces");
 
-  // S6: coarse saddle point, multifrontal signed Cholesky level by level
+  // coarse saddle point: multifrontal signed Cholesky, level by level
   const int nk = h->nk;
   h->coarse_bytes = 0.0;
+  h->bc = h->alloc<double>(nk + 1);
+  h->csol = h->alloc<double>(nk + 1);
   if (nk > 0) {
     DevFronts &fd = h->fd;
     fd.first = h->upload(P.first);
@@ -400,24 +420,16 @@ void do_setup(bddc_problem *h, const bddc_grid *gr, const double *perm, const bd
     fill(h, h->cS0, P.v_off[nfr], 0.0);   // slots no child writes stay zero
     fill(h, h->cS1, P.v_off[nfr], 0.0);
     DevSweep &sv = h->sw;
-    sv.first = fd.first;
-    sv.n = fd.n;
-    sv.m = fd.m;
-    sv.gf = h->upload(P.gf);
-    sv.gb = h->upload(P.gb);
-    sv.cslot = h->upload(P.cslot);
-    sv.b_off = fd.b_off;
     sv.wdst = h->upload(P.wdst);
-    sv.r_off = fd.r_off;
-    sv.v_off = fd.v_off;
-    sv.xsc = (const int2 *)h->upload(P.xsc);
-    sv.ftask = (const int2 *)h->upload(P.ftask);
-    sv.btask = (const int2 *)h->upload(P.btask);
-    sv.xcp = (const int2 *)h->upload(P.xcp);
+    sv.xsc_off = h->upload(P.xsc_off);
+    sv.xsc = h->upload(P.xsc);
+    sv.ftask = (const int4 *)h->upload(P.ftask);
+    sv.btask = (const int4 *)h->upload(P.btask);
     std::vector<double> sg(nk, 1.0);
     for (int i = 0; i < N; ++i)
       if (pidx[i] >= 0) sg[pidx[i]] = -1.0;
     h->csgn = h->upload(sg);
+    check_coarse_ptrs(h);
     for (int lv = 0; lv < P.H; ++lv) {
       const int f0 = P.lvl_off[lv], nf = P.lvl_off[lv + 1] - f0;
       k_front_factor<<<nf, 256, 0, s>>>(g, cs, fd, f0, cw.Ac, cw.ac_off, h->dscale, h->csgn, Fall, Wall, Qall,
@@ -447,8 +459,6 @@ void do_setup(bddc_problem *h, const bddc_grid *gr, const double *perm, const bd
   h->yloc = h->alloc<double>(totG);
   h->wloc = h->alloc<double>(totG);
   h->gloc = h->alloc<double>(sub_coff[N]);
-  h->bc = h->alloc<double>(nk + 1);
-  h->csol = h->alloc<double>(nk + 1);
   h->part_g = h->alloc<double>(nblk(nGm) + 1);
   h->part_r = h->alloc<double>(nblk(nGm) + 1);
   h->part_z = h->alloc<double>(nF + 1);
@@ -462,6 +472,9 @@ void do_setup(bddc_problem *h, const bddc_grid *gr, const double *perm, const bd
   HIPCHK(hipHostMalloc((void **)&h->st_host, sizeof(CgState), hipHostMallocDefault));
   HIPCHK(hipEventCreate(&h->ev0));
   HIPCHK(hipEventCreate(&h->ev1));
+  HIPCHK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
+  HIPCHK(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
   HIPCHK(hipStreamSynchronize(s));
 
   // statistics of the operators streamed per iteration
@@ -472,18 +485,17 @@ void do_setup(bddc_problem *h, const bddc_grid *gr, const double *perm, const bd
 }
 
 // Coarse solve csol = K^{-1} bc by the multifrontal forward / backward sweeps.
-void launch_coarse_solve(bddc_problem *h, const int *done) {
-  hipStream_t s = h->stream;
+void launch_coarse_solve(bddc_problem *h, hipStream_t s, const int *done) {
   const NdPlan &P = h->nd;
   if (h->nk == 0) return;
+  check_coarse_ptrs(h);
   for (int lv = 0; lv < P.H; ++lv) {
     const int t0 = P.ftask_off[lv], nt = P.ftask_off[lv + 1] - t0;
     k_nd_fwd<<<nt, 256, 0, s>>>(t0, h->sw, h->FR, h->bc, h->cS0, h->cS1, h->cy, done);
   }
   for (int lv = P.H - 1; lv >= 0; --lv) {
     const int t0 = P.btask_off[lv], nt = P.btask_off[lv + 1] - t0;
-    k_nd_bwd<<<nt, 256, 0, s>>>(t0, P.xcp_off[lv], P.xcp_off[lv + 1], h->sw, h->BC, h->cy, h->csgn, h->cXB,
-                                h->csol, done);
+    k_nd_bwd<<<nt, 256, 0, s>>>(t0, h->sw, h->BC, h->cy, h->csgn, h->cXB, h->csol, done);
   }
 }
 
@@ -496,35 +508,46 @@ void launch_precond(bddc_problem *h, const double *r, double *z, double *zpart, 
   CgState *st = check ? h->st : nullptr;
   const double *rp = check ? h->part_r : nullptr;
   const int nrp = (int)nblk(L.nGamma);
-  if (h->precision == BDDC_MIXED) {
-    k_symv<float, true><<<N, 256, shm, s>>>(h->g, h->T32, h->d_pk, r, 0.5, h->yloc, h->Psi32, h->d_psi_off,
-                                            h->cs.sub_coff, h->gloc, st, rp, nrp);
-  } else {
-    k_symv<double, true><<<N, 256, shm, s>>>(h->g, h->T64, h->d_pk, r, 0.5, h->yloc, h->Psi64, h->d_psi_off,
-                                             h->cs.sub_coff, h->gloc, st, rp, nrp);
-  }
+  const bool mixed = h->precision == BDDC_MIXED;
+  // Coarse right-hand side pieces Psi^{iT} r^i first (with the stopping test),
+  // then the substructure corrections T^i r^i on the main stream and, forked
+  // behind them, the coarse solve on the side stream; they join before the
+  // coarse basis correction Psi^i alpha.  The long T^i launch is enqueued
+  // first so that it is dispatched at once and the coarse levels fill the
+  // slots it leaves free.
+  if (mixed)
+    k_psi_apply<float><<<N, 256, shm, s>>>(h->g, h->Psi32, h->d_psi_off, h->cs.sub_coff, r, 0.5, h->gloc, st, rp, nrp);
+  else
+    k_psi_apply<double><<<N, 256, shm, s>>>(h->g, h->Psi64, h->d_psi_off, h->cs.sub_coff, r, 0.5, h->gloc, st, rp,
+                                            nrp);
+  if (h->nk > 0) HIPCHK(hipEventRecord(h->ev_fork, s));
+  if (mixed)
+    k_symv<float><<<N, 256, shm, s>>>(h->g, h->T32, h->d_pk, r, 0.5, h->yloc, st, nullptr, 0);
+  else
+    k_symv<double><<<N, 256, shm, s>>>(h->g, h->T64, h->d_pk, r, 0.5, h->yloc, st, nullptr, 0);
   // The coarse solve stays FP64 in both forms: the CG runs in the balanced
   // subspace, so the face-average coarse fluxes must satisfy B_c alpha = 0 to
   // FP64 accuracy (the FP32 local operators are corrected by the balance step).
   if (h->nk > 0) {
-    k_coarse_rhs<<<nblk(h->nk), 256, 0, s>>>(h->cs, h->gloc, h->bc, st);
-    launch_coarse_solve(h, st ? &st->done : nullptr);
+    HIPCHK(hipStreamWaitEvent(h->side, h->ev_fork, 0));
+    k_coarse_rhs<<<nblk(h->nk), 256, 0, h->side>>>(h->cs, h->gloc, h->bc, st);
+    launch_coarse_solve(h, h->side, st ? &st->done : nullptr);
+    HIPCHK(hipEventRecord(h->ev_join, h->side));
   }
-  if (h->precision == BDDC_MIXED)
+  if (h->nk > 0) HIPCHK(hipStreamWaitEvent(s, h->ev_join, 0));
+  if (mixed)
     k_psi_correct<float><<<N, 256, 0, s>>>(h->g, h->cs, h->Psi32, h->d_psi_off, h->yloc, h->csol, h->wloc, st);
   else
     k_psi_correct<double><<<N, 256, 0, s>>>(h->g, h->cs, h->Psi64, h->d_psi_off, h->yloc, h->csol, h->wloc, st);
   if (nF > 0) k_average_balance<<<nF, 256, 0, s>>>(h->g, h->cs, h->wloc, h->csol, z, r, zpart, st);
 }
-
 void launch_iteration(bddc_problem *h) {
   const Layout &L = h->L;
   hipStream_t s = h->stream;
   const int N = L.N, nGm = L.nGamma;
   const size_t shm = (size_t)5 * ld4(L.maxG) * sizeof(double);
   const int nb = (int)nblk(nGm);
-  k_symv<double, false><<<N, 256, shm, s>>>(h->g, h->Spk, h->d_pk, h->pu, 1.0, h->yloc, nullptr, nullptr,
-                                            nullptr, nullptr, h->st, nullptr, 0);
+  k_symv<double><<<N, 256, shm, s>>>(h->g, h->Spk, h->d_pk, h->pu, 1.0, h->yloc, h->st, nullptr, 0);
   k_sys_assemble<<<nb, 256, 0, s>>>(h->g, h->yloc, h->pp, h->dscale, h->pu, h->qu, h->part_g, h->st);
   k_update_xr<<<nb, 256, 0, s>>>(nGm, N, h->part_g, nb, h->pu, h->qu, h->pp, h->xu, h->ru, h->xp, h->part_r,
                                  h->st, h->alpha_h);
@@ -575,6 +598,38 @@ double lanczos_kappa(const std::vector<double> &a, const std::vector<double> &b,
   return *lmax / *lmin;
 }
 
+constexpr int CG_CHUNK = 8;   // CG iterations between host convergence checks
+
+// Capture CG_CHUNK iterations (main and side stream) into a graph.  The
+// capture runs on the handle's own stream; the graph is replayed on whatever
+// stream the handle uses.  Every kernel reads its scalars from the device CG
+// state, so one graph serves every chunk of every solve.
+void build_cg_graph(bddc_problem *h) {
+  hipStream_t keep = h->stream;
+  h->stream = h->own_stream;
+  hipGraph_t gr = nullptr;
+  hipError_t e = hipStreamBeginCapture(h->own_stream, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    for (int k = 0; k < CG_CHUNK && e == hipSuccess; ++k) {
+      try {
+        launch_iteration(h);
+      } catch (const Error &) {
+        e = hipErrorUnknown;
+      }
+      if (e == hipSuccess) e = hipGetLastError();
+    }
+    const hipError_t e2 = hipStreamEndCapture(h->own_stream, &gr);
+    if (e == hipSuccess) e = e2;
+  }
+  h->stream = keep;
+  if (e == hipSuccess) e = hipGraphInstantiate(&h->cg_graph, gr, nullptr, nullptr, 0);
+  if (gr) (void)hipGraphDestroy(gr);
+  if (e != hipSuccess) {
+    h->cg_graph = nullptr;
+    throw Error{BDDC_EDEVICE, std::string("capturing the CG iteration graph: ") + hipGetErrorString(e)};
+  }
+}
+
 int do_solve(bddc_problem *h, const double *rhs, double rtol, double *flux, double *pressure, uint32_t flags) {
   const Layout &L = h->L;
   hipStream_t s = h->stream;
@@ -606,13 +661,12 @@ int do_solve(bddc_problem *h, const double *rhs, double rtol, double *flux, doub
     // step 1: coarse solve with (0, D F_0), u0 = E Psi alpha
     fill(h, h->bc, h->nk, 0.0);
     k_step1_rhs<<<N, 256, 0, s>>>(h->g, h->cs.pidx, src, h->dscale, h->bc);
-    launch_coarse_solve(h, nullptr);
+    launch_coarse_solve(h, h->stream, nullptr);
     k_psi_correct<double><<<N, 256, 0, s>>>(h->g, h->cs, h->Psi64, h->d_psi_off, nullptr, h->csol, h->wloc,
                                             nullptr);
     k_average_balance<<<nF, 256, 0, s>>>(h->g, h->cs, h->wloc, h->csol, h->u0, nullptr, nullptr, nullptr);
     // steps 2-3 right-hand side: f* = -S u0 + H^T X F
-    k_symv<double, false><<<N, 256, shm, s>>>(h->g, h->Spk, h->d_pk, h->u0, 1.0, h->yloc, nullptr, nullptr,
-                                              nullptr, nullptr, nullptr, nullptr, 0);
+    k_symv<double><<<N, 256, shm, s>>>(h->g, h->Spk, h->d_pk, h->u0, 1.0, h->yloc, nullptr, nullptr, 0);
     k_source_term<<<N, 256, (size_t)2 * L.maxC * sizeof(double), s>>>(h->g, h->mcoef, h->Xmat, h->d_Xoff, src,
                                                                        h->wloc);
     k_fstar<<<nblk(nGm), 256, 0, s>>>(h->g, h->yloc, h->wloc, h->ru);
@@ -623,11 +677,16 @@ int do_solve(bddc_problem *h, const double *rhs, double rtol, double *flux, doub
     k_init_p<<<nb, 256, 0, s>>>(nGm, N, h->cs.pidx, h->part_z, nF, h->part_r, nb, h->zu, h->csol, h->pu, h->pp,
                                 h->st, rtol, h->max_it);
     HIPCHK(hipGetLastError());
+    const bool eager = (flags & BDDC_EAGER) != 0;
+    if (!eager && !h->cg_graph) build_cg_graph(h);
     HIPCHK(hipEventRecord(h->ev0, s));
-    const int chunk = 8;
     for (int rounds = 0;; ++rounds) {
-      if (rounds > h->max_it / chunk + 2) throw Error{BDDC_EDEVICE, "CG loop did not report completion"};
-      for (int k = 0; k < chunk; ++k) launch_iteration(h);
+      if (rounds > h->max_it / CG_CHUNK + 2) throw Error{BDDC_EDEVICE, "CG loop did not report completion"};
+      if (eager) {
+        for (int k = 0; k < CG_CHUNK; ++k) launch_iteration(h);
+      } else {
+        HIPCHK(hipGraphLaunch(h->cg_graph, s));
+      }
       HIPCHK(hipGetLastError());
       HIPCHK(hipMemcpyAsync(h->st_host, h->st, sizeof(CgState), hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
@@ -870,7 +929,7 @@ int64_t bddc_export(bddc_handle h, int32_t what, int32_t index, void *dst, int64
           std::fill(e.begin(), e.end(), 0.0);
           e[fl[c]] = 1.0;
           HIPCHK(hipMemcpy(h->bc, e.data(), nk * sizeof(double), hipMemcpyHostToDevice));
-          launch_coarse_solve(h, nullptr);
+          launch_coarse_solve(h, h->stream, nullptr);
           HIPCHK(hipStreamSynchronize(h->stream));
           HIPCHK(hipMemcpy(x.data(), h->csol, nk * sizeof(double), hipMemcpyDeviceToHost));
           for (int r = 0; r < ncu; ++r) o[r + (size_t)c * ncu] = x[fl[r]];
@@ -926,8 +985,7 @@ int bddc_apply(bddc_handle h, int32_t which, const double *x_u, const double *x_
       if (!x_p) throw Error{BDDC_EINVAL, "x_p required"};
       HIPCHK(hipMemcpyAsync(h->pp, x_p, N * sizeof(double), hipMemcpyHostToDevice, s));
       const size_t shm = (size_t)5 * ld4(L.maxG) * sizeof(double);
-      k_symv<double, false><<<N, 256, shm, s>>>(h->g, h->Spk, h->d_pk, h->ru, 1.0, h->yloc, nullptr, nullptr,
-                                                nullptr, nullptr, nullptr, nullptr, 0);
+      k_symv<double><<<N, 256, shm, s>>>(h->g, h->Spk, h->d_pk, h->ru, 1.0, h->yloc, nullptr, nullptr, 0);
       k_sys_assemble<<<nblk(nGm), 256, 0, s>>>(h->g, h->yloc, h->pp, h->dscale, nullptr, h->qu, nullptr, nullptr);
       k_b0<<<N, 256, 0, s>>>(h->g, h->ru, h->dscale, h->xp);
       HIPCHK(hipMemcpyAsync(y_u, h->qu, nGm * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -956,30 +1014,24 @@ int bddc_time_kernel(bddc_handle h, int32_t which, int32_t reps, double *avg_ms,
     const int N = L.N;
     if (L.nGamma == 0) throw Error{BDDC_EINVAL, "no interface"};
     const size_t shm = (size_t)5 * ld4(L.maxG) * sizeof(double);
-    double pk = 0.0, psi = 0.0;
-    for (int i = 0; i < N; ++i) {
-      pk += (double)L.nG[i] * (L.nG[i] + 1) / 2;
-      psi += (double)L.nG[i] * (h->sub_coff_h[i + 1] - h->sub_coff_h[i]);
-    }
+    double pk = 0.0;
+    for (int i = 0; i < N; ++i) pk += (double)L.nG[i] * (L.nG[i] + 1) / 2;
     const double totG = (double)L.g_off[N];
     const double sT = h->precision == BDDC_MIXED ? 4.0 : 8.0;
     double b = 0.0;
     auto launch = [&]() {
-      if (which == BDDC_K_SCHUR_APPLY) {
-        k_symv<double, false><<<N, 256, shm, s>>>(h->g, h->Spk, h->d_pk, h->pu, 1.0, h->yloc, nullptr, nullptr,
-                                                  nullptr, nullptr, nullptr, nullptr, 0);
-      } else if (h->precision == BDDC_MIXED) {
-        k_symv<float, true><<<N, 256, shm, s>>>(h->g, h->T32, h->d_pk, h->ru, 0.5, h->yloc, h->Psi32,
-                                                h->d_psi_off, h->cs.sub_coff, h->gloc, nullptr, nullptr, 0);
-      } else {
-        k_symv<double, true><<<N, 256, shm, s>>>(h->g, h->T64, h->d_pk, h->ru, 0.5, h->yloc, h->Psi64,
-                                                 h->d_psi_off, h->cs.sub_coff, h->gloc, nullptr, nullptr, 0);
-      }
+      if (which == BDDC_K_SCHUR_APPLY)
+        k_symv<double><<<N, 256, shm, s>>>(h->g, h->Spk, h->d_pk, h->pu, 1.0, h->yloc, nullptr, nullptr, 0);
+      else if (h->precision == BDDC_MIXED)
+        k_symv<float><<<N, 256, shm, s>>>(h->g, h->T32, h->d_pk, h->ru, 0.5, h->yloc, nullptr, nullptr, 0);
+      else
+        k_symv<double><<<N, 256, shm, s>>>(h->g, h->T64, h->d_pk, h->ru, 0.5, h->yloc, nullptr, nullptr, 0);
     };
+    // algorithmic bytes: the lower triangles, the gather map and gathered x, y
     if (which == BDDC_K_SCHUR_APPLY)
-      b = pk * 8.0 + totG * (4.0 + 8.0) + totG * 8.0;   // S^i, Rmap + gathered x, y
+      b = pk * 8.0 + totG * (4.0 + 8.0) + totG * 8.0;
     else if (which == BDDC_K_PRECOND_APPLY)
-      b = pk * sT + psi * sT + totG * (4.0 + 8.0) + totG * 8.0 + (double)h->sub_coff_h[N] * 8.0;
+      b = pk * sT + totG * (4.0 + 8.0) + totG * 8.0;
     else
       throw Error{BDDC_EINVAL, "unknown kernel"};
     launch();

@@ -19,8 +19,8 @@
 //     z_P = L_PP^{-1} t_p and w_p = S0_p[B] + S1_p[B] - L_BP L_PP^{-1} t_p,
 //     pushed into the parent's slot array of this child.
 //   backward, from the root: x_P = L_PP^{-T} s_P z_P - (L_BP L_PP^{-1})^T x_B,
-//     where x_B (the front's B vector) was filled by the parent: scattered
-//     from its own x_P or copied from the parent's B vector.
+//     where x_B (the front's B vector) was filled by the ancestors: every x[d]
+//     is stored into all B vectors that hold d as soon as it is computed.
 // A row (column) of R is handled by a group of g = 4, 16 or 64 lanes chosen
 // from its length, so short rows do not leave lanes idle.
 #include "common.hpp"
@@ -34,11 +34,9 @@ struct DevFronts {
 };
 
 struct DevSweep {
-  const int *first, *n, *m, *gf, *gb, *cslot, *b_off, *wdst;
-  const int64_t *r_off, *v_off;
-  const int2 *xsc;                 // per dof: positions in the children's B vectors (-1: none)
-  const int2 *ftask, *btask;       // {front, first row / column}
-  const int2 *xcp;                 // {dst, src} B-vector copies
+  const int *wdst;                 // forward push target of every B row
+  const int *xsc_off, *xsc;        // backward: B-vector positions holding x[d]
+  const int4 *ftask, *btask;       // three int4 per task (nd.hpp)
 };
 
 // Assemble, partially factor and invert the fronts [f0, f0 + gridDim.x) of one
@@ -148,26 +146,33 @@ __device__ __forceinline__ double group_reduce(double v, int g) {
   return group_sum<4>(v);
 }
 
-// Forward sweep over the tasks [t0, t0 + gridDim.x) of one level.
+// Forward sweep over the tasks [t0, t0 + gridDim.x) of one level.  A task
+// descriptor carries everything the workgroup needs, so its matrix and vector
+// loads go out one memory round trip after the launch.
 __global__ __launch_bounds__(256) void k_nd_fwd(int t0, DevSweep sw, const double *__restrict__ FR,
                                                 const double *__restrict__ b, double *S0, double *S1,
                                                 double *__restrict__ z, const int *done) {
   if (done && *done) return;
-  const int2 tk = sw.ftask[t0 + blockIdx.x];
-  const int p = tk.x, g = sw.gf[p];
-  const int lane = threadIdx.x & (g - 1), r = tk.y + threadIdx.x / g;
-  const int n = sw.n[p], m = sw.m[p];
+  const int4 *td = sw.ftask + 3 * (int64_t)(t0 + blockIdx.x);
+  const int4 d0 = td[0], d1 = td[1], d2 = td[2];
+  const int g = d0.z, n = d0.w, m = d1.x, fst = d1.y, vo = d1.z, bo = d1.w;
+  const int64_t ro = (int64_t)(((uint64_t)(uint32_t)d2.y << 32) | (uint32_t)d2.x);
+  const int lane = threadIdx.x & (g - 1), r = d0.y + threadIdx.x / g;
   if (r >= n + m) return;            // whole lane groups leave together
-  const int64_t vo = sw.v_off[p];
-  const int fst = sw.first[p];
   const double *row;
   int len;
   if (r < n) {
-    row = FR + sw.r_off[p] + (int64_t)r * (r + 1) / 2;
+    row = FR + ro + (int64_t)r * (r + 1) / 2;
     len = r + 1;
   } else {
-    row = FR + sw.r_off[p] + (int64_t)n * (n + 1) / 2 + (int64_t)(r - n) * n;
+    row = FR + ro + (int64_t)n * (n + 1) / 2 + (int64_t)(r - n) * n;
     len = n;
+  }
+  double base = 0.0;
+  int dst = 0;
+  if (r >= n && lane == 0) {
+    base = S0[vo + r] + S1[vo + r];
+    dst = sw.wdst[bo + (r - n)];
   }
   double a[4] = {0.0, 0.0, 0.0, 0.0};
   for (int c0 = lane; c0 < len; c0 += 4 * g) {
@@ -182,34 +187,28 @@ __global__ __launch_bounds__(256) void k_nd_fwd(int t0, DevSweep sw, const doubl
   }
   const double s = group_reduce((a[0] + a[1]) + (a[2] + a[3]), g);
   if (lane == 0) {
-    if (r < n) {
-      z[fst + r] = s;
-    } else {
-      const double w = (S0[vo + r] + S1[vo + r]) - s;
-      const int dst = sw.wdst[sw.b_off[p] + (r - n)];
-      if (sw.cslot[p]) S1[dst] = w; else S0[dst] = w;
-    }
+    if (r < n) z[fst + r] = s;
+    else if (d2.z) S1[dst] = base - s;
+    else S0[dst] = base - s;
   }
 }
 
-// Backward sweep over the tasks [t0, t0 + gridDim.x) of one level, plus the
-// level's B-vector copies [c0, c1).
-__global__ __launch_bounds__(256) void k_nd_bwd(int t0, int c0, int c1, DevSweep sw, const double *__restrict__ BC,
+// Backward sweep over the tasks [t0, t0 + gridDim.x) of one level; each x[d]
+// is also stored into every B vector that holds d (those of the fronts below).
+__global__ __launch_bounds__(256) void k_nd_bwd(int t0, DevSweep sw, const double *__restrict__ BC,
                                                 const double *__restrict__ z, const double *__restrict__ sg,
                                                 double *XB, double *__restrict__ x, const int *done) {
   if (done && *done) return;
-  for (int q = c0 + blockIdx.x * 256 + threadIdx.x; q < c1; q += gridDim.x * 256) {
-    const int2 cp = sw.xcp[q];
-    XB[cp.x] = XB[cp.y];
-  }
-  const int2 tk = sw.btask[t0 + blockIdx.x];
-  const int p = tk.x, g = sw.gb[p];
-  const int lane = threadIdx.x & (g - 1), c = tk.y + threadIdx.x / g;
-  const int n = sw.n[p], m = sw.m[p];
+  const int4 *td = sw.btask + 3 * (int64_t)(t0 + blockIdx.x);
+  const int4 d0 = td[0], d1 = td[1], d2 = td[2];
+  const int g = d0.z, n = d0.w, m = d1.x, fst = d1.y, bo = d1.w;
+  const int64_t ro = (int64_t)(((uint64_t)(uint32_t)d2.y << 32) | (uint32_t)d2.x);
+  const int lane = threadIdx.x & (g - 1), c = d0.y + threadIdx.x / g;
   if (c >= n) return;
-  const int f = n + m, d = sw.first[p] + c;
-  const double *col = BC + sw.r_off[p] + (int64_t)c * f - (int64_t)c * (c - 1) / 2;
-  const double *xb = XB + sw.b_off[p];
+  const int f = n + m, d = fst + c;
+  const int s0 = sw.xsc_off[d], s1 = sw.xsc_off[d + 1];
+  const double *col = BC + ro + (int64_t)c * f - (int64_t)c * (c - 1) / 2;
+  const double *xb = XB + bo;
   const int nl = n - c, len = nl + m;
   double a[4] = {0.0, 0.0, 0.0, 0.0};
   for (int q0 = lane; q0 < len; q0 += 4 * g) {
@@ -223,12 +222,8 @@ __global__ __launch_bounds__(256) void k_nd_bwd(int t0, int c0, int c1, DevSweep
     }
   }
   const double s = group_reduce((a[0] + a[1]) + (a[2] + a[3]), g);
-  if (lane == 0) {
-    x[d] = s;
-    const int2 sc = sw.xsc[d];
-    if (sc.x >= 0) XB[sc.x] = s;
-    if (sc.y >= 0) XB[sc.y] = s;
-  }
+  if (lane == 0) x[d] = s;
+  for (int k = s0 + lane; k < s1; k += g) XB[sw.xsc[k]] = s;
 }
 
 }  // namespace bddc

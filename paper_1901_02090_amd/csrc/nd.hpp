@@ -57,10 +57,8 @@ struct NdPlan {
   std::vector<int> gf, gb;          // [nfr] group widths, forward rows / backward columns
   std::vector<int> cslot;           // [nfr]
   std::vector<int> wdst;            // [sum m] forward: position of w_c[k] in the parent's vectors
-  std::vector<int> xsc;             // [2 nk] backward: positions in the children's B vectors or -1
-  std::vector<int> xcp;             // [2 ncopy] backward copies {dst, src} in B-vector positions
-  std::vector<int> xcp_off;         // [H+1] copies of level h
-  std::vector<int> ftask, btask;    // [2 ntask] {front, first row / column}
+  std::vector<int> xsc_off, xsc;    // [nk+1], [sum m]: every B-vector position holding x[d]
+  std::vector<int> ftask, btask;    // [12 ntask] task descriptors (see coarse.hip)
   std::vector<int> ftask_off, btask_off;  // [H+1]
 };
 
@@ -324,42 +322,40 @@ inline void nd_plan(const Layout &L, const std::vector<int> &face_k, int leaf, N
       if (P.ch[2 * r + k] >= 0) P.cslot[P.ch[2 * r + k]] = k;
   }
   P.wdst.assign(P.b_off[nn], -1);
-  P.xsc.assign(2 * (size_t)cur, -1);
-  P.xcp_off.assign(H + 1, 0);
-  std::vector<int> lvl_of(nn);
-  for (int h = 0; h < H; ++h)
-    for (int r = P.lvl_off[h]; r < P.lvl_off[h + 1]; ++r) lvl_of[r] = h;
-  std::vector<std::vector<int>> cps(H);
   for (int c = 0; c < nn; ++c) {
     const int p = parent[c];
     if (p < 0) continue;
-    const int k = P.cslot[c];
-    for (int t = 0; t < P.m[c]; ++t) {
-      const int e = P.ext[P.b_off[c] + t];
-      P.wdst[P.b_off[c] + t] = (int)(P.v_off[p] + e);
-      if (e < P.n[p]) {
-        P.xsc[2 * (size_t)(P.first[p] + e) + k] = P.b_off[c] + t;
-      } else {
-        cps[lvl_of[p]].push_back(P.b_off[c] + t);
-        cps[lvl_of[p]].push_back(P.b_off[p] + e - P.n[p]);
-      }
-    }
+    for (int t = 0; t < P.m[c]; ++t) P.wdst[P.b_off[c] + t] = (int)(P.v_off[p] + P.ext[P.b_off[c] + t]);
   }
-  for (int h = 0; h < H; ++h) {
-    P.xcp_off[h + 1] = P.xcp_off[h] + (int)cps[h].size() / 2;
-    P.xcp.insert(P.xcp.end(), cps[h].begin(), cps[h].end());
+  // x[d] goes to every B vector that holds d (the fronts below d's front)
+  P.xsc_off.assign(cur + 1, 0);
+  for (int v : P.bidx) ++P.xsc_off[v + 1];
+  for (int d = 0; d < cur; ++d) P.xsc_off[d + 1] += P.xsc_off[d];
+  P.xsc.assign(P.bidx.size(), -1);
+  {
+    std::vector<int> fillp(P.xsc_off.begin(), P.xsc_off.end() - 1);
+    for (int q = 0; q < (int)P.bidx.size(); ++q) P.xsc[fillp[P.bidx[q]]++] = q;
   }
-  // tasks: one workgroup (256 lanes) per 256/g rows (forward) or columns (backward)
+  // task descriptors, three int4 each:
+  //   {front, first row / column, lane-group width, n}, {m, first dof, v_off, b_off},
+  //   {r_off low 32 bits, r_off high 32 bits, child slot, 0}
+  // one workgroup (256 lanes) takes 256/g rows (forward) or columns (backward)
   P.ftask_off.assign(H + 1, 0);
   P.btask_off.assign(H + 1, 0);
+  auto push = [&](std::vector<int> &T, int r, int j, int g) {
+    const int64_t ro = P.r_off[r];
+    const int d[12] = {r, j, g, P.n[r], P.m[r], P.first[r], (int)P.v_off[r], P.b_off[r],
+                       (int)(uint32_t)(ro & 0xffffffff), (int)(uint32_t)(ro >> 32), P.cslot[r], 0};
+    T.insert(T.end(), d, d + 12);
+  };
   for (int h = 0; h < H; ++h) {
     for (int r = P.lvl_off[h]; r < P.lvl_off[h + 1]; ++r) {
       const int fr = 256 / P.gf[r], br = 256 / P.gb[r];
-      for (int j = 0; j < P.n[r] + P.m[r]; j += fr) { P.ftask.push_back(r); P.ftask.push_back(j); }
-      for (int j = 0; j < P.n[r]; j += br) { P.btask.push_back(r); P.btask.push_back(j); }
+      for (int j = 0; j < P.n[r] + P.m[r]; j += fr) push(P.ftask, r, j, P.gf[r]);
+      for (int j = 0; j < P.n[r]; j += br) push(P.btask, r, j, P.gb[r]);
     }
-    P.ftask_off[h + 1] = (int)P.ftask.size() / 2;
-    P.btask_off[h + 1] = (int)P.btask.size() / 2;
+    P.ftask_off[h + 1] = (int)P.ftask.size() / 12;
+    P.btask_off[h + 1] = (int)P.btask.size() / 12;
   }
   if (nv > INT32_MAX) throw std::length_error("coarse plan: front vectors too long");
 }

@@ -73,13 +73,12 @@ __device__ __forceinline__ void block_write_partial(double v, double *part, doub
 }
 
 // ---------------------------------------------------------------------------
-// local symmetric operator: y^i = M^i (xscale R^i x), M packed lower column
-// major.  Optionally also g^i = Psi^{iT} (xscale R^i x).
-// Column j of the packed matrix holds rows j..n-1 contiguously; each wave
-// streams whole columns (coalesced), accumulating the strictly-lower product
-// lane-locally in its own LDS row buffer and the transposed product by a wave
-// reduction.  If `check` is set the block first evaluates the stopping test
-// from the residual partials of the previous kernel.
+// Local symmetric operators y^i = M^i (xscale R^i x) with M^i in the
+// group-aligned packed lower storage of common.hpp.  Each wave streams column
+// groups (coalesced 16-byte loads), accumulating the strictly-lower product in
+// its own LDS row buffer and the transposed product by a wave reduction.  With
+// residual partials given, the first kernel of the preconditioner evaluates the
+// stopping test before any work.
 // ---------------------------------------------------------------------------
 // 16-byte vector load of 16/sizeof(TS) consecutive entries, widened to FP64.
 __device__ __forceinline__ void load16(const float *p, double *o) {
@@ -91,32 +90,38 @@ __device__ __forceinline__ void load16(const double *p, double *o) {
   o[0] = v.x; o[1] = v.y;
 }
 
-template <typename TS, bool WITH_PSI>
+// Convergence test at the head of the first kernel of the preconditioner:
+// ||r||^2 from the partials of the residual update decides whether the CG
+// stops here.  Returns true when the calling kernel must leave.
+__device__ __forceinline__ bool cg_exit(CgState *st, const double *__restrict__ rpart, int nrpart, double *red) {
+  if (!st) return false;
+  if (st->done) return true;
+  if (!rpart) return false;
+  const double rn2 = block_sum_partials(rpart, nrpart, red);
+  const bool conv = rn2 <= st->rtol2 * st->r0sq;
+  const bool cap = st->nupd >= st->maxit;
+  if (conv || cap || !isfinite(rn2)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      st->done = 1;
+      st->converged = conv ? 1 : 0;
+      st->relres = st->r0sq > 0.0 ? sqrt(rn2 / st->r0sq) : 0.0;
+      if (!isfinite(rn2)) st->fail = 1;
+    }
+    return true;
+  }
+  return false;
+}
+
+// y^i = M^i (xscale * R_i x) for every subdomain (one workgroup each), M^i in
+// group-aligned packed storage (S^i, or T^i of the preconditioner).
+template <typename TS>
 __global__ __launch_bounds__(256) void k_symv(DevGeom g, const TS *__restrict__ M, const int64_t *__restrict__ pk,
                                               const double *__restrict__ x, double xscale,
-                                              double *__restrict__ yloc, const TS *__restrict__ Psi,
-                                              const int64_t *__restrict__ psi_off,
-                                              const int *__restrict__ sub_coff, double *__restrict__ gloc,
-                                              CgState *st, const double *__restrict__ rpart, int nrpart) {
+                                              double *__restrict__ yloc, CgState *st,
+                                              const double *__restrict__ rpart, int nrpart) {
   extern __shared__ double sh[];
   __shared__ double red[8];
-  if (st) {
-    if (st->done) return;
-    if (rpart) {
-      const double rn2 = block_sum_partials(rpart, nrpart, red);
-      const bool conv = rn2 <= st->rtol2 * st->r0sq;
-      const bool cap = st->nupd >= st->maxit;
-      if (conv || cap || !isfinite(rn2)) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-          st->done = 1;
-          st->converged = conv ? 1 : 0;
-          st->relres = st->r0sq > 0.0 ? sqrt(rn2 / st->r0sq) : 0.0;
-          if (!isfinite(rn2)) st->fail = 1;
-        }
-        return;
-      }
-    }
-  }
+  if (cg_exit(st, rpart, nrpart, red)) return;
   constexpr int VW = 16 / sizeof(TS);
   const int i = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int n = g.nG[i];
@@ -163,29 +168,48 @@ __global__ __launch_bounds__(256) void k_symv(DevGeom g, const TS *__restrict__ 
   }
   __syncthreads();
   for (int r = tid; r < n; r += 256) yloc[go + r] = yw[r] + yw[np + r] + yw[2 * np + r] + yw[3 * np + r];
-  if (WITH_PSI) {
-    const int c0 = sub_coff[i], nci = sub_coff[i + 1] - c0;
-    const TS *P = Psi + psi_off[i];
-    for (int cb = 4 * wv; cb < nci; cb += 16) {
-      double d[4] = {0.0, 0.0, 0.0, 0.0};
-      for (int t = lane * VW; t < np; t += 64 * VW) {
+}
+
+// g^i = Psi^{iT} (xscale * R_i x): the coarse right-hand side pieces of the
+// preconditioner (one workgroup per subdomain; four columns per wave, 16-byte
+// loads over the ld4-padded columns).
+template <typename TS>
+__global__ __launch_bounds__(256) void k_psi_apply(DevGeom g, const TS *__restrict__ Psi,
+                                                   const int64_t *__restrict__ psi_off,
+                                                   const int *__restrict__ sub_coff, const double *__restrict__ x,
+                                                   double xscale, double *__restrict__ gloc, CgState *st,
+                                                   const double *__restrict__ rpart, int nrpart) {
+  extern __shared__ double sh[];
+  __shared__ double red[8];
+  if (cg_exit(st, rpart, nrpart, red)) return;
+  constexpr int VW = 16 / sizeof(TS);
+  const int i = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int n = g.nG[i], np = ld4(n);
+  const int64_t go = g.g_off[i];
+  double *xs = sh;
+  for (int r = tid; r < np; r += 256) xs[r] = (r < n) ? xscale * x[g.Rmap[go + r]] : 0.0;
+  __syncthreads();
+  const int c0 = sub_coff[i], nci = sub_coff[i + 1] - c0;
+  const TS *P = Psi + psi_off[i];
+  for (int cb = 4 * wv; cb < nci; cb += 16) {
+    double d[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int t = lane * VW; t < np; t += 64 * VW) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          double a[VW];
-          if (cb + q < nci) load16(P + (int64_t)(cb + q) * np + t, a);
-          else {
+      for (int q = 0; q < 4; ++q) {
+        double a[VW];
+        if (cb + q < nci) load16(P + (int64_t)(cb + q) * np + t, a);
+        else {
 #pragma unroll
-            for (int v = 0; v < VW; ++v) a[v] = 0.0;
-          }
-#pragma unroll
-          for (int v = 0; v < VW; ++v) d[q] = fma(a[v], xs[t + v], d[q]);
+          for (int v = 0; v < VW; ++v) a[v] = 0.0;
         }
+#pragma unroll
+        for (int v = 0; v < VW; ++v) d[q] = fma(a[v], xs[t + v], d[q]);
       }
-      const double tot = transpose_reduce4(d, lane);
-      if ((lane & 15) == 0) {
-        const int c = cb + (lane >> 4);
-        if (c < nci) gloc[c0 + c] = tot;
-      }
+    }
+    const double tot = transpose_reduce4(d, lane);
+    if ((lane & 15) == 0) {
+      const int c = cb + (lane >> 4);
+      if (c < nci) gloc[c0 + c] = tot;
     }
   }
 }
@@ -632,15 +656,14 @@ __global__ __launch_bounds__(256) void k_sub_mean(int64_t n, double *x, const do
 }
 
 // explicit instantiations used by the host code
-template __global__ void k_symv<double, false>(DevGeom, const double *, const int64_t *, const double *, double,
-                                               double *, const double *, const int64_t *, const int *, double *,
-                                               CgState *, const double *, int);
-template __global__ void k_symv<double, true>(DevGeom, const double *, const int64_t *, const double *, double,
-                                              double *, const double *, const int64_t *, const int *, double *,
-                                              CgState *, const double *, int);
-template __global__ void k_symv<float, true>(DevGeom, const float *, const int64_t *, const double *, double,
-                                             double *, const float *, const int64_t *, const int *, double *,
-                                             CgState *, const double *, int);
+template __global__ void k_symv<double>(DevGeom, const double *, const int64_t *, const double *, double, double *,
+                                        CgState *, const double *, int);
+template __global__ void k_symv<float>(DevGeom, const float *, const int64_t *, const double *, double, double *,
+                                       CgState *, const double *, int);
+template __global__ void k_psi_apply<double>(DevGeom, const double *, const int64_t *, const int *, const double *,
+                                             double, double *, CgState *, const double *, int);
+template __global__ void k_psi_apply<float>(DevGeom, const float *, const int64_t *, const int *, const double *,
+                                            double, double *, CgState *, const double *, int);
 template __global__ void k_psi_correct<double>(DevGeom, DevCoarse, const double *, const int64_t *, const double *,
                                                const double *, double *, const CgState *);
 template __global__ void k_psi_correct<float>(DevGeom, DevCoarse, const float *, const int64_t *, const double *,

@@ -73,9 +73,8 @@ int main(int argc, char **argv) {
   dump("gb", P.gb);
   dump("cslot", P.cslot);
   dump("wdst", P.wdst);
+  dump("xsc_off", P.xsc_off);
   dump("xsc", P.xsc);
-  dump("xcp", P.xcp);
-  dump("xcp_off", P.xcp_off);
   dump("ftask", P.ftask);
   dump("btask", P.btask);
   dump("ftask_off", P.ftask_off);

@@ -163,62 +163,68 @@ def factor(P, Ac, cmap, sub_coff, dsc, sg):
 
 
 def sweep(P, FR, BC, sg, b):
-    """k_nd_fwd / k_nd_bwd, level by level."""
+    """k_nd_fwd / k_nd_bwd, level by level, driven by the task descriptors."""
     nfr, nk, H = P["nfr"], P["nk"], P["H"]
-    first, n, m, b_off = P["first"], P["n"], P["m"], P["b_off"]
     nv = P["v_off"][nfr]
     S = [np.zeros(nv), np.zeros(nv)]
     written = np.zeros((2, nv), bool)
     z = np.full(nk, np.nan)
     x = np.full(nk, np.nan)
     XB = np.full(max(1, P["b_off"][nfr]), np.nan)
-    ft, bt = P["ftask"].reshape(-1, 2), P["btask"].reshape(-1, 2)
+    ft, bt = P["ftask"].reshape(-1, 12), P["btask"].reshape(-1, 12)
+    lvl = np.empty(nfr, int)
+    for h in range(H):
+        lvl[P["lvl_off"][h]:P["lvl_off"][h + 1]] = h
+
+    def unpack(d):
+        p, j, g, n, m, fst, vo, bo, rlo, rhi, slot, _ = (int(v) for v in d)
+        ro = (rhi & 0xffffffff) << 32 | (rlo & 0xffffffff)
+        assert (p, n, m, fst, vo, bo, ro) == (p, P["n"][p], P["m"][p], P["first"][p], P["v_off"][p],
+                                              P["b_off"][p], P["r_off"][p])
+        assert g in (4, 16, 64)
+        return p, j, g, n, m, fst, vo, bo, ro, slot
+
     for lv in range(H):
         done = set()
         for task in range(P["ftask_off"][lv], P["ftask_off"][lv + 1]):
-            p, r0 = ft[task]
+            p, r0, g, nn, mm, fst, vo, bo, ro, slot = unpack(ft[task])
             assert P["lvl_off"][lv] <= p < P["lvl_off"][lv + 1]
-            nn, mm, vo = n[p], m[p], P["v_off"][p]
-            t = b[first[p]:first[p] + nn] + S[0][vo:vo + nn] + S[1][vo:vo + nn]
-            for r in range(r0, min(r0 + 256 // P["gf"][p], nn + mm)):
+            assert slot == P["cslot"][p]
+            t = b[fst:fst + nn] + S[0][vo:vo + nn] + S[1][vo:vo + nn]
+            for r in range(r0, min(r0 + 256 // g, nn + mm)):
                 assert (p, r) not in done
                 done.add((p, r))
                 if r < nn:
-                    o = P["r_off"][p] + r * (r + 1) // 2
-                    z[first[p] + r] = FR[o:o + r + 1] @ t[:r + 1]
+                    o = ro + r * (r + 1) // 2
+                    z[fst + r] = FR[o:o + r + 1] @ t[:r + 1]
                 else:
-                    o = P["r_off"][p] + nn * (nn + 1) // 2 + (r - nn) * nn
-                    dst, sl = P["wdst"][b_off[p] + r - nn], P["cslot"][p]
-                    assert not written[sl, dst]
-                    written[sl, dst] = True
-                    S[sl][dst] = S[0][vo + r] + S[1][vo + r] - FR[o:o + nn] @ t
-        assert len(done) == sum(n[p] + m[p] for p in range(P["lvl_off"][lv], P["lvl_off"][lv + 1]))
+                    o = ro + nn * (nn + 1) // 2 + (r - nn) * nn
+                    dst = P["wdst"][bo + r - nn]
+                    assert not written[slot, dst]
+                    written[slot, dst] = True
+                    S[slot][dst] = S[0][vo + r] + S[1][vo + r] - FR[o:o + nn] @ t
+        assert len(done) == sum(P["n"][p] + P["m"][p] for p in range(P["lvl_off"][lv], P["lvl_off"][lv + 1]))
     for lv in range(H - 1, -1, -1):
         done = set()
-        XBn = XB.copy()
         for task in range(P["btask_off"][lv], P["btask_off"][lv + 1]):
-            p, c0 = bt[task]
-            fst, nn, mm = first[p], n[p], m[p]
+            p, c0, g, nn, mm, fst, vo, bo, ro, slot = unpack(bt[task])
             f = nn + mm
-            xb = XB[b_off[p]:b_off[p] + mm]
+            xb = XB[bo:bo + mm].copy()
             assert not np.isnan(xb).any(), "B vector read before it was filled"
-            for c in range(c0, min(c0 + 256 // P["gb"][p], nn)):
+            for c in range(c0, min(c0 + 256 // g, nn)):
                 d = fst + c
                 assert d not in done
                 done.add(d)
-                o = P["r_off"][p] + c * f - c * (c - 1) // 2
+                o = ro + c * f - c * (c - 1) // 2
                 nl = nn - c
                 val = BC[o:o + nl] @ (sg[d:d + nl] * z[d:d + nl]) - BC[o + nl:o + nl + mm] @ xb
                 x[d] = val
-                for k in range(2):
-                    q = P["xsc"][2 * d + k]
-                    if q >= 0:
-                        XBn[q] = val
-        cp = P["xcp"].reshape(-1, 2)
-        for q in range(P["xcp_off"][lv], P["xcp_off"][lv + 1]):
-            assert not np.isnan(XB[cp[q, 1]])
-            XBn[cp[q, 0]] = XB[cp[q, 1]]
-        XB = XBn
+                for k in range(P["xsc_off"][d], P["xsc_off"][d + 1]):
+                    q = P["xsc"][k]
+                    assert P["bidx"][q] == d
+                    owner = int(np.searchsorted(P["b_off"], q, side="right")) - 1
+                    assert lvl[owner] < lv, "scatter into a front of the same or a higher level"
+                    XB[q] = val
         assert len(done) == P["lvl_dof"][lv + 1] - P["lvl_dof"][lv]
     return x
 
