@@ -54,6 +54,9 @@ extern "C" {
 
 /* bddc_options.flags */
 #define BDDC_ALL_CONSTRAINED 1u  /* diagnostic: every interface dof is a coarse dof */
+#define BDDC_COARSE_DATAFLOW 2u  /* coarse sweeps as one dataflow launch instead of
+                                    one launch per level (same results; slower on
+                                    the 60x220x85 reservoir)                     */
 
 /* bddc_solve flags */
 #define BDDC_DEVICE_PTRS 1u      /* rhs, flux and pressure are device pointers   */

@@ -12,6 +12,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libbddc.so"
 BDDC_OK, BDDC_EINVAL, BDDC_ENOMEM, BDDC_ENOCONV, BDDC_EBREAKDOWN, BDDC_EFACTOR, BDDC_EDEVICE = 0, -1, -2, -3, -4, -5, -6
 BDDC_FP64, BDDC_MIXED = 0, 1
 BDDC_ALL_CONSTRAINED = 1
+BDDC_COARSE_DATAFLOW = 2
 BDDC_DEVICE_PTRS = 1
 BDDC_EAGER = 2
 X_SCHUR, X_FACE_EIG, X_FACE_K, X_DSCALE, X_GAMMA, X_OMEGA, X_T, X_PSI, X_COARSE_INV = 1, 2, 3, 4, 5, 6, 7, 8, 9
@@ -102,7 +103,7 @@ class Solver:
     """One problem resident on the GPU: setup once, solve many right-hand sides."""
 
     def __init__(self, n, h, perm, cuts, tau=math.inf, precision="fp64", max_it=10000, all_constrained=False,
-                 coarse_leaf=0):
+                 coarse_leaf=0, coarse_dataflow=False):
         self.lib = lib = load_library()
         dim = len(n)
         self.n = tuple(int(v) for v in n)
@@ -113,7 +114,8 @@ class Solver:
                                         [C.POINTER(C.c_int32)()] * (3 - dim))
         part = Partition((C.c_int32 * 3)(*([len(c) - 1 for c in self._cuts] + [1] * (3 - dim))), cp)
         opt = Options(BDDC_MIXED if precision == "mixed" else BDDC_FP64, int(max_it),
-                      BDDC_ALL_CONSTRAINED if all_constrained else 0, int(coarse_leaf))
+                      (BDDC_ALL_CONSTRAINED if all_constrained else 0) | (BDDC_COARSE_DATAFLOW if coarse_dataflow else 0),
+                      int(coarse_leaf))
         perm = np.ascontiguousarray(perm, dtype=np.float64).reshape(-1)
         t = float(tau) if (tau is not None and math.isfinite(tau)) else 0.0
         self.h = C.c_void_p()

@@ -75,6 +75,9 @@ struct bddc_problem {
   std::vector<int> pidx_h;
   double *FR = nullptr, *BC = nullptr, *csgn = nullptr, *cy = nullptr, *cS0 = nullptr, *cS1 = nullptr,
          *cXB = nullptr;
+  int *ccnt = nullptr, *cabort = nullptr;         // dataflow counters and abort word
+  int flow_grid = 0, flow_cap = 0;                // resident grid, LDS staging capacity (doubles)
+  bool coarse_dataflow = false;                   // one dataflow launch instead of one per level
   double coarse_bytes = 0.0;
   int64_t *d_pk = nullptr, *d_psi_off = nullptr, *d_Xoff = nullptr, *d_gamma_face = nullptr;
 
@@ -145,8 +148,8 @@ void check_coarse_ptrs(const bddc_problem *h) {
   const DevFronts &f = h->fd;
   const DevSweep &w = h->sw;
   const void *p[] = {f.first, f.n, f.m, f.ch, f.b_off, f.bidx, f.ext, f.touch_off, f.touch, f.F_off, f.w_off,
-                     f.q_off, f.r_off, f.v_off, w.wdst, w.xsc_off, w.xsc, w.ftask, w.btask, h->FR, h->BC, h->csgn,
-                     h->cy, h->cS0, h->cS1, h->cXB, h->bc, h->csol};
+                     f.q_off, f.r_off, f.v_off, w.wdst, w.xsc_off, w.xsc, w.task, h->FR, h->BC, h->csgn,
+                     h->cy, h->cS0, h->cS1, h->cXB, h->bc, h->csol, h->ccnt, h->cabort};
   for (const void *q : p)
     if (!q) throw Error{BDDC_EDEVICE, "coarse solver arrays not initialised"};
 }
@@ -423,8 +426,27 @@ void do_setup(bddc_problem *h, const bddc_grid *gr, const double *perm, const bd
     sv.wdst = h->upload(P.wdst);
     sv.xsc_off = h->upload(P.xsc_off);
     sv.xsc = h->upload(P.xsc);
-    sv.ftask = (const int4 *)h->upload(P.ftask);
-    sv.btask = (const int4 *)h->upload(P.btask);
+    sv.task = (const int4 *)h->upload(P.task);
+    sv.nfr = P.nfr;
+    h->ccnt = h->alloc<int>(2 * P.nfr + 1);
+    h->cabort = h->alloc<int>(1);
+    HIPCHK(hipMemsetAsync(h->ccnt, 0, (2 * (size_t)P.nfr + 1) * sizeof(int), s));
+    HIPCHK(hipMemsetAsync(h->cabort, 0, sizeof(int), s));
+    {
+      // resident grid of the dataflow sweep: at most two workgroups per CU, so
+      // it fits beside the substructure corrections running concurrently
+      int dev = 0, ncu = 0, per_cu = 0;
+      HIPCHK(hipGetDevice(&dev));
+      HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+      // LDS staging: the largest front input (n forward, n + m backward), capped at 48 KB
+      int need = 0;
+      for (int r = 0; r < P.nfr; ++r) need = std::max(need, P.n[r] + P.m[r]);
+      h->flow_cap = std::min(need, 6144);
+      HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_nd_flow, 256,
+                                                          (size_t)h->flow_cap * sizeof(double)));
+      if (ncu < 1 || per_cu < 1) throw Error{BDDC_EDEVICE, "no occupancy for the coarse sweep"};
+      h->flow_grid = std::max(1, std::min(P.ntask, ncu * std::min(per_cu, 2)));
+    }
     std::vector<double> sg(nk, 1.0);
     for (int i = 0; i < N; ++i)
       if (pidx[i] >= 0) sg[pidx[i]] = -1.0;
@@ -484,22 +506,44 @@ void do_setup(bddc_problem *h, const bddc_grid *gr, const double *perm, const bd
   h->stats.bytes_per_iter = h->stats.bytes_prec + sumpk * 8.0 + 2.0 * totG * 8.0 + 8.0 * nGm * 8.0;
 }
 
-// Coarse solve csol = K^{-1} bc by the multifrontal forward / backward sweeps.
+// Coarse solve csol = K^{-1} bc by the multifrontal forward / backward sweeps:
+// one launch per level and direction, or (BDDC_COARSE_DATAFLOW) one dataflow
+// launch.  Both run the same task bodies and give identical results.  On the
+// reservoir the level launches are faster: a dataflow level still costs about
+// four dependent memory round trips (wait, staging, matrix, store completion)
+// and its wide levels take several rounds of the resident grid.
 void launch_coarse_solve(bddc_problem *h, hipStream_t s, const int *done) {
   const NdPlan &P = h->nd;
   if (h->nk == 0) return;
   check_coarse_ptrs(h);
+  if (h->coarse_dataflow) {
+    k_nd_flow<<<h->flow_grid, 256, (size_t)h->flow_cap * sizeof(double), s>>>(
+        P.ntask, h->sw, h->FR, h->BC, h->bc, h->cS0, h->cS1, h->cy, h->csgn, h->cXB, h->csol, h->ccnt, h->cabort,
+        h->flow_cap, done);
+    return;
+  }
   for (int lv = 0; lv < P.H; ++lv) {
     const int t0 = P.ftask_off[lv], nt = P.ftask_off[lv + 1] - t0;
     k_nd_fwd<<<nt, 256, 0, s>>>(t0, h->sw, h->FR, h->bc, h->cS0, h->cS1, h->cy, done);
   }
   for (int lv = P.H - 1; lv >= 0; --lv) {
-    const int t0 = P.btask_off[lv], nt = P.btask_off[lv + 1] - t0;
+    const int t0 = P.btask_lo[lv], nt = P.btask_hi[lv] - t0;
     k_nd_bwd<<<nt, 256, 0, s>>>(t0, h->sw, h->BC, h->cy, h->csgn, h->cXB, h->csol, done);
   }
 }
 
-// Preconditioner on r (FP64 or mixed operators) -> zu (and csol for the pressures).
+// A dataflow sweep that timed out leaves the abort word set (and its results
+// invalid); report it and clear the word.
+void check_flow(bddc_problem *h) {
+  if (!h->cabort) return;
+  int ab = 0;
+  HIPCHK(hipMemcpy(&ab, h->cabort, sizeof(int), hipMemcpyDeviceToHost));
+  if (ab) {
+    HIPCHK(hipMemset(h->cabort, 0, sizeof(int)));
+    throw Error{BDDC_EDEVICE, "coarse dataflow sweep timed out"};
+  }
+}
+
 void launch_precond(bddc_problem *h, const double *r, double *z, double *zpart, bool check) {
   const Layout &L = h->L;
   hipStream_t s = h->stream;
@@ -724,6 +768,7 @@ int do_solve(bddc_problem *h, const double *rhs, double rtol, double *flux, doub
     HIPCHK(hipMemcpyAsync(pressure, pr, L.ncells * sizeof(double), hipMemcpyDeviceToHost, s));
   }
   HIPCHK(hipStreamSynchronize(s));
+  check_flow(h);
   h->stats.it = iters;
   h->stats.converged = converged;
   h->stats.relres = relres;
@@ -771,6 +816,7 @@ int bddc_setup(const bddc_grid *g, const double *perm, const bddc_partition *par
         if (opt->max_it > 0) h->max_it = opt->max_it;
         h->flags = opt->flags;
         h->coarse_leaf = opt->coarse_leaf;
+        h->coarse_dataflow = (opt->flags & BDDC_COARSE_DATAFLOW) != 0;
       }
       if (h->precision != BDDC_FP64 && h->precision != BDDC_MIXED) throw Error{BDDC_EINVAL, "bad precision"};
       h->tau = tau;
@@ -934,6 +980,7 @@ int64_t bddc_export(bddc_handle h, int32_t what, int32_t index, void *dst, int64
           HIPCHK(hipMemcpy(x.data(), h->csol, nk * sizeof(double), hipMemcpyDeviceToHost));
           for (int r = 0; r < ncu; ++r) o[r + (size_t)c * ncu] = x[fl[r]];
         }
+        check_flow(h);
         break;
       }
       case BDDC_X_FACE_EIG: {
@@ -1002,6 +1049,7 @@ int bddc_apply(bddc_handle h, int32_t which, const double *x_u, const double *x_
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s));
+    check_flow(h);
     return BDDC_OK;
   });
 }

@@ -58,8 +58,12 @@ struct NdPlan {
   std::vector<int> cslot;           // [nfr]
   std::vector<int> wdst;            // [sum m] forward: position of w_c[k] in the parent's vectors
   std::vector<int> xsc_off, xsc;    // [nk+1], [sum m]: every B-vector position holding x[d]
-  std::vector<int> ftask, btask;    // [12 ntask] task descriptors (see coarse.hip)
-  std::vector<int> ftask_off, btask_off;  // [H+1]
+  // task descriptors (four int4 each, see coarse.hip): all forward tasks by
+  // ascending level, then all backward tasks by descending level
+  std::vector<int> task;            // [16 ntask]
+  int ntask = 0;
+  std::vector<int> ftask_off;       // [H+1] forward tasks of level h
+  std::vector<int> btask_lo, btask_hi;  // [H] backward tasks of level h
 };
 
 // `leaf`: largest number of subdomains in a leaf box (>= 1).
@@ -336,27 +340,55 @@ inline void nd_plan(const Layout &L, const std::vector<int> &face_k, int leaf, N
     std::vector<int> fillp(P.xsc_off.begin(), P.xsc_off.end() - 1);
     for (int q = 0; q < (int)P.bidx.size(); ++q) P.xsc[fillp[P.bidx[q]]++] = q;
   }
-  // task descriptors, three int4 each:
+  // Task descriptors, four int4 each:
   //   {front, first row / column, lane-group width, n}, {m, first dof, v_off, b_off},
-  //   {r_off low 32 bits, r_off high 32 bits, child slot, 0}
-  // one workgroup (256 lanes) takes 256/g rows (forward) or columns (backward)
-  P.ftask_off.assign(H + 1, 0);
-  P.btask_off.assign(H + 1, 0);
-  auto push = [&](std::vector<int> &T, int r, int j, int g) {
-    const int64_t ro = P.r_off[r];
-    const int d[12] = {r, j, g, P.n[r], P.m[r], P.first[r], (int)P.v_off[r], P.b_off[r],
-                       (int)(uint32_t)(ro & 0xffffffff), (int)(uint32_t)(ro >> 32), P.cslot[r], 0};
-    T.insert(T.end(), d, d + 12);
-  };
-  for (int h = 0; h < H; ++h) {
-    for (int r = P.lvl_off[h]; r < P.lvl_off[h + 1]; ++r) {
-      const int fr = 256 / P.gf[r], br = 256 / P.gb[r];
-      for (int j = 0; j < P.n[r] + P.m[r]; j += fr) push(P.ftask, r, j, P.gf[r]);
-      for (int j = 0; j < P.n[r]; j += br) push(P.btask, r, j, P.gb[r]);
-    }
-    P.ftask_off[h + 1] = (int)P.ftask.size() / 12;
-    P.btask_off[h + 1] = (int)P.btask.size() / 12;
+  //   {r_off low 32 bits, r_off high 32 bits, child slot, kind (0 forward, 1 backward)},
+  //   {counter a, target a, counter b, target b}  (-1: no dependency)
+  // One workgroup (256 lanes) takes 256/g rows (forward) or columns (backward).
+  // Counter p counts the finished forward tasks of front p, counter nfr + p its
+  // backward tasks.  A forward task waits for its children's forward tasks; a
+  // backward task for its parent's backward tasks (the root: its own forward
+  // tasks).  The order is topological, as the dataflow sweep requires.
+  std::vector<int> nft(nn, 0), nbt(nn, 0);
+  for (int r = 0; r < nn; ++r) {
+    const int fr = 256 / P.gf[r], br = 256 / P.gb[r];
+    nft[r] = (P.n[r] + P.m[r] + fr - 1) / fr;
+    nbt[r] = (P.n[r] + br - 1) / br;
   }
+  auto push = [&](int r, int j, int g, int kind) {
+    const int64_t ro = P.r_off[r];
+    int da = -1, ta = 0, db = -1, tb = 0;
+    if (kind == 0) {
+      const int c0 = P.ch[2 * r], c1 = P.ch[2 * r + 1];
+      if (c0 >= 0) { da = c0; ta = nft[c0]; }
+      if (c1 >= 0) { db = c1; tb = nft[c1]; }
+    } else if (parent[r] >= 0) {
+      da = nn + parent[r];
+      ta = nbt[parent[r]];
+    } else {
+      da = r;
+      ta = nft[r];
+    }
+    const int d[16] = {r, j, g, P.n[r], P.m[r], P.first[r], (int)P.v_off[r], P.b_off[r],
+                       (int)(uint32_t)(ro & 0xffffffff), (int)(uint32_t)(ro >> 32), P.cslot[r], kind,
+                       da, ta, db, tb};
+    P.task.insert(P.task.end(), d, d + 16);
+  };
+  P.ftask_off.assign(H + 1, 0);
+  P.btask_lo.assign(H, 0);
+  P.btask_hi.assign(H, 0);
+  for (int h = 0; h < H; ++h) {
+    for (int r = P.lvl_off[h]; r < P.lvl_off[h + 1]; ++r)
+      for (int j = 0; j < P.n[r] + P.m[r]; j += 256 / P.gf[r]) push(r, j, P.gf[r], 0);
+    P.ftask_off[h + 1] = (int)P.task.size() / 16;
+  }
+  for (int h = H - 1; h >= 0; --h) {
+    P.btask_lo[h] = (int)P.task.size() / 16;
+    for (int r = P.lvl_off[h]; r < P.lvl_off[h + 1]; ++r)
+      for (int j = 0; j < P.n[r]; j += 256 / P.gb[r]) push(r, j, P.gb[r], 1);
+    P.btask_hi[h] = (int)P.task.size() / 16;
+  }
+  P.ntask = (int)P.task.size() / 16;
   if (nv > INT32_MAX) throw std::length_error("coarse plan: front vectors too long");
 }
 

@@ -75,9 +75,9 @@ int main(int argc, char **argv) {
   dump("wdst", P.wdst);
   dump("xsc_off", P.xsc_off);
   dump("xsc", P.xsc);
-  dump("ftask", P.ftask);
-  dump("btask", P.btask);
+  dump("task", P.task);
   dump("ftask_off", P.ftask_off);
-  dump("btask_off", P.btask_off);
+  dump("btask_lo", P.btask_lo);
+  dump("btask_hi", P.btask_hi);
   return 0;
 }

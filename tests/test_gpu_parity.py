@@ -338,3 +338,29 @@ def test_graph_replays_match_eager(precision):
         assert s.stats()["it"] == itb
         assert np.array_equal(u, ub) and np.array_equal(p, pb), f"replay {rep}, source b"
     s.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_coarse_dataflow_matches_level_sweeps(precision):
+    """The single-launch dataflow coarse sweep and the level-by-level sweeps are bit-identical.
+
+    Both run the same task bodies on the same data; only the scheduling
+    differs.  Several solves in a row also exercise the counter reset.
+    """
+    Solver = _gpu()
+    pr = W.layer_60x220(0, tau=10.0)
+    s_flow = Solver(pr.n, pr.h, pr.perm, pr.cuts, tau=10.0, precision=precision, coarse_dataflow=True)
+    s_lvl = Solver(pr.n, pr.h, pr.perm, pr.cuts, tau=10.0, precision=precision)
+    assert s_flow.stats()["coarse_fronts"] == s_lvl.stats()["coarse_fronts"] > 1
+    rng = np.random.default_rng(11)
+    xu = rng.standard_normal(s_flow.n_gamma)
+    zf, pf = s_flow.apply_precond(xu)
+    zl, pl = s_lvl.apply_precond(xu)
+    assert np.array_equal(zf, zl) and np.array_equal(pf, pl)
+    ul, ql = s_lvl.solve(pr.source, rtol=1e-8)
+    for _ in range(3):
+        uf, qf = s_flow.solve(pr.source, rtol=1e-8)
+        assert s_flow.stats()["it"] == s_lvl.stats()["it"]
+        assert np.array_equal(uf, ul) and np.array_equal(qf, ql)
+    s_flow.close()
+    s_lvl.close()

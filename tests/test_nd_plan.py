@@ -162,8 +162,42 @@ def factor(P, Ac, cmap, sub_coff, dsc, sg):
     return FR, BC
 
 
+def check_tasks(P):
+    """Task list: level ranges partition it, dependencies point backwards with exact targets."""
+    nfr, H = P["nfr"], P["H"]
+    T = P["task"].reshape(-1, 16)
+    nt = len(T)
+    fo, blo, bhi = P["ftask_off"], P["btask_lo"], P["btask_hi"]
+    assert fo[0] == 0 and fo[H] == blo[H - 1] and bhi[0] == nt
+    for h in range(H - 1):
+        assert bhi[h + 1] == blo[h]
+    kind = T[:, 11]
+    assert (kind[:fo[H]] == 0).all() and (kind[fo[H]:] == 1).all()
+    # tasks per counter, and the last task index of each counter
+    count = np.zeros(2 * nfr, int)
+    last = np.full(2 * nfr, -1)
+    for i, d in enumerate(T):
+        c = d[0] + (nfr if d[11] else 0)
+        count[c] += 1
+        last[c] = i
+    for i, d in enumerate(T):
+        for dep, target in ((d[12], d[13]), (d[14], d[15])):
+            if dep < 0:
+                continue
+            assert target == count[dep] and last[dep] < i, "dependency not strictly earlier"
+        p = d[0]
+        if d[11] == 0:
+            kids = {c for c in P["ch"][2 * p:2 * p + 2] if c >= 0}
+            assert {x for x in (d[12], d[14]) if x >= 0} == kids
+        else:
+            parent = [q for q in range(nfr) if p in P["ch"][2 * q:2 * q + 2]]
+            want = nfr + parent[0] if parent else p
+            assert d[12] == want and d[14] == -1
+
+
 def sweep(P, FR, BC, sg, b):
-    """k_nd_fwd / k_nd_bwd, level by level, driven by the task descriptors."""
+    """k_nd_flow serialised: the task list in index order (also what the
+    level-by-level kernels compute)."""
     nfr, nk, H = P["nfr"], P["nk"], P["H"]
     nv = P["v_off"][nfr]
     S = [np.zeros(nv), np.zeros(nv)]
@@ -171,61 +205,52 @@ def sweep(P, FR, BC, sg, b):
     z = np.full(nk, np.nan)
     x = np.full(nk, np.nan)
     XB = np.full(max(1, P["b_off"][nfr]), np.nan)
-    ft, bt = P["ftask"].reshape(-1, 12), P["btask"].reshape(-1, 12)
+    T = P["task"].reshape(-1, 16)
     lvl = np.empty(nfr, int)
     for h in range(H):
         lvl[P["lvl_off"][h]:P["lvl_off"][h + 1]] = h
-
-    def unpack(d):
-        p, j, g, n, m, fst, vo, bo, rlo, rhi, slot, _ = (int(v) for v in d)
+    done_f, done_b = set(), set()
+    for d in T:
+        p, j, g, n, m, fst, vo, bo, rlo, rhi, slot, kind = (int(v) for v in d[:12])
         ro = (rhi & 0xffffffff) << 32 | (rlo & 0xffffffff)
-        assert (p, n, m, fst, vo, bo, ro) == (p, P["n"][p], P["m"][p], P["first"][p], P["v_off"][p],
-                                              P["b_off"][p], P["r_off"][p])
+        assert (n, m, fst, vo, bo, ro) == (P["n"][p], P["m"][p], P["first"][p], P["v_off"][p], P["b_off"][p],
+                                           P["r_off"][p])
         assert g in (4, 16, 64)
-        return p, j, g, n, m, fst, vo, bo, ro, slot
-
-    for lv in range(H):
-        done = set()
-        for task in range(P["ftask_off"][lv], P["ftask_off"][lv + 1]):
-            p, r0, g, nn, mm, fst, vo, bo, ro, slot = unpack(ft[task])
-            assert P["lvl_off"][lv] <= p < P["lvl_off"][lv + 1]
+        if kind == 0:
             assert slot == P["cslot"][p]
-            t = b[fst:fst + nn] + S[0][vo:vo + nn] + S[1][vo:vo + nn]
-            for r in range(r0, min(r0 + 256 // g, nn + mm)):
-                assert (p, r) not in done
-                done.add((p, r))
-                if r < nn:
+            t = b[fst:fst + n] + S[0][vo:vo + n] + S[1][vo:vo + n]
+            assert not np.isnan(t).any()
+            for r in range(j, min(j + 256 // g, n + m)):
+                assert (p, r) not in done_f
+                done_f.add((p, r))
+                if r < n:
                     o = ro + r * (r + 1) // 2
                     z[fst + r] = FR[o:o + r + 1] @ t[:r + 1]
                 else:
-                    o = ro + nn * (nn + 1) // 2 + (r - nn) * nn
-                    dst = P["wdst"][bo + r - nn]
+                    o = ro + n * (n + 1) // 2 + (r - n) * n
+                    dst = P["wdst"][bo + r - n]
                     assert not written[slot, dst]
                     written[slot, dst] = True
-                    S[slot][dst] = S[0][vo + r] + S[1][vo + r] - FR[o:o + nn] @ t
-        assert len(done) == sum(P["n"][p] + P["m"][p] for p in range(P["lvl_off"][lv], P["lvl_off"][lv + 1]))
-    for lv in range(H - 1, -1, -1):
-        done = set()
-        for task in range(P["btask_off"][lv], P["btask_off"][lv + 1]):
-            p, c0, g, nn, mm, fst, vo, bo, ro, slot = unpack(bt[task])
-            f = nn + mm
-            xb = XB[bo:bo + mm].copy()
+                    S[slot][dst] = S[0][vo + r] + S[1][vo + r] - FR[o:o + n] @ t
+        else:
+            f = n + m
+            xb = XB[bo:bo + m].copy()
             assert not np.isnan(xb).any(), "B vector read before it was filled"
-            for c in range(c0, min(c0 + 256 // g, nn)):
-                d = fst + c
-                assert d not in done
-                done.add(d)
+            for c in range(j, min(j + 256 // g, n)):
+                dd = fst + c
+                assert dd not in done_b
+                done_b.add(dd)
                 o = ro + c * f - c * (c - 1) // 2
-                nl = nn - c
-                val = BC[o:o + nl] @ (sg[d:d + nl] * z[d:d + nl]) - BC[o + nl:o + nl + mm] @ xb
-                x[d] = val
-                for k in range(P["xsc_off"][d], P["xsc_off"][d + 1]):
+                nl = n - c
+                val = BC[o:o + nl] @ (sg[dd:dd + nl] * z[dd:dd + nl]) - BC[o + nl:o + nl + m] @ xb
+                x[dd] = val
+                for k in range(P["xsc_off"][dd], P["xsc_off"][dd + 1]):
                     q = P["xsc"][k]
-                    assert P["bidx"][q] == d
+                    assert P["bidx"][q] == dd
                     owner = int(np.searchsorted(P["b_off"], q, side="right")) - 1
-                    assert lvl[owner] < lv, "scatter into a front of the same or a higher level"
+                    assert lvl[owner] < lvl[p], "scatter into a front of the same or a higher level"
                     XB[q] = val
-        assert len(done) == P["lvl_dof"][lv + 1] - P["lvl_dof"][lv]
+    assert len(done_f) == int(sum(P["n"]) + sum(P["m"])) and len(done_b) == nk
     return x
 
 
@@ -257,6 +282,7 @@ def test_plan_factor_and_sweeps_match_dense_solve(dumper, args):
         for c in P["ch"][2 * p:2 * p + 2]:
             if c >= 0:
                 assert lvl[c] < lvl[p]
+    check_tasks(P)
     K, Ac, cmap, sub_coff, dsc, sg = coarse_matrix(P, rng)
     FR, BC = factor(P, Ac, cmap, sub_coff, dsc, sg)
     b = rng.standard_normal(P["nk"])
