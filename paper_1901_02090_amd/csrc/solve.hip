@@ -90,6 +90,26 @@ __device__ __forceinline__ void load16(const double *p, double *o) {
   o[0] = v.x; o[1] = v.y;
 }
 
+// The same 16 bytes kept in their storage type (widened at use), for kernels
+// that hold many loads in flight.
+template <typename TS> struct Raw16;
+template <> struct Raw16<float> {
+  float4 v;
+  __device__ __forceinline__ double operator[](int i) const {
+    return i == 0 ? v.x : (i == 1 ? v.y : (i == 2 ? v.z : v.w));
+  }
+};
+template <> struct Raw16<double> {
+  double2 v;
+  __device__ __forceinline__ double operator[](int i) const { return i == 0 ? v.x : v.y; }
+};
+template <typename TS>
+__device__ __forceinline__ Raw16<TS> load_raw16(const TS *p) {
+  Raw16<TS> r;
+  r.v = *reinterpret_cast<const decltype(r.v) *>(p);
+  return r;
+}
+
 // Convergence test at the head of the first kernel of the preconditioner:
 // ||r||^2 from the partials of the residual update decides whether the CG
 // stops here.  Returns true when the calling kernel must leave.
@@ -191,25 +211,28 @@ __global__ __launch_bounds__(256) void k_psi_apply(DevGeom g, const TS *__restri
   __syncthreads();
   const int c0 = sub_coff[i], nci = sub_coff[i + 1] - c0;
   const TS *P = Psi + psi_off[i];
-  for (int cb = 4 * wv; cb < nci; cb += 16) {
-    double d[4] = {0.0, 0.0, 0.0, 0.0};
+  // eight columns per wave and round: sixteen 16-byte loads per lane in flight
+  // for two row steps, then two four-column transposed reductions
+  for (int cb = 8 * wv; cb < nci; cb += 32) {
+    double d[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     for (int t = lane * VW; t < np; t += 64 * VW) {
+      Raw16<TS> a[8];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        double a[VW];
-        if (cb + q < nci) load16(P + (int64_t)(cb + q) * np + t, a);
-        else {
-#pragma unroll
-          for (int v = 0; v < VW; ++v) a[v] = 0.0;
-        }
-#pragma unroll
-        for (int v = 0; v < VW; ++v) d[q] = fma(a[v], xs[t + v], d[q]);
+      for (int q = 0; q < 8; ++q) {
+        if (cb + q < nci) a[q] = load_raw16(P + (int64_t)(cb + q) * np + t);
+        else a[q].v = {};
       }
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+#pragma unroll
+        for (int v = 0; v < VW; ++v) d[q] = fma(a[q][v], xs[t + v], d[q]);
     }
-    const double tot = transpose_reduce4(d, lane);
+    const double tot0 = transpose_reduce4(d, lane);
+    const double tot1 = transpose_reduce4(d + 4, lane);
     if ((lane & 15) == 0) {
       const int c = cb + (lane >> 4);
-      if (c < nci) gloc[c0 + c] = tot;
+      if (c < nci) gloc[c0 + c] = tot0;
+      if (c + 4 < nci) gloc[c0 + c + 4] = tot1;
     }
   }
 }
@@ -282,14 +305,20 @@ __global__ void k_coarse_rhs(DevCoarse cs, const double *__restrict__ gloc, doub
   }
 }
 
-// w^i = y^i + Psi^i alpha^(i)  (y may be null)
+// w^i = y^i + Psi^i alpha^(i)  (y may be null).  Each lane owns 16-byte row
+// chunks of the ld4-padded columns (VW rows), the four waves split the
+// columns, and the partial sums meet in LDS; a lane keeps a dozen independent
+// 16-byte loads in flight.
 template <typename TS>
 __global__ __launch_bounds__(256) void k_psi_correct(DevGeom g, DevCoarse cs, const TS *__restrict__ Psi,
                                                      const int64_t *__restrict__ psi_off,
                                                      const double *__restrict__ yloc,
                                                      const double *__restrict__ csol, double *__restrict__ wloc,
                                                      const CgState *st) {
+  constexpr int VW = 16 / sizeof(TS);
+  constexpr int RB = 64 * VW;        // rows per block
   __shared__ double al[1024];
+  __shared__ double part[4 * RB];
   if (st && st->done) return;
   const int i = blockIdx.x;
   const int n = g.nG[i];
@@ -299,10 +328,30 @@ __global__ __launch_bounds__(256) void k_psi_correct(DevGeom g, DevCoarse cs, co
   __syncthreads();
   const TS *P = Psi + psi_off[i];
   const int ldp = ld4(n);
-  for (int r = threadIdx.x; r < n; r += 256) {
-    double s = yloc ? yloc[go + r] : 0.0;
-    for (int c = 0; c < nci; ++c) s = fma((double)P[r + (int64_t)c * ldp], al[c], s);
-    wloc[go + r] = s;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int rb = 0; rb < n; rb += RB) {
+    const int r0 = rb + lane * VW;
+    double acc[VW];
+#pragma unroll
+    for (int v = 0; v < VW; ++v) acc[v] = 0.0;
+    if (r0 < ldp) {
+#pragma unroll 4
+      for (int c = wv; c < nci; c += 4) {
+        double a[VW];
+        load16(P + (int64_t)c * ldp + r0, a);
+        const double ac = al[c];
+#pragma unroll
+        for (int v = 0; v < VW; ++v) acc[v] = fma(a[v], ac, acc[v]);
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < VW; ++v) part[wv * RB + lane * VW + v] = acc[v];
+    __syncthreads();
+    for (int r = threadIdx.x; r < RB && rb + r < n; r += 256) {
+      const double s = (part[r] + part[RB + r]) + (part[2 * RB + r] + part[3 * RB + r]);
+      wloc[go + rb + r] = (yloc ? yloc[go + rb + r] : 0.0) + s;
+    }
+    __syncthreads();
   }
 }
 
