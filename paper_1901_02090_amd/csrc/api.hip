@@ -143,6 +143,9 @@ void check_err(bddc_problem *h, const char *stage) {
                                        " (code " + std::to_string(e) + ")"};
 }
 
+// LDS of k_symv: the gathered x and one row buffer per wavefront.
+inline size_t symv_shm(const Layout &L) { return (size_t)(1 + SYMV_WAVES) * ld4(L.maxG) * sizeof(double); }
+
 // Every device array the coarse kernels dereference must exist before a launch.
 void check_coarse_ptrs(const bddc_problem *h) {
   const DevFronts &f = h->fd;
@@ -363,6 +366,13 @@ void do_setup(bddc_problem *h, const bddc_grid *gr, const double *perm, const bd
   cs.co_plus = h->upload(co_plus);
   cs.pidx = h->upload(pidx);
 
+  {
+    int dev = 0, lds_max = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    if (symv_shm(L) > (size_t)lds_max)
+      throw Error{BDDC_EINVAL, "subdomain interface too large for the local operator kernels' LDS"};
+  }
   // local coarse spaces Psi^i, coarse matrices and substructure operators T^i
   std::vector<int64_t> cwoff(N), acoff(N), psioff(N);
   int64_t cws = 0, acs = 0, pss = 0;
@@ -566,9 +576,9 @@ void launch_precond(bddc_problem *h, const double *r, double *z, double *zpart, 
                                             nrp);
   if (h->nk > 0) HIPCHK(hipEventRecord(h->ev_fork, s));
   if (mixed)
-    k_symv<float><<<N, 256, shm, s>>>(h->g, h->T32, h->d_pk, r, 0.5, h->yloc, st, nullptr, 0);
+    k_symv<float><<<N, SYMV_THREADS, symv_shm(L), s>>>(h->g, h->T32, h->d_pk, r, 0.5, h->yloc, st, nullptr, 0);
   else
-    k_symv<double><<<N, 256, shm, s>>>(h->g, h->T64, h->d_pk, r, 0.5, h->yloc, st, nullptr, 0);
+    k_symv<double><<<N, SYMV_THREADS, symv_shm(L), s>>>(h->g, h->T64, h->d_pk, r, 0.5, h->yloc, st, nullptr, 0);
   // The coarse solve stays FP64 in both forms: the CG runs in the balanced
   // subspace, so the face-average coarse fluxes must satisfy B_c alpha = 0 to
   // FP64 accuracy (the FP32 local operators are corrected by the balance step).
@@ -591,7 +601,7 @@ void launch_iteration(bddc_problem *h) {
   const int N = L.N, nGm = L.nGamma;
   const size_t shm = (size_t)5 * ld4(L.maxG) * sizeof(double);
   const int nb = (int)nblk(nGm);
-  k_symv<double><<<N, 256, shm, s>>>(h->g, h->Spk, h->d_pk, h->pu, 1.0, h->yloc, h->st, nullptr, 0);
+  k_symv<double><<<N, SYMV_THREADS, symv_shm(L), s>>>(h->g, h->Spk, h->d_pk, h->pu, 1.0, h->yloc, h->st, nullptr, 0);
   k_sys_assemble<<<nb, 256, 0, s>>>(h->g, h->yloc, h->pp, h->dscale, h->pu, h->qu, h->part_g, h->st);
   k_update_xr<<<nb, 256, 0, s>>>(nGm, N, h->part_g, nb, h->pu, h->qu, h->pp, h->xu, h->ru, h->xp, h->part_r,
                                  h->st, h->alpha_h);
@@ -710,7 +720,7 @@ int do_solve(bddc_problem *h, const double *rhs, double rtol, double *flux, doub
                                             nullptr);
     k_average_balance<<<nF, 256, 0, s>>>(h->g, h->cs, h->wloc, h->csol, h->u0, nullptr, nullptr, nullptr);
     // steps 2-3 right-hand side: f* = -S u0 + H^T X F
-    k_symv<double><<<N, 256, shm, s>>>(h->g, h->Spk, h->d_pk, h->u0, 1.0, h->yloc, nullptr, nullptr, 0);
+    k_symv<double><<<N, SYMV_THREADS, symv_shm(L), s>>>(h->g, h->Spk, h->d_pk, h->u0, 1.0, h->yloc, nullptr, nullptr, 0);
     k_source_term<<<N, 256, (size_t)2 * L.maxC * sizeof(double), s>>>(h->g, h->mcoef, h->Xmat, h->d_Xoff, src,
                                                                        h->wloc);
     k_fstar<<<nblk(nGm), 256, 0, s>>>(h->g, h->yloc, h->wloc, h->ru);
@@ -1032,7 +1042,7 @@ int bddc_apply(bddc_handle h, int32_t which, const double *x_u, const double *x_
       if (!x_p) throw Error{BDDC_EINVAL, "x_p required"};
       HIPCHK(hipMemcpyAsync(h->pp, x_p, N * sizeof(double), hipMemcpyHostToDevice, s));
       const size_t shm = (size_t)5 * ld4(L.maxG) * sizeof(double);
-      k_symv<double><<<N, 256, shm, s>>>(h->g, h->Spk, h->d_pk, h->ru, 1.0, h->yloc, nullptr, nullptr, 0);
+      k_symv<double><<<N, SYMV_THREADS, symv_shm(L), s>>>(h->g, h->Spk, h->d_pk, h->ru, 1.0, h->yloc, nullptr, nullptr, 0);
       k_sys_assemble<<<nblk(nGm), 256, 0, s>>>(h->g, h->yloc, h->pp, h->dscale, nullptr, h->qu, nullptr, nullptr);
       k_b0<<<N, 256, 0, s>>>(h->g, h->ru, h->dscale, h->xp);
       HIPCHK(hipMemcpyAsync(y_u, h->qu, nGm * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1069,11 +1079,11 @@ int bddc_time_kernel(bddc_handle h, int32_t which, int32_t reps, double *avg_ms,
     double b = 0.0;
     auto launch = [&]() {
       if (which == BDDC_K_SCHUR_APPLY)
-        k_symv<double><<<N, 256, shm, s>>>(h->g, h->Spk, h->d_pk, h->pu, 1.0, h->yloc, nullptr, nullptr, 0);
+        k_symv<double><<<N, SYMV_THREADS, symv_shm(L), s>>>(h->g, h->Spk, h->d_pk, h->pu, 1.0, h->yloc, nullptr, nullptr, 0);
       else if (h->precision == BDDC_MIXED)
-        k_symv<float><<<N, 256, shm, s>>>(h->g, h->T32, h->d_pk, h->ru, 0.5, h->yloc, nullptr, nullptr, 0);
+        k_symv<float><<<N, SYMV_THREADS, symv_shm(L), s>>>(h->g, h->T32, h->d_pk, h->ru, 0.5, h->yloc, nullptr, nullptr, 0);
       else
-        k_symv<double><<<N, 256, shm, s>>>(h->g, h->T64, h->d_pk, h->ru, 0.5, h->yloc, nullptr, nullptr, 0);
+        k_symv<double><<<N, SYMV_THREADS, symv_shm(L), s>>>(h->g, h->T64, h->d_pk, h->ru, 0.5, h->yloc, nullptr, nullptr, 0);
     };
     // algorithmic bytes: the lower triangles, the gather map and gathered x, y
     if (which == BDDC_K_SCHUR_APPLY)

@@ -132,15 +132,23 @@ __device__ __forceinline__ bool cg_exit(CgState *st, const double *__restrict__ 
   return false;
 }
 
-// y^i = M^i (xscale * R_i x) for every subdomain (one workgroup each), M^i in
-// group-aligned packed storage (S^i, or T^i of the preconditioner).
+// y^i = M^i (xscale * R_i x) for every subdomain (one workgroup of SYMV_WAVES
+// wavefronts each), M^i in group-aligned packed storage (S^i, or T^i of the
+// preconditioner).  Eight waves per workgroup: with one subdomain per
+// workgroup the launch is about three rounds of resident workgroups on 256
+// CUs for the 2,244 subdomains of the reservoir, so the last round is nearly
+// full (four waves left it half empty).
+constexpr int SYMV_WAVES = 8;
+constexpr int SYMV_THREADS = 64 * SYMV_WAVES;
+
 template <typename TS>
-__global__ __launch_bounds__(256) void k_symv(DevGeom g, const TS *__restrict__ M, const int64_t *__restrict__ pk,
-                                              const double *__restrict__ x, double xscale,
-                                              double *__restrict__ yloc, CgState *st,
-                                              const double *__restrict__ rpart, int nrpart) {
+__global__ __launch_bounds__(SYMV_THREADS) void k_symv(DevGeom g, const TS *__restrict__ M,
+                                                       const int64_t *__restrict__ pk,
+                                                       const double *__restrict__ x, double xscale,
+                                                       double *__restrict__ yloc, CgState *st,
+                                                       const double *__restrict__ rpart, int nrpart) {
   extern __shared__ double sh[];
-  __shared__ double red[8];
+  __shared__ double red[SYMV_WAVES];
   if (cg_exit(st, rpart, nrpart, red)) return;
   constexpr int VW = 16 / sizeof(TS);
   const int i = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -149,8 +157,8 @@ __global__ __launch_bounds__(256) void k_symv(DevGeom g, const TS *__restrict__ 
   const int64_t go = g.g_off[i];
   double *xs = sh;
   double *yw = sh + np;
-  for (int r = tid; r < np; r += 256) xs[r] = (r < n) ? xscale * x[g.Rmap[go + r]] : 0.0;
-  for (int e = tid; e < 4 * np; e += 256) yw[e] = 0.0;
+  for (int r = tid; r < np; r += SYMV_THREADS) xs[r] = (r < n) ? xscale * x[g.Rmap[go + r]] : 0.0;
+  for (int e = tid; e < SYMV_WAVES * np; e += SYMV_THREADS) yw[e] = 0.0;
   __syncthreads();
   const TS *Mi = M + pk[i];
   double *yme = yw + wv * np;
@@ -158,7 +166,7 @@ __global__ __launch_bounds__(256) void k_symv(DevGeom g, const TS *__restrict__ 
   // time: each lane loads VW consecutive rows of all four columns with 16-byte
   // loads, folds the strictly-lower products into one LDS update per row, and
   // the four transposed dot products are reduced together.
-  for (int gi = wv; gi < G4; gi += 4) {
+  for (int gi = wv; gi < G4; gi += SYMV_WAVES) {
     const int rs = 4 * gi;
     const int L = 4 * (G4 - gi);
     const TS *base = Mi + gp_group(n, gi);
@@ -187,7 +195,12 @@ __global__ __launch_bounds__(256) void k_symv(DevGeom g, const TS *__restrict__ 
     if ((lane & 15) == 0) yme[rs + (lane >> 4)] += tot;
   }
   __syncthreads();
-  for (int r = tid; r < n; r += 256) yloc[go + r] = yw[r] + yw[np + r] + yw[2 * np + r] + yw[3 * np + r];
+  for (int r = tid; r < n; r += SYMV_THREADS) {
+    double y = 0.0;
+#pragma unroll
+    for (int w = 0; w < SYMV_WAVES; ++w) y += yw[w * np + r];
+    yloc[go + r] = y;
+  }
 }
 
 // g^i = Psi^{iT} (xscale * R_i x): the coarse right-hand side pieces of the
