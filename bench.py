@@ -58,7 +58,7 @@ def time_gpu(pr, precision, steps, warmup, kernel_reps=0):
     """
     import torch
     from paper_1901_02090_amd import Solver
-    from paper_1901_02090_amd.bddc import K_SCHUR_APPLY, K_PRECOND_APPLY
+    from paper_1901_02090_amd.bddc import K_SCHUR_APPLY, K_PRECOND_APPLY, K_PRECOND_FULL
     t0 = time.perf_counter()
     s = Solver(pr.n, pr.h, pr.perm, pr.cuts, tau=pr.tau, precision=precision, max_it=5000)
     setup_s = time.perf_counter() - t0
@@ -94,6 +94,7 @@ def time_gpu(pr, precision, steps, warmup, kernel_reps=0):
         if kernel_reps > 0:
             kern["schur"] = s.time_kernel(K_SCHUR_APPLY, kernel_reps)
             kern["precond"] = s.time_kernel(K_PRECOND_APPLY, kernel_reps)
+            kern["precond_full"] = s.time_kernel(K_PRECOND_FULL, kernel_reps)
         return dict(setup_s=setup_s, total_s=total, lat=np.array(lat), stats=st, kernels=kern, host_ms=host_ms,
                     flux=flux.cpu().numpy(), pres=pres.cpu().numpy())
     finally:
@@ -183,6 +184,23 @@ def measured_traffic(kernel):
     return None
 
 
+def copy_rate(reps=20):
+    """Device-to-device copy of COPY_BYTES, timed with events: GB/s moved (read + write)."""
+    import torch
+    a = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    c = torch.empty_like(a)
+    c.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        c.copy_(a)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, c
+    return 2.0 * COPY_BYTES / (ms * 1e-3) / 1e9
+
+
 def kernels_only(pr, reps):
     """Launch the local apply kernels and a 1 GiB device-to-device copy alone.
 
@@ -245,6 +263,15 @@ def main():
             "kernel": f"{kern[0]} ({kern[1]})", "bytes_per_launch": kern[3], "avg_launch_us": kern[2] * 1e3}
 
     st = rmx["stats"]
+    # the whole preconditioner of one CG iteration (Psi^T r, T^i beside the
+    # coarse solve, Psi alpha, averaging), against the vendor HBM peak and the
+    # copy rate measured here
+    ms_p, by_p = rmx["kernels"]["precond_full"]
+    cp = copy_rate()
+    ach_p = by_p / (ms_p * 1e-3) / 1e9
+    prec = {"avg_us": ms_p * 1e3, "bytes": by_p, "achieved_gbs": ach_p, "frac_of_peak": ach_p / HBM_PEAK_GBS,
+            "copy_gbs": cp, "frac_of_copy": ach_p / cp, "coarse_levels": st["coarse_levels"],
+            "coarse_dense_dofs": st["coarse_dense"]}
     lat = rmx["lat"] * 1e3
     value = args.steps / rmx["total_s"]
     ref_u, ref_p = r64["flux"], r64["pres"]
@@ -278,6 +305,7 @@ def main():
         "mixed_vs_fp64": {"flux_relerr": float(np.linalg.norm(rmx["flux"] - ref_u) / np.linalg.norm(ref_u)),
                           "pressure_relerr": float(np.linalg.norm(rmx["pres"] - ref_p) / np.linalg.norm(ref_p))},
         "roofline": roof,
+        "precond_apply": prec,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pr, args.cpu_seconds, st["it"])

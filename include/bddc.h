@@ -47,6 +47,7 @@ extern "C" {
 #define BDDC_EBREAKDOWN -4   /* CG breakdown: p^T S p <= 0 or not finite       */
 #define BDDC_EFACTOR    -5   /* a local or coarse factorization lost definiteness */
 #define BDDC_EDEVICE    -6   /* HIP runtime error                              */
+#define BDDC_EBUSY      -7   /* server request still pending                   */
 
 /* precision of the preconditioner (the CG recurrences and S are always FP64) */
 #define BDDC_FP64  0
@@ -85,6 +86,15 @@ typedef struct {
   uint32_t flags;        /* BDDC_ALL_CONSTRAINED (diagnostic)                 */
   int32_t coarse_leaf;   /* nested dissection of the coarse problem stops at
                             boxes of at most this many subdomains (<= 0: 1) */
+  int32_t coarse_top;    /* the top levels of the coarse tree holding at most
+                            this many coarse dofs are solved with the explicit
+                            inverse of their Schur complement, formed at setup
+                            (0: 4096; < 0: none; at most 8192; ignored with
+                            BDDC_COARSE_DATAFLOW)                          */
+  int32_t t_workgroups;  /* workgroups of the substructure corrections T^i,
+                            which run beside the coarse solve; fewer leave
+                            more memory bandwidth to its latency-bound
+                            sweeps (<= 0 or > N: one per subdomain)        */
 } bddc_options;
 
 typedef struct {
@@ -103,6 +113,7 @@ typedef struct {
   int32_t precision;
   int32_t coarse_levels;    /* levels of the coarse multifrontal factorization   */
   int32_t coarse_fronts;    /* fronts (separators and leaf boxes) of it          */
+  int32_t coarse_dense;     /* coarse dofs of the dense top block (0: none)      */
   double t_setup_ms;        /* wall time of bddc_setup                           */
   double t_solve_ms;        /* wall time of the last bddc_solve                  */
   double t_pcg_ms;          /* device time of the CG loop of the last solve      */
@@ -204,14 +215,100 @@ int bddc_apply(bddc_handle h, int32_t which, const double *x_u, const double *x_
 /* Time one kernel of the CG iteration on the handle's stream with HIP events:
  * `reps` back-to-back launches on the vectors of the last solve, bracketed by
  * two events.  which = BDDC_K_SCHUR_APPLY (local Schur products S^i of the
- * CG operator) or BDDC_K_PRECOND_APPLY (local substructure corrections T^i of
- * the preconditioner).
+ * CG operator), BDDC_K_PRECOND_APPLY (local substructure corrections T^i of
+ * the preconditioner) or BDDC_K_PRECOND_FULL (the whole preconditioner of
+ * Algorithm "BDDC preconditioner" as one CG iteration applies it: coarse
+ * right-hand sides Psi^{iT} r^i, the corrections T^i r^i beside the coarse
+ * solve, the coarse correction Psi^i alpha and the weighted averaging; one
+ * "launch" is that sequence of kernels on two streams).
  * avg_ms receives the mean duration of one launch, bytes the algorithmic HBM
  * bytes of one launch (operator entries read once, vectors gathered and
  * written once).  Call after a bddc_solve. */
 #define BDDC_K_SCHUR_APPLY   1
 #define BDDC_K_PRECOND_APPLY 2
+#define BDDC_K_PRECOND_FULL  3
 int bddc_time_kernel(bddc_handle h, int32_t which, int32_t reps, double *avg_ms, double *bytes);
+
+/* Device bytes a problem may hold at the peak of its setup (the figure the
+ * server admits requests by).  Every array fixed by the grid and partition is
+ * counted exactly; the adaptive rows of a face are unknown before its
+ * eigenproblem and are taken as min(n_F - 1, 8) when tau is finite (none
+ * otherwise), which also fixes the coarse plan the estimate is built on.
+ * Host-only; opt may be NULL.  Returns BDDC_OK or BDDC_EINVAL. */
+int bddc_estimate_bytes(const bddc_grid *g, const bddc_partition *part, double tau, const bddc_options *opt,
+                        double *bytes);
+
+/* ------------------------------------------------------------------------
+ * Serving: a request loop over independent problems (own grid, permeability,
+ * partition, tau and source each), with continuous batching.  Requests are
+ * admitted in arrival order while fewer than max_active are set up or
+ * solving and their estimated bytes (bddc_estimate_bytes) fit under mem_cap
+ * next to what the admitted ones hold (after its setup a problem counts with
+ * the bytes it actually holds).  Setup runs on worker threads, beside the CG
+ * iterations of the requests already solving; a driver thread advances every
+ * solving request by captured chunks of CG iterations on its own streams, so
+ * the requests' kernels overlap on the device, and a request that finishes
+ * frees its memory and slot for the next.  Every request's arithmetic is that
+ * of bddc_solve on its own handle: its result does not depend on the mix.
+ * ------------------------------------------------------------------------ */
+typedef struct bddc_server *bddc_server_handle;
+
+typedef struct {
+  double mem_cap;         /* device bytes the admitted problems may hold
+                             (<= 0: 90% of the free device memory at create) */
+  int32_t max_active;     /* problems set up or solving at once (<= 0: 4)   */
+  int32_t setup_workers;  /* host threads running setups (<= 0: 1)          */
+  int32_t precision;      /* BDDC_FP64 or BDDC_MIXED, for every request     */
+  uint32_t flags;         /* bddc_options flags for every request           */
+} bddc_server_options;
+
+typedef struct {
+  bddc_grid grid;
+  const double *perm;     /* [n_cells][dim], as for bddc_setup; copied       */
+  bddc_partition part;    /* cuts copied                                    */
+  double tau;             /* as for bddc_setup                              */
+  const double *rhs;      /* [n_cells] cell sources summing to 0; copied     */
+  double rtol;            /* > 0                                            */
+  int32_t max_it;         /* <= 0: 10000                                    */
+} bddc_request;
+
+typedef struct {
+  int32_t status;         /* BDDC_OK, BDDC_ENOCONV or the error code        */
+  int32_t it, converged;
+  double relres, kappa;
+  int32_t n_sub, n_coarse;
+  double queue_ms;        /* submit to admission                            */
+  double setup_ms;        /* setup and the solve's start                    */
+  double solve_ms;        /* CG and post-correction, after the setup        */
+  double latency_ms;      /* submit to completion                           */
+  double est_bytes;       /* admission estimate                             */
+  double device_bytes;    /* bytes the problem held while solving           */
+  double peak_bytes;      /* high-water mark during its setup               */
+} bddc_request_stats;
+
+typedef struct {
+  int64_t submitted, completed, failed, queued, active;
+  int32_t peak_active;    /* most problems set up or solving at once        */
+  double p50_ms, p99_ms;  /* latency percentiles of the completed requests  */
+  double solves_per_s;    /* completed / (last completion - first submit)   */
+  double peak_bytes;      /* most bytes counted against mem_cap at once     */
+  double mem_cap;
+} bddc_server_stats_t;
+
+/* Start the scheduler threads on the current device. */
+int bddc_server_create(const bddc_server_options *opt, bddc_server_handle *out);
+/* Queue a request (its arrays are copied; the call does not wait for the GPU).
+ * BDDC_EINVAL for a bad request, BDDC_ENOMEM if its estimate exceeds mem_cap. */
+int bddc_server_submit(bddc_server_handle s, const bddc_request *req, uint64_t *ticket);
+/* Wait up to wait_ms (< 0: no limit) for a request.  While it is pending:
+ * BDDC_EBUSY.  Once done: copies flux [n_faces_all] and pressure [n_cells]
+ * (host arrays, either may be NULL) and its statistics (may be NULL), releases
+ * the ticket and returns the request's status. */
+int bddc_server_poll(bddc_server_handle s, uint64_t ticket, double wait_ms, double *flux, double *pressure,
+                     bddc_request_stats *st);
+int bddc_server_stats(bddc_server_handle s, bddc_server_stats_t *out);
+/* Drop the queued requests, finish the admitted ones, stop the threads. */
+int bddc_server_destroy(bddc_server_handle s);
 
 #ifdef __cplusplus
 }

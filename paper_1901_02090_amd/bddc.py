@@ -9,7 +9,8 @@ import numpy as np
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libbddc.so")
 
-BDDC_OK, BDDC_EINVAL, BDDC_ENOMEM, BDDC_ENOCONV, BDDC_EBREAKDOWN, BDDC_EFACTOR, BDDC_EDEVICE = 0, -1, -2, -3, -4, -5, -6
+BDDC_OK, BDDC_EINVAL, BDDC_ENOMEM, BDDC_ENOCONV, BDDC_EBREAKDOWN, BDDC_EFACTOR, BDDC_EDEVICE, BDDC_EBUSY = \
+    0, -1, -2, -3, -4, -5, -6, -7
 BDDC_FP64, BDDC_MIXED = 0, 1
 BDDC_ALL_CONSTRAINED = 1
 BDDC_COARSE_DATAFLOW = 2
@@ -19,8 +20,10 @@ X_SCHUR, X_FACE_EIG, X_FACE_K, X_DSCALE, X_GAMMA, X_OMEGA, X_T, X_PSI, X_COARSE_
 OP_SYSTEM, OP_PRECOND = 1, 2
 
 EXPORTED = ["bddc_setup", "bddc_solve", "bddc_stats", "bddc_set_stream", "bddc_destroy", "bddc_last_error",
-            "bddc_sizes", "bddc_export", "bddc_apply", "bddc_time_kernel"]
-K_SCHUR_APPLY, K_PRECOND_APPLY = 1, 2
+            "bddc_sizes", "bddc_export", "bddc_apply", "bddc_time_kernel", "bddc_estimate_bytes",
+            "bddc_server_create", "bddc_server_submit", "bddc_server_poll", "bddc_server_stats",
+            "bddc_server_destroy"]
+K_SCHUR_APPLY, K_PRECOND_APPLY, K_PRECOND_FULL = 1, 2, 3
 
 
 class Grid(C.Structure):
@@ -32,7 +35,8 @@ class Partition(C.Structure):
 
 
 class Options(C.Structure):
-    _fields_ = [("precision", C.c_int32), ("max_it", C.c_int32), ("flags", C.c_uint32), ("coarse_leaf", C.c_int32)]
+    _fields_ = [("precision", C.c_int32), ("max_it", C.c_int32), ("flags", C.c_uint32), ("coarse_leaf", C.c_int32),
+                ("coarse_top", C.c_int32), ("t_workgroups", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -40,9 +44,33 @@ class Stats(C.Structure):
                 ("lambda_min", C.c_double), ("lambda_max", C.c_double), ("omega_tilde", C.c_double),
                 ("n_adaptive", C.c_int32), ("n_coarse_flux", C.c_int32), ("n_coarse", C.c_int32),
                 ("n_sub", C.c_int32), ("n_gamma", C.c_int32), ("n_faces", C.c_int32), ("precision", C.c_int32),
-                ("coarse_levels", C.c_int32), ("coarse_fronts", C.c_int32), ("t_setup_ms", C.c_double), ("t_solve_ms", C.c_double),
+                ("coarse_levels", C.c_int32), ("coarse_fronts", C.c_int32), ("coarse_dense", C.c_int32),
+                ("t_setup_ms", C.c_double), ("t_solve_ms", C.c_double),
                 ("t_pcg_ms", C.c_double), ("bytes_per_iter", C.c_double), ("bytes_prec", C.c_double),
                 ("device_bytes", C.c_double)]
+
+
+class ServerOptions(C.Structure):
+    _fields_ = [("mem_cap", C.c_double), ("max_active", C.c_int32), ("setup_workers", C.c_int32),
+                ("precision", C.c_int32), ("flags", C.c_uint32)]
+
+
+class Request(C.Structure):
+    _fields_ = [("grid", Grid), ("perm", C.POINTER(C.c_double)), ("part", Partition), ("tau", C.c_double),
+                ("rhs", C.POINTER(C.c_double)), ("rtol", C.c_double), ("max_it", C.c_int32)]
+
+
+class RequestStats(C.Structure):
+    _fields_ = [("status", C.c_int32), ("it", C.c_int32), ("converged", C.c_int32), ("relres", C.c_double),
+                ("kappa", C.c_double), ("n_sub", C.c_int32), ("n_coarse", C.c_int32), ("queue_ms", C.c_double),
+                ("setup_ms", C.c_double), ("solve_ms", C.c_double), ("latency_ms", C.c_double),
+                ("est_bytes", C.c_double), ("device_bytes", C.c_double), ("peak_bytes", C.c_double)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64), ("queued", C.c_int64),
+                ("active", C.c_int64), ("peak_active", C.c_int32), ("p50_ms", C.c_double), ("p99_ms", C.c_double),
+                ("solves_per_s", C.c_double), ("peak_bytes", C.c_double), ("mem_cap", C.c_double)]
 
 
 class BddcError(RuntimeError):
@@ -85,6 +113,18 @@ def load_library(path=LIB_PATH):
     lib.bddc_apply.restype = C.c_int
     lib.bddc_time_kernel.argtypes = [P, C.c_int32, C.c_int32, dp, dp]
     lib.bddc_time_kernel.restype = C.c_int
+    lib.bddc_estimate_bytes.argtypes = [C.POINTER(Grid), C.POINTER(Partition), C.c_double, C.POINTER(Options), dp]
+    lib.bddc_estimate_bytes.restype = C.c_int
+    lib.bddc_server_create.argtypes = [C.POINTER(ServerOptions), C.POINTER(P)]
+    lib.bddc_server_create.restype = C.c_int
+    lib.bddc_server_submit.argtypes = [P, C.POINTER(Request), C.POINTER(C.c_uint64)]
+    lib.bddc_server_submit.restype = C.c_int
+    lib.bddc_server_poll.argtypes = [P, C.c_uint64, C.c_double, dp, dp, C.POINTER(RequestStats)]
+    lib.bddc_server_poll.restype = C.c_int
+    lib.bddc_server_stats.argtypes = [P, C.POINTER(ServerStats)]
+    lib.bddc_server_stats.restype = C.c_int
+    lib.bddc_server_destroy.argtypes = [P]
+    lib.bddc_server_destroy.restype = C.c_int
     _lib = lib
     return lib
 
@@ -99,25 +139,47 @@ def _dptr(a):
     return a.ctypes.data_as(C.POINTER(C.c_double))
 
 
+def _grid_part(n, h, cuts):
+    """ctypes grid and partition; the cut arrays are returned to keep them alive."""
+    dim = len(n)
+    n = tuple(int(v) for v in n)
+    g = Grid(dim, (C.c_int32 * 3)(*(list(n) + [1] * (3 - dim))),
+             (C.c_double * 3)(*(list(map(float, h)) + [1.0] * (3 - dim))))
+    keep = [np.ascontiguousarray(c, dtype=np.int32) for c in cuts]
+    cp = (C.POINTER(C.c_int32) * 3)(*[c.ctypes.data_as(C.POINTER(C.c_int32)) for c in keep] +
+                                    [C.POINTER(C.c_int32)()] * (3 - dim))
+    part = Partition((C.c_int32 * 3)(*([len(c) - 1 for c in keep] + [1] * (3 - dim))), cp)
+    return g, part, keep
+
+
+def _tau(tau):
+    return float(tau) if (tau is not None and math.isfinite(tau)) else 0.0
+
+
+def estimate_bytes(n, h, cuts, tau=math.inf, precision="fp64", all_constrained=False):
+    """Device bytes a problem may hold at the peak of its setup (host-only)."""
+    lib = load_library()
+    g, part, _keep = _grid_part(n, h, cuts)
+    opt = Options(BDDC_MIXED if precision == "mixed" else BDDC_FP64, 0,
+                  BDDC_ALL_CONSTRAINED if all_constrained else 0, 0, 0, 0)
+    out = C.c_double()
+    _check(lib, lib.bddc_estimate_bytes(C.byref(g), C.byref(part), _tau(tau), C.byref(opt), C.byref(out)))
+    return out.value
+
+
 class Solver:
     """One problem resident on the GPU: setup once, solve many right-hand sides."""
 
     def __init__(self, n, h, perm, cuts, tau=math.inf, precision="fp64", max_it=10000, all_constrained=False,
-                 coarse_leaf=0, coarse_dataflow=False):
+                 coarse_leaf=0, coarse_dataflow=False, coarse_top=0, t_workgroups=0):
         self.lib = lib = load_library()
-        dim = len(n)
         self.n = tuple(int(v) for v in n)
-        g = Grid(dim, (C.c_int32 * 3)(*(list(self.n) + [1] * (3 - dim))),
-                 (C.c_double * 3)(*(list(map(float, h)) + [1.0] * (3 - dim))))
-        self._cuts = [np.ascontiguousarray(c, dtype=np.int32) for c in cuts]
-        cp = (C.POINTER(C.c_int32) * 3)(*[c.ctypes.data_as(C.POINTER(C.c_int32)) for c in self._cuts] +
-                                        [C.POINTER(C.c_int32)()] * (3 - dim))
-        part = Partition((C.c_int32 * 3)(*([len(c) - 1 for c in self._cuts] + [1] * (3 - dim))), cp)
+        g, part, self._cuts = _grid_part(n, h, cuts)
         opt = Options(BDDC_MIXED if precision == "mixed" else BDDC_FP64, int(max_it),
                       (BDDC_ALL_CONSTRAINED if all_constrained else 0) | (BDDC_COARSE_DATAFLOW if coarse_dataflow else 0),
-                      int(coarse_leaf))
+                      int(coarse_leaf), int(coarse_top), int(t_workgroups))
         perm = np.ascontiguousarray(perm, dtype=np.float64).reshape(-1)
-        t = float(tau) if (tau is not None and math.isfinite(tau)) else 0.0
+        t = _tau(tau)
         self.h = C.c_void_p()
         _check(lib, lib.bddc_setup(C.byref(g), _dptr(perm), C.byref(part), t, C.byref(opt), C.byref(self.h)))
         sz = (C.c_int64 * 8)()
@@ -207,7 +269,7 @@ class Solver:
         return self.apply(OP_PRECOND, xu)
 
     def time_kernel(self, which, reps=50):
-        """Mean launch duration (ms) and algorithmic bytes of one CG kernel."""
+        """Mean duration (ms) and algorithmic bytes of one CG kernel (or of the whole preconditioner)."""
         ms, by = C.c_double(), C.c_double()
         _check(self.lib, self.lib.bddc_time_kernel(self.h, which, int(reps), C.byref(ms), C.byref(by)))
         return ms.value, by.value
@@ -215,6 +277,67 @@ class Solver:
     def close(self):
         if getattr(self, "h", None) and self.h.value:
             self.lib.bddc_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Request loop with continuous batching over independent problems (bddc_server_*)."""
+
+    def __init__(self, precision="fp64", mem_cap=0.0, max_active=4, setup_workers=1, all_constrained=False):
+        self.lib = lib = load_library()
+        opt = ServerOptions(float(mem_cap), int(max_active), int(setup_workers),
+                            BDDC_MIXED if precision == "mixed" else BDDC_FP64,
+                            BDDC_ALL_CONSTRAINED if all_constrained else 0)
+        self.h = C.c_void_p()
+        _check(lib, lib.bddc_server_create(C.byref(opt), C.byref(self.h)))
+        self._sizes = {}
+
+    def submit(self, n, h, perm, cuts, source, tau=math.inf, rtol=1e-8, max_it=10000):
+        """Queue one problem; returns its ticket at once (inputs are copied)."""
+        g, part, keep = _grid_part(n, h, cuts)
+        perm = np.ascontiguousarray(perm, dtype=np.float64).reshape(-1)
+        src = np.ascontiguousarray(source, dtype=np.float64).reshape(-1)
+        req = Request(g, _dptr(perm), part, _tau(tau), _dptr(src), float(rtol), int(max_it))
+        t = C.c_uint64()
+        _check(self.lib, self.lib.bddc_server_submit(self.h, C.byref(req), C.byref(t)))
+        dim = len(n)
+        nn = [int(v) for v in n] + [1] * (3 - dim)
+        ncells = int(np.prod(nn))
+        nfaces = sum(int(np.prod([nn[e] + (1 if e == d else 0) for e in range(3)])) for d in range(dim))
+        self._sizes[t.value] = (nfaces, ncells)
+        return t.value
+
+    def poll(self, ticket, wait_ms=0.0):
+        """None while pending; else (flux, pressure, stats dict) once done (raises on a failed request)."""
+        nfaces, ncells = self._sizes[ticket]
+        flux = np.empty(nfaces)
+        pres = np.empty(ncells)
+        st = RequestStats()
+        rc = self.lib.bddc_server_poll(self.h, C.c_uint64(ticket), float(wait_ms), _dptr(flux), _dptr(pres),
+                                       C.byref(st))
+        if rc == BDDC_EBUSY:
+            return None
+        del self._sizes[ticket]
+        _check(self.lib, rc, allow=(BDDC_ENOCONV,))
+        return flux, pres, {k: getattr(st, k) for k, _ in RequestStats._fields_}
+
+    def result(self, ticket):
+        return self.poll(ticket, wait_ms=-1.0)
+
+    def stats(self):
+        s = ServerStats()
+        _check(self.lib, self.lib.bddc_server_stats(self.h, C.byref(s)))
+        return {k: getattr(s, k) for k, _ in ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "h", None) and self.h.value:
+            self.lib.bddc_server_destroy(self.h)
             self.h = C.c_void_p()
 
     def __del__(self):

@@ -6,7 +6,10 @@
 #include <string.h>
 
 #include <chrono>
+#include <condition_variable>
 #include <cstdio>
+#include <mutex>
+#include <shared_mutex>
 #include <new>
 #include <stdexcept>
 #include <string>
@@ -51,8 +54,11 @@ struct bddc_problem {
   int max_it = 10000;
   uint32_t flags = 0;
   int coarse_leaf = 0;
+  int coarse_top = 0;
+  int t_grid = 0;                                 // workgroups of the T^i launch beside the coarse solve
   double tau = 0.0;
   std::vector<void *> allocs;
+  std::vector<double> alloc_bytes;
   double device_bytes = 0;
 
   DevGeom g{};
@@ -78,6 +84,9 @@ struct bddc_problem {
   int *ccnt = nullptr, *cabort = nullptr;         // dataflow counters and abort word
   int flow_grid = 0, flow_cap = 0;                // resident grid, LDS staging capacity (doubles)
   bool coarse_dataflow = false;                   // one dataflow launch instead of one per level
+  double *Kt = nullptr, *ctt = nullptr;           // dense top block: S_t^{-1} (nt x top_ld), t_t
+  int *tg_off = nullptr, *tg = nullptr;           // gather map of t_t
+  int top_ld = 0;
   double coarse_bytes = 0.0;
   int64_t *d_pk = nullptr, *d_psi_off = nullptr, *d_Xoff = nullptr, *d_gamma_face = nullptr;
 
@@ -88,7 +97,19 @@ struct bddc_problem {
   double *d_src = nullptr, *d_flux = nullptr, *d_pres = nullptr;
   double *alpha_h = nullptr, *beta_h = nullptr;
   CgState *st = nullptr;
-  CgState *st_host = nullptr;
+  CgState *st_host = nullptr;                     // [2] pinned: state after chunk k lands in [k & 1]
+  hipEvent_t ev_state[2] = {nullptr, nullptr};    // recorded after each chunk's state copy
+  // the solve in progress (solve_begin ... solve_finish)
+  struct Run {
+    bool dev = false, eager = false;
+    const double *src = nullptr;
+    double *fl = nullptr, *pr = nullptr;          // device outputs
+    double *flux = nullptr, *pressure = nullptr;  // caller's outputs (host unless dev)
+    int chunks = 0, checked = 0;                  // chunks launched / whose state was read
+    bool stop = false;                            // a chunk reported completion
+    std::chrono::steady_clock::time_point t0;
+  } run;
+  double peak_bytes = 0;                          // high-water mark of device_bytes
   int *d_err = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   hipStream_t side = nullptr;                     // coarse solve of the preconditioner
@@ -103,14 +124,18 @@ struct bddc_problem {
     void *p = nullptr;
     HIPCHK(hipMalloc(&p, (size_t)count * sizeof(T)));
     allocs.push_back(p);
+    alloc_bytes.push_back((double)count * sizeof(T));
     device_bytes += (double)count * sizeof(T);
+    peak_bytes = std::max(peak_bytes, device_bytes);
     return (T *)p;
   }
   void release(void *p) {
-    for (auto &a : allocs)
-      if (a == p) {
-        (void)hipFree(a);
-        a = nullptr;
+    for (size_t k = 0; k < allocs.size(); ++k)
+      if (allocs[k] == p) {
+        (void)hipFree(allocs[k]);
+        allocs[k] = nullptr;
+        device_bytes -= alloc_bytes[k];
+        alloc_bytes[k] = 0.0;
       }
   }
   template <typename T>
@@ -123,6 +148,8 @@ struct bddc_problem {
     for (void *p : allocs)
       if (p) (void)hipFree(p);
     if (st_host) (void)hipHostFree(st_host);
+    for (hipEvent_t e : ev_state)
+      if (e) (void)hipEventDestroy(e);
     if (ev0) (void)hipEventDestroy(ev0);
     if (ev1) (void)hipEventDestroy(ev1);
     if (ev_fork) (void)hipEventDestroy(ev_fork);
@@ -155,10 +182,63 @@ void check_coarse_ptrs(const bddc_problem *h) {
                      h->cy, h->cS0, h->cS1, h->cXB, h->bc, h->csol, h->ccnt, h->cabort};
   for (const void *q : p)
     if (!q) throw Error{BDDC_EDEVICE, "coarse solver arrays not initialised"};
+  if (h->nd.nt > 0 && (!h->Kt || !h->ctt || !h->tg_off || !h->tg || h->top_ld < h->nd.nt))
+    throw Error{BDDC_EDEVICE, "dense top block not initialised"};
 }
 
 void fill(bddc_problem *h, double *x, int64_t n, double v) {
   if (n > 0) k_fill<<<nblk(n), 256, 0, h->stream>>>(n, x, v);
+}
+
+// Dense top block of the coarse solve (nd_dense_top): S_t^{-1} column by
+// column, each column the top part of the sweeps of the top levels applied to
+// a unit right-hand side (the factor of the top levels is that of S_t), for
+// TOP_BATCH columns per pass.  Rounding aside, the dense product then gives
+// what those sweeps give.
+constexpr int TOP_BATCH = 128;
+
+void setup_dense_top(bddc_problem *h, hipStream_t s) {
+  NdPlan &P = h->nd;
+  const int cap = h->coarse_dataflow ? 0 : (h->coarse_top == 0 ? TOP_DEFAULT_DOFS : h->coarse_top);
+  nd_dense_top(P, cap);
+  if (P.nt == 0) return;
+  const int nt = P.nt, d0 = P.lvl_dof[P.top], nfr = P.nfr;
+  if (nt > TOP_MAX_DOFS) throw Error{BDDC_EINVAL, "dense top block too large"};
+  int dev = 0, max_lds = 0;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  h->top_ld = (nt + 1) & ~1;
+  if ((size_t)h->top_ld * sizeof(double) > (size_t)max_lds)
+    throw Error{BDDC_EINVAL, "dense top block exceeds the LDS of one workgroup"};
+  h->Kt = h->alloc<double>((int64_t)nt * h->top_ld);
+  h->ctt = h->alloc<double>(nt);
+  h->tg_off = h->upload(P.tg_off);
+  h->tg = h->upload(P.tg);
+  const int nb = std::min(nt, TOP_BATCH);
+  const int64_t sk = h->nk, sv = P.v_off[nfr], sb = std::max<int64_t>(P.b_off[nfr], 1);
+  const int64_t v0 = P.v_off[P.lvl_off[P.top]], v1 = P.v_off[nfr];
+  double *bb = h->alloc<double>(nb * sk), *zb = h->alloc<double>(nb * sk), *xb = h->alloc<double>(nb * sk);
+  double *S0b = h->alloc<double>(nb * sv), *S1b = h->alloc<double>(nb * sv), *XBb = h->alloc<double>(nb * sb);
+  const unsigned ub = std::min(64u, nblk(std::max<int64_t>(nt, v1 - v0)));
+  for (int j0 = 0; j0 < nt; j0 += nb) {
+    const unsigned nc = (unsigned)std::min(nb, nt - j0);
+    k_top_unit<<<dim3(ub, nc), 256, 0, s>>>(j0, nt, d0, sk, v0, v1, sv, bb, S0b, S1b);
+    for (int lv = P.top; lv < P.H; ++lv) {
+      const int t0 = P.ftask_off[lv], ntk = P.ftask_off[lv + 1] - t0;
+      k_nd_fwd_cols<<<dim3(ntk, nc), 256, 0, s>>>(t0, h->sw, h->FR, bb, S0b, S1b, zb, sk, sv);
+    }
+    for (int lv = P.H - 1; lv >= P.top; --lv) {
+      const int t0 = P.btask_lo[lv], ntk = P.btask_hi[lv] - t0;
+      k_nd_bwd_cols<<<dim3(ntk, nc), 256, 0, s>>>(t0, h->sw, h->BC, zb, h->csgn, XBb, xb, sk, sb);
+    }
+    k_top_store<<<dim3(nblk(h->top_ld), nc), 256, 0, s>>>(j0, nt, d0, h->top_ld, xb, sk, h->Kt);
+    HIPCHK(hipGetLastError());
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  for (double *q : {bb, zb, xb, S0b, S1b, XBb}) h->release(q);
+  // streamed per coarse solve: R of the swept fronts twice, S_t^{-1} once, the gather
+  h->coarse_bytes = 2.0 * 8.0 * (double)P.r_off[P.lvl_off[P.top]] + 8.0 * (double)nt * h->top_ld +
+                    (4.0 + 16.0) * (double)P.tg.size() + 16.0 * nt;
 }
 
 void do_setup(bddc_problem *h, const bddc_grid *gr, const double *perm, const bddc_partition *part) {
@@ -475,6 +555,7 @@ void do_setup(bddc_problem *h, const bddc_grid *gr, const double *perm, const bd
     h->release(Qall);
     // streamed per coarse solve: R twice (rows forward, columns backward)
     h->coarse_bytes = 2.0 * 8.0 * (double)P.r_off[nfr];
+    setup_dense_top(h, s);
   }
 
   const int nGm = L.nGamma;
@@ -501,7 +582,8 @@ void do_setup(bddc_problem *h, const bddc_grid *gr, const double *perm, const bd
   h->alpha_h = h->alloc<double>(h->max_it + 2);
   h->beta_h = h->alloc<double>(h->max_it + 2);
   h->st = h->alloc<CgState>(1);
-  HIPCHK(hipHostMalloc((void **)&h->st_host, sizeof(CgState), hipHostMallocDefault));
+  HIPCHK(hipHostMalloc((void **)&h->st_host, 2 * sizeof(CgState), hipHostMallocDefault));
+  for (hipEvent_t &e : h->ev_state) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   HIPCHK(hipEventCreate(&h->ev0));
   HIPCHK(hipEventCreate(&h->ev1));
   HIPCHK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
@@ -510,13 +592,23 @@ void do_setup(bddc_problem *h, const bddc_grid *gr, const double *perm, const bd
   HIPCHK(hipStreamSynchronize(s));
 
   // statistics of the operators streamed per iteration
-  double sumpk = (double)pks, sumpsi = (double)pss;
+  // entries of the operators as the method defines them: lower triangles of
+  // T^i and S^i, the n_Gamma^i x n_c^i bases Psi^i (storage padding excluded)
+  double sumpk = 0.0, sumpsi = 0.0;
+  for (int i = 0; i < N; ++i) {
+    const double nG = L.nG[i];
+    sumpk += nG * (nG + 1) / 2;
+    sumpsi += nG * (double)(sub_coff[i + 1] - sub_coff[i]);
+  }
   const double sT = h->precision == BDDC_MIXED ? 4.0 : 8.0;
   h->stats.bytes_prec = sumpk * sT + 2.0 * sumpsi * sT + h->coarse_bytes + 6.0 * totG * 8.0 + 4.0 * nGm * 8.0;
   h->stats.bytes_per_iter = h->stats.bytes_prec + sumpk * 8.0 + 2.0 * totG * 8.0 + 8.0 * nGm * 8.0;
 }
 
 // Coarse solve csol = K^{-1} bc by the multifrontal forward / backward sweeps:
+// the levels below the dense top block (all of them without one) sweep one
+// launch per level and direction; the top block is one gather and one dense
+// product with S_t^{-1}.
 // one launch per level and direction, or (BDDC_COARSE_DATAFLOW) one dataflow
 // launch.  Both run the same task bodies and give identical results.  On the
 // reservoir the level launches are faster: a dataflow level still costs about
@@ -532,11 +624,17 @@ void launch_coarse_solve(bddc_problem *h, hipStream_t s, const int *done) {
         h->flow_cap, done);
     return;
   }
-  for (int lv = 0; lv < P.H; ++lv) {
+  for (int lv = 0; lv < P.top; ++lv) {
     const int t0 = P.ftask_off[lv], nt = P.ftask_off[lv + 1] - t0;
     k_nd_fwd<<<nt, 256, 0, s>>>(t0, h->sw, h->FR, h->bc, h->cS0, h->cS1, h->cy, done);
   }
-  for (int lv = P.H - 1; lv >= 0; --lv) {
+  if (P.nt > 0) {
+    const int d0 = P.lvl_dof[P.top];
+    k_top_gather<<<nblk(P.nt), 256, 0, s>>>(P.nt, d0, h->tg_off, h->tg, h->bc, h->cS0, h->cS1, h->ctt, done);
+    k_top_gemv<<<nblk(P.nt, TOP_ROWS_PER_WG), TOP_THREADS, (size_t)h->top_ld * sizeof(double), s>>>(
+        P.nt, h->top_ld, h->Kt, h->ctt, d0, h->sw.xsc_off, h->sw.xsc, h->cXB, h->csol, done);
+  }
+  for (int lv = P.top - 1; lv >= 0; --lv) {
     const int t0 = P.btask_lo[lv], nt = P.btask_hi[lv] - t0;
     k_nd_bwd<<<nt, 256, 0, s>>>(t0, h->sw, h->BC, h->cy, h->csgn, h->cXB, h->csol, done);
   }
@@ -563,37 +661,39 @@ void launch_precond(bddc_problem *h, const double *r, double *z, double *zpart, 
   const double *rp = check ? h->part_r : nullptr;
   const int nrp = (int)nblk(L.nGamma);
   const bool mixed = h->precision == BDDC_MIXED;
-  // Coarse right-hand side pieces Psi^{iT} r^i first (with the stopping test),
-  // then the substructure corrections T^i r^i on the main stream and, forked
-  // behind them, the coarse solve on the side stream; they join before the
-  // coarse basis correction Psi^i alpha.  The long T^i launch is enqueued
-  // first so that it is dispatched at once and the coarse levels fill the
-  // slots it leaves free.
+  // The coarse chain (right-hand side pieces Psi^{iT} r^i with the stopping
+  // test, the coarse solve, the correction Psi^i alpha) is the longest path
+  // and stays on the main stream; the substructure corrections T^i r^i run
+  // beside it on the side stream (t_grid workgroups, which sets how much of
+  // the memory bandwidth they take from the latency-bound coarse sweeps) and
+  // join before the averaging, which adds the two parts.
   if (mixed)
     k_psi_apply<float><<<N, 256, shm, s>>>(h->g, h->Psi32, h->d_psi_off, h->cs.sub_coff, r, 0.5, h->gloc, st, rp, nrp);
   else
     k_psi_apply<double><<<N, 256, shm, s>>>(h->g, h->Psi64, h->d_psi_off, h->cs.sub_coff, r, 0.5, h->gloc, st, rp,
                                             nrp);
-  if (h->nk > 0) HIPCHK(hipEventRecord(h->ev_fork, s));
+  HIPCHK(hipEventRecord(h->ev_fork, s));
+  HIPCHK(hipStreamWaitEvent(h->side, h->ev_fork, 0));
+  const int tg = h->t_grid > 0 ? std::min(h->t_grid, N) : N;
   if (mixed)
-    k_symv<float><<<N, SYMV_THREADS, symv_shm(L), s>>>(h->g, h->T32, h->d_pk, r, 0.5, h->yloc, st, nullptr, 0);
+    k_symv<float><<<tg, SYMV_THREADS, symv_shm(L), h->side>>>(h->g, h->T32, h->d_pk, r, 0.5, h->yloc, st, nullptr, 0);
   else
-    k_symv<double><<<N, SYMV_THREADS, symv_shm(L), s>>>(h->g, h->T64, h->d_pk, r, 0.5, h->yloc, st, nullptr, 0);
+    k_symv<double><<<tg, SYMV_THREADS, symv_shm(L), h->side>>>(h->g, h->T64, h->d_pk, r, 0.5, h->yloc, st, nullptr,
+                                                               0);
+  HIPCHK(hipEventRecord(h->ev_join, h->side));
   // The coarse solve stays FP64 in both forms: the CG runs in the balanced
   // subspace, so the face-average coarse fluxes must satisfy B_c alpha = 0 to
   // FP64 accuracy (the FP32 local operators are corrected by the balance step).
   if (h->nk > 0) {
-    HIPCHK(hipStreamWaitEvent(h->side, h->ev_fork, 0));
-    k_coarse_rhs<<<nblk(h->nk), 256, 0, h->side>>>(h->cs, h->gloc, h->bc, st);
-    launch_coarse_solve(h, h->side, st ? &st->done : nullptr);
-    HIPCHK(hipEventRecord(h->ev_join, h->side));
+    k_coarse_rhs<<<nblk(h->nk), 256, 0, s>>>(h->cs, h->gloc, h->bc, st);
+    launch_coarse_solve(h, s, st ? &st->done : nullptr);
   }
-  if (h->nk > 0) HIPCHK(hipStreamWaitEvent(s, h->ev_join, 0));
   if (mixed)
-    k_psi_correct<float><<<N, 256, 0, s>>>(h->g, h->cs, h->Psi32, h->d_psi_off, h->yloc, h->csol, h->wloc, st);
+    k_psi_correct<float><<<N, 256, 0, s>>>(h->g, h->cs, h->Psi32, h->d_psi_off, nullptr, h->csol, h->wloc, st);
   else
-    k_psi_correct<double><<<N, 256, 0, s>>>(h->g, h->cs, h->Psi64, h->d_psi_off, h->yloc, h->csol, h->wloc, st);
-  if (nF > 0) k_average_balance<<<nF, 256, 0, s>>>(h->g, h->cs, h->wloc, h->csol, z, r, zpart, st);
+    k_psi_correct<double><<<N, 256, 0, s>>>(h->g, h->cs, h->Psi64, h->d_psi_off, nullptr, h->csol, h->wloc, st);
+  HIPCHK(hipStreamWaitEvent(s, h->ev_join, 0));
+  if (nF > 0) k_average_balance<<<nF, 256, 0, s>>>(h->g, h->cs, h->wloc, h->yloc, h->csol, z, r, zpart, st);
 }
 void launch_iteration(bddc_problem *h) {
   const Layout &L = h->L;
@@ -657,42 +757,114 @@ constexpr int CG_CHUNK = 8;   // CG iterations between host convergence checks
 // Capture CG_CHUNK iterations (main and side stream) into a graph.  The
 // capture runs on the handle's own stream; the graph is replayed on whatever
 // stream the handle uses.  Every kernel reads its scalars from the device CG
-// state, so one graph serves every chunk of every solve.
+// state, so one graph serves every chunk of every solve.  The capturing thread
+// only launches kernels and records / waits on events; the capture is relaxed
+// so that other threads (the server's driver) may keep synchronising, copying
+// and freeing meanwhile; the HIP gate keeps such calls out of the capture.
+// A stream capture must not overlap HIP calls of other threads that allocate,
+// free, copy synchronously or synchronise (each has invalidated a capture in
+// flight here).  Captures take this gate exclusively; every other path of the
+// library that calls HIP holds it shared.  Waiting writers stop new readers,
+// so a capture is not starved by a busy server driver.
+class HipGate {
+  std::mutex m_;
+  std::condition_variable cv_;
+  int readers_ = 0, waiting_ = 0;
+  bool writer_ = false;
+
+ public:
+  void lock_shared() {
+    std::unique_lock<std::mutex> lk(m_);
+    cv_.wait(lk, [&] { return !writer_ && waiting_ == 0; });
+    ++readers_;
+  }
+  void unlock_shared() {
+    std::lock_guard<std::mutex> lk(m_);
+    if (--readers_ == 0) cv_.notify_all();
+  }
+  void lock() {
+    std::unique_lock<std::mutex> lk(m_);
+    ++waiting_;
+    cv_.wait(lk, [&] { return !writer_ && readers_ == 0; });
+    --waiting_;
+    writer_ = true;
+  }
+  void unlock() {
+    std::lock_guard<std::mutex> lk(m_);
+    writer_ = false;
+    cv_.notify_all();
+  }
+};
+HipGate g_gate;
+using GateShared = std::shared_lock<HipGate>;
+using GateExclusive = std::unique_lock<HipGate>;
+
 void build_cg_graph(bddc_problem *h) {
+  GateExclusive capture_lock(g_gate);
   hipStream_t keep = h->stream;
   h->stream = h->own_stream;
   hipGraph_t gr = nullptr;
-  hipError_t e = hipStreamBeginCapture(h->own_stream, hipStreamCaptureModeThreadLocal);
+  std::string where = "begin";
+  hipError_t e = hipStreamBeginCapture(h->own_stream, hipStreamCaptureModeRelaxed);
   if (e == hipSuccess) {
     for (int k = 0; k < CG_CHUNK && e == hipSuccess; ++k) {
       try {
         launch_iteration(h);
-      } catch (const Error &) {
+      } catch (const Error &err) {
         e = hipErrorUnknown;
+        where = "iteration " + std::to_string(k) + ": " + err.msg;
       }
-      if (e == hipSuccess) e = hipGetLastError();
+      if (e == hipSuccess) {
+        e = hipGetLastError();
+        if (e != hipSuccess) where = "launch in iteration " + std::to_string(k);
+      }
     }
     const hipError_t e2 = hipStreamEndCapture(h->own_stream, &gr);
-    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) {
+      e = e2;
+      where = "end";
+    }
   }
   h->stream = keep;
-  if (e == hipSuccess) e = hipGraphInstantiate(&h->cg_graph, gr, nullptr, nullptr, 0);
+  if (e == hipSuccess) {
+    e = hipGraphInstantiate(&h->cg_graph, gr, nullptr, nullptr, 0);
+    where = "instantiate";
+  }
   if (gr) (void)hipGraphDestroy(gr);
   if (e != hipSuccess) {
     h->cg_graph = nullptr;
-    throw Error{BDDC_EDEVICE, std::string("capturing the CG iteration graph: ") + hipGetErrorString(e)};
+    throw Error{BDDC_EDEVICE, std::string("capturing the CG iteration graph (") + where +
+                                  "): " + hipGetErrorString(e)};
   }
 }
 
-int do_solve(bddc_problem *h, const double *rhs, double rtol, double *flux, double *pressure, uint32_t flags) {
+// One solve in phases, so that a scheduler can interleave several handles
+// without blocking on any of them:
+//   solve_begin   validates and uploads the source and enqueues steps 1-2, the
+//                 reduced right-hand side, the first preconditioner apply and p_0;
+//   solve_chunk   enqueues CG_CHUNK iterations and an asynchronous copy of the
+//                 CG state (several chunks may be in flight: iterations after
+//                 convergence leave at once);
+//   solve_poll    tells, without blocking, whether the oldest chunk in flight
+//                 has landed and whether the CG has stopped;
+//   solve_finish  waits for the chunks in flight, enqueues the final interface
+//                 flux, the post-correction and the output copies, and waits.
+// bddc_solve runs them back to back with one chunk in flight.
+bool solve_needs_cg(const bddc_problem *h) { return h->L.N > 1; }
+
+void solve_begin_launch(bddc_problem *h, const double *rhs, double rtol, double *flux, double *pressure,
+                        uint32_t flags) {
   const Layout &L = h->L;
   hipStream_t s = h->stream;
   const int N = L.N, nF = L.nF, nGm = L.nGamma;
-  const bool dev = (flags & BDDC_DEVICE_PTRS) != 0;
-  auto t0 = std::chrono::steady_clock::now();
+  auto &R = h->run;
+  R = bddc_problem::Run();
+  R.t0 = std::chrono::steady_clock::now();
+  R.dev = (flags & BDDC_DEVICE_PTRS) != 0;
+  R.eager = (flags & BDDC_EAGER) != 0;
   if (!(rtol > 0.0)) throw Error{BDDC_EINVAL, "rtol must be > 0"};
-  const double *src = rhs;
-  if (!dev) {
+  R.src = rhs;
+  if (!R.dev) {
     double sum = 0.0, asum = 0.0;
     for (int64_t c = 0; c < L.ncells; ++c) {
       if (!isfinite(rhs[c])) throw Error{BDDC_EINVAL, "source must be finite"};
@@ -701,58 +873,110 @@ int do_solve(bddc_problem *h, const double *rhs, double rtol, double *flux, doub
     }
     if (fabs(sum) > 1e-12 * asum) throw Error{BDDC_EINVAL, "source must sum to zero (no-flow compatibility)"};
     HIPCHK(hipMemcpyAsync(h->d_src, rhs, L.ncells * sizeof(double), hipMemcpyHostToDevice, s));
-    src = h->d_src;
+    R.src = h->d_src;
   }
-  double *fl = dev ? flux : h->d_flux;
-  double *pr = dev ? pressure : h->d_pres;
-  const size_t shm = (size_t)5 * ld4(L.maxG) * sizeof(double);
+  R.flux = flux;
+  R.pressure = pressure;
+  R.fl = R.dev ? flux : h->d_flux;
+  R.pr = R.dev ? pressure : h->d_pres;
+  if (!solve_needs_cg(h)) return;
   const int nb = (int)nblk(nGm);
+  const double *src = R.src;
+  // step 1: coarse solve with (0, D F_0), u0 = E Psi alpha
+  fill(h, h->bc, h->nk, 0.0);
+  k_step1_rhs<<<N, 256, 0, s>>>(h->g, h->cs.pidx, src, h->dscale, h->bc);
+  launch_coarse_solve(h, h->stream, nullptr);
+  k_psi_correct<double><<<N, 256, 0, s>>>(h->g, h->cs, h->Psi64, h->d_psi_off, nullptr, h->csol, h->wloc,
+                                          nullptr);
+  k_average_balance<<<nF, 256, 0, s>>>(h->g, h->cs, h->wloc, nullptr, h->csol, h->u0, nullptr, nullptr, nullptr);
+  // steps 2-3 right-hand side: f* = -S u0 + H^T X F
+  k_symv<double><<<N, SYMV_THREADS, symv_shm(L), s>>>(h->g, h->Spk, h->d_pk, h->u0, 1.0, h->yloc, nullptr, nullptr, 0);
+  k_source_term<<<N, 256, (size_t)2 * L.maxC * sizeof(double), s>>>(h->g, h->mcoef, h->Xmat, h->d_Xoff, src,
+                                                                     h->wloc);
+  k_fstar<<<nblk(nGm), 256, 0, s>>>(h->g, h->yloc, h->wloc, h->ru);
+  fill(h, h->xu, nGm, 0.0);
+  fill(h, h->xp, N, 0.0);
+  k_norm2_partial<<<nb, 256, 0, s>>>(nGm, h->ru, h->part_r);
+  launch_precond(h, h->ru, h->zu, h->part_z, false);
+  k_init_p<<<nb, 256, 0, s>>>(nGm, N, h->cs.pidx, h->part_z, nF, h->part_r, nb, h->zu, h->csol, h->pu, h->pp,
+                              h->st, rtol, h->max_it);
+  HIPCHK(hipGetLastError());
+}
 
+void solve_begin(bddc_problem *h, const double *rhs, double rtol, double *flux, double *pressure, uint32_t flags) {
+  {
+    GateShared g(g_gate);
+    solve_begin_launch(h, rhs, rtol, flux, pressure, flags);
+  }
+  if (!solve_needs_cg(h)) return;
+  if (!h->run.eager && !h->cg_graph) build_cg_graph(h);
+  GateShared g(g_gate);
+  HIPCHK(hipEventRecord(h->ev0, h->stream));
+}
+
+void solve_chunk(bddc_problem *h) {
+  GateShared g(g_gate);
+  auto &R = h->run;
+  hipStream_t s = h->stream;
+  if (R.chunks > h->max_it / CG_CHUNK + 2) throw Error{BDDC_EDEVICE, "CG loop did not report completion"};
+  if (R.chunks - R.checked >= 2) throw Error{BDDC_EINVAL, "at most two CG chunks in flight"};
+  if (R.eager) {
+    for (int k = 0; k < CG_CHUNK; ++k) launch_iteration(h);
+  } else {
+    HIPCHK(hipGraphLaunch(h->cg_graph, s));
+  }
+  HIPCHK(hipGetLastError());
+  const int slot = R.chunks & 1;
+  HIPCHK(hipMemcpyAsync(h->st_host + slot, h->st, sizeof(CgState), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipEventRecord(h->ev_state[slot], s));
+  ++R.chunks;
+}
+
+// 1: the oldest chunk in flight has landed (R.stop tells whether the CG has
+// stopped); 0: not yet; throws on a device error.
+int solve_poll(bddc_problem *h, bool wait) {
+  GateShared g(g_gate);
+  auto &R = h->run;
+  if (R.checked >= R.chunks) return 0;
+  const int slot = R.checked & 1;
+  if (wait) {
+    HIPCHK(hipEventSynchronize(h->ev_state[slot]));
+  } else {
+    const hipError_t e = hipEventQuery(h->ev_state[slot]);
+    if (e == hipErrorNotReady) return 0;
+    HIPCHK(e);
+  }
+  if (h->st_host[slot].done) R.stop = true;
+  ++R.checked;
+  return 1;
+}
+
+int solve_finish_locked(bddc_problem *h);
+
+int solve_finish(bddc_problem *h) {
+  auto &R = h->run;
+  while (R.checked < R.chunks) solve_poll(h, true);
+  GateShared g(g_gate);
+  return solve_finish_locked(h);
+}
+
+int solve_finish_locked(bddc_problem *h) {
+  const Layout &L = h->L;
+  hipStream_t s = h->stream;
+  const int N = L.N, nGm = L.nGamma;
+  auto &R = h->run;
   int iters = 0, converged = 1, fail = 0;
   double relres = 0.0;
   float pcg_ms = 0.f;
-  if (N > 1) {
-    // step 1: coarse solve with (0, D F_0), u0 = E Psi alpha
-    fill(h, h->bc, h->nk, 0.0);
-    k_step1_rhs<<<N, 256, 0, s>>>(h->g, h->cs.pidx, src, h->dscale, h->bc);
-    launch_coarse_solve(h, h->stream, nullptr);
-    k_psi_correct<double><<<N, 256, 0, s>>>(h->g, h->cs, h->Psi64, h->d_psi_off, nullptr, h->csol, h->wloc,
-                                            nullptr);
-    k_average_balance<<<nF, 256, 0, s>>>(h->g, h->cs, h->wloc, h->csol, h->u0, nullptr, nullptr, nullptr);
-    // steps 2-3 right-hand side: f* = -S u0 + H^T X F
-    k_symv<double><<<N, SYMV_THREADS, symv_shm(L), s>>>(h->g, h->Spk, h->d_pk, h->u0, 1.0, h->yloc, nullptr, nullptr, 0);
-    k_source_term<<<N, 256, (size_t)2 * L.maxC * sizeof(double), s>>>(h->g, h->mcoef, h->Xmat, h->d_Xoff, src,
-                                                                       h->wloc);
-    k_fstar<<<nblk(nGm), 256, 0, s>>>(h->g, h->yloc, h->wloc, h->ru);
-    fill(h, h->xu, nGm, 0.0);
-    fill(h, h->xp, N, 0.0);
-    k_norm2_partial<<<nb, 256, 0, s>>>(nGm, h->ru, h->part_r);
-    launch_precond(h, h->ru, h->zu, h->part_z, false);
-    k_init_p<<<nb, 256, 0, s>>>(nGm, N, h->cs.pidx, h->part_z, nF, h->part_r, nb, h->zu, h->csol, h->pu, h->pp,
-                                h->st, rtol, h->max_it);
-    HIPCHK(hipGetLastError());
-    const bool eager = (flags & BDDC_EAGER) != 0;
-    if (!eager && !h->cg_graph) build_cg_graph(h);
-    HIPCHK(hipEventRecord(h->ev0, s));
-    for (int rounds = 0;; ++rounds) {
-      if (rounds > h->max_it / CG_CHUNK + 2) throw Error{BDDC_EDEVICE, "CG loop did not report completion"};
-      if (eager) {
-        for (int k = 0; k < CG_CHUNK; ++k) launch_iteration(h);
-      } else {
-        HIPCHK(hipGraphLaunch(h->cg_graph, s));
-      }
-      HIPCHK(hipGetLastError());
-      HIPCHK(hipMemcpyAsync(h->st_host, h->st, sizeof(CgState), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipStreamSynchronize(s));
-      if (h->st_host->done) break;
-    }
+  if (solve_needs_cg(h)) {
+    const CgState &fs = h->st_host[(R.chunks - 1) & 1];
     HIPCHK(hipEventRecord(h->ev1, s));
     HIPCHK(hipEventSynchronize(h->ev1));
     HIPCHK(hipEventElapsedTime(&pcg_ms, h->ev0, h->ev1));
-    iters = h->st_host->nupd;
-    converged = h->st_host->converged;
-    fail = h->st_host->fail;
-    relres = h->st_host->relres;
+    iters = fs.nupd;
+    converged = fs.converged;
+    fail = fs.fail;
+    relres = fs.relres;
     // Lanczos estimate from the CG coefficients
     std::vector<double> a(iters), b(iters > 0 ? iters - 1 : 0);
     if (iters > 0) HIPCHK(hipMemcpy(a.data(), h->alpha_h, iters * sizeof(double), hipMemcpyDeviceToHost));
@@ -765,17 +989,18 @@ int do_solve(bddc_problem *h, const double *rhs, double rtol, double *flux, doub
     k_axpby<<<nblk(nGm), 256, 0, s>>>(nGm, 1.0, h->u0, 1.0, h->xu, h->uG);
   }
   // post-correction: interior fluxes and pressures
+  double *fl = R.fl, *pr = R.pr;
   fill(h, fl, L.nfaces_all, 0.0);
   if (nGm > 0) k_scatter_iface<<<nblk(nGm), 256, 0, s>>>(nGm, h->d_gamma_face, h->uG, fl);
   if (N == 1) fill(h, h->xp, 1, 0.0);
   k_recover<<<N, 256, (size_t)(L.maxG + 2 * L.maxC) * sizeof(double), s>>>(h->g, h->mcoef, h->Xmat, h->d_Xoff,
-                                                                            src, h->uG, h->xp, h->dscale, fl, pr);
+                                                                            R.src, h->uG, h->xp, h->dscale, fl, pr);
   k_sum_partial<<<256, 256, 0, s>>>(L.ncells, pr, h->part_p);
   k_sub_mean<<<256, 256, 0, s>>>(L.ncells, pr, h->part_p, 256);
   HIPCHK(hipGetLastError());
-  if (!dev) {
-    HIPCHK(hipMemcpyAsync(flux, fl, L.nfaces_all * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(pressure, pr, L.ncells * sizeof(double), hipMemcpyDeviceToHost, s));
+  if (!R.dev) {
+    HIPCHK(hipMemcpyAsync(R.flux, fl, L.nfaces_all * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(R.pressure, pr, L.ncells * sizeof(double), hipMemcpyDeviceToHost, s));
   }
   HIPCHK(hipStreamSynchronize(s));
   check_flow(h);
@@ -784,10 +1009,54 @@ int do_solve(bddc_problem *h, const double *rhs, double rtol, double *flux, doub
   h->stats.relres = relres;
   h->stats.t_pcg_ms = pcg_ms;
   h->stats.t_solve_ms =
-      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - R.t0).count();
   if (fail) throw Error{BDDC_EBREAKDOWN, "CG breakdown (p^T S p <= 0 or not finite)"};
   if (!converged) return BDDC_ENOCONV;
   return BDDC_OK;
+}
+
+int do_solve(bddc_problem *h, const double *rhs, double rtol, double *flux, double *pressure, uint32_t flags) {
+  solve_begin(h, rhs, rtol, flux, pressure, flags);
+  if (solve_needs_cg(h)) {
+    do {
+      solve_chunk(h);
+      solve_poll(h, true);
+    } while (!h->run.stop);
+  }
+  return solve_finish(h);
+}
+
+void apply_options(bddc_problem *h, const bddc_options *opt) {
+  if (opt) {
+    h->precision = opt->precision;
+    if (opt->max_it > 0) h->max_it = opt->max_it;
+    h->flags = opt->flags;
+    h->coarse_leaf = opt->coarse_leaf;
+    h->coarse_top = opt->coarse_top;
+    h->t_grid = opt->t_workgroups;
+    h->coarse_dataflow = (opt->flags & BDDC_COARSE_DATAFLOW) != 0;
+  }
+  if (h->coarse_top > TOP_MAX_DOFS) throw Error{BDDC_EINVAL, "coarse_top above 8192"};
+  if (h->precision != BDDC_FP64 && h->precision != BDDC_MIXED) throw Error{BDDC_EINVAL, "bad precision"};
+}
+
+bddc_problem *make_problem(const bddc_grid *g, const double *perm, const bddc_partition *part, double tau,
+                           const bddc_options *opt) {
+  GateShared gate(g_gate);
+  auto t0 = std::chrono::steady_clock::now();
+  bddc_problem *h = new bddc_problem();
+  try {
+    apply_options(h, opt);
+    h->tau = tau;
+    HIPCHK(hipStreamCreateWithFlags(&h->own_stream, hipStreamNonBlocking));
+    h->stream = h->own_stream;
+    do_setup(h, g, perm, part);
+  } catch (...) {
+    delete h;
+    throw;
+  }
+  h->stats.t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return h;
 }
 
 template <typename F>
@@ -818,27 +1087,7 @@ int bddc_setup(const bddc_grid *g, const double *perm, const bddc_partition *par
   return guarded([&]() -> int {
     if (!g || !perm || !part || !out) throw Error{BDDC_EINVAL, "null argument"};
     *out = nullptr;
-    auto t0 = std::chrono::steady_clock::now();
-    bddc_problem *h = new bddc_problem();
-    try {
-      if (opt) {
-        h->precision = opt->precision;
-        if (opt->max_it > 0) h->max_it = opt->max_it;
-        h->flags = opt->flags;
-        h->coarse_leaf = opt->coarse_leaf;
-        h->coarse_dataflow = (opt->flags & BDDC_COARSE_DATAFLOW) != 0;
-      }
-      if (h->precision != BDDC_FP64 && h->precision != BDDC_MIXED) throw Error{BDDC_EINVAL, "bad precision"};
-      h->tau = tau;
-      HIPCHK(hipStreamCreateWithFlags(&h->own_stream, hipStreamNonBlocking));
-      h->stream = h->own_stream;
-      do_setup(h, g, perm, part);
-    } catch (...) {
-      delete h;
-      throw;
-    }
-    h->stats.t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-    *out = h;
+    *out = make_problem(g, perm, part, tau, opt);
     return BDDC_OK;
   });
 }
@@ -866,6 +1115,7 @@ int bddc_stats(bddc_handle h, bddc_stats_t *out) {
     s.precision = h->precision;
     s.coarse_levels = h->nd.H;
     s.coarse_fronts = h->nd.nfr;
+    s.coarse_dense = h->nd.nt;
     s.device_bytes = h->device_bytes;
     *out = s;
     return BDDC_OK;
@@ -875,6 +1125,7 @@ int bddc_stats(bddc_handle h, bddc_stats_t *out) {
 int bddc_set_stream(bddc_handle h, void *stream) {
   return guarded([&]() -> int {
     if (!h) throw Error{BDDC_EINVAL, "null handle"};
+    GateShared g(g_gate);
     HIPCHK(hipStreamSynchronize(h->stream));
     h->stream = stream ? (hipStream_t)stream : h->own_stream;
     return BDDC_OK;
@@ -884,6 +1135,7 @@ int bddc_set_stream(bddc_handle h, void *stream) {
 int bddc_destroy(bddc_handle h) {
   return guarded([&]() -> int {
     if (h) {
+      GateShared g(g_gate);
       (void)hipStreamSynchronize(h->stream);
       delete h;
     }
@@ -912,6 +1164,7 @@ int64_t bddc_export(bddc_handle h, int32_t what, int32_t index, void *dst, int64
   int64_t count = 0;
   const int rc = guarded([&]() -> int {
     if (!h || !dst) throw Error{BDDC_EINVAL, "null argument"};
+    GateShared g(g_gate);
     const Layout &L = h->L;
     switch (what) {
       case BDDC_X_SCHUR: {
@@ -1033,6 +1286,7 @@ int64_t bddc_export(bddc_handle h, int32_t what, int32_t index, void *dst, int64
 int bddc_apply(bddc_handle h, int32_t which, const double *x_u, const double *x_p, double *y_u, double *y_p) {
   return guarded([&]() -> int {
     if (!h || !x_u || !y_u || !y_p) throw Error{BDDC_EINVAL, "null argument"};
+    GateShared g(g_gate);
     const Layout &L = h->L;
     hipStream_t s = h->stream;
     const int N = L.N, nGm = L.nGamma;
@@ -1067,6 +1321,7 @@ int bddc_apply(bddc_handle h, int32_t which, const double *x_u, const double *x_
 int bddc_time_kernel(bddc_handle h, int32_t which, int32_t reps, double *avg_ms, double *bytes) {
   return guarded([&]() -> int {
     if (!h || !avg_ms || !bytes || reps <= 0) throw Error{BDDC_EINVAL, "bad argument"};
+    GateShared g(g_gate);
     const Layout &L = h->L;
     hipStream_t s = h->stream;
     const int N = L.N;
@@ -1078,7 +1333,9 @@ int bddc_time_kernel(bddc_handle h, int32_t which, int32_t reps, double *avg_ms,
     const double sT = h->precision == BDDC_MIXED ? 4.0 : 8.0;
     double b = 0.0;
     auto launch = [&]() {
-      if (which == BDDC_K_SCHUR_APPLY)
+      if (which == BDDC_K_PRECOND_FULL)
+        launch_precond(h, h->ru, h->zu, nullptr, false);
+      else if (which == BDDC_K_SCHUR_APPLY)
         k_symv<double><<<N, SYMV_THREADS, symv_shm(L), s>>>(h->g, h->Spk, h->d_pk, h->pu, 1.0, h->yloc, nullptr, nullptr, 0);
       else if (h->precision == BDDC_MIXED)
         k_symv<float><<<N, SYMV_THREADS, symv_shm(L), s>>>(h->g, h->T32, h->d_pk, h->ru, 0.5, h->yloc, nullptr, nullptr, 0);
@@ -1090,6 +1347,8 @@ int bddc_time_kernel(bddc_handle h, int32_t which, int32_t reps, double *avg_ms,
       b = pk * 8.0 + totG * (4.0 + 8.0) + totG * 8.0;
     else if (which == BDDC_K_PRECOND_APPLY)
       b = pk * sT + totG * (4.0 + 8.0) + totG * 8.0;
+    else if (which == BDDC_K_PRECOND_FULL)
+      b = h->stats.bytes_prec;
     else
       throw Error{BDDC_EINVAL, "unknown kernel"};
     launch();
@@ -1107,3 +1366,5 @@ int bddc_time_kernel(bddc_handle h, int32_t which, int32_t reps, double *avg_ms,
 }
 
 }  // extern "C"
+
+#include "server.hpp"

@@ -276,6 +276,131 @@ __global__ __launch_bounds__(256) void k_nd_bwd(int t0, DevSweep sw, const doubl
   bwd_task<false>(td[0], td[1], td[2], sw, BC, z, sg, XB, x, nullptr, 0);
 }
 
+// ---- dense top block (nd_dense_top) ---------------------------------------------
+// t_t[j] = b[d0 + j] plus the updates the lower fronts pushed into the top
+// fronts' vectors for that dof.
+__global__ __launch_bounds__(256) void k_top_gather(int nt, int d0, const int *__restrict__ tg_off,
+                                                    const int *__restrict__ tg, const double *__restrict__ b,
+                                                    const double *__restrict__ S0, const double *__restrict__ S1,
+                                                    double *__restrict__ tt, const int *done) {
+  if (done && *done) return;
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= nt) return;
+  double v = b[d0 + j];
+  for (int q = tg_off[j]; q < tg_off[j + 1]; ++q) {
+    const int p = tg[q];
+    v += S0[p] + S1[p];
+  }
+  tt[j] = v;
+}
+
+// x_t = S_t^{-1} t_t for the rows [8 blockIdx.x, 8 blockIdx.x + 8): t_t is
+// staged in LDS (ld doubles, zero padded), each wave forms two rows of the
+// row-major inverse (leading dimension ld, even, so rows are 16-byte aligned)
+// with 16-byte loads.  Each x[d] is also stored into every B vector holding d,
+// for the backward sweep of the levels below.
+constexpr int TOP_THREADS = 256;
+constexpr int TOP_ROWS_PER_WG = 8;
+constexpr int TOP_DEFAULT_DOFS = 4096;   // 128 MB of FP64 inverse at most
+constexpr int TOP_MAX_DOFS = 8192;       // t_t in 64 KB of LDS
+
+__global__ __launch_bounds__(TOP_THREADS) void k_top_gemv(int nt, int ld, const double *__restrict__ Kt,
+                                                          const double *__restrict__ tt, int d0,
+                                                          const int *__restrict__ xsc_off,
+                                                          const int *__restrict__ xsc, double *__restrict__ XB,
+                                                          double *__restrict__ x, const int *done) {
+  if (done && *done) return;
+  extern __shared__ double tl[];
+  for (int j = threadIdx.x; j < ld; j += TOP_THREADS) tl[j] = j < nt ? tt[j] : 0.0;
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int r0 = blockIdx.x * TOP_ROWS_PER_WG + 2 * (threadIdx.x >> 6);
+  if (r0 >= nt) return;
+  const bool two = r0 + 1 < nt;
+  const int ld2 = ld >> 1;
+  const double2 *A0 = reinterpret_cast<const double2 *>(Kt + (int64_t)r0 * ld);
+  const double2 *A1 = two ? A0 + ld2 : A0;
+  const double2 *T = reinterpret_cast<const double2 *>(tl);
+  double a0 = 0.0, c0 = 0.0, a1 = 0.0, c1 = 0.0;
+  int k = lane;
+  for (; k + 192 < ld2; k += 256) {
+    double2 u[4], v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      u[q] = A0[k + 64 * q];
+      v[q] = A1[k + 64 * q];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const double2 t = T[k + 64 * q];
+      a0 = fma(u[q].x, t.x, a0);
+      c0 = fma(u[q].y, t.y, c0);
+      a1 = fma(v[q].x, t.x, a1);
+      c1 = fma(v[q].y, t.y, c1);
+    }
+  }
+  for (; k < ld2; k += 64) {
+    const double2 u = A0[k], v = A1[k], t = T[k];
+    a0 = fma(u.x, t.x, a0);
+    c0 = fma(u.y, t.y, c0);
+    a1 = fma(v.x, t.x, a1);
+    c1 = fma(v.y, t.y, c1);
+  }
+  const double s0 = group_sum<64>(a0 + c0), s1 = group_sum<64>(a1 + c1);
+  const int d = d0 + r0;
+  if (lane == 0) {
+    x[d] = s0;
+    if (two) x[d + 1] = s1;
+  }
+  for (int q = xsc_off[d] + lane; q < xsc_off[d + 1]; q += 64) XB[xsc[q]] = s0;
+  if (two)
+    for (int q = xsc_off[d + 1] + lane; q < xsc_off[d + 2]; q += 64) XB[xsc[q]] = s1;
+}
+
+// Setup of S_t^{-1}, gridDim.y columns [j0, j0 + gridDim.y) at a time: each
+// column c has its own copies of the sweep vectors (strides sk for dof
+// vectors, sv for front vectors, sb for B vectors), its top right-hand side
+// is the unit vector of dof j0 + c and the top fronts' vectors [v0, v1) start
+// cleared; the sweeps of the top levels then leave column j0 + c of S_t^{-1}
+// in the top part of x.
+__global__ __launch_bounds__(256) void k_top_unit(int j0, int nt, int d0, int64_t sk, int64_t v0, int64_t v1,
+                                                  int64_t sv, double *__restrict__ b, double *__restrict__ S0,
+                                                  double *__restrict__ S1) {
+  const int64_t c = blockIdx.y;
+  const int64_t len = std::max<int64_t>(nt, v1 - v0);
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < len; i += (int64_t)gridDim.x * 256) {
+    if (i < nt) b[c * sk + d0 + i] = (i == j0 + c) ? 1.0 : 0.0;
+    if (i < v1 - v0) {
+      S0[c * sv + v0 + i] = 0.0;
+      S1[c * sv + v0 + i] = 0.0;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_nd_fwd_cols(int t0, DevSweep sw, const double *__restrict__ FR,
+                                                     const double *__restrict__ b, double *S0, double *S1,
+                                                     double *__restrict__ z, int64_t sk, int64_t sv) {
+  const int4 *td = sw.task + 4 * (int64_t)(t0 + blockIdx.x);
+  const int64_t c = blockIdx.y;
+  fwd_task<false>(td[0], td[1], td[2], sw, FR, b + c * sk, S0 + c * sv, S1 + c * sv, z + c * sk, nullptr, 0);
+}
+
+__global__ __launch_bounds__(256) void k_nd_bwd_cols(int t0, DevSweep sw, const double *__restrict__ BC,
+                                                     const double *__restrict__ z, const double *__restrict__ sg,
+                                                     double *XB, double *__restrict__ x, int64_t sk, int64_t sb) {
+  const int4 *td = sw.task + 4 * (int64_t)(t0 + blockIdx.x);
+  const int64_t c = blockIdx.y;
+  bwd_task<false>(td[0], td[1], td[2], sw, BC, z + c * sk, sg, XB + c * sb, x + c * sk, nullptr, 0);
+}
+
+__global__ __launch_bounds__(256) void k_top_store(int j0, int nt, int d0, int ld, const double *__restrict__ x,
+                                                   int64_t sk, double *__restrict__ Kt) {
+  const int64_t c = blockIdx.y;
+  const double *xc = x + c * sk + d0;
+  double *row = Kt + (int64_t)(j0 + c) * ld;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < ld; i += gridDim.x * 256) row[i] = i < nt ? xc[i] : 0.0;
+}
+
 // ---- dataflow sweep ------------------------------------------------------------
 // One launch runs the whole coarse solve.  A resident grid walks the task list
 // (forward tasks leaves-up, then backward tasks root-down) in index order,

@@ -64,6 +64,13 @@ struct NdPlan {
   int ntask = 0;
   std::vector<int> ftask_off;       // [H+1] forward tasks of level h
   std::vector<int> btask_lo, btask_hi;  // [H] backward tasks of level h
+  // dense top block (nd_dense_top): levels [top, H) are solved with the
+  // explicit inverse of their Schur complement; their nt dofs are the last
+  // ones, [lvl_dof[top], nk).  tg lists, for every top dof, the positions of
+  // the top fronts' work vectors (own part and B part) that hold updates of it.
+  int top = 0;                      // H: no dense block
+  int nt = 0;
+  std::vector<int> tg_off, tg;      // [nt+1], positions
 };
 
 // `leaf`: largest number of subdomains in a leaf box (>= 1).
@@ -389,7 +396,46 @@ inline void nd_plan(const Layout &L, const std::vector<int> &face_k, int leaf, N
     P.btask_hi[h] = (int)P.task.size() / 16;
   }
   P.ntask = (int)P.task.size() / 16;
+  P.top = H;
+  P.tg_off.assign(1, 0);
   if (nv > INT32_MAX) throw std::length_error("coarse plan: front vectors too long");
+}
+
+// Dense top block.  After the forward sweep of the levels below `top`, the
+// dofs of levels top.. H-1 satisfy S_t x_t = t_t, where S_t is the Schur
+// complement of the coarse matrix on them and t_t[d] is the right-hand side at
+// d plus every update the lower fronts pushed into the top fronts' vectors for
+// d (own rows of d's front, B rows of the top fronts below it).  S_t^{-1} is
+// formed at setup; a solve then needs one gather and one dense product in
+// place of the 2 (H - top) sweep launches of those levels.  `top` is the
+// lowest level at which the top block holds at most max_dofs dofs; max_dofs
+// <= 0 leaves the plan without a dense block.
+inline void nd_dense_top(NdPlan &P, int max_dofs) {
+  P.top = P.H;
+  P.nt = 0;
+  P.tg_off.assign(1, 0);
+  P.tg.clear();
+  if (max_dofs <= 0 || P.nk == 0) return;
+  int top = P.H;
+  while (top > 0 && P.nk - P.lvl_dof[top - 1] <= max_dofs) --top;
+  if (top == P.H) return;
+  const int d0 = P.lvl_dof[top];
+  P.top = top;
+  P.nt = P.nk - d0;
+  std::vector<std::vector<int>> pos(P.nt);
+  for (int r = P.lvl_off[top]; r < P.nfr; ++r) {
+    for (int k = 0; k < P.n[r]; ++k) pos[P.first[r] + k - d0].push_back((int)P.v_off[r] + k);
+    for (int k = 0; k < P.m[r]; ++k) {
+      const int v = P.bidx[P.b_off[r] + k];
+      if (v < d0) throw std::logic_error("coarse plan: top front couples below the top block");
+      pos[v - d0].push_back((int)(P.v_off[r] + P.n[r] + k));
+    }
+  }
+  P.tg_off.assign(P.nt + 1, 0);
+  for (int j = 0; j < P.nt; ++j) {
+    P.tg_off[j + 1] = P.tg_off[j] + (int)pos[j].size();
+    P.tg.insert(P.tg.end(), pos[j].begin(), pos[j].end());
+  }
 }
 
 }  // namespace bddc

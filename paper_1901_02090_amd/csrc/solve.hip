@@ -151,55 +151,59 @@ __global__ __launch_bounds__(SYMV_THREADS) void k_symv(DevGeom g, const TS *__re
   __shared__ double red[SYMV_WAVES];
   if (cg_exit(st, rpart, nrpart, red)) return;
   constexpr int VW = 16 / sizeof(TS);
-  const int i = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int n = g.nG[i];
-  const int G4 = (n + 3) / 4, np = 4 * G4;
-  const int64_t go = g.g_off[i];
-  double *xs = sh;
-  double *yw = sh + np;
-  for (int r = tid; r < np; r += SYMV_THREADS) xs[r] = (r < n) ? xscale * x[g.Rmap[go + r]] : 0.0;
-  for (int e = tid; e < SYMV_WAVES * np; e += SYMV_THREADS) yw[e] = 0.0;
-  __syncthreads();
-  const TS *Mi = M + pk[i];
-  double *yme = yw + wv * np;
-  // A wave takes one column group (four columns, common first row rs) at a
-  // time: each lane loads VW consecutive rows of all four columns with 16-byte
-  // loads, folds the strictly-lower products into one LDS update per row, and
-  // the four transposed dot products are reduced together.
-  for (int gi = wv; gi < G4; gi += SYMV_WAVES) {
-    const int rs = 4 * gi;
-    const int L = 4 * (G4 - gi);
-    const TS *base = Mi + gp_group(n, gi);
-    double xj[4];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  // subdomains blockIdx.x, blockIdx.x + gridDim.x, ... (one each with a full grid)
+  for (int i = blockIdx.x; i < g.N; i += gridDim.x) {
+    const int n = g.nG[i];
+    const int G4 = (n + 3) / 4, np = 4 * G4;
+    const int64_t go = g.g_off[i];
+    double *xs = sh;
+    double *yw = sh + np;
+    for (int r = tid; r < np; r += SYMV_THREADS) xs[r] = (r < n) ? xscale * x[g.Rmap[go + r]] : 0.0;
+    for (int e = tid; e < SYMV_WAVES * np; e += SYMV_THREADS) yw[e] = 0.0;
+    __syncthreads();
+    const TS *Mi = M + pk[i];
+    double *yme = yw + wv * np;
+    // A wave takes one column group (four columns, common first row rs) at a
+    // time: each lane loads VW consecutive rows of all four columns with 16-byte
+    // loads, folds the strictly-lower products into one LDS update per row, and
+    // the four transposed dot products are reduced together.
+    for (int gi = wv; gi < G4; gi += SYMV_WAVES) {
+      const int rs = 4 * gi;
+      const int L = 4 * (G4 - gi);
+      const TS *base = Mi + gp_group(n, gi);
+      double xj[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) xj[q] = xs[rs + q];
-    double d[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int t = lane * VW; t < L; t += 64 * VW) {
-      double a[4][VW];
+      for (int q = 0; q < 4; ++q) xj[q] = xs[rs + q];
+      double d[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int t = lane * VW; t < L; t += 64 * VW) {
+        double a[4][VW];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) load16(base + (int64_t)q * L + t, a[q]);
+        for (int q = 0; q < 4; ++q) load16(base + (int64_t)q * L + t, a[q]);
 #pragma unroll
-      for (int v = 0; v < VW; ++v) {
-        const int r = rs + t + v;
-        const double xr = xs[r];
-        double acc = 0.0;
+        for (int v = 0; v < VW; ++v) {
+          const int r = rs + t + v;
+          const double xr = xs[r];
+          double acc = 0.0;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          d[q] = fma(a[q][v], xr, d[q]);
-          if (r > rs + q) acc = fma(a[q][v], xj[q], acc);
+          for (int q = 0; q < 4; ++q) {
+            d[q] = fma(a[q][v], xr, d[q]);
+            if (r > rs + q) acc = fma(a[q][v], xj[q], acc);
+          }
+          yme[r] += acc;
         }
-        yme[r] += acc;
       }
+      const double tot = transpose_reduce4(d, lane);
+      if ((lane & 15) == 0) yme[rs + (lane >> 4)] += tot;
     }
-    const double tot = transpose_reduce4(d, lane);
-    if ((lane & 15) == 0) yme[rs + (lane >> 4)] += tot;
-  }
-  __syncthreads();
-  for (int r = tid; r < n; r += SYMV_THREADS) {
-    double y = 0.0;
+    __syncthreads();
+    for (int r = tid; r < n; r += SYMV_THREADS) {
+      double y = 0.0;
 #pragma unroll
-    for (int w = 0; w < SYMV_WAVES; ++w) y += yw[w * np + r];
-    yloc[go + r] = y;
+      for (int w = 0; w < SYMV_WAVES; ++w) y += yw[w * np + r];
+      yloc[go + r] = y;
+    }
+    __syncthreads();   // LDS is reused by the next subdomain
   }
 }
 
@@ -318,7 +322,7 @@ __global__ void k_coarse_rhs(DevCoarse cs, const double *__restrict__ gloc, doub
   }
 }
 
-// w^i = y^i + Psi^i alpha^(i)  (y may be null).  Each lane owns 16-byte row
+// w^i = y^i + Psi^i alpha^(i)  (y may be null: w^i = Psi^i alpha^(i)).  Each lane owns 16-byte row
 // chunks of the ld4-padded columns (VW rows), the four waves split the
 // columns, and the partial sums meet in LDS; a lane keeps a dozen independent
 // 16-byte loads in flight.
@@ -368,12 +372,17 @@ __global__ __launch_bounds__(256) void k_psi_correct(DevGeom g, DevCoarse cs, co
   }
 }
 
-// z = E w (weights 1/2), then each face total is set to the face's
-// zero-net-flux coarse dof (a no-op in exact arithmetic, since C^i T^i = 0 and
-// C^i Psi^i = I; it keeps the output balanced to rounding).  One block per
-// face; optional partial of r . z.
+// z = E w (weights 1/2) with w = y + wloc (y may be null: w = wloc), then
+// each face total is set to the face's zero-net-flux coarse dof (a no-op in
+// exact arithmetic, since C^i T^i = 0 and C^i Psi^i = I; it keeps the output
+// balanced to rounding).  One block per face; optional partial of r . z.
+__device__ __forceinline__ double wsum(const double *__restrict__ y, const double *__restrict__ wloc, int64_t k) {
+  return y ? y[k] + wloc[k] : wloc[k];
+}
+
 __global__ __launch_bounds__(256) void k_average_balance(DevGeom g, DevCoarse cs,
                                                          const double *__restrict__ wloc,
+                                                         const double *__restrict__ yloc,
                                                          const double *__restrict__ csol, double *__restrict__ z,
                                                          const double *__restrict__ r, double *part,
                                                          const CgState *st) {
@@ -385,7 +394,7 @@ __global__ __launch_bounds__(256) void k_average_balance(DevGeom g, DevCoarse cs
   double tsum = 0.0;
   for (int a = threadIdx.x; a < n; a += 256) {
     const int gi = g.Rmap[base + a];
-    tsum += 0.5 * (wloc[base + a] + wloc[g.own_plus[gi]]);
+    tsum += 0.5 * (wsum(yloc, wloc, base + a) + wsum(yloc, wloc, g.own_plus[gi]));
   }
   tsum = wave_sum(tsum);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = tsum;
@@ -396,7 +405,7 @@ __global__ __launch_bounds__(256) void k_average_balance(DevGeom g, DevCoarse cs
   double v = 0.0;
   for (int a = threadIdx.x; a < n; a += 256) {
     const int gi = g.Rmap[base + a];
-    const double zz = 0.5 * (wloc[base + a] + wloc[g.own_plus[gi]]) + corr;
+    const double zz = 0.5 * (wsum(yloc, wloc, base + a) + wsum(yloc, wloc, g.own_plus[gi])) + corr;
     z[gi] = zz;
     if (r) v += r[gi] * zz;
   }

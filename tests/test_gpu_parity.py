@@ -257,21 +257,8 @@ def test_device_pointer_solve_matches_host_solve():
     s.close()
 
 
-@pytest.mark.parametrize("leaf", [1, 2, 6, 132])
-def test_coarse_leaf_sizes_agree(leaf):
-    """The multifrontal coarse factorization gives the same solve for any dissection depth.
-
-    leaf = 132 keeps the whole 6 x 22 subdomain grid as one dense front.
-    """
-    Solver = _gpu()
-    pr = W.layer_60x220(0, tau=10.0)
-    s = Solver(pr.n, pr.h, pr.perm, pr.cuts, tau=10.0, coarse_leaf=leaf)
-    st = s.stats()
-    if leaf == 132:
-        assert st["coarse_levels"] == 1 and st["coarse_fronts"] == 1
-    else:
-        assert st["coarse_levels"] > 1
-    o = _oracle(pr, 10.0)
+def _coarse_case(s, pr, o):
+    """Preconditioner apply and solve of one handle against the oracle."""
     rng = np.random.default_rng(2)
     xu = rng.standard_normal(o.subs.n_gamma)
     zu, zp = s.apply_precond(xu)
@@ -285,7 +272,63 @@ def test_coarse_leaf_sizes_agree(leaf):
     assert s.stats()["it"] == ref["it"]
     assert _relerr(u, ref["u"]) <= 1e-8
     assert _relerr(p, ref["p"]) <= 1e-8
+    return zu, zp, u, p
+
+
+@pytest.mark.parametrize("leaf", [1, 2, 6, 132])
+def test_coarse_leaf_sizes_agree(leaf):
+    """The multifrontal coarse factorization gives the same solve for any dissection depth.
+
+    leaf = 132 keeps the whole 6 x 22 subdomain grid as one dense front.  All
+    levels are swept (no dense top block).
+    """
+    Solver = _gpu()
+    pr = W.layer_60x220(0, tau=10.0)
+    s = Solver(pr.n, pr.h, pr.perm, pr.cuts, tau=10.0, coarse_leaf=leaf, coarse_top=-1)
+    st = s.stats()
+    assert st["coarse_dense"] == 0
+    if leaf == 132:
+        assert st["coarse_levels"] == 1 and st["coarse_fronts"] == 1
+    else:
+        assert st["coarse_levels"] > 1
+    _coarse_case(s, pr, _oracle(pr, 10.0))
     s.close()
+
+
+@pytest.mark.parametrize("top", [40, 300, 0])
+def test_coarse_dense_top_block_agrees(top):
+    """The dense top block (explicit inverse of the top levels' Schur complement)
+    matches the oracle and the all-sweeps solver to rounding.
+
+    top = 40 puts only the root front in the block, 300 several levels; the
+    default (0, up to 4096 dofs) holds the whole coarse problem of this layer.
+    """
+    Solver = _gpu()
+    pr = W.layer_60x220(0, tau=10.0)
+    o = _oracle(pr, 10.0)
+    s_sw = Solver(pr.n, pr.h, pr.perm, pr.cuts, tau=10.0, coarse_top=-1)
+    s = Solver(pr.n, pr.h, pr.perm, pr.cuts, tau=10.0, coarse_top=top)
+    st = s.stats()
+    nk = st["n_coarse"] - 1
+    if top == 0:
+        assert st["coarse_dense"] == nk
+    else:
+        assert st["coarse_dense"] <= top < nk
+        if top == 300:
+            assert st["coarse_dense"] > 0
+    zu, zp, u, p = _coarse_case(s, pr, o)
+    rng = np.random.default_rng(2)
+    zs, ps = s_sw.apply_precond(rng.standard_normal(o.subs.n_gamma))
+    assert _relerr(zu, zs) <= 1e-12
+    assert _relerr(zp, ps) <= 1e-12
+    us, qs = s_sw.solve(pr.source, rtol=1e-8)
+    assert s.stats()["it"] == s_sw.stats()["it"]
+    assert _relerr(u, us) <= 1e-10 and _relerr(p, qs) <= 1e-10
+    # the whole-preconditioner timing covers the dense block too
+    ms, by = s.time_kernel(3, reps=5)
+    assert ms > 0 and by == s.stats()["bytes_prec"]
+    s.close()
+    s_sw.close()
 
 
 def test_cube_homogeneous_table5_row():
@@ -350,8 +393,9 @@ def test_coarse_dataflow_matches_level_sweeps(precision):
     Solver = _gpu()
     pr = W.layer_60x220(0, tau=10.0)
     s_flow = Solver(pr.n, pr.h, pr.perm, pr.cuts, tau=10.0, precision=precision, coarse_dataflow=True)
-    s_lvl = Solver(pr.n, pr.h, pr.perm, pr.cuts, tau=10.0, precision=precision)
+    s_lvl = Solver(pr.n, pr.h, pr.perm, pr.cuts, tau=10.0, precision=precision, coarse_top=-1)
     assert s_flow.stats()["coarse_fronts"] == s_lvl.stats()["coarse_fronts"] > 1
+    assert s_flow.stats()["coarse_dense"] == 0
     rng = np.random.default_rng(11)
     xu = rng.standard_normal(s_flow.n_gamma)
     zf, pf = s_flow.apply_precond(xu)

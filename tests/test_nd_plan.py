@@ -9,7 +9,10 @@ kernels (front assembly, extend-add, partial signed Cholesky, packed R storage,
 push-form forward / backward sweeps).  The result must equal a dense solve, the
 pivot signs must be +1 on face dofs and -1 on pressures, every packed entry and
 every sweep row / column must be produced exactly once, and every B-vector
-entry must be filled before it is read.
+entry must be filled before it is read.  With a dense top block the levels
+below it are swept, the top right-hand side is gathered through the plan's
+map, and the top dofs are solved with the Schur complement of the coarse matrix
+on them (formed here from the dense matrix, independently of the factor).
 """
 import os
 import shutil
@@ -33,11 +36,16 @@ def dumper(tmp_path_factory):
     return exe
 
 
-SCALARS = ("N", "nF", "H", "nfr", "nk")
+SCALARS = ("N", "nF", "H", "nfr", "nk", "top", "nt")
 
 
-def load(exe, args):
-    out = subprocess.run([exe] + [str(a) for a in args], capture_output=True, text=True, check=True).stdout
+def load(exe, args, top=None):
+    env = dict(os.environ)
+    env.pop("ND_TOP", None)
+    if top is not None:
+        env["ND_TOP"] = str(top)
+    out = subprocess.run([exe] + [str(a) for a in args], capture_output=True, text=True, check=True,
+                         env=env).stdout
     d = {}
     for line in out.splitlines():
         t = line.split()
@@ -195,10 +203,13 @@ def check_tasks(P):
             assert d[12] == want and d[14] == -1
 
 
-def sweep(P, FR, BC, sg, b):
+def sweep(P, FR, BC, sg, b, K=None):
     """k_nd_flow serialised: the task list in index order (also what the
-    level-by-level kernels compute)."""
+    level-by-level kernels compute).  With a dense top block (P["top"] < H)
+    the tasks of the top levels are replaced by the gather of t_t and a dense
+    solve with the Schur complement of K on the top dofs."""
     nfr, nk, H = P["nfr"], P["nk"], P["H"]
+    top = P["top"]
     nv = P["v_off"][nfr]
     S = [np.zeros(nv), np.zeros(nv)]
     written = np.zeros((2, nv), bool)
@@ -210,8 +221,39 @@ def sweep(P, FR, BC, sg, b):
     for h in range(H):
         lvl[P["lvl_off"][h]:P["lvl_off"][h + 1]] = h
     done_f, done_b = set(), set()
+    topped = False
+
+    def top_solve():
+        d0 = P["lvl_dof"][top]
+        nt = nk - d0
+        assert P["nt"] == nt and len(P["tg_off"]) == nt + 1
+        tg = P["tg"]
+        v0 = P["v_off"][P["lvl_off"][top]]
+        # every position of the top fronts' vectors feeds exactly one top dof
+        assert np.array_equal(np.sort(tg), np.arange(v0, P["v_off"][nfr]))
+        tt = np.array([b[d0 + j] + sum(S[0][q] + S[1][q] for q in tg[P["tg_off"][j]:P["tg_off"][j + 1]])
+                       for j in range(nt)])
+        bot = np.arange(d0)
+        St = K[d0:, d0:] - K[d0:, :d0] @ np.linalg.solve(K[:d0, :d0], K[:d0, d0:]) if d0 else K.copy()
+        xt = np.linalg.solve(St, tt)
+        for jj in range(nt):
+            dd = d0 + jj
+            x[dd] = xt[jj]
+            done_b.add(dd)
+            for k in range(P["xsc_off"][dd], P["xsc_off"][dd + 1]):
+                XB[P["xsc"][k]] = xt[jj]
+        del bot
+
     for d in T:
         p, j, g, n, m, fst, vo, bo, rlo, rhi, slot, kind = (int(v) for v in d[:12])
+        if lvl[p] >= top:
+            if kind == 1 and not topped:
+                top_solve()
+                topped = True
+            continue
+        if kind == 1 and not topped and top < H:
+            top_solve()
+            topped = True
         ro = (rhi & 0xffffffff) << 32 | (rlo & 0xffffffff)
         assert (n, m, fst, vo, bo, ro) == (P["n"][p], P["m"][p], P["first"][p], P["v_off"][p], P["b_off"][p],
                                            P["r_off"][p])
@@ -250,7 +292,10 @@ def sweep(P, FR, BC, sg, b):
                     owner = int(np.searchsorted(P["b_off"], q, side="right")) - 1
                     assert lvl[owner] < lvl[p], "scatter into a front of the same or a higher level"
                     XB[q] = val
-    assert len(done_f) == int(sum(P["n"]) + sum(P["m"])) and len(done_b) == nk
+    if top < H and not topped:
+        top_solve()
+    swept = slice(0, P["lvl_off"][top])
+    assert len(done_f) == int(sum(P["n"][swept]) + sum(P["m"][swept])) and len(done_b) == nk
     return x
 
 
@@ -265,9 +310,17 @@ CASES = [
 ]
 
 
+@pytest.mark.parametrize("top", [None, 40, 150, 100000], ids=["sweeps", "top40", "top150", "alldense"])
 @pytest.mark.parametrize("args", CASES, ids=lambda a: "x".join(map(str, a[4:7])) + f"_leaf{a[7]}")
-def test_plan_factor_and_sweeps_match_dense_solve(dumper, args):
-    P = load(dumper, args)
+def test_plan_factor_and_sweeps_match_dense_solve(dumper, args, top):
+    P = load(dumper, args, top)
+    if top is None:
+        assert P["top"] == P["H"] and P["nt"] == 0
+    else:
+        # the top block: the lowest level whose dofs and all above fit the cap
+        d0 = P["lvl_dof"][P["top"]]
+        assert P["nk"] - d0 <= top
+        assert P["top"] == 0 or P["nk"] - P["lvl_dof"][P["top"] - 1] > top
     rng = np.random.default_rng(args[-1])
     # numbering covers every coarse dof once, pinned pressure excluded
     fk, cof, pidx = P["face_k"], P["face_cofs"], P["pidx"]
@@ -286,7 +339,7 @@ def test_plan_factor_and_sweeps_match_dense_solve(dumper, args):
     K, Ac, cmap, sub_coff, dsc, sg = coarse_matrix(P, rng)
     FR, BC = factor(P, Ac, cmap, sub_coff, dsc, sg)
     b = rng.standard_normal(P["nk"])
-    x = sweep(P, FR, BC, sg, b)
+    x = sweep(P, FR, BC, sg, b, K)
     ref = np.linalg.solve(K, b)
     assert np.linalg.norm(x - ref) / np.linalg.norm(ref) < 1e-10
 

@@ -253,3 +253,64 @@ def homogeneous(n, h, cuts, source=None):
     perm = np.ones((ncell, len(n)))
     src = corner_pair(n) if source is None else source
     return Problem("homogeneous", tuple(n), tuple(h), perm, src, cuts, tau=math.inf, rtol=1e-6)
+
+
+# ----------------------------------------------------------------------------
+# serving requests
+# ----------------------------------------------------------------------------
+
+def seeded_wells(n, rng, n_prod=None):
+    """One injector and 1..4 producers at seeded cells (columns in 3D), zero total."""
+    ncell = int(np.prod(n))
+    f = np.zeros(ncell)
+    nz = n[2] if len(n) == 3 else 1
+    if n_prod is None:
+        n_prod = int(rng.integers(1, 5))
+    inj = (int(rng.integers(0, n[0])), int(rng.integers(0, n[1])))
+    prods = []
+    while len(prods) < n_prod:
+        c = (int(rng.integers(0, n[0])), int(rng.integers(0, n[1])))
+        if c != inj and c not in prods:
+            prods.append(c)
+    for iz in range(nz):
+        tail = (iz,) if len(n) == 3 else ()
+        f[_cell(n, inj + tail)] += 1.0 / nz
+        for c in prods:
+            f[_cell(n, c + tail)] -= 1.0 / (n_prod * nz)
+    return f
+
+
+def serving_request(seed):
+    """One request of the serving stream: its own grid, field, wells and tau.
+
+    2D: n_x in [32, 60], n_y in [32, 220] cells of 20 x 10 ft, one channelised
+    layer, boxes of about 8 cells when the grid is 32 x 32 and about 10 cells
+    otherwise.  3D (one request in four): a 60 x 220 x {5, 17, 34} slab of the
+    layered channel field with 20 x 10 x 2 ft cells, 10 x 10 boxes in plane and
+    about 5 layers per box.  tau is off or 10 with equal odds; rtol 1e-8.
+    """
+    rng = np.random.default_rng(5000 + seed)
+    tau = math.inf if rng.random() < 0.5 else 10.0
+    if rng.random() < 0.25:
+        nz = int(rng.choice([5, 17, 34]))
+        pr = reservoir_3d(nz=nz, seed=7000 + seed, tau=tau, sub=(10, 10, 5))
+        nzs = max(1, round(nz / 5))
+        cuts = split_cuts(pr.n, (6, 22, nzs))
+        src = seeded_wells(pr.n, rng)
+        return Problem(f"serve{seed}_3d{nz}", pr.n, pr.h, pr.perm, src, cuts, tau=tau, rtol=1e-8)
+    nx = int(rng.integers(32, 61))
+    ny = int(rng.integers(32, 221))
+    n, h = (nx, ny), (20.0, 10.0)
+    lnk = channel_layer(nx, ny, rng, n_channels=max(1, nx // 10))
+    k = clip_k(lnk).reshape(-1, order="F")
+    perm = np.stack([k, k], axis=1)
+    box = 8 if (nx, ny) == (32, 32) else 10
+    cuts = split_cuts(n, (max(1, round(nx / box)), max(1, round(ny / box))))
+    src = seeded_wells(n, rng)
+    return Problem(f"serve{seed}_2d{nx}x{ny}", n, h, perm, src, cuts, tau=tau, rtol=1e-8)
+
+
+def poisson_arrivals(rate, count, seed):
+    """Arrival times (s) of a Poisson stream with the given mean rate."""
+    rng = np.random.default_rng(9000 + seed)
+    return np.cumsum(rng.exponential(1.0 / rate, size=count))
