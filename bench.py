@@ -11,6 +11,7 @@ Prints one JSON line.  ``value`` is solves per second of the mixed form (FP32
 local operators inside the FP64 CG); the FP64 form is reported beside it.
 """
 import argparse
+import faulthandler
 import json
 import math
 import os
@@ -184,6 +185,48 @@ def measured_traffic(kernel):
     return None
 
 
+SERVE_DESC = ("Poisson stream (mean 50 requests/s, seeded) of independent solves: each request its own "
+              "2D grid (32..60 x 32..220 cells) or 3D 60x220x{5,17,34} slab, own channelised field and seeded "
+              "wells, tau off or 10, rtol 1e-8; setup and solve per request")
+
+
+def serve_stream(precision, requests, arrivals, max_active=4, setup_workers=2):
+    """Submit `requests` at their arrival times (s from start) and wait for all."""
+    from paper_1901_02090_amd import Server
+    srv = Server(precision=precision, max_active=max_active, setup_workers=setup_workers)
+    try:
+        tickets = []
+        t0 = time.perf_counter()
+        for pr, ta in zip(requests, arrivals):
+            dt = ta - (time.perf_counter() - t0)
+            if dt > 0:
+                time.sleep(dt)
+            tickets.append(srv.submit(pr.n, pr.h, pr.perm, pr.cuts, pr.source, tau=pr.tau, rtol=pr.rtol))
+        its, conv = [], 0
+        for t in tickets:
+            _, _, st = srv.result(t)
+            its.append(st["it"])
+            conv += st["converged"]
+        wall = time.perf_counter() - t0
+        ss = srv.stats()
+    finally:
+        srv.close()
+    return {"solves_per_s": ss["solves_per_s"], "p50_ms": ss["p50_ms"], "p99_ms": ss["p99_ms"],
+            "completed": ss["completed"], "converged": conv, "wall_s": wall, "peak_active": ss["peak_active"],
+            "peak_bytes": ss["peak_bytes"], "mean_iterations": float(np.mean(its))}
+
+
+def serving(n_req, rate=50.0, seed=0):
+    import workloads as W
+    reqs = [W.serving_request(seed * 100000 + k) for k in range(n_req)]
+    arr = W.poisson_arrivals(rate, n_req, seed)
+    out = {"workload": SERVE_DESC, "requests": n_req, "arrival_rate_per_s": rate, "max_active": 4,
+           "setup_workers": 2, "dims": {"2d": sum(r.dim == 2 for r in reqs), "3d": sum(r.dim == 3 for r in reqs)}}
+    for prec in ("fp64", "mixed"):
+        out[prec] = serve_stream(prec, reqs, arr)
+    return out
+
+
 def copy_rate(reps=20):
     """Device-to-device copy of COPY_BYTES, timed with events: GB/s moved (read + write)."""
     import torch
@@ -227,6 +270,7 @@ def kernels_only(pr, reps):
 
 
 def main():
+    faulthandler.enable()
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
@@ -234,6 +278,9 @@ def main():
     ap.add_argument("--workload", default="reservoir", choices=["reservoir", "layer", "square"])
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=0,
+                    help="requests of a served Poisson stream (mean 50/s) through bddc_server_* in both forms "
+                         "(default 0: not run)")
     ap.add_argument("--kernels-only", action="store_true",
                     help="set up the mixed form, launch the S^i and T^i apply kernels alone and a plain "
                          "device copy of known size (for scaling hardware byte counters), then exit")
@@ -307,6 +354,8 @@ def main():
         "roofline": roof,
         "precond_apply": prec,
     }
+    if args.serve_requests > 0:
+        out["serving"] = serving(args.serve_requests)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pr, args.cpu_seconds, st["it"])
     print(json.dumps(out), flush=True)

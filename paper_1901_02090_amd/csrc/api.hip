@@ -144,19 +144,23 @@ struct bddc_problem {
     if (!v.empty()) HIPCHK(hipMemcpy(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
     return d;
   }
+  // The graph goes first (its nodes name the events and streams below), the
+  // streams are drained before anything they use is released.
   ~bddc_problem() {
-    for (void *p : allocs)
-      if (p) (void)hipFree(p);
-    if (st_host) (void)hipHostFree(st_host);
+    if (cg_graph) (void)hipGraphExecDestroy(cg_graph);
+    if (side) (void)hipStreamSynchronize(side);
+    if (own_stream) (void)hipStreamSynchronize(own_stream);
     for (hipEvent_t e : ev_state)
       if (e) (void)hipEventDestroy(e);
     if (ev0) (void)hipEventDestroy(ev0);
     if (ev1) (void)hipEventDestroy(ev1);
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
-    if (cg_graph) (void)hipGraphExecDestroy(cg_graph);
     if (side) (void)hipStreamDestroy(side);
     if (own_stream) (void)hipStreamDestroy(own_stream);
+    if (st_host) (void)hipHostFree(st_host);
+    for (void *p : allocs)
+      if (p) (void)hipFree(p);
   }
 };
 
