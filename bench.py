@@ -161,21 +161,24 @@ def cpu_baseline(pr, seconds, gpu_iters):
 COPY_BYTES = 1 << 30
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "symv_reservoir_60x220x85_hbm_traffic.md")
 KERNEL_SOURCES = ("paper_1901_02090_amd/csrc/solve.hip", "paper_1901_02090_amd/csrc/common.hpp")
+PREC_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "precond_apply_reservoir_60x220x85_hbm_traffic.md")
+PREC_SOURCES = ("paper_1901_02090_amd/csrc/solve.hip", "paper_1901_02090_amd/csrc/coarse.hip",
+                "paper_1901_02090_amd/csrc/common.hpp", "paper_1901_02090_amd/csrc/nd.hpp")
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed counter summary.
+def measured_traffic(kernel, path=TRAFFIC_FILE, sources=KERNEL_SOURCES):
+    """HBM bytes per launch of `kernel` from a committed counter summary.
 
     Returns None when there is no entry or when the kernel sources changed
     since the counters were taken (their sha256 is stored beside the figure).
     """
     import hashlib
     try:
-        text = open(TRAFFIC_FILE).read()
+        text = open(path).read()
     except OSError:
         return None
     h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
+    for p in sources:
         with open(os.path.join(ROOT, p), "rb") as f:
             h.update(f.read())
     for line in text.splitlines():
@@ -253,10 +256,12 @@ def kernels_only(pr, reps):
     """
     import torch
     from paper_1901_02090_amd import Solver
-    from paper_1901_02090_amd.bddc import K_SCHUR_APPLY, K_PRECOND_APPLY
+    from paper_1901_02090_amd.bddc import K_SCHUR_APPLY, K_PRECOND_APPLY, K_PRECOND_FULL
     s = Solver(pr.n, pr.h, pr.perm, pr.cuts, tau=pr.tau, precision="mixed", max_it=5000)
+    s.solve(pr.source, rtol=pr.rtol)
     ms_s, by_s = s.time_kernel(K_SCHUR_APPLY, reps)
     ms_t, by_t = s.time_kernel(K_PRECOND_APPLY, reps)
+    ms_p, by_p = s.time_kernel(K_PRECOND_FULL, reps)
     a = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device="cuda").fill_(1.0)
     c = torch.empty_like(a)
     torch.cuda.synchronize()
@@ -266,6 +271,7 @@ def kernels_only(pr, reps):
     s.close()
     print(json.dumps({"schur_apply": {"avg_ms": ms_s, "bytes": by_s},
                       "precond_apply": {"avg_ms": ms_t, "bytes": by_t},
+                      "precond_full": {"avg_ms": ms_p, "bytes": by_p},
                       "copy_bytes": COPY_BYTES, "reps": reps}), flush=True)
 
 
@@ -282,8 +288,9 @@ def main():
                     help="requests of a served Poisson stream (mean 50/s) through bddc_server_* in both forms "
                          "(default 0: not run)")
     ap.add_argument("--kernels-only", action="store_true",
-                    help="set up the mixed form, launch the S^i and T^i apply kernels alone and a plain "
-                         "device copy of known size (for scaling hardware byte counters), then exit")
+                    help="set up the mixed form, solve once, launch the S^i and T^i apply kernels alone, the "
+                         "whole preconditioner, and a plain device copy of known size (for scaling hardware "
+                         "byte counters), then exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("this benchmark runs on exactly one GPU: the solver is a single-GPU build "
@@ -317,8 +324,9 @@ def main():
     cp = copy_rate()
     ach_p = by_p / (ms_p * 1e-3) / 1e9
     prec = {"avg_us": ms_p * 1e3, "bytes": by_p, "achieved_gbs": ach_p, "frac_of_peak": ach_p / HBM_PEAK_GBS,
-            "copy_gbs": cp, "frac_of_copy": ach_p / cp, "coarse_levels": st["coarse_levels"],
-            "coarse_dense_dofs": st["coarse_dense"]}
+            "copy_gbs": cp, "frac_of_copy": ach_p / cp,
+            "traffic": measured_traffic("precond_full", PREC_TRAFFIC_FILE, PREC_SOURCES),
+            "coarse_levels": st["coarse_levels"], "coarse_dense_dofs": st["coarse_dense"]}
     lat = rmx["lat"] * 1e3
     value = args.steps / rmx["total_s"]
     ref_u, ref_p = r64["flux"], r64["pres"]
