@@ -19,6 +19,7 @@
 #include "common.hpp"
 #include "layout.hpp"
 #include "nd.hpp"
+#include "gate.hpp"
 #include "setup.hip"
 #include "solve.hip"
 #include "coarse.hip"
@@ -765,43 +766,7 @@ constexpr int CG_CHUNK = 8;   // CG iterations between host convergence checks
 // only launches kernels and records / waits on events; the capture is relaxed
 // so that other threads (the server's driver) may keep synchronising, copying
 // and freeing meanwhile; the HIP gate keeps such calls out of the capture.
-// A stream capture must not overlap HIP calls of other threads that allocate,
-// free, copy synchronously or synchronise (each has invalidated a capture in
-// flight here).  Captures take this gate exclusively; every other path of the
-// library that calls HIP holds it shared.  Waiting writers stop new readers,
-// so a capture is not starved by a busy server driver.
-class HipGate {
-  std::mutex m_;
-  std::condition_variable cv_;
-  int readers_ = 0, waiting_ = 0;
-  bool writer_ = false;
 
- public:
-  void lock_shared() {
-    std::unique_lock<std::mutex> lk(m_);
-    cv_.wait(lk, [&] { return !writer_ && waiting_ == 0; });
-    ++readers_;
-  }
-  void unlock_shared() {
-    std::lock_guard<std::mutex> lk(m_);
-    if (--readers_ == 0) cv_.notify_all();
-  }
-  void lock() {
-    std::unique_lock<std::mutex> lk(m_);
-    ++waiting_;
-    cv_.wait(lk, [&] { return !writer_ && readers_ == 0; });
-    --waiting_;
-    writer_ = true;
-  }
-  void unlock() {
-    std::lock_guard<std::mutex> lk(m_);
-    writer_ = false;
-    cv_.notify_all();
-  }
-};
-HipGate g_gate;
-using GateShared = std::shared_lock<HipGate>;
-using GateExclusive = std::unique_lock<HipGate>;
 
 void build_cg_graph(bddc_problem *h) {
   GateExclusive capture_lock(g_gate);

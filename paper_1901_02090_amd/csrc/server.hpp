@@ -117,6 +117,10 @@ double ms_between(sclock::time_point a, sclock::time_point b) {
   return std::chrono::duration<double, std::milli>(b - a).count();
 }
 
+}  // namespace
+
+namespace bddc {
+
 struct SrvRequest {
   uint64_t id = 0;
   bddc_grid grid{};
@@ -143,7 +147,7 @@ struct SrvRequest {
   }
 };
 
-}  // namespace
+}  // namespace bddc
 
 struct bddc_server {
   bddc_server_options opt{};
