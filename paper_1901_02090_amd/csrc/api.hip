@@ -44,6 +44,10 @@ struct Error {
   } while (0)
 
 inline unsigned nblk(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
+// blocks of the kernels that leave dot-product partials: interface vectors
+// (256 entries per block and round) and faces (four per block and round)
+inline int vec_blocks(int64_t n) { return (int)std::min<int64_t>(nblk(n), PART_BLOCKS); }
+inline int face_blocks(int64_t nF) { return (int)std::min<int64_t>(nblk(nF, 4), PART_BLOCKS); }
 
 }  // namespace
 
@@ -664,7 +668,7 @@ void launch_precond(bddc_problem *h, const double *r, double *z, double *zpart, 
   const size_t shm = (size_t)5 * ld4(L.maxG) * sizeof(double);
   CgState *st = check ? h->st : nullptr;
   const double *rp = check ? h->part_r : nullptr;
-  const int nrp = (int)nblk(L.nGamma);
+  const int nrp = vec_blocks(L.nGamma);
   const bool mixed = h->precision == BDDC_MIXED;
   // The coarse chain (right-hand side pieces Psi^{iT} r^i with the stopping
   // test, the coarse solve, the correction Psi^i alpha) is the longest path
@@ -698,20 +702,22 @@ void launch_precond(bddc_problem *h, const double *r, double *z, double *zpart, 
   else
     k_psi_correct<double><<<N, 256, 0, s>>>(h->g, h->cs, h->Psi64, h->d_psi_off, nullptr, h->csol, h->wloc, st);
   HIPCHK(hipStreamWaitEvent(s, h->ev_join, 0));
-  if (nF > 0) k_average_balance<<<nF, 256, 0, s>>>(h->g, h->cs, h->wloc, h->yloc, h->csol, z, r, zpart, st);
+  if (nF > 0)
+    k_average_balance<<<face_blocks(nF), 256, 0, s>>>(h->g, h->cs, h->wloc, h->yloc, h->csol, z, r, zpart, st);
 }
 void launch_iteration(bddc_problem *h) {
   const Layout &L = h->L;
   hipStream_t s = h->stream;
   const int N = L.N, nGm = L.nGamma;
   const size_t shm = (size_t)5 * ld4(L.maxG) * sizeof(double);
-  const int nb = (int)nblk(nGm);
+  const int nb = vec_blocks(nGm);
   k_symv<double><<<N, SYMV_THREADS, symv_shm(L), s>>>(h->g, h->Spk, h->d_pk, h->pu, 1.0, h->yloc, h->st, nullptr, 0);
   k_sys_assemble<<<nb, 256, 0, s>>>(h->g, h->yloc, h->pp, h->dscale, h->pu, h->qu, h->part_g, h->st);
   k_update_xr<<<nb, 256, 0, s>>>(nGm, N, h->part_g, nb, h->pu, h->qu, h->pp, h->xu, h->ru, h->xp, h->part_r,
                                  h->st, h->alpha_h);
   launch_precond(h, h->ru, h->zu, h->part_z, true);
-  k_update_p<<<nb, 256, 0, s>>>(nGm, N, h->cs.pidx, h->part_z, L.nF, h->zu, h->csol, h->pu, h->pp, h->st, h->beta_h);
+  k_update_p<<<nb, 256, 0, s>>>(nGm, N, h->cs.pidx, h->part_z, face_blocks(L.nF), h->zu, h->csol, h->pu, h->pp,
+                                h->st, h->beta_h);
   k_advance<<<1, 1, 0, s>>>(h->st);
 }
 
@@ -857,7 +863,8 @@ void solve_begin_launch(bddc_problem *h, const double *rhs, double rtol, double 
   launch_coarse_solve(h, h->stream, nullptr);
   k_psi_correct<double><<<N, 256, 0, s>>>(h->g, h->cs, h->Psi64, h->d_psi_off, nullptr, h->csol, h->wloc,
                                           nullptr);
-  k_average_balance<<<nF, 256, 0, s>>>(h->g, h->cs, h->wloc, nullptr, h->csol, h->u0, nullptr, nullptr, nullptr);
+  k_average_balance<<<face_blocks(nF), 256, 0, s>>>(h->g, h->cs, h->wloc, nullptr, h->csol, h->u0, nullptr, nullptr,
+                                                    nullptr);
   // steps 2-3 right-hand side: f* = -S u0 + H^T X F
   k_symv<double><<<N, SYMV_THREADS, symv_shm(L), s>>>(h->g, h->Spk, h->d_pk, h->u0, 1.0, h->yloc, nullptr, nullptr, 0);
   k_source_term<<<N, 256, (size_t)2 * L.maxC * sizeof(double), s>>>(h->g, h->mcoef, h->Xmat, h->d_Xoff, src,
@@ -865,9 +872,10 @@ void solve_begin_launch(bddc_problem *h, const double *rhs, double rtol, double 
   k_fstar<<<nblk(nGm), 256, 0, s>>>(h->g, h->yloc, h->wloc, h->ru);
   fill(h, h->xu, nGm, 0.0);
   fill(h, h->xp, N, 0.0);
-  k_norm2_partial<<<nb, 256, 0, s>>>(nGm, h->ru, h->part_r);
+  k_norm2_partial<<<vec_blocks(nGm), 256, 0, s>>>(nGm, h->ru, h->part_r);
   launch_precond(h, h->ru, h->zu, h->part_z, false);
-  k_init_p<<<nb, 256, 0, s>>>(nGm, N, h->cs.pidx, h->part_z, nF, h->part_r, nb, h->zu, h->csol, h->pu, h->pp,
+  k_init_p<<<nb, 256, 0, s>>>(nGm, N, h->cs.pidx, h->part_z, face_blocks(nF), h->part_r, vec_blocks(nGm), h->zu,
+                              h->csol, h->pu, h->pp,
                               h->st, rtol, h->max_it);
   HIPCHK(hipGetLastError());
 }

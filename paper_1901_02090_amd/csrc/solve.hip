@@ -60,6 +60,11 @@ __device__ __forceinline__ double block_sum_partials(const double *__restrict__ 
   return t;
 }
 
+// Kernels that leave one partial per block for a dot product run on at most
+// PART_BLOCKS blocks (grid-stride loops), so that every block of the kernel
+// that needs the total can add the partials up cheaply.
+constexpr int PART_BLOCKS = 512;
+
 __device__ __forceinline__ void block_write_partial(double v, double *part, double *red) {
   v = wave_sum(v);
   const int w = threadIdx.x >> 6;
@@ -262,15 +267,14 @@ __global__ __launch_bounds__(256) void k_sys_assemble(DevGeom g, const double *_
                                                       double *part, CgState *st) {
   __shared__ double red[8];
   if (st && st->done) return;
-  const int gi = blockIdx.x * 256 + threadIdx.x;
   double v = 0.0;
-  if (gi < g.nGamma) {
+  for (int gi = blockIdx.x * 256 + threadIdx.x; gi < g.nGamma; gi += gridDim.x * 256) {
     const int sm = g.sub_minus[gi], sp = g.sub_plus[gi];
     double b0 = 0.0;
     if (xp) b0 = -dscale[sm] * xp[sm] + dscale[sp] * xp[sp];
     const double qq = yloc[g.own_minus[gi]] + yloc[g.own_plus[gi]] + b0;
     q[gi] = qq;
-    if (pu) v = pu[gi] * qq;
+    if (pu) v = fma(pu[gi], qq, v);
   }
   if (part) block_write_partial(v, part, red);
 }
@@ -292,13 +296,12 @@ __global__ __launch_bounds__(256) void k_update_xr(int nGamma, int N, const doub
     return;
   }
   const double alpha = st->rho / gam;
-  const int gi = blockIdx.x * 256 + threadIdx.x;
   double v = 0.0;
-  if (gi < nGamma) {
+  for (int gi = blockIdx.x * 256 + threadIdx.x; gi < nGamma; gi += gridDim.x * 256) {
     xu[gi] = fma(alpha, pu[gi], xu[gi]);
     const double r = fma(-alpha, q[gi], ru[gi]);
     ru[gi] = r;
-    v = r * r;
+    v = fma(r, r, v);
   }
   if (blockIdx.x == 0) {
     for (int k = threadIdx.x; k < N; k += 256) xp[k] = fma(alpha, pp[k], xp[k]);
@@ -388,26 +391,24 @@ __global__ __launch_bounds__(256) void k_average_balance(DevGeom g, DevCoarse cs
                                                          const CgState *st) {
   __shared__ double red[8];
   if (st && st->done) return;
-  const int f = blockIdx.x;
-  const int n = g.f_n[f];
-  const int64_t base = g.g_off[g.f_minus[f]] + g.f_loffm[f];
-  double tsum = 0.0;
-  for (int a = threadIdx.x; a < n; a += 256) {
-    const int gi = g.Rmap[base + a];
-    tsum += 0.5 * (wsum(yloc, wloc, base + a) + wsum(yloc, wloc, g.own_plus[gi]));
-  }
-  tsum = wave_sum(tsum);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = tsum;
-  __syncthreads();
-  const double tot = red[0] + red[1] + red[2] + red[3];
-  __syncthreads();
-  const double corr = (csol[cs.face_cofs[f]] - tot) / n;
+  const int lane = threadIdx.x & 63;
   double v = 0.0;
-  for (int a = threadIdx.x; a < n; a += 256) {
-    const int gi = g.Rmap[base + a];
-    const double zz = 0.5 * (wsum(yloc, wloc, base + a) + wsum(yloc, wloc, g.own_plus[gi])) + corr;
-    z[gi] = zz;
-    if (r) v += r[gi] * zz;
+  // one face per wave: faces 4 blockIdx.x + wave, then strided by the grid
+  for (int f = blockIdx.x * 4 + (threadIdx.x >> 6); f < g.nF; f += gridDim.x * 4) {
+    const int n = g.f_n[f];
+    const int64_t base = g.g_off[g.f_minus[f]] + g.f_loffm[f];
+    double tsum = 0.0;
+    for (int a = lane; a < n; a += 64) {
+      const int gi = g.Rmap[base + a];
+      tsum += 0.5 * (wsum(yloc, wloc, base + a) + wsum(yloc, wloc, g.own_plus[gi]));
+    }
+    const double corr = (csol[cs.face_cofs[f]] - wave_sum(tsum)) / n;
+    for (int a = lane; a < n; a += 64) {
+      const int gi = g.Rmap[base + a];
+      const double zz = 0.5 * (wsum(yloc, wloc, base + a) + wsum(yloc, wloc, g.own_plus[gi])) + corr;
+      z[gi] = zz;
+      if (r) v = fma(r[gi], zz, v);
+    }
   }
   if (part) block_write_partial(v, part, red);
 }
@@ -421,8 +422,8 @@ __global__ __launch_bounds__(256) void k_update_p(int nGamma, int N, const int *
   if (st->done) return;
   const double rn = block_sum_partials(zpart, nzpart, red);
   const double beta = rn / st->rho;
-  const int gi = blockIdx.x * 256 + threadIdx.x;
-  if (gi < nGamma) pu[gi] = fma(beta, pu[gi], zu[gi]);
+  for (int gi = blockIdx.x * 256 + threadIdx.x; gi < nGamma; gi += gridDim.x * 256)
+    pu[gi] = fma(beta, pu[gi], zu[gi]);
   if (blockIdx.x == 0) {
     for (int k = threadIdx.x; k < N; k += 256) {
       const double zp = (pidx[k] >= 0) ? csol[pidx[k]] : 0.0;
@@ -473,8 +474,8 @@ __global__ __launch_bounds__(256) void k_init_p(int nGamma, int N, const int *__
 // partial of x.x over a vector
 __global__ __launch_bounds__(256) void k_norm2_partial(int n, const double *__restrict__ x, double *part) {
   __shared__ double red[8];
-  const int k = blockIdx.x * 256 + threadIdx.x;
-  const double v = (k < n) ? x[k] * x[k] : 0.0;
+  double v = 0.0;
+  for (int k = blockIdx.x * 256 + threadIdx.x; k < n; k += gridDim.x * 256) v = fma(x[k], x[k], v);
   block_write_partial(v, part, red);
 }
 
