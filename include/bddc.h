@@ -212,6 +212,25 @@ int64_t bddc_export(bddc_handle h, int32_t what, int32_t index, void *dst, int64
 int bddc_apply(bddc_handle h, int32_t which, const double *x_u, const double *x_p, double *y_u,
                double *y_p);
 
+/* Solve nrhs sources on the resident problem, one after the other with the
+ * captured CG iterations (each result equals that of bddc_solve on the same
+ * source, bit for bit).  rhs [nrhs][n_cells], flux [nrhs][n_faces_all],
+ * pressure [nrhs][n_cells], host or (BDDC_DEVICE_PTRS) device pointers;
+ * iterations [nrhs] receives each CG count (may be NULL).  Returns BDDC_OK,
+ * BDDC_ENOCONV if some source reached max_it (all are still solved), or the
+ * first error, which stops the batch.  Statistics are those of the last
+ * source. */
+int bddc_solve_batch(bddc_handle h, int32_t nrhs, const double *rhs, double rtol, double *flux, double *pressure,
+                     uint32_t flags, int32_t *iterations);
+
+/* Device memory of every handle set up afterwards comes from alloc(bytes,
+ * ctx) and goes back through free(ptr, ctx) (for instance a framework's
+ * caching allocator); both NULL restore hipMalloc / hipFree.  The routines
+ * must be thread-safe when a server runs (its setup workers allocate).  An
+ * allocation is released through the routine it came from, whatever is set
+ * later.  Host-only; BDDC_EINVAL if only one routine is given. */
+int bddc_set_allocator(void *(*alloc)(size_t, void *), void (*free)(void *, void *), void *ctx);
+
 /* Time one kernel of the CG iteration on the handle's stream with HIP events:
  * `reps` back-to-back launches on the vectors of the last solve, bracketed by
  * two events.  which = BDDC_K_SCHUR_APPLY (local Schur products S^i of the

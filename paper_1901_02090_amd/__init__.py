@@ -3,4 +3,4 @@
 The numerical work runs in the HIP library ``libbddc.so`` (C ABI declared in
 ``include/bddc.h``); this package only marshals arguments.
 """
-from .bddc import Solver, Server, BddcError, estimate_bytes, load_library, LIB_PATH  # noqa: F401
+from .bddc import Solver, Server, BddcError, estimate_bytes, set_allocator, load_library, LIB_PATH  # noqa: F401

@@ -21,6 +21,7 @@ OP_SYSTEM, OP_PRECOND = 1, 2
 
 EXPORTED = ["bddc_setup", "bddc_solve", "bddc_stats", "bddc_set_stream", "bddc_destroy", "bddc_last_error",
             "bddc_sizes", "bddc_export", "bddc_apply", "bddc_time_kernel", "bddc_estimate_bytes",
+            "bddc_solve_batch", "bddc_set_allocator",
             "bddc_server_create", "bddc_server_submit", "bddc_server_poll", "bddc_server_stats",
             "bddc_server_destroy"]
 K_SCHUR_APPLY, K_PRECOND_APPLY, K_PRECOND_FULL = 1, 2, 3
@@ -81,6 +82,28 @@ class BddcError(RuntimeError):
 
 _lib = None
 
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+_allocator_keep = None
+
+
+def set_allocator(alloc=None, free=None):
+    """Route the device allocations of handles created afterwards through
+    alloc(nbytes) -> int address and free(address); None for both restores
+    hipMalloc / hipFree.  The Python callables must stay thread-safe."""
+    global _allocator_keep
+    lib = load_library()
+    if (alloc is None) != (free is None):
+        raise ValueError("give both routines or neither")
+    if alloc is None:
+        _check(lib, lib.bddc_set_allocator(ALLOC_FN(), FREE_FN(), None))
+        _allocator_keep = None
+        return
+    a = ALLOC_FN(lambda n, ctx: alloc(int(n)))
+    f = FREE_FN(lambda p, ctx: free(int(p)))
+    _check(lib, lib.bddc_set_allocator(a, f, None))
+    _allocator_keep = (a, f)          # the C side holds these pointers
+
 
 def load_library(path=LIB_PATH):
     """Load libbddc.so; raises if it was not built (there is no fallback)."""
@@ -113,6 +136,10 @@ def load_library(path=LIB_PATH):
     lib.bddc_apply.restype = C.c_int
     lib.bddc_time_kernel.argtypes = [P, C.c_int32, C.c_int32, dp, dp]
     lib.bddc_time_kernel.restype = C.c_int
+    lib.bddc_solve_batch.argtypes = [P, C.c_int32, P, C.c_double, P, P, C.c_uint32, C.POINTER(C.c_int32)]
+    lib.bddc_solve_batch.restype = C.c_int
+    lib.bddc_set_allocator.argtypes = [ALLOC_FN, FREE_FN, C.c_void_p]
+    lib.bddc_set_allocator.restype = C.c_int
     lib.bddc_estimate_bytes.argtypes = [C.POINTER(Grid), C.POINTER(Partition), C.c_double, C.POINTER(Options), dp]
     lib.bddc_estimate_bytes.restype = C.c_int
     lib.bddc_server_create.argtypes = [C.POINTER(ServerOptions), C.POINTER(P)]
@@ -197,6 +224,18 @@ class Solver:
                                  BDDC_EAGER if eager else 0)
         _check(self.lib, rc, allow=(BDDC_ENOCONV,) if allow_noconv else ())
         return flux, pres
+
+    def solve_batch(self, sources, rtol=1e-8):
+        """Solve several sources ([k, n_cells]) on the resident problem; returns (flux, pressure, iterations)."""
+        src = np.ascontiguousarray(sources, dtype=np.float64).reshape(-1, self.n_cells)
+        k = src.shape[0]
+        flux = np.empty((k, self.n_faces_all))
+        pres = np.empty((k, self.n_cells))
+        its = (C.c_int32 * max(k, 1))()
+        rc = self.lib.bddc_solve_batch(self.h, k, src.ctypes.data, float(rtol), flux.ctypes.data, pres.ctypes.data, 0,
+                                       its)
+        _check(self.lib, rc, allow=(BDDC_ENOCONV,))
+        return flux, pres, np.array(its[:k], dtype=np.int32)
 
     def solve_device(self, src_ptr, rtol, flux_ptr, pres_ptr, eager=False):
         """Device-pointer solve (e.g. torch tensor data_ptr()); no host copies."""

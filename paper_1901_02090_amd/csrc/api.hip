@@ -30,6 +30,17 @@ namespace {
 
 thread_local std::string g_last_error;
 
+// Device allocator for the arrays of every handle created afterwards
+// (bddc_set_allocator); null: hipMalloc / hipFree.  Each allocation keeps the
+// free routine it came with.
+struct Allocator {
+  void *(*alloc)(size_t, void *) = nullptr;
+  void (*free)(void *, void *) = nullptr;
+  void *ctx = nullptr;
+};
+std::mutex g_alloc_mu;
+Allocator g_alloc;
+
 struct Error {
   int code;
   std::string msg;
@@ -64,6 +75,7 @@ struct bddc_problem {
   double tau = 0.0;
   std::vector<void *> allocs;
   std::vector<double> alloc_bytes;
+  std::vector<Allocator> alloc_by;
   double device_bytes = 0;
 
   DevGeom g{};
@@ -126,19 +138,38 @@ struct bddc_problem {
   template <typename T>
   T *alloc(int64_t count) {
     if (count <= 0) count = 1;
+    const size_t bytes = (size_t)count * sizeof(T);
+    Allocator a;
+    {
+      std::lock_guard<std::mutex> lk(g_alloc_mu);
+      a = g_alloc;
+    }
     void *p = nullptr;
-    HIPCHK(hipMalloc(&p, (size_t)count * sizeof(T)));
+    if (a.alloc) {
+      p = a.alloc(bytes, a.ctx);
+      if (!p) throw Error{BDDC_ENOMEM, "the caller's allocator returned no memory"};
+    } else {
+      HIPCHK(hipMalloc(&p, bytes));
+    }
     allocs.push_back(p);
-    alloc_bytes.push_back((double)count * sizeof(T));
-    device_bytes += (double)count * sizeof(T);
+    alloc_bytes.push_back((double)bytes);
+    alloc_by.push_back(a);
+    device_bytes += (double)bytes;
     peak_bytes = std::max(peak_bytes, device_bytes);
     return (T *)p;
+  }
+  void free_at(size_t k) {
+    if (!allocs[k]) return;
+    if (alloc_by[k].free)
+      alloc_by[k].free(allocs[k], alloc_by[k].ctx);
+    else if (!alloc_by[k].alloc)
+      (void)hipFree(allocs[k]);
+    allocs[k] = nullptr;
   }
   void release(void *p) {
     for (size_t k = 0; k < allocs.size(); ++k)
       if (allocs[k] == p) {
-        (void)hipFree(allocs[k]);
-        allocs[k] = nullptr;
+        free_at(k);
         device_bytes -= alloc_bytes[k];
         alloc_bytes[k] = 0.0;
       }
@@ -164,8 +195,7 @@ struct bddc_problem {
     if (side) (void)hipStreamDestroy(side);
     if (own_stream) (void)hipStreamDestroy(own_stream);
     if (st_host) (void)hipHostFree(st_host);
-    for (void *p : allocs)
-      if (p) (void)hipFree(p);
+    for (size_t k = 0; k < allocs.size(); ++k) free_at(k);
   }
 };
 
@@ -1075,6 +1105,31 @@ int bddc_solve(bddc_handle h, const double *rhs, double rtol, double *flux, doub
     const int rc = do_solve(h, rhs, rtol, flux, pressure, flags);
     if (rc == BDDC_ENOCONV) g_last_error = "maximum number of CG iterations reached";
     return rc;
+  });
+}
+
+int bddc_solve_batch(bddc_handle h, int32_t nrhs, const double *rhs, double rtol, double *flux, double *pressure,
+                     uint32_t flags, int32_t *iterations) {
+  return guarded([&]() -> int {
+    if (!h || !rhs || !flux || !pressure || nrhs < 0) throw Error{BDDC_EINVAL, "bad argument"};
+    const int64_t nc = h->L.ncells, nf = h->L.nfaces_all;
+    int rc_all = BDDC_OK;
+    for (int32_t k = 0; k < nrhs; ++k) {
+      const int rc = do_solve(h, rhs + k * nc, rtol, flux + k * nf, pressure + k * nc, flags);
+      if (iterations) iterations[k] = h->stats.it;
+      if (rc == BDDC_ENOCONV) rc_all = BDDC_ENOCONV;
+    }
+    if (rc_all == BDDC_ENOCONV) g_last_error = "maximum number of CG iterations reached for a right-hand side";
+    return rc_all;
+  });
+}
+
+int bddc_set_allocator(void *(*alloc)(size_t, void *), void (*free_fn)(void *, void *), void *ctx) {
+  return guarded([&]() -> int {
+    if ((alloc == nullptr) != (free_fn == nullptr)) throw Error{BDDC_EINVAL, "give both routines or neither"};
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    g_alloc = Allocator{alloc, free_fn, ctx};
+    return BDDC_OK;
   });
 }
 

@@ -39,3 +39,16 @@ def test_binding_has_no_cpu_fallback(tmp_path):
             bddc.load_library(str(tmp_path / "missing.so"))
     finally:
         bddc._lib = saved
+
+
+def test_allocator_hooks_are_host_only_and_checked():
+    from paper_1901_02090_amd import bddc
+    if not os.path.exists(bddc.LIB_PATH):
+        pytest.skip("libbddc.so not built")
+    lib = bddc.load_library()
+    keep = bddc.FREE_FN(lambda p, c: None)
+    assert lib.bddc_set_allocator(bddc.ALLOC_FN(), keep, None) == bddc.BDDC_EINVAL
+    bddc.set_allocator(lambda n: 0, lambda p: None)
+    bddc.set_allocator()                 # back to hipMalloc / hipFree
+    with pytest.raises(ValueError):
+        bddc.set_allocator(lambda n: 0, None)
