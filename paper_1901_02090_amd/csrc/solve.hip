@@ -86,32 +86,37 @@ __device__ __forceinline__ void block_write_partial(double v, double *part, doub
 // stopping test before any work.
 // ---------------------------------------------------------------------------
 // 16-byte vector load of 16/sizeof(TS) consecutive entries, widened to FP64.
+// The local operators and bases are read once per application and are far
+// larger than the caches: their loads are marked non-temporal, so that they do
+// not push out of the L2s and the Infinity Cache the data that is read again
+// (the coarse factor, the sweep descriptors and the interface vectors).
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
 __device__ __forceinline__ void load16(const float *p, double *o) {
-  const float4 v = *reinterpret_cast<const float4 *>(p);
-  o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+  const f32x4 v = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(p));
+  o[0] = v[0]; o[1] = v[1]; o[2] = v[2]; o[3] = v[3];
 }
 __device__ __forceinline__ void load16(const double *p, double *o) {
-  const double2 v = *reinterpret_cast<const double2 *>(p);
-  o[0] = v.x; o[1] = v.y;
+  const f64x2 v = __builtin_nontemporal_load(reinterpret_cast<const f64x2 *>(p));
+  o[0] = v[0]; o[1] = v[1];
 }
 
 // The same 16 bytes kept in their storage type (widened at use), for kernels
 // that hold many loads in flight.
 template <typename TS> struct Raw16;
 template <> struct Raw16<float> {
-  float4 v;
-  __device__ __forceinline__ double operator[](int i) const {
-    return i == 0 ? v.x : (i == 1 ? v.y : (i == 2 ? v.z : v.w));
-  }
+  f32x4 v;
+  __device__ __forceinline__ double operator[](int i) const { return v[i]; }
 };
 template <> struct Raw16<double> {
-  double2 v;
-  __device__ __forceinline__ double operator[](int i) const { return i == 0 ? v.x : v.y; }
+  f64x2 v;
+  __device__ __forceinline__ double operator[](int i) const { return v[i]; }
 };
 template <typename TS>
 __device__ __forceinline__ Raw16<TS> load_raw16(const TS *p) {
   Raw16<TS> r;
-  r.v = *reinterpret_cast<const decltype(r.v) *>(p);
+  r.v = __builtin_nontemporal_load(reinterpret_cast<const decltype(r.v) *>(p));
   return r;
 }
 
