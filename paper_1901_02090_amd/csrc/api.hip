@@ -748,7 +748,6 @@ void launch_iteration(bddc_problem *h) {
   launch_precond(h, h->ru, h->zu, h->part_z, true);
   k_update_p<<<nb, 256, 0, s>>>(nGm, N, h->cs.pidx, h->part_z, face_blocks(L.nF), h->zu, h->csol, h->pu, h->pp,
                                 h->st, h->beta_h);
-  k_advance<<<1, 1, 0, s>>>(h->st);
 }
 
 double lanczos_kappa(const std::vector<double> &a, const std::vector<double> &b, double *lmin, double *lmax) {

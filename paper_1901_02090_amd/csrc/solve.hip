@@ -23,6 +23,7 @@ struct CgState {
   int converged;
   int fail;      // 1: breakdown
   int maxit;
+  int pending;   // 1: rho = rho_next and it += 1 still to do (left by the p update)
 };
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -272,6 +273,13 @@ __global__ __launch_bounds__(256) void k_sys_assemble(DevGeom g, const double *_
                                                       double *part, CgState *st) {
   __shared__ double red[8];
   if (st && st->done) return;
+  // the state advance of the previous p update: no block of this kernel or of
+  // the S^i products before it reads rho or the iteration count
+  if (st && blockIdx.x == 0 && threadIdx.x == 0 && st->pending) {
+    st->rho = st->rho_next;
+    st->it += 1;
+    st->pending = 0;
+  }
   double v = 0.0;
   for (int gi = blockIdx.x * 256 + threadIdx.x; gi < g.nGamma; gi += gridDim.x * 256) {
     const int sm = g.sub_minus[gi], sp = g.sub_plus[gi];
@@ -437,14 +445,9 @@ __global__ __launch_bounds__(256) void k_update_p(int nGamma, int N, const int *
     if (threadIdx.x == 0) {
       beta_hist[st->it] = beta;
       st->rho_next = rn;
+      st->pending = 1;     // applied by the next assembly kernel
     }
   }
-}
-
-__global__ void k_advance(CgState *st) {
-  if (st->done) return;
-  st->rho = st->rho_next;
-  st->it += 1;
 }
 
 // initial direction p = z, rho = r.z, ||r_0||^2
@@ -472,6 +475,7 @@ __global__ __launch_bounds__(256) void k_init_p(int nGamma, int N, const int *__
       st->done = (r0 == 0.0) ? 1 : 0;
       st->fail = 0;
       st->maxit = maxit;
+      st->pending = 0;
     }
   }
 }
