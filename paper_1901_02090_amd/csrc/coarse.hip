@@ -43,7 +43,7 @@ struct DevSweep {
 
 // Assemble, partially factor and invert the fronts [f0, f0 + gridDim.x) of one
 // level.  F, W (n x n), Q (m x n) are workspaces; FR / BC receive R.
-__global__ __launch_bounds__(256) void k_front_factor(DevGeom g, DevCoarse cs, DevFronts fd, int f0,
+__global__ __launch_bounds__(256, 2) void k_front_factor(DevGeom g, DevCoarse cs, DevFronts fd, int f0,
                                                       const double *__restrict__ Ac, const int64_t *__restrict__ ac_off,
                                                       const double *__restrict__ dscale,
                                                       const double *__restrict__ sgn, double *F, double *W,

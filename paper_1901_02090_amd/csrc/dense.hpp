@@ -19,6 +19,13 @@ constexpr int NB = 32;      // block size of the blocked factorizations
 constexpr int LDS_DOUBLES = 2 * KT * TILE + NB * NB + 2 * NB + 2;
 
 // One TILE x TILE tile of C at (i0, j0); see wg_gemm.  No trailing barrier.
+// The k panels are staged in LDS (zero padded past m, n, k); the product runs
+// on the FP64 matrix cores: wave w owns the 32 x 32 quarter at rows 32 (w & 1),
+// columns 32 (w >> 1), as 2 x 2 blocks of 16 x 16.  One
+// v_mfma_f64_16x16x4f64 takes A(i, k) from lane i + 16 k, B(k, j) from lane
+// j + 16 k, and leaves C(4 r + lane / 16, lane % 16) in result register r.
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
 template <bool TA, bool TB, bool LOWER = false>
 __device__ __forceinline__ void wg_gemm_tile(int i0, int j0, int m, int n, int k, double alpha,
                                              const double *__restrict__ A, int lda, const double *__restrict__ B,
@@ -27,66 +34,63 @@ __device__ __forceinline__ void wg_gemm_tile(int i0, int j0, int m, int n, int k
   double *As = lds;              // As[kk * TILE + i] = op(A)(i0 + i, k0 + kk)
   double *Bs = lds + KT * TILE;  // Bs[kk * TILE + j] = op(B)(k0 + kk, j0 + j)
   const int tid = threadIdx.x;
-  const int tx = tid & 15, ty = tid >> 4;
-  {
-    {
-      double acc[4][4];
+  const int lane = tid & 63, wv = tid >> 6;
+  const int rb = 32 * (wv & 1), cb = 32 * (wv >> 1);
+  const int li = lane & 15, lk = lane >> 4;
+  f64x4 acc[2][2];
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
+  for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc[r][c] = 0.0;
-      for (int k0 = 0; k0 < k; k0 += KT) {
-        for (int e = tid; e < KT * TILE; e += WG) {
-          int i, kk;
-          if (!TA) { i = e & (TILE - 1); kk = e / TILE; }
-          else { kk = e & (KT - 1); i = e / KT; }
-          const int gi = i0 + i, gk = k0 + kk;
-          double v = 0.0;
-          if (gi < m && gk < k) {
-            v = TA ? A[gk + (size_t)gi * lda] : A[gi + (size_t)gk * lda];
-            if (kscale) v *= kscale[gk];
-          }
-          As[kk * TILE + i] = v;
-        }
-        for (int e = tid; e < KT * TILE; e += WG) {
-          int j, kk;
-          if (!TB) { kk = e & (KT - 1); j = e / KT; }
-          else { j = e & (TILE - 1); kk = e / TILE; }
-          const int gj = j0 + j, gk = k0 + kk;
-          double v = 0.0;
-          if (gj < n && gk < k) v = TB ? B[gj + (size_t)gk * ldb] : B[gk + (size_t)gj * ldb];
-          Bs[kk * TILE + j] = v;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int kk = 0; kk < KT; ++kk) {
-          double a[4], b[4];
-#pragma unroll
-          for (int r = 0; r < 4; ++r) a[r] = As[kk * TILE + ty + 16 * r];
-#pragma unroll
-          for (int c = 0; c < 4; ++c) b[c] = Bs[kk * TILE + tx + 16 * c];
-#pragma unroll
-          for (int r = 0; r < 4; ++r)
-#pragma unroll
-            for (int c = 0; c < 4; ++c) acc[r][c] = fma(a[r], b[c], acc[r][c]);
-        }
-        __syncthreads();
+    for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = f64x4{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < k; k0 += KT) {
+    for (int e = tid; e < KT * TILE; e += WG) {
+      int i, kk;
+      if (!TA) { i = e & (TILE - 1); kk = e / TILE; }
+      else { kk = e & (KT - 1); i = e / KT; }
+      const int gi = i0 + i, gk = k0 + kk;
+      double v = 0.0;
+      if (gi < m && gk < k) {
+        v = TA ? A[gk + (size_t)gi * lda] : A[gi + (size_t)gk * lda];
+        if (kscale) v *= kscale[gk];
       }
+      As[kk * TILE + i] = v;
+    }
+    for (int e = tid; e < KT * TILE; e += WG) {
+      int j, kk;
+      if (!TB) { kk = e & (KT - 1); j = e / KT; }
+      else { j = e & (TILE - 1); kk = e / TILE; }
+      const int gj = j0 + j, gk = k0 + kk;
+      double v = 0.0;
+      if (gj < n && gk < k) v = TB ? B[gj + (size_t)gk * ldb] : B[gk + (size_t)gj * ldb];
+      Bs[kk * TILE + j] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < KT; kk += 4) {
+      const double *Ak = As + (kk + lk) * TILE, *Bk = Bs + (kk + lk) * TILE;
+      const double a0 = Ak[rb + li], a1 = Ak[rb + 16 + li];
+      const double b0 = Bk[cb + li], b1 = Bk[cb + 16 + li];
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int gi = i0 + ty + 16 * r;
-        if (gi >= m) continue;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          const int gj = j0 + tx + 16 * c;
-          if (gj >= n) continue;
-          if (LOWER && gj > gi) continue;
-          double *dst = C + gi + (size_t)gj * ldc;
-          *dst = (beta == 0.0) ? alpha * acc[r][c] : fma(alpha, acc[r][c], beta * (*dst));
-        }
+        const int gi = i0 + rb + 16 * bi + 4 * r + lk;
+        const int gj = j0 + cb + 16 * bj + li;
+        if (gi >= m || gj >= n) continue;
+        if (LOWER && gj > gi) continue;
+        double *dst = C + gi + (size_t)gj * ldc;
+        const double v = acc[bi][bj][r];
+        *dst = (beta == 0.0) ? alpha * v : fma(alpha, v, beta * (*dst));
       }
-    }
-  }
 }
 
 // C = alpha * op(A) * op(B) * [diag(kscale)] + beta * C, op = transpose if TA/TB.
@@ -143,6 +147,52 @@ __device__ __forceinline__ int lds_sign_chol(double *L, int nb, const double *s,
   return f;
 }
 
+// Diagonal block of a lower triangular matrix into LDS (ld NB), padded to
+// NB x NB with the identity so that the substitutions below need no bounds:
+// padded unknowns stay zero and never touch the real ones.
+__device__ __forceinline__ void lds_load_lower_block(double *Lk, const double *L, int ldl, int k0, int nb) {
+  for (int e = threadIdx.x; e < NB * NB; e += WG) {
+    const int i = e % NB, j = e / NB;
+    double v = (i == j) ? 1.0 : 0.0;
+    if (i < nb && j < nb) v = (i >= j) ? L[(k0 + i) + (size_t)(k0 + j) * ldl] : 0.0;
+    Lk[e] = v;
+  }
+}
+
+// x <- Lk^{-1} x for one right-hand side held in registers (Lk padded as
+// above).  Column oriented: x_i receives its updates in increasing order of
+// the eliminated unknown, as in a row-wise forward substitution.  Padded
+// entries x_j, j >= nb, may hold any value: no x_i with i < nb reads them.
+__device__ __forceinline__ void lds_lower_solve(const double *Lk, double (&x)[NB]) {
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    // One column of Lk in flight at a time.  Without these empty asm
+    // statements the compiler sinks each update to the step that next needs
+    // x_i and keeps every block element read before it in registers (up to
+    // NB (NB + 1) / 2 of them), which spills.
+    asm volatile("" ::: "memory");
+#pragma unroll
+    for (int i = j; i < NB; ++i) asm volatile("" : "+v"(x[i]));
+    x[j] = x[j] / Lk[j + j * NB];
+#pragma unroll
+    for (int i = j + 1; i < NB; ++i) x[i] = fma(-Lk[i + j * NB], x[j], x[i]);
+  }
+}
+
+// x <- Lk^{-T} x for one right-hand side held in registers (Lk padded).
+// Padded entries must be zero: they are eliminated first.
+__device__ __forceinline__ void lds_lower_t_solve(const double *Lk, double (&x)[NB]) {
+#pragma unroll
+  for (int j = NB - 1; j >= 0; --j) {
+    asm volatile("" ::: "memory");
+#pragma unroll
+    for (int i = 0; i <= j; ++i) asm volatile("" : "+v"(x[i]));
+    x[j] = x[j] / Lk[j + j * NB];
+#pragma unroll
+    for (int i = 0; i < j; ++i) x[i] = fma(-Lk[j + i * NB], x[j], x[i]);
+  }
+}
+
 // In-place blocked signed Cholesky of the n x n lower triangle of A:
 // A = L diag(s) L^T with s = +-1 per column (s == nullptr: ordinary Cholesky).
 // Returns 0, or (index + 1) of the first pivot whose sign disagrees with s.
@@ -159,11 +209,8 @@ __device__ __forceinline__ int wg_potrf(int n, double *A, int lda, double *lds, 
   const int tid = threadIdx.x;
   for (int k0 = 0; k0 < n; k0 += NB) {
     const int nb = min(NB, n - k0);
-    for (int e = tid; e < nb * nb; e += WG) {
-      const int i = e % nb, j = e / nb;
-      Lk[i + j * NB] = (i >= j) ? A[(k0 + i) + (size_t)(k0 + j) * lda] : 0.0;
-    }
-    if (tid < nb) sk[tid] = s ? s[k0 + tid] : 1.0;
+    lds_load_lower_block(Lk, A, lda, k0, nb);
+    if (tid < NB) sk[tid] = (tid < nb && s) ? s[k0 + tid] : 1.0;
     __syncthreads();
     const int f = lds_sign_chol(Lk, nb, sk, flag);
     if (f && !fail) fail = k0 + f;
@@ -176,17 +223,15 @@ __device__ __forceinline__ int wg_potrf(int n, double *A, int lda, double *lds, 
     for (int r = r0 + tid; r < nr; r += WG) {
       double x[NB];
 #pragma unroll
-      for (int j = 0; j < NB; ++j) {
-        if (j < nb) {
-          double v = A[r + (size_t)(k0 + j) * lda];
-#pragma unroll
-          for (int l = 0; l < j; ++l) v -= x[l] * Lk[j + l * NB];
-          x[j] = v / Lk[j + j * NB];
-        }
-      }
+      for (int j = 0; j < NB; ++j) x[j] = A[r + (size_t)(k0 + min(j, nb - 1)) * lda];
+      lds_lower_solve(Lk, x);
+      // recompute the row addresses and re-read the signs here rather than
+      // keep NB of each live across the substitution
+      int ld = lda;
+      asm volatile("" : "+s"(ld) : : "memory");
 #pragma unroll
       for (int j = 0; j < NB; ++j)
-        if (j < nb) A[r + (size_t)(k0 + j) * lda] = x[j] * sk[j];
+        if (j < nb) A[r + (size_t)(k0 + j) * ld] = x[j] * sk[j];
     }
     __syncthreads();
     // trailing: A22 -= X diag(s_k) X^T  (lower triangle only)
@@ -206,23 +251,14 @@ __device__ __forceinline__ void wg_trsm_lower(int n, int nrhs, const double *L, 
   const int tid = threadIdx.x;
   for (int k0 = 0; k0 < n; k0 += NB) {
     const int nb = min(NB, n - k0);
-    for (int e = tid; e < nb * nb; e += WG) {
-      const int i = e % nb, j = e / nb;
-      Lk[i + j * NB] = (i >= j) ? L[(k0 + i) + (size_t)(k0 + j) * ldl] : 0.0;
-    }
+    lds_load_lower_block(Lk, L, ldl, k0, nb);
     __syncthreads();
     for (int c = tid; c < nrhs; c += WG) {
       double *b = B + k0 + (size_t)c * ldb;
       double x[NB];
 #pragma unroll
-      for (int j = 0; j < NB; ++j) {
-        if (j < nb) {
-          double v = b[j];
-#pragma unroll
-          for (int l = 0; l < j; ++l) v -= Lk[j + l * NB] * x[l];
-          x[j] = v / Lk[j + j * NB];
-        }
-      }
+      for (int j = 0; j < NB; ++j) x[j] = (j < nb) ? b[j] : 0.0;
+      lds_lower_solve(Lk, x);
 #pragma unroll
       for (int j = 0; j < NB; ++j)
         if (j < nb) b[j] = x[j];
@@ -244,25 +280,15 @@ __device__ __forceinline__ void wg_trsm_lower_t(int n, int nrhs, const double *L
   for (int kb = nblk - 1; kb >= 0; --kb) {
     const int k0 = kb * NB;
     const int nb = min(NB, n - k0);
-    for (int e = tid; e < nb * nb; e += WG) {
-      const int i = e % nb, j = e / nb;
-      Lk[i + j * NB] = (i >= j) ? L[(k0 + i) + (size_t)(k0 + j) * ldl] : 0.0;
-    }
+    lds_load_lower_block(Lk, L, ldl, k0, nb);
     __syncthreads();
     // solve L_kk^T x = b_k (backward substitution)
     for (int c = tid; c < nrhs; c += WG) {
       double *b = B + k0 + (size_t)c * ldb;
       double x[NB];
 #pragma unroll
-      for (int jj = NB - 1; jj >= 0; --jj) {
-        if (jj < nb) {
-          double v = b[jj];
-#pragma unroll
-          for (int l = jj + 1; l < NB; ++l)
-            if (l < nb) v -= Lk[l + jj * NB] * x[l];
-          x[jj] = v / Lk[jj + jj * NB];
-        }
-      }
+      for (int j = 0; j < NB; ++j) x[j] = (j < nb) ? b[j] : 0.0;
+      lds_lower_t_solve(Lk, x);
 #pragma unroll
       for (int j = 0; j < NB; ++j)
         if (j < nb) b[j] = x[j];
@@ -389,6 +415,83 @@ __device__ __forceinline__ void wg_jacobi(int n, double *A, int lda, double *V, 
         const double vp = V[k + (size_t)p * ldv], vq = V[k + (size_t)q * ldv];
         V[k + (size_t)p * ldv] = c * vp - s * vq;
         V[k + (size_t)q * ldv] = s * vp + c * vq;
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// The same cyclic Jacobi iteration (ordering, rotations, convergence test)
+// with A and V (both n x n, ld n) in LDS.  A round's row and column rotations
+// are applied in one pass over the disjoint 2 x 2 blocks that the round's
+// pairs cut out of A, so a round needs two barriers.  cs, sn (doubles) and
+// pp, qq (ints) are LDS arrays of at least 128 entries, red 4 doubles.
+__device__ __forceinline__ void wg_jacobi_lds(int n, double *A, double *V, double *cs, double *sn, int *pp,
+                                              int *qq, double *red, int max_sweeps = 40) {
+  const int tid = threadIdx.x;
+  for (int e = tid; e < n * n; e += WG) V[e] = (e % n == e / n) ? 1.0 : 0.0;
+  __syncthreads();
+  const int m = (n + 1) & ~1;   // even number of players (n odd: one bye)
+  const int npair = m / 2;
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    double off = 0.0, dia = 0.0;
+    for (int e = tid; e < n * n; e += WG) {
+      const double a = A[e];
+      if (e % n == e / n) dia += a * a; else off += a * a;
+    }
+    off = wg_sum(off, red);
+    dia = wg_sum(dia, red);
+    if (off <= 1e-30 * dia || off == 0.0) break;
+    for (int round = 0; round < m - 1; ++round) {
+      if (tid < npair) {
+        // round-robin: position 0 holds player 0, the others rotate
+        const int b = m - 1 - tid;
+        int p = (tid == 0) ? 0 : 1 + (tid - 1 + round) % (m - 1);
+        int q = 1 + (b - 1 + round) % (m - 1);
+        if (p > q) { const int t = p; p = q; q = t; }
+        double c = 1.0, s = 0.0;
+        if (q < n) {
+          const double apq = A[p + q * n];
+          if (apq != 0.0) {
+            const double app = A[p + p * n], aqq = A[q + q * n];
+            const double theta = (aqq - app) / (2.0 * apq);
+            const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+            c = 1.0 / sqrt(t * t + 1.0);
+            s = t * c;
+          }
+        }
+        cs[tid] = c;
+        sn[tid] = s;
+        pp[tid] = p;
+        qq[tid] = q;
+      }
+      __syncthreads();
+      // A <- J^T A J on the block of rows {p_t, q_t} and columns {p_u, q_u}
+      for (int e = tid; e < npair * npair; e += WG) {
+        const int t = e % npair, u = e / npair;
+        const int pt = pp[t], qt = qq[t], pu = pp[u], qu = qq[u];
+        const bool rq = qt < n, cq = qu < n;
+        const double ct = cs[t], st = sn[t], cu = cs[u], su = sn[u];
+        const double a = A[pt + pu * n];
+        const double b = cq ? A[pt + qu * n] : 0.0;
+        const double c = rq ? A[qt + pu * n] : 0.0;
+        const double d = (rq && cq) ? A[qt + qu * n] : 0.0;
+        const double a1 = ct * a - st * c, c1 = st * a + ct * c;
+        const double b1 = ct * b - st * d, d1 = st * b + ct * d;
+        A[pt + pu * n] = cu * a1 - su * b1;
+        if (cq) A[pt + qu * n] = su * a1 + cu * b1;
+        if (rq) A[qt + pu * n] = cu * c1 - su * d1;
+        if (rq && cq) A[qt + qu * n] = su * c1 + cu * d1;
+      }
+      // V <- V J
+      for (int e = tid; e < n * npair; e += WG) {
+        const int k = e % n, u = e / n;
+        const int pu = pp[u], qu = qq[u];
+        if (qu >= n) continue;
+        const double c = cs[u], s = sn[u];
+        const double vp = V[k + pu * n], vq = V[k + qu * n];
+        V[k + pu * n] = c * vp - s * vq;
+        V[k + qu * n] = s * vp + c * vq;
       }
       __syncthreads();
     }

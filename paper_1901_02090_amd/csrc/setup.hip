@@ -85,7 +85,7 @@ __global__ void k_cell_coef(DevGeom g, const double *__restrict__ perm, int64_t 
 // ---------------------------------------------------------------------------
 // per-subdomain: d_i, P, H, S_A, L_P, S^i, X^i
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_local_setup(DevGeom g, const double *__restrict__ mcoef,
+__global__ __launch_bounds__(256, 2) void k_local_setup(DevGeom g, const double *__restrict__ mcoef,
                                                      SetupWs ws, double *dscale, int *err) {
   __shared__ double lds[LDS_DOUBLES];
   __shared__ double red[8];
@@ -229,7 +229,7 @@ __global__ __launch_bounds__(256) void k_local_setup(DevGeom g, const double *__
 }
 
 // Cholesky of S^i and W_S = L_S^{-1}; packed copy of S^i for the CG operator.
-__global__ __launch_bounds__(256) void k_schur_factor(DevGeom g, SetupWs ws, int *err) {
+__global__ __launch_bounds__(256, 2) void k_schur_factor(DevGeom g, SetupWs ws, int *err) {
   __shared__ double lds[LDS_DOUBLES];
   const int i = blockIdx.x;
   const int nG = g.nG[i];
@@ -264,14 +264,18 @@ __global__ __launch_bounds__(256) void k_schur_factor(DevGeom g, SetupWs ws, int
 // a fixed jump yields the parallel sum of the two face Schur complements.  Z is
 // an orthonormal basis of 1^perp (a Householder reflector).  The row of eq.
 // constraints for eigenvector y is, up to scale and within span{1}, X_F Z y.
-__global__ __launch_bounds__(256) void k_face_eig(DevGeom g, SetupWs ws, double *fbase,
-                                                  const int64_t *foff, double tau, int all_constrained,
-                                                  double *eig_out, const int64_t *eig_off, int *kout,
-                                                  double *omega_out, double *rows_out,
-                                                  const int64_t *rows_off, int *err) {
+//
+// The work is split in three launches that pass everything through the face's
+// workspace: k_face_reduce forms the reduced m x m matrix C = L^{-1} Xr L^{-T}
+// (into U; L, the Cholesky factor of Yr, stays in T1), k_face_jacobi
+// diagonalises it (eigenvalues onto the diagonal of U, eigenvectors into T2)
+// and k_face_rows selects the eigenvalues above tau and builds the rows.
+__global__ __launch_bounds__(256, 2) void k_face_reduce(DevGeom g, SetupWs ws, double *fbase,
+                                                     const int64_t *foff, int all_constrained,
+                                                     double *eig_out, const int64_t *eig_off, int *kout,
+                                                     double *omega_out, double *rows_out,
+                                                     const int64_t *rows_off, int *err) {
   __shared__ double lds[LDS_DOUBLES];
-  __shared__ double jac[512];
-  __shared__ int perm[256];
   __shared__ double red[8];
   const int f = blockIdx.x;
   const int tid = threadIdx.x;
@@ -370,7 +374,55 @@ __global__ __launch_bounds__(256) void k_face_eig(DevGeom g, SetupWs ws, double 
     }
   }
   __syncthreads();
-  wg_jacobi(m, U, m, T2, m, jac, perm);
+}
+
+// Jacobi stage for the faces listed in `faces`.  IN_LDS: C and its eigenvector
+// matrix are held in dynamic LDS (16 m^2 bytes, m <= 128), the matrix C in U
+// is left untouched apart from its diagonal; otherwise the rotations work in
+// the workspace.
+template <bool IN_LDS>
+__global__ __launch_bounds__(256) void k_face_jacobi(DevGeom g, double *fbase, const int64_t *foff,
+                                                     const int *faces) {
+  const int f = faces[blockIdx.x];
+  const int n = g.f_n[f], m = n - 1;
+  if (m <= 0) return;
+  double *w = fbase + foff[f];
+  double *T2 = w + 4 * n * n, *U = w + 5 * n * n;
+  if constexpr (IN_LDS) {
+    extern __shared__ double sh[];
+    __shared__ double cs[128], sn[128], red[8];
+    __shared__ int pp[128], qq[128];
+    double *A = sh, *V = sh + m * m;
+    for (int e = threadIdx.x; e < m * m; e += WG) A[e] = U[e];
+    __syncthreads();
+    wg_jacobi_lds(m, A, V, cs, sn, pp, qq, red);
+    for (int t = threadIdx.x; t < m; t += WG) U[t + (size_t)t * m] = A[t + t * m];
+    for (int e = threadIdx.x; e < m * m; e += WG) T2[e] = V[e];
+  } else {
+    __shared__ double jac[512];
+    __shared__ int perm[256];
+    wg_jacobi(m, U, m, T2, m, jac, perm);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_face_rows(DevGeom g, double *fbase, const int64_t *foff, double tau,
+                                                   double *eig_out, const int64_t *eig_off, int *kout,
+                                                   double *omega_out, double *rows_out,
+                                                   const int64_t *rows_off) {
+  __shared__ double lds[LDS_DOUBLES];
+  __shared__ int perm[256];
+  __shared__ double red[8];
+  const int f = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int n = g.f_n[f];
+  const int m = n - 1;
+  if (m <= 0) return;
+  double *w = fbase + foff[f];
+  double *XF = w, *XH = w + n * n, *YF = w + 2 * n * n, *T1 = w + 3 * n * n, *T2 = w + 4 * n * n,
+         *U = w + 5 * n * n, *v = w + 6 * n * n;
+  double *rows = rows_out + rows_off[f];
+  double *eig = eig_out + eig_off[f];
+  const double beta = 2.0 / ((1.0 + sqrt((double)n)) * (1.0 + sqrt((double)n)) + (double)(n - 1));
   // sort eigenvalues descending (rank by count, ties by index)
   for (int t = tid; t < m; t += WG) {
     const double lt = U[t + (size_t)t * m];
