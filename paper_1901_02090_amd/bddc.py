@@ -213,7 +213,6 @@ class Solver:
         _check(lib, lib.bddc_sizes(self.h, sz))
         (self.N, self.n_gamma, self.n_faces, self.n_coarse_flux, self.n_cells, self.n_faces_all,
          self.n_adaptive, self.max_gamma_local) = [int(v) for v in sz]
-        self._sub_nG = [self.schur(i).shape[0] for i in range(self.N)] if self.N <= 4096 else None
 
     # -- solves ----------------------------------------------------------------
     def solve(self, source, rtol=1e-8, allow_noconv=False, eager=False):
@@ -271,7 +270,7 @@ class Solver:
 
     def psi(self, i):
         out = self._export(X_PSI, i, self.max_gamma_local * 1024, np.float64)
-        nG = int(self._sub_nG[i])
+        nG = self.schur(i).shape[0]        # interface size of subdomain i
         return out.reshape(nG, -1, order="F")
 
     def coarse_inverse(self):

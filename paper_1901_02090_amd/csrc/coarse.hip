@@ -113,7 +113,7 @@ __global__ __launch_bounds__(256, 2) void k_front_factor(DevGeom g, DevCoarse cs
   }
   double *Wp = W + fd.w_off[p];
   wg_set_identity(n, Wp, n);
-  wg_trsm_lower(n, n, Fp, f, Wp, n, lds);
+  wg_trsm_lower(n, n, Fp, f, Wp, n, lds, true);
   double *Qp = Q + fd.q_off[p];
   if (m > 0) wg_gemm<false, false>(m, n, n, 1.0, Fp + n, f, Wp, n, 0.0, Qp, m, lds);
   double *R = FR + fd.r_off[p];

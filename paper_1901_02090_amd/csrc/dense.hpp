@@ -16,6 +16,7 @@ constexpr int WG = 256;
 constexpr int TILE = 64;    // C tile edge of the workgroup GEMM
 constexpr int KT = 16;      // k depth staged per LDS round
 constexpr int NB = 32;      // block size of the blocked factorizations
+constexpr int KB = 4 * NB;  // super-block: updates below it are delayed to its end
 constexpr int LDS_DOUBLES = 2 * KT * TILE + NB * NB + 2 * NB + 2;
 
 // One TILE x TILE tile of C at (i0, j0); see wg_gemm.  No trailing barrier.
@@ -42,8 +43,14 @@ __device__ __forceinline__ void wg_gemm_tile(int i0, int j0, int m, int n, int k
   for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = f64x4{0.0, 0.0, 0.0, 0.0};
-  for (int k0 = 0; k0 < k; k0 += KT) {
-    for (int e = tid; e < KT * TILE; e += WG) {
+  // The next k panel is loaded into registers while the matrix cores work on
+  // the current one.
+  constexpr int PER = KT * TILE / WG;
+  double pa[PER], pb[PER];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+      const int e = tid + r * WG;
       int i, kk;
       if (!TA) { i = e & (TILE - 1); kk = e / TILE; }
       else { kk = e & (KT - 1); i = e / KT; }
@@ -53,18 +60,32 @@ __device__ __forceinline__ void wg_gemm_tile(int i0, int j0, int m, int n, int k
         v = TA ? A[gk + (size_t)gi * lda] : A[gi + (size_t)gk * lda];
         if (kscale) v *= kscale[gk];
       }
-      As[kk * TILE + i] = v;
+      pa[r] = v;
     }
-    for (int e = tid; e < KT * TILE; e += WG) {
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+      const int e = tid + r * WG;
       int j, kk;
       if (!TB) { kk = e & (KT - 1); j = e / KT; }
       else { j = e & (TILE - 1); kk = e / TILE; }
       const int gj = j0 + j, gk = k0 + kk;
       double v = 0.0;
       if (gj < n && gk < k) v = TB ? B[gj + (size_t)gk * ldb] : B[gk + (size_t)gj * ldb];
-      Bs[kk * TILE + j] = v;
+      pb[r] = v;
+    }
+  };
+  load(0);
+  for (int k0 = 0; k0 < k; k0 += KT) {
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+      const int e = tid + r * WG;
+      if (!TA) As[(e / TILE) * TILE + (e & (TILE - 1))] = pa[r];
+      else As[(e & (KT - 1)) * TILE + e / KT] = pa[r];
+      if (!TB) Bs[(e & (KT - 1)) * TILE + e / KT] = pb[r];
+      else Bs[(e / TILE) * TILE + (e & (TILE - 1))] = pb[r];
     }
     __syncthreads();
+    if (k0 + KT < k) load(k0 + KT);
 #pragma unroll
     for (int kk = 0; kk < KT; kk += 4) {
       const double *Ak = As + (kk + lk) * TILE, *Bk = Bs + (kk + lk) * TILE;
@@ -207,67 +228,89 @@ __device__ __forceinline__ int wg_potrf(int n, double *A, int lda, double *lds, 
   int *flag = (int *)(sk + NB);      // pivot-failure word
   int fail = 0;
   const int tid = threadIdx.x;
-  for (int k0 = 0; k0 < n; k0 += NB) {
-    const int nb = min(NB, n - k0);
-    lds_load_lower_block(Lk, A, lda, k0, nb);
-    if (tid < NB) sk[tid] = (tid < nb && s) ? s[k0 + tid] : 1.0;
-    __syncthreads();
-    const int f = lds_sign_chol(Lk, nb, sk, flag);
-    if (f && !fail) fail = k0 + f;
-    for (int e = tid; e < nb * nb; e += WG) {
-      const int i = e % nb, j = e / nb;
-      if (i >= j) A[(k0 + i) + (size_t)(k0 + j) * lda] = Lk[i + j * NB];
-    }
-    // panel: X with X diag(s_k) L_kk^T = A_panel  (row-wise forward substitution)
-    const int r0 = k0 + nb;
-    for (int r = r0 + tid; r < nr; r += WG) {
-      double x[NB];
+  for (int kb0 = 0; kb0 < n; kb0 += KB) {
+    const int kb1 = min(kb0 + KB, n);
+    for (int k0 = kb0; k0 < kb1; k0 += NB) {
+      const int nb = min(NB, n - k0);
+      lds_load_lower_block(Lk, A, lda, k0, nb);
+      if (tid < NB) sk[tid] = (tid < nb && s) ? s[k0 + tid] : 1.0;
+      __syncthreads();
+      const int f = lds_sign_chol(Lk, nb, sk, flag);
+      if (f && !fail) fail = k0 + f;
+      for (int e = tid; e < nb * nb; e += WG) {
+        const int i = e % nb, j = e / nb;
+        if (i >= j) A[(k0 + i) + (size_t)(k0 + j) * lda] = Lk[i + j * NB];
+      }
+      // panel: X with X diag(s_k) L_kk^T = A_panel  (row-wise forward substitution)
+      const int r0 = k0 + nb;
+      for (int r = r0 + tid; r < nr; r += WG) {
+        double x[NB];
 #pragma unroll
-      for (int j = 0; j < NB; ++j) x[j] = A[r + (size_t)(k0 + min(j, nb - 1)) * lda];
-      lds_lower_solve(Lk, x);
-      // recompute the row addresses and re-read the signs here rather than
-      // keep NB of each live across the substitution
-      int ld = lda;
-      asm volatile("" : "+s"(ld) : : "memory");
+        for (int j = 0; j < NB; ++j) x[j] = A[r + (size_t)(k0 + min(j, nb - 1)) * lda];
+        lds_lower_solve(Lk, x);
+        // recompute the row addresses and re-read the signs here rather than
+        // keep NB of each live across the substitution
+        int ld = lda;
+        asm volatile("" : "+s"(ld) : : "memory");
 #pragma unroll
-      for (int j = 0; j < NB; ++j)
-        if (j < nb) A[r + (size_t)(k0 + j) * ld] = x[j] * sk[j];
+        for (int j = 0; j < NB; ++j)
+          if (j < nb) A[r + (size_t)(k0 + j) * ld] = x[j] * sk[j];
+      }
+      __syncthreads();
+      // the super-block's remaining columns: A[r0:, r0:kb1] -= X diag(s_k) X[r0:kb1]^T
+      if (r0 < kb1) {
+        double *X = A + r0 + (size_t)k0 * lda;
+        wg_gemm<false, true, true>(nr - r0, kb1 - r0, nb, -1.0, X, lda, X, lda, 1.0,
+                                   A + r0 + (size_t)r0 * lda, lda, lds, sk);
+      }
     }
-    __syncthreads();
-    // trailing: A22 -= X diag(s_k) X^T  (lower triangle only)
-    if (r0 < nr) {
-      double *X = A + r0 + (size_t)k0 * lda;
-      wg_gemm<false, true, true>(nr - r0, nr - r0, nb, -1.0, X, lda, X, lda, 1.0,
-                                 A + r0 + (size_t)r0 * lda, lda, lds, sk);
+    // delayed trailing update by the whole super-block (lower triangle only)
+    if (kb1 < nr) {
+      double *X = A + kb1 + (size_t)kb0 * lda;
+      wg_gemm<false, true, true>(nr - kb1, nr - kb1, kb1 - kb0, -1.0, X, lda, X, lda, 1.0,
+                                 A + kb1 + (size_t)kb1 * lda, lda, lds, s ? s + kb0 : nullptr);
     }
   }
   return fail;
 }
 
 // B <- L^{-1} B  (L lower triangular n x n, B n x nrhs).
+// lower_rhs: column c of B vanishes above row c (B = I, say), and so does the
+// same column of L^{-1} B; block k0 then only involves columns < k0 + NB.
 __device__ __forceinline__ void wg_trsm_lower(int n, int nrhs, const double *L, int ldl, double *B, int ldb,
-                                     double *lds) {
+                                     double *lds, bool lower_rhs = false) {
   double *Lk = lds + 2 * KT * TILE;
   const int tid = threadIdx.x;
-  for (int k0 = 0; k0 < n; k0 += NB) {
-    const int nb = min(NB, n - k0);
-    lds_load_lower_block(Lk, L, ldl, k0, nb);
-    __syncthreads();
-    for (int c = tid; c < nrhs; c += WG) {
-      double *b = B + k0 + (size_t)c * ldb;
-      double x[NB];
+  for (int kb0 = 0; kb0 < n; kb0 += KB) {
+    const int kb1 = min(kb0 + KB, n);
+    for (int k0 = kb0; k0 < kb1; k0 += NB) {
+      const int nb = min(NB, n - k0);
+      const int ncol = lower_rhs ? min(nrhs, k0 + nb) : nrhs;
+      lds_load_lower_block(Lk, L, ldl, k0, nb);
+      __syncthreads();
+      for (int c = tid; c < ncol; c += WG) {
+        double *b = B + k0 + (size_t)c * ldb;
+        double x[NB];
 #pragma unroll
-      for (int j = 0; j < NB; ++j) x[j] = (j < nb) ? b[j] : 0.0;
-      lds_lower_solve(Lk, x);
+        for (int j = 0; j < NB; ++j) x[j] = (j < nb) ? b[j] : 0.0;
+        lds_lower_solve(Lk, x);
 #pragma unroll
-      for (int j = 0; j < NB; ++j)
-        if (j < nb) b[j] = x[j];
+        for (int j = 0; j < NB; ++j)
+          if (j < nb) b[j] = x[j];
+      }
+      __syncthreads();
+      // the rest of the super-block's rows
+      const int r0 = k0 + nb;
+      if (r0 < kb1)
+        wg_gemm<false, false>(kb1 - r0, ncol, nb, -1.0, L + r0 + (size_t)k0 * ldl, ldl, B + k0, ldb, 1.0,
+                              B + r0, ldb, lds);
     }
-    __syncthreads();
-    const int r0 = k0 + nb;
-    if (r0 < n)
-      wg_gemm<false, false>(n - r0, nrhs, nb, -1.0, L + r0 + (size_t)k0 * ldl, ldl, B + k0, ldb, 1.0,
-                            B + r0, ldb, lds);
+    // delayed update of the rows below by the whole super-block
+    if (kb1 < n) {
+      const int ncol = lower_rhs ? min(nrhs, kb1) : nrhs;
+      wg_gemm<false, false>(n - kb1, ncol, kb1 - kb0, -1.0, L + kb1 + (size_t)kb0 * ldl, ldl, B + kb0, ldb, 1.0,
+                            B + kb1, ldb, lds);
+    }
   }
 }
 

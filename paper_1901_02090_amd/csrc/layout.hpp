@@ -217,19 +217,24 @@ struct Layout {
           }
       }
     }
-    // interface numbering: sorted by global face id
-    std::vector<int64_t> all(lface);
-    std::sort(all.begin(), all.end());
-    all.erase(std::unique(all.begin(), all.end()), all.end());
-    gamma_face = all;
-    nGamma = (int)all.size();
+    // interface numbering: by increasing global face id (a direct map over
+    // the grid faces: mark, then number in order)
+    std::vector<int> gidx(nfaces_all, -1);
+    for (int64_t fl = 0; fl < totG; ++fl) gidx[lface[fl]] = 0;
+    gamma_face.clear();
+    for (int64_t gid = 0; gid < nfaces_all; ++gid)
+      if (gidx[gid] == 0) {
+        gidx[gid] = (int)gamma_face.size();
+        gamma_face.push_back(gid);
+      }
+    nGamma = (int)gamma_face.size();
     own_minus.assign(nGamma, -1);
     own_plus.assign(nGamma, -1);
     sub_minus.assign(nGamma, -1);
     sub_plus.assign(nGamma, -1);
     for (int i = 0; i < N; ++i) {
       for (int64_t fl = g_off[i]; fl < g_off[i + 1]; ++fl) {
-        const int gi = (int)(std::lower_bound(all.begin(), all.end(), lface[fl]) - all.begin());
+        const int gi = gidx[lface[fl]];
         Rmap[fl] = gi;
         if (lg_end[fl] == 1) { own_minus[gi] = (int)fl; sub_minus[gi] = i; }
         else { own_plus[gi] = (int)fl; sub_plus[gi] = i; }
@@ -237,27 +242,6 @@ struct Layout {
     }
     for (int g = 0; g < nGamma; ++g)
       if (own_minus[g] < 0 || own_plus[g] < 0) throw std::logic_error("interface dof without two owners");
-    // partner: the interface dof at the opposite end of the same grid line
-    lg_partner.assign(totG, -1);
-    for (int i = 0; i < N; ++i) {
-      std::vector<int64_t> key(nG[i]);
-      for (int t = 0; t < nG[i]; ++t) {
-        const int64_t fl = g_off[i] + t;
-        const int d = lg_dir[fl];
-        int lc[3] = {lg_cell[fl] % ext[0][i], (lg_cell[fl] / ext[0][i]) % ext[1][i],
-                     lg_cell[fl] / (ext[0][i] * ext[1][i])};
-        lc[d] = 0;
-        key[t] = (int64_t)d * ncells + lc[0] + ext[0][i] * (lc[1] + (int64_t)ext[1][i] * lc[2]);
-      }
-      std::vector<int> ord(nG[i]);
-      for (int t = 0; t < nG[i]; ++t) ord[t] = t;
-      std::sort(ord.begin(), ord.end(), [&](int a, int b) { return key[a] < key[b]; });
-      for (int t = 0; t + 1 < nG[i]; ++t)
-        if (key[ord[t]] == key[ord[t + 1]]) {
-          lg_partner[g_off[i] + ord[t]] = ord[t + 1];
-          lg_partner[g_off[i] + ord[t + 1]] = ord[t];
-        }
-    }
     line_off.assign(N + 1, 0);
     for (int i = 0; i < N; ++i) {
       int64_t cnt = 0;
@@ -265,6 +249,7 @@ struct Layout {
       line_off[i + 1] = line_off[i] + cnt;
     }
     line_g.assign(line_off[N], -1);
+    std::vector<int64_t> line_of(totG);   // first slot of the dof's line in line_g
     for (int i = 0; i < N; ++i) {
       int64_t dbase[3] = {0, 0, 0};
       int64_t acc = line_off[i];
@@ -284,8 +269,12 @@ struct Layout {
         const int l = lc[a0] + ext[a0][i] * lc[a1];
         (void)st;
         line_g[dbase[d] + 2 * l + lg_end[fl]] = t;
+        line_of[fl] = dbase[d] + 2 * l;
       }
     }
+    // partner: the interface dof at the opposite end of the same grid line
+    lg_partner.assign(totG, -1);
+    for (int64_t fl = 0; fl < totG; ++fl) lg_partner[fl] = line_g[line_of[fl] + 1 - lg_end[fl]];
     maxG = 0;
     maxC = 0;
     maxFn = 0;

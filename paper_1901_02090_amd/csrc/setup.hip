@@ -216,7 +216,7 @@ __global__ __launch_bounds__(256, 2) void k_local_setup(DevGeom g, const double 
   wg_symmetrize_lower(nG, S, nG);
   // (7) X = V'^T V' with V' = (I - z z^T) L_P^{-1}
   wg_set_identity(nc, V, nc);
-  wg_trsm_lower(nc, nc, P, nc, V, nc, lds);
+  wg_trsm_lower(nc, nc, P, nc, V, nc, lds, true);
   for (int t = tid; t < nc; t += WG) {
     double *col = V + (size_t)t * nc;
     double dot = 0.0;
@@ -250,7 +250,7 @@ __global__ __launch_bounds__(256, 2) void k_schur_factor(DevGeom g, SetupWs ws, 
   }
   wg_zero_upper(nG, L, nG);
   wg_set_identity(nG, W, nG);
-  wg_trsm_lower(nG, nG, L, nG, W, nG, lds);
+  wg_trsm_lower(nG, nG, L, nG, W, nG, lds, true);
 }
 
 // ---------------------------------------------------------------------------
@@ -321,7 +321,7 @@ __global__ __launch_bounds__(256, 2) void k_face_reduce(DevGeom g, SetupWs ws, d
   }
   wg_zero_upper(n, T1, n);
   wg_set_identity(n, T2, n);
-  wg_trsm_lower(n, n, T1, n, T2, n, lds);
+  wg_trsm_lower(n, n, T1, n, T2, n, lds, true);
   wg_gemm<true, false>(n, n, n, 1.0, T2, n, T2, n, 0.0, YF, n, lds);
   // two-sided reflector on copies: M <- H M H
   for (int e = tid; e < n * n; e += WG) XH[e] = XF[e];
