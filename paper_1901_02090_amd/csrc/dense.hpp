@@ -370,6 +370,37 @@ __device__ __forceinline__ void wg_symmetrize_lower(int n, double *A, int lda) {
   __syncthreads();
 }
 
+// B[:, c] <- B[:, c] - (z . B[:, c]) z for the ncols columns of B (n rows,
+// z of unit length).  Wave w takes columns w, w + 4, ... two at a time; its
+// lanes split the rows and a butterfly sums the dot product.
+__device__ __forceinline__ void wg_project_out(int n, const double *z, int ncols, double *B, int ldb) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  constexpr int NW = WG / 64;
+  for (int c = wv; c < ncols; c += 2 * NW) {
+    const int c2 = min(c + NW, ncols - 1);
+    const bool two = c + NW < ncols;
+    double *b1 = B + (size_t)c * ldb, *b2 = B + (size_t)c2 * ldb;
+    double d1 = 0.0, d2 = 0.0;
+#pragma unroll 4
+    for (int a = lane; a < n; a += 64) {
+      const double za = z[a];
+      d1 += za * b1[a];
+      d2 += za * b2[a];
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      d1 += __shfl_xor(d1, o, 64);
+      d2 += __shfl_xor(d2, o, 64);
+    }
+#pragma unroll 4
+    for (int a = lane; a < n; a += 64) {
+      const double za = z[a];
+      b1[a] -= d1 * za;
+      if (two) b2[a] -= d2 * za;
+    }
+  }
+  __syncthreads();
+}
+
 // Workgroup sum reduction (all threads receive the result).
 __device__ __forceinline__ double wg_sum(double v, double *red) {
   const int tid = threadIdx.x;
@@ -465,23 +496,49 @@ __device__ __forceinline__ void wg_jacobi(int n, double *A, int lda, double *V, 
 }
 
 // The same cyclic Jacobi iteration (ordering, rotations, convergence test)
-// with A and V (both n x n, ld n) in LDS.  A round's row and column rotations
-// are applied in one pass over the disjoint 2 x 2 blocks that the round's
-// pairs cut out of A, so a round needs two barriers.  cs, sn (doubles) and
-// pp, qq (ints) are LDS arrays of at least 128 entries, red 4 doubles.
+// with A and V (both n x n, ld n, n <= 128) in LDS.  A round's row and column
+// rotations are applied in one pass over the disjoint 2 x 2 blocks that the
+// round's pairs cut out of A, so a round needs two barriers.  Lane t of every
+// wave owns row pair t (its indices and rotation stay in registers) and wave
+// w takes the column pairs w, w + 4, ..., four blocks at a time.  cs, sn
+// (doubles) and pp, qq (ints) are LDS arrays of at least 64 entries, red 4
+// doubles.
+__device__ __forceinline__ void jac_block(const double *A, int n, int pt, int qt, bool rq, int pu, int qu,
+                                          double (&v)[4]) {
+  const bool cq = qu < n;
+  v[0] = A[pt + pu * n];
+  v[1] = cq ? A[pt + qu * n] : 0.0;
+  v[2] = rq ? A[qt + pu * n] : 0.0;
+  v[3] = (rq && cq) ? A[qt + qu * n] : 0.0;
+}
+
+__device__ __forceinline__ void jac_rotate_store(double *A, int n, int pt, int qt, bool rq, double ct, double st,
+                                                 int pu, int qu, double cu, double su, const double (&v)[4]) {
+  const bool cq = qu < n;
+  const double a1 = ct * v[0] - st * v[2], c1 = st * v[0] + ct * v[2];
+  const double b1 = ct * v[1] - st * v[3], d1 = st * v[1] + ct * v[3];
+  A[pt + pu * n] = cu * a1 - su * b1;
+  if (cq) A[pt + qu * n] = su * a1 + cu * b1;
+  if (rq) A[qt + pu * n] = cu * c1 - su * d1;
+  if (rq && cq) A[qt + qu * n] = su * c1 + cu * d1;
+}
+
 __device__ __forceinline__ void wg_jacobi_lds(int n, double *A, double *V, double *cs, double *sn, int *pp,
                                               int *qq, double *red, int max_sweeps = 40) {
-  const int tid = threadIdx.x;
-  for (int e = tid; e < n * n; e += WG) V[e] = (e % n == e / n) ? 1.0 : 0.0;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  constexpr int NW = WG / 64;
+  for (int j = wv; j < n; j += NW)
+    for (int i = lane; i < n; i += 64) V[i + j * n] = (i == j) ? 1.0 : 0.0;
   __syncthreads();
   const int m = (n + 1) & ~1;   // even number of players (n odd: one bye)
-  const int npair = m / 2;
+  const int npair = m / 2;      // <= 64
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     double off = 0.0, dia = 0.0;
-    for (int e = tid; e < n * n; e += WG) {
-      const double a = A[e];
-      if (e % n == e / n) dia += a * a; else off += a * a;
-    }
+    for (int j = wv; j < n; j += NW)
+      for (int i = lane; i < n; i += 64) {
+        const double a = A[i + j * n];
+        if (i == j) dia += a * a; else off += a * a;
+      }
     off = wg_sum(off, red);
     dia = wg_sum(dia, red);
     if (off <= 1e-30 * dia || off == 0.0) break;
@@ -509,32 +566,53 @@ __device__ __forceinline__ void wg_jacobi_lds(int n, double *A, double *V, doubl
         qq[tid] = q;
       }
       __syncthreads();
-      // A <- J^T A J on the block of rows {p_t, q_t} and columns {p_u, q_u}
-      for (int e = tid; e < npair * npair; e += WG) {
-        const int t = e % npair, u = e / npair;
-        const int pt = pp[t], qt = qq[t], pu = pp[u], qu = qq[u];
-        const bool rq = qt < n, cq = qu < n;
-        const double ct = cs[t], st = sn[t], cu = cs[u], su = sn[u];
-        const double a = A[pt + pu * n];
-        const double b = cq ? A[pt + qu * n] : 0.0;
-        const double c = rq ? A[qt + pu * n] : 0.0;
-        const double d = (rq && cq) ? A[qt + qu * n] : 0.0;
-        const double a1 = ct * a - st * c, c1 = st * a + ct * c;
-        const double b1 = ct * b - st * d, d1 = st * b + ct * d;
-        A[pt + pu * n] = cu * a1 - su * b1;
-        if (cq) A[pt + qu * n] = su * a1 + cu * b1;
-        if (rq) A[qt + pu * n] = cu * c1 - su * d1;
-        if (rq && cq) A[qt + qu * n] = su * c1 + cu * d1;
+      // A <- J^T A J on the block of rows {p_t, q_t} and columns {p_u, q_u};
+      // U column pairs at a time, all loads before any store (the blocks are
+      // disjoint)
+      constexpr int U = 4;
+      if (lane < npair) {
+        const int pt = pp[lane], qt = qq[lane];
+        const bool rq = qt < n;
+        const double ct = cs[lane], st = sn[lane];
+        for (int u0 = wv; u0 < npair; u0 += U * NW) {
+          int pu[U], qu[U];
+          double cu[U], su[U], v[U][4];
+#pragma unroll
+          for (int j = 0; j < U; ++j) {
+            const int u = min(u0 + j * NW, npair - 1);
+            pu[j] = pp[u]; qu[j] = qq[u]; cu[j] = cs[u]; su[j] = sn[u];
+          }
+#pragma unroll
+          for (int j = 0; j < U; ++j)
+            if (u0 + j * NW < npair) jac_block(A, n, pt, qt, rq, pu[j], qu[j], v[j]);
+#pragma unroll
+          for (int j = 0; j < U; ++j)
+            if (u0 + j * NW < npair) jac_rotate_store(A, n, pt, qt, rq, ct, st, pu[j], qu[j], cu[j], su[j], v[j]);
+        }
       }
-      // V <- V J
-      for (int e = tid; e < n * npair; e += WG) {
-        const int k = e % n, u = e / n;
-        const int pu = pp[u], qu = qq[u];
-        if (qu >= n) continue;
-        const double c = cs[u], s = sn[u];
-        const double vp = V[k + pu * n], vq = V[k + qu * n];
-        V[k + pu * n] = c * vp - s * vq;
-        V[k + qu * n] = s * vp + c * vq;
+      // V <- V J, U column pairs at a time
+      for (int u0 = wv; u0 < npair; u0 += U * NW) {
+        int pu[U], qu[U];
+        double cu[U], su[U];
+        bool ok[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+          const int u = min(u0 + j * NW, npair - 1);
+          pu[j] = pp[u]; qu[j] = qq[u]; cu[j] = cs[u]; su[j] = sn[u];
+          ok[j] = (u0 + j * NW < npair) && qu[j] < n;
+        }
+        for (int k = lane; k < n; k += 64) {
+          double vp[U], vq[U];
+#pragma unroll
+          for (int j = 0; j < U; ++j)
+            if (ok[j]) { vp[j] = V[k + pu[j] * n]; vq[j] = V[k + qu[j] * n]; }
+#pragma unroll
+          for (int j = 0; j < U; ++j)
+            if (ok[j]) {
+              V[k + pu[j] * n] = cu[j] * vp[j] - su[j] * vq[j];
+              V[k + qu[j] * n] = su[j] * vp[j] + cu[j] * vq[j];
+            }
+        }
       }
       __syncthreads();
     }

@@ -204,26 +204,14 @@ __global__ __launch_bounds__(256, 2) void k_local_setup(DevGeom g, const double 
   for (int a = tid; a < nc; a += WG) zc[a] *= zinv;
   __syncthreads();
   // Y' = (I - z z^T) Y  (the projection realises the zero-mean constraint)
-  for (int t = tid; t < nG; t += WG) {
-    double *col = H + (size_t)t * ldh;
-    double dot = 0.0;
-    for (int a = 0; a < nc; ++a) dot += zc[a] * col[a];
-    for (int a = 0; a < nc; ++a) col[a] -= dot * zc[a];
-  }
-  __syncthreads();
+  wg_project_out(nc, zc, nG, H, ldh);
   // (6) S = S_A + Y'^T Y'
   wg_gemm<true, false, true>(nG, nG, nc, 1.0, H, ldh, H, ldh, 1.0, S, nG, lds);
   wg_symmetrize_lower(nG, S, nG);
   // (7) X = V'^T V' with V' = (I - z z^T) L_P^{-1}
   wg_set_identity(nc, V, nc);
   wg_trsm_lower(nc, nc, P, nc, V, nc, lds, true);
-  for (int t = tid; t < nc; t += WG) {
-    double *col = V + (size_t)t * nc;
-    double dot = 0.0;
-    for (int a = 0; a < nc; ++a) dot += zc[a] * col[a];
-    for (int a = 0; a < nc; ++a) col[a] -= dot * zc[a];
-  }
-  __syncthreads();
+  wg_project_out(nc, zc, nc, V, nc);
   wg_gemm<true, false, true>(nc, nc, nc, 1.0, V, nc, V, nc, 0.0, X, nc, lds);
   wg_symmetrize_lower(nc, X, nc);
 }
@@ -557,17 +545,37 @@ __global__ __launch_bounds__(256) void k_coarse_local(DevGeom g, SetupWs ws, Dev
   for (int jc = 0; jc < nci; ++jc) {
     double *qj = Q + (size_t)jc * nG;
     for (int pass = 0; pass < 2; ++pass) {
-      // d_k = q_k . q_j for k < j (thread per k)
-      for (int kk = tid; kk < jc; kk += WG) {
-        const double *qk = Q + (size_t)kk * nG;
-        double s = 0.0;
-        for (int r = 0; r < nG; ++r) s += qk[r] * qj[r];
-        lds[kk] = s;
+      // d_k = q_k . q_j for k < j: wave w takes k = w, w + 4, ... (two at a
+      // time), its lanes split the rows and a butterfly sums them
+      {
+        const int lane = tid & 63, wv = tid >> 6;
+        constexpr int NW = WG / 64;
+        for (int kk = wv; kk < jc; kk += 2 * NW) {
+          const int k2 = kk + NW;
+          const double *qa = Q + (size_t)kk * nG;
+          const double *qb = Q + (size_t)min(k2, jc - 1) * nG;
+          double sa = 0.0, sb = 0.0;
+#pragma unroll 4
+          for (int r = lane; r < nG; r += 64) {
+            const double x = qj[r];
+            sa += qa[r] * x;
+            sb += qb[r] * x;
+          }
+          for (int o = 32; o > 0; o >>= 1) {
+            sa += __shfl_xor(sa, o, 64);
+            sb += __shfl_xor(sb, o, 64);
+          }
+          if (lane == 0) {
+            lds[kk] = sa;
+            if (k2 < jc) lds[k2] = sb;
+          }
+        }
       }
       __syncthreads();
       for (int kk = tid; kk < jc; kk += WG) R[kk + (size_t)jc * nci] += lds[kk];
       for (int r = tid; r < nG; r += WG) {
         double s = qj[r];
+#pragma unroll 8
         for (int kk = 0; kk < jc; ++kk) s -= Q[r + (size_t)kk * nG] * lds[kk];
         qj[r] = s;
       }
@@ -588,6 +596,7 @@ __global__ __launch_bounds__(256) void k_coarse_local(DevGeom g, SetupWs ws, Dev
   for (int r = tid; r < nG; r += WG) {
     for (int jj = nci - 1; jj >= 0; --jj) {
       double s = Q[r + (size_t)jj * nG];
+#pragma unroll 8
       for (int l = jj + 1; l < nci; ++l) s -= U[r + (size_t)l * nG] * R[jj + (size_t)l * nci];
       U[r + (size_t)jj * nG] = s / R[jj + (size_t)jj * nci];
     }
