@@ -23,6 +23,7 @@
 #include "setup.hip"
 #include "solve.hip"
 #include "coarse.hip"
+#include "front.hip"
 
 using namespace bddc;
 

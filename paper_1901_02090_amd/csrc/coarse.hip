@@ -3,15 +3,9 @@
 // multifrontal signed Cholesky K = L diag(s) L^T over the nested-dissection
 // fronts of nd.hpp (s = +1 on face dofs, -1 on pressures).
 //
-// Setup, one launch per level, one workgroup per front p (own dofs P, n of
-// them, later dofs B, m of them):
-//   F = [K_PP K_PB; K_BP K_BB]-part assembled from the local coarse matrices
-//       A_c^i and divergence rows, plus the children's update matrices;
-//   partial factor: L_PP, L_BP = K_BP L_PP^{-T} s_P, U = F_BB - L_BP s_P L_BP^T
-//       (U stays in F for the parent's extend-add);
-//   stored per front: R = [L_PP^{-1}; L_BP L_PP^{-1}] ((n+m) x n, the first
-//       block lower triangular), row-packed for the forward sweep and
-//       column-packed for the backward sweep.
+// The fronts are assembled and factored at setup (front.hip); the stored
+// per-front R = [L_PP^{-1}; L_BP L_PP^{-1}] is applied here.
+//
 // Solve (a front's results go straight into contiguous vectors of the fronts
 // that read them next; one dataflow launch, or one launch per level and
 // direction):
@@ -29,110 +23,12 @@
 
 namespace bddc {
 
-struct DevFronts {
-  const int *first, *n, *m, *ch, *b_off, *bidx, *ext, *touch_off, *touch;
-  const int64_t *F_off, *w_off, *q_off, *r_off, *v_off;
-};
-
 struct DevSweep {
   const int *wdst;                 // forward push target of every B row
   const int *xsc_off, *xsc;        // backward: B-vector positions holding x[d]
   const int4 *task;                // four int4 per task (nd.hpp)
   int nfr;                         // fronts (counters: nfr forward, nfr backward, 1 exit)
 };
-
-// Assemble, partially factor and invert the fronts [f0, f0 + gridDim.x) of one
-// level.  F, W (n x n), Q (m x n) are workspaces; FR / BC receive R.
-__global__ __launch_bounds__(256, 2) void k_front_factor(DevGeom g, DevCoarse cs, DevFronts fd, int f0,
-                                                      const double *__restrict__ Ac, const int64_t *__restrict__ ac_off,
-                                                      const double *__restrict__ dscale,
-                                                      const double *__restrict__ sgn, double *F, double *W,
-                                                      double *Q, double *FR, double *BC, int *err) {
-  __shared__ double lds[LDS_DOUBLES];
-  const int p = f0 + blockIdx.x, tid = threadIdx.x;
-  const int first = fd.first[p], n = fd.n[p], m = fd.m[p], f = n + m;
-  const int *Bp = fd.bidx + fd.b_off[p];
-  double *Fp = F + fd.F_off[p];
-  for (int64_t e = tid; e < (int64_t)f * f; e += WG) Fp[e] = 0.0;
-  __syncthreads();
-  // position of coarse dof u >= first in [P, B]; -1 if absent
-  auto pos = [&](int u) -> int {
-    if (u < first + n) return u - first;
-    int lo = 0, hi = m;
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if (Bp[mid] < u) lo = mid + 1; else hi = mid;
-    }
-    return (lo < m && Bp[lo] == u) ? n + lo : -1;
-  };
-  // original entries K(u, v), u >= v, v in P: subdomain by subdomain, so a
-  // face entry shared by two subdomains is summed in a fixed order
-  for (int t = fd.touch_off[p]; t < fd.touch_off[p + 1]; ++t) {
-    const int i = fd.touch[t];
-    const int c0 = cs.sub_coff[i], nci = cs.sub_coff[i + 1] - c0;
-    const double *A = Ac + ac_off[i];
-    for (int e = tid; e < nci * nci; e += WG) {
-      const int a = e % nci, b = e / nci;
-      const int u = cs.sub_cmap[c0 + a], v = cs.sub_cmap[c0 + b];
-      if (u < v || v < first || v >= first + n) continue;
-      const int pu = pos(u);
-      if (pu < 0) { atomicOr(err, 128); continue; }
-      Fp[pu + (size_t)(v - first) * f] += A[e];
-    }
-    const int pi = cs.pidx[i];
-    if (pi >= 0) {
-      // divergence row of subdomain i: -d_i * (+1 if the face normal leaves Omega^i)
-      for (int t2 = g.sub_face_off[i] + tid; t2 < g.sub_face_off[i + 1]; t2 += WG) {
-        const int fc = g.sub_faces[t2];
-        const int jf = cs.face_cofs[fc];
-        if (jf < first || jf >= first + n) continue;
-        const double so = (g.f_minus[fc] == i) ? 1.0 : -1.0;
-        const int pp = pos(pi);
-        if (pp < 0 || pi < jf) { atomicOr(err, 128); continue; }
-        Fp[pp + (size_t)(jf - first) * f] += -dscale[i] * so;
-      }
-    }
-    __syncthreads();
-  }
-  // extend-add of the children's update matrices (lower triangles)
-  for (int k = 0; k < 2; ++k) {
-    const int c = fd.ch[2 * p + k];
-    if (c < 0) continue;
-    const int nc = fd.n[c], mc = fd.m[c], fc = nc + mc;
-    const double *Uc = F + fd.F_off[c] + nc + (size_t)nc * fc;
-    const int *ex = fd.ext + fd.b_off[c];
-    for (int64_t e = tid; e < (int64_t)mc * mc; e += WG) {
-      const int k1 = (int)(e % mc), k2 = (int)(e / mc);
-      if (k1 < k2) continue;
-      Fp[ex[k1] + (size_t)ex[k2] * f] += Uc[k1 + (size_t)k2 * fc];
-    }
-    __syncthreads();
-  }
-  if (wg_potrf(n, Fp, f, lds, sgn + first, f)) {
-    if (tid == 0) atomicOr(err, 64);
-  }
-  double *Wp = W + fd.w_off[p];
-  wg_set_identity(n, Wp, n);
-  wg_trsm_lower(n, n, Fp, f, Wp, n, lds, true);
-  double *Qp = Q + fd.q_off[p];
-  if (m > 0) wg_gemm<false, false>(m, n, n, 1.0, Fp + n, f, Wp, n, 0.0, Qp, m, lds);
-  double *R = FR + fd.r_off[p];
-  double *C = BC + fd.r_off[p];
-  const int64_t tri = (int64_t)n * (n + 1) / 2;
-  for (int64_t e = tid; e < (int64_t)n * n; e += WG) {
-    const int r = (int)(e % n), c = (int)(e / n);
-    if (r < c) continue;
-    const double v = Wp[e];
-    R[(int64_t)r * (r + 1) / 2 + c] = v;
-    C[(int64_t)c * f - (int64_t)c * (c - 1) / 2 + (r - c)] = v;
-  }
-  for (int64_t e = tid; e < (int64_t)m * n; e += WG) {
-    const int k = (int)(e % m), c = (int)(e / m);
-    const double v = Qp[e];
-    R[tri + (int64_t)k * n + c] = v;
-    C[(int64_t)c * f - (int64_t)c * (c - 1) / 2 + (n - c) + k] = v;
-  }
-}
 
 // ---- per-solve sweeps --------------------------------------------------------
 template <int W>

@@ -1,0 +1,130 @@
+// Setup of the coarse saddle point's multifrontal signed Cholesky
+// K = L diag(s) L^T (step 1 of Algorithm "BDDC preconditioner"; coarse.hip
+// applies the result), one launch per nested-dissection level, one workgroup
+// per front p (own dofs P, n of them, later dofs B, m of them):
+//   F = [K_PP K_PB; K_BP K_BB]-part assembled from the local coarse matrices
+//       A_c^i and divergence rows, plus the children's update matrices;
+//   partial factor: L_PP, L_BP = K_BP L_PP^{-T} s_P, U = F_BB - L_BP s_P L_BP^T
+//       (U stays in F for the parent's extend-add);
+//   stored per front: R = [L_PP^{-1}; L_BP L_PP^{-1}] ((n+m) x n, the first
+//       block lower triangular), row-packed for the forward sweep and
+//       column-packed for the backward sweep.
+#include "common.hpp"
+#include "dense.hpp"
+
+namespace bddc {
+
+struct DevFronts {
+  const int *first, *n, *m, *ch, *b_off, *bidx, *ext, *touch_off, *touch;
+  const int64_t *F_off, *w_off, *q_off, *r_off, *v_off;
+};
+
+// Assemble, partially factor and invert the fronts [f0, f0 + gridDim.x) of one
+// level.  F, W (n x n), Q (m x n) are workspaces; FR / BC receive R.
+__global__ __launch_bounds__(256, 2) void k_front_factor(DevGeom g, DevCoarse cs, DevFronts fd, int f0,
+                                                      const double *__restrict__ Ac, const int64_t *__restrict__ ac_off,
+                                                      const double *__restrict__ dscale,
+                                                      const double *__restrict__ sgn, double *F, double *W,
+                                                      double *Q, double *FR, double *BC, int *err) {
+  __shared__ double lds[LDS_DOUBLES];
+  const int p = f0 + blockIdx.x, tid = threadIdx.x;
+  const int first = fd.first[p], n = fd.n[p], m = fd.m[p], f = n + m;
+  const int *Bp = fd.bidx + fd.b_off[p];
+  double *Fp = F + fd.F_off[p];
+  for (int64_t e = tid; e < (int64_t)f * f; e += WG) Fp[e] = 0.0;
+  __syncthreads();
+  // position of coarse dof u >= first in [P, B]; -1 if absent
+  auto pos = [&](int u) -> int {
+    if (u < first + n) return u - first;
+    int lo = 0, hi = m;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (Bp[mid] < u) lo = mid + 1; else hi = mid;
+    }
+    return (lo < m && Bp[lo] == u) ? n + lo : -1;
+  };
+  // original entries K(u, v), u >= v, v in P: subdomain by subdomain, so a
+  // face entry shared by two subdomains is summed in a fixed order
+  for (int t = fd.touch_off[p]; t < fd.touch_off[p + 1]; ++t) {
+    const int i = fd.touch[t];
+    const int c0 = cs.sub_coff[i], nci = cs.sub_coff[i + 1] - c0;
+    const double *A = Ac + ac_off[i];
+    for (int e = tid; e < nci * nci; e += WG) {
+      const int a = e % nci, b = e / nci;
+      const int u = cs.sub_cmap[c0 + a], v = cs.sub_cmap[c0 + b];
+      if (u < v || v < first || v >= first + n) continue;
+      const int pu = pos(u);
+      if (pu < 0) { atomicOr(err, 128); continue; }
+      Fp[pu + (size_t)(v - first) * f] += A[e];
+    }
+    const int pi = cs.pidx[i];
+    if (pi >= 0) {
+      // divergence row of subdomain i: -d_i * (+1 if the face normal leaves Omega^i)
+      for (int t2 = g.sub_face_off[i] + tid; t2 < g.sub_face_off[i + 1]; t2 += WG) {
+        const int fc = g.sub_faces[t2];
+        const int jf = cs.face_cofs[fc];
+        if (jf < first || jf >= first + n) continue;
+        const double so = (g.f_minus[fc] == i) ? 1.0 : -1.0;
+        const int pp = pos(pi);
+        if (pp < 0 || pi < jf) { atomicOr(err, 128); continue; }
+        Fp[pp + (size_t)(jf - first) * f] += -dscale[i] * so;
+      }
+    }
+    __syncthreads();
+  }
+  // extend-add of the children's update matrices (lower triangles): wave w
+  // takes columns w, w + 4, ...; its lanes run down the column four rows at a
+  // time (ex is one-to-one, so the four targets are distinct)
+  const int lane = tid & 63, wv = tid >> 6;
+  constexpr int NW = WG / 64;
+  for (int k = 0; k < 2; ++k) {
+    const int c = fd.ch[2 * p + k];
+    if (c < 0) continue;
+    const int nc = fd.n[c], mc = fd.m[c], fc = nc + mc;
+    const double *Uc = F + fd.F_off[c] + nc + (size_t)nc * fc;
+    const int *ex = fd.ext + fd.b_off[c];
+    for (int k2 = wv; k2 < mc; k2 += NW) {
+      double *Fcol = Fp + (size_t)ex[k2] * f;
+      const double *Ucol = Uc + (size_t)k2 * fc;
+      int k1 = k2 + lane;
+      for (; k1 + 192 < mc; k1 += 256) {
+        const int e0 = ex[k1], e1 = ex[k1 + 64], e2 = ex[k1 + 128], e3 = ex[k1 + 192];
+        const double u0 = Ucol[k1], u1 = Ucol[k1 + 64], u2 = Ucol[k1 + 128], u3 = Ucol[k1 + 192];
+        const double v0 = Fcol[e0], v1 = Fcol[e1], v2 = Fcol[e2], v3 = Fcol[e3];
+        Fcol[e0] = v0 + u0;
+        Fcol[e1] = v1 + u1;
+        Fcol[e2] = v2 + u2;
+        Fcol[e3] = v3 + u3;
+      }
+      for (; k1 < mc; k1 += 64) Fcol[ex[k1]] += Ucol[k1];
+    }
+    __syncthreads();
+  }
+  if (wg_potrf(n, Fp, f, lds, sgn + first, f)) {
+    if (tid == 0) atomicOr(err, 64);
+  }
+  double *Wp = W + fd.w_off[p];
+  wg_set_identity(n, Wp, n);
+  wg_trsm_lower(n, n, Fp, f, Wp, n, lds, true);
+  double *Qp = Q + fd.q_off[p];
+  if (m > 0) wg_gemm<false, false>(m, n, n, 1.0, Fp + n, f, Wp, n, 0.0, Qp, m, lds);
+  double *R = FR + fd.r_off[p];
+  double *C = BC + fd.r_off[p];
+  const int64_t tri = (int64_t)n * (n + 1) / 2;
+  // packing: wave per column c, lanes down the rows r >= c (then the m rows of Q)
+  for (int c = wv; c < n; c += NW) {
+    double *Cc = C + (int64_t)c * f - (int64_t)c * (c - 1) / 2;
+    for (int r = c + lane; r < n; r += 64) {
+      const double v = Wp[r + (size_t)c * n];
+      R[(int64_t)r * (r + 1) / 2 + c] = v;
+      Cc[r - c] = v;
+    }
+    for (int k = lane; k < m; k += 64) {
+      const double v = Qp[k + (size_t)c * m];
+      R[tri + (int64_t)k * n + c] = v;
+      Cc[(n - c) + k] = v;
+    }
+  }
+}
+
+}  // namespace bddc
