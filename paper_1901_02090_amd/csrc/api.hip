@@ -637,14 +637,35 @@ void do_setup(bddc_problem *h, const bddc_grid *gr, const double *perm, const bd
       if (pidx[i] >= 0) sg[pidx[i]] = -1.0;
     h->csgn = h->upload(sg);
     check_coarse_ptrs(h);
+    // tiles of the update matrices, level by level
+    std::vector<int> tl_off(P.H + 1, 0);
+    std::vector<int> tl;
+    for (int lv = 0; lv < P.H; ++lv) {
+      for (int r = P.lvl_off[lv]; r < P.lvl_off[lv + 1]; ++r)
+        for (int i0 = 0; i0 < P.m[r]; i0 += TILE)
+          for (int j0 = 0; j0 <= i0; j0 += TILE) {
+            tl.push_back(r);
+            tl.push_back(i0);
+            tl.push_back(j0);
+            tl.push_back(0);
+          }
+      tl_off[lv + 1] = (int)(tl.size() / 4);
+    }
+    const int4 *d_tl = (const int4 *)h->upload(tl);
     for (int lv = 0; lv < P.H; ++lv) {
       const int f0 = P.lvl_off[lv], nf = P.lvl_off[lv + 1] - f0;
       k_front_factor<<<nf, 256, 0, s>>>(g, cs, fd, f0, cw.Ac, cw.ac_off, h->dscale, h->csgn, Fall, Wall, Qall,
                                         h->FR, h->BC, h->d_err);
       HIPCHK(hipGetLastError());
+      const int nt = tl_off[lv + 1] - tl_off[lv];
+      if (nt > 0) {
+        k_front_schur<<<nt, 256, 0, s>>>(fd, d_tl + tl_off[lv], h->csgn, Fall);
+        HIPCHK(hipGetLastError());
+      }
     }
     HIPCHK(hipStreamSynchronize(s));
     check_err(h, "the coarse problem");
+    h->release((void *)d_tl);
     h->release(Fall);
     h->release(Wall);
     h->release(Qall);

@@ -220,9 +220,12 @@ __device__ __forceinline__ void lds_lower_t_solve(const double *Lk, double (&x)[
 // With nrows > n only the first n pivots are taken over the nrows x nrows
 // lower triangle: rows n.. receive the panel A_{2,1} L_11^{-T} diag(s) and the
 // trailing block the update A_22 - L_21 diag(s) L_21^T.
+// defer_bb (with nrows > n): the trailing block A[n:, n:] is left untouched;
+// the caller applies A[n:, n:] -= L_21 diag(s) L_21^T itself.
 __device__ __forceinline__ int wg_potrf(int n, double *A, int lda, double *lds, const double *s = nullptr,
-                                        int nrows = -1) {
+                                        int nrows = -1, bool defer_bb = false) {
   const int nr = nrows < 0 ? n : nrows;
+  const int ncu = defer_bb ? n : nr;   // trailing updates reach columns < ncu
   double *Lk = lds + 2 * KT * TILE;  // NB x NB
   double *sk = Lk + NB * NB;         // NB signs
   int *flag = (int *)(sk + NB);      // pivot-failure word
@@ -265,9 +268,9 @@ __device__ __forceinline__ int wg_potrf(int n, double *A, int lda, double *lds, 
       }
     }
     // delayed trailing update by the whole super-block (lower triangle only)
-    if (kb1 < nr) {
+    if (kb1 < nr && kb1 < ncu) {
       double *X = A + kb1 + (size_t)kb0 * lda;
-      wg_gemm<false, true, true>(nr - kb1, nr - kb1, kb1 - kb0, -1.0, X, lda, X, lda, 1.0,
+      wg_gemm<false, true, true>(nr - kb1, ncu - kb1, kb1 - kb0, -1.0, X, lda, X, lda, 1.0,
                                  A + kb1 + (size_t)kb1 * lda, lda, lds, s ? s + kb0 : nullptr);
     }
   }

@@ -100,7 +100,8 @@ __global__ __launch_bounds__(256, 2) void k_front_factor(DevGeom g, DevCoarse cs
     }
     __syncthreads();
   }
-  if (wg_potrf(n, Fp, f, lds, sgn + first, f)) {
+  // U = F_BB - L_BP s_P L_BP^T is left to k_front_schur (many workgroups)
+  if (wg_potrf(n, Fp, f, lds, sgn + first, f, true)) {
     if (tid == 0) atomicOr(err, 64);
   }
   double *Wp = W + fd.w_off[p];
@@ -125,6 +126,22 @@ __global__ __launch_bounds__(256, 2) void k_front_factor(DevGeom g, DevCoarse cs
       Cc[(n - c) + k] = v;
     }
   }
+}
+
+// The update matrices of one level's fronts, U = F_BB - L_BP diag(s_P) L_BP^T,
+// one 64 x 64 tile of a lower triangle per workgroup; tiles[b] = (front,
+// first row, first column).  Large fronts near the root get as many
+// workgroups as they have tiles instead of one.
+__global__ __launch_bounds__(256) void k_front_schur(DevFronts fd, const int4 *__restrict__ tiles,
+                                                     const double *__restrict__ sgn, double *F) {
+  __shared__ double lds[2 * KT * TILE];
+  const int4 t = tiles[blockIdx.x];
+  const int p = t.x;
+  const int n = fd.n[p], m = fd.m[p], f = n + m;
+  double *Fp = F + fd.F_off[p];
+  const double *X = Fp + n;                 // L_BP, m x n, ld f
+  wg_gemm_tile<false, true, true>(t.y, t.z, m, m, n, -1.0, X, f, X, f, 1.0, Fp + n + (size_t)n * f, f, lds,
+                                  sgn + fd.first[p]);
 }
 
 }  // namespace bddc
