@@ -291,13 +291,23 @@ def main():
                     help="set up the mixed form, solve once, launch the S^i and T^i apply kernels alone, the "
                          "whole preconditioner, and a plain device copy of known size (for scaling hardware "
                          "byte counters), then exit")
+    ap.add_argument("--alloc", default="torch", choices=["torch", "hip"],
+                    help="device memory of the solver handles: torch's caching allocator through "
+                         "bddc_set_allocator (default), or the library's own hipMalloc / hipFree.  With hipFree "
+                         "the tens of GB of setup workspace released at the end of a setup slow the solves of "
+                         "the following half second or so by about 2%%")
     args = ap.parse_args()
     if args.gpus != 1:
         print("this benchmark runs on exactly one GPU: the solver is a single-GPU build "
               "(--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
 
+    if args.alloc == "torch":
+        import torch
+        from paper_1901_02090_amd import set_allocator
+        set_allocator(torch.cuda.caching_allocator_alloc, torch.cuda.caching_allocator_delete)
     pr, desc = make_workload(args.workload)
+    desc = dict(desc, allocator="torch caching allocator" if args.alloc == "torch" else "hipMalloc")
     if args.kernels_only:
         kernels_only(pr, args.steps)
         return

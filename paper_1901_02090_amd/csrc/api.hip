@@ -116,6 +116,7 @@ struct bddc_problem {
   double *alpha_h = nullptr, *beta_h = nullptr;
   CgState *st = nullptr;
   CgState *st_host = nullptr;                     // [2] pinned: state after chunk k lands in [k & 1]
+  double *ab_host = nullptr;                      // pinned: CG alpha / beta history of the last solve
   hipEvent_t ev_state[2] = {nullptr, nullptr};    // recorded after each chunk's state copy
   // the solve in progress (solve_begin ... solve_finish)
   struct Run {
@@ -196,6 +197,7 @@ struct bddc_problem {
     if (side) (void)hipStreamDestroy(side);
     if (own_stream) (void)hipStreamDestroy(own_stream);
     if (st_host) (void)hipHostFree(st_host);
+    if (ab_host) (void)hipHostFree(ab_host);
     for (size_t k = 0; k < allocs.size(); ++k) free_at(k);
   }
 };
@@ -699,6 +701,7 @@ void do_setup(bddc_problem *h, const bddc_grid *gr, const double *perm, const bd
   h->beta_h = h->alloc<double>(h->max_it + 2);
   h->st = h->alloc<CgState>(1);
   HIPCHK(hipHostMalloc((void **)&h->st_host, 2 * sizeof(CgState), hipHostMallocDefault));
+  HIPCHK(hipHostMalloc((void **)&h->ab_host, 2 * (size_t)(h->max_it + 2) * sizeof(double), hipHostMallocDefault));
   for (hipEvent_t &e : h->ev_state) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   HIPCHK(hipEventCreate(&h->ev0));
   HIPCHK(hipEventCreate(&h->ev1));
@@ -759,7 +762,7 @@ void launch_coarse_solve(bddc_problem *h, hipStream_t s, const int *done) {
 // A dataflow sweep that timed out leaves the abort word set (and its results
 // invalid); report it and clear the word.
 void check_flow(bddc_problem *h) {
-  if (!h->cabort) return;
+  if (!h->cabort || !h->coarse_dataflow) return;
   int ab = 0;
   HIPCHK(hipMemcpy(&ab, h->cabort, sizeof(int), hipMemcpyDeviceToHost));
   if (ab) {
@@ -1051,23 +1054,18 @@ int solve_finish_locked(bddc_problem *h) {
   int iters = 0, converged = 1, fail = 0;
   double relres = 0.0;
   float pcg_ms = 0.f;
-  if (solve_needs_cg(h)) {
-    const CgState &fs = h->st_host[(R.chunks - 1) & 1];
+  // Everything below is enqueued behind the CG and the host waits once, at the
+  // end: the CG coefficients for the condition estimate come back through
+  // pinned memory (at most CG_CHUNK iterations per chunk were run).
+  const bool cg = solve_needs_cg(h);
+  const int it_bound = std::min(h->max_it + 1, R.chunks * CG_CHUNK + 1);
+  if (cg) {
     HIPCHK(hipEventRecord(h->ev1, s));
-    HIPCHK(hipEventSynchronize(h->ev1));
-    HIPCHK(hipEventElapsedTime(&pcg_ms, h->ev0, h->ev1));
-    iters = fs.nupd;
-    converged = fs.converged;
-    fail = fs.fail;
-    relres = fs.relres;
-    // Lanczos estimate from the CG coefficients
-    std::vector<double> a(iters), b(iters > 0 ? iters - 1 : 0);
-    if (iters > 0) HIPCHK(hipMemcpy(a.data(), h->alpha_h, iters * sizeof(double), hipMemcpyDeviceToHost));
-    if (iters > 1) HIPCHK(hipMemcpy(b.data(), h->beta_h, (iters - 1) * sizeof(double), hipMemcpyDeviceToHost));
-    double lmin = 1, lmax = 1;
-    h->stats.kappa = lanczos_kappa(a, b, &lmin, &lmax);
-    h->stats.lambda_min = lmin;
-    h->stats.lambda_max = lmax;
+    if (it_bound > 0) {
+      double *ah = h->ab_host, *bh = h->ab_host + (h->max_it + 2);
+      HIPCHK(hipMemcpyAsync(ah, h->alpha_h, it_bound * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(bh, h->beta_h, it_bound * sizeof(double), hipMemcpyDeviceToHost, s));
+    }
     // final interface flux
     k_axpby<<<nblk(nGm), 256, 0, s>>>(nGm, 1.0, h->u0, 1.0, h->xu, h->uG);
   }
@@ -1087,6 +1085,21 @@ int solve_finish_locked(bddc_problem *h) {
   }
   HIPCHK(hipStreamSynchronize(s));
   check_flow(h);
+  if (cg) {
+    const CgState &fs = h->st_host[(R.chunks - 1) & 1];
+    HIPCHK(hipEventElapsedTime(&pcg_ms, h->ev0, h->ev1));
+    iters = std::min(fs.nupd, it_bound);
+    converged = fs.converged;
+    fail = fs.fail;
+    relres = fs.relres;
+    // Lanczos estimate from the CG coefficients
+    std::vector<double> a(h->ab_host, h->ab_host + iters),
+        b(h->ab_host + (h->max_it + 2), h->ab_host + (h->max_it + 2) + (iters > 0 ? iters - 1 : 0));
+    double lmin = 1, lmax = 1;
+    h->stats.kappa = lanczos_kappa(a, b, &lmin, &lmax);
+    h->stats.lambda_min = lmin;
+    h->stats.lambda_max = lmax;
+  }
   h->stats.it = iters;
   h->stats.converged = converged;
   h->stats.relres = relres;
