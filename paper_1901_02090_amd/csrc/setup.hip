@@ -13,7 +13,7 @@
 //     S^i = (A_GG - A_GI G A_IG) + H^T X H with H = B_G - B_I G A_IG and X the
 //     generalized inverse of P on the zero-mean subspace;
 //   * the pair eigenproblems of every face (eq. eigenvalue-problem-local-matrix)
-//     in reduced form (see k_face_eig) and the adaptive rows (eq. constraints,
+//     in reduced form (see k_face_reduce) and the adaptive rows (eq. constraints,
 //     Algorithm "Adaptive BDDC");
 //   * the coarse basis Psi^i, the coarse matrix block A_c^i and the substructure
 //     operator T^i of Algorithm "BDDC preconditioner" from one Cholesky factor
