@@ -91,13 +91,25 @@ def time_gpu(pr, precision, steps, warmup, kernel_reps=0):
             for _ in range(3):
                 s.solve(pr.source, rtol=pr.rtol)
             host_ms = (time.perf_counter() - t_h) / 3 * 1e3
+        # approximation quality of steps 1-2 (eq. epsilon): u_0 and u^* against the converged flux
+        eps = None
+        if kernel_reps > 0:
+            fu = flux.cpu().numpy()
+            ref = np.linalg.norm(fu)
+            eps = {}
+            for name, steps_flag in (("eps0", 1), ("eps_star", 12)):
+                f2 = torch.empty_like(flux)
+                p2 = torch.empty_like(pres)
+                s.solve_device(src.data_ptr(), pr.rtol, f2.data_ptr(), p2.data_ptr(), steps=steps_flag)
+                torch.cuda.synchronize()
+                eps[name] = float(np.linalg.norm(f2.cpu().numpy() - fu) / ref)
         kern = {}
         if kernel_reps > 0:
             kern["schur"] = s.time_kernel(K_SCHUR_APPLY, kernel_reps)
             kern["precond"] = s.time_kernel(K_PRECOND_APPLY, kernel_reps)
             kern["precond_full"] = s.time_kernel(K_PRECOND_FULL, kernel_reps)
         return dict(setup_s=setup_s, total_s=total, lat=np.array(lat), stats=st, kernels=kern, host_ms=host_ms,
-                    flux=flux.cpu().numpy(), pres=pres.cpu().numpy())
+                    flux=flux.cpu().numpy(), pres=pres.cpu().numpy(), eps=eps)
     finally:
         s.close()
 
@@ -369,6 +381,8 @@ def main():
                  "iterations": r64["stats"]["it"], "setup_ms": r64["setup_s"] * 1e3},
         "mixed_vs_fp64": {"flux_relerr": float(np.linalg.norm(rmx["flux"] - ref_u) / np.linalg.norm(ref_u)),
                           "pressure_relerr": float(np.linalg.norm(rmx["pres"] - ref_p) / np.linalg.norm(ref_p))},
+        "steps12": dict(rmx["eps"] or {}, note="relative flux errors of u_0 (step 1) and u^* (steps 1-2) "
+                                              "against the converged solve, eq. epsilon"),
         "roofline": roof,
         "precond_apply": prec,
     }

@@ -63,6 +63,8 @@ extern "C" {
 #define BDDC_DEVICE_PTRS 1u      /* rhs, flux and pressure are device pointers   */
 #define BDDC_EAGER       2u      /* launch the CG iterations kernel by kernel
                                     instead of replaying the captured graph     */
+#define BDDC_STEP1_ONLY  4u      /* return u_0 of step 1 (see bddc_solve)        */
+#define BDDC_STEP12_ONLY 8u      /* return u^* of steps 1-2 (see bddc_solve)     */
 
 typedef struct bddc_problem *bddc_handle;
 
@@ -153,6 +155,15 @@ int bddc_setup(const bddc_grid *g, const double *perm, const bddc_partition *par
  *              captures a chunk of eight CG iterations (both streams) into a
  *              HIP graph that later chunks and solves replay; both ways run
  *              the same kernels on the same data and give identical results.
+ *              BDDC_STEP1_ONLY / BDDC_STEP12_ONLY (at most one of the two) stop
+ *              before the CG and return the approximations whose errors the
+ *              paper reports as epsilon_0 and epsilon^* (eq. epsilon, Section 6):
+ *              u_0 = E Psi alpha_0 on the interface, continued into every
+ *              subdomain by the local saddle point with zero source (the
+ *              coarse solution of step 1), or u^* = u_0 plus the substructure
+ *              components of step 2 (the local saddle points with the source
+ *              and interface flux u_0).  The pressure output is that of the
+ *              same local problems.  Statistics report 0 iterations.
  * Returns BDDC_OK, BDDC_ENOCONV (outputs hold the last iterate),
  * BDDC_EBREAKDOWN, BDDC_EINVAL, BDDC_EDEVICE.
  */

@@ -16,6 +16,8 @@ BDDC_ALL_CONSTRAINED = 1
 BDDC_COARSE_DATAFLOW = 2
 BDDC_DEVICE_PTRS = 1
 BDDC_EAGER = 2
+BDDC_STEP1_ONLY = 4
+BDDC_STEP12_ONLY = 8
 X_SCHUR, X_FACE_EIG, X_FACE_K, X_DSCALE, X_GAMMA, X_OMEGA, X_T, X_PSI, X_COARSE_INV = 1, 2, 3, 4, 5, 6, 7, 8, 9
 OP_SYSTEM, OP_PRECOND = 1, 2
 
@@ -179,6 +181,16 @@ def _grid_part(n, h, cuts):
     return g, part, keep
 
 
+def _steps_flag(steps):
+    if steps is None:
+        return 0
+    if steps == 1:
+        return BDDC_STEP1_ONLY
+    if steps == 12:
+        return BDDC_STEP12_ONLY
+    raise ValueError("steps must be None, 1 or 12")
+
+
 def _tau(tau):
     return float(tau) if (tau is not None and math.isfinite(tau)) else 0.0
 
@@ -215,12 +227,13 @@ class Solver:
          self.n_adaptive, self.max_gamma_local) = [int(v) for v in sz]
 
     # -- solves ----------------------------------------------------------------
-    def solve(self, source, rtol=1e-8, allow_noconv=False, eager=False):
+    def solve(self, source, rtol=1e-8, allow_noconv=False, eager=False, steps=None):
+        """steps=1 / 12: return u_0 of step 1 / u^* of steps 1-2 instead of the solution."""
         src = np.ascontiguousarray(source, dtype=np.float64)
         flux = np.empty(self.n_faces_all)
         pres = np.empty(self.n_cells)
         rc = self.lib.bddc_solve(self.h, src.ctypes.data, float(rtol), flux.ctypes.data, pres.ctypes.data,
-                                 BDDC_EAGER if eager else 0)
+                                 (BDDC_EAGER if eager else 0) | _steps_flag(steps))
         _check(self.lib, rc, allow=(BDDC_ENOCONV,) if allow_noconv else ())
         return flux, pres
 
@@ -236,10 +249,11 @@ class Solver:
         _check(self.lib, rc, allow=(BDDC_ENOCONV,))
         return flux, pres, np.array(its[:k], dtype=np.int32)
 
-    def solve_device(self, src_ptr, rtol, flux_ptr, pres_ptr, eager=False):
+    def solve_device(self, src_ptr, rtol, flux_ptr, pres_ptr, eager=False, steps=None):
         """Device-pointer solve (e.g. torch tensor data_ptr()); no host copies."""
         rc = self.lib.bddc_solve(self.h, C.c_void_p(src_ptr), float(rtol), C.c_void_p(flux_ptr),
-                                 C.c_void_p(pres_ptr), BDDC_DEVICE_PTRS | (BDDC_EAGER if eager else 0))
+                                 C.c_void_p(pres_ptr),
+                                 BDDC_DEVICE_PTRS | (BDDC_EAGER if eager else 0) | _steps_flag(steps))
         return _check(self.lib, rc, allow=(BDDC_ENOCONV,))
 
     def set_stream(self, stream_ptr):

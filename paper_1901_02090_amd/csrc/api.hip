@@ -113,6 +113,7 @@ struct bddc_problem {
          *csol = nullptr;
   double *part_g = nullptr, *part_r = nullptr, *part_z = nullptr, *part_p = nullptr;
   double *d_src = nullptr, *d_flux = nullptr, *d_pres = nullptr;
+  double *d_zero_src = nullptr;                   // zero source of the step-1-only mode
   double *alpha_h = nullptr, *beta_h = nullptr;
   CgState *st = nullptr;
   CgState *st_host = nullptr;                     // [2] pinned: state after chunk k lands in [k & 1]
@@ -126,6 +127,7 @@ struct bddc_problem {
     double *flux = nullptr, *pressure = nullptr;  // caller's outputs (host unless dev)
     int chunks = 0, checked = 0;                  // chunks launched / whose state was read
     bool stop = false;                            // a chunk reported completion
+    int upto = 0;                                 // 1 / 2: stop after step 1 / steps 1-2
     std::chrono::steady_clock::time_point t0;
   } run;
   double peak_bytes = 0;                          // high-water mark of device_bytes
@@ -695,6 +697,7 @@ void do_setup(bddc_problem *h, const bddc_grid *gr, const double *perm, const bd
   h->part_z = h->alloc<double>(nF + 1);
   h->part_p = h->alloc<double>(1024);
   h->d_src = h->alloc<double>(L.ncells);
+  h->d_zero_src = h->alloc<double>(L.ncells);
   h->d_flux = h->alloc<double>(L.nfaces_all);
   h->d_pres = h->alloc<double>(L.ncells);
   h->alpha_h = h->alloc<double>(h->max_it + 2);
@@ -934,7 +937,7 @@ void build_cg_graph(bddc_problem *h) {
 //   solve_finish  waits for the chunks in flight, enqueues the final interface
 //                 flux, the post-correction and the output copies, and waits.
 // bddc_solve runs them back to back with one chunk in flight.
-bool solve_needs_cg(const bddc_problem *h) { return h->L.N > 1; }
+bool solve_needs_cg(const bddc_problem *h) { return h->L.N > 1 && h->run.upto == 0; }
 
 void solve_begin_launch(bddc_problem *h, const double *rhs, double rtol, double *flux, double *pressure,
                         uint32_t flags) {
@@ -946,6 +949,9 @@ void solve_begin_launch(bddc_problem *h, const double *rhs, double rtol, double 
   R.t0 = std::chrono::steady_clock::now();
   R.dev = (flags & BDDC_DEVICE_PTRS) != 0;
   R.eager = (flags & BDDC_EAGER) != 0;
+  if ((flags & BDDC_STEP1_ONLY) && (flags & BDDC_STEP12_ONLY))
+    throw Error{BDDC_EINVAL, "BDDC_STEP1_ONLY and BDDC_STEP12_ONLY exclude each other"};
+  R.upto = (flags & BDDC_STEP1_ONLY) ? 1 : (flags & BDDC_STEP12_ONLY) ? 2 : 0;
   if (!(rtol > 0.0)) throw Error{BDDC_EINVAL, "rtol must be > 0"};
   R.src = rhs;
   if (!R.dev) {
@@ -963,7 +969,7 @@ void solve_begin_launch(bddc_problem *h, const double *rhs, double rtol, double 
   R.pressure = pressure;
   R.fl = R.dev ? flux : h->d_flux;
   R.pr = R.dev ? pressure : h->d_pres;
-  if (!solve_needs_cg(h)) return;
+  if (N <= 1) return;
   const int nb = (int)nblk(nGm);
   const double *src = R.src;
   // step 1: coarse solve with (0, D F_0), u0 = E Psi alpha
@@ -974,6 +980,12 @@ void solve_begin_launch(bddc_problem *h, const double *rhs, double rtol, double 
                                           nullptr);
   k_average_balance<<<face_blocks(nF), 256, 0, s>>>(h->g, h->cs, h->wloc, nullptr, h->csol, h->u0, nullptr, nullptr,
                                                     nullptr);
+  if (R.upto) {
+    // u_0 or u^*: the post-correction with x = 0 continues u_0 into the interiors
+    fill(h, h->xp, N, 0.0);
+    HIPCHK(hipGetLastError());
+    return;
+  }
   // steps 2-3 right-hand side: f* = -S u0 + H^T X F
   k_symv<double><<<N, SYMV_THREADS, symv_shm(L), s>>>(h->g, h->Spk, h->d_pk, h->u0, 1.0, h->yloc, nullptr, nullptr, 0);
   k_source_term<<<N, 256, (size_t)2 * L.maxC * sizeof(double), s>>>(h->g, h->mcoef, h->Xmat, h->d_Xoff, src,
@@ -1068,14 +1080,22 @@ int solve_finish_locked(bddc_problem *h) {
     }
     // final interface flux
     k_axpby<<<nblk(nGm), 256, 0, s>>>(nGm, 1.0, h->u0, 1.0, h->xu, h->uG);
+  } else if (R.upto && nGm > 0) {
+    k_axpby<<<nblk(nGm), 256, 0, s>>>(nGm, 1.0, h->u0, 0.0, h->u0, h->uG);
   }
   // post-correction: interior fluxes and pressures
   double *fl = R.fl, *pr = R.pr;
   fill(h, fl, L.nfaces_all, 0.0);
   if (nGm > 0) k_scatter_iface<<<nblk(nGm), 256, 0, s>>>(nGm, h->d_gamma_face, h->uG, fl);
   if (N == 1) fill(h, h->xp, 1, 0.0);
+  // step 1 alone continues u_0 with zero source
+  const double *rsrc = R.src;
+  if (R.upto == 1) {
+    fill(h, h->d_zero_src, L.ncells, 0.0);
+    rsrc = h->d_zero_src;
+  }
   k_recover<<<N, 256, (size_t)(L.maxG + 2 * L.maxC) * sizeof(double), s>>>(h->g, h->mcoef, h->Xmat, h->d_Xoff,
-                                                                            R.src, h->uG, h->xp, h->dscale, fl, pr);
+                                                                            rsrc, h->uG, h->xp, h->dscale, fl, pr);
   k_sum_partial<<<256, 256, 0, s>>>(L.ncells, pr, h->part_p);
   k_sub_mean<<<256, 256, 0, s>>>(L.ncells, pr, h->part_p, 256);
   HIPCHK(hipGetLastError());

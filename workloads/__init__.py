@@ -104,18 +104,23 @@ def gaussian_field_exact(n, h, std, corr, seed):
     """Gaussian random field sampled exactly from its covariance.
 
     Squared-exponential covariance ``std^2 exp(-r^2 / (2 corr^2))`` between
-    cell centres; the sample is ``V sqrt(max(L,0)) xi`` from a dense
-    eigendecomposition.  Only sensible for small grids (a few thousand cells).
+    cell centres, plus a nugget of 1e-10 std^2 on the diagonal; the sample is
+    ``L xi`` with L the Cholesky factor.  (The covariance is numerically rank
+    deficient: an eigendecomposition would leave the basis of its near-null
+    space, and so the sample, to the LAPACK build; the Cholesky factor of the
+    regularised matrix is unique, so every machine draws the same field.)
+    Only sensible for small grids (a few thousand cells).
     """
     axes = [(np.arange(nd) + 0.5) * hd for nd, hd in zip(n, h)]
     mesh = np.meshgrid(*axes, indexing="ij")
     pts = np.stack([m.reshape(-1, order="F") for m in mesh], axis=1)
     d2 = ((pts[:, None, :] - pts[None, :, :]) ** 2).sum(-1)
     cov = std ** 2 * np.exp(-d2 / (2.0 * corr ** 2))
-    lam, vec = np.linalg.eigh(cov)
+    cov[np.diag_indices_from(cov)] += 1e-10 * std ** 2
+    chol = np.linalg.cholesky(cov)
     rng = np.random.default_rng(seed)
-    xi = rng.standard_normal(len(lam))
-    return vec @ (np.sqrt(np.maximum(lam, 0.0)) * xi)
+    xi = rng.standard_normal(len(cov))
+    return chol @ xi
 
 
 def _smoothed_normal(shape, sigma, rng):
