@@ -269,11 +269,13 @@ void setup_dense_top(bddc_problem *h, hipStream_t s) {
     k_top_unit<<<dim3(ub, nc), 256, 0, s>>>(j0, nt, d0, sk, v0, v1, sv, bb, S0b, S1b);
     for (int lv = P.top; lv < P.H; ++lv) {
       const int t0 = P.ftask_off[lv], ntk = P.ftask_off[lv + 1] - t0;
-      k_nd_fwd_cols<<<dim3(ntk, nc), 256, 0, s>>>(t0, h->sw, h->FR, bb, S0b, S1b, zb, sk, sv);
+      k_top_fwd_cols<<<dim3(ntk, (nc + TOP_NC - 1) / TOP_NC), 256, 0, s>>>(t0, h->sw, h->FR, bb, S0b, S1b, zb, sk,
+                                                                           sv, (int)nc);
     }
     for (int lv = P.H - 1; lv >= P.top; --lv) {
       const int t0 = P.btask_lo[lv], ntk = P.btask_hi[lv] - t0;
-      k_nd_bwd_cols<<<dim3(ntk, nc), 256, 0, s>>>(t0, h->sw, h->BC, zb, h->csgn, XBb, xb, sk, sb);
+      k_top_bwd_cols<<<dim3(ntk, (nc + TOP_NC - 1) / TOP_NC), 256, 0, s>>>(t0, h->sw, h->BC, zb, h->csgn, XBb, xb,
+                                                                           sk, sb, (int)nc);
     }
     k_top_store<<<dim3(nblk(h->top_ld), nc), 256, 0, s>>>(j0, nt, d0, h->top_ld, xb, sk, h->Kt);
     HIPCHK(hipGetLastError());

@@ -273,22 +273,6 @@ __global__ __launch_bounds__(256) void k_top_unit(int j0, int nt, int d0, int64_
   }
 }
 
-__global__ __launch_bounds__(256) void k_nd_fwd_cols(int t0, DevSweep sw, const double *__restrict__ FR,
-                                                     const double *__restrict__ b, double *S0, double *S1,
-                                                     double *__restrict__ z, int64_t sk, int64_t sv) {
-  const int4 *td = sw.task + 4 * (int64_t)(t0 + blockIdx.x);
-  const int64_t c = blockIdx.y;
-  fwd_task<false>(td[0], td[1], td[2], sw, FR, b + c * sk, S0 + c * sv, S1 + c * sv, z + c * sk, nullptr, 0);
-}
-
-__global__ __launch_bounds__(256) void k_nd_bwd_cols(int t0, DevSweep sw, const double *__restrict__ BC,
-                                                     const double *__restrict__ z, const double *__restrict__ sg,
-                                                     double *XB, double *__restrict__ x, int64_t sk, int64_t sb) {
-  const int4 *td = sw.task + 4 * (int64_t)(t0 + blockIdx.x);
-  const int64_t c = blockIdx.y;
-  bwd_task<false>(td[0], td[1], td[2], sw, BC, z + c * sk, sg, XB + c * sb, x + c * sk, nullptr, 0);
-}
-
 __global__ __launch_bounds__(256) void k_top_store(int j0, int nt, int d0, int ld, const double *__restrict__ x,
                                                    int64_t sk, double *__restrict__ Kt) {
   const int64_t c = blockIdx.y;

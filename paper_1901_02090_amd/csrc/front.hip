@@ -144,4 +144,109 @@ __global__ __launch_bounds__(256) void k_front_schur(DevFronts fd, const int4 *_
                                   sgn + fd.first[p]);
 }
 
+// Columns of S_t^{-1} (setup of the dense top block): the forward and backward
+// sweep tasks of coarse.hip for TOP_NC unit right-hand sides at once, so that
+// each entry of R is read once per TOP_NC columns.  Every column's sums run in
+// the order of the single-column tasks (same results).
+constexpr int TOP_NC = 4;
+
+__global__ __launch_bounds__(256) void k_top_fwd_cols(int t0, DevSweep sw, const double *__restrict__ FR,
+                                                      const double *__restrict__ b, double *S0, double *S1,
+                                                      double *__restrict__ z, int64_t sk, int64_t sv, int ncols) {
+  const int4 *td = sw.task + 4 * (int64_t)(t0 + blockIdx.x);
+  const int4 d0 = td[0], d1 = td[1], d2 = td[2];
+  const int c0 = blockIdx.y * TOP_NC, nq = min(TOP_NC, ncols - c0);
+  const int g = d0.z, n = d0.w, m = d1.x, fst = d1.y, vo = d1.z, bo = d1.w;
+  const int64_t ro = (int64_t)(((uint64_t)(uint32_t)d2.y << 32) | (uint32_t)d2.x);
+  const int lane = threadIdx.x & (g - 1), r = d0.y + threadIdx.x / g;
+  if (r >= n + m) return;            // whole lane groups leave together
+  const double *row;
+  int len;
+  if (r < n) {
+    row = FR + ro + (int64_t)r * (r + 1) / 2;
+    len = r + 1;
+  } else {
+    row = FR + ro + (int64_t)n * (n + 1) / 2 + (int64_t)(r - n) * n;
+    len = n;
+  }
+  double base[TOP_NC] = {0.0, 0.0, 0.0, 0.0};
+  int dst = 0;
+  if (r >= n && lane == 0) {
+    for (int q = 0; q < nq; ++q) {
+      const int64_t o = c0 + q;
+      base[q] = S0[o * sv + vo + r] + S1[o * sv + vo + r];
+    }
+    dst = sw.wdst[bo + (r - n)];
+  }
+  double a[TOP_NC][4] = {};
+  for (int e0 = lane; e0 < len; e0 += 4 * g) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int c = e0 + u * g;
+      if (c < len) {
+        const double rv = row[c];
+#pragma unroll
+        for (int q = 0; q < TOP_NC; ++q)
+          if (q < nq) {
+            const int64_t o = c0 + q;
+            const double t = (b[o * sk + fst + c] + S0[o * sv + vo + c]) + S1[o * sv + vo + c];
+            a[q][u] = fma(rv, t, a[q][u]);
+          }
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < TOP_NC; ++q) {
+    const double s = group_reduce((a[q][0] + a[q][1]) + (a[q][2] + a[q][3]), g);
+    if (q < nq && lane == 0) {
+      const int64_t o = c0 + q;
+      if (r < n) z[o * sk + fst + r] = s;
+      else (d2.z ? S1 : S0)[o * sv + dst] = base[q] - s;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_top_bwd_cols(int t0, DevSweep sw, const double *__restrict__ BC,
+                                                      const double *__restrict__ z, const double *__restrict__ sg,
+                                                      double *XB, double *__restrict__ x, int64_t sk, int64_t sb,
+                                                      int ncols) {
+  const int4 *td = sw.task + 4 * (int64_t)(t0 + blockIdx.x);
+  const int4 d0 = td[0], d1 = td[1], d2 = td[2];
+  const int c0 = blockIdx.y * TOP_NC, nq = min(TOP_NC, ncols - c0);
+  const int g = d0.z, n = d0.w, m = d1.x, fst = d1.y, bo = d1.w;
+  const int64_t ro = (int64_t)(((uint64_t)(uint32_t)d2.y << 32) | (uint32_t)d2.x);
+  const int lane = threadIdx.x & (g - 1), c = d0.y + threadIdx.x / g;
+  if (c >= n) return;
+  const int f = n + m, d = fst + c;
+  const int s0 = sw.xsc_off[d], s1 = sw.xsc_off[d + 1];
+  const double *col = BC + ro + (int64_t)c * f - (int64_t)c * (c - 1) / 2;
+  const int nl = n - c, len = nl + m;
+  double a[TOP_NC][4] = {};
+  for (int e0 = lane; e0 < len; e0 += 4 * g) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int q = e0 + u * g;
+      if (q < len) {
+        const double cv = col[q];
+#pragma unroll
+        for (int k = 0; k < TOP_NC; ++k)
+          if (k < nq) {
+            const int64_t o = c0 + k;
+            const double in = q < nl ? sg[d + q] * z[o * sk + d + q] : -XB[o * sb + bo + (q - nl)];
+            a[k][u] = fma(cv, in, a[k][u]);
+          }
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < TOP_NC; ++k) {
+    const double s = group_reduce((a[k][0] + a[k][1]) + (a[k][2] + a[k][3]), g);
+    if (k < nq) {
+      const int64_t o = c0 + k;
+      if (lane == 0) x[o * sk + d] = s;
+      for (int j = s0 + lane; j < s1; j += g) XB[o * sb + sw.xsc[j]] = s;
+    }
+  }
+}
+
 }  // namespace bddc
