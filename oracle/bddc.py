@@ -265,6 +265,55 @@ def face_rows(lam, ci, tau, n_f):
     return np.array(rows), k, omega
 
 
+def multiscale_face_flux(grid, perm, subs, i, j, dofs):
+    """Face flux of the local Darcy problem behind the multiscale constraints (Section 6).
+
+    On the union of the neighbours i and j (i on the minus side of the face):
+    source w_i = 1/|Omega^i| in Omega^i and -w_j in Omega^j, no flow on the
+    union's boundary, the pressure fixed by a zero mean.  Returns the fluxes
+    on the face dofs ``dofs`` (global orientation; they sum to the unit net
+    flux from i to j).  READING: the paper shapes w by the well source in
+    subdomains that contain a well; the setup here knows no source, so every
+    subdomain takes the uniform w.
+    """
+    perm = np.asarray(perm, dtype=np.float64).reshape(grid.ncells, grid.dim)
+    ci, cj = subs.sub_cells[i], subs.sub_cells[j]
+    cells = np.concatenate([ci, cj])
+    (ar, ac, av), (br, bc, bv) = rt0.assemble(grid, perm, cells)
+    # flux dofs: faces shared by two cells of the union (the rest carry no flow)
+    cnt = np.zeros(grid.nfaces, dtype=np.int64)
+    np.add.at(cnt, bc, 1)
+    inner = np.flatnonzero(cnt == 2)
+    loc = -np.ones(grid.nfaces, dtype=np.int64)
+    loc[inner] = np.arange(len(inner))
+    cloc = -np.ones(grid.ncells, dtype=np.int64)
+    cloc[cells] = np.arange(len(cells))
+    keep = (loc[ar] >= 0) & (loc[ac] >= 0)
+    A = sp.csr_matrix((av[keep], (loc[ar[keep]], loc[ac[keep]])), shape=(len(inner), len(inner)))
+    keep = loc[bc] >= 0
+    B = sp.csr_matrix((bv[keep], (cloc[br[keep]], loc[bc[keep]])), shape=(len(cells), len(inner)))
+    vol = np.full(len(cells), grid.cell_volume)
+    # cell-integrated source: +1 spread over Omega^i, -1 over Omega^j
+    f = np.concatenate([np.full(len(ci), 1.0 / len(ci)), np.full(len(cj), -1.0 / len(cj))])
+    K = sp.bmat([[A, B.T, None],
+                 [B, None, sp.csr_matrix(vol[:, None])],
+                 [None, sp.csr_matrix(vol[None, :]), None]], format="csc")
+    rhs = np.concatenate([np.zeros(len(inner)), -f, [0.0]])     # b(u, q) = -int div u q = -<f, q>
+    sol = spla.spsolve(K, rhs)
+    return sol[loc[np.asarray(dofs)]]
+
+
+def multiscale_rows(u_face, n_f):
+    """Rows of C_U on one face with the multiscale constraint: the zero-net-flux
+    row plus the face flux of the local problem, projected off the first row and
+    normalised (dropped when the flux is uniform).  Returns (rows, k)."""
+    rows = [np.ones(n_f)]
+    r = u_face - u_face.mean()
+    if n_f > 1 and np.linalg.norm(r) > 1e-12 * np.linalg.norm(u_face):
+        rows.append(r / np.linalg.norm(r))
+    return np.array(rows), len(rows) - 1
+
+
 # ----------------------------------------------------------------------------
 # the BDDC method
 # ----------------------------------------------------------------------------
@@ -272,7 +321,7 @@ def face_rows(lam, ci, tau, n_f):
 class BDDC:
     """Setup of Algorithm "BDDC method" for a given grid, field and partition."""
 
-    def __init__(self, grid, perm, cuts, tau=math.inf, all_constrained=False):
+    def __init__(self, grid, perm, cuts, tau=math.inf, all_constrained=False, multiscale=False):
         self.grid = grid
         self.perm = np.asarray(perm, dtype=np.float64).reshape(grid.ncells, grid.dim)
         self.tau = tau
@@ -293,6 +342,15 @@ class BDDC:
         self.face_lam, self.face_k, self.face_omega, self.face_C = [], [], [], []
         for k, (i, j) in enumerate(subs.face_pairs):
             nF = len(subs.face_dofs[k])
+            if multiscale:
+                # Section 6: the local Darcy problem in place of the eigenproblem (tau unused)
+                uF = multiscale_face_flux(grid, self.perm, subs, i, j, subs.face_dofs[k])
+                rows, kk = multiscale_rows(uF, nF)
+                self.face_lam.append(np.zeros(0))
+                self.face_k.append(kk)
+                self.face_omega.append(0.0)
+                self.face_C.append(rows)
+                continue
             if all_constrained:
                 Z = sla.null_space(np.ones((1, nF)))
                 rows = np.vstack([np.ones(nF), Z.T])
