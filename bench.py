@@ -114,6 +114,41 @@ def time_gpu(pr, precision, steps, warmup, kernel_reps=0):
         s.close()
 
 
+def multiscale_compare(pr, ref_flux):
+    """Section 6's comparison: the multiscale rows (one per face) in place of the
+    adaptive ones, mixed form, same source; one setup and one timed solve."""
+    import torch
+    from paper_1901_02090_amd import Solver
+    t0 = time.perf_counter()
+    s = Solver(pr.n, pr.h, pr.perm, pr.cuts, precision="mixed", max_it=5000, multiscale=True)
+    setup_ms = (time.perf_counter() - t0) * 1e3
+    try:
+        stream = torch.cuda.current_stream()
+        s.set_stream(stream.cuda_stream)
+        src = torch.tensor(pr.source, dtype=torch.float64, device="cuda")
+        flux = torch.empty(s.n_faces_all, dtype=torch.float64, device="cuda")
+        pres = torch.empty(s.n_cells, dtype=torch.float64, device="cuda")
+        out = {}
+        for name, steps_flag in (("eps0", 1), ("eps_star", 12)):
+            s.solve_device(src.data_ptr(), pr.rtol, flux.data_ptr(), pres.data_ptr(), steps=steps_flag)
+            torch.cuda.synchronize()
+            out[name] = float(np.linalg.norm(flux.cpu().numpy() - ref_flux) / np.linalg.norm(ref_flux))
+        s.solve_device(src.data_ptr(), pr.rtol, flux.data_ptr(), pres.data_ptr())   # warm-up (graph capture)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        s.solve_device(src.data_ptr(), pr.rtol, flux.data_ptr(), pres.data_ptr())
+        torch.cuda.synchronize()
+        solve_ms = (time.perf_counter() - t1) * 1e3
+        st = s.stats()
+        out.update(iterations=st["it"], converged=bool(st["converged"]), n_rows=st["n_adaptive"],
+                   n_coarse=st["n_coarse"], kappa=st["kappa"], setup_ms=setup_ms, ms_per_solve=solve_ms,
+                   flux_relerr_vs_adaptive=float(np.linalg.norm(flux.cpu().numpy() - ref_flux) /
+                                                 np.linalg.norm(ref_flux)))
+        return out
+    finally:
+        s.close()
+
+
 def _cutout(pr, lo, ext):
     """Sub-block of a 3D problem (same field), with the cut sources made compatible."""
     import workloads as W
@@ -326,6 +361,7 @@ def main():
 
     r64 = time_gpu(pr, "fp64", args.steps, args.warmup)
     rmx = time_gpu(pr, "mixed", args.steps, args.warmup, kernel_reps=200)
+    msc = multiscale_compare(pr, rmx["flux"]) if args.workload == "reservoir" else None
 
     # dominant kernel of an iteration: the local S^i products (FP64 in both forms)
     ms_s, by_s = rmx["kernels"]["schur"]
@@ -381,6 +417,8 @@ def main():
                  "iterations": r64["stats"]["it"], "setup_ms": r64["setup_s"] * 1e3},
         "mixed_vs_fp64": {"flux_relerr": float(np.linalg.norm(rmx["flux"] - ref_u) / np.linalg.norm(ref_u)),
                           "pressure_relerr": float(np.linalg.norm(rmx["pres"] - ref_p) / np.linalg.norm(ref_p))},
+        "multiscale": dict(msc, note="one multiscale row per face (Section 6) in place of the adaptive rows, "
+                                     "mixed form") if msc else None,
         "steps12": dict(rmx["eps"] or {}, note="relative flux errors of u_0 (step 1) and u^* (steps 1-2) "
                                               "against the converged solve, eq. epsilon"),
         "roofline": roof,

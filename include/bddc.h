@@ -58,6 +58,13 @@ extern "C" {
 #define BDDC_COARSE_DATAFLOW 2u  /* coarse sweeps as one dataflow launch instead of
                                     one launch per level (same results; slower on
                                     the 60x220x85 reservoir)                     */
+#define BDDC_MULTISCALE 4u       /* multiscale constraints (Section 6) in place of
+                                    the face eigenproblems, tau unused: each face
+                                    gets one row, its fluxes in the Darcy problem
+                                    on the two neighbours with a uniform unit
+                                    source / sink and no flow on their other
+                                    faces, projected off the zero-net-flux row
+                                    (none when that flux is uniform)             */
 
 /* bddc_solve flags */
 #define BDDC_DEVICE_PTRS 1u      /* rhs, flux and pressure are device pointers   */

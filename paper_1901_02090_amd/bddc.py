@@ -14,6 +14,7 @@ BDDC_OK, BDDC_EINVAL, BDDC_ENOMEM, BDDC_ENOCONV, BDDC_EBREAKDOWN, BDDC_EFACTOR, 
 BDDC_FP64, BDDC_MIXED = 0, 1
 BDDC_ALL_CONSTRAINED = 1
 BDDC_COARSE_DATAFLOW = 2
+BDDC_MULTISCALE = 4
 BDDC_DEVICE_PTRS = 1
 BDDC_EAGER = 2
 BDDC_STEP1_ONLY = 4
@@ -195,12 +196,13 @@ def _tau(tau):
     return float(tau) if (tau is not None and math.isfinite(tau)) else 0.0
 
 
-def estimate_bytes(n, h, cuts, tau=math.inf, precision="fp64", all_constrained=False):
+def estimate_bytes(n, h, cuts, tau=math.inf, precision="fp64", all_constrained=False, multiscale=False):
     """Device bytes a problem may hold at the peak of its setup (host-only)."""
     lib = load_library()
     g, part, _keep = _grid_part(n, h, cuts)
     opt = Options(BDDC_MIXED if precision == "mixed" else BDDC_FP64, 0,
-                  BDDC_ALL_CONSTRAINED if all_constrained else 0, 0, 0, 0)
+                  (BDDC_ALL_CONSTRAINED if all_constrained else 0) | (BDDC_MULTISCALE if multiscale else 0),
+                  0, 0, 0)
     out = C.c_double()
     _check(lib, lib.bddc_estimate_bytes(C.byref(g), C.byref(part), _tau(tau), C.byref(opt), C.byref(out)))
     return out.value
@@ -210,12 +212,13 @@ class Solver:
     """One problem resident on the GPU: setup once, solve many right-hand sides."""
 
     def __init__(self, n, h, perm, cuts, tau=math.inf, precision="fp64", max_it=10000, all_constrained=False,
-                 coarse_leaf=0, coarse_dataflow=False, coarse_top=0, t_workgroups=0):
+                 coarse_leaf=0, coarse_dataflow=False, coarse_top=0, t_workgroups=0, multiscale=False):
         self.lib = lib = load_library()
         self.n = tuple(int(v) for v in n)
         g, part, self._cuts = _grid_part(n, h, cuts)
         opt = Options(BDDC_MIXED if precision == "mixed" else BDDC_FP64, int(max_it),
-                      (BDDC_ALL_CONSTRAINED if all_constrained else 0) | (BDDC_COARSE_DATAFLOW if coarse_dataflow else 0),
+                      (BDDC_ALL_CONSTRAINED if all_constrained else 0) | (BDDC_COARSE_DATAFLOW if coarse_dataflow else 0) |
+                      (BDDC_MULTISCALE if multiscale else 0),
                       int(coarse_leaf), int(coarse_top), int(t_workgroups))
         perm = np.ascontiguousarray(perm, dtype=np.float64).reshape(-1)
         t = _tau(tau)

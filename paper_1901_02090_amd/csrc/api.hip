@@ -468,22 +468,27 @@ void do_setup(bddc_problem *h, const bddc_grid *gr, const double *perm, const bd
   }
   h->eig_off_h = eoff;
   h->face_eig.assign(es, 0.0);
-  const bool adaptive = (h->tau > 0.0 && isfinite(h->tau));
   const bool allc = (h->flags & BDDC_ALL_CONSTRAINED) != 0;
-  if ((adaptive || allc) && L.maxFn > 256)
+  const bool ms = !allc && (h->flags & BDDC_MULTISCALE) != 0;
+  const bool adaptive = !ms && (h->tau > 0.0 && isfinite(h->tau));
+  if ((adaptive || allc || ms) && L.maxFn > 256)
     throw Error{BDDC_EINVAL, "adaptive constraints need faces of at most 256 dofs"};
   double *d_rows = h->alloc<double>(rs);
   double *d_fws = nullptr;
-  if (nF > 0 && (adaptive || allc)) {
+  if (nF > 0 && (adaptive || allc || ms)) {
     d_fws = h->alloc<double>(fws);
     double *d_eig = h->alloc<double>(es);
     int *d_k = h->alloc<int>(nF);
     double *d_om = h->alloc<double>(nF);
     int64_t *d_foff = h->upload(foff), *d_eoff = h->upload(eoff), *d_roff = h->upload(roff);
-    k_face_reduce<<<nF, 256, 0, s>>>(g, sw, d_fws, d_foff, allc ? 1 : 0, d_eig, d_eoff, d_k, d_om, d_rows,
-                                     d_roff, h->d_err);
+    if (ms) {
+      k_face_ms<<<nF, 256, 0, s>>>(g, sw, d_fws, d_foff, d_eig, d_eoff, d_k, d_om, d_rows, d_roff, h->d_err);
+    } else {
+      k_face_reduce<<<nF, 256, 0, s>>>(g, sw, d_fws, d_foff, allc ? 1 : 0, d_eig, d_eoff, d_k, d_om, d_rows,
+                                       d_roff, h->d_err);
+    }
     HIPCHK(hipGetLastError());
-    if (!allc) {
+    if (!allc && !ms) {
       launch_face_jacobi(h, L, g, d_fws, d_foff, s);
       k_face_rows<<<nF, 256, 0, s>>>(g, d_fws, d_foff, h->tau, d_eig, d_eoff, d_k, d_om, d_rows, d_roff);
       HIPCHK(hipGetLastError());

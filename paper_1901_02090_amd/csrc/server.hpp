@@ -51,12 +51,13 @@ Layout build_layout(const bddc_grid *gr, const bddc_partition *part) {
 double estimate_bytes(const bddc_grid *gr, const bddc_partition *part, double tau, const bddc_options *opt) {
   const Layout L = build_layout(gr, part);
   const int N = L.N, nF = L.nF, dim = L.dim;
-  const bool adaptive = tau > 0.0 && std::isfinite(tau);
   const bool allc = opt && (opt->flags & BDDC_ALL_CONSTRAINED);
+  const bool ms = !allc && opt && (opt->flags & BDDC_MULTISCALE);
+  const bool adaptive = !ms && tau > 0.0 && std::isfinite(tau);
   std::vector<int> fk(nF, 0);
   for (int f = 0; f < nF; ++f) {
     const int room = std::max(0, L.f_n[f] - 1);
-    fk[f] = allc ? room : (adaptive ? std::min(room, EST_ADAPTIVE_ROWS) : 0);
+    fk[f] = allc ? room : ms ? std::min(room, 1) : (adaptive ? std::min(room, EST_ADAPTIVE_ROWS) : 0);
   }
   const double totG = (double)L.g_off[N];
   double b = 0.0;
@@ -73,7 +74,7 @@ double estimate_bytes(const bddc_grid *gr, const bddc_partition *part, double ta
   for (int f = 0; f < nF; ++f) {
     const double fn = L.f_n[f];
     b += 8.0 * fn * fn;
-    if (adaptive || allc) b += 8.0 * (6 * fn * fn + fn) + 8.0 * fn + 40.0;
+    if (adaptive || allc || ms) b += 8.0 * (6 * fn * fn + fn) + 8.0 * fn + 40.0;
   }
   // local coarse spaces: workspaces, A_c^i, Psi^i (FP64 + FP32), T^i (FP64 + FP32)
   double sum_nci = 0.0;

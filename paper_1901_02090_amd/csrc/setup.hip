@@ -364,6 +364,68 @@ __global__ __launch_bounds__(256, 2) void k_face_reduce(DevGeom g, SetupWs ws, d
   __syncthreads();
 }
 
+// Multiscale constraint of a face (Section 6, in place of the eigenproblem):
+// the face fluxes of the Darcy problem on the two neighbours with a uniform
+// unit source in Omega^i, the matching sink in Omega^j and no flow through
+// their other faces.  With those fluxes zero the problem reduces to the face:
+// the flux minimises u^T (S^i_FF + S^j_FF) u at unit net flux, so it is
+// proportional to y = (S^i_FF + S^j_FF)^{-1} 1 (the uniform sources lie in
+// the constants the local pressure operators leave out).  The row is y
+// projected off the zero-net-flux row and normalised; a uniform y adds none.
+__global__ __launch_bounds__(256, 2) void k_face_ms(DevGeom g, SetupWs ws, double *fbase, const int64_t *foff,
+                                                 double *eig_out, const int64_t *eig_off, int *kout,
+                                                 double *omega_out, double *rows_out, const int64_t *rows_off,
+                                                 int *err) {
+  __shared__ double lds[LDS_DOUBLES];
+  __shared__ double red[8];
+  const int f = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int i = g.f_minus[f], j = g.f_plus[f], n = g.f_n[f];
+  const int oi = g.f_loffm[f], oj = g.f_loffp[f];
+  const int ni = g.nG[i], nj = g.nG[j];
+  const int m = n - 1;
+  double *w = fbase + foff[f];
+  double *XF = w, *y = w + n * n;
+  double *eig = eig_out + eig_off[f];
+  for (int a = tid; a < m; a += WG) eig[a] = 0.0;
+  if (m == 0) {
+    if (tid == 0) { kout[f] = 0; omega_out[f] = 0.0; }
+    return;
+  }
+  const double *Si = ws.base + ws.S[i], *Sj = ws.base + ws.S[j];
+  for (int e = tid; e < n * n; e += WG) {
+    const int a = e % n, b = e / n;
+    XF[e] = Si[(oi + a) + (size_t)(oi + b) * ni] + Sj[(oj + a) + (size_t)(oj + b) * nj];
+  }
+  for (int a = tid; a < n; a += WG) y[a] = 1.0;
+  __syncthreads();
+  if (wg_potrf(n, XF, n, lds)) {
+    if (tid == 0) atomicOr(err, 8);
+  }
+  wg_trsm_lower(n, 1, XF, n, y, n, lds);
+  wg_trsm_lower_t(n, 1, XF, n, y, n, lds);
+  double sy = 0.0, syy = 0.0;
+  for (int a = tid; a < n; a += WG) {
+    sy += y[a];
+    syy += y[a] * y[a];
+  }
+  sy = wg_sum(sy, red);
+  syy = wg_sum(syy, red);
+  const double mean = sy / n;
+  double rr = 0.0;
+  for (int a = tid; a < n; a += WG) rr += (y[a] - mean) * (y[a] - mean);
+  const double nrm = sqrt(wg_sum(rr, red));
+  const int k = (nrm > 1e-12 * sqrt(syy)) ? 1 : 0;
+  if (k) {
+    double *rows = rows_out + rows_off[f];
+    for (int a = tid; a < n; a += WG) rows[a] = (y[a] - mean) / nrm;
+  }
+  if (tid == 0) {
+    kout[f] = k;
+    omega_out[f] = 0.0;
+  }
+}
+
 // Jacobi stage for the faces listed in `faces`.  IN_LDS: C and its eigenvector
 // matrix are held in dynamic LDS (16 m^2 bytes, m <= 128), the matrix C in U
 // is left untouched apart from its diagonal; otherwise the rotations work in
