@@ -321,7 +321,8 @@ def multiscale_rows(u_face, n_f):
 class BDDC:
     """Setup of Algorithm "BDDC method" for a given grid, field and partition."""
 
-    def __init__(self, grid, perm, cuts, tau=math.inf, all_constrained=False, multiscale=False):
+    def __init__(self, grid, perm, cuts, tau=math.inf, all_constrained=False, multiscale=False,
+                 scaling="multiplicity"):
         self.grid = grid
         self.perm = np.asarray(perm, dtype=np.float64).reshape(grid.ncells, grid.dim)
         self.tau = tau
@@ -369,6 +370,25 @@ class BDDC:
             self.face_omega.append(om)
             self.face_C.append(rows)
         self.omega_tilde = max(self.face_omega) if self.face_omega else 0.0
+
+        # weights of the averaging operator E on the two copies of every interface
+        # dof: multiplicity (1/2 each), or stiffness scaling (the paper's choice
+        # when coefficient jumps follow the interfaces; for RT0 it is rho-scaling
+        # with rho = 1/k), kept constant along each face as the Remark on the
+        # starting flux constraints requires: delta_i = a_i / (a_i + a_j), a_i
+        # the mean of diag(A^i) over the face's dofs
+        if scaling not in ("multiplicity", "stiffness"):
+            raise ValueError("scaling must be 'multiplicity' or 'stiffness'")
+        if scaling == "stiffness" and math.isfinite(tau) and not (multiscale or all_constrained):
+            raise ValueError("the pair eigenproblems assume the multiplicity weights")
+        self.weight = [np.full(lp.nG, 0.5) for lp in self.loc]
+        if scaling == "stiffness":
+            for k, (i, j) in enumerate(subs.face_pairs):
+                pi, pj = self.face_pos[k]
+                ai = self.loc[i].AGG.diagonal()[pi].mean()
+                aj = self.loc[j].AGG.diagonal()[pj].mean()
+                self.weight[i][pi] = ai / (ai + aj)
+                self.weight[j][pj] = aj / (ai + aj)
 
         # global coarse dof numbering: face by face
         self.cofs = np.concatenate([[0], np.cumsum([c.shape[0] for c in self.face_C])]).astype(np.int64)
@@ -436,16 +456,16 @@ class BDDC:
         return self.apply_S(xu) + self.B0.T @ xp, self.B0 @ xu
 
     def average(self, locals_):
-        """E: multiplicity-weighted sum of the subdomain copies (weights 1/2)."""
+        """E: weighted sum of the subdomain copies (weights 1/2, or the stiffness weights)."""
         y = np.zeros(self.subs.n_gamma)
         for i, lp in enumerate(self.loc):
-            y[self.subs.gamma_pos[lp.G]] += 0.5 * locals_[i]
+            y[self.subs.gamma_pos[lp.G]] += self.weight[i] * locals_[i]
         return y
 
     def precondition(self, ru):
         """Algorithm "BDDC preconditioner": (r_B, 0) -> (w_hat, p_0)."""
         N = self.subs.N
-        rloc = [0.5 * self.restrict(i, ru) for i in range(N)]   # <r_B, E z> pairing
+        rloc = [self.weight[i] * self.restrict(i, ru) for i in range(N)]   # E^T r: <r_B, E z> pairing
         gu = np.zeros(self.n_cu)
         for i, lp in enumerate(self.loc):
             gu[self.sub_cdofs[i]] += lp.Psi.T @ rloc[i]
