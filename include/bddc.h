@@ -65,6 +65,12 @@ extern "C" {
                                     source / sink and no flow on their other
                                     faces, projected off the zero-net-flux row
                                     (none when that flux is uniform)             */
+#define BDDC_STIFFNESS_SCALING 8u /* averaging weights a_i / (a_i + a_j) per face,
+                                    a_s the mean diagonal of A^s over the face
+                                    (rho-scaling for RT0; the paper's choice when
+                                    coefficient jumps follow the interfaces) in
+                                    place of 1/2; needs tau off (or multiscale):
+                                    BDDC_EINVAL otherwise                        */
 
 /* bddc_solve flags */
 #define BDDC_DEVICE_PTRS 1u      /* rhs, flux and pressure are device pointers   */

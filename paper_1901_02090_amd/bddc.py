@@ -15,6 +15,7 @@ BDDC_FP64, BDDC_MIXED = 0, 1
 BDDC_ALL_CONSTRAINED = 1
 BDDC_COARSE_DATAFLOW = 2
 BDDC_MULTISCALE = 4
+BDDC_STIFFNESS_SCALING = 8
 BDDC_DEVICE_PTRS = 1
 BDDC_EAGER = 2
 BDDC_STEP1_ONLY = 4
@@ -182,6 +183,14 @@ def _grid_part(n, h, cuts):
     return g, part, keep
 
 
+def _scaling_flag(scaling):
+    if scaling == "multiplicity":
+        return 0
+    if scaling == "stiffness":
+        return BDDC_STIFFNESS_SCALING
+    raise ValueError("scaling must be 'multiplicity' or 'stiffness'")
+
+
 def _steps_flag(steps):
     if steps is None:
         return 0
@@ -212,13 +221,14 @@ class Solver:
     """One problem resident on the GPU: setup once, solve many right-hand sides."""
 
     def __init__(self, n, h, perm, cuts, tau=math.inf, precision="fp64", max_it=10000, all_constrained=False,
-                 coarse_leaf=0, coarse_dataflow=False, coarse_top=0, t_workgroups=0, multiscale=False):
+                 coarse_leaf=0, coarse_dataflow=False, coarse_top=0, t_workgroups=0, multiscale=False,
+                 scaling="multiplicity"):
         self.lib = lib = load_library()
         self.n = tuple(int(v) for v in n)
         g, part, self._cuts = _grid_part(n, h, cuts)
         opt = Options(BDDC_MIXED if precision == "mixed" else BDDC_FP64, int(max_it),
                       (BDDC_ALL_CONSTRAINED if all_constrained else 0) | (BDDC_COARSE_DATAFLOW if coarse_dataflow else 0) |
-                      (BDDC_MULTISCALE if multiscale else 0),
+                      (BDDC_MULTISCALE if multiscale else 0) | _scaling_flag(scaling),
                       int(coarse_leaf), int(coarse_top), int(t_workgroups))
         perm = np.ascontiguousarray(perm, dtype=np.float64).reshape(-1)
         t = _tau(tau)

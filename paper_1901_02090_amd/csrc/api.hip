@@ -73,6 +73,7 @@ struct bddc_problem {
   int coarse_leaf = 0;
   int coarse_top = 0;
   int t_grid = 0;                                 // workgroups of the T^i launch beside the coarse solve
+  int n_cu = 0;                                   // compute units of the device
   double tau = 0.0;
   std::vector<void *> allocs;
   std::vector<double> alloc_bytes;
@@ -114,6 +115,7 @@ struct bddc_problem {
   double *part_g = nullptr, *part_r = nullptr, *part_z = nullptr, *part_p = nullptr;
   double *d_src = nullptr, *d_flux = nullptr, *d_pres = nullptr;
   double *d_zero_src = nullptr;                   // zero source of the step-1-only mode
+  double *lw = nullptr;                           // [sum nG] weights of E^T per local interface dof (null: 1/2)
   double *alpha_h = nullptr, *beta_h = nullptr;
   CgState *st = nullptr;
   CgState *st_host = nullptr;                     // [2] pinned: state after chunk k lands in [k & 1]
@@ -339,6 +341,15 @@ void launch_face_jacobi(bddc_problem *h, const Layout &L, const DevGeom &g, doub
 
 void do_setup(bddc_problem *h, const bddc_grid *gr, const double *perm, const bddc_partition *part) {
   Layout &L = h->L;
+  {
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&h->n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+  }
+  if ((h->flags & BDDC_STIFFNESS_SCALING) && !(h->flags & (BDDC_MULTISCALE | BDDC_ALL_CONSTRAINED)) &&
+      h->tau > 0.0 && isfinite(h->tau))
+    throw Error{BDDC_EINVAL, "stiffness scaling needs tau off or the multiscale constraints: the face "
+                             "eigenproblems assume the weights 1/2"};
   int n[3] = {gr->n[0], gr->n[1], gr->n[2]};
   double hh[3] = {gr->h[0], gr->h[1], gr->h[2]};
   const int *cuts[3] = {part->cuts[0], part->cuts[1], part->cuts[2]};
@@ -417,6 +428,17 @@ void do_setup(bddc_problem *h, const bddc_grid *gr, const double *perm, const bd
   h->mcoef = h->alloc<double>(L.ncells * 3);
   k_cell_coef<<<nblk(L.ncells), 256, 0, s>>>(g, d_perm, L.ncells, h->mcoef, h->d_err);
   HIPCHK(hipGetLastError());
+  if (h->flags & BDDC_STIFFNESS_SCALING) {
+    // weights of E, constant along each face (stiffness scaling)
+    double *fwm = h->alloc<double>(std::max(L.nF, 1)), *fwp = h->alloc<double>(std::max(L.nF, 1));
+    h->lw = h->alloc<double>(std::max<int64_t>(L.g_off[N], 1));
+    if (L.nF > 0) {
+      k_face_weights<<<L.nF, 64, 0, s>>>(g, h->mcoef, fwm, fwp, h->lw);
+      HIPCHK(hipGetLastError());
+    }
+    g.fw_minus = fwm;
+    g.fw_plus = fwp;
+  }
   h->dscale = h->alloc<double>(N);
 
   // local dense setup: Schur complements S^i and the pressure operators
@@ -797,17 +819,20 @@ void launch_precond(bddc_problem *h, const double *r, double *z, double *zpart, 
   // the memory bandwidth they take from the latency-bound coarse sweeps) and
   // join before the averaging, which adds the two parts.
   if (mixed)
-    k_psi_apply<float><<<N, 256, shm, s>>>(h->g, h->Psi32, h->d_psi_off, h->cs.sub_coff, r, 0.5, h->gloc, st, rp, nrp);
+    k_psi_apply<float><<<N, 256, shm, s>>>(h->g, h->Psi32, h->d_psi_off, h->cs.sub_coff, r, 0.5, h->lw, h->gloc, st, rp, nrp);
   else
-    k_psi_apply<double><<<N, 256, shm, s>>>(h->g, h->Psi64, h->d_psi_off, h->cs.sub_coff, r, 0.5, h->gloc, st, rp,
+    k_psi_apply<double><<<N, 256, shm, s>>>(h->g, h->Psi64, h->d_psi_off, h->cs.sub_coff, r, 0.5, h->lw, h->gloc, st, rp,
                                             nrp);
   HIPCHK(hipEventRecord(h->ev_fork, s));
   HIPCHK(hipStreamWaitEvent(h->side, h->ev_fork, 0));
-  const int tg = h->t_grid > 0 ? std::min(h->t_grid, N) : N;
+  // By default the FP32 T^i gets one workgroup of SYMV_THREADS per CU (a
+  // grid-stride loop over the subdomains): with two per CU it finishes sooner
+  // but takes enough bandwidth from the coarse sweeps to lengthen the apply.
+  const int tg = h->t_grid > 0 ? std::min(h->t_grid, N) : (mixed && h->n_cu > 0 ? std::min(h->n_cu, N) : N);
   if (mixed)
-    k_symv<float><<<tg, SYMV_THREADS, symv_shm(L), h->side>>>(h->g, h->T32, h->d_pk, r, 0.5, h->yloc, st, nullptr, 0);
+    k_symv<float><<<tg, SYMV_THREADS, symv_shm(L), h->side>>>(h->g, h->T32, h->d_pk, r, 0.5, h->lw, h->yloc, st, nullptr, 0);
   else
-    k_symv<double><<<tg, SYMV_THREADS, symv_shm(L), h->side>>>(h->g, h->T64, h->d_pk, r, 0.5, h->yloc, st, nullptr,
+    k_symv<double><<<tg, SYMV_THREADS, symv_shm(L), h->side>>>(h->g, h->T64, h->d_pk, r, 0.5, h->lw, h->yloc, st, nullptr,
                                                                0);
   HIPCHK(hipEventRecord(h->ev_join, h->side));
   // The coarse solve stays FP64 in both forms: the CG runs in the balanced
@@ -831,7 +856,7 @@ void launch_iteration(bddc_problem *h) {
   const int N = L.N, nGm = L.nGamma;
   const size_t shm = (size_t)5 * ld4(L.maxG) * sizeof(double);
   const int nb = vec_blocks(nGm);
-  k_symv<double><<<N, SYMV_THREADS, symv_shm(L), s>>>(h->g, h->Spk, h->d_pk, h->pu, 1.0, h->yloc, h->st, nullptr, 0);
+  k_symv<double><<<N, SYMV_THREADS, symv_shm(L), s>>>(h->g, h->Spk, h->d_pk, h->pu, 1.0, nullptr, h->yloc, h->st, nullptr, 0);
   k_sys_assemble<<<nb, 256, 0, s>>>(h->g, h->yloc, h->pp, h->dscale, h->pu, h->qu, h->part_g, h->st);
   k_update_xr<<<nb, 256, 0, s>>>(nGm, N, h->part_g, nb, h->pu, h->qu, h->pp, h->xu, h->ru, h->xp, h->part_r,
                                  h->st, h->alpha_h);
@@ -994,7 +1019,7 @@ void solve_begin_launch(bddc_problem *h, const double *rhs, double rtol, double 
     return;
   }
   // steps 2-3 right-hand side: f* = -S u0 + H^T X F
-  k_symv<double><<<N, SYMV_THREADS, symv_shm(L), s>>>(h->g, h->Spk, h->d_pk, h->u0, 1.0, h->yloc, nullptr, nullptr, 0);
+  k_symv<double><<<N, SYMV_THREADS, symv_shm(L), s>>>(h->g, h->Spk, h->d_pk, h->u0, 1.0, nullptr, h->yloc, nullptr, nullptr, 0);
   k_source_term<<<N, 256, (size_t)2 * L.maxC * sizeof(double), s>>>(h->g, h->mcoef, h->Xmat, h->d_Xoff, src,
                                                                      h->wloc);
   k_fstar<<<nblk(nGm), 256, 0, s>>>(h->g, h->yloc, h->wloc, h->ru);
@@ -1444,7 +1469,7 @@ int bddc_apply(bddc_handle h, int32_t which, const double *x_u, const double *x_
       if (!x_p) throw Error{BDDC_EINVAL, "x_p required"};
       HIPCHK(hipMemcpyAsync(h->pp, x_p, N * sizeof(double), hipMemcpyHostToDevice, s));
       const size_t shm = (size_t)5 * ld4(L.maxG) * sizeof(double);
-      k_symv<double><<<N, SYMV_THREADS, symv_shm(L), s>>>(h->g, h->Spk, h->d_pk, h->ru, 1.0, h->yloc, nullptr, nullptr, 0);
+      k_symv<double><<<N, SYMV_THREADS, symv_shm(L), s>>>(h->g, h->Spk, h->d_pk, h->ru, 1.0, nullptr, h->yloc, nullptr, nullptr, 0);
       k_sys_assemble<<<nblk(nGm), 256, 0, s>>>(h->g, h->yloc, h->pp, h->dscale, nullptr, h->qu, nullptr, nullptr);
       k_b0<<<N, 256, 0, s>>>(h->g, h->ru, h->dscale, h->xp);
       HIPCHK(hipMemcpyAsync(y_u, h->qu, nGm * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1484,11 +1509,11 @@ int bddc_time_kernel(bddc_handle h, int32_t which, int32_t reps, double *avg_ms,
       if (which == BDDC_K_PRECOND_FULL)
         launch_precond(h, h->ru, h->zu, nullptr, false);
       else if (which == BDDC_K_SCHUR_APPLY)
-        k_symv<double><<<N, SYMV_THREADS, symv_shm(L), s>>>(h->g, h->Spk, h->d_pk, h->pu, 1.0, h->yloc, nullptr, nullptr, 0);
+        k_symv<double><<<N, SYMV_THREADS, symv_shm(L), s>>>(h->g, h->Spk, h->d_pk, h->pu, 1.0, nullptr, h->yloc, nullptr, nullptr, 0);
       else if (h->precision == BDDC_MIXED)
-        k_symv<float><<<N, SYMV_THREADS, symv_shm(L), s>>>(h->g, h->T32, h->d_pk, h->ru, 0.5, h->yloc, nullptr, nullptr, 0);
+        k_symv<float><<<N, SYMV_THREADS, symv_shm(L), s>>>(h->g, h->T32, h->d_pk, h->ru, 0.5, h->lw, h->yloc, nullptr, nullptr, 0);
       else
-        k_symv<double><<<N, SYMV_THREADS, symv_shm(L), s>>>(h->g, h->T64, h->d_pk, h->ru, 0.5, h->yloc, nullptr, nullptr, 0);
+        k_symv<double><<<N, SYMV_THREADS, symv_shm(L), s>>>(h->g, h->T64, h->d_pk, h->ru, 0.5, h->lw, h->yloc, nullptr, nullptr, 0);
     };
     // algorithmic bytes: the lower triangles, the gather map and gathered x, y
     if (which == BDDC_K_SCHUR_APPLY)

@@ -50,6 +50,9 @@ struct DevGeom {
   const int *sub_face_off, *sub_faces;
   const int64_t *line_off;    // [N+1] offsets into line_g
   const int *line_g;          // per subdomain, direction d, line l, end e: local interface index or -1
+  // weights of the averaging operator E on the minus / plus copy of each
+  // face's dofs (stiffness scaling); null: 1/2 each (multiplicity)
+  const double *fw_minus = nullptr, *fw_plus = nullptr;   // [nF]
 };
 
 // Per-subdomain dense setup workspace (FP64, column major).

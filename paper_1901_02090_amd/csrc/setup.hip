@@ -82,6 +82,42 @@ __global__ void k_cell_coef(DevGeom g, const double *__restrict__ perm, int64_t 
   }
 }
 
+// Weights of the averaging operator E for stiffness scaling (Section 6; for
+// RT0 the same as rho-scaling).  On the face between i and j, a_s is the mean
+// over the face's dofs of the diagonal entry of A^s there (m / 3 of the cell of
+// Omega^s next to the face); the two copies are weighted a_i / (a_i + a_j) and
+// a_j / (a_i + a_j), constant along the face as the Remark on the starting
+// flux constraints requires.  One wave per face.
+__global__ __launch_bounds__(64) void k_face_weights(DevGeom g, const double *__restrict__ mcoef, double *fwm,
+                                                     double *fwp, double *lw) {
+  const int f = blockIdx.x, lane = threadIdx.x;
+  const int i = g.f_minus[f], j = g.f_plus[f], n = g.f_n[f];
+  const int64_t bi = g.g_off[i] + g.f_loffm[f], bj = g.g_off[j] + g.f_loffp[f];
+  auto diag = [&](int sd, int64_t fl) {
+    const int gc = g.lcell_global[g.cell_off[sd] + g.lg_cell[fl]];
+    return mcoef[(int64_t)gc * 3 + g.lg_dir[fl]] / 3.0;
+  };
+  double si = 0.0, sj = 0.0;
+  for (int a = lane; a < n; a += 64) {
+    si += diag(i, bi + a);
+    sj += diag(j, bj + a);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    si += __shfl_xor(si, o, 64);
+    sj += __shfl_xor(sj, o, 64);
+  }
+  const double ai = si / n, aj = sj / n;
+  const double wi = ai / (ai + aj), wj = aj / (ai + aj);
+  if (lane == 0) {
+    fwm[f] = wi;
+    fwp[f] = wj;
+  }
+  for (int a = lane; a < n; a += 64) {
+    lw[bi + a] = wi;
+    lw[bj + a] = wj;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // per-subdomain: d_i, P, H, S_A, L_P, S^i, X^i
 // ---------------------------------------------------------------------------

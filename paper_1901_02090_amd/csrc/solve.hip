@@ -143,7 +143,7 @@ __device__ __forceinline__ bool cg_exit(CgState *st, const double *__restrict__ 
   return false;
 }
 
-// y^i = M^i (xscale * R_i x) for every subdomain (one workgroup of SYMV_WAVES
+// y^i = M^i (w * R_i x), w = xw (per local dof) or xscale, for every subdomain (one workgroup of SYMV_WAVES
 // wavefronts each), M^i in group-aligned packed storage (S^i, or T^i of the
 // preconditioner).  Eight waves per workgroup: with one subdomain per
 // workgroup the launch is about three rounds of resident workgroups on 256
@@ -156,6 +156,7 @@ template <typename TS>
 __global__ __launch_bounds__(SYMV_THREADS) void k_symv(DevGeom g, const TS *__restrict__ M,
                                                        const int64_t *__restrict__ pk,
                                                        const double *__restrict__ x, double xscale,
+                                                       const double *__restrict__ xw,
                                                        double *__restrict__ yloc, CgState *st,
                                                        const double *__restrict__ rpart, int nrpart) {
   extern __shared__ double sh[];
@@ -170,7 +171,7 @@ __global__ __launch_bounds__(SYMV_THREADS) void k_symv(DevGeom g, const TS *__re
     const int64_t go = g.g_off[i];
     double *xs = sh;
     double *yw = sh + np;
-    for (int r = tid; r < np; r += SYMV_THREADS) xs[r] = (r < n) ? xscale * x[g.Rmap[go + r]] : 0.0;
+    for (int r = tid; r < np; r += SYMV_THREADS) xs[r] = (r < n) ? (xw ? xw[go + r] : xscale) * x[g.Rmap[go + r]] : 0.0;
     for (int e = tid; e < SYMV_WAVES * np; e += SYMV_THREADS) yw[e] = 0.0;
     __syncthreads();
     const TS *Mi = M + pk[i];
@@ -218,14 +219,16 @@ __global__ __launch_bounds__(SYMV_THREADS) void k_symv(DevGeom g, const TS *__re
   }
 }
 
-// g^i = Psi^{iT} (xscale * R_i x): the coarse right-hand side pieces of the
+
+// g^i = Psi^{iT} (w * R_i x), w = xw or xscale: the coarse right-hand side pieces of the
 // preconditioner (one workgroup per subdomain; four columns per wave, 16-byte
 // loads over the ld4-padded columns).
 template <typename TS>
 __global__ __launch_bounds__(256) void k_psi_apply(DevGeom g, const TS *__restrict__ Psi,
                                                    const int64_t *__restrict__ psi_off,
                                                    const int *__restrict__ sub_coff, const double *__restrict__ x,
-                                                   double xscale, double *__restrict__ gloc, CgState *st,
+                                                   double xscale, const double *__restrict__ xw,
+                                                   double *__restrict__ gloc, CgState *st,
                                                    const double *__restrict__ rpart, int nrpart) {
   extern __shared__ double sh[];
   __shared__ double red[8];
@@ -235,7 +238,7 @@ __global__ __launch_bounds__(256) void k_psi_apply(DevGeom g, const TS *__restri
   const int n = g.nG[i], np = ld4(n);
   const int64_t go = g.g_off[i];
   double *xs = sh;
-  for (int r = tid; r < np; r += 256) xs[r] = (r < n) ? xscale * x[g.Rmap[go + r]] : 0.0;
+  for (int r = tid; r < np; r += 256) xs[r] = (r < n) ? (xw ? xw[go + r] : xscale) * x[g.Rmap[go + r]] : 0.0;
   __syncthreads();
   const int c0 = sub_coff[i], nci = sub_coff[i + 1] - c0;
   const TS *P = Psi + psi_off[i];
@@ -411,14 +414,17 @@ __global__ __launch_bounds__(256) void k_average_balance(DevGeom g, DevCoarse cs
     const int n = g.f_n[f];
     const int64_t base = g.g_off[g.f_minus[f]] + g.f_loffm[f];
     double tsum = 0.0;
+    const double wm = g.fw_minus ? g.fw_minus[f] : 0.5, wp = g.fw_minus ? g.fw_plus[f] : 0.5;
     for (int a = lane; a < n; a += 64) {
       const int gi = g.Rmap[base + a];
-      tsum += 0.5 * (wsum(yloc, wloc, base + a) + wsum(yloc, wloc, g.own_plus[gi]));
+      tsum += wm * wsum(yloc, wloc, base + a) + wp * wsum(yloc, wloc, g.own_plus[gi]);
     }
     const double corr = (csol[cs.face_cofs[f]] - wave_sum(tsum)) / n;
     for (int a = lane; a < n; a += 64) {
       const int gi = g.Rmap[base + a];
-      const double zz = 0.5 * (wsum(yloc, wloc, base + a) + wsum(yloc, wloc, g.own_plus[gi])) + corr;
+      const double zz = (g.fw_minus ? wm * wsum(yloc, wloc, base + a) + wp * wsum(yloc, wloc, g.own_plus[gi])
+                                    : 0.5 * (wsum(yloc, wloc, base + a) + wsum(yloc, wloc, g.own_plus[gi]))) +
+                        corr;
       z[gi] = zz;
       if (r) v = fma(r[gi], zz, v);
     }
@@ -737,14 +743,14 @@ __global__ __launch_bounds__(256) void k_sub_mean(int64_t n, double *x, const do
 }
 
 // explicit instantiations used by the host code
-template __global__ void k_symv<double>(DevGeom, const double *, const int64_t *, const double *, double, double *,
-                                        CgState *, const double *, int);
-template __global__ void k_symv<float>(DevGeom, const float *, const int64_t *, const double *, double, double *,
-                                       CgState *, const double *, int);
+template __global__ void k_symv<double>(DevGeom, const double *, const int64_t *, const double *, double,
+                                        const double *, double *, CgState *, const double *, int);
+template __global__ void k_symv<float>(DevGeom, const float *, const int64_t *, const double *, double, const double *,
+                                       double *, CgState *, const double *, int);
 template __global__ void k_psi_apply<double>(DevGeom, const double *, const int64_t *, const int *, const double *,
-                                             double, double *, CgState *, const double *, int);
+                                             double, const double *, double *, CgState *, const double *, int);
 template __global__ void k_psi_apply<float>(DevGeom, const float *, const int64_t *, const int *, const double *,
-                                            double, double *, CgState *, const double *, int);
+                                            double, const double *, double *, CgState *, const double *, int);
 template __global__ void k_psi_correct<double>(DevGeom, DevCoarse, const double *, const int64_t *, const double *,
                                                const double *, double *, const CgState *);
 template __global__ void k_psi_correct<float>(DevGeom, DevCoarse, const float *, const int64_t *, const double *,

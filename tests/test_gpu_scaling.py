@@ -1,0 +1,95 @@
+"""Stiffness scaling (GPU): BDDC_STIFFNESS_SCALING against the oracle.
+
+Permeability constant on each 4 x 4 box of the 16 x 16 square (lognormal,
+and a checkerboard of 1 and 1e4), both forms, tau off:
+* the preconditioner applied to a random interface vector within 1e-10 of the
+  oracle's;
+* solves within 1e-8 (FP64, the oracle's iteration count) / 1e-6 (mixed, +-1),
+  with the condition estimate of the oracle (1e-6) and far below the one of
+  the weights 1/2;
+* a homogeneous field gives the multiplicity results bit for bit;
+* adaptive rows with stiffness weights are refused.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import bddc as ob
+from oracle import rt0
+
+pytestmark = pytest.mark.gpu
+
+N2, H2 = (16, 16), (1 / 16, 1 / 16)
+
+
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1901_02090_amd import Solver
+    return Solver
+
+
+def _relerr(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def _boxwise(kb):
+    k = np.array([kb[x // 4, y // 4] for y in range(16) for x in range(16)])
+    return np.stack([k, k], 1)
+
+
+FIELDS = {
+    "lognormal": lambda: _boxwise(np.random.default_rng(0).lognormal(0, 3, (4, 4))),
+    "checker": lambda: _boxwise(np.array([[1e4 if (bx + by) % 2 else 1.0 for by in range(4)] for bx in range(4)])),
+}
+
+
+@pytest.mark.parametrize("name", list(FIELDS))
+def test_stiffness_scaling_matches_oracle(name):
+    Solver = _gpu()
+    perm = FIELDS[name]()
+    cuts = W.regular_cuts(N2, (4, 4))
+    src = W.corner_pair(N2)
+    o = ob.BDDC(rt0.Grid(N2, H2), perm, cuts, scaling="stiffness")
+    ref = o.solve(src, rtol=1e-10)
+    for prec, tol, dit in (("fp64", 1e-8, 0), ("mixed", 1e-6, 1)):
+        s = Solver(N2, H2, perm, cuts, precision=prec, scaling="stiffness")
+        try:
+            if prec == "fp64":
+                xu = np.random.default_rng(1).standard_normal(o.subs.n_gamma)
+                zu, _ = s.apply_precond(xu)
+                assert _relerr(zu, o.precondition(xu)[0]) <= 1e-10
+            u, p = s.solve(src, rtol=1e-10)
+            st = s.stats()
+            print(f"{name} {prec}: it {st['it']} (oracle {ref['it']}), kappa {st['kappa']:.3f} "
+                  f"(oracle {ref['kappa']:.3f}), flux {_relerr(u, ref['u']):.1e}", flush=True)
+            assert abs(st["it"] - ref["it"]) <= dit
+            assert _relerr(u, ref["u"]) <= tol and _relerr(p, ref["p"]) <= tol
+            if prec == "fp64":
+                assert abs(st["kappa"] - ref["kappa"]) <= 1e-6 * ref["kappa"]
+        finally:
+            s.close()
+
+
+def test_homogeneous_stiffness_equals_multiplicity():
+    Solver = _gpu()
+    pr = W.homogeneous(N2, H2, W.regular_cuts(N2, (4, 4)))
+    out = []
+    for sc in ("multiplicity", "stiffness"):
+        s = Solver(pr.n, pr.h, pr.perm, pr.cuts, scaling=sc)
+        try:
+            out.append(s.solve(pr.source, rtol=1e-10))
+        finally:
+            s.close()
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+
+
+def test_adaptive_with_stiffness_refused():
+    Solver = _gpu()
+    from paper_1901_02090_amd import BddcError
+    perm = FIELDS["lognormal"]()
+    with pytest.raises(BddcError):
+        Solver(N2, H2, perm, W.regular_cuts(N2, (4, 4)), tau=3.0, scaling="stiffness")
