@@ -13,7 +13,6 @@ local operators inside the FP64 CG); the FP64 form is reported beside it.
 import argparse
 import faulthandler
 import json
-import math
 import os
 import sys
 import time

@@ -854,7 +854,6 @@ void launch_iteration(bddc_problem *h) {
   const Layout &L = h->L;
   hipStream_t s = h->stream;
   const int N = L.N, nGm = L.nGamma;
-  const size_t shm = (size_t)5 * ld4(L.maxG) * sizeof(double);
   const int nb = vec_blocks(nGm);
   k_symv<double><<<N, SYMV_THREADS, symv_shm(L), s>>>(h->g, h->Spk, h->d_pk, h->pu, 1.0, nullptr, h->yloc, h->st, nullptr, 0);
   k_sys_assemble<<<nb, 256, 0, s>>>(h->g, h->yloc, h->pp, h->dscale, h->pu, h->qu, h->part_g, h->st);
@@ -1468,7 +1467,6 @@ int bddc_apply(bddc_handle h, int32_t which, const double *x_u, const double *x_
     if (which == BDDC_OP_SYSTEM) {
       if (!x_p) throw Error{BDDC_EINVAL, "x_p required"};
       HIPCHK(hipMemcpyAsync(h->pp, x_p, N * sizeof(double), hipMemcpyHostToDevice, s));
-      const size_t shm = (size_t)5 * ld4(L.maxG) * sizeof(double);
       k_symv<double><<<N, SYMV_THREADS, symv_shm(L), s>>>(h->g, h->Spk, h->d_pk, h->ru, 1.0, nullptr, h->yloc, nullptr, nullptr, 0);
       k_sys_assemble<<<nblk(nGm), 256, 0, s>>>(h->g, h->yloc, h->pp, h->dscale, nullptr, h->qu, nullptr, nullptr);
       k_b0<<<N, 256, 0, s>>>(h->g, h->ru, h->dscale, h->xp);
@@ -1499,7 +1497,6 @@ int bddc_time_kernel(bddc_handle h, int32_t which, int32_t reps, double *avg_ms,
     hipStream_t s = h->stream;
     const int N = L.N;
     if (L.nGamma == 0) throw Error{BDDC_EINVAL, "no interface"};
-    const size_t shm = (size_t)5 * ld4(L.maxG) * sizeof(double);
     double pk = 0.0;
     for (int i = 0; i < N; ++i) pk += (double)L.nG[i] * (L.nG[i] + 1) / 2;
     const double totG = (double)L.g_off[N];

@@ -10,7 +10,6 @@ and a checkerboard of 1 and 1e4), both forms, tau off:
 * a homogeneous field gives the multiplicity results bit for bit;
 * adaptive rows with stiffness weights are refused.
 """
-import math
 
 import numpy as np
 import pytest

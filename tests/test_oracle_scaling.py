@@ -14,7 +14,6 @@ constant along each face.  Pinned by:
 * adaptive rows with stiffness weights are refused (the pair eigenproblems
   assume 1/2).
 """
-import math
 
 import numpy as np
 import pytest
