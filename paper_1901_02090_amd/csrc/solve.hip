@@ -550,15 +550,34 @@ __device__ __forceinline__ void line_solve_s(int n, const double *m, double *y) 
   for (int j = n - 2; j >= 1; --j) y[j] -= cp[j] * y[j + 1];
 }
 
-// Block GEMV y = X v with X symmetric n x n column major (wave per row).
-__device__ __forceinline__ void block_symgemv(int n, const double *__restrict__ X, const double *v, double *y) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int r = wv; r < n; r += 4) {
-    const double *col = X + (int64_t)r * n;
-    double s = 0.0;
-    for (int c = lane; c < n; c += 64) s = fma(col[c], v[c], s);
-    s = wave_sum(s);
-    if (lane == 0) y[r] = s;
+// Block GEMV y = X v, X n x n column major, v and y in LDS.  A thread owns two
+// rows (r, r + 256) and walks the columns four at a time with eight
+// independent accumulators, so eight loads are in flight per thread and every
+// column is read coalesced across the rows (non-temporal: X is read once).  (One wave per row with a strided
+// inner loop waits on one load after another and ran at a third of this.)
+__device__ __forceinline__ void block_gemv(int n, const double *__restrict__ X, const double *v, double *y) {
+  for (int r0 = threadIdx.x; r0 < n; r0 += 512) {
+    const int r1 = r0 + 256;
+    const bool two = r1 < n;
+    const double *x0 = X + r0, *x1 = X + (two ? r1 : r0);
+    double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int c = 0;
+    for (; c + 4 <= n; c += 4) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t o = (int64_t)(c + q) * n;
+        const double vc = v[c + q];
+        a[q] = fma(__builtin_nontemporal_load(x0 + o), vc, a[q]);
+        a[4 + q] = fma(__builtin_nontemporal_load(x1 + o), vc, a[4 + q]);
+      }
+    }
+    for (; c < n; ++c) {
+      const int64_t o = (int64_t)c * n;
+      a[0] = fma(__builtin_nontemporal_load(x0 + o), v[c], a[0]);
+      a[4] = fma(__builtin_nontemporal_load(x1 + o), v[c], a[4]);
+    }
+    y[r0] = (a[0] + a[1]) + (a[2] + a[3]);
+    if (two) y[r1] = (a[4] + a[5]) + (a[6] + a[7]);
   }
   __syncthreads();
 }
@@ -587,7 +606,7 @@ __global__ __launch_bounds__(256) void k_source_term(DevGeom g, const double *__
     for (int t = tid; t < nG; t += 256) hloc[go + t] = 0.0;
     return;
   }
-  block_symgemv(nc, Xmat + Xoff[i], Fs, ys);
+  block_gemv(nc, Xmat + Xoff[i], Fs, ys);
   int ext[3], st[3];
   for (int d = 0; d < 3; ++d) ext[d] = g.ext[3 * i + d];
   st[0] = 1; st[1] = ext[0]; st[2] = ext[0] * ext[1];
@@ -691,7 +710,7 @@ __global__ __launch_bounds__(256) void k_recover(DevGeom g, const double *__rest
     lbase += 2 * lines;
     __syncthreads();
   }
-  block_symgemv(nc, Xmat + Xoff[i], ys, ps);
+  block_gemv(nc, Xmat + Xoff[i], ys, ps);
   // interior fluxes: u_I = G(-A_IG w - B_I^T p), line by line
   lbase = 0;
   for (int d = 0; d < g.dim; ++d) {
