@@ -408,3 +408,27 @@ def test_coarse_dataflow_matches_level_sweeps(precision):
         assert np.array_equal(uf, ul) and np.array_equal(qf, ql)
     s_flow.close()
     s_lvl.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_zero_source_gives_zero_solution(prec):
+    """Degenerate source: with F = 0 the flux and the zero-mean pressure vanish, the CG stops before its first
+    iteration (r_0 = 0), and steps 1 and 1-2 give zero as well."""
+    Solver = _gpu()
+    pr = W.layer_60x220(0, tau=10.0)
+    s = Solver(pr.n, pr.h, pr.perm, pr.cuts, tau=10.0, precision=prec)
+    zero = np.zeros_like(pr.source)
+    u, p = s.solve(zero, rtol=1e-8)
+    st = s.stats()
+    assert st["it"] == 0 and st["converged"] == 1
+    assert not np.any(u) and not np.any(p)
+    for steps in (1, 12):
+        u, p = s.solve(zero, rtol=1e-8, steps=steps)
+        assert not np.any(u) and not np.any(p)
+    # the handle is unchanged: a real source still solves as on a fresh handle
+    u1, p1 = s.solve(pr.source, rtol=1e-8)
+    s.close()
+    s2 = Solver(pr.n, pr.h, pr.perm, pr.cuts, tau=10.0, precision=prec)
+    u2, p2 = s2.solve(pr.source, rtol=1e-8)
+    s2.close()
+    assert np.array_equal(u1, u2) and np.array_equal(p1, p2)
