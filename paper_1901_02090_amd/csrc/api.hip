@@ -115,6 +115,7 @@ struct bddc_problem {
   double *part_g = nullptr, *part_r = nullptr, *part_z = nullptr, *part_p = nullptr;
   double *d_src = nullptr, *d_flux = nullptr, *d_pres = nullptr;
   double *d_zero_src = nullptr;                   // zero source of the step-1-only mode
+  double *rec_y = nullptr, *rec_p = nullptr;      // [n_cells] post-correction: pressure rhs, X^i product
   double *lw = nullptr;                           // [sum nG] weights of E^T per local interface dof (null: 1/2)
   double *alpha_h = nullptr, *beta_h = nullptr;
   CgState *st = nullptr;
@@ -727,6 +728,8 @@ void do_setup(bddc_problem *h, const bddc_grid *gr, const double *perm, const bd
   h->part_p = h->alloc<double>(1024);
   h->d_src = h->alloc<double>(L.ncells);
   h->d_zero_src = h->alloc<double>(L.ncells);
+  h->rec_y = h->alloc<double>(L.ncells);
+  h->rec_p = h->alloc<double>(L.ncells);
   h->d_flux = h->alloc<double>(L.nfaces_all);
   h->d_pres = h->alloc<double>(L.ncells);
   h->alpha_h = h->alloc<double>(h->max_it + 2);
@@ -1125,8 +1128,11 @@ int solve_finish_locked(bddc_problem *h) {
     fill(h, h->d_zero_src, L.ncells, 0.0);
     rsrc = h->d_zero_src;
   }
-  k_recover<<<N, 256, (size_t)(L.maxG + 2 * L.maxC) * sizeof(double), s>>>(h->g, h->mcoef, h->Xmat, h->d_Xoff,
-                                                                            rsrc, h->uG, h->xp, h->dscale, fl, pr);
+  const size_t rec_shm = (size_t)(L.maxG + L.maxC) * sizeof(double);
+  k_recover_rhs<<<N, 256, rec_shm, s>>>(h->g, h->mcoef, rsrc, h->uG, h->rec_y);
+  k_recover_xgemv<<<dim3(N, nblk(L.maxC)), 256, (size_t)L.maxC * sizeof(double), s>>>(h->g, h->Xmat, h->d_Xoff,
+                                                                                       h->rec_y, h->rec_p);
+  k_recover_flux<<<N, 256, rec_shm, s>>>(h->g, h->mcoef, h->uG, h->rec_p, h->xp, h->dscale, fl, pr);
   k_sum_partial<<<256, 256, 0, s>>>(L.ncells, pr, h->part_p);
   k_sub_mean<<<256, 256, 0, s>>>(L.ncells, pr, h->part_p, 256);
   HIPCHK(hipGetLastError());

@@ -107,7 +107,7 @@ double estimate_bytes(const bddc_grid *gr, const bddc_partition *part, double ta
     }
   }
   // CG and output vectors
-  b += 8.0 * (7.0 * L.nGamma + 2.0 * N + 2.0 * totG + sum_nci + 4.0 * (double)L.ncells + (double)L.nfaces_all +
+  b += 8.0 * (7.0 * L.nGamma + 2.0 * N + 2.0 * totG + sum_nci + 6.0 * (double)L.ncells + (double)L.nfaces_all +
               2.0 * nblk(L.nGamma) + nF + 1024 + 20000.0);
   return b;
 }

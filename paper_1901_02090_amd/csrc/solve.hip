@@ -660,27 +660,29 @@ __global__ __launch_bounds__(256) void k_b0(DevGeom g, const double *__restrict_
 
 // ---------------------------------------------------------------------------
 // post-correction: interior fluxes and pressures of every subdomain from the
-// final interface flux u_G and the source (local Dirichlet problems)
+// final interface flux u_G and the source (local Dirichlet problems), in three
+// launches: the pressure right-hand side (one block per subdomain), the
+// product with X^i (a pure stream over X^i in row chunks, so the 4.5 GB of the
+// reservoir are read at the copy rate with no latency-bound line solves and no
+// partial last round of whole subdomains in the way), and the interior fluxes
+// and pressures (one block per subdomain).  ybuf and pbuf hold one value per
+// local cell, in the subdomains' local cell order.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_recover(DevGeom g, const double *__restrict__ mcoef,
-                                                 const double *__restrict__ Xmat, const int64_t *__restrict__ Xoff,
-                                                 const double *__restrict__ src, const double *__restrict__ uG,
-                                                 const double *__restrict__ xp, const double *__restrict__ dscale,
-                                                 double *__restrict__ flux, double *__restrict__ pressure) {
+// y = H w - F = H w + source, with w = R_i u_G
+__global__ __launch_bounds__(256) void k_recover_rhs(DevGeom g, const double *__restrict__ mcoef,
+                                                     const double *__restrict__ src, const double *__restrict__ uG,
+                                                     double *__restrict__ ybuf) {
   extern __shared__ double sh[];
   const int i = blockIdx.x, tid = threadIdx.x;
   const int nc = g.nc[i], nG = g.nG[i];
   const int64_t go = g.g_off[i];
   const int *lcg = g.lcell_global + g.cell_off[i];
-  double *ws = sh, *ys = sh + nG, *ps = ys + nc;
-  int ext[3], lo[3], st[3];
-  for (int d = 0; d < 3; ++d) {
-    ext[d] = g.ext[3 * i + d];
-    lo[d] = g.lo[3 * i + d];
-  }
+  double *ws = sh, *ys = sh + nG;
+  int ext[3], st[3];
+  for (int d = 0; d < 3; ++d) ext[d] = g.ext[3 * i + d];
   st[0] = 1; st[1] = ext[0]; st[2] = ext[0] * ext[1];
   for (int t = tid; t < nG; t += 256) ws[t] = uG[g.Rmap[go + t]];
-  for (int c = tid; c < nc; c += 256) ys[c] = src[lcg[c]];   // y = H w - F = H w + source
+  for (int c = tid; c < nc; c += 256) ys[c] = src[lcg[c]];
   __syncthreads();
   const int *lg = g.line_g + g.line_off[i];
   int64_t lbase = 0;
@@ -710,9 +712,62 @@ __global__ __launch_bounds__(256) void k_recover(DevGeom g, const double *__rest
     lbase += 2 * lines;
     __syncthreads();
   }
-  block_gemv(nc, Xmat + Xoff[i], ys, ps);
-  // interior fluxes: u_I = G(-A_IG w - B_I^T p), line by line
-  lbase = 0;
+  double *yo = ybuf + g.cell_off[i];
+  for (int c = tid; c < nc; c += 256) yo[c] = ys[c];
+}
+
+// p = X^i y: block (i, k) forms rows 256k .. 256k + 255 of subdomain i, one row
+// per thread, eight columns per step with eight independent accumulators (eight
+// loads in flight, each column read coalesced across the rows, non-temporal:
+// X^i is read once).
+__global__ __launch_bounds__(256) void k_recover_xgemv(DevGeom g, const double *__restrict__ Xmat,
+                                                       const int64_t *__restrict__ Xoff,
+                                                       const double *__restrict__ ybuf, double *__restrict__ pbuf) {
+  extern __shared__ double vs[];
+  const int i = blockIdx.x, tid = threadIdx.x;
+  const int nc = g.nc[i];
+  const int r = blockIdx.y * 256 + tid;
+  if (blockIdx.y * 256 >= nc) return;   // the whole block leaves
+  const double *yi = ybuf + g.cell_off[i];
+  for (int c = tid; c < nc; c += 256) vs[c] = yi[c];
+  __syncthreads();
+  if (r >= nc) return;
+  const double *xr = Xmat + Xoff[i] + r;
+  double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  int c = 0;
+  for (; c + 8 <= nc; c += 8) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) a[q] = fma(__builtin_nontemporal_load(xr + (int64_t)(c + q) * nc), vs[c + q], a[q]);
+  }
+  for (; c < nc; ++c) a[0] = fma(__builtin_nontemporal_load(xr + (int64_t)c * nc), vs[c], a[0]);
+  pbuf[g.cell_off[i] + r] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+}
+
+// interior fluxes u_I = G(-A_IG w - B_I^T p), line by line, and the pressures
+// p + D p_0
+__global__ __launch_bounds__(256) void k_recover_flux(DevGeom g, const double *__restrict__ mcoef,
+                                                      const double *__restrict__ uG, const double *__restrict__ pbuf,
+                                                      const double *__restrict__ xp,
+                                                      const double *__restrict__ dscale, double *__restrict__ flux,
+                                                      double *__restrict__ pressure) {
+  extern __shared__ double sh[];
+  const int i = blockIdx.x, tid = threadIdx.x;
+  const int nc = g.nc[i], nG = g.nG[i];
+  const int64_t go = g.g_off[i];
+  const int *lcg = g.lcell_global + g.cell_off[i];
+  double *ws = sh, *ps = sh + nG;
+  int ext[3], lo[3], st[3];
+  for (int d = 0; d < 3; ++d) {
+    ext[d] = g.ext[3 * i + d];
+    lo[d] = g.lo[3 * i + d];
+  }
+  st[0] = 1; st[1] = ext[0]; st[2] = ext[0] * ext[1];
+  const double *pi = pbuf + g.cell_off[i];
+  for (int t = tid; t < nG; t += 256) ws[t] = uG[g.Rmap[go + t]];
+  for (int c = tid; c < nc; c += 256) ps[c] = pi[c];
+  __syncthreads();
+  const int *lg = g.line_g + g.line_off[i];
+  int64_t lbase = 0;
   for (int d = 0; d < g.dim; ++d) {
     const int n = ext[d], lines = nc / n;
     if (n >= 2) {
