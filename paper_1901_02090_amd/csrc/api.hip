@@ -219,6 +219,10 @@ void check_err(bddc_problem *h, const char *stage) {
 
 // LDS of k_symv: the gathered x and one row buffer per wavefront.
 inline size_t symv_shm(const Layout &L) { return (size_t)(1 + SYMV_WAVES) * ld4(L.maxG) * sizeof(double); }
+// LDS of k_source_term (F, X F, staged cell coefficients) and of the
+// post-correction's line kernels (w, one cell vector, staged coefficients).
+inline size_t source_shm(const Layout &L) { return (size_t)5 * L.maxC * sizeof(double); }
+inline size_t recover_shm(const Layout &L) { return (size_t)(L.maxG + 4 * L.maxC) * sizeof(double); }
 
 // Every device array the coarse kernels dereference must exist before a launch.
 void check_coarse_ptrs(const bddc_problem *h) {
@@ -581,6 +585,9 @@ void do_setup(bddc_problem *h, const bddc_grid *gr, const double *perm, const bd
     HIPCHK(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
     if (symv_shm(L) > (size_t)lds_max)
       throw Error{BDDC_EINVAL, "subdomain interface too large for the local operator kernels' LDS"};
+    // source term and post-correction: their vectors and the staged cell coefficients
+    if (std::max(source_shm(L), recover_shm(L)) > (size_t)lds_max)
+      throw Error{BDDC_EINVAL, "subdomain too large for the LDS of the source-term and post-correction kernels"};
   }
   // local coarse spaces Psi^i, coarse matrices and substructure operators T^i
   std::vector<int64_t> cwoff(N), acoff(N), psioff(N);
@@ -1022,7 +1029,7 @@ void solve_begin_launch(bddc_problem *h, const double *rhs, double rtol, double 
   }
   // steps 2-3 right-hand side: f* = -S u0 + H^T X F
   k_symv<double><<<N, SYMV_THREADS, symv_shm(L), s>>>(h->g, h->Spk, h->d_pk, h->u0, 1.0, nullptr, h->yloc, nullptr, nullptr, 0);
-  k_source_term<<<N, 256, (size_t)2 * L.maxC * sizeof(double), s>>>(h->g, h->mcoef, h->Xmat, h->d_Xoff, src,
+  k_source_term<<<N, 256, source_shm(L), s>>>(h->g, h->mcoef, h->Xmat, h->d_Xoff, src,
                                                                      h->wloc);
   k_fstar<<<nblk(nGm), 256, 0, s>>>(h->g, h->yloc, h->wloc, h->ru);
   fill(h, h->xu, nGm, 0.0);
@@ -1128,7 +1135,7 @@ int solve_finish_locked(bddc_problem *h) {
     fill(h, h->d_zero_src, L.ncells, 0.0);
     rsrc = h->d_zero_src;
   }
-  const size_t rec_shm = (size_t)(L.maxG + L.maxC) * sizeof(double);
+  const size_t rec_shm = recover_shm(L);
   k_recover_rhs<<<N, 256, rec_shm, s>>>(h->g, h->mcoef, rsrc, h->uG, h->rec_y);
   k_recover_xgemv<<<dim3(N, nblk(L.maxC)), 256, (size_t)L.maxC * sizeof(double), s>>>(h->g, h->Xmat, h->d_Xoff,
                                                                                        h->rec_y, h->rec_p);

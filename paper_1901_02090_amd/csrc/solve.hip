@@ -535,19 +535,32 @@ __device__ __forceinline__ int line_start_s(int d, int l, const int *ext, const 
   return (l % ext[a0]) * st[a0] + (l / ext[a0]) * st[a1];
 }
 
-__device__ __forceinline__ void line_solve_s(int n, const double *m, double *y) {
+// The line's cell coefficients are m[0], m[ms], ..., m[(n-1) ms] (staged in
+// LDS by the caller).
+__device__ __forceinline__ void line_solve_s(int n, const double *m, int ms, double *y) {
   double cp[MAXLINE];
   if (n < 2) return;
-  double den = (m[0] + m[1]) / 3.0;
-  cp[1] = (n > 2) ? (m[1] / 6.0) / den : 0.0;
+  double den = (m[0] + m[ms]) / 3.0;
+  cp[1] = (n > 2) ? (m[ms] / 6.0) / den : 0.0;
   y[1] = y[1] / den;
   for (int j = 2; j <= n - 1; ++j) {
-    const double e = m[j - 1] / 6.0;
-    den = (m[j - 1] + m[j]) / 3.0 - e * cp[j - 1];
-    cp[j] = (j <= n - 2) ? (m[j] / 6.0) / den : 0.0;
+    const double mj1 = m[(j - 1) * ms], mj = m[j * ms];
+    const double e = mj1 / 6.0;
+    den = (mj1 + mj) / 3.0 - e * cp[j - 1];
+    cp[j] = (j <= n - 2) ? (mj / 6.0) / den : 0.0;
     y[j] = (y[j] - e * y[j - 1]) / den;
   }
   for (int j = n - 2; j >= 1; --j) y[j] -= cp[j] * y[j + 1];
+}
+
+// Cell coefficients of the subdomain's local cells, mc[3c + d], gathered once
+// per block so that the line solves read them from LDS.
+__device__ __forceinline__ void stage_mcoef(int nc, const int *__restrict__ lcg, const double *__restrict__ mcoef,
+                                            double *mc) {
+  for (int k = threadIdx.x; k < 3 * nc; k += blockDim.x) {
+    const int c = k / 3;
+    mc[k] = mcoef[(int64_t)lcg[c] * 3 + (k - 3 * c)];
+  }
 }
 
 // Block GEMV y = X v, X n x n column major, v and y in LDS.  A thread owns two
@@ -593,7 +606,7 @@ __global__ __launch_bounds__(256) void k_source_term(DevGeom g, const double *__
   const int nc = g.nc[i], nG = g.nG[i];
   const int64_t go = g.g_off[i];
   const int *lcg = g.lcell_global + g.cell_off[i];
-  double *Fs = sh, *ys = sh + nc;
+  double *Fs = sh, *ys = sh + nc, *mc = sh + 2 * nc;
   if (tid == 0) any = 0;
   __syncthreads();
   for (int c = tid; c < nc; c += 256) {
@@ -606,7 +619,8 @@ __global__ __launch_bounds__(256) void k_source_term(DevGeom g, const double *__
     for (int t = tid; t < nG; t += 256) hloc[go + t] = 0.0;
     return;
   }
-  block_gemv(nc, Xmat + Xoff[i], Fs, ys);
+  stage_mcoef(nc, lcg, mcoef, mc);
+  block_gemv(nc, Xmat + Xoff[i], Fs, ys);   // ends with a barrier
   int ext[3], st[3];
   for (int d = 0; d < 3; ++d) ext[d] = g.ext[3 * i + d];
   st[0] = 1; st[1] = ext[0]; st[2] = ext[0] * ext[1];
@@ -616,17 +630,18 @@ __global__ __launch_bounds__(256) void k_source_term(DevGeom g, const double *__
     const int n = ext[d];
     const int cd = (lc / st[d]) % n;
     const int s0 = lc - cd * st[d];
-    double m[MAXLINE], y[MAXLINE + 1];
-    for (int u = 0; u < n; ++u) m[u] = mcoef[(int64_t)lcg[s0 + u * st[d]] * 3 + d];
+    const double *m = mc + 3 * s0 + d;
+    const int ms = 3 * st[d];
+    double y[MAXLINE + 1];
     const int eidx = end ? n - 1 : 0;
     double v = (end ? -1.0 : 1.0) * ys[s0 + eidx * st[d]];
     if (n >= 2) {
       // (G B_l^T y)[adj]: (B_l^T y)_j = y[c_j] - y[c_{j-1}]
       y[0] = 0.0;
       for (int j = 1; j <= n - 1; ++j) y[j] = ys[s0 + j * st[d]] - ys[s0 + (j - 1) * st[d]];
-      line_solve_s(n, m, y);
+      line_solve_s(n, m, ms, y);
       const int adj = end ? n - 1 : 1;
-      v -= (m[eidx] / 6.0) * y[adj];
+      v -= (m[eidx * ms] / 6.0) * y[adj];
     }
     hloc[go + t] = v;
   }
@@ -677,12 +692,13 @@ __global__ __launch_bounds__(256) void k_recover_rhs(DevGeom g, const double *__
   const int nc = g.nc[i], nG = g.nG[i];
   const int64_t go = g.g_off[i];
   const int *lcg = g.lcell_global + g.cell_off[i];
-  double *ws = sh, *ys = sh + nG;
+  double *ws = sh, *ys = sh + nG, *mc = sh + nG + nc;
   int ext[3], st[3];
   for (int d = 0; d < 3; ++d) ext[d] = g.ext[3 * i + d];
   st[0] = 1; st[1] = ext[0]; st[2] = ext[0] * ext[1];
   for (int t = tid; t < nG; t += 256) ws[t] = uG[g.Rmap[go + t]];
   for (int c = tid; c < nc; c += 256) ys[c] = src[lcg[c]];
+  stage_mcoef(nc, lcg, mcoef, mc);
   __syncthreads();
   const int *lg = g.line_g + g.line_off[i];
   int64_t lbase = 0;
@@ -695,12 +711,13 @@ __global__ __launch_bounds__(256) void k_recover_rhs(DevGeom g, const double *__
       ys[s0] += wm;
       ys[s0 + (n - 1) * st[d]] -= wp;
       if (n >= 2 && (tm >= 0 || tp >= 0)) {
-        double m[MAXLINE], y[MAXLINE + 1];
-        for (int u = 0; u < n; ++u) m[u] = mcoef[(int64_t)lcg[s0 + u * st[d]] * 3 + d];
+        const double *m = mc + 3 * s0 + d;
+        const int ms = 3 * st[d];
+        double y[MAXLINE + 1];
         for (int j = 0; j <= n; ++j) y[j] = 0.0;
         y[1] += (m[0] / 6.0) * wm;
-        y[n - 1] += (m[n - 1] / 6.0) * wp;
-        line_solve_s(n, m, y);
+        y[n - 1] += (m[(n - 1) * ms] / 6.0) * wp;
+        line_solve_s(n, m, ms, y);
         for (int c = 0; c < n; ++c) {
           double v = 0.0;
           if (c >= 1) v += y[c];
@@ -726,8 +743,8 @@ __global__ __launch_bounds__(256) void k_recover_xgemv(DevGeom g, const double *
   extern __shared__ double vs[];
   const int i = blockIdx.x, tid = threadIdx.x;
   const int nc = g.nc[i];
-  const int r = blockIdx.y * 256 + tid;
-  if (blockIdx.y * 256 >= nc) return;   // the whole block leaves
+  const int r0 = (int)blockIdx.y * 256, r = r0 + tid;
+  if (r0 >= nc) return;   // the whole block leaves
   const double *yi = ybuf + g.cell_off[i];
   for (int c = tid; c < nc; c += 256) vs[c] = yi[c];
   __syncthreads();
@@ -755,7 +772,7 @@ __global__ __launch_bounds__(256) void k_recover_flux(DevGeom g, const double *_
   const int nc = g.nc[i], nG = g.nG[i];
   const int64_t go = g.g_off[i];
   const int *lcg = g.lcell_global + g.cell_off[i];
-  double *ws = sh, *ps = sh + nG;
+  double *ws = sh, *ps = sh + nG, *mc = sh + nG + nc;
   int ext[3], lo[3], st[3];
   for (int d = 0; d < 3; ++d) {
     ext[d] = g.ext[3 * i + d];
@@ -765,6 +782,7 @@ __global__ __launch_bounds__(256) void k_recover_flux(DevGeom g, const double *_
   const double *pi = pbuf + g.cell_off[i];
   for (int t = tid; t < nG; t += 256) ws[t] = uG[g.Rmap[go + t]];
   for (int c = tid; c < nc; c += 256) ps[c] = pi[c];
+  stage_mcoef(nc, lcg, mcoef, mc);
   __syncthreads();
   const int *lg = g.line_g + g.line_off[i];
   int64_t lbase = 0;
@@ -775,13 +793,14 @@ __global__ __launch_bounds__(256) void k_recover_flux(DevGeom g, const double *_
         const int s0 = line_start_s(d, l, ext, st);
         const int tm = lg[lbase + 2 * l], tp = lg[lbase + 2 * l + 1];
         const double wm = tm >= 0 ? ws[tm] : 0.0, wp = tp >= 0 ? ws[tp] : 0.0;
-        double m[MAXLINE], y[MAXLINE + 1];
-        for (int u = 0; u < n; ++u) m[u] = mcoef[(int64_t)lcg[s0 + u * st[d]] * 3 + d];
+        const double *m = mc + 3 * s0 + d;
+        const int ms = 3 * st[d];
+        double y[MAXLINE + 1];
         y[0] = 0.0;
         for (int j = 1; j <= n - 1; ++j) y[j] = -(ps[s0 + j * st[d]] - ps[s0 + (j - 1) * st[d]]);
         y[1] -= (m[0] / 6.0) * wm;
-        y[n - 1] -= (m[n - 1] / 6.0) * wp;
-        line_solve_s(n, m, y);
+        y[n - 1] -= (m[(n - 1) * ms] / 6.0) * wp;
+        line_solve_s(n, m, ms, y);
         for (int j = 1; j <= n - 1; ++j) {
           const int lc = s0 + j * st[d];
           int c[3] = {lo[0] + lc % ext[0], lo[1] + (lc / ext[0]) % ext[1], lo[2] + lc / (ext[0] * ext[1])};
