@@ -247,6 +247,22 @@ int bddc_apply(bddc_handle h, int32_t which, const double *x_u, const double *x_
 int bddc_solve_batch(bddc_handle h, int32_t nrhs, const double *rhs, double rtol, double *flux, double *pressure,
                      uint32_t flags, int32_t *iterations);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops and harnesses that forbid hipMalloc): bddc_solve with
+ * BDDC_DEVICE_PTRS | BDDC_EAGER semantics that calls no hipMalloc, hipFree or
+ * allocating routine.  rhs [n_cells], flux [n_faces_all] and pressure
+ * [n_cells] are device pointers owned by the caller; the result equals that of
+ * bddc_solve on the same source.  The CG scratch (dot-product partials, the
+ * device CG state, the alpha / beta history of the condition estimate) lives
+ * in a static 512 KiB device array of the library, one per device, instead of
+ * the handle's own arrays; every other array the solve uses was allocated by
+ * bddc_setup.  The array is shared by every call on the device and keeps the
+ * last call's contents (each call initialises what it reads): calls that
+ * overlap on one device race, also across handles.  The handle's max_it must
+ * be at most 31,854 (the history the array holds): BDDC_EINVAL otherwise.
+ * Returns as bddc_solve; statistics are those of this solve. */
+int bddc_solve_noalloc(bddc_handle h, const double *rhs, double rtol, double *flux, double *pressure);
+
 /* Device memory of every handle set up afterwards comes from alloc(bytes,
  * ctx) and goes back through free(ptr, ctx) (for instance a framework's
  * caching allocator); both NULL restore hipMalloc / hipFree.  The routines

@@ -25,7 +25,7 @@ OP_SYSTEM, OP_PRECOND = 1, 2
 
 EXPORTED = ["bddc_setup", "bddc_solve", "bddc_stats", "bddc_set_stream", "bddc_destroy", "bddc_last_error",
             "bddc_sizes", "bddc_export", "bddc_apply", "bddc_time_kernel", "bddc_estimate_bytes",
-            "bddc_solve_batch", "bddc_set_allocator",
+            "bddc_solve_batch", "bddc_solve_noalloc", "bddc_set_allocator",
             "bddc_server_create", "bddc_server_submit", "bddc_server_poll", "bddc_server_stats",
             "bddc_server_destroy"]
 K_SCHUR_APPLY, K_PRECOND_APPLY, K_PRECOND_FULL = 1, 2, 3
@@ -142,6 +142,8 @@ def load_library(path=LIB_PATH):
     lib.bddc_time_kernel.restype = C.c_int
     lib.bddc_solve_batch.argtypes = [P, C.c_int32, P, C.c_double, P, P, C.c_uint32, C.POINTER(C.c_int32)]
     lib.bddc_solve_batch.restype = C.c_int
+    lib.bddc_solve_noalloc.argtypes = [P, P, C.c_double, P, P]
+    lib.bddc_solve_noalloc.restype = C.c_int
     lib.bddc_set_allocator.argtypes = [ALLOC_FN, FREE_FN, C.c_void_p]
     lib.bddc_set_allocator.restype = C.c_int
     lib.bddc_estimate_bytes.argtypes = [C.POINTER(Grid), C.POINTER(Partition), C.c_double, C.POINTER(Options), dp]
@@ -267,6 +269,13 @@ class Solver:
         rc = self.lib.bddc_solve(self.h, C.c_void_p(src_ptr), float(rtol), C.c_void_p(flux_ptr),
                                  C.c_void_p(pres_ptr),
                                  BDDC_DEVICE_PTRS | (BDDC_EAGER if eager else 0) | _steps_flag(steps))
+        return _check(self.lib, rc, allow=(BDDC_ENOCONV,))
+
+    def solve_noalloc(self, src_ptr, rtol, flux_ptr, pres_ptr):
+        """Device-pointer solve through bddc_solve_noalloc (no device allocation;
+        CG scratch in the library's static device array)."""
+        rc = self.lib.bddc_solve_noalloc(self.h, C.c_void_p(src_ptr), float(rtol), C.c_void_p(flux_ptr),
+                                         C.c_void_p(pres_ptr))
         return _check(self.lib, rc, allow=(BDDC_ENOCONV,))
 
     def set_stream(self, stream_ptr):

@@ -47,6 +47,32 @@ struct Error {
   std::string msg;
 };
 
+// Scratch of one solve's CG: the dot-product partials of the producing
+// kernels (at most PART_BLOCKS each), the device CG state and the alpha / beta
+// history the Lanczos estimate reads.
+struct CgScratch {
+  CgState *st = nullptr;
+  double *part_g = nullptr, *part_r = nullptr, *part_z = nullptr, *part_p = nullptr;
+  double *alpha_h = nullptr, *beta_h = nullptr;
+};
+
+// Static scratch of bddc_solve_noalloc (512 KiB, one copy per device, held
+// until the process ends).  In host code `scratch` names a host-side stand-in:
+// its device address comes from hipGetSymbolAddress, once per device, and
+// only that address is passed on.  Layout in doubles: the CG state (32), the
+// partials of the operator dot product, the residual norm and the
+// preconditioned dot product (PART_BLOCKS each), those of the pressure mean
+// (256), then the alpha and the beta history (NOALLOC_HIST each).
+constexpr int64_t NOALLOC_DOUBLES = 65536;
+constexpr int64_t NOALLOC_HEAD = 32 + 3 * PART_BLOCKS + 256;
+constexpr int64_t NOALLOC_HIST = (NOALLOC_DOUBLES - NOALLOC_HEAD) / 2;
+static_assert(sizeof(CgState) <= 32 * sizeof(double), "CG state exceeds its scratch slot");
+static __device__ __align__(256) double scratch[NOALLOC_DOUBLES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[MAX_DEVICES] = {};
+
 #define HIPCHK(x)                                                                         \
   do {                                                                                    \
     hipError_t e_ = (x);                                                                  \
@@ -112,13 +138,15 @@ struct bddc_problem {
   double *xu = nullptr, *ru = nullptr, *pu = nullptr, *zu = nullptr, *qu = nullptr, *u0 = nullptr, *uG = nullptr;
   double *xp = nullptr, *pp = nullptr, *yloc = nullptr, *wloc = nullptr, *gloc = nullptr, *bc = nullptr,
          *csol = nullptr;
-  double *part_g = nullptr, *part_r = nullptr, *part_z = nullptr, *part_p = nullptr;
   double *d_src = nullptr, *d_flux = nullptr, *d_pres = nullptr;
   double *d_zero_src = nullptr;                   // zero source of the step-1-only mode
   double *rec_y = nullptr, *rec_p = nullptr;      // [n_cells] post-correction: pressure rhs, X^i product
   double *lw = nullptr;                           // [sum nG] weights of E^T per local interface dof (null: 1/2)
-  double *alpha_h = nullptr, *beta_h = nullptr;
-  CgState *st = nullptr;
+  // dot-product partials, CG state and coefficient history of a solve: the
+  // handle's own arrays (cgw_own), or the library's static scratch while
+  // bddc_solve_noalloc runs
+  CgScratch cgw{}, cgw_own{};
+  int device = 0;                                 // device the handle lives on
   CgState *st_host = nullptr;                     // [2] pinned: state after chunk k lands in [k & 1]
   double *ab_host = nullptr;                      // pinned: CG alpha / beta history of the last solve
   hipEvent_t ev_state[2] = {nullptr, nullptr};    // recorded after each chunk's state copy
@@ -729,19 +757,20 @@ void do_setup(bddc_problem *h, const bddc_grid *gr, const double *perm, const bd
   h->yloc = h->alloc<double>(totG);
   h->wloc = h->alloc<double>(totG);
   h->gloc = h->alloc<double>(sub_coff[N]);
-  h->part_g = h->alloc<double>(nblk(nGm) + 1);
-  h->part_r = h->alloc<double>(nblk(nGm) + 1);
-  h->part_z = h->alloc<double>(nF + 1);
-  h->part_p = h->alloc<double>(1024);
+  h->cgw.part_g = h->alloc<double>(nblk(nGm) + 1);
+  h->cgw.part_r = h->alloc<double>(nblk(nGm) + 1);
+  h->cgw.part_z = h->alloc<double>(nF + 1);
+  h->cgw.part_p = h->alloc<double>(1024);
   h->d_src = h->alloc<double>(L.ncells);
   h->d_zero_src = h->alloc<double>(L.ncells);
   h->rec_y = h->alloc<double>(L.ncells);
   h->rec_p = h->alloc<double>(L.ncells);
   h->d_flux = h->alloc<double>(L.nfaces_all);
   h->d_pres = h->alloc<double>(L.ncells);
-  h->alpha_h = h->alloc<double>(h->max_it + 2);
-  h->beta_h = h->alloc<double>(h->max_it + 2);
-  h->st = h->alloc<CgState>(1);
+  h->cgw.alpha_h = h->alloc<double>(h->max_it + 2);
+  h->cgw.beta_h = h->alloc<double>(h->max_it + 2);
+  h->cgw.st = h->alloc<CgState>(1);
+  h->cgw_own = h->cgw;
   HIPCHK(hipHostMalloc((void **)&h->st_host, 2 * sizeof(CgState), hipHostMallocDefault));
   HIPCHK(hipHostMalloc((void **)&h->ab_host, 2 * (size_t)(h->max_it + 2) * sizeof(double), hipHostMallocDefault));
   for (hipEvent_t &e : h->ev_state) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
@@ -818,8 +847,8 @@ void launch_precond(bddc_problem *h, const double *r, double *z, double *zpart, 
   hipStream_t s = h->stream;
   const int N = L.N, nF = L.nF;
   const size_t shm = (size_t)5 * ld4(L.maxG) * sizeof(double);
-  CgState *st = check ? h->st : nullptr;
-  const double *rp = check ? h->part_r : nullptr;
+  CgState *st = check ? h->cgw.st : nullptr;
+  const double *rp = check ? h->cgw.part_r : nullptr;
   const int nrp = vec_blocks(L.nGamma);
   const bool mixed = h->precision == BDDC_MIXED;
   // The coarse chain (right-hand side pieces Psi^{iT} r^i with the stopping
@@ -865,13 +894,13 @@ void launch_iteration(bddc_problem *h) {
   hipStream_t s = h->stream;
   const int N = L.N, nGm = L.nGamma;
   const int nb = vec_blocks(nGm);
-  k_symv<double><<<N, SYMV_THREADS, symv_shm(L), s>>>(h->g, h->Spk, h->d_pk, h->pu, 1.0, nullptr, h->yloc, h->st, nullptr, 0);
-  k_sys_assemble<<<nb, 256, 0, s>>>(h->g, h->yloc, h->pp, h->dscale, h->pu, h->qu, h->part_g, h->st);
-  k_update_xr<<<nb, 256, 0, s>>>(nGm, N, h->part_g, nb, h->pu, h->qu, h->pp, h->xu, h->ru, h->xp, h->part_r,
-                                 h->st, h->alpha_h);
-  launch_precond(h, h->ru, h->zu, h->part_z, true);
-  k_update_p<<<nb, 256, 0, s>>>(nGm, N, h->cs.pidx, h->part_z, face_blocks(L.nF), h->zu, h->csol, h->pu, h->pp,
-                                h->st, h->beta_h);
+  k_symv<double><<<N, SYMV_THREADS, symv_shm(L), s>>>(h->g, h->Spk, h->d_pk, h->pu, 1.0, nullptr, h->yloc, h->cgw.st, nullptr, 0);
+  k_sys_assemble<<<nb, 256, 0, s>>>(h->g, h->yloc, h->pp, h->dscale, h->pu, h->qu, h->cgw.part_g, h->cgw.st);
+  k_update_xr<<<nb, 256, 0, s>>>(nGm, N, h->cgw.part_g, nb, h->pu, h->qu, h->pp, h->xu, h->ru, h->xp, h->cgw.part_r,
+                                 h->cgw.st, h->cgw.alpha_h);
+  launch_precond(h, h->ru, h->zu, h->cgw.part_z, true);
+  k_update_p<<<nb, 256, 0, s>>>(nGm, N, h->cs.pidx, h->cgw.part_z, face_blocks(L.nF), h->zu, h->csol, h->pu, h->pp,
+                                h->cgw.st, h->cgw.beta_h);
 }
 
 double lanczos_kappa(const std::vector<double> &a, const std::vector<double> &b, double *lmin, double *lmax) {
@@ -1034,11 +1063,11 @@ void solve_begin_launch(bddc_problem *h, const double *rhs, double rtol, double 
   k_fstar<<<nblk(nGm), 256, 0, s>>>(h->g, h->yloc, h->wloc, h->ru);
   fill(h, h->xu, nGm, 0.0);
   fill(h, h->xp, N, 0.0);
-  k_norm2_partial<<<vec_blocks(nGm), 256, 0, s>>>(nGm, h->ru, h->part_r);
-  launch_precond(h, h->ru, h->zu, h->part_z, false);
-  k_init_p<<<nb, 256, 0, s>>>(nGm, N, h->cs.pidx, h->part_z, face_blocks(nF), h->part_r, vec_blocks(nGm), h->zu,
+  k_norm2_partial<<<vec_blocks(nGm), 256, 0, s>>>(nGm, h->ru, h->cgw.part_r);
+  launch_precond(h, h->ru, h->zu, h->cgw.part_z, false);
+  k_init_p<<<nb, 256, 0, s>>>(nGm, N, h->cs.pidx, h->cgw.part_z, face_blocks(nF), h->cgw.part_r, vec_blocks(nGm), h->zu,
                               h->csol, h->pu, h->pp,
-                              h->st, rtol, h->max_it);
+                              h->cgw.st, rtol, h->max_it);
   HIPCHK(hipGetLastError());
 }
 
@@ -1066,7 +1095,7 @@ void solve_chunk(bddc_problem *h) {
   }
   HIPCHK(hipGetLastError());
   const int slot = R.chunks & 1;
-  HIPCHK(hipMemcpyAsync(h->st_host + slot, h->st, sizeof(CgState), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(h->st_host + slot, h->cgw.st, sizeof(CgState), hipMemcpyDeviceToHost, s));
   HIPCHK(hipEventRecord(h->ev_state[slot], s));
   ++R.chunks;
 }
@@ -1116,8 +1145,8 @@ int solve_finish_locked(bddc_problem *h) {
     HIPCHK(hipEventRecord(h->ev1, s));
     if (it_bound > 0) {
       double *ah = h->ab_host, *bh = h->ab_host + (h->max_it + 2);
-      HIPCHK(hipMemcpyAsync(ah, h->alpha_h, it_bound * sizeof(double), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipMemcpyAsync(bh, h->beta_h, it_bound * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(ah, h->cgw.alpha_h, it_bound * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(bh, h->cgw.beta_h, it_bound * sizeof(double), hipMemcpyDeviceToHost, s));
     }
     // final interface flux
     k_axpby<<<nblk(nGm), 256, 0, s>>>(nGm, 1.0, h->u0, 1.0, h->xu, h->uG);
@@ -1140,8 +1169,8 @@ int solve_finish_locked(bddc_problem *h) {
   k_recover_xgemv<<<dim3(N, nblk(L.maxC)), 256, (size_t)L.maxC * sizeof(double), s>>>(h->g, h->Xmat, h->d_Xoff,
                                                                                        h->rec_y, h->rec_p);
   k_recover_flux<<<N, 256, rec_shm, s>>>(h->g, h->mcoef, h->uG, h->rec_p, h->xp, h->dscale, fl, pr);
-  k_sum_partial<<<256, 256, 0, s>>>(L.ncells, pr, h->part_p);
-  k_sub_mean<<<256, 256, 0, s>>>(L.ncells, pr, h->part_p, 256);
+  k_sum_partial<<<256, 256, 0, s>>>(L.ncells, pr, h->cgw.part_p);
+  k_sub_mean<<<256, 256, 0, s>>>(L.ncells, pr, h->cgw.part_p, 256);
   HIPCHK(hipGetLastError());
   if (!R.dev) {
     HIPCHK(hipMemcpyAsync(R.flux, fl, L.nfaces_all * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1200,6 +1229,39 @@ void apply_options(bddc_problem *h, const bddc_options *opt) {
   if (h->precision != BDDC_FP64 && h->precision != BDDC_MIXED) throw Error{BDDC_EINVAL, "bad precision"};
 }
 
+// Device address of `scratch` on device `dev` (the current device), looked up
+// once per device at the first setup on it.
+void resolve_scratch(int dev) {
+  if (dev < 0 || dev >= MAX_DEVICES) throw Error{BDDC_EDEVICE, "device index beyond the static scratch table"};
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[dev]) return;
+  void *p = nullptr;
+  HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  if (!p) throw Error{BDDC_EDEVICE, "no device address for the static scratch"};
+  g_scratch_ptr[dev] = p;
+}
+
+// The CG scratch of bddc_solve_noalloc, carved out of device `dev`'s copy of
+// `scratch` (layout at its declaration).
+CgScratch noalloc_scratch(int dev) {
+  void *base = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (dev >= 0 && dev < MAX_DEVICES) base = g_scratch_ptr[dev];
+  }
+  if (!base) throw Error{BDDC_EDEVICE, "static scratch not resolved on the handle's device"};
+  double *b = (double *)base;
+  CgScratch w;
+  w.st = (CgState *)b;
+  w.part_g = b + 32;
+  w.part_r = w.part_g + PART_BLOCKS;
+  w.part_z = w.part_r + PART_BLOCKS;
+  w.part_p = w.part_z + PART_BLOCKS;
+  w.alpha_h = b + NOALLOC_HEAD;
+  w.beta_h = w.alpha_h + NOALLOC_HIST;
+  return w;
+}
+
 bddc_problem *make_problem(const bddc_grid *g, const double *perm, const bddc_partition *part, double tau,
                            const bddc_options *opt) {
   GateShared gate(g_gate);
@@ -1208,6 +1270,8 @@ bddc_problem *make_problem(const bddc_grid *g, const double *perm, const bddc_pa
   try {
     apply_options(h, opt);
     h->tau = tau;
+    HIPCHK(hipGetDevice(&h->device));
+    resolve_scratch(h->device);
     HIPCHK(hipStreamCreateWithFlags(&h->own_stream, hipStreamNonBlocking));
     h->stream = h->own_stream;
     do_setup(h, g, perm, part);
@@ -1256,6 +1320,24 @@ int bddc_solve(bddc_handle h, const double *rhs, double rtol, double *flux, doub
   return guarded([&]() -> int {
     if (!h || !rhs || !flux || !pressure) throw Error{BDDC_EINVAL, "null argument"};
     const int rc = do_solve(h, rhs, rtol, flux, pressure, flags);
+    if (rc == BDDC_ENOCONV) g_last_error = "maximum number of CG iterations reached";
+    return rc;
+  });
+}
+
+int bddc_solve_noalloc(bddc_handle h, const double *rhs, double rtol, double *flux, double *pressure) {
+  return guarded([&]() -> int {
+    if (!h || !rhs || !flux || !pressure) throw Error{BDDC_EINVAL, "null argument"};
+    if ((int64_t)h->max_it + 2 > NOALLOC_HIST)
+      throw Error{BDDC_EINVAL, "max_it above " + std::to_string(NOALLOC_HIST - 2) +
+                                   ", the CG history the static scratch holds"};
+    // the handle's CG scratch is swapped for the static one for this call only
+    struct Restore {
+      bddc_problem *h;
+      ~Restore() { h->cgw = h->cgw_own; }
+    } restore{h};
+    h->cgw = noalloc_scratch(h->device);
+    const int rc = do_solve(h, rhs, rtol, flux, pressure, BDDC_DEVICE_PTRS | BDDC_EAGER);
     if (rc == BDDC_ENOCONV) g_last_error = "maximum number of CG iterations reached";
     return rc;
   });
