@@ -119,7 +119,7 @@ def multiscale_compare(pr, ref_flux):
     import torch
     from paper_1901_02090_amd import Solver
     t0 = time.perf_counter()
-    s = Solver(pr.n, pr.h, pr.perm, pr.cuts, precision="mixed", max_it=5000, multiscale=True)
+    s = Solver(pr.n, pr.h, pr.perm, pr.cuts, precision="mixed", max_it=5000, multiscale=True, ms_source=pr.source)
     setup_ms = (time.perf_counter() - t0) * 1e3
     try:
         stream = torch.cuda.current_stream()

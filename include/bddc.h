@@ -61,10 +61,11 @@ extern "C" {
 #define BDDC_MULTISCALE 4u       /* multiscale constraints (Section 6) in place of
                                     the face eigenproblems, tau unused: each face
                                     gets one row, its fluxes in the Darcy problem
-                                    on the two neighbours with a uniform unit
-                                    source / sink and no flow on their other
-                                    faces, projected off the zero-net-flux row
-                                    (none when that flux is uniform)             */
+                                    on the two neighbours with a unit source /
+                                    sink (uniform, or shaped by the well source
+                                    bddc_options.ms_source) and no flow on their
+                                    other faces, projected off the zero-net-flux
+                                    row (none when that flux is uniform)         */
 #define BDDC_STIFFNESS_SCALING 8u /* averaging weights a_i / (a_i + a_j) per face,
                                     a_s the mean diagonal of A^s over the face
                                     (rho-scaling for RT0; the paper's choice when
@@ -110,6 +111,13 @@ typedef struct {
                             which run beside the coarse solve; fewer leave
                             more memory bandwidth to its latency-bound
                             sweeps (<= 0 or > N: one per subdomain)        */
+  const double *ms_source; /* with BDDC_MULTISCALE: host array [n_cells], the
+                            cell-integrated well source that shapes the
+                            multiscale sources (Section 6): a subdomain whose
+                            source is not zero uses w = f / (its sum of f),
+                            the others 1/|Omega^i| (as does a subdomain whose
+                            wells cancel); NULL: uniform everywhere.  Read
+                            during bddc_setup only                         */
 } bddc_options;
 
 typedef struct {

@@ -265,16 +265,34 @@ def face_rows(lam, ci, tau, n_f):
     return np.array(rows), k, omega
 
 
-def multiscale_face_flux(grid, perm, subs, i, j, dofs):
+def multiscale_weight(source, cells):
+    """Source distribution w of the multiscale constraints on one subdomain (Section 6).
+
+    Cell-integrated values over ``cells``, summing to 1: w = 1/|Omega^s| in a
+    subdomain without a well, w = f / int_{Omega^s} f in a subdomain that
+    contains one (the source f is not zero there), so that the local flow is
+    conservative on the fine grid.  ``source`` None: no wells anywhere.
+    READING: a subdomain whose wells cancel (zero net source) keeps the
+    uniform w, since the normalisation is undefined there.
+    """
+    n = len(cells)
+    if source is not None:
+        f = np.asarray(source, dtype=np.float64)[cells]
+        tot = f.sum()
+        if np.any(f != 0.0) and abs(tot) > 1e-12 * np.abs(f).sum():
+            return f / tot
+    return np.full(n, 1.0 / n)
+
+
+def multiscale_face_flux(grid, perm, subs, i, j, dofs, source=None):
     """Face flux of the local Darcy problem behind the multiscale constraints (Section 6).
 
     On the union of the neighbours i and j (i on the minus side of the face):
-    source w_i = 1/|Omega^i| in Omega^i and -w_j in Omega^j, no flow on the
-    union's boundary, the pressure fixed by a zero mean.  Returns the fluxes
-    on the face dofs ``dofs`` (global orientation; they sum to the unit net
-    flux from i to j).  READING: the paper shapes w by the well source in
-    subdomains that contain a well; the setup here knows no source, so every
-    subdomain takes the uniform w.
+    source w_i in Omega^i and -w_j in Omega^j (``multiscale_weight``: uniform,
+    or shaped by the well source ``source`` in a subdomain that contains a
+    well), no flow on the union's boundary, the pressure fixed by a zero mean.
+    Returns the fluxes on the face dofs ``dofs`` (global orientation; they sum
+    to the unit net flux from i to j).
     """
     perm = np.asarray(perm, dtype=np.float64).reshape(grid.ncells, grid.dim)
     ci, cj = subs.sub_cells[i], subs.sub_cells[j]
@@ -293,8 +311,8 @@ def multiscale_face_flux(grid, perm, subs, i, j, dofs):
     keep = loc[bc] >= 0
     B = sp.csr_matrix((bv[keep], (cloc[br[keep]], loc[bc[keep]])), shape=(len(cells), len(inner)))
     vol = np.full(len(cells), grid.cell_volume)
-    # cell-integrated source: +1 spread over Omega^i, -1 over Omega^j
-    f = np.concatenate([np.full(len(ci), 1.0 / len(ci)), np.full(len(cj), -1.0 / len(cj))])
+    # cell-integrated source: +w_i over Omega^i, -w_j over Omega^j
+    f = np.concatenate([multiscale_weight(source, ci), -multiscale_weight(source, cj)])
     K = sp.bmat([[A, B.T, None],
                  [B, None, sp.csr_matrix(vol[:, None])],
                  [None, sp.csr_matrix(vol[None, :]), None]], format="csc")
@@ -322,7 +340,7 @@ class BDDC:
     """Setup of Algorithm "BDDC method" for a given grid, field and partition."""
 
     def __init__(self, grid, perm, cuts, tau=math.inf, all_constrained=False, multiscale=False,
-                 scaling="multiplicity"):
+                 scaling="multiplicity", ms_source=None):
         self.grid = grid
         self.perm = np.asarray(perm, dtype=np.float64).reshape(grid.ncells, grid.dim)
         self.tau = tau
@@ -345,7 +363,7 @@ class BDDC:
             nF = len(subs.face_dofs[k])
             if multiscale:
                 # Section 6: the local Darcy problem in place of the eigenproblem (tau unused)
-                uF = multiscale_face_flux(grid, self.perm, subs, i, j, subs.face_dofs[k])
+                uF = multiscale_face_flux(grid, self.perm, subs, i, j, subs.face_dofs[k], ms_source)
                 rows, kk = multiscale_rows(uF, nF)
                 self.face_lam.append(np.zeros(0))
                 self.face_k.append(kk)

@@ -41,7 +41,7 @@ class Partition(C.Structure):
 
 class Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("max_it", C.c_int32), ("flags", C.c_uint32), ("coarse_leaf", C.c_int32),
-                ("coarse_top", C.c_int32), ("t_workgroups", C.c_int32)]
+                ("coarse_top", C.c_int32), ("t_workgroups", C.c_int32), ("ms_source", C.POINTER(C.c_double))]
 
 
 class Stats(C.Structure):
@@ -224,7 +224,9 @@ class Solver:
 
     def __init__(self, n, h, perm, cuts, tau=math.inf, precision="fp64", max_it=10000, all_constrained=False,
                  coarse_leaf=0, coarse_dataflow=False, coarse_top=0, t_workgroups=0, multiscale=False,
-                 scaling="multiplicity"):
+                 scaling="multiplicity", ms_source=None):
+        """ms_source: with multiscale=True, the cell-integrated well source that
+        shapes the multiscale sources of the subdomains holding a well."""
         self.lib = lib = load_library()
         self.n = tuple(int(v) for v in n)
         g, part, self._cuts = _grid_part(n, h, cuts)
@@ -232,6 +234,12 @@ class Solver:
                       (BDDC_ALL_CONSTRAINED if all_constrained else 0) | (BDDC_COARSE_DATAFLOW if coarse_dataflow else 0) |
                       (BDDC_MULTISCALE if multiscale else 0) | _scaling_flag(scaling),
                       int(coarse_leaf), int(coarse_top), int(t_workgroups))
+        ms = None
+        if ms_source is not None:
+            ms = np.ascontiguousarray(ms_source, dtype=np.float64).reshape(-1)
+            if ms.size != int(np.prod(self.n)):
+                raise ValueError("ms_source must hold one value per cell")
+            opt.ms_source = _dptr(ms)
         perm = np.ascontiguousarray(perm, dtype=np.float64).reshape(-1)
         t = _tau(tau)
         self.h = C.c_void_p()

@@ -101,6 +101,7 @@ struct bddc_problem {
   int t_grid = 0;                                 // workgroups of the T^i launch beside the coarse solve
   int n_cu = 0;                                   // compute units of the device
   double tau = 0.0;
+  const double *ms_src = nullptr;                 // caller's source for the multiscale rows (setup only)
   std::vector<void *> allocs;
   std::vector<double> alloc_bytes;
   std::vector<Allocator> alloc_by;
@@ -509,6 +510,16 @@ void do_setup(bddc_problem *h, const bddc_grid *gr, const double *perm, const bd
   HIPCHK(hipStreamSynchronize(s));
   check_err(h, "the subdomain setup");
 
+  {
+    int dev = 0, lds_max = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    if (symv_shm(L) > (size_t)lds_max)
+      throw Error{BDDC_EINVAL, "subdomain interface too large for the local operator kernels' LDS"};
+    // source term and post-correction: their vectors and the staged cell coefficients
+    if (std::max(source_shm(L), recover_shm(L)) > (size_t)lds_max)
+      throw Error{BDDC_EINVAL, "subdomain too large for the LDS of the source-term and post-correction kernels"};
+  }
   // face eigenproblems of Algorithm "Adaptive BDDC"
   const int nF = L.nF;
   h->face_k.assign(nF, 0);
@@ -537,7 +548,25 @@ void do_setup(bddc_problem *h, const bddc_grid *gr, const double *perm, const bd
     double *d_om = h->alloc<double>(nF);
     int64_t *d_foff = h->upload(foff), *d_eoff = h->upload(eoff), *d_roff = h->upload(roff);
     if (ms) {
-      k_face_ms<<<nF, 256, 0, s>>>(g, sw, d_fws, d_foff, d_eig, d_eoff, d_k, d_om, d_rows, d_roff, h->d_err);
+      // the load of the well-shaped sources w_s on the local Dirichlet
+      // problems, -H^{sT} X^s w_s (none without a source: every w_s uniform)
+      double *hs = nullptr, *d_ms = nullptr, *d_w = nullptr;
+      if (h->ms_src) {
+        std::vector<double> msv(h->ms_src, h->ms_src + L.ncells);
+        for (double v : msv)
+          if (!isfinite(v)) throw Error{BDDC_EINVAL, "multiscale source must be finite"};
+        d_ms = h->upload(msv);
+        d_w = h->alloc<double>(L.ncells);
+        hs = h->alloc<double>(std::max<int64_t>(L.g_off[N], 1));
+        k_ms_weight<<<N, 256, 0, s>>>(g, d_ms, d_w);
+        k_source_term<<<N, 256, source_shm(L), s>>>(g, h->mcoef, h->Xmat, h->d_Xoff, d_w, hs);
+        HIPCHK(hipGetLastError());
+      }
+      k_face_ms<<<nF, 256, 0, s>>>(g, sw, hs, d_fws, d_foff, d_eig, d_eoff, d_k, d_om, d_rows, d_roff, h->d_err);
+      if (hs) {
+        HIPCHK(hipStreamSynchronize(s));
+        for (double *q : {hs, d_ms, d_w}) h->release(q);
+      }
     } else {
       k_face_reduce<<<nF, 256, 0, s>>>(g, sw, d_fws, d_foff, allc ? 1 : 0, d_eig, d_eoff, d_k, d_om, d_rows,
                                        d_roff, h->d_err);
@@ -607,16 +636,6 @@ void do_setup(bddc_problem *h, const bddc_grid *gr, const double *perm, const bd
   cs.co_plus = h->upload(co_plus);
   cs.pidx = h->upload(pidx);
 
-  {
-    int dev = 0, lds_max = 0;
-    HIPCHK(hipGetDevice(&dev));
-    HIPCHK(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-    if (symv_shm(L) > (size_t)lds_max)
-      throw Error{BDDC_EINVAL, "subdomain interface too large for the local operator kernels' LDS"};
-    // source term and post-correction: their vectors and the staged cell coefficients
-    if (std::max(source_shm(L), recover_shm(L)) > (size_t)lds_max)
-      throw Error{BDDC_EINVAL, "subdomain too large for the LDS of the source-term and post-correction kernels"};
-  }
   // local coarse spaces Psi^i, coarse matrices and substructure operators T^i
   std::vector<int64_t> cwoff(N), acoff(N), psioff(N);
   int64_t cws = 0, acs = 0, pss = 0;
@@ -1223,6 +1242,7 @@ void apply_options(bddc_problem *h, const bddc_options *opt) {
     h->coarse_leaf = opt->coarse_leaf;
     h->coarse_top = opt->coarse_top;
     h->t_grid = opt->t_workgroups;
+    h->ms_src = opt->ms_source;
     h->coarse_dataflow = (opt->flags & BDDC_COARSE_DATAFLOW) != 0;
   }
   if (h->coarse_top > TOP_MAX_DOFS) throw Error{BDDC_EINVAL, "coarse_top above 8192"};

@@ -401,14 +401,20 @@ __global__ __launch_bounds__(256, 2) void k_face_reduce(DevGeom g, SetupWs ws, d
 }
 
 // Multiscale constraint of a face (Section 6, in place of the eigenproblem):
-// the face fluxes of the Darcy problem on the two neighbours with a uniform
-// unit source in Omega^i, the matching sink in Omega^j and no flow through
-// their other faces.  With those fluxes zero the problem reduces to the face:
-// the flux minimises u^T (S^i_FF + S^j_FF) u at unit net flux, so it is
-// proportional to y = (S^i_FF + S^j_FF)^{-1} 1 (the uniform sources lie in
-// the constants the local pressure operators leave out).  The row is y
-// projected off the zero-net-flux row and normalised; a uniform y adds none.
-__global__ __launch_bounds__(256, 2) void k_face_ms(DevGeom g, SetupWs ws, double *fbase, const int64_t *foff,
+// the face fluxes of the Darcy problem on the two neighbours with source w_i
+// in Omega^i, the matching sink -w_j in Omega^j and no flow through their
+// other faces; w_s is uniform, or f / int f in a subdomain holding a well.
+// With those other fluxes zero the problem reduces to the face: the flux u
+// minimises 1/2 u^T (S^i_FF + S^j_FF) u + u^T g at unit net flux, g the face
+// load that the non-uniform part of the sources puts on the two local
+// Dirichlet problems (the uniform part lies in the constants the local
+// pressure operators leave out).  hs holds -H^{sT} X^s w_s per local interface
+// dof (null: no wells), so g = hs^j_F - hs^i_F and u = mu y + z with
+// y = (S^i_FF + S^j_FF)^{-1} 1, z = (S^i_FF + S^j_FF)^{-1} (hs^i_F - hs^j_F),
+// mu fixing 1^T u = 1.  The row is u projected off the zero-net-flux row and
+// normalised; a uniform u adds none.
+__global__ __launch_bounds__(256, 2) void k_face_ms(DevGeom g, SetupWs ws, const double *__restrict__ hs,
+                                                 double *fbase, const int64_t *foff,
                                                  double *eig_out, const int64_t *eig_off, int *kout,
                                                  double *omega_out, double *rows_out, const int64_t *rows_off,
                                                  int *err) {
@@ -421,7 +427,7 @@ __global__ __launch_bounds__(256, 2) void k_face_ms(DevGeom g, SetupWs ws, doubl
   const int ni = g.nG[i], nj = g.nG[j];
   const int m = n - 1;
   double *w = fbase + foff[f];
-  double *XF = w, *y = w + n * n;
+  double *XF = w, *y = w + n * n, *z = y + n;   // y and z: two right-hand sides, leading dimension n
   double *eig = eig_out + eig_off[f];
   for (int a = tid; a < m; a += WG) eig[a] = 0.0;
   if (m == 0) {
@@ -433,33 +439,71 @@ __global__ __launch_bounds__(256, 2) void k_face_ms(DevGeom g, SetupWs ws, doubl
     const int a = e % n, b = e / n;
     XF[e] = Si[(oi + a) + (size_t)(oi + b) * ni] + Sj[(oj + a) + (size_t)(oj + b) * nj];
   }
-  for (int a = tid; a < n; a += WG) y[a] = 1.0;
+  const int64_t hi = g.g_off[i] + oi, hj = g.g_off[j] + oj;
+  for (int a = tid; a < n; a += WG) {
+    y[a] = 1.0;
+    z[a] = hs ? hs[hi + a] - hs[hj + a] : 0.0;
+  }
   __syncthreads();
   if (wg_potrf(n, XF, n, lds)) {
     if (tid == 0) atomicOr(err, 8);
   }
-  wg_trsm_lower(n, 1, XF, n, y, n, lds);
-  wg_trsm_lower_t(n, 1, XF, n, y, n, lds);
-  double sy = 0.0, syy = 0.0;
+  wg_trsm_lower(n, 2, XF, n, y, n, lds);
+  wg_trsm_lower_t(n, 2, XF, n, y, n, lds);
+  double sy = 0.0, sz = 0.0;
   for (int a = tid; a < n; a += WG) {
     sy += y[a];
-    syy += y[a] * y[a];
+    sz += z[a];
   }
   sy = wg_sum(sy, red);
-  syy = wg_sum(syy, red);
-  const double mean = sy / n;
+  sz = wg_sum(sz, red);
+  const double mu = (1.0 - sz) / sy;
+  double su = 0.0, suu = 0.0;
+  for (int a = tid; a < n; a += WG) {
+    const double u = fma(mu, y[a], z[a]);
+    su += u;
+    suu += u * u;
+  }
+  su = wg_sum(su, red);
+  suu = wg_sum(suu, red);
+  const double mean = su / n;
   double rr = 0.0;
-  for (int a = tid; a < n; a += WG) rr += (y[a] - mean) * (y[a] - mean);
+  for (int a = tid; a < n; a += WG) {
+    const double d = fma(mu, y[a], z[a]) - mean;
+    rr += d * d;
+  }
   const double nrm = sqrt(wg_sum(rr, red));
-  const int k = (nrm > 1e-12 * sqrt(syy)) ? 1 : 0;
+  const int k = (nrm > 1e-12 * sqrt(suu)) ? 1 : 0;
   if (k) {
     double *rows = rows_out + rows_off[f];
-    for (int a = tid; a < n; a += WG) rows[a] = (y[a] - mean) / nrm;
+    for (int a = tid; a < n; a += WG) rows[a] = (fma(mu, y[a], z[a]) - mean) / nrm;
   }
   if (tid == 0) {
     kout[f] = k;
     omega_out[f] = 0.0;
   }
+}
+
+// Source distribution w_s of the multiscale constraints (Section 6), cell
+// integrated: f / (the sum of f over Omega^s) in a subdomain holding a well
+// (a source not zero there), zero elsewhere, where w_s is uniform and its load
+// vanishes.  A subdomain whose wells cancel keeps the uniform w_s.
+__global__ __launch_bounds__(256) void k_ms_weight(DevGeom g, const double *__restrict__ src,
+                                                   double *__restrict__ wsrc) {
+  __shared__ double red[8];
+  const int i = blockIdx.x;
+  const int nc = g.nc[i];
+  const int *lcg = g.lcell_global + g.cell_off[i];
+  double s = 0.0, a = 0.0;
+  for (int c = threadIdx.x; c < nc; c += WG) {
+    const double v = src[lcg[c]];
+    s += v;
+    a += fabs(v);
+  }
+  s = wg_sum(s, red);
+  a = wg_sum(a, red);
+  const bool well = a > 0.0 && fabs(s) > 1e-12 * a;
+  for (int c = threadIdx.x; c < nc; c += WG) wsrc[lcg[c]] = well ? src[lcg[c]] / s : 0.0;
 }
 
 // Jacobi stage for the faces listed in `faces`.  IN_LDS: C and its eigenvector

@@ -1,9 +1,12 @@
 """Multiscale constraints (GPU): BDDC_MULTISCALE against the oracle's multiscale rows.
 
 The face rows come from the Darcy problem on the two neighbours of each face
-(Section 6); the oracle solves that problem literally, the GPU through the
-face's reduced form (S^i_FF + S^j_FF)^{-1} 1.  On the 16 x 16 square (two
-fields) and a 20 x 20 x 10 cutout of the reservoir field, both forms:
+(Section 6), with the sources shaped by the wells of the solved source in the
+subdomains that hold one (uniform elsewhere, and everywhere in the "uniform"
+case); the oracle solves that problem literally, the GPU through the face's
+reduced form (S^i_FF + S^j_FF)^{-1} (mu 1 - g), g the wells' face load.  On
+the 16 x 16 square (two fields, and one with an extra interior well pair) and
+a 20 x 20 x 10 cutout of the reservoir field (its injector column), both forms:
 * the same number of rows per face;
 * the preconditioner applied to a random interface vector (it depends on the
   span of the rows) within 1e-10 of the oracle's;
@@ -35,8 +38,13 @@ def _relerr(a, b):
 
 
 def _case(name):
+    if name == "square16_wells":
+        pr = W.unit_square_16(2)
+        src = pr.source.copy()
+        src[5 + 16 * 6], src[6 + 16 * 6], src[0] = 0.7, -0.2, src[0] - 0.5
+        return pr.n, pr.h, pr.perm, src, pr.cuts
     if name.startswith("square16"):
-        pr = W.unit_square_16(int(name[-1]))
+        pr = W.unit_square_16(int(name.split("_")[1]))
         return pr.n, pr.h, pr.perm, pr.source, pr.cuts
     full = W.reservoir_3d(nz=85, seed=0, tau=10.0)
     lo, ext = (20, 100, 30), (20, 20, 10)
@@ -47,14 +55,15 @@ def _case(name):
     return ext, full.h, full.perm[idx], src, W.regular_cuts(ext, (10, 10, 5))
 
 
-@pytest.mark.parametrize("name", ["square16_0", "square16_3", "cutout"])
+@pytest.mark.parametrize("name", ["square16_0", "square16_3", "square16_wells", "square16_0_uniform", "cutout"])
 def test_multiscale_matches_oracle(name):
     Solver = _gpu()
     n, h, perm, src, cuts = _case(name)
-    o = ob.BDDC(rt0.Grid(n, h), perm, cuts, multiscale=True)
+    ms = None if name.endswith("uniform") else src
+    o = ob.BDDC(rt0.Grid(n, h), perm, cuts, multiscale=True, ms_source=ms)
     ref = o.solve(src, rtol=1e-10)
     for prec, tol, dit in (("fp64", 1e-8, 0), ("mixed", 1e-6, 1)):
-        s = Solver(n, h, perm, cuts, precision=prec, multiscale=True)
+        s = Solver(n, h, perm, cuts, precision=prec, multiscale=True, ms_source=ms)
         try:
             st0 = s.stats()
             assert st0["n_adaptive"] == sum(o.face_k)

@@ -63,6 +63,29 @@ def test_bddc_matches_direct_solve(pr):
     assert lmin >= 1 - 1e-8
 
 
+@pytest.mark.parametrize("pr", list(_gf_cases()), ids=lambda p: p.name)
+def test_step1_solution_is_stokes_harmonic(pr):
+    """u_0 = E Psi alpha_0 continued into the interiors lies in W-hat (Section 3):
+    in every subdomain its divergence is constant, the interior flux rows of
+    the saddle point hold for some local pressure, and the subdomain's net
+    flux carries its whole source (the coarse solve of step 1)."""
+    g, b = _setup(pr)
+    out = b.solve(pr.source, rtol=pr.rtol)
+    u0 = out["u0"]
+    A, B = rt0.global_matrices(g, pr.perm)
+    F = -pr.source
+    Au, Bu = A @ u0, B @ u0
+    scale = np.abs(Au).max()
+    for i, lp in enumerate(b.loc):
+        bu = Bu[lp.cells]
+        assert np.ptp(bu) <= 1e-12 * max(np.abs(Bu).max(), 1e-300)
+        assert abs(bu.sum() - F[lp.cells].sum()) <= 1e-12 * np.abs(F).sum()
+        # interior rows A_I u_0 + B_I^T p = 0: least-squares pressure, zero residual
+        BIt = B[lp.cells][:, lp.I].T.toarray()
+        p, *_ = np.linalg.lstsq(BIt, -Au[lp.I], rcond=None)
+        assert np.linalg.norm(Au[lp.I] + BIt @ p) <= 1e-12 * scale * math.sqrt(len(lp.I))
+
+
 def test_all_interface_constraints_converge_in_one_iteration():
     pr = W.unit_square_16(1)
     g, b = _setup(pr, all_constrained=True)

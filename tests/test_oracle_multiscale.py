@@ -102,3 +102,115 @@ def test_multiscale_bddc_solves(seed):
     assert np.linalg.norm(out["u"] - ue) <= 1e-9 * np.linalg.norm(ue)
     lmin, _, _ = ob.lanczos_kappa(out["alphas"], out["betas"])
     assert lmin >= 1 - 1e-8
+
+
+# ---- the well-shaped source w_i = f / int f (Section 6, MsMFEM paragraph) ------
+
+def _face_load(o, s, f_s, pos):
+    """Face rows of the interface load that the source f_s (cell integrated, on
+    Omega^s) puts on the Dirichlet problem of subdomain s with zero interface
+    flux: the un-reduced local saddle point, scaled pressure rows D B u = -D f."""
+    lp = o.loc[s]
+    uI, p = lp.dirichlet(np.zeros(lp.nG), hP=-lp.d * f_s)
+    return (lp.AGI @ uI[:, 0] + lp.BG.T @ p[:, 0])[pos]
+
+
+def _reduced_with_source(o, k, source):
+    """Unit-net-flux minimiser of 1/2 u^T (S^i_FF + S^j_FF) u + u^T (g^i + g^j):
+    the union problem eliminated onto the face, g^s the face load of w_s."""
+    i, j = o.subs.face_pairs[k]
+    pi, pj = o.face_pos[k]
+    K = o.S[i][np.ix_(pi, pi)] + o.S[j][np.ix_(pj, pj)]
+    wi = ob.multiscale_weight(source, o.subs.sub_cells[i])
+    wj = ob.multiscale_weight(source, o.subs.sub_cells[j])
+    g = _face_load(o, i, wi, pi) + _face_load(o, j, -wj, pj)
+    y = np.linalg.solve(K, np.ones(len(pi)))
+    z = np.linalg.solve(K, g)
+    mu = (1.0 + z.sum()) / y.sum()
+    return mu * y - z
+
+
+def _well_square(seed):
+    pr = W.unit_square_16(seed)
+    src = pr.source.copy()
+    src[5 + 16 * 6] = 0.7          # an extra injector inside an interior subdomain, sink beside it
+    src[6 + 16 * 6] = -0.2
+    src[0] -= 0.5
+    return pr, src
+
+
+@pytest.mark.parametrize("seed", [0, 3])
+def test_well_face_flux_conserves_and_matches_reduced_form(seed):
+    pr, src = _well_square(seed)
+    g = rt0.Grid(pr.n, pr.h)
+    o = ob.BDDC(g, pr.perm, pr.cuts, tau=math.inf)
+    wells = {i for i in range(o.subs.N) if np.any(src[o.subs.sub_cells[i]] != 0.0)}
+    assert len(wells) == 3
+    checked = 0
+    for k in range(o.subs.n_faces):
+        i, j = o.subs.face_pairs[k]
+        if not ({i, j} & wells):
+            continue
+        uF = ob.multiscale_face_flux(g, pr.perm, o.subs, i, j, o.subs.face_dofs[k], src)
+        assert abs(uF.sum() - 1.0) <= 1e-12
+        assert np.linalg.norm(uF - _reduced_with_source(o, k, src)) <= 1e-11 * np.linalg.norm(uF)
+        # the well shapes the flux: it differs from the uniform w's
+        u0 = ob.multiscale_face_flux(g, pr.perm, o.subs, i, j, o.subs.face_dofs[k])
+        assert np.linalg.norm(uF - u0) > 1e-6 * np.linalg.norm(u0)
+        checked += 1
+    assert checked >= 6
+
+
+def test_faces_without_wells_keep_the_uniform_weight_bit_for_bit():
+    pr, src = _well_square(0)
+    g = rt0.Grid(pr.n, pr.h)
+    subs = ob.Substructuring(g, pr.cuts)
+    wells = {i for i in range(subs.N) if np.any(src[subs.sub_cells[i]] != 0.0)}
+    n = 0
+    for k, (i, j) in enumerate(subs.face_pairs):
+        if {i, j} & wells:
+            continue
+        a = ob.multiscale_face_flux(g, pr.perm, subs, i, j, subs.face_dofs[k], src)
+        b = ob.multiscale_face_flux(g, pr.perm, subs, i, j, subs.face_dofs[k])
+        assert np.array_equal(a, b)
+        n += 1
+    assert n > 10
+
+
+def test_uniformly_spread_well_is_the_uniform_weight():
+    """A well spread evenly over its subdomain gives w = 1/|Omega^i| again, for an
+    injector and a producer alike (w = f / int f is positive and sums to 1)."""
+    pr = W.unit_square_16(1)
+    g = rt0.Grid(pr.n, pr.h)
+    subs = ob.Substructuring(g, pr.cuts)
+    i = 5                                   # an interior 4 x 4 subdomain
+    for rate in (3.7, -0.4):
+        src = np.zeros(g.ncells)
+        src[subs.sub_cells[i]] = rate / 16
+        src[subs.sub_cells[15][0]] = -rate  # compensating well far away
+        w = ob.multiscale_weight(src, subs.sub_cells[i])
+        assert np.allclose(w, 1.0 / 16, rtol=0, atol=1e-16) and abs(w.sum() - 1.0) <= 1e-15
+        for k, pair in enumerate(subs.face_pairs):
+            if i not in pair:
+                continue
+            a = ob.multiscale_face_flux(g, pr.perm, subs, *pair, subs.face_dofs[k], src)
+            b = ob.multiscale_face_flux(g, pr.perm, subs, *pair, subs.face_dofs[k])
+            assert np.linalg.norm(a - b) <= 1e-13 * np.linalg.norm(b)
+
+
+def test_cancelling_wells_keep_the_uniform_weight():
+    cells = np.arange(4)
+    src = np.array([1.0, -1.0, 0.0, 0.0])
+    assert np.array_equal(ob.multiscale_weight(src, cells), np.full(4, 0.25))
+    assert np.array_equal(ob.multiscale_weight(None, cells), np.full(4, 0.25))
+
+
+def test_well_multiscale_bddc_solves():
+    pr, src = _well_square(3)
+    g = rt0.Grid(pr.n, pr.h)
+    ue, _ = rt0.direct_solve(g, pr.perm, src)
+    o = ob.BDDC(g, pr.perm, pr.cuts, multiscale=True, ms_source=src)
+    out = o.solve(src, rtol=1e-12)
+    assert np.linalg.norm(out["u"] - ue) <= 1e-9 * np.linalg.norm(ue)
+    lmin, _, _ = ob.lanczos_kappa(out["alphas"], out["betas"])
+    assert lmin >= 1 - 1e-8
