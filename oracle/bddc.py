@@ -431,26 +431,41 @@ class BDDC:
             self.sub_cdofs.append(np.array(gidx, dtype=np.int64))
 
         # coarse saddle point [A_c B_c^T 0; B_c 0 g; 0 g^T 0] (gauge g: zero mean of D p0)
+        # (sparse storage: A_c = sum of the local blocks, an entry shared by two
+        # subdomains is the sum of their two values; exact zeros are dropped)
         N, ncu = subs.N, self.n_cu
-        Ac = np.zeros((ncu, ncu))
-        Bc = np.zeros((N, ncu))
+        ar, ac, av, br, bcol, bv = [], [], [], [], [], []
         for i, lp in enumerate(self.loc):
             idx = self.sub_cdofs[i]
-            Ac[np.ix_(idx, idx)] += lp.Ac
-            Bc[i, idx] += lp.Bc
+            rr, cc = np.meshgrid(idx, idx, indexing="ij")
+            ar.append(rr.ravel())
+            ac.append(cc.ravel())
+            av.append(np.asarray(lp.Ac).ravel())
+            br.append(np.full(len(idx), i))
+            bcol.append(idx)
+            bv.append(lp.Bc)
+        cat = lambda v, dt=np.float64: np.concatenate(v).astype(dt) if v else np.zeros(0, dt)
+        Ac = sp.csr_matrix((cat(av), (cat(ar, np.int64), cat(ac, np.int64))), shape=(ncu, ncu))
+        Bc = sp.csr_matrix((cat(bv), (cat(br, np.int64), cat(bcol, np.int64))), shape=(N, ncu))
+        Ac.sum_duplicates()
+        Bc.sum_duplicates()
+        Ac.eliminate_zeros()
+        Bc.eliminate_zeros()
         self.Ac, self.Bc = Ac, Bc
         gvec = np.array([len(lp.cells) * grid.cell_volume * lp.d for lp in self.loc])
         self.gauge = gvec
-        K = sp.bmat([[sp.csr_matrix(Ac), sp.csr_matrix(Bc.T), None],
-                     [sp.csr_matrix(Bc), None, sp.csr_matrix(gvec[:, None])],
+        K = sp.bmat([[Ac, sp.csr_matrix(Bc.T), None],
+                     [Bc, None, sp.csr_matrix(gvec[:, None])],
                      [None, sp.csr_matrix(gvec[None, :]), None]], format="csc")
         self.Kc = spla.splu(K)
 
-        # B_0: interface flux -> scaled net divergence per subdomain
-        B0 = np.zeros((N, subs.n_gamma))
+        # B_0: interface flux -> scaled net divergence per subdomain (sparse)
+        rows, cols, vals = [], [], []
         for i, lp in enumerate(self.loc):
-            B0[i, subs.gamma_pos[lp.G]] = np.ones(lp.nc) @ lp.BG
-        self.B0 = B0
+            rows.append(np.full(lp.nG, i))
+            cols.append(subs.gamma_pos[lp.G])
+            vals.append(np.asarray(np.ones(lp.nc) @ lp.BG).ravel())
+        self.B0 = sp.csr_matrix((cat(vals), (cat(rows, np.int64), cat(cols, np.int64))), shape=(N, subs.n_gamma))
 
     # -- pieces --------------------------------------------------------------
     def coarse_solve(self, gu, hp):
