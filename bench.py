@@ -60,7 +60,7 @@ def time_gpu(pr, precision, steps, warmup, kernel_reps=0):
     from paper_1901_02090_amd import Solver
     from paper_1901_02090_amd.bddc import K_SCHUR_APPLY, K_PRECOND_APPLY, K_PRECOND_FULL
     t0 = time.perf_counter()
-    s = Solver(pr.n, pr.h, pr.perm, pr.cuts, tau=pr.tau, precision=precision, max_it=5000)
+    s = Solver(pr.n, pr.h, pr.perm, pr.cuts, tau=pr.tau, precision=precision, max_it=5000, autotune=True)
     setup_s = time.perf_counter() - t0
     try:
         stream = torch.cuda.current_stream()
@@ -160,27 +160,29 @@ def _cutout(pr, lo, ext):
     return W.Problem("cutout", tuple(ext), pr.h, pr.perm[idx], src, cuts, tau=pr.tau, rtol=pr.rtol)
 
 
-def cpu_baseline(pr, seconds, gpu_iters):
-    """The oracle (plain CPU FP64 BDDC) timed on the host, setup excluded.
+def host_info():
+    """CPU model, logical CPUs this process may use, and RAM of the host."""
+    model, ram = None, None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+        for line in open("/proc/meminfo"):
+            if line.startswith("MemTotal"):
+                ram = round(int(line.split()[1]) / 1024 ** 2, 1)
+                break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": len(os.sched_getaffinity(0)), "ram_gib": ram}
 
-    For the 2D layer the sample is the workload itself.  The reservoir's oracle
-    setup (2,244 local saddle-point factorizations, 6,124 dense pair
-    eigenproblems) does not fit a bench run, so the sample is a 20x20x10 cutout
-    of the same field around the injector column (8 subdomains of the same
-    10x10x5 shape), scaled by the subdomain count and the iteration ratio (the
-    oracle's solve cost is linear in both).
-    """
-    try:
-        from threadpoolctl import threadpool_limits
-    except Exception:  # pragma: no cover
-        threadpool_limits = None
+
+def _oracle_rate(sample, seconds, threads):
+    """Complete oracle solves of `sample` (setup excluded) for about `seconds` with
+    `threads` BLAS threads: (seconds per solve, solves, elapsed, last result)."""
+    from threadpoolctl import threadpool_limits
     from oracle import bddc as ob, rt0
-    ctx = threadpool_limits(1) if threadpool_limits else None
-    try:
-        scale, what = 1.0, "the same workload"
-        sample = pr
-        if len(pr.n) == 3:
-            sample = _cutout(pr, (20, 100, 30), (20, 20, 10))
+    with threadpool_limits(threads):
         g = rt0.Grid(sample.n, sample.h)
         o = ob.BDDC(g, sample.perm, sample.cuts, tau=sample.tau)
         n = 0
@@ -191,17 +193,41 @@ def cpu_baseline(pr, seconds, gpu_iters):
             el = time.perf_counter() - t0
             if el >= seconds or n >= 1000:
                 break
+    return el / n, n, el, out, o
+
+
+def cpu_baseline(pr, seconds, gpu_iters):
+    """The oracle (plain CPU FP64 BDDC) timed on the host, setup excluded, with
+    all the host's threads and with one.
+
+    For the 2D layer the sample is the workload itself.  The reservoir's oracle
+    setup (2,244 local saddle-point factorizations, 6,124 dense pair
+    eigenproblems) does not fit a bench run, so the sample is a 20x20x10 cutout
+    of the same field around the injector column (8 subdomains of the same
+    10x10x5 shape), scaled by the subdomain count and the iteration ratio (the
+    oracle's solve cost is linear in both).
+    """
+    host = host_info()
+    # the threads this process may use (the box's CPU share sets OMP_NUM_THREADS)
+    nthr = int(os.environ.get("OMP_NUM_THREADS") or 0) or host["nproc"]
+    sample = pr if len(pr.n) != 3 else _cutout(pr, (20, 100, 30), (20, 20, 10))
+    runs = {}
+    for thr in (nthr, 1):
+        t_solve, n, el, out, o = _oracle_rate(sample, seconds / 2, thr)
+        scale, what = 1.0, "the same workload"
         if sample is not pr:
             N_full = int(np.prod([len(c) - 1 for c in pr.cuts]))
             scale = (N_full / o.subs.N) * (gpu_iters / max(out["it"], 1))
             what = (f"a 20x20x10 cutout of the same field (x 20-40, y 100-120, z 30-40; {o.subs.N} subdomains, "
                     f"{out['it']} iterations), scaled x{scale:.1f} to {N_full} subdomains and {gpu_iters} iterations")
-    finally:
-        if ctx is not None:
-            ctx.__exit__(None, None, None)
-    t_solve = el / n * scale
-    return {"value": 1.0 / t_solve, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n} complete oracle solves (setup excluded, {el:.1f} s, one BLAS thread) of {what}"}
+        runs[thr] = (1.0 / (t_solve * scale), n, el, what)
+    v, n, el, what = runs[nthr]
+    v1, n1, el1, _ = runs[1]
+    return {"value": v, "unit": "solves/s", "cores": nthr, "kind": "oracle",
+            "sample": f"{n} complete oracle solves (setup excluded, {el:.1f} s, {nthr} BLAS threads) of {what}",
+            "one_thread": {"value": v1, "unit": "solves/s", "cores": 1,
+                           "sample": f"{n1} solves in {el1:.1f} s with one BLAS thread"},
+            "host": host}
 
 
 COPY_BYTES = 1 << 30
@@ -330,9 +356,9 @@ def main():
     ap.add_argument("--workload", default="reservoir", choices=["reservoir", "layer", "square"])
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=0,
+    ap.add_argument("--serve-requests", type=int, default=48,
                     help="requests of a served Poisson stream (mean 50/s) through bddc_server_* in both forms "
-                         "(default 0: not run)")
+                         "(0: not run)")
     ap.add_argument("--kernels-only", action="store_true",
                     help="set up the mixed form, solve once, launch the S^i and T^i apply kernels alone, the "
                          "whole preconditioner, and a plain device copy of known size (for scaling hardware "
@@ -409,6 +435,11 @@ def main():
         "setup_ms": rmx["setup_s"] * 1e3,
         "host_buffers_ms_per_step": rmx["host_ms"],
         "pcg_ms": st["t_pcg_ms"],
+        "autotune": {"sweep_widths": [st["sweep_wide4"], st["sweep_wide16"]], "t_workgroups": st["t_workgroups"],
+                     "tune_ms": st["t_tune_ms"], "coarse_ms_per_width": st["tune_coarse_ms"],
+                     "precond_ms_per_t_grid": st["tune_precond_ms"],
+                     "note": "coarse sweeps timed with lane-group widths (8,32) (12,48) (24,96) (48,192); "
+                             "preconditioner with T^i on n_cu, 2 n_cu, 4 n_cu, N workgroups"},
         "fp64": {"value": args.steps / r64["total_s"], "unit": "solves/s",
                  "ms_per_step": r64["total_s"] / args.steps * 1e3,
                  "latency_ms": {"p50": float(np.percentile(r64["lat"] * 1e3, 50)),
@@ -424,7 +455,17 @@ def main():
         "precond_apply": prec,
     }
     if args.serve_requests > 0:
-        out["serving"] = serving(args.serve_requests)
+        # The server's handles take device memory with the library's own
+        # hipMalloc: its setup workers and driver are native threads, and the
+        # one run whose handles allocated through torch's caching allocator
+        # (ctypes callbacks into Python from those threads) ended in a host
+        # segmentation fault whose cause is not known.
+        if args.alloc == "torch":
+            import torch
+            from paper_1901_02090_amd import set_allocator
+            set_allocator()
+            torch.cuda.empty_cache()
+        out["serving"] = dict(serving(args.serve_requests), allocator="hipMalloc")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pr, args.cpu_seconds, st["it"])
     print(json.dumps(out), flush=True)

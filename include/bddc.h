@@ -17,10 +17,11 @@
  *     along +x/+y/+z.  Faces are numbered direction by direction (all x-faces,
  *     then y-faces, then z-faces); inside direction d the face with integer
  *     position (i0,i1,i2), i_d in [0, n_d], has index i0 + s0*(i1 + s1*i2)
- *     with s_e = n_e + (e == d).  Boundary faces are included and carry zero
- *     flux (no-flow boundary, Section 2);
+ *     with s_e = n_e + (e == d).  Boundary faces are included; they carry
+ *     zero flux (no-flow boundary, Section 2) unless bddc_options.bflux
+ *     prescribes their fluxes (eq. problem-4);
  *   - the source is cell integrated (injection > 0) and must sum to zero
- *     (eq. compatibility with g_E = 0).
+ *     (eq. compatibility with g_E = 0), or to the net boundary outflow.
  *
  * Ownership: input arrays are read during the call only.  The handle owns all
  * device memory it allocates; it is released by bddc_destroy.  A handle is not
@@ -55,9 +56,6 @@ extern "C" {
 
 /* bddc_options.flags */
 #define BDDC_ALL_CONSTRAINED 1u  /* diagnostic: every interface dof is a coarse dof */
-#define BDDC_COARSE_DATAFLOW 2u  /* coarse sweeps as one dataflow launch instead of
-                                    one launch per level (same results; slower on
-                                    the 60x220x85 reservoir)                     */
 #define BDDC_MULTISCALE 4u       /* multiscale constraints (Section 6) in place of
                                     the face eigenproblems, tau unused: each face
                                     gets one row, its fluxes in the Darcy problem
@@ -66,6 +64,13 @@ extern "C" {
                                     bddc_options.ms_source) and no flow on their
                                     other faces, projected off the zero-net-flux
                                     row (none when that flux is uniform)         */
+#define BDDC_AUTOTUNE 16u        /* at the end of bddc_setup, time candidate launch
+                                    shapes of the per-iteration kernels on the
+                                    problem's own operators and keep the fastest:
+                                    the lane-group widths of the coarse sweeps
+                                    (coarse solve timed) and the workgroups of
+                                    the T^i corrections beside it (whole
+                                    preconditioner timed); see bddc_stats_t    */
 #define BDDC_STIFFNESS_SCALING 8u /* averaging weights a_i / (a_i + a_j) per face,
                                     a_s the mean diagonal of A^s over the face
                                     (rho-scaling for RT0; the paper's choice when
@@ -105,8 +110,7 @@ typedef struct {
   int32_t coarse_top;    /* the top levels of the coarse tree holding at most
                             this many coarse dofs are solved with the explicit
                             inverse of their Schur complement, formed at setup
-                            (0: 4096; < 0: none; at most 8192; ignored with
-                            BDDC_COARSE_DATAFLOW)                          */
+                            (0: 4096; < 0: none; at most 8192)             */
   int32_t t_workgroups;  /* workgroups of the substructure corrections T^i,
                             which run beside the coarse solve; fewer leave
                             more memory bandwidth to its latency-bound
@@ -118,6 +122,14 @@ typedef struct {
                             the others 1/|Omega^i| (as does a subdomain whose
                             wells cancel); NULL: uniform everywhere.  Read
                             during bddc_setup only                         */
+  const double *bflux;    /* host array [n_faces_all] (global face numbering and
+                            orientation): the prescribed normal fluxes of the
+                            boundary faces (eq. problem-4; interior entries
+                            are ignored); NULL: no flow.  Every solve on the
+                            handle uses them; its source must then sum to
+                            the net outflow through the boundary instead of
+                            zero, and the boundary entries of the flux
+                            output carry them.  Read during bddc_setup only */
 } bddc_options;
 
 typedef struct {
@@ -143,6 +155,15 @@ typedef struct {
   double bytes_per_iter;    /* algorithmic HBM bytes of one CG iteration         */
   double bytes_prec;        /* ... of which the BDDC preconditioner              */
   double device_bytes;      /* device memory held by the handle                  */
+  int32_t sweep_wide4;      /* coarse sweeps: rows / columns up to this long take
+                               4 lanes, up to sweep_wide16 16, longer 64       */
+  int32_t sweep_wide16;
+  int32_t t_workgroups;     /* workgroups of the T^i launch                      */
+  double t_tune_ms;         /* wall time of the autotuner (0: not run)           */
+  double tune_coarse_ms[4]; /* coarse solve with widths (8,32) (12,48) (24,96)
+                               (48,192)                                         */
+  double tune_precond_ms[4];/* preconditioner with T^i on n_cu, 2 n_cu, 4 n_cu, N
+                               workgroups (n_cu: compute units)                 */
 } bddc_stats_t;
 
 /*

@@ -13,9 +13,9 @@ BDDC_OK, BDDC_EINVAL, BDDC_ENOMEM, BDDC_ENOCONV, BDDC_EBREAKDOWN, BDDC_EFACTOR, 
     0, -1, -2, -3, -4, -5, -6, -7
 BDDC_FP64, BDDC_MIXED = 0, 1
 BDDC_ALL_CONSTRAINED = 1
-BDDC_COARSE_DATAFLOW = 2
 BDDC_MULTISCALE = 4
 BDDC_STIFFNESS_SCALING = 8
+BDDC_AUTOTUNE = 16
 BDDC_DEVICE_PTRS = 1
 BDDC_EAGER = 2
 BDDC_STEP1_ONLY = 4
@@ -41,7 +41,8 @@ class Partition(C.Structure):
 
 class Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("max_it", C.c_int32), ("flags", C.c_uint32), ("coarse_leaf", C.c_int32),
-                ("coarse_top", C.c_int32), ("t_workgroups", C.c_int32), ("ms_source", C.POINTER(C.c_double))]
+                ("coarse_top", C.c_int32), ("t_workgroups", C.c_int32), ("ms_source", C.POINTER(C.c_double)),
+                ("bflux", C.POINTER(C.c_double))]
 
 
 class Stats(C.Structure):
@@ -52,7 +53,9 @@ class Stats(C.Structure):
                 ("coarse_levels", C.c_int32), ("coarse_fronts", C.c_int32), ("coarse_dense", C.c_int32),
                 ("t_setup_ms", C.c_double), ("t_solve_ms", C.c_double),
                 ("t_pcg_ms", C.c_double), ("bytes_per_iter", C.c_double), ("bytes_prec", C.c_double),
-                ("device_bytes", C.c_double)]
+                ("device_bytes", C.c_double), ("sweep_wide4", C.c_int32), ("sweep_wide16", C.c_int32),
+                ("t_workgroups", C.c_int32), ("t_tune_ms", C.c_double), ("tune_coarse_ms", C.c_double * 4),
+                ("tune_precond_ms", C.c_double * 4)]
 
 
 class ServerOptions(C.Structure):
@@ -223,16 +226,19 @@ class Solver:
     """One problem resident on the GPU: setup once, solve many right-hand sides."""
 
     def __init__(self, n, h, perm, cuts, tau=math.inf, precision="fp64", max_it=10000, all_constrained=False,
-                 coarse_leaf=0, coarse_dataflow=False, coarse_top=0, t_workgroups=0, multiscale=False,
-                 scaling="multiplicity", ms_source=None):
+                 coarse_leaf=0, coarse_top=0, t_workgroups=0, multiscale=False,
+                 scaling="multiplicity", ms_source=None, autotune=False, bflux=None):
         """ms_source: with multiscale=True, the cell-integrated well source that
-        shapes the multiscale sources of the subdomains holding a well."""
+        shapes the multiscale sources of the subdomains holding a well.
+        bflux: [n_faces_all] prescribed normal fluxes of the boundary faces
+        (global face numbering; interior entries ignored), None: no flow."""
         self.lib = lib = load_library()
         self.n = tuple(int(v) for v in n)
         g, part, self._cuts = _grid_part(n, h, cuts)
         opt = Options(BDDC_MIXED if precision == "mixed" else BDDC_FP64, int(max_it),
-                      (BDDC_ALL_CONSTRAINED if all_constrained else 0) | (BDDC_COARSE_DATAFLOW if coarse_dataflow else 0) |
-                      (BDDC_MULTISCALE if multiscale else 0) | _scaling_flag(scaling),
+                      (BDDC_ALL_CONSTRAINED if all_constrained else 0) |
+                      (BDDC_MULTISCALE if multiscale else 0) | _scaling_flag(scaling) |
+                      (BDDC_AUTOTUNE if autotune else 0),
                       int(coarse_leaf), int(coarse_top), int(t_workgroups))
         ms = None
         if ms_source is not None:
@@ -240,6 +246,14 @@ class Solver:
             if ms.size != int(np.prod(self.n)):
                 raise ValueError("ms_source must hold one value per cell")
             opt.ms_source = _dptr(ms)
+        bf = None
+        if bflux is not None:
+            nn = list(self.n) + [1] * (3 - len(self.n))
+            nfa = sum(int(np.prod([nn[e] + (e == d) for e in range(3)])) for d in range(len(self.n)))
+            bf = np.ascontiguousarray(bflux, dtype=np.float64).reshape(-1)
+            if bf.size != nfa:
+                raise ValueError("bflux must hold one value per grid face")
+            opt.bflux = _dptr(bf)
         perm = np.ascontiguousarray(perm, dtype=np.float64).reshape(-1)
         t = _tau(tau)
         self.h = C.c_void_p()
@@ -292,7 +306,8 @@ class Solver:
     def stats(self):
         s = Stats()
         _check(self.lib, self.lib.bddc_stats(self.h, C.byref(s)))
-        return {k: getattr(s, k) for k, _ in Stats._fields_}
+        return {k: (list(getattr(s, k)) if isinstance(getattr(s, k), C.Array) else getattr(s, k))
+                for k, _ in Stats._fields_}
 
     # -- diagnostics -------------------------------------------------------------
     def _export(self, what, index, count, dtype):

@@ -82,6 +82,14 @@ void *g_scratch_ptr[MAX_DEVICES] = {};
   } while (0)
 
 inline unsigned nblk(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
+
+// Launch the instance of a line kernel whose private line arrays hold the
+// longest subdomain extent of the problem (SHORTLINE or MAXLINE cells).
+#define LINE_LAUNCH(longl, K, grid, block, shm, stream, ...)                   \
+  do {                                                                          \
+    if (longl) K<MAXLINE><<<(grid), (block), (shm), (stream)>>>(__VA_ARGS__);   \
+    else K<SHORTLINE><<<(grid), (block), (shm), (stream)>>>(__VA_ARGS__);       \
+  } while (0)
 // blocks of the kernels that leave dot-product partials: interface vectors
 // (256 entries per block and round) and faces (four per block and round)
 inline int vec_blocks(int64_t n) { return (int)std::min<int64_t>(nblk(n), PART_BLOCKS); }
@@ -102,6 +110,11 @@ struct bddc_problem {
   int n_cu = 0;                                   // compute units of the device
   double tau = 0.0;
   const double *ms_src = nullptr;                 // caller's source for the multiscale rows (setup only)
+  const double *bflux_in = nullptr;               // caller's boundary fluxes (setup only)
+  double *d_bflux = nullptr;                      // [n_faces_all] boundary fluxes, interior entries zero
+  double *d_hb = nullptr, *d_sb = nullptr;        // their cell load H_b g [n_cells], interface load [sum nG]
+  double *d_srcb = nullptr;                       // [n_cells] source plus H_b g (per solve)
+  double b_outflow = 0.0, b_abs = 0.0;            // net outflow through the boundary and sum |g|
   std::vector<void *> allocs;
   std::vector<double> alloc_bytes;
   std::vector<Allocator> alloc_by;
@@ -127,17 +140,17 @@ struct bddc_problem {
   std::vector<int> pidx_h;
   double *FR = nullptr, *BC = nullptr, *csgn = nullptr, *cy = nullptr, *cS0 = nullptr, *cS1 = nullptr,
          *cXB = nullptr;
-  int *ccnt = nullptr, *cabort = nullptr;         // dataflow counters and abort word
-  int flow_grid = 0, flow_cap = 0;                // resident grid, LDS staging capacity (doubles)
-  bool coarse_dataflow = false;                   // one dataflow launch instead of one per level
   double *Kt = nullptr, *ctt = nullptr;           // dense top block: S_t^{-1} (nt x top_ld), t_t
   int *tg_off = nullptr, *tg = nullptr;           // gather map of t_t
   int top_ld = 0;
+  bool longl = false;                             // a subdomain extent exceeds SHORTLINE cells
+  double tune_coarse_ms[4] = {0, 0, 0, 0};        // autotuner: coarse solve per sweep width candidate
+  double tune_precond_ms[4] = {0, 0, 0, 0};       // autotuner: preconditioner per T^i grid candidate
   double coarse_bytes = 0.0;
   int64_t *d_pk = nullptr, *d_psi_off = nullptr, *d_Xoff = nullptr, *d_gamma_face = nullptr;
 
   double *xu = nullptr, *ru = nullptr, *pu = nullptr, *zu = nullptr, *qu = nullptr, *u0 = nullptr, *uG = nullptr;
-  double *xp = nullptr, *pp = nullptr, *yloc = nullptr, *wloc = nullptr, *gloc = nullptr, *bc = nullptr,
+  double *xp = nullptr, *pp = nullptr, *yloc = nullptr, *wloc = nullptr, *bc = nullptr,
          *csol = nullptr;
   double *d_src = nullptr, *d_flux = nullptr, *d_pres = nullptr;
   double *d_zero_src = nullptr;                   // zero source of the step-1-only mode
@@ -259,7 +272,7 @@ void check_coarse_ptrs(const bddc_problem *h) {
   const DevSweep &w = h->sw;
   const void *p[] = {f.first, f.n, f.m, f.ch, f.b_off, f.bidx, f.ext, f.touch_off, f.touch, f.F_off, f.w_off,
                      f.q_off, f.r_off, f.v_off, w.wdst, w.xsc_off, w.xsc, w.task, h->FR, h->BC, h->csgn,
-                     h->cy, h->cS0, h->cS1, h->cXB, h->bc, h->csol, h->ccnt, h->cabort};
+                     h->cy, h->cS0, h->cS1, h->cXB, h->bc, h->csol};
   for (const void *q : p)
     if (!q) throw Error{BDDC_EDEVICE, "coarse solver arrays not initialised"};
   if (h->nd.nt > 0 && (!h->Kt || !h->ctt || !h->tg_off || !h->tg || h->top_ld < h->nd.nt))
@@ -279,7 +292,7 @@ constexpr int TOP_BATCH = 128;
 
 void setup_dense_top(bddc_problem *h, hipStream_t s) {
   NdPlan &P = h->nd;
-  const int cap = h->coarse_dataflow ? 0 : (h->coarse_top == 0 ? TOP_DEFAULT_DOFS : h->coarse_top);
+  const int cap = h->coarse_top == 0 ? TOP_DEFAULT_DOFS : h->coarse_top;
   nd_dense_top(P, cap);
   if (P.nt == 0) return;
   const int nt = P.nt, d0 = P.lvl_dof[P.top], nfr = P.nfr;
@@ -396,7 +409,8 @@ void do_setup(bddc_problem *h, const bddc_grid *gr, const double *perm, const bd
   }
   for (int i = 0; i < L.N; ++i)
     for (int d = 0; d < L.dim; ++d)
-      if (L.ext[d][i] > MAXLINE) throw Error{BDDC_EINVAL, "subdomain extent exceeds 32 cells"};
+      if (L.ext[d][i] > MAXLINE) throw Error{BDDC_EINVAL, "subdomain extent exceeds 128 cells"};
+      else if (L.ext[d][i] > SHORTLINE) h->longl = true;
   const int dim = L.dim;
   for (int64_t c = 0; c < L.ncells * dim; ++c)
     if (!(perm[c] > 0.0) || !isfinite(perm[c])) throw Error{BDDC_EINVAL, "permeability must be finite and > 0"};
@@ -503,7 +517,7 @@ void do_setup(bddc_problem *h, const bddc_grid *gr, const double *perm, const bd
   sw.pk = h->d_pk = h->upload(opk);
   sw.Spk = h->Spk = h->alloc<double>(pks);
   h->pk_h = opk;
-  k_local_setup<<<N, 256, 0, s>>>(g, h->mcoef, sw, h->dscale, h->d_err);
+  LINE_LAUNCH(h->longl, k_local_setup, N, 256, 0, s, g, h->mcoef, sw, h->dscale, h->d_err);
   HIPCHK(hipGetLastError());
   k_schur_factor<<<N, 256, 0, s>>>(g, sw, h->d_err);
   HIPCHK(hipGetLastError());
@@ -559,7 +573,7 @@ void do_setup(bddc_problem *h, const bddc_grid *gr, const double *perm, const bd
         d_w = h->alloc<double>(L.ncells);
         hs = h->alloc<double>(std::max<int64_t>(L.g_off[N], 1));
         k_ms_weight<<<N, 256, 0, s>>>(g, d_ms, d_w);
-        k_source_term<<<N, 256, source_shm(L), s>>>(g, h->mcoef, h->Xmat, h->d_Xoff, d_w, hs);
+        LINE_LAUNCH(h->longl, k_source_term, N, 256, source_shm(L), s, g, h->mcoef, h->Xmat, h->d_Xoff, d_w, hs);
         HIPCHK(hipGetLastError());
       }
       k_face_ms<<<nF, 256, 0, s>>>(g, sw, hs, d_fws, d_foff, d_eig, d_eoff, d_k, d_om, d_rows, d_roff, h->d_err);
@@ -623,6 +637,8 @@ void do_setup(bddc_problem *h, const bddc_grid *gr, const double *perm, const bd
   h->nk = nkc;
   h->sub_coff_h = sub_coff;
   h->pidx_h = pidx;
+  if ((int)h->pidx_h.size() != N || (int)h->sub_coff_h.size() != N + 1)
+    throw Error{BDDC_EDEVICE, "coarse bookkeeping of the subdomains incomplete"};
   DevCoarse &cs = h->cs;
   cs.ncu = ncu;
   cs.nk = h->nk;
@@ -666,6 +682,7 @@ void do_setup(bddc_problem *h, const bddc_grid *gr, const double *perm, const bd
   const int nk = h->nk;
   h->coarse_bytes = 0.0;
   h->bc = h->alloc<double>(nk + 1);
+  fill(h, h->bc, nk + 1, 0.0);   // the preconditioner adds into b; the coarse solve clears what it read
   h->csol = h->alloc<double>(nk + 1);
   if (nk > 0) {
     DevFronts &fd = h->fd;
@@ -701,25 +718,6 @@ void do_setup(bddc_problem *h, const bddc_grid *gr, const double *perm, const bd
     sv.xsc = h->upload(P.xsc);
     sv.task = (const int4 *)h->upload(P.task);
     sv.nfr = P.nfr;
-    h->ccnt = h->alloc<int>(2 * P.nfr + 1);
-    h->cabort = h->alloc<int>(1);
-    HIPCHK(hipMemsetAsync(h->ccnt, 0, (2 * (size_t)P.nfr + 1) * sizeof(int), s));
-    HIPCHK(hipMemsetAsync(h->cabort, 0, sizeof(int), s));
-    {
-      // resident grid of the dataflow sweep: at most two workgroups per CU, so
-      // it fits beside the substructure corrections running concurrently
-      int dev = 0, ncu = 0, per_cu = 0;
-      HIPCHK(hipGetDevice(&dev));
-      HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-      // LDS staging: the largest front input (n forward, n + m backward), capped at 48 KB
-      int need = 0;
-      for (int r = 0; r < P.nfr; ++r) need = std::max(need, P.n[r] + P.m[r]);
-      h->flow_cap = std::min(need, 6144);
-      HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_nd_flow, 256,
-                                                          (size_t)h->flow_cap * sizeof(double)));
-      if (ncu < 1 || per_cu < 1) throw Error{BDDC_EDEVICE, "no occupancy for the coarse sweep"};
-      h->flow_grid = std::max(1, std::min(P.ntask, ncu * std::min(per_cu, 2)));
-    }
     std::vector<double> sg(nk, 1.0);
     for (int i = 0; i < N; ++i)
       if (pidx[i] >= 0) sg[pidx[i]] = -1.0;
@@ -775,7 +773,6 @@ void do_setup(bddc_problem *h, const bddc_grid *gr, const double *perm, const bd
   h->pp = h->alloc<double>(N);
   h->yloc = h->alloc<double>(totG);
   h->wloc = h->alloc<double>(totG);
-  h->gloc = h->alloc<double>(sub_coff[N]);
   h->cgw.part_g = h->alloc<double>(nblk(nGm) + 1);
   h->cgw.part_r = h->alloc<double>(nblk(nGm) + 1);
   h->cgw.part_z = h->alloc<double>(nF + 1);
@@ -798,6 +795,33 @@ void do_setup(bddc_problem *h, const bddc_grid *gr, const double *perm, const bd
   HIPCHK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
   HIPCHK(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
   HIPCHK(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
+  if (h->bflux_in) {
+    // prescribed boundary fluxes (eq. problem-4): the boundary entries of the
+    // caller's array, their net outflow for the compatibility check, and
+    // their loads on the local problems
+    std::vector<double> bf(L.nfaces_all, 0.0);
+    for (int d = 0; d < dim; ++d) {
+      const int *fs = L.fshape[d];
+      for (int k = 0; k < fs[0] * fs[1] * fs[2]; ++k) {
+        int c[3] = {k % fs[0], (k / fs[0]) % fs[1], k / (fs[0] * fs[1])};
+        if (c[d] != 0 && c[d] != L.n[d]) continue;
+        const int64_t fid = L.face_off[d] + k;
+        const double v = h->bflux_in[fid];
+        if (!isfinite(v)) throw Error{BDDC_EINVAL, "boundary fluxes must be finite"};
+        bf[fid] = v;
+        h->b_outflow += c[d] == 0 ? -v : v;
+        h->b_abs += fabs(v);
+      }
+    }
+    h->d_bflux = h->upload(bf);
+    g.bflux = h->d_bflux;
+    h->d_hb = h->alloc<double>(L.ncells);
+    h->d_sb = h->alloc<double>(std::max<int64_t>(totG, 1));
+    h->d_srcb = h->alloc<double>(L.ncells);
+    LINE_LAUNCH(h->longl, k_bflux_load, N, 256, (size_t)4 * L.maxC * sizeof(double), s, g, h->mcoef, h->d_hb,
+                h->d_sb);
+    HIPCHK(hipGetLastError());
+  }
   HIPCHK(hipStreamSynchronize(s));
 
   // statistics of the operators streamed per iteration
@@ -817,22 +841,12 @@ void do_setup(bddc_problem *h, const bddc_grid *gr, const double *perm, const bd
 // Coarse solve csol = K^{-1} bc by the multifrontal forward / backward sweeps:
 // the levels below the dense top block (all of them without one) sweep one
 // launch per level and direction; the top block is one gather and one dense
-// product with S_t^{-1}.
-// one launch per level and direction, or (BDDC_COARSE_DATAFLOW) one dataflow
-// launch.  Both run the same task bodies and give identical results.  On the
-// reservoir the level launches are faster: a dataflow level still costs about
-// four dependent memory round trips (wait, staging, matrix, store completion)
-// and its wide levels take several rounds of the resident grid.
+// product with S_t^{-1}.  bc is left zero (each entry is cleared once read),
+// ready for the next right-hand side to be added into it.
 void launch_coarse_solve(bddc_problem *h, hipStream_t s, const int *done) {
   const NdPlan &P = h->nd;
   if (h->nk == 0) return;
   check_coarse_ptrs(h);
-  if (h->coarse_dataflow) {
-    k_nd_flow<<<h->flow_grid, 256, (size_t)h->flow_cap * sizeof(double), s>>>(
-        P.ntask, h->sw, h->FR, h->BC, h->bc, h->cS0, h->cS1, h->cy, h->csgn, h->cXB, h->csol, h->ccnt, h->cabort,
-        h->flow_cap, done);
-    return;
-  }
   for (int lv = 0; lv < P.top; ++lv) {
     const int t0 = P.ftask_off[lv], nt = P.ftask_off[lv + 1] - t0;
     k_nd_fwd<<<nt, 256, 0, s>>>(t0, h->sw, h->FR, h->bc, h->cS0, h->cS1, h->cy, done);
@@ -841,23 +855,11 @@ void launch_coarse_solve(bddc_problem *h, hipStream_t s, const int *done) {
     const int d0 = P.lvl_dof[P.top];
     k_top_gather<<<nblk(P.nt), 256, 0, s>>>(P.nt, d0, h->tg_off, h->tg, h->bc, h->cS0, h->cS1, h->ctt, done);
     k_top_gemv<<<nblk(P.nt, TOP_ROWS_PER_WG), TOP_THREADS, (size_t)h->top_ld * sizeof(double), s>>>(
-        P.nt, h->top_ld, h->Kt, h->ctt, d0, h->sw.xsc_off, h->sw.xsc, h->cXB, h->csol, done);
+        P.nt, h->top_ld, h->Kt, h->ctt, d0, h->sw.xsc_off, h->sw.xsc, h->cXB, h->csol, h->bc, done);
   }
   for (int lv = P.top - 1; lv >= 0; --lv) {
     const int t0 = P.btask_lo[lv], nt = P.btask_hi[lv] - t0;
-    k_nd_bwd<<<nt, 256, 0, s>>>(t0, h->sw, h->BC, h->cy, h->csgn, h->cXB, h->csol, done);
-  }
-}
-
-// A dataflow sweep that timed out leaves the abort word set (and its results
-// invalid); report it and clear the word.
-void check_flow(bddc_problem *h) {
-  if (!h->cabort || !h->coarse_dataflow) return;
-  int ab = 0;
-  HIPCHK(hipMemcpy(&ab, h->cabort, sizeof(int), hipMemcpyDeviceToHost));
-  if (ab) {
-    HIPCHK(hipMemset(h->cabort, 0, sizeof(int)));
-    throw Error{BDDC_EDEVICE, "coarse dataflow sweep timed out"};
+    k_nd_bwd<<<nt, 256, 0, s>>>(t0, h->sw, h->BC, h->cy, h->csgn, h->cXB, h->csol, h->bc, done);
   }
 }
 
@@ -877,10 +879,11 @@ void launch_precond(bddc_problem *h, const double *r, double *z, double *zpart, 
   // the memory bandwidth they take from the latency-bound coarse sweeps) and
   // join before the averaging, which adds the two parts.
   if (mixed)
-    k_psi_apply<float><<<N, 256, shm, s>>>(h->g, h->Psi32, h->d_psi_off, h->cs.sub_coff, r, 0.5, h->lw, h->gloc, st, rp, nrp);
+    k_psi_apply<float><<<N, 256, shm, s>>>(h->g, h->Psi32, h->d_psi_off, h->cs.sub_coff, h->cs.sub_cmap, r, 0.5,
+                                           h->lw, h->bc, st, rp, nrp);
   else
-    k_psi_apply<double><<<N, 256, shm, s>>>(h->g, h->Psi64, h->d_psi_off, h->cs.sub_coff, r, 0.5, h->lw, h->gloc, st, rp,
-                                            nrp);
+    k_psi_apply<double><<<N, 256, shm, s>>>(h->g, h->Psi64, h->d_psi_off, h->cs.sub_coff, h->cs.sub_cmap, r, 0.5,
+                                            h->lw, h->bc, st, rp, nrp);
   HIPCHK(hipEventRecord(h->ev_fork, s));
   HIPCHK(hipStreamWaitEvent(h->side, h->ev_fork, 0));
   // By default the FP32 T^i gets one workgroup of SYMV_THREADS per CU (a
@@ -897,7 +900,6 @@ void launch_precond(bddc_problem *h, const double *r, double *z, double *zpart, 
   // subspace, so the face-average coarse fluxes must satisfy B_c alpha = 0 to
   // FP64 accuracy (the FP32 local operators are corrected by the balance step).
   if (h->nk > 0) {
-    k_coarse_rhs<<<nblk(h->nk), 256, 0, s>>>(h->cs, h->gloc, h->bc, st);
     launch_coarse_solve(h, s, st ? &st->done : nullptr);
   }
   if (mixed)
@@ -965,6 +967,77 @@ double lanczos_kappa(const std::vector<double> &a, const std::vector<double> &b,
 }
 
 constexpr int CG_CHUNK = 8;   // CG iterations between host convergence checks
+
+// Mean duration (ms) of `reps` back-to-back runs of fn on the handle's stream
+// (two warm-up runs first), from HIP events.
+template <typename F>
+double time_ms(bddc_problem *h, int reps, F &&fn) {
+  for (int k = 0; k < 2; ++k) fn();
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipEventRecord(h->ev0, h->stream));
+  for (int k = 0; k < reps; ++k) fn();
+  HIPCHK(hipEventRecord(h->ev1, h->stream));
+  HIPCHK(hipEventSynchronize(h->ev1));
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+  return ms / reps;
+}
+
+// Autotuner of the launch shapes of the per-iteration kernels (BDDC_AUTOTUNE),
+// run at the end of the setup on the problem's own operators:
+//  * the lane-group widths of the coarse sweeps (rows or columns up to wide4
+//    entries take 4 lanes, up to wide16 16, longer ones 64; a workgroup takes
+//    256 / g of them): fewer, fuller workgroups per level against more
+//    parallelism.  Each candidate task list is timed on the coarse solve;
+//  * the workgroups of the substructure corrections T^i, which run beside the
+//    coarse solve and share the memory bandwidth with it: timed on the whole
+//    preconditioner.
+// Both only change how the work is laid out on the device: a sweep row is
+// summed by a different number of lanes (rounding order only), and the T^i
+// grid changes which workgroup takes which subdomain (same bits).
+void autotune(bddc_problem *h) {
+  const auto t0 = std::chrono::steady_clock::now();
+  NdPlan &P = h->nd;
+  const Layout &L = h->L;
+  hipStream_t s = h->stream;
+  constexpr int REPS = 20;
+  if (h->nk > 0 && P.top > 0) {
+    fill(h, h->bc, h->nk, 1.0);
+    static const int cand[][2] = {{8, 32}, {12, 48}, {24, 96}, {48, 192}};
+    double best = 1e300;
+    int bi = 0;
+    for (int c = 0; c < 4; ++c) {
+      nd_tasks(P, cand[c][0], cand[c][1]);
+      h->release((void *)h->sw.task);
+      h->sw.task = (const int4 *)h->upload(P.task);
+      const double ms = time_ms(h, REPS, [&] { launch_coarse_solve(h, s, nullptr); });
+      h->tune_coarse_ms[c] = ms;
+      if (ms < best) { best = ms; bi = c; }
+    }
+    if (bi != 3) {   // the last candidate's tasks are in place
+      nd_tasks(P, cand[bi][0], cand[bi][1]);
+      h->release((void *)h->sw.task);
+      h->sw.task = (const int4 *)h->upload(P.task);
+    }
+    fill(h, h->bc, h->nk, 0.0);
+  }
+  if (L.N > 1 && L.nGamma > 0) {
+    fill(h, h->ru, L.nGamma, 1.0);
+    const int cand[] = {h->n_cu, 2 * h->n_cu, 4 * h->n_cu, L.N};
+    double best = 1e300;
+    int bg = L.N;
+    for (int c = 0; c < 4; ++c) {
+      const int tg = std::max(1, std::min(cand[c], L.N));
+      h->t_grid = tg;
+      const double ms = time_ms(h, REPS, [&] { launch_precond(h, h->ru, h->zu, nullptr, false); });
+      h->tune_precond_ms[c] = ms;
+      if (ms < best) { best = ms; bg = tg; }
+    }
+    h->t_grid = bg;
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  h->stats.t_tune_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
 
 // Capture CG_CHUNK iterations (main and side stream) into a graph.  The
 // capture runs on the handle's own stream; the graph is replayed on whatever
@@ -1050,7 +1123,9 @@ void solve_begin_launch(bddc_problem *h, const double *rhs, double rtol, double 
       sum += rhs[c];
       asum += fabs(rhs[c]);
     }
-    if (fabs(sum) > 1e-12 * asum) throw Error{BDDC_EINVAL, "source must sum to zero (no-flow compatibility)"};
+    if (fabs(sum - h->b_outflow) > 1e-12 * (asum + h->b_abs))
+      throw Error{BDDC_EINVAL, h->d_bflux ? "source must equal the net boundary outflow (compatibility)"
+                                          : "source must sum to zero (no-flow compatibility)"};
     HIPCHK(hipMemcpyAsync(h->d_src, rhs, L.ncells * sizeof(double), hipMemcpyHostToDevice, s));
     R.src = h->d_src;
   }
@@ -1061,6 +1136,11 @@ void solve_begin_launch(bddc_problem *h, const double *rhs, double rtol, double 
   if (N <= 1) return;
   const int nb = (int)nblk(nGm);
   const double *src = R.src;
+  if (h->d_bflux) {
+    // with boundary fluxes the local problems see the source plus H_b g
+    k_axpby<<<nblk(L.ncells), 256, 0, s>>>((int)L.ncells, 1.0, R.src, 1.0, h->d_hb, h->d_srcb);
+    src = h->d_srcb;
+  }
   // step 1: coarse solve with (0, D F_0), u0 = E Psi alpha
   fill(h, h->bc, h->nk, 0.0);
   k_step1_rhs<<<N, 256, 0, s>>>(h->g, h->cs.pidx, src, h->dscale, h->bc);
@@ -1077,9 +1157,9 @@ void solve_begin_launch(bddc_problem *h, const double *rhs, double rtol, double 
   }
   // steps 2-3 right-hand side: f* = -S u0 + H^T X F
   k_symv<double><<<N, SYMV_THREADS, symv_shm(L), s>>>(h->g, h->Spk, h->d_pk, h->u0, 1.0, nullptr, h->yloc, nullptr, nullptr, 0);
-  k_source_term<<<N, 256, source_shm(L), s>>>(h->g, h->mcoef, h->Xmat, h->d_Xoff, src,
+  LINE_LAUNCH(h->longl, k_source_term, N, 256, source_shm(L), s, h->g, h->mcoef, h->Xmat, h->d_Xoff, src,
                                                                      h->wloc);
-  k_fstar<<<nblk(nGm), 256, 0, s>>>(h->g, h->yloc, h->wloc, h->ru);
+  k_fstar<<<nblk(nGm), 256, 0, s>>>(h->g, h->yloc, h->wloc, h->d_sb, h->ru);
   fill(h, h->xu, nGm, 0.0);
   fill(h, h->xp, N, 0.0);
   k_norm2_partial<<<vec_blocks(nGm), 256, 0, s>>>(nGm, h->ru, h->cgw.part_r);
@@ -1174,7 +1254,10 @@ int solve_finish_locked(bddc_problem *h) {
   }
   // post-correction: interior fluxes and pressures
   double *fl = R.fl, *pr = R.pr;
-  fill(h, fl, L.nfaces_all, 0.0);
+  if (h->d_bflux)
+    HIPCHK(hipMemcpyAsync(fl, h->d_bflux, L.nfaces_all * sizeof(double), hipMemcpyDeviceToDevice, s));
+  else
+    fill(h, fl, L.nfaces_all, 0.0);
   if (nGm > 0) k_scatter_iface<<<nblk(nGm), 256, 0, s>>>(nGm, h->d_gamma_face, h->uG, fl);
   if (N == 1) fill(h, h->xp, 1, 0.0);
   // step 1 alone continues u_0 with zero source
@@ -1184,10 +1267,11 @@ int solve_finish_locked(bddc_problem *h) {
     rsrc = h->d_zero_src;
   }
   const size_t rec_shm = recover_shm(L);
-  k_recover_rhs<<<N, 256, rec_shm, s>>>(h->g, h->mcoef, rsrc, h->uG, h->rec_y);
+  LINE_LAUNCH(h->longl, k_recover_rhs, N, 256, rec_shm, s, h->g, h->mcoef, rsrc, h->uG, h->rec_y);
   k_recover_xgemv<<<dim3(N, nblk(L.maxC)), 256, (size_t)L.maxC * sizeof(double), s>>>(h->g, h->Xmat, h->d_Xoff,
                                                                                        h->rec_y, h->rec_p);
-  k_recover_flux<<<N, 256, rec_shm, s>>>(h->g, h->mcoef, h->uG, h->rec_p, h->xp, h->dscale, fl, pr);
+  LINE_LAUNCH(h->longl, k_recover_flux, N, 256, rec_shm, s, h->g, h->mcoef, h->uG, h->rec_p, h->xp, h->dscale, fl,
+              pr);
   k_sum_partial<<<256, 256, 0, s>>>(L.ncells, pr, h->cgw.part_p);
   k_sub_mean<<<256, 256, 0, s>>>(L.ncells, pr, h->cgw.part_p, 256);
   HIPCHK(hipGetLastError());
@@ -1196,7 +1280,6 @@ int solve_finish_locked(bddc_problem *h) {
     HIPCHK(hipMemcpyAsync(R.pressure, pr, L.ncells * sizeof(double), hipMemcpyDeviceToHost, s));
   }
   HIPCHK(hipStreamSynchronize(s));
-  check_flow(h);
   if (cg) {
     const CgState &fs = h->st_host[(R.chunks - 1) & 1];
     HIPCHK(hipEventElapsedTime(&pcg_ms, h->ev0, h->ev1));
@@ -1243,7 +1326,7 @@ void apply_options(bddc_problem *h, const bddc_options *opt) {
     h->coarse_top = opt->coarse_top;
     h->t_grid = opt->t_workgroups;
     h->ms_src = opt->ms_source;
-    h->coarse_dataflow = (opt->flags & BDDC_COARSE_DATAFLOW) != 0;
+    h->bflux_in = opt->bflux;
   }
   if (h->coarse_top > TOP_MAX_DOFS) throw Error{BDDC_EINVAL, "coarse_top above 8192"};
   if (h->precision != BDDC_FP64 && h->precision != BDDC_MIXED) throw Error{BDDC_EINVAL, "bad precision"};
@@ -1295,6 +1378,7 @@ bddc_problem *make_problem(const bddc_grid *g, const double *perm, const bddc_pa
     HIPCHK(hipStreamCreateWithFlags(&h->own_stream, hipStreamNonBlocking));
     h->stream = h->own_stream;
     do_setup(h, g, perm, part);
+    if (h->flags & BDDC_AUTOTUNE) autotune(h);
   } catch (...) {
     delete h;
     throw;
@@ -1404,6 +1488,14 @@ int bddc_stats(bddc_handle h, bddc_stats_t *out) {
     s.coarse_fronts = h->nd.nfr;
     s.coarse_dense = h->nd.nt;
     s.device_bytes = h->device_bytes;
+    s.sweep_wide4 = h->nd.wide4;
+    s.sweep_wide16 = h->nd.wide16;
+    s.t_workgroups = h->t_grid > 0 ? std::min(h->t_grid, h->L.N)
+                                   : (h->precision == BDDC_MIXED && h->n_cu > 0 ? std::min(h->n_cu, h->L.N) : h->L.N);
+    for (int c = 0; c < 4; ++c) {
+      s.tune_coarse_ms[c] = h->tune_coarse_ms[c];
+      s.tune_precond_ms[c] = h->tune_precond_ms[c];
+    }
     *out = s;
     return BDDC_OK;
   });
@@ -1530,7 +1622,6 @@ int64_t bddc_export(bddc_handle h, int32_t what, int32_t index, void *dst, int64
           HIPCHK(hipMemcpy(x.data(), h->csol, nk * sizeof(double), hipMemcpyDeviceToHost));
           for (int r = 0; r < ncu; ++r) o[r + (size_t)c * ncu] = x[fl[r]];
         }
-        check_flow(h);
         break;
       }
       case BDDC_X_FACE_EIG: {
@@ -1599,7 +1690,6 @@ int bddc_apply(bddc_handle h, int32_t which, const double *x_u, const double *x_
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s));
-    check_flow(h);
     return BDDC_OK;
   });
 }

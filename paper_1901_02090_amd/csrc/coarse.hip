@@ -7,8 +7,7 @@
 // per-front R = [L_PP^{-1}; L_BP L_PP^{-1}] is applied here.
 //
 // Solve (a front's results go straight into contiguous vectors of the fronts
-// that read them next; one dataflow launch, or one launch per level and
-// direction):
+// that read them next; one launch per level and direction):
 //   forward, from the leaves: t_p = b_P + S0_p[P] + S1_p[P], where S0 / S1 hold
 //     the updates pushed by children 0 / 1 at their positions in [P, B(p)];
 //     z_P = L_PP^{-1} t_p and w_p = S0_p[B] + S1_p[B] - L_BP L_PP^{-1} t_p,
@@ -27,7 +26,7 @@ struct DevSweep {
   const int *wdst;                 // forward push target of every B row
   const int *xsc_off, *xsc;        // backward: B-vector positions holding x[d]
   const int4 *task;                // four int4 per task (nd.hpp)
-  int nfr;                         // fronts (counters: nfr forward, nfr backward, 1 exit)
+  int nfr;                         // fronts
 };
 
 // ---- per-solve sweeps --------------------------------------------------------
@@ -44,40 +43,16 @@ __device__ __forceinline__ double group_reduce(double v, int g) {
   return group_sum<4>(v);
 }
 
-// Loads and stores of the vectors that pass between fronts (slot arrays S0 /
-// S1, z, the B vectors).  In the dataflow sweep producer and consumer run in
-// the same launch on different XCDs, so these accesses are device-coherent
-// (agent-scope relaxed atomics, which bypass the per-XCD L2); kernel
-// boundaries order them in the level-synchronous sweeps.
-template <bool COH>
-__device__ __forceinline__ double vld(const double *p) {
-  if (COH) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  return *p;
-}
-template <bool COH>
-__device__ __forceinline__ void vst(double *p, double v) {
-  if (COH) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  else *p = v;
-}
-
 // Rows [d0.y, d0.y + 256/g) of one front, forward: each lane group of g
 // lanes forms one row of R against t_p; rows r < n give z_P[r], rows n + k
-// push w_p[k] into the parent's slot array of this front.  With COH the
-// workgroup first stages t_p in LDS (if it fits in `cap` doubles), so each
-// device-coherent load happens once per task instead of once per row.  Called
-// by the whole workgroup.
-template <bool COH>
+// push w_p[k] into the parent's slot array of this front.  Called by the
+// whole workgroup.
 __device__ __forceinline__ void fwd_task(const int4 d0, const int4 d1, const int4 d2, const DevSweep &sw,
                                          const double *__restrict__ FR, const double *__restrict__ b, double *S0,
-                                         double *S1, double *z, double *lds, int cap) {
+                                         double *S1, double *z) {
   const int g = d0.z, n = d0.w, m = d1.x, fst = d1.y, vo = d1.z, bo = d1.w;
   const int64_t ro = (int64_t)(((uint64_t)(uint32_t)d2.y << 32) | (uint32_t)d2.x);
   const int lane = threadIdx.x & (g - 1), r = d0.y + threadIdx.x / g;
-  const bool staged = COH && n <= cap;
-  if (staged) {
-    for (int c = threadIdx.x; c < n; c += 256) lds[c] = (b[fst + c] + vld<COH>(S0 + vo + c)) + vld<COH>(S1 + vo + c);
-    __syncthreads();
-  }
   if (r >= n + m) return;            // whole lane groups leave together
   const double *row;
   int len;
@@ -91,7 +66,7 @@ __device__ __forceinline__ void fwd_task(const int4 d0, const int4 d1, const int
   double base = 0.0;
   int dst = 0;
   if (r >= n && lane == 0) {
-    base = vld<COH>(S0 + vo + r) + vld<COH>(S1 + vo + r);
+    base = S0[vo + r] + S1[vo + r];
     dst = sw.wdst[bo + (r - n)];
   }
   double a[4] = {0.0, 0.0, 0.0, 0.0};
@@ -100,37 +75,30 @@ __device__ __forceinline__ void fwd_task(const int4 d0, const int4 d1, const int
     for (int u = 0; u < 4; ++u) {
       const int c = c0 + u * g;
       if (c < len) {
-        const double t = staged ? lds[c] : (b[fst + c] + vld<COH>(S0 + vo + c)) + vld<COH>(S1 + vo + c);
+        const double t = (b[fst + c] + S0[vo + c]) + S1[vo + c];
         a[u] = fma(row[c], t, a[u]);
       }
     }
   }
   const double s = group_reduce((a[0] + a[1]) + (a[2] + a[3]), g);
   if (lane == 0) {
-    if (r < n) vst<COH>(z + fst + r, s);
-    else vst<COH>((d2.z ? S1 : S0) + dst, base - s);
+    if (r < n) z[fst + r] = s;
+    else (d2.z ? S1 : S0)[dst] = base - s;
   }
 }
 
 // Columns [d0.y, d0.y + 256/g) of one front, backward; each x[d] is also
-// stored into every B vector that holds d (those of the fronts below).  With
-// COH the input [s_P z_P; -x_B] is staged in LDS when n + m <= cap.  Called
-// by the whole workgroup.
-template <bool COH>
+// stored into every B vector that holds d (those of the fronts below), and
+// the right-hand side b[d], consumed by the forward sweep, is cleared for the
+// next solve.  Called by the whole workgroup.
 __device__ __forceinline__ void bwd_task(const int4 d0, const int4 d1, const int4 d2, const DevSweep &sw,
                                          const double *__restrict__ BC, const double *z,
                                          const double *__restrict__ sg, double *XB, double *__restrict__ x,
-                                         double *lds, int cap) {
+                                         double *__restrict__ b) {
   const int g = d0.z, n = d0.w, m = d1.x, fst = d1.y, bo = d1.w;
   const int64_t ro = (int64_t)(((uint64_t)(uint32_t)d2.y << 32) | (uint32_t)d2.x);
   const int lane = threadIdx.x & (g - 1), c = d0.y + threadIdx.x / g;
   const double *xb = XB + bo;
-  const bool staged = COH && n + m <= cap;
-  if (staged) {
-    for (int k = threadIdx.x; k < n + m; k += 256)
-      lds[k] = k < n ? sg[fst + k] * vld<COH>(z + fst + k) : -vld<COH>(xb + (k - n));
-    __syncthreads();
-  }
   if (c >= n) return;
   const int f = n + m, d = fst + c;
   const int s0 = sw.xsc_off[d], s1 = sw.xsc_off[d + 1];
@@ -142,16 +110,17 @@ __device__ __forceinline__ void bwd_task(const int4 d0, const int4 d1, const int
     for (int u = 0; u < 4; ++u) {
       const int q = q0 + u * g;
       if (q < len) {
-        double in;
-        if (staged) in = lds[q < nl ? c + q : n + (q - nl)];
-        else in = q < nl ? sg[d + q] * vld<COH>(z + d + q) : -vld<COH>(xb + q - nl);
+        const double in = q < nl ? sg[d + q] * z[d + q] : -xb[q - nl];
         a[u] = fma(col[q], in, a[u]);
       }
     }
   }
   const double s = group_reduce((a[0] + a[1]) + (a[2] + a[3]), g);
-  if (lane == 0) x[d] = s;
-  for (int k = s0 + lane; k < s1; k += g) vst<COH>(XB + sw.xsc[k], s);
+  if (lane == 0) {
+    x[d] = s;
+    b[d] = 0.0;
+  }
+  for (int k = s0 + lane; k < s1; k += g) XB[sw.xsc[k]] = s;
 }
 
 // Level-synchronous sweeps: the tasks [t0, t0 + gridDim.x) of one level, one
@@ -161,15 +130,16 @@ __global__ __launch_bounds__(256) void k_nd_fwd(int t0, DevSweep sw, const doubl
                                                 double *__restrict__ z, const int *done) {
   if (done && *done) return;
   const int4 *td = sw.task + 4 * (int64_t)(t0 + blockIdx.x);
-  fwd_task<false>(td[0], td[1], td[2], sw, FR, b, S0, S1, z, nullptr, 0);
+  fwd_task(td[0], td[1], td[2], sw, FR, b, S0, S1, z);
 }
 
 __global__ __launch_bounds__(256) void k_nd_bwd(int t0, DevSweep sw, const double *__restrict__ BC,
                                                 const double *__restrict__ z, const double *__restrict__ sg,
-                                                double *XB, double *__restrict__ x, const int *done) {
+                                                double *XB, double *__restrict__ x, double *__restrict__ b,
+                                                const int *done) {
   if (done && *done) return;
   const int4 *td = sw.task + 4 * (int64_t)(t0 + blockIdx.x);
-  bwd_task<false>(td[0], td[1], td[2], sw, BC, z, sg, XB, x, nullptr, 0);
+  bwd_task(td[0], td[1], td[2], sw, BC, z, sg, XB, x, b);
 }
 
 // ---- dense top block (nd_dense_top) ---------------------------------------------
@@ -194,7 +164,8 @@ __global__ __launch_bounds__(256) void k_top_gather(int nt, int d0, const int *_
 // staged in LDS (ld doubles, zero padded), each wave forms two rows of the
 // row-major inverse (leading dimension ld, even, so rows are 16-byte aligned)
 // with 16-byte loads.  Each x[d] is also stored into every B vector holding d,
-// for the backward sweep of the levels below.
+// for the backward sweep of the levels below, and b[d] (read by the gather
+// before this launch) is cleared for the next solve.
 constexpr int TOP_THREADS = 256;
 constexpr int TOP_ROWS_PER_WG = 8;
 constexpr int TOP_DEFAULT_DOFS = 4096;   // 128 MB of FP64 inverse at most
@@ -204,7 +175,8 @@ __global__ __launch_bounds__(TOP_THREADS) void k_top_gemv(int nt, int ld, const 
                                                           const double *__restrict__ tt, int d0,
                                                           const int *__restrict__ xsc_off,
                                                           const int *__restrict__ xsc, double *__restrict__ XB,
-                                                          double *__restrict__ x, const int *done) {
+                                                          double *__restrict__ x, double *__restrict__ b,
+                                                          const int *done) {
   if (done && *done) return;
   extern __shared__ double tl[];
   for (int j = threadIdx.x; j < ld; j += TOP_THREADS) tl[j] = j < nt ? tt[j] : 0.0;
@@ -246,7 +218,11 @@ __global__ __launch_bounds__(TOP_THREADS) void k_top_gemv(int nt, int ld, const 
   const int d = d0 + r0;
   if (lane == 0) {
     x[d] = s0;
-    if (two) x[d + 1] = s1;
+    b[d] = 0.0;
+    if (two) {
+      x[d + 1] = s1;
+      b[d + 1] = 0.0;
+    }
   }
   for (int q = xsc_off[d] + lane; q < xsc_off[d + 1]; q += 64) XB[xsc[q]] = s0;
   if (two)
@@ -279,70 +255,6 @@ __global__ __launch_bounds__(256) void k_top_store(int j0, int nt, int d0, int l
   const double *xc = x + c * sk + d0;
   double *row = Kt + (int64_t)(j0 + c) * ld;
   for (int i = blockIdx.x * 256 + threadIdx.x; i < ld; i += gridDim.x * 256) row[i] = i < nt ? xc[i] : 0.0;
-}
-
-// ---- dataflow sweep ------------------------------------------------------------
-// One launch runs the whole coarse solve.  A resident grid walks the task list
-// (forward tasks leaves-up, then backward tasks root-down) in index order,
-// workgroup w taking tasks w, w + G, w + 2G, ...  Before a task its first
-// thread waits until the counters it depends on reach their targets; after
-// it, every lane waits for its device-coherent stores to complete and the
-// task's counter is raised.  No cache maintenance is needed: the vectors that
-// pass between fronts are read and written device-coherently, everything else
-// a task reads was written before the launch.  The list is in topological
-// order and every workgroup takes its tasks in increasing order, so the lowest
-// unfinished task always has its producers done: the sweep cannot deadlock
-// while the grid fits on the device.  Waits are bounded: on timeout the abort
-// word is set, every workgroup skips its remaining tasks and the host reports
-// an error.  The last workgroup to leave clears the counters for the next
-// solve.
-constexpr int FLOW_SPIN_MAX = 1 << 20;
-
-__device__ __forceinline__ bool flow_wait(const int *cnt, int target, int *abort_flag) {
-  for (int it = 0;; ++it) {
-    if (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) return true;
-    if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
-    if (it >= FLOW_SPIN_MAX) {
-      __hip_atomic_fetch_or(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      return false;
-    }
-    __builtin_amdgcn_s_sleep(1);
-  }
-}
-
-__global__ __launch_bounds__(256) void k_nd_flow(int ntask, DevSweep sw, const double *__restrict__ FR,
-                                                 const double *__restrict__ BC, const double *__restrict__ b,
-                                                 double *S0, double *S1, double *z, const double *__restrict__ sg,
-                                                 double *XB, double *x, int *cnt, int *abort_flag, int cap,
-                                                 const int *done) {
-  if (done && *done) return;
-  extern __shared__ double lds[];    // cap doubles: the staged input of a task
-  __shared__ int go, last;
-  for (int t = blockIdx.x; t < ntask; t += gridDim.x) {
-    const int4 *td = sw.task + 4 * (int64_t)t;
-    const int4 d0 = td[0], d1 = td[1], d2 = td[2], d3 = td[3];
-    if (threadIdx.x == 0) {
-      bool ok = true;
-      if (d3.x >= 0) ok = flow_wait(cnt + d3.x, d3.y, abort_flag);
-      if (ok && d3.z >= 0) ok = flow_wait(cnt + d3.z, d3.w, abort_flag);
-      go = ok ? 1 : 0;
-    }
-    __syncthreads();
-    if (!go) break;
-    if (d2.w == 0) fwd_task<true>(d0, d1, d2, sw, FR, b, S0, S1, z, lds, cap);
-    else bwd_task<true>(d0, d1, d2, sw, BC, z, sg, XB, x, lds, cap);
-    __builtin_amdgcn_s_waitcnt(0);   // this lane's coherent stores have completed
-    __syncthreads();
-    if (threadIdx.x == 0)
-      __hip_atomic_fetch_add(cnt + (d2.w ? sw.nfr : 0) + d0.x, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-  __syncthreads();
-  if (threadIdx.x == 0)
-    last = __hip_atomic_fetch_add(cnt + 2 * sw.nfr, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) ==
-           (int)gridDim.x - 1;
-  __syncthreads();
-  if (last)
-    for (int i = threadIdx.x; i <= 2 * sw.nfr; i += 256) cnt[i] = 0;
 }
 
 }  // namespace bddc

@@ -5,7 +5,12 @@
 
 namespace bddc {
 
-constexpr int MAXLINE = 32;   // longest subdomain extent along one axis
+// Kernels that solve along lines of subdomain cells keep a line in private
+// arrays; they come in two instances, for extents up to SHORTLINE cells (all
+// boxes of the benchmarks) and up to MAXLINE, the longest subdomain extent
+// along one axis that the library accepts.
+constexpr int SHORTLINE = 32;
+constexpr int MAXLINE = 128;
 
 // Group-aligned packed storage of a symmetric n x n matrix (lower triangle).
 // Columns come in groups of four; group g holds its four columns over rows
@@ -53,6 +58,9 @@ struct DevGeom {
   // weights of the averaging operator E on the minus / plus copy of each
   // face's dofs (stiffness scaling); null: 1/2 each (multiplicity)
   const double *fw_minus = nullptr, *fw_plus = nullptr;   // [nF]
+  // prescribed normal fluxes of the boundary faces (global face numbering,
+  // interior entries zero); null: no flow through the boundary
+  const double *bflux = nullptr;
 };
 
 // Per-subdomain dense setup workspace (FP64, column major).

@@ -55,6 +55,8 @@ struct NdPlan {
   // rows, backward scatter targets of the own dofs and the copies of the
   // parents' B values into their children's B vectors
   std::vector<int> gf, gb;          // [nfr] group widths, forward rows / backward columns
+  std::vector<int> parent;          // [nfr] parent front (-1: root)
+  int wide4 = 24, wide16 = 96;      // rows (columns) up to wide4 long take 4 lanes, up to wide16 16, else 64
   std::vector<int> cslot;           // [nfr]
   std::vector<int> wdst;            // [sum m] forward: position of w_c[k] in the parent's vectors
   std::vector<int> xsc_off, xsc;    // [nk+1], [sum m]: every B-vector position holding x[d]
@@ -72,6 +74,76 @@ struct NdPlan {
   int nt = 0;
   std::vector<int> tg_off, tg;      // [nt+1], positions
 };
+
+// Lane-group widths and the task list of the solve sweeps.  A row (forward)
+// or column (backward) of at most wide4 entries is handled by 4 lanes, of at
+// most wide16 by 16, longer ones by 64, so that short rows do not leave lanes
+// idle; a workgroup of 256 lanes takes 256 / g of them.  Called by nd_plan
+// with the defaults and again by the autotuner with other thresholds (the
+// factor and the dense top block do not depend on them).
+inline void nd_tasks(NdPlan &P, int wide4, int wide16) {
+  const int nn = P.nfr, H = P.H;
+  P.wide4 = wide4;
+  P.wide16 = wide16;
+  auto width = [&](int len) { return len <= wide4 ? 4 : (len <= wide16 ? 16 : 64); };
+  P.gf.assign(nn, 4);
+  P.gb.assign(nn, 4);
+  for (int r = 0; r < nn; ++r) {
+    P.gf[r] = width(P.n[r]);
+    P.gb[r] = width(P.n[r] + P.m[r]);
+  }
+  P.task.clear();
+  // Task descriptors, four int4 each:
+  //   {front, first row / column, lane-group width, n}, {m, first dof, v_off, b_off},
+  //   {r_off low 32 bits, r_off high 32 bits, child slot, kind (0 forward, 1 backward)},
+  //   {dependency a, count a, dependency b, count b}  (-1: none)
+  // One workgroup (256 lanes) takes 256/g rows (forward) or columns (backward).
+  // The dependencies name what a task reads (p: the forward tasks of front p,
+  // nfr + p: its backward tasks, with their number): a forward task reads its
+  // children's forward results, a backward task its parent's backward results
+  // (the root: its own forward results).  The list is in topological order;
+  // the host plan test checks both against the level order of the sweeps.
+  std::vector<int> nft(nn, 0), nbt(nn, 0);
+  for (int r = 0; r < nn; ++r) {
+    const int fr = 256 / P.gf[r], br = 256 / P.gb[r];
+    nft[r] = (P.n[r] + P.m[r] + fr - 1) / fr;
+    nbt[r] = (P.n[r] + br - 1) / br;
+  }
+  auto push = [&](int r, int j, int g, int kind) {
+    const int64_t ro = P.r_off[r];
+    int da = -1, ta = 0, db = -1, tb = 0;
+    if (kind == 0) {
+      const int c0 = P.ch[2 * r], c1 = P.ch[2 * r + 1];
+      if (c0 >= 0) { da = c0; ta = nft[c0]; }
+      if (c1 >= 0) { db = c1; tb = nft[c1]; }
+    } else if (P.parent[r] >= 0) {
+      da = nn + P.parent[r];
+      ta = nbt[P.parent[r]];
+    } else {
+      da = r;
+      ta = nft[r];
+    }
+    const int d[16] = {r, j, g, P.n[r], P.m[r], P.first[r], (int)P.v_off[r], P.b_off[r],
+                       (int)(uint32_t)(ro & 0xffffffff), (int)(uint32_t)(ro >> 32), P.cslot[r], kind,
+                       da, ta, db, tb};
+    P.task.insert(P.task.end(), d, d + 16);
+  };
+  P.ftask_off.assign(H + 1, 0);
+  P.btask_lo.assign(H, 0);
+  P.btask_hi.assign(H, 0);
+  for (int h = 0; h < H; ++h) {
+    for (int r = P.lvl_off[h]; r < P.lvl_off[h + 1]; ++r)
+      for (int j = 0; j < P.n[r] + P.m[r]; j += 256 / P.gf[r]) push(r, j, P.gf[r], 0);
+    P.ftask_off[h + 1] = (int)P.task.size() / 16;
+  }
+  for (int h = H - 1; h >= 0; --h) {
+    P.btask_lo[h] = (int)P.task.size() / 16;
+    for (int r = P.lvl_off[h]; r < P.lvl_off[h + 1]; ++r)
+      for (int j = 0; j < P.n[r]; j += 256 / P.gb[r]) push(r, j, P.gb[r], 1);
+    P.btask_hi[h] = (int)P.task.size() / 16;
+  }
+  P.ntask = (int)P.task.size() / 16;
+}
 
 // `leaf`: largest number of subdomains in a leaf box (>= 1).
 inline void nd_plan(const Layout &L, const std::vector<int> &face_k, int leaf, NdPlan &P) {
@@ -322,16 +394,11 @@ inline void nd_plan(const Layout &L, const std::vector<int> &face_k, int leaf, N
   }
   // sweep maps
   const int64_t nv = P.v_off[nn];
-  P.gf.assign(nn, 4);
-  P.gb.assign(nn, 4);
   P.cslot.assign(nn, 0);
-  auto width = [](int len) { return len <= 24 ? 4 : (len <= 96 ? 16 : 64); };
-  for (int r = 0; r < nn; ++r) {
-    P.gf[r] = width(P.n[r]);
-    P.gb[r] = width(P.n[r] + P.m[r]);
+  for (int r = 0; r < nn; ++r)
     for (int k = 0; k < 2; ++k)
       if (P.ch[2 * r + k] >= 0) P.cslot[P.ch[2 * r + k]] = k;
-  }
+  P.parent = parent;
   P.wdst.assign(P.b_off[nn], -1);
   for (int c = 0; c < nn; ++c) {
     const int p = parent[c];
@@ -347,55 +414,7 @@ inline void nd_plan(const Layout &L, const std::vector<int> &face_k, int leaf, N
     std::vector<int> fillp(P.xsc_off.begin(), P.xsc_off.end() - 1);
     for (int q = 0; q < (int)P.bidx.size(); ++q) P.xsc[fillp[P.bidx[q]]++] = q;
   }
-  // Task descriptors, four int4 each:
-  //   {front, first row / column, lane-group width, n}, {m, first dof, v_off, b_off},
-  //   {r_off low 32 bits, r_off high 32 bits, child slot, kind (0 forward, 1 backward)},
-  //   {counter a, target a, counter b, target b}  (-1: no dependency)
-  // One workgroup (256 lanes) takes 256/g rows (forward) or columns (backward).
-  // Counter p counts the finished forward tasks of front p, counter nfr + p its
-  // backward tasks.  A forward task waits for its children's forward tasks; a
-  // backward task for its parent's backward tasks (the root: its own forward
-  // tasks).  The order is topological, as the dataflow sweep requires.
-  std::vector<int> nft(nn, 0), nbt(nn, 0);
-  for (int r = 0; r < nn; ++r) {
-    const int fr = 256 / P.gf[r], br = 256 / P.gb[r];
-    nft[r] = (P.n[r] + P.m[r] + fr - 1) / fr;
-    nbt[r] = (P.n[r] + br - 1) / br;
-  }
-  auto push = [&](int r, int j, int g, int kind) {
-    const int64_t ro = P.r_off[r];
-    int da = -1, ta = 0, db = -1, tb = 0;
-    if (kind == 0) {
-      const int c0 = P.ch[2 * r], c1 = P.ch[2 * r + 1];
-      if (c0 >= 0) { da = c0; ta = nft[c0]; }
-      if (c1 >= 0) { db = c1; tb = nft[c1]; }
-    } else if (parent[r] >= 0) {
-      da = nn + parent[r];
-      ta = nbt[parent[r]];
-    } else {
-      da = r;
-      ta = nft[r];
-    }
-    const int d[16] = {r, j, g, P.n[r], P.m[r], P.first[r], (int)P.v_off[r], P.b_off[r],
-                       (int)(uint32_t)(ro & 0xffffffff), (int)(uint32_t)(ro >> 32), P.cslot[r], kind,
-                       da, ta, db, tb};
-    P.task.insert(P.task.end(), d, d + 16);
-  };
-  P.ftask_off.assign(H + 1, 0);
-  P.btask_lo.assign(H, 0);
-  P.btask_hi.assign(H, 0);
-  for (int h = 0; h < H; ++h) {
-    for (int r = P.lvl_off[h]; r < P.lvl_off[h + 1]; ++r)
-      for (int j = 0; j < P.n[r] + P.m[r]; j += 256 / P.gf[r]) push(r, j, P.gf[r], 0);
-    P.ftask_off[h + 1] = (int)P.task.size() / 16;
-  }
-  for (int h = H - 1; h >= 0; --h) {
-    P.btask_lo[h] = (int)P.task.size() / 16;
-    for (int r = P.lvl_off[h]; r < P.lvl_off[h + 1]; ++r)
-      for (int j = 0; j < P.n[r]; j += 256 / P.gb[r]) push(r, j, P.gb[r], 1);
-    P.btask_hi[h] = (int)P.task.size() / 16;
-  }
-  P.ntask = (int)P.task.size() / 16;
+  nd_tasks(P, P.wide4, P.wide16);
   P.top = H;
   P.tg_off.assign(1, 0);
   if (nv > INT32_MAX) throw std::length_error("coarse plan: front vectors too long");

@@ -95,8 +95,7 @@ double estimate_bytes(const bddc_grid *gr, const bddc_partition *part, double ta
       throw Error{BDDC_EINVAL, std::string("coarse plan: ") + e.what()};
     }
     const int ct = opt ? opt->coarse_top : 0;
-    const bool flow = opt && (opt->flags & BDDC_COARSE_DATAFLOW);
-    nd_dense_top(P, flow ? 0 : (ct == 0 ? TOP_DEFAULT_DOFS : ct));
+    nd_dense_top(P, ct == 0 ? TOP_DEFAULT_DOFS : ct);
     const int nfr = P.nfr;
     const double nk = P.nk, nv = (double)P.v_off[nfr], nb = (double)P.b_off[nfr];
     b += 8.0 * ((double)P.F_off[nfr] + (double)P.w_off[nfr] + (double)P.q_off[nfr] + 2.0 * (double)P.r_off[nfr]);

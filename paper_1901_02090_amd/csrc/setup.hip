@@ -40,8 +40,9 @@ __device__ __forceinline__ int line_start(int d, int l, const int *ext, const in
 // Solve the interior-face system of one line of n cells: faces j = 1..n-1,
 // diagonal (m[j-1] + m[j]) / 3, coupling of faces j and j+1 through cell j:
 // m[j] / 6.  y[1..n-1] holds the right-hand side on entry, the solution on exit.
+template <int CAP>
 __device__ __forceinline__ void line_solve(int n, const double *m, double *y) {
-  double cp[MAXLINE];
+  double cp[CAP];
   if (n < 2) return;
   double den = (m[0] + m[1]) / 3.0;
   cp[1] = (n > 2) ? (m[1] / 6.0) / den : 0.0;
@@ -121,6 +122,7 @@ __global__ __launch_bounds__(64) void k_face_weights(DevGeom g, const double *__
 // ---------------------------------------------------------------------------
 // per-subdomain: d_i, P, H, S_A, L_P, S^i, X^i
 // ---------------------------------------------------------------------------
+template <int CAP>
 __global__ __launch_bounds__(256, 2) void k_local_setup(DevGeom g, const double *__restrict__ mcoef,
                                                      SetupWs ws, double *dscale, int *err) {
   __shared__ double lds[LDS_DOUBLES];
@@ -171,12 +173,12 @@ __global__ __launch_bounds__(256, 2) void k_local_setup(DevGeom g, const double 
       for (int it = tid; it < lines * n; it += WG) {
         const int l = it / n, c = it % n;
         const int s0 = line_start(d, l, ext, st);
-        double m[MAXLINE], y[MAXLINE + 1];
+        double m[CAP], y[CAP + 1];
         for (int t = 0; t < n; ++t) m[t] = mloc(s0 + t * st[d], d);
         for (int j = 0; j <= n; ++j) y[j] = 0.0;
         if (c >= 1) y[c] += 1.0;
         if (c + 1 <= n - 1) y[c + 1] -= 1.0;
-        line_solve(n, m, y);
+        line_solve<CAP>(n, m, y);
         const int colc = s0 + c * st[d];
         for (int cp = 0; cp < n; ++cp) P[(s0 + cp * st[d]) + (size_t)colc * nc] += line_B(n, y, cp);
       }
@@ -195,7 +197,7 @@ __global__ __launch_bounds__(256, 2) void k_local_setup(DevGeom g, const double 
     const int n = ext[d];
     const int cd = (lc / st[d]) % n;
     const int s0 = lc - cd * st[d];
-    double m[MAXLINE], y[MAXLINE + 1];
+    double m[CAP], y[CAP + 1];
     for (int u = 0; u < n; ++u) m[u] = mloc(s0 + u * st[d], d);
     const int eidx = end ? n - 1 : 0;
     const double mend = m[eidx];
@@ -205,7 +207,7 @@ __global__ __launch_bounds__(256, 2) void k_local_setup(DevGeom g, const double 
       const int adj = end ? n - 1 : 1, oadj = end ? 1 : n - 1;
       for (int j = 0; j <= n; ++j) y[j] = 0.0;
       y[adj] = 1.0;
-      line_solve(n, m, y);
+      line_solve<CAP>(n, m, y);
       for (int cp = 0; cp < n; ++cp)
         H[(s0 + cp * st[d]) + (size_t)t * ldh] -= (mend / 6.0) * line_B(n, y, cp);
       S[t + (size_t)t * nG] += mend / 3.0 - (mend / 6.0) * (mend / 6.0) * y[adj];

@@ -222,13 +222,17 @@ __global__ __launch_bounds__(SYMV_THREADS) void k_symv(DevGeom g, const TS *__re
 
 // g^i = Psi^{iT} (w * R_i x), w = xw or xscale: the coarse right-hand side pieces of the
 // preconditioner (one workgroup per subdomain; four columns per wave, 16-byte
-// loads over the ld4-padded columns).
+// loads over the ld4-padded columns), added straight into the coarse
+// right-hand side b at the coarse dofs (sub_cmap).  A face's coarse dof gets
+// the pieces of its two subdomains, b must be zero there on entry (the coarse
+// solve clears b as it consumes it), and the sum of two values onto zero is
+// the same in either order; the pressure rows of b stay zero.
 template <typename TS>
 __global__ __launch_bounds__(256) void k_psi_apply(DevGeom g, const TS *__restrict__ Psi,
                                                    const int64_t *__restrict__ psi_off,
-                                                   const int *__restrict__ sub_coff, const double *__restrict__ x,
-                                                   double xscale, const double *__restrict__ xw,
-                                                   double *__restrict__ gloc, CgState *st,
+                                                   const int *__restrict__ sub_coff, const int *__restrict__ sub_cmap,
+                                                   const double *__restrict__ x, double xscale,
+                                                   const double *__restrict__ xw, double *__restrict__ b, CgState *st,
                                                    const double *__restrict__ rpart, int nrpart) {
   extern __shared__ double sh[];
   __shared__ double red[8];
@@ -262,8 +266,8 @@ __global__ __launch_bounds__(256) void k_psi_apply(DevGeom g, const TS *__restri
     const double tot1 = transpose_reduce4(d + 4, lane);
     if ((lane & 15) == 0) {
       const int c = cb + (lane >> 4);
-      if (c < nci) gloc[c0 + c] = tot0;
-      if (c + 4 < nci) gloc[c0 + c + 4] = tot1;
+      if (c < nci) atomicAdd(b + sub_cmap[c0 + c], tot0);
+      if (c + 4 < nci) atomicAdd(b + sub_cmap[c0 + c + 4], tot1);
     }
   }
 }
@@ -327,18 +331,6 @@ __global__ __launch_bounds__(256) void k_update_xr(int nGamma, int N, const doub
     }
   }
   block_write_partial(v, rpart, red);
-}
-
-// coarse right-hand side: each flux coarse dof gathers its two local values,
-// pressure rows are zero (the preconditioner's input is (r_B, 0))
-__global__ void k_coarse_rhs(DevCoarse cs, const double *__restrict__ gloc, double *__restrict__ b,
-                             const CgState *st) {
-  if (st && st->done) return;
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j < cs.nk) {
-    const int a = cs.co_minus[j];
-    b[j] = (a >= 0) ? gloc[a] + gloc[cs.co_plus[j]] : 0.0;
-  }
 }
 
 // w^i = y^i + Psi^i alpha^(i)  (y may be null: w^i = Psi^i alpha^(i)).  Each lane owns 16-byte row
@@ -535,10 +527,23 @@ __device__ __forceinline__ int line_start_s(int d, int l, const int *ext, const 
   return (l % ext[a0]) * st[a0] + (l / ext[a0]) * st[a1];
 }
 
+// Flux at an end of a line of subdomain cells that is not an interface dof:
+// a face of the domain boundary, whose flux is prescribed (zero without
+// boundary data).  lc: the line's end cell (local index), d: direction, e: 0
+// for the minus end, 1 for the plus end.
+__device__ __forceinline__ double boundary_end_flux(const DevGeom &g, int d, int lc, int e, const int *lo,
+                                                    const int *ext) {
+  if (!g.bflux) return 0.0;
+  int c[3] = {lo[0] + lc % ext[0], lo[1] + (lc / ext[0]) % ext[1], lo[2] + lc / (ext[0] * ext[1])};
+  c[d] += e;
+  return g.bflux[g.face_off[d] + c[0] + (int64_t)g.fshape[d][0] * (c[1] + (int64_t)g.fshape[d][1] * c[2])];
+}
+
 // The line's cell coefficients are m[0], m[ms], ..., m[(n-1) ms] (staged in
 // LDS by the caller).
+template <int CAP>
 __device__ __forceinline__ void line_solve_s(int n, const double *m, int ms, double *y) {
-  double cp[MAXLINE];
+  double cp[CAP];
   if (n < 2) return;
   double den = (m[0] + m[ms]) / 3.0;
   cp[1] = (n > 2) ? (m[ms] / 6.0) / den : 0.0;
@@ -597,6 +602,7 @@ __device__ __forceinline__ void block_gemv(int n, const double *__restrict__ X, 
 
 // h^i = H^{iT} X^i F^i: the source-dependent part of the reduced right-hand
 // side f* (zero in subdomains without source).
+template <int CAP>
 __global__ __launch_bounds__(256) void k_source_term(DevGeom g, const double *__restrict__ mcoef,
                                                      const double *__restrict__ Xmat, const int64_t *__restrict__ Xoff,
                                                      const double *__restrict__ src, double *__restrict__ hloc) {
@@ -632,14 +638,14 @@ __global__ __launch_bounds__(256) void k_source_term(DevGeom g, const double *__
     const int s0 = lc - cd * st[d];
     const double *m = mc + 3 * s0 + d;
     const int ms = 3 * st[d];
-    double y[MAXLINE + 1];
+    double y[CAP + 1];
     const int eidx = end ? n - 1 : 0;
     double v = (end ? -1.0 : 1.0) * ys[s0 + eidx * st[d]];
     if (n >= 2) {
       // (G B_l^T y)[adj]: (B_l^T y)_j = y[c_j] - y[c_{j-1}]
       y[0] = 0.0;
       for (int j = 1; j <= n - 1; ++j) y[j] = ys[s0 + j * st[d]] - ys[s0 + (j - 1) * st[d]];
-      line_solve_s(n, m, ms, y);
+      line_solve_s<CAP>(n, m, ms, y);
       const int adj = end ? n - 1 : 1;
       v -= (m[eidx * ms] / 6.0) * y[adj];
     }
@@ -647,13 +653,101 @@ __global__ __launch_bounds__(256) void k_source_term(DevGeom g, const double *__
   }
 }
 
-// f* = -assembled S u0 + assembled h  (step-3 reduced right-hand side)
+// f* = -assembled S u0 + assembled h (+ assembled sb, the interface load of
+// the boundary fluxes; may be null)  (step-3 reduced right-hand side)
 __global__ void k_fstar(DevGeom g, const double *__restrict__ yloc, const double *__restrict__ hloc,
-                        double *__restrict__ r) {
+                        const double *__restrict__ sb, double *__restrict__ r) {
   const int gi = blockIdx.x * blockDim.x + threadIdx.x;
   if (gi >= g.nGamma) return;
   const int a = g.own_minus[gi], b = g.own_plus[gi];
-  r[gi] = -(yloc[a] + yloc[b]) + hloc[a] + hloc[b];
+  double v = -(yloc[a] + yloc[b]) + hloc[a] + hloc[b];
+  if (sb) v += sb[a] + sb[b];
+  r[gi] = v;
+}
+
+// Boundary flux data (prescribed normal fluxes g on the boundary faces) for the
+// reduced problem.  With u = u_b + u_0, u_b carrying g on the boundary faces,
+// each local problem gains the cell load H_b g = B_b g - B_I A_II^{-1} A_Ib g
+// (its flux-row load -A_Ib g eliminated along the lines of cells) and each
+// interface dof t the load -(A_tb - A_tI A_II^{-1} A_Ib) g of the line through
+// it whose other end is on the boundary.  hb: per cell (global order), the
+// first; sb: per local interface dof, the second.  One block per subdomain.
+template <int CAP>
+__global__ __launch_bounds__(256) void k_bflux_load(DevGeom g, const double *__restrict__ mcoef,
+                                                    double *__restrict__ hb, double *__restrict__ sb) {
+  extern __shared__ double sh[];
+  const int i = blockIdx.x, tid = threadIdx.x;
+  const int nc = g.nc[i], nG = g.nG[i];
+  const int64_t go = g.g_off[i];
+  const int *lcg = g.lcell_global + g.cell_off[i];
+  double *ys = sh, *mc = sh + nc;
+  int ext[3], lo[3], st[3];
+  for (int d = 0; d < 3; ++d) {
+    ext[d] = g.ext[3 * i + d];
+    lo[d] = g.lo[3 * i + d];
+  }
+  st[0] = 1; st[1] = ext[0]; st[2] = ext[0] * ext[1];
+  for (int c = tid; c < nc; c += 256) ys[c] = 0.0;
+  stage_mcoef(nc, lcg, mcoef, mc);
+  __syncthreads();
+  const int *lg = g.line_g + g.line_off[i];
+  int64_t lbase = 0;
+  for (int d = 0; d < g.dim; ++d) {
+    const int n = ext[d], lines = nc / n;
+    for (int l = tid; l < lines; l += 256) {
+      const int s0 = line_start_s(d, l, ext, st), s1 = s0 + (n - 1) * st[d];
+      const double gm = lg[lbase + 2 * l] < 0 ? boundary_end_flux(g, d, s0, 0, lo, ext) : 0.0;
+      const double gp = lg[lbase + 2 * l + 1] < 0 ? boundary_end_flux(g, d, s1, 1, lo, ext) : 0.0;
+      ys[s0] += gm;
+      ys[s1] -= gp;
+      if (n >= 2 && (gm != 0.0 || gp != 0.0)) {
+        const double *m = mc + 3 * s0 + d;
+        const int ms = 3 * st[d];
+        double y[CAP + 1];
+        for (int j = 0; j <= n; ++j) y[j] = 0.0;
+        y[1] += (m[0] / 6.0) * gm;
+        y[n - 1] += (m[(n - 1) * ms] / 6.0) * gp;
+        line_solve_s<CAP>(n, m, ms, y);
+        for (int c = 0; c < n; ++c) {
+          double v = 0.0;
+          if (c >= 1) v += y[c];
+          if (c + 1 <= n - 1) v -= y[c + 1];
+          ys[s0 + c * st[d]] -= v;
+        }
+      }
+    }
+    lbase += 2 * lines;
+    __syncthreads();
+  }
+  for (int c = tid; c < nc; c += 256) hb[lcg[c]] = ys[c];
+  // interface dofs whose line ends on the boundary at its other end
+  for (int t = tid; t < nG; t += 256) {
+    const int64_t fl = go + t;
+    const int d = g.lg_dir[fl], lc = g.lg_cell[fl], end = g.lg_end[fl];
+    const int n = ext[d];
+    const int cd = (lc / st[d]) % n;
+    const int s0 = lc - cd * st[d], s1 = s0 + (n - 1) * st[d];
+    const bool other_on_boundary = end ? (lo[d] == 0) : (lo[d] + n == g.n[d]);
+    double v = 0.0;
+    if (other_on_boundary) {
+      const double gb = end ? boundary_end_flux(g, d, s0, 0, lo, ext) : boundary_end_flux(g, d, s1, 1, lo, ext);
+      const double *m = mc + 3 * s0 + d;
+      const int ms = 3 * st[d];
+      if (gb != 0.0) {
+        if (n == 1) {
+          v = -(m[0] / 6.0) * gb;                  // -A_tb g: both faces of one cell
+        } else {
+          double y[CAP + 1];
+          for (int j = 0; j <= n; ++j) y[j] = 0.0;
+          if (end) y[1] = (m[0] / 6.0) * gb;       // A_Ib g next to the minus (boundary) end
+          else y[n - 1] = (m[(n - 1) * ms] / 6.0) * gb;
+          line_solve_s<CAP>(n, m, ms, y);
+          v = end ? (m[(n - 1) * ms] / 6.0) * y[n - 1] : (m[0] / 6.0) * y[1];   // A_tI A_II^{-1} A_Ib g
+        }
+      }
+    }
+    sb[fl] = v;
+  }
 }
 
 // B_0 x per subdomain (diagnostic operator)
@@ -684,6 +778,7 @@ __global__ __launch_bounds__(256) void k_b0(DevGeom g, const double *__restrict_
 // local cell, in the subdomains' local cell order.
 // ---------------------------------------------------------------------------
 // y = H w - F = H w + source, with w = R_i u_G
+template <int CAP>
 __global__ __launch_bounds__(256) void k_recover_rhs(DevGeom g, const double *__restrict__ mcoef,
                                                      const double *__restrict__ src, const double *__restrict__ uG,
                                                      double *__restrict__ ybuf) {
@@ -693,11 +788,14 @@ __global__ __launch_bounds__(256) void k_recover_rhs(DevGeom g, const double *__
   const int64_t go = g.g_off[i];
   const int *lcg = g.lcell_global + g.cell_off[i];
   double *ws = sh, *ys = sh + nG, *mc = sh + nG + nc;
-  int ext[3], st[3];
-  for (int d = 0; d < 3; ++d) ext[d] = g.ext[3 * i + d];
+  int ext[3], lo[3], st[3];
+  for (int d = 0; d < 3; ++d) {
+    ext[d] = g.ext[3 * i + d];
+    lo[d] = g.lo[3 * i + d];
+  }
   st[0] = 1; st[1] = ext[0]; st[2] = ext[0] * ext[1];
-  for (int t = tid; t < nG; t += 256) ws[t] = uG[g.Rmap[go + t]];
-  for (int c = tid; c < nc; c += 256) ys[c] = src[lcg[c]];
+  for (int t = tid; t < nG; t += 256) ws[t] = uG ? uG[g.Rmap[go + t]] : 0.0;
+  for (int c = tid; c < nc; c += 256) ys[c] = src ? src[lcg[c]] : 0.0;
   stage_mcoef(nc, lcg, mcoef, mc);
   __syncthreads();
   const int *lg = g.line_g + g.line_off[i];
@@ -707,17 +805,19 @@ __global__ __launch_bounds__(256) void k_recover_rhs(DevGeom g, const double *__
     for (int l = tid; l < lines; l += 256) {
       const int s0 = line_start_s(d, l, ext, st);
       const int tm = lg[lbase + 2 * l], tp = lg[lbase + 2 * l + 1];
-      const double wm = tm >= 0 ? ws[tm] : 0.0, wp = tp >= 0 ? ws[tp] : 0.0;
+      const int s1 = s0 + (n - 1) * st[d];
+      const double wm = tm >= 0 ? ws[tm] : boundary_end_flux(g, d, s0, 0, lo, ext);
+      const double wp = tp >= 0 ? ws[tp] : boundary_end_flux(g, d, s1, 1, lo, ext);
       ys[s0] += wm;
-      ys[s0 + (n - 1) * st[d]] -= wp;
-      if (n >= 2 && (tm >= 0 || tp >= 0)) {
+      ys[s1] -= wp;
+      if (n >= 2 && (wm != 0.0 || wp != 0.0)) {
         const double *m = mc + 3 * s0 + d;
         const int ms = 3 * st[d];
-        double y[MAXLINE + 1];
+        double y[CAP + 1];
         for (int j = 0; j <= n; ++j) y[j] = 0.0;
         y[1] += (m[0] / 6.0) * wm;
         y[n - 1] += (m[(n - 1) * ms] / 6.0) * wp;
-        line_solve_s(n, m, ms, y);
+        line_solve_s<CAP>(n, m, ms, y);
         for (int c = 0; c < n; ++c) {
           double v = 0.0;
           if (c >= 1) v += y[c];
@@ -762,6 +862,7 @@ __global__ __launch_bounds__(256) void k_recover_xgemv(DevGeom g, const double *
 
 // interior fluxes u_I = G(-A_IG w - B_I^T p), line by line, and the pressures
 // p + D p_0
+template <int CAP>
 __global__ __launch_bounds__(256) void k_recover_flux(DevGeom g, const double *__restrict__ mcoef,
                                                       const double *__restrict__ uG, const double *__restrict__ pbuf,
                                                       const double *__restrict__ xp,
@@ -792,15 +893,16 @@ __global__ __launch_bounds__(256) void k_recover_flux(DevGeom g, const double *_
       for (int l = tid; l < lines; l += 256) {
         const int s0 = line_start_s(d, l, ext, st);
         const int tm = lg[lbase + 2 * l], tp = lg[lbase + 2 * l + 1];
-        const double wm = tm >= 0 ? ws[tm] : 0.0, wp = tp >= 0 ? ws[tp] : 0.0;
+        const double wm = tm >= 0 ? ws[tm] : boundary_end_flux(g, d, s0, 0, lo, ext);
+        const double wp = tp >= 0 ? ws[tp] : boundary_end_flux(g, d, s0 + (n - 1) * st[d], 1, lo, ext);
         const double *m = mc + 3 * s0 + d;
         const int ms = 3 * st[d];
-        double y[MAXLINE + 1];
+        double y[CAP + 1];
         y[0] = 0.0;
         for (int j = 1; j <= n - 1; ++j) y[j] = -(ps[s0 + j * st[d]] - ps[s0 + (j - 1) * st[d]]);
         y[1] -= (m[0] / 6.0) * wm;
         y[n - 1] -= (m[(n - 1) * ms] / 6.0) * wp;
-        line_solve_s(n, m, ms, y);
+        line_solve_s<CAP>(n, m, ms, y);
         for (int j = 1; j <= n - 1; ++j) {
           const int lc = s0 + j * st[d];
           int c[3] = {lo[0] + lc % ext[0], lo[1] + (lc / ext[0]) % ext[1], lo[2] + lc / (ext[0] * ext[1])};
@@ -840,10 +942,13 @@ template __global__ void k_symv<double>(DevGeom, const double *, const int64_t *
                                         const double *, double *, CgState *, const double *, int);
 template __global__ void k_symv<float>(DevGeom, const float *, const int64_t *, const double *, double, const double *,
                                        double *, CgState *, const double *, int);
-template __global__ void k_psi_apply<double>(DevGeom, const double *, const int64_t *, const int *, const double *,
-                                             double, const double *, double *, CgState *, const double *, int);
-template __global__ void k_psi_apply<float>(DevGeom, const float *, const int64_t *, const int *, const double *,
-                                            double, const double *, double *, CgState *, const double *, int);
+template __global__ void k_psi_apply<double>(DevGeom, const double *, const int64_t *, const int *, const int *,
+                                             const double *, double, const double *, double *, CgState *,
+                                             const double *, int);
+template __global__ void k_psi_apply<float>(DevGeom, const float *, const int64_t *, const int *, const int *,
+                                            const double *, double, const double *, double *, CgState *,
+                                            const double *, int);
+
 template __global__ void k_psi_correct<double>(DevGeom, DevCoarse, const double *, const int64_t *, const double *,
                                                const double *, double *, const CgState *);
 template __global__ void k_psi_correct<float>(DevGeom, DevCoarse, const float *, const int64_t *, const double *,

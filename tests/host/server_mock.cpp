@@ -13,6 +13,9 @@
 #include <stdio.h>
 
 #include <atomic>
+#include <cstring>
+#include <mutex>
+#include <new>
 #include <chrono>
 #include <cmath>
 #include <cstdlib>
@@ -59,9 +62,40 @@ using sclock_t = std::chrono::steady_clock;
 
 std::atomic<int> g_live{0};   // stand-in handles alive
 
+// The library's device-memory hook (bddc_set_allocator): the stand-in handle
+// takes a few blocks through it at setup and hands them back when destroyed,
+// on whichever server thread does that, as the real handle does.
+struct Allocator {
+  void *(*alloc)(size_t, void *) = nullptr;
+  void (*free)(void *, void *) = nullptr;
+  void *ctx = nullptr;
+};
+std::mutex g_alloc_mu;
+Allocator g_alloc;
+std::atomic<long> g_blocks{0};   // blocks taken through the hook and not yet handed back
+
 struct bddc_problem {
   bddc_problem() { ++g_live; }
-  ~bddc_problem() { --g_live; }
+  ~bddc_problem() {
+    for (auto &b : blocks) {
+      if (b.second.free) b.second.free(b.first, b.second.ctx);
+      else std::free(b.first);
+      --g_blocks;
+    }
+    --g_live;
+  }
+  std::vector<std::pair<void *, Allocator>> blocks;
+  void take(size_t bytes) {
+    Allocator a;
+    {
+      std::lock_guard<std::mutex> lk(g_alloc_mu);
+      a = g_alloc;
+    }
+    void *p = a.alloc ? a.alloc(bytes, a.ctx) : std::malloc(bytes);
+    if (!p) throw std::bad_alloc();
+    blocks.emplace_back(p, a);
+    ++g_blocks;
+  }
   Layout L;
   struct Run {
     bool stop = false;
@@ -136,6 +170,7 @@ bddc_problem *make_problem(const bddc_grid *g, const double *perm, const bddc_pa
     h->peak_bytes = est * (0.8 + 0.2 * u(h->rng));
     h->target = 1 + h->L.N % 4;
     h->ncu = h->L.nF;
+    for (int k = 0; k < 3; ++k) h->take(64 + (size_t)(4096 * u(h->rng)));
     sleep_us(3000.0 * u(h->rng));
     h->stats.t_setup_ms = 1.0;
   } catch (...) {
@@ -201,6 +236,20 @@ int solve_finish(bddc_problem *h) {
 }  // namespace
 
 #include "../../paper_1901_02090_amd/csrc/server.hpp"
+
+extern "C" {
+int bddc_set_allocator(void *(*alloc)(size_t, void *), void (*free_fn)(void *, void *), void *ctx) {
+  if ((alloc == nullptr) != (free_fn == nullptr)) return BDDC_EINVAL;
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  g_alloc = Allocator{alloc, free_fn, ctx};
+  return BDDC_OK;
+}
+long mock_live_handles(void) { return g_live.load(); }
+long mock_live_blocks(void) { return g_blocks.load(); }
+const char *bddc_last_error(void) { return g_last_error.c_str(); }
+}
+
+#ifndef SERVER_MOCK_LIB
 
 struct Req {
   bddc_grid g{};
@@ -359,3 +408,4 @@ int main(int argc, char **argv) {
          ss.p99_ms);
   return bad ? 1 : 0;
 }
+#endif  // SERVER_MOCK_LIB

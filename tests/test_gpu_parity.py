@@ -176,20 +176,30 @@ def test_layer_solve_fp64(tau):
 
 
 def test_layer_solve_fp64_nonadaptive():
-    """tau = inf: kappa ~ 2e4 and several hundred CG steps.
+    """tau = inf: kappa ~ 2e4 and about 800 CG steps to rtol 1e-10.
 
-    Two FP64 CG runs of that length lose orthogonality differently, so the
-    iteration counts agree only to a few percent; both solutions are compared
-    with the monolithic direct solve, to the accuracy rtol * kappa allows.
+    Two FP64 CG runs of that length lose orthogonality differently, and near
+    the threshold the residual falls by only a factor of three in 40 steps, so
+    the stopping step moves with the order of the rounding (the oracle's own
+    count went from 825 to 828 when only the storage of its B_0 products
+    changed; the GPU stops at 786).  The count is therefore checked against
+    the oracle's residual
+    curve: the GPU stops between the oracle's first steps below 4 rtol and
+    below rtol / 4.  Both solutions are compared with the monolithic direct
+    solve, to the accuracy rtol * kappa allows.
     """
     Solver = _gpu()
     pr = W.layer_60x220(0, tau=math.inf)
     s = Solver(pr.n, pr.h, pr.perm, pr.cuts)
     o = _oracle(pr, math.inf)
-    u, p = s.solve(pr.source, rtol=1e-10)
-    ref = o.solve(pr.source, rtol=1e-10, maxit=5000)
+    rtol = 1e-10
+    u, p = s.solve(pr.source, rtol=rtol)
+    ref = o.solve(pr.source, rtol=rtol / 4, maxit=5000)
     st = s.stats()
-    assert abs(st["it"] - ref["it"]) <= 0.05 * ref["it"]
+    h = ref["history"]
+    lo, hi = int(np.argmax(h <= 4 * rtol)), int(np.argmax(h <= rtol / 4))
+    print(f"layer tau=inf: GPU stops at {st['it']}, oracle below 4 rtol at {lo}, below rtol/4 at {hi}", flush=True)
+    assert 0 < lo <= st["it"] <= hi
     g = rt0.Grid(pr.n, pr.h)
     ue, pe = rt0.direct_solve(g, pr.perm, pr.source)
     pe = rt0.remove_mean(g, pe)
@@ -383,33 +393,6 @@ def test_graph_replays_match_eager(precision):
     s.close()
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_coarse_dataflow_matches_level_sweeps(precision):
-    """The single-launch dataflow coarse sweep and the level-by-level sweeps are bit-identical.
-
-    Both run the same task bodies on the same data; only the scheduling
-    differs.  Several solves in a row also exercise the counter reset.
-    """
-    Solver = _gpu()
-    pr = W.layer_60x220(0, tau=10.0)
-    s_flow = Solver(pr.n, pr.h, pr.perm, pr.cuts, tau=10.0, precision=precision, coarse_dataflow=True)
-    s_lvl = Solver(pr.n, pr.h, pr.perm, pr.cuts, tau=10.0, precision=precision, coarse_top=-1)
-    assert s_flow.stats()["coarse_fronts"] == s_lvl.stats()["coarse_fronts"] > 1
-    assert s_flow.stats()["coarse_dense"] == 0
-    rng = np.random.default_rng(11)
-    xu = rng.standard_normal(s_flow.n_gamma)
-    zf, pf = s_flow.apply_precond(xu)
-    zl, pl = s_lvl.apply_precond(xu)
-    assert np.array_equal(zf, zl) and np.array_equal(pf, pl)
-    ul, ql = s_lvl.solve(pr.source, rtol=1e-8)
-    for _ in range(3):
-        uf, qf = s_flow.solve(pr.source, rtol=1e-8)
-        assert s_flow.stats()["it"] == s_lvl.stats()["it"]
-        assert np.array_equal(uf, ul) and np.array_equal(qf, ql)
-    s_flow.close()
-    s_lvl.close()
-
-
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_zero_source_gives_zero_solution(prec):
     """Degenerate source: with F = 0 the flux and the zero-mean pressure vanish, the CG stops before its first
@@ -432,3 +415,34 @@ def test_zero_source_gives_zero_solution(prec):
     u2, p2 = s2.solve(pr.source, rtol=1e-8)
     s2.close()
     assert np.array_equal(u1, u2) and np.array_equal(p1, p2)
+
+
+def test_table2_h30_long_lines():
+    """Table 2, row k = 1, H/h = 30 (60 x 220 cells of 20 x 10 ft, 2 x 7 boxes, six of them
+    30 cells long in y and one 40): subdomain extents above 32 cells run the long-line instances
+    of the line kernels.  The GPU must reproduce the oracle's iteration count and condition
+    estimate, and the paper's printed 11 iterations and kappa 2.790 as the oracle pin does
+    (+-1, 0.1 %); the solution at a tight tolerance equals the direct solve."""
+    Solver = _gpu()
+    import json
+    import os
+    golden = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_tables.json")))
+    row = golden["homogeneous_k1"][0]
+    cuts = W.regular_cuts(row["n"], row["sub"])
+    assert max(np.diff(cuts[1])) > 32
+    pr = W.homogeneous(row["n"], row["h"], cuts)
+    o = ob.BDDC(rt0.Grid(pr.n, pr.h), pr.perm, pr.cuts)
+    ref = o.solve(pr.source, rtol=row["rtol"])
+    s = Solver(pr.n, pr.h, pr.perm, pr.cuts)
+    u, p = s.solve(pr.source, rtol=row["rtol"])
+    st = s.stats()
+    print(f"H/h=30: it {st['it']} (oracle {ref['it']}, paper {row['it']}), kappa {st['kappa']:.4f} "
+          f"(oracle {ref['kappa']:.4f}, paper {row['kappa']})", flush=True)
+    assert st["it"] == ref["it"]
+    assert abs(st["kappa"] - ref["kappa"]) <= 1e-6 * ref["kappa"]
+    assert abs(st["it"] - row["it"]) <= 1 and abs(st["kappa"] - row["kappa"]) <= 1e-3 * row["kappa"]
+    u, p = s.solve(pr.source, rtol=1e-11)
+    s.close()
+    g = rt0.Grid(pr.n, pr.h)
+    ue, pe = rt0.direct_solve(g, pr.perm, pr.source)
+    assert _relerr(u, ue) <= 1e-9 and _relerr(p, rt0.remove_mean(g, pe)) <= 1e-9

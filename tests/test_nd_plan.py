@@ -204,8 +204,8 @@ def check_tasks(P):
 
 
 def sweep(P, FR, BC, sg, b, K=None):
-    """k_nd_flow serialised: the task list in index order (also what the
-    level-by-level kernels compute).  With a dense top block (P["top"] < H)
+    """The sweep tasks serialised in index order (what the level-by-level
+    kernels compute).  With a dense top block (P["top"] < H)
     the tasks of the top levels are replaced by the gather of t_t and a dense
     solve with the Schur complement of K on the top dofs."""
     nfr, nk, H = P["nfr"], P["nk"], P["H"]

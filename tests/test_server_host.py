@@ -14,6 +14,7 @@ import math
 import os
 import shutil
 import subprocess
+import sys
 
 import pytest
 
@@ -75,3 +76,42 @@ def test_server_scheduler_under_sanitizers(request, geometry, kind, cap):
     exe = request.getfixturevalue(kind)
     _run(exe, geometry, 4, 2, cap, 1, 0)          # serve all, check every ticket
     _run(exe, geometry, 3, 1, cap, 2, 1)          # destroy with the queue full
+
+
+def _build_lib(tmp_path_factory, flags, name):
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("g++ not available")
+    out = str(tmp_path_factory.mktemp("srvlib") / name)
+    subprocess.run([gxx, "-std=c++17", "-O1", "-g", "-pthread", "-shared", "-fPIC", "-DSERVER_MOCK_LIB",
+                    "-Wno-subobject-linkage"] + flags + ["-o", out, SRC], check=True, capture_output=True)
+    return out
+
+
+@pytest.mark.parametrize("kind", ["plain", "asan"])
+def test_server_with_python_allocator_callbacks(tmp_path_factory, kind):
+    """The device-memory hook set to Python callbacks (as a framework's caching
+    allocator is): setup workers and the driver thread allocate and free
+    through ctypes from native threads, with allocations refused now and then
+    and servers destroyed with requests in flight.  Every request must return
+    its own outputs or an out-of-memory error, every block must be handed
+    back, and AddressSanitizer (preloaded into the Python process together with
+    the C++ runtime it intercepts) must stay silent."""
+    env = dict(os.environ)
+    if kind == "asan":
+        lib = _build_lib(tmp_path_factory, ["-fsanitize=address,undefined", "-fno-sanitize-recover=all"], "m_asan.so")
+        gxx = shutil.which("g++")
+        pre = [subprocess.run([gxx, f"-print-file-name={n}"], capture_output=True, text=True).stdout.strip()
+               for n in ("libasan.so", "libstdc++.so")]
+        env["LD_PRELOAD"] = " ".join(pre)
+        env["ASAN_OPTIONS"] = "detect_leaks=0"
+    else:
+        lib = _build_lib(tmp_path_factory, [], "m.so")
+    driver = os.path.join(HERE, "host", "server_callbacks_driver.py")
+    for fail_every in (0, 5):
+        res = subprocess.run([sys.executable, driver, lib, "3", str(fail_every)], capture_output=True, text=True,
+                             timeout=600, env=env)
+        out = res.stdout + res.stderr
+        assert res.returncode == 0, out[-4000:]
+        assert "ERROR: AddressSanitizer" not in out and "runtime error" not in out, out[-4000:]
+        assert out.strip().splitlines()[-1].startswith("OK"), out[-2000:]
