@@ -124,22 +124,26 @@ __device__ __forceinline__ void bwd_task(const int4 d0, const int4 d1, const int
 }
 
 // Level-synchronous sweeps: the tasks [t0, t0 + gridDim.x) of one level, one
-// per workgroup; kernel boundaries order the levels.
+// per workgroup; kernel boundaries order the levels.  The task descriptor is
+// read before the CG stop flag, so that the two loads are in flight together
+// (a level is a few dependent memory round trips long).
 __global__ __launch_bounds__(256) void k_nd_fwd(int t0, DevSweep sw, const double *__restrict__ FR,
                                                 const double *__restrict__ b, double *S0, double *S1,
                                                 double *__restrict__ z, const int *done) {
-  if (done && *done) return;
   const int4 *td = sw.task + 4 * (int64_t)(t0 + blockIdx.x);
-  fwd_task(td[0], td[1], td[2], sw, FR, b, S0, S1, z);
+  const int4 d0 = td[0], d1 = td[1], d2 = td[2];
+  if (done && *done) return;
+  fwd_task(d0, d1, d2, sw, FR, b, S0, S1, z);
 }
 
 __global__ __launch_bounds__(256) void k_nd_bwd(int t0, DevSweep sw, const double *__restrict__ BC,
                                                 const double *__restrict__ z, const double *__restrict__ sg,
                                                 double *XB, double *__restrict__ x, double *__restrict__ b,
                                                 const int *done) {
-  if (done && *done) return;
   const int4 *td = sw.task + 4 * (int64_t)(t0 + blockIdx.x);
-  bwd_task(td[0], td[1], td[2], sw, BC, z, sg, XB, x, b);
+  const int4 d0 = td[0], d1 = td[1], d2 = td[2];
+  if (done && *done) return;
+  bwd_task(d0, d1, d2, sw, BC, z, sg, XB, x, b);
 }
 
 // ---- dense top block (nd_dense_top) ---------------------------------------------
@@ -149,11 +153,12 @@ __global__ __launch_bounds__(256) void k_top_gather(int nt, int d0, const int *_
                                                     const int *__restrict__ tg, const double *__restrict__ b,
                                                     const double *__restrict__ S0, const double *__restrict__ S1,
                                                     double *__restrict__ tt, const int *done) {
-  if (done && *done) return;
   const int j = blockIdx.x * 256 + threadIdx.x;
   if (j >= nt) return;
   double v = b[d0 + j];
-  for (int q = tg_off[j]; q < tg_off[j + 1]; ++q) {
+  const int q0 = tg_off[j], q1 = tg_off[j + 1];
+  if (done && *done) return;
+  for (int q = q0; q < q1; ++q) {
     const int p = tg[q];
     v += S0[p] + S1[p];
   }
@@ -177,10 +182,10 @@ __global__ __launch_bounds__(TOP_THREADS) void k_top_gemv(int nt, int ld, const 
                                                           const int *__restrict__ xsc, double *__restrict__ XB,
                                                           double *__restrict__ x, double *__restrict__ b,
                                                           const int *done) {
-  if (done && *done) return;
   extern __shared__ double tl[];
   for (int j = threadIdx.x; j < ld; j += TOP_THREADS) tl[j] = j < nt ? tt[j] : 0.0;
   __syncthreads();
+  if (done && *done) return;
   const int lane = threadIdx.x & 63;
   const int r0 = blockIdx.x * TOP_ROWS_PER_WG + 2 * (threadIdx.x >> 6);
   if (r0 >= nt) return;

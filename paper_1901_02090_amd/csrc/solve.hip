@@ -347,11 +347,11 @@ __global__ __launch_bounds__(256) void k_psi_correct(DevGeom g, DevCoarse cs, co
   constexpr int RB = 64 * VW;        // rows per block
   __shared__ double al[1024];
   __shared__ double part[4 * RB];
-  if (st && st->done) return;
   const int i = blockIdx.x;
   const int n = g.nG[i];
   const int64_t go = g.g_off[i];
   const int c0 = cs.sub_coff[i], nci = cs.sub_coff[i + 1] - c0;
+  if (st && st->done) return;   // read beside the subdomain's sizes
   for (int c = threadIdx.x; c < nci; c += 256) al[c] = csol[cs.sub_cmap[c0 + c]];
   __syncthreads();
   const TS *P = Psi + psi_off[i];
