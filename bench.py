@@ -439,7 +439,7 @@ def main():
                      "tune_ms": st["t_tune_ms"], "coarse_ms_per_width": st["tune_coarse_ms"],
                      "precond_ms_per_t_grid": st["tune_precond_ms"],
                      "note": "coarse sweeps timed with lane-group widths (8,32) (12,48) (24,96) (48,192); "
-                             "preconditioner with T^i on n_cu, 2 n_cu, 4 n_cu, N workgroups"},
+                             "preconditioner with T^i on n_cu/2, n_cu, 2 n_cu, N workgroups; both timed from graph replays"},
         "fp64": {"value": args.steps / r64["total_s"], "unit": "solves/s",
                  "ms_per_step": r64["total_s"] / args.steps * 1e3,
                  "latency_ms": {"p50": float(np.percentile(r64["lat"] * 1e3, 50)),

@@ -162,7 +162,7 @@ typedef struct {
   double t_tune_ms;         /* wall time of the autotuner (0: not run)           */
   double tune_coarse_ms[4]; /* coarse solve with widths (8,32) (12,48) (24,96)
                                (48,192)                                         */
-  double tune_precond_ms[4];/* preconditioner with T^i on n_cu, 2 n_cu, 4 n_cu, N
+  double tune_precond_ms[4];/* preconditioner with T^i on n_cu/2, n_cu, 2 n_cu, N
                                workgroups (n_cu: compute units)                 */
 } bddc_stats_t;
 
@@ -308,7 +308,9 @@ int bddc_set_allocator(void *(*alloc)(size_t, void *), void (*free)(void *, void
  * Algorithm "BDDC preconditioner" as one CG iteration applies it: coarse
  * right-hand sides Psi^{iT} r^i, the corrections T^i r^i beside the coarse
  * solve, the coarse correction Psi^i alpha and the weighted averaging; one
- * "launch" is that sequence of kernels on two streams).
+ * "launch" is that sequence of kernels on two streams, timed as the solve
+ * runs it: eight applies captured into a HIP graph on the handle's own
+ * stream, the graph replayed ceil(reps / 8) times on the handle's stream).
  * avg_ms receives the mean duration of one launch, bytes the algorithmic HBM
  * bytes of one launch (operator entries read once, vectors gathered and
  * written once).  Call after a bddc_solve. */

@@ -540,7 +540,7 @@ __device__ __forceinline__ double boundary_end_flux(const DevGeom &g, int d, int
 }
 
 // The line's cell coefficients are m[0], m[ms], ..., m[(n-1) ms] (staged in
-// LDS by the caller).
+// LDS by the caller, or read in place; see line_coef).
 template <int CAP>
 __device__ __forceinline__ void line_solve_s(int n, const double *m, int ms, double *y) {
   double cp[CAP];
@@ -566,6 +566,21 @@ __device__ __forceinline__ void stage_mcoef(int nc, const int *__restrict__ lcg,
     const int c = k / 3;
     mc[k] = mcoef[(int64_t)lcg[c] * 3 + (k - 3 * c)];
   }
+}
+
+// Coefficients of the line of cells that starts at local cell s0 along d:
+// from the staged copy mc (local strides), or, in the kernels' unstaged form
+// for subdomains whose staged copy does not fit in LDS, in place in the
+// global array (strides of the lexicographic global cell numbering).
+template <bool STAGED>
+__device__ __forceinline__ const double *line_coef(const DevGeom &g, const double *mc, const double *mcoef,
+                                                   const int *lcg, int s0, int d, const int *st, int &ms) {
+  if (STAGED) {
+    ms = 3 * st[d];
+    return mc + 3 * s0 + d;
+  }
+  ms = 3 * (d == 0 ? 1 : (d == 1 ? g.n[0] : g.n[0] * g.n[1]));
+  return mcoef + 3 * (int64_t)lcg[s0] + d;
 }
 
 // Block GEMV y = X v, X n x n column major, v and y in LDS.  A thread owns two
@@ -602,31 +617,33 @@ __device__ __forceinline__ void block_gemv(int n, const double *__restrict__ X, 
 
 // h^i = H^{iT} X^i F^i: the source-dependent part of the reduced right-hand
 // side f* (zero in subdomains without source).
-template <int CAP>
+// LDS: ys = X F (nc), then F (nc), whose space the staged coefficients (3 nc)
+// take over once the product is formed.
+template <int CAP, bool STAGED>
 __global__ __launch_bounds__(256) void k_source_term(DevGeom g, const double *__restrict__ mcoef,
                                                      const double *__restrict__ Xmat, const int64_t *__restrict__ Xoff,
                                                      const double *__restrict__ src, double *__restrict__ hloc) {
   extern __shared__ double sh[];
-  __shared__ int any;
   const int i = blockIdx.x, tid = threadIdx.x;
   const int nc = g.nc[i], nG = g.nG[i];
   const int64_t go = g.g_off[i];
   const int *lcg = g.lcell_global + g.cell_off[i];
-  double *Fs = sh, *ys = sh + nc, *mc = sh + 2 * nc;
-  if (tid == 0) any = 0;
-  __syncthreads();
+  double *ys = sh, *Fs = sh + nc, *mc = sh + nc;
+  int any = 0;
   for (int c = tid; c < nc; c += 256) {
     const double v = -src[lcg[c]];
     Fs[c] = v;
-    if (v != 0.0) any = 1;
+    any |= v != 0.0;
   }
-  __syncthreads();
-  if (!any) {
+  if (!__syncthreads_or(any)) {
     for (int t = tid; t < nG; t += 256) hloc[go + t] = 0.0;
     return;
   }
-  stage_mcoef(nc, lcg, mcoef, mc);
   block_gemv(nc, Xmat + Xoff[i], Fs, ys);   // ends with a barrier
+  if (STAGED) {
+    stage_mcoef(nc, lcg, mcoef, mc);
+    __syncthreads();
+  }
   int ext[3], st[3];
   for (int d = 0; d < 3; ++d) ext[d] = g.ext[3 * i + d];
   st[0] = 1; st[1] = ext[0]; st[2] = ext[0] * ext[1];
@@ -636,8 +653,8 @@ __global__ __launch_bounds__(256) void k_source_term(DevGeom g, const double *__
     const int n = ext[d];
     const int cd = (lc / st[d]) % n;
     const int s0 = lc - cd * st[d];
-    const double *m = mc + 3 * s0 + d;
-    const int ms = 3 * st[d];
+    int ms;
+    const double *m = line_coef<STAGED>(g, mc, mcoef, lcg, s0, d, st, ms);
     double y[CAP + 1];
     const int eidx = end ? n - 1 : 0;
     double v = (end ? -1.0 : 1.0) * ys[s0 + eidx * st[d]];
@@ -672,7 +689,7 @@ __global__ void k_fstar(DevGeom g, const double *__restrict__ yloc, const double
 // interface dof t the load -(A_tb - A_tI A_II^{-1} A_Ib) g of the line through
 // it whose other end is on the boundary.  hb: per cell (global order), the
 // first; sb: per local interface dof, the second.  One block per subdomain.
-template <int CAP>
+template <int CAP, bool STAGED>
 __global__ __launch_bounds__(256) void k_bflux_load(DevGeom g, const double *__restrict__ mcoef,
                                                     double *__restrict__ hb, double *__restrict__ sb) {
   extern __shared__ double sh[];
@@ -688,7 +705,7 @@ __global__ __launch_bounds__(256) void k_bflux_load(DevGeom g, const double *__r
   }
   st[0] = 1; st[1] = ext[0]; st[2] = ext[0] * ext[1];
   for (int c = tid; c < nc; c += 256) ys[c] = 0.0;
-  stage_mcoef(nc, lcg, mcoef, mc);
+  if (STAGED) stage_mcoef(nc, lcg, mcoef, mc);
   __syncthreads();
   const int *lg = g.line_g + g.line_off[i];
   int64_t lbase = 0;
@@ -701,8 +718,8 @@ __global__ __launch_bounds__(256) void k_bflux_load(DevGeom g, const double *__r
       ys[s0] += gm;
       ys[s1] -= gp;
       if (n >= 2 && (gm != 0.0 || gp != 0.0)) {
-        const double *m = mc + 3 * s0 + d;
-        const int ms = 3 * st[d];
+        int ms;
+        const double *m = line_coef<STAGED>(g, mc, mcoef, lcg, s0, d, st, ms);
         double y[CAP + 1];
         for (int j = 0; j <= n; ++j) y[j] = 0.0;
         y[1] += (m[0] / 6.0) * gm;
@@ -731,8 +748,8 @@ __global__ __launch_bounds__(256) void k_bflux_load(DevGeom g, const double *__r
     double v = 0.0;
     if (other_on_boundary) {
       const double gb = end ? boundary_end_flux(g, d, s0, 0, lo, ext) : boundary_end_flux(g, d, s1, 1, lo, ext);
-      const double *m = mc + 3 * s0 + d;
-      const int ms = 3 * st[d];
+      int ms;
+      const double *m = line_coef<STAGED>(g, mc, mcoef, lcg, s0, d, st, ms);
       if (gb != 0.0) {
         if (n == 1) {
           v = -(m[0] / 6.0) * gb;                  // -A_tb g: both faces of one cell
@@ -778,7 +795,7 @@ __global__ __launch_bounds__(256) void k_b0(DevGeom g, const double *__restrict_
 // local cell, in the subdomains' local cell order.
 // ---------------------------------------------------------------------------
 // y = H w - F = H w + source, with w = R_i u_G
-template <int CAP>
+template <int CAP, bool STAGED>
 __global__ __launch_bounds__(256) void k_recover_rhs(DevGeom g, const double *__restrict__ mcoef,
                                                      const double *__restrict__ src, const double *__restrict__ uG,
                                                      double *__restrict__ ybuf) {
@@ -796,7 +813,7 @@ __global__ __launch_bounds__(256) void k_recover_rhs(DevGeom g, const double *__
   st[0] = 1; st[1] = ext[0]; st[2] = ext[0] * ext[1];
   for (int t = tid; t < nG; t += 256) ws[t] = uG ? uG[g.Rmap[go + t]] : 0.0;
   for (int c = tid; c < nc; c += 256) ys[c] = src ? src[lcg[c]] : 0.0;
-  stage_mcoef(nc, lcg, mcoef, mc);
+  if (STAGED) stage_mcoef(nc, lcg, mcoef, mc);
   __syncthreads();
   const int *lg = g.line_g + g.line_off[i];
   int64_t lbase = 0;
@@ -811,8 +828,8 @@ __global__ __launch_bounds__(256) void k_recover_rhs(DevGeom g, const double *__
       ys[s0] += wm;
       ys[s1] -= wp;
       if (n >= 2 && (wm != 0.0 || wp != 0.0)) {
-        const double *m = mc + 3 * s0 + d;
-        const int ms = 3 * st[d];
+        int ms;
+        const double *m = line_coef<STAGED>(g, mc, mcoef, lcg, s0, d, st, ms);
         double y[CAP + 1];
         for (int j = 0; j <= n; ++j) y[j] = 0.0;
         y[1] += (m[0] / 6.0) * wm;
@@ -862,7 +879,7 @@ __global__ __launch_bounds__(256) void k_recover_xgemv(DevGeom g, const double *
 
 // interior fluxes u_I = G(-A_IG w - B_I^T p), line by line, and the pressures
 // p + D p_0
-template <int CAP>
+template <int CAP, bool STAGED>
 __global__ __launch_bounds__(256) void k_recover_flux(DevGeom g, const double *__restrict__ mcoef,
                                                       const double *__restrict__ uG, const double *__restrict__ pbuf,
                                                       const double *__restrict__ xp,
@@ -883,7 +900,7 @@ __global__ __launch_bounds__(256) void k_recover_flux(DevGeom g, const double *_
   const double *pi = pbuf + g.cell_off[i];
   for (int t = tid; t < nG; t += 256) ws[t] = uG[g.Rmap[go + t]];
   for (int c = tid; c < nc; c += 256) ps[c] = pi[c];
-  stage_mcoef(nc, lcg, mcoef, mc);
+  if (STAGED) stage_mcoef(nc, lcg, mcoef, mc);
   __syncthreads();
   const int *lg = g.line_g + g.line_off[i];
   int64_t lbase = 0;
@@ -895,8 +912,8 @@ __global__ __launch_bounds__(256) void k_recover_flux(DevGeom g, const double *_
         const int tm = lg[lbase + 2 * l], tp = lg[lbase + 2 * l + 1];
         const double wm = tm >= 0 ? ws[tm] : boundary_end_flux(g, d, s0, 0, lo, ext);
         const double wp = tp >= 0 ? ws[tp] : boundary_end_flux(g, d, s0 + (n - 1) * st[d], 1, lo, ext);
-        const double *m = mc + 3 * s0 + d;
-        const int ms = 3 * st[d];
+        int ms;
+        const double *m = line_coef<STAGED>(g, mc, mcoef, lcg, s0, d, st, ms);
         double y[CAP + 1];
         y[0] = 0.0;
         for (int j = 1; j <= n - 1; ++j) y[j] = -(ps[s0 + j * st[d]] - ps[s0 + (j - 1) * st[d]]);

@@ -12,6 +12,11 @@ flux dofs, faces of up to 256) in one batch, tau = 5.
   of the global RT0 system (oracle matrices) for three of them, mixed against
   FP64 for all 32, and S^i of the largest box against the oracle on a cutout
   holding the box and its neighbours.
+* Boxes at the LDS limits of the line kernels (source term, boundary loads,
+  post-correction): 16^3-cell boxes, whose cell coefficients are still staged
+  in LDS beside the kernels' vectors, and 20^3-cell boxes, where they no longer
+  fit and are read in place; with wells and prescribed boundary fluxes, against
+  the oracle's monolithic direct solve.
 """
 import numpy as np
 import pytest
@@ -154,3 +159,36 @@ def test_uneven_full_size_largest_box_schur(full_batch):
     _say(f"largest box {i}: n_gamma {Sg.shape[0]}, relerr {_relerr(Sg, So):.1e}")
     assert Sg.shape == So.shape and Sg.shape[0] > 500
     assert _relerr(Sg, So) <= 1e-11
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-8), ("mixed", 1e-6)])
+@pytest.mark.parametrize("case", [
+    ((48, 16, 16), 16, TAU),           # 4,096 cells: coefficients staged in LDS
+    ((40, 20, 20), 20, float("inf")),  # 8,000 cells: read in place (faces of 400 dofs: no adaptive rows)
+], ids=["16cube_staged", "20cube_in_place"])
+def test_boxes_at_the_lds_limit(case, prec, tol):
+    Solver = _gpu()
+    n, b, tau = case
+    full = _field()
+    perm = _sub_field(full, (5, 100, 40), n)
+    cuts = [np.arange(0, n[d] + 1, b) for d in range(3)]
+    g = rt0.Grid(n, full.h)
+    rng = np.random.default_rng(7)
+    bnd = g.boundary_faces()
+    bf = np.where(bnd, rng.standard_normal(g.nfaces), 0.0)
+    dirs, coords = g.face_dir_coords()
+    hi = coords[np.arange(g.nfaces), dirs] > 0
+    outflow = np.sum(np.where(bnd & hi, bf, 0.0)) - np.sum(np.where(bnd & ~hi, bf, 0.0))
+    src = W.seeded_wells(n, rng)
+    src[0] += outflow
+    ue, pe = rt0.direct_solve(g, perm, src, bflux=bf)
+    pe = rt0.remove_mean(g, pe)
+    s = Solver(n, full.h, perm, cuts, tau=tau, precision=prec, bflux=bf)
+    try:
+        u, p = s.solve(src, rtol=1e-11)
+        st = s.stats()
+    finally:
+        s.close()
+    _say(f"{b}^3 boxes {prec}: it {st['it']}, flux {_relerr(u, ue):.1e}, pressure {_relerr(p, pe):.1e}")
+    assert st["converged"] == 1
+    assert _relerr(u, ue) <= tol and _relerr(p, pe) <= tol
