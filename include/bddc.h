@@ -164,6 +164,10 @@ typedef struct {
                                (48,192)                                         */
   double tune_precond_ms[4];/* preconditioner with T^i on n_cu/2, n_cu, 2 n_cu, N
                                workgroups (n_cu: compute units)                 */
+  double bytes_prec_block;  /* algorithmic bytes of one block preconditioner
+                               apply (16 columns; 0 before a block solve)      */
+  double flops_block_local; /* 2 * 16 * sum n_Gamma^i^2: the flops of one block
+                               product with S^i or T^i (16 columns)             */
 } bddc_stats_t;
 
 /*
@@ -276,6 +280,29 @@ int bddc_apply(bddc_handle h, int32_t which, const double *x_u, const double *x_
 int bddc_solve_batch(bddc_handle h, int32_t nrhs, const double *rhs, double rtol, double *flux, double *pressure,
                      uint32_t flags, int32_t *iterations);
 
+/* Several sources solved together (Algorithm "BDDC method" for each): steps
+ * 1-2, the reduced right-hand side and the post-correction run source by
+ * source, and step 3's CG runs for blocks of up to 16 sources at once.  Each
+ * source keeps its own CG scalars and stopping test, so it takes the
+ * iterations of its single solve, while every block iteration streams S^i,
+ * T^i, Psi^i, the swept coarse factor and S_t^{-1} once for all 16 columns:
+ * the local operators and bases as 16 x 16 tiles on the FP64 matrix cores
+ * against the block's columns (a partial block is padded with zero sources,
+ * which stop at once).  Both forms stream the FP64 copies of T^i and Psi^i
+ * (resident in both): widened FP32 tiles loaded slower on the matrix cores.
+ * The results equal those of bddc_solve to rounding (the block kernels add in
+ * another order; in the mixed form, also the FP64 operators).  Arguments as bddc_solve_batch
+ * (BDDC_DEVICE_PTRS and BDDC_EAGER apply; the step flags are refused with
+ * BDDC_EINVAL).  The first call allocates the block's vectors (16 copies of
+ * the interface, local and coarse vectors, about 2 GB on the 60x220x85
+ * reservoir).  BDDC_EINVAL too if a subdomain's interface (over 1,232 dofs)
+ * or coarse basis does not fit the block kernels' LDS.  Returns BDDC_OK,
+ * BDDC_ENOCONV if a source reached max_it, BDDC_EBREAKDOWN if a source's CG
+ * broke down (all sources are still solved), or the first error.  Statistics
+ * are those of the last source. */
+int bddc_solve_block(bddc_handle h, int32_t nrhs, const double *rhs, double rtol, double *flux, double *pressure,
+                     uint32_t flags, int32_t *iterations);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, serving loops and harnesses that forbid hipMalloc): bddc_solve with
  * BDDC_DEVICE_PTRS | BDDC_EAGER semantics that calls no hipMalloc, hipFree or
@@ -317,6 +344,16 @@ int bddc_set_allocator(void *(*alloc)(size_t, void *), void (*free)(void *, void
 #define BDDC_K_SCHUR_APPLY   1
 #define BDDC_K_PRECOND_APPLY 2
 #define BDDC_K_PRECOND_FULL  3
+/* The block CG's kernels (after a bddc_solve_block; BDDC_EINVAL before), on
+ * the last block's vectors: the local Schur products S^i for 16 columns
+ * (BDDC_K_BLOCK_SCHUR), the local corrections T^i for 16 columns
+ * (BDDC_K_BLOCK_PRECOND_APPLY), and the whole block preconditioner as a
+ * graph replay (BDDC_K_BLOCK_PRECOND_FULL).  bytes: each operator entry once,
+ * the gather map, 16 gathered and 16 written values per local dof; the
+ * matrix-core flops of the first two are in bddc_stats_t.flops_block_local. */
+#define BDDC_K_BLOCK_SCHUR         4
+#define BDDC_K_BLOCK_PRECOND_APPLY 5
+#define BDDC_K_BLOCK_PRECOND_FULL  6
 int bddc_time_kernel(bddc_handle h, int32_t which, int32_t reps, double *avg_ms, double *bytes);
 
 /* Device bytes a problem may hold at the peak of its setup (the figure the

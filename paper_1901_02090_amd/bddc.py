@@ -25,10 +25,11 @@ OP_SYSTEM, OP_PRECOND = 1, 2
 
 EXPORTED = ["bddc_setup", "bddc_solve", "bddc_stats", "bddc_set_stream", "bddc_destroy", "bddc_last_error",
             "bddc_sizes", "bddc_export", "bddc_apply", "bddc_time_kernel", "bddc_estimate_bytes",
-            "bddc_solve_batch", "bddc_solve_noalloc", "bddc_set_allocator",
+            "bddc_solve_batch", "bddc_solve_block", "bddc_solve_noalloc", "bddc_set_allocator",
             "bddc_server_create", "bddc_server_submit", "bddc_server_poll", "bddc_server_stats",
             "bddc_server_destroy"]
 K_SCHUR_APPLY, K_PRECOND_APPLY, K_PRECOND_FULL = 1, 2, 3
+K_BLOCK_SCHUR, K_BLOCK_PRECOND_APPLY, K_BLOCK_PRECOND_FULL = 4, 5, 6
 
 
 class Grid(C.Structure):
@@ -55,7 +56,8 @@ class Stats(C.Structure):
                 ("t_pcg_ms", C.c_double), ("bytes_per_iter", C.c_double), ("bytes_prec", C.c_double),
                 ("device_bytes", C.c_double), ("sweep_wide4", C.c_int32), ("sweep_wide16", C.c_int32),
                 ("t_workgroups", C.c_int32), ("t_tune_ms", C.c_double), ("tune_coarse_ms", C.c_double * 4),
-                ("tune_precond_ms", C.c_double * 4)]
+                ("tune_precond_ms", C.c_double * 4), ("bytes_prec_block", C.c_double),
+                ("flops_block_local", C.c_double)]
 
 
 class ServerOptions(C.Structure):
@@ -145,6 +147,8 @@ def load_library(path=LIB_PATH):
     lib.bddc_time_kernel.restype = C.c_int
     lib.bddc_solve_batch.argtypes = [P, C.c_int32, P, C.c_double, P, P, C.c_uint32, C.POINTER(C.c_int32)]
     lib.bddc_solve_batch.restype = C.c_int
+    lib.bddc_solve_block.argtypes = [P, C.c_int32, P, C.c_double, P, P, C.c_uint32, C.POINTER(C.c_int32)]
+    lib.bddc_solve_block.restype = C.c_int
     lib.bddc_solve_noalloc.argtypes = [P, P, C.c_double, P, P]
     lib.bddc_solve_noalloc.restype = C.c_int
     lib.bddc_set_allocator.argtypes = [ALLOC_FN, FREE_FN, C.c_void_p]
@@ -285,6 +289,28 @@ class Solver:
                                        its)
         _check(self.lib, rc, allow=(BDDC_ENOCONV,))
         return flux, pres, np.array(its[:k], dtype=np.int32)
+
+    def solve_block(self, sources, rtol=1e-8, eager=False):
+        """Solve several sources ([k, n_cells]) with the block CG (blocks of 16
+        sources per iteration); returns (flux, pressure, iterations)."""
+        src = np.ascontiguousarray(sources, dtype=np.float64).reshape(-1, self.n_cells)
+        k = src.shape[0]
+        flux = np.empty((k, self.n_faces_all))
+        pres = np.empty((k, self.n_cells))
+        its = (C.c_int32 * max(k, 1))()
+        rc = self.lib.bddc_solve_block(self.h, k, src.ctypes.data, float(rtol), flux.ctypes.data, pres.ctypes.data,
+                                       BDDC_EAGER if eager else 0, its)
+        _check(self.lib, rc, allow=(BDDC_ENOCONV,))
+        return flux, pres, np.array(its[:k], dtype=np.int32)
+
+    def solve_block_device(self, k, src_ptr, rtol, flux_ptr, pres_ptr):
+        """Device-pointer block solve of k sources ([k][n_cells] at src_ptr, outputs likewise);
+        returns the iterations."""
+        its = (C.c_int32 * max(k, 1))()
+        rc = self.lib.bddc_solve_block(self.h, int(k), C.c_void_p(src_ptr), float(rtol), C.c_void_p(flux_ptr),
+                                       C.c_void_p(pres_ptr), BDDC_DEVICE_PTRS, its)
+        _check(self.lib, rc, allow=(BDDC_ENOCONV,))
+        return np.array(its[:k], dtype=np.int32)
 
     def solve_device(self, src_ptr, rtol, flux_ptr, pres_ptr, eager=False, steps=None):
         """Device-pointer solve (e.g. torch tensor data_ptr()); no host copies."""

@@ -23,6 +23,7 @@
 #include "setup.hip"
 #include "solve.hip"
 #include "coarse.hip"
+#include "block.hip"
 #include "front.hip"
 
 using namespace bddc;
@@ -190,6 +191,9 @@ struct bddc_problem {
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   hipStream_t side = nullptr;                     // coarse solve of the preconditioner
   hipGraphExec_t cg_graph = nullptr;              // CG_CHUNK iterations, captured once
+  BlockWs blk{};                                  // block CG (several sources at once)
+  hipGraphExec_t blk_graph = nullptr;             // CG_CHUNK block iterations, captured once
+  CgBlockState *blk_st_host = nullptr;            // pinned: block CG state after a chunk
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 
   bddc_stats_t stats{};
@@ -243,6 +247,7 @@ struct bddc_problem {
   // streams are drained before anything they use is released.
   ~bddc_problem() {
     if (cg_graph) (void)hipGraphExecDestroy(cg_graph);
+    if (blk_graph) (void)hipGraphExecDestroy(blk_graph);
     if (side) (void)hipStreamSynchronize(side);
     if (own_stream) (void)hipStreamSynchronize(own_stream);
     for (hipEvent_t e : ev_state)
@@ -255,6 +260,7 @@ struct bddc_problem {
     if (own_stream) (void)hipStreamDestroy(own_stream);
     if (st_host) (void)hipHostFree(st_host);
     if (ab_host) (void)hipHostFree(ab_host);
+    if (blk_st_host) (void)hipHostFree(blk_st_host);
     for (size_t k = 0; k < allocs.size(); ++k) free_at(k);
   }
 };
@@ -334,12 +340,12 @@ void setup_dense_top(bddc_problem *h, hipStream_t s) {
     for (int lv = P.top; lv < P.H; ++lv) {
       const int t0 = P.ftask_off[lv], ntk = P.ftask_off[lv + 1] - t0;
       k_top_fwd_cols<<<dim3(ntk, (nc + TOP_NC - 1) / TOP_NC), 256, 0, s>>>(t0, h->sw, h->FR, bb, S0b, S1b, zb, sk,
-                                                                           sv, (int)nc);
+                                                                           sv, (int)nc, nullptr);
     }
     for (int lv = P.H - 1; lv >= P.top; --lv) {
       const int t0 = P.btask_lo[lv], ntk = P.btask_hi[lv] - t0;
       k_top_bwd_cols<<<dim3(ntk, (nc + TOP_NC - 1) / TOP_NC), 256, 0, s>>>(t0, h->sw, h->BC, zb, h->csgn, XBb, xb,
-                                                                           sk, sb, (int)nc);
+                                                                           sk, sb, (int)nc, nullptr);
     }
     k_top_store<<<dim3(nblk(h->top_ld), nc), 256, 0, s>>>(j0, nt, d0, h->top_ld, xb, sk, h->Kt);
     HIPCHK(hipGetLastError());
@@ -846,14 +852,19 @@ void do_setup(bddc_problem *h, const bddc_grid *gr, const double *perm, const bd
   // statistics of the operators streamed per iteration
   // entries of the operators as the method defines them: lower triangles of
   // T^i and S^i, the n_Gamma^i x n_c^i bases Psi^i (storage padding excluded)
-  double sumpk = 0.0, sumpsi = 0.0;
+  double sumpk = 0.0, sumpsi = 0.0, sumsq = 0.0;
   for (int i = 0; i < N; ++i) {
     const double nG = L.nG[i];
     sumpk += nG * (nG + 1) / 2;
+    sumsq += nG * nG;
     sumpsi += nG * (double)(sub_coff[i + 1] - sub_coff[i]);
   }
   const double sT = h->precision == BDDC_MIXED ? 4.0 : 8.0;
   h->stats.bytes_prec = sumpk * sT + 2.0 * sumpsi * sT + h->coarse_bytes + 6.0 * totG * 8.0 + 4.0 * nGm * 8.0;
+  // the block preconditioner (FP64 operators in both forms), 16 columns of the vectors
+  h->stats.bytes_prec_block =
+      sumpk * 8.0 + 2.0 * sumpsi * 8.0 + h->coarse_bytes + BK * (6.0 * totG * 8.0 + 4.0 * nGm * 8.0);
+  h->stats.flops_block_local = 2.0 * BK * sumsq;
   h->stats.bytes_per_iter = h->stats.bytes_prec + sumpk * 8.0 + 2.0 * totG * 8.0 + 8.0 * nGm * 8.0;
 }
 
@@ -1146,8 +1157,10 @@ void autotune(bddc_problem *h) {
 // bddc_solve runs them back to back with one chunk in flight.
 bool solve_needs_cg(const bddc_problem *h) { return h->L.N > 1 && h->run.upto == 0; }
 
+// start_cg = false stops after the reduced right-hand side f* (in ru), for
+// the block CG, which starts its iterations from several of them.
 void solve_begin_launch(bddc_problem *h, const double *rhs, double rtol, double *flux, double *pressure,
-                        uint32_t flags) {
+                        uint32_t flags, bool start_cg = true) {
   const Layout &L = h->L;
   hipStream_t s = h->stream;
   const int N = L.N, nF = L.nF, nGm = L.nGamma;
@@ -1205,6 +1218,7 @@ void solve_begin_launch(bddc_problem *h, const double *rhs, double rtol, double 
   LINE_LAUNCH_S(h->longl, h->mc_staged, k_source_term, N, 256, source_shm(L, h->mc_staged), s, h->g, h->mcoef,
                 h->Xmat, h->d_Xoff, src, h->wloc);
   k_fstar<<<nblk(nGm), 256, 0, s>>>(h->g, h->yloc, h->wloc, h->d_sb, h->ru);
+  if (!start_cg) return;
   fill(h, h->xu, nGm, 0.0);
   fill(h, h->xp, N, 0.0);
   k_norm2_partial<<<vec_blocks(nGm), 256, 0, s>>>(nGm, h->ru, h->cgw.part_r);
@@ -1263,6 +1277,42 @@ int solve_poll(bddc_problem *h, bool wait) {
   return 1;
 }
 
+// Post-correction of Algorithm "BDDC method": the interior fluxes and
+// pressures of every subdomain from the final interface flux uG and the
+// source (local Dirichlet problems), into the run's outputs (enqueued only).
+void post_correct(bddc_problem *h) {
+  const Layout &L = h->L;
+  hipStream_t s = h->stream;
+  const int N = L.N, nGm = L.nGamma;
+  auto &R = h->run;
+  double *fl = R.fl, *pr = R.pr;
+  if (h->d_bflux)
+    HIPCHK(hipMemcpyAsync(fl, h->d_bflux, L.nfaces_all * sizeof(double), hipMemcpyDeviceToDevice, s));
+  else
+    fill(h, fl, L.nfaces_all, 0.0);
+  if (nGm > 0) k_scatter_iface<<<nblk(nGm), 256, 0, s>>>(nGm, h->d_gamma_face, h->uG, fl);
+  if (N == 1) fill(h, h->xp, 1, 0.0);
+  // step 1 alone continues u_0 with zero source
+  const double *rsrc = R.src;
+  if (R.upto == 1) {
+    fill(h, h->d_zero_src, L.ncells, 0.0);
+    rsrc = h->d_zero_src;
+  }
+  const size_t rec_shm = recover_shm(L, h->mc_staged);
+  LINE_LAUNCH_S(h->longl, h->mc_staged, k_recover_rhs, N, 256, rec_shm, s, h->g, h->mcoef, rsrc, h->uG, h->rec_y);
+  k_recover_xgemv<<<dim3(N, nblk(L.maxC)), 256, (size_t)L.maxC * sizeof(double), s>>>(h->g, h->Xmat, h->d_Xoff,
+                                                                                       h->rec_y, h->rec_p);
+  LINE_LAUNCH_S(h->longl, h->mc_staged, k_recover_flux, N, 256, rec_shm, s, h->g, h->mcoef, h->uG, h->rec_p, h->xp,
+                h->dscale, fl, pr);
+  k_sum_partial<<<256, 256, 0, s>>>(L.ncells, pr, h->cgw.part_p);
+  k_sub_mean<<<256, 256, 0, s>>>(L.ncells, pr, h->cgw.part_p, 256);
+  HIPCHK(hipGetLastError());
+  if (!R.dev) {
+    HIPCHK(hipMemcpyAsync(R.flux, fl, L.nfaces_all * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(R.pressure, pr, L.ncells * sizeof(double), hipMemcpyDeviceToHost, s));
+  }
+}
+
 int solve_finish_locked(bddc_problem *h);
 
 int solve_finish(bddc_problem *h) {
@@ -1297,33 +1347,7 @@ int solve_finish_locked(bddc_problem *h) {
   } else if (R.upto && nGm > 0) {
     k_axpby<<<nblk(nGm), 256, 0, s>>>(nGm, 1.0, h->u0, 0.0, h->u0, h->uG);
   }
-  // post-correction: interior fluxes and pressures
-  double *fl = R.fl, *pr = R.pr;
-  if (h->d_bflux)
-    HIPCHK(hipMemcpyAsync(fl, h->d_bflux, L.nfaces_all * sizeof(double), hipMemcpyDeviceToDevice, s));
-  else
-    fill(h, fl, L.nfaces_all, 0.0);
-  if (nGm > 0) k_scatter_iface<<<nblk(nGm), 256, 0, s>>>(nGm, h->d_gamma_face, h->uG, fl);
-  if (N == 1) fill(h, h->xp, 1, 0.0);
-  // step 1 alone continues u_0 with zero source
-  const double *rsrc = R.src;
-  if (R.upto == 1) {
-    fill(h, h->d_zero_src, L.ncells, 0.0);
-    rsrc = h->d_zero_src;
-  }
-  const size_t rec_shm = recover_shm(L, h->mc_staged);
-  LINE_LAUNCH_S(h->longl, h->mc_staged, k_recover_rhs, N, 256, rec_shm, s, h->g, h->mcoef, rsrc, h->uG, h->rec_y);
-  k_recover_xgemv<<<dim3(N, nblk(L.maxC)), 256, (size_t)L.maxC * sizeof(double), s>>>(h->g, h->Xmat, h->d_Xoff,
-                                                                                       h->rec_y, h->rec_p);
-  LINE_LAUNCH_S(h->longl, h->mc_staged, k_recover_flux, N, 256, rec_shm, s, h->g, h->mcoef, h->uG, h->rec_p, h->xp,
-                h->dscale, fl, pr);
-  k_sum_partial<<<256, 256, 0, s>>>(L.ncells, pr, h->cgw.part_p);
-  k_sub_mean<<<256, 256, 0, s>>>(L.ncells, pr, h->cgw.part_p, 256);
-  HIPCHK(hipGetLastError());
-  if (!R.dev) {
-    HIPCHK(hipMemcpyAsync(R.flux, fl, L.nfaces_all * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(R.pressure, pr, L.ncells * sizeof(double), hipMemcpyDeviceToHost, s));
-  }
+  post_correct(h);
   HIPCHK(hipStreamSynchronize(s));
   if (cg) {
     const CgState &fs = h->st_host[(R.chunks - 1) & 1];
@@ -1360,6 +1384,258 @@ int do_solve(bddc_problem *h, const double *rhs, double rtol, double *flux, doub
     } while (!h->run.stop);
   }
   return solve_finish(h);
+}
+
+// ---- block CG: several sources at once ---------------------------------------
+// Workspace of the block CG, allocated at the first block solve.
+void block_setup(bddc_problem *h) {
+  BlockWs &B = h->blk;
+  if (B.ready) return;
+  const Layout &L = h->L;
+  const NdPlan &P = h->nd;
+  const int N = L.N;
+  if ((int)h->sub_coff_h.size() != N + 1) throw Error{BDDC_EDEVICE, "coarse basis offsets missing"};
+  int dev = 0, lds_max = 0;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  int maxnc = 0;
+  for (int i = 0; i < N; ++i) maxnc = std::max(maxnc, h->sub_coff_h[i + 1] - h->sub_coff_h[i]);
+  const size_t nbmax = (size_t)(L.maxG + 15) / 16;
+  B.symv_shm = nbmax * 16 * BK * sizeof(double);
+  B.psi_shm = B.symv_shm + 256 * sizeof(double);
+  B.symv_threads = 2 * B.symv_shm > (size_t)lds_max ? 64 * BLK_SYMV_WAVES : 256;
+  B.corr_shm = (size_t)((maxnc + 15) / 16) * 16 * BK * sizeof(double);
+  // coarse sweep tasks of the swept levels: 64 rows / columns of a front each
+  int maxn = 0;
+  std::vector<int> tk;
+  auto push = [&](int r, int j0) {
+    const int64_t ro = P.r_off[r];
+    const int d[12] = {j0, P.n[r], P.m[r], P.first[r], (int)P.v_off[r], P.b_off[r], P.cslot[r], 0,
+                       (int)(uint32_t)(ro & 0xffffffff), (int)(uint32_t)(ro >> 32), 0, 0};
+    tk.insert(tk.end(), d, d + 12);
+  };
+  B.tf_off.assign(P.top + 1, 0);
+  B.tb_lo.assign(P.top, 0);
+  B.tb_hi.assign(P.top, 0);
+  for (int lv = 0; lv < P.top; ++lv) {
+    for (int r = P.lvl_off[lv]; r < P.lvl_off[lv + 1]; ++r) {
+      maxn = std::max(maxn, P.n[r]);
+      for (int j0 = 0; j0 < P.n[r] + P.m[r]; j0 += BLK_SWEEP_ROWS) push(r, j0);
+    }
+    B.tf_off[lv + 1] = (int)tk.size() / 12;
+  }
+  for (int lv = P.top - 1; lv >= 0; --lv) {
+    B.tb_lo[lv] = (int)tk.size() / 12;
+    for (int r = P.lvl_off[lv]; r < P.lvl_off[lv + 1]; ++r)
+      for (int c0 = 0; c0 < P.n[r]; c0 += BLK_SWEEP_ROWS) push(r, c0);
+    B.tb_hi[lv] = (int)tk.size() / 12;
+  }
+  B.fwd_shm = (size_t)((maxn + 3) & ~3) * BK * sizeof(double);
+  if (std::max({B.symv_shm, B.psi_shm, B.corr_shm, B.fwd_shm}) > (size_t)lds_max)
+    throw Error{BDDC_EINVAL, "a subdomain interface, coarse basis or coarse front is too large for the block "
+                             "kernels' LDS"};
+  const int64_t nG = L.nGamma, totG = L.g_off[N];
+  const int64_t nk = std::max(h->nk, 1), nv = std::max<int64_t>(P.v_off[P.nfr], 1),
+                nbv = std::max<int64_t>(P.b_off[P.nfr], 1);
+  B.task = (int4 *)h->upload(tk);
+  for (double **v : {&B.ru, &B.zu, &B.pu, &B.xu, &B.qu, &B.u0}) *v = h->alloc<double>(nG * BK);
+  B.yloc = h->alloc<double>(totG * BK);
+  B.wloc = h->alloc<double>(totG * BK);
+  B.pp = h->alloc<double>((int64_t)N * BK);
+  B.xp = h->alloc<double>((int64_t)N * BK);
+  B.bc = h->alloc<double>(nk * BK);
+  B.cy = h->alloc<double>(nk * BK);
+  B.csol = h->alloc<double>(nk * BK);
+  B.S0 = h->alloc<double>(nv * BK);
+  B.S1 = h->alloc<double>(nv * BK);
+  B.XB = h->alloc<double>(nbv * BK);
+  B.tt = h->alloc<double>((int64_t)std::max(P.nt, 1) * BK);
+  B.part_g = h->alloc<double>((int64_t)PART_BLOCKS * BK);
+  B.part_r = h->alloc<double>((int64_t)PART_BLOCKS * BK);
+  B.part_z = h->alloc<double>((int64_t)PART_BLOCKS * BK);
+  B.alpha_h = h->alloc<double>((int64_t)(h->max_it + 2) * BK);
+  B.beta_h = h->alloc<double>((int64_t)(h->max_it + 2) * BK);
+  B.st = h->alloc<CgBlockState>(1);
+  fill(h, B.S0, nv * BK, 0.0);   // slots no child writes stay zero
+  fill(h, B.S1, nv * BK, 0.0);
+  fill(h, B.csol, nk * BK, 0.0);
+  if (!h->blk_st_host) HIPCHK(hipHostMalloc((void **)&h->blk_st_host, sizeof(CgBlockState), hipHostMallocDefault));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  B.ready = true;
+}
+
+// grid of the block vector kernels (they leave one partial per block)
+inline int blk_vec_blocks(int64_t n) { return (int)std::min<int64_t>(nblk(n * BK), PART_BLOCKS); }
+
+// Z = M R for the block's columns: the steps of launch_precond, each over all
+// BK columns (T^i on the side stream beside the coarse chain).
+// st: the block CG state (every kernel leaves once all columns have stopped),
+// or null (timing).
+void launch_precond_blk(bddc_problem *h, CgBlockState *st) {
+  const Layout &L = h->L;
+  const NdPlan &P = h->nd;
+  BlockWs &B = h->blk;
+  hipStream_t s = h->stream;
+  const int N = L.N;
+  k_blk_fill<<<256, 256, 0, s>>>((int64_t)std::max(h->nk, 1) * BK, B.bc, 0.0, st);
+  // Both forms stream the FP64 copies of T^i and Psi^i here (both copies are
+  // resident): on the matrix cores the FP32 tiles, widened, loaded slower.
+  k_blk_psi_apply<double><<<N, 256, B.psi_shm, s>>>(h->g, h->Psi64, h->d_psi_off, h->cs.sub_coff, h->cs.sub_cmap,
+                                                   B.ru, 0.5, h->lw, B.bc, st);
+  HIPCHK(hipEventRecord(h->ev_fork, s));
+  HIPCHK(hipStreamWaitEvent(h->side, h->ev_fork, 0));
+  k_blk_symv<double><<<N, B.symv_threads, B.symv_shm, h->side>>>(h->g, h->T64, h->d_pk, B.ru, 0.5, h->lw, B.yloc, st);
+  HIPCHK(hipEventRecord(h->ev_join, h->side));
+  if (h->nk > 0) {
+    check_coarse_ptrs(h);
+    for (int lv = 0; lv < P.top; ++lv) {
+      const int t0 = B.tf_off[lv], nt = B.tf_off[lv + 1] - t0;
+      if (nt > 0)
+        k_blk_nd_fwd<<<nt, 256, B.fwd_shm, s>>>(t0, B.task, h->FR, h->sw.wdst, B.bc, B.S0, B.S1, B.cy, st);
+    }
+    if (P.nt > 0) {
+      const int d0 = P.lvl_dof[P.top];
+      k_blk_top_gather<<<nblk((int64_t)P.nt * BK), 256, 0, s>>>(P.nt, d0, h->tg_off, h->tg, B.bc, B.S0, B.S1, B.tt,
+                                                                 st);
+      k_blk_top_gemm<<<nblk(P.nt, 16), 64 * TOP_GEMM_WAVES, 0, s>>>(P.nt, h->top_ld, h->Kt, B.tt, d0,
+                                                                     h->sw.xsc_off, h->sw.xsc, B.XB, B.csol, st);
+    }
+    for (int lv = P.top - 1; lv >= 0; --lv) {
+      const int t0 = B.tb_lo[lv], nt = B.tb_hi[lv] - t0;
+      if (nt > 0)
+        k_blk_nd_bwd<<<nt, 256, 0, s>>>(t0, B.task, h->BC, B.cy, h->csgn, h->sw.xsc_off, h->sw.xsc, B.XB, B.csol,
+                                        st);
+    }
+  }
+  k_blk_psi_correct<double><<<N, 256, B.corr_shm, s>>>(h->g, h->cs, h->Psi64, h->d_psi_off, B.csol, B.wloc, st);
+  HIPCHK(hipStreamWaitEvent(s, h->ev_join, 0));
+  k_blk_average<<<face_blocks(L.nF), 256, 0, s>>>(h->g, h->cs, B.wloc, B.yloc, B.csol, B.zu, B.ru, B.part_z, st);
+}
+
+// One block CG iteration: q = A p, alpha, x / r update, stopping test, z = M r, beta, p update.
+void launch_iteration_blk(bddc_problem *h) {
+  const Layout &L = h->L;
+  BlockWs &B = h->blk;
+  hipStream_t s = h->stream;
+  const int N = L.N, nGm = L.nGamma;
+  const int gv = blk_vec_blocks(nGm);
+  CgBlockState *st = B.st;
+  k_blk_symv<double><<<N, B.symv_threads, B.symv_shm, s>>>(h->g, h->Spk, h->d_pk, B.pu, 1.0, nullptr, B.yloc, st);
+  k_blk_assemble<<<gv, 256, 0, s>>>(h->g, B.yloc, B.pp, h->dscale, B.pu, B.qu, B.part_g, st);
+  k_blk_alpha<<<1, 256, 0, s>>>(st, B.part_g, gv, B.alpha_h);
+  k_blk_update_xr<<<gv, 256, 0, s>>>(nGm, N, B.pu, B.qu, B.pp, B.xu, B.ru, B.xp, B.part_r, st);
+  k_blk_test<<<1, 256, 0, s>>>(st, B.part_r, gv);
+  launch_precond_blk(h, st);
+  k_blk_beta<<<1, 256, 0, s>>>(st, B.part_z, face_blocks(L.nF), B.beta_h);
+  k_blk_update_p<<<gv, 256, 0, s>>>(nGm, N, h->cs.pidx, B.zu, B.csol, B.pu, B.pp, st);
+}
+
+// Sources [0, k) of one block: steps 1-2 and the reduced right-hand side of
+// each (the single-source kernels), the block CG, and the post-correction of
+// each.  its[j] receives each source's CG iterations.  Returns the worst
+// status of the block.
+int solve_block_of(bddc_problem *h, int k, const double *rhs, double rtol, double *flux, double *pressure,
+                   uint32_t flags, int32_t *its) {
+  const Layout &L = h->L;
+  BlockWs &B = h->blk;
+  const int N = L.N, nGm = L.nGamma;
+  const int64_t nc = L.ncells, nf = L.nfaces_all;
+  const bool dev = (flags & BDDC_DEVICE_PTRS) != 0, eager = (flags & BDDC_EAGER) != 0;
+  const int gv = blk_vec_blocks(nGm);
+  const auto t0 = std::chrono::steady_clock::now();
+  {
+    GateShared g(g_gate);
+    hipStream_t s = h->stream;
+    fill(h, B.ru, nGm * BK, 0.0);
+    for (int j = 0; j < k; ++j) {
+      solve_begin_launch(h, rhs + j * nc, rtol, flux + j * nf, pressure + j * nc, flags, false);
+      k_blk_put<<<nblk(nGm), 256, 0, s>>>(nGm, j, h->ru, B.ru);
+      k_blk_put<<<nblk(nGm), 256, 0, s>>>(nGm, j, h->u0, B.u0);
+    }
+    for (double *v : {B.xu, B.pu}) fill(h, v, nGm * BK, 0.0);
+    for (double *v : {B.xp, B.pp}) fill(h, v, (int64_t)N * BK, 0.0);
+    k_blk_norm2<<<gv, 256, 0, s>>>(nGm, B.ru, B.part_r);
+    k_blk_init<<<1, 256, 0, s>>>(B.st, B.part_r, gv, rtol, h->max_it);
+    launch_precond_blk(h, B.st);
+    k_blk_rho<<<1, 256, 0, s>>>(B.st, B.part_z, face_blocks(L.nF));
+    k_blk_update_p<<<gv, 256, 0, s>>>(nGm, N, h->cs.pidx, B.zu, B.csol, B.pu, B.pp, B.st);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipEventRecord(h->ev0, s));
+  }
+  if (!eager && !h->blk_graph)
+    h->blk_graph = capture_graph(h, CG_CHUNK, [&] { launch_iteration_blk(h); }, "the block CG iteration graph");
+  CgBlockState &fs = *h->blk_st_host;
+  int chunks = 0;
+  {
+    GateShared g(g_gate);
+    hipStream_t s = h->stream;
+    for (;;) {
+      if (chunks > h->max_it / CG_CHUNK + 2) throw Error{BDDC_EDEVICE, "block CG did not report completion"};
+      if (eager) {
+        for (int c = 0; c < CG_CHUNK; ++c) launch_iteration_blk(h);
+      } else {
+        HIPCHK(hipGraphLaunch(h->blk_graph, s));
+      }
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipMemcpyAsync(&fs, B.st, sizeof(CgBlockState), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      ++chunks;
+      if (fs.done) break;
+    }
+    HIPCHK(hipEventRecord(h->ev1, s));
+    // post-correction source by source
+    auto &R = h->run;
+    for (int j = 0; j < k; ++j) {
+      R = bddc_problem::Run();
+      R.t0 = t0;
+      R.dev = dev;
+      R.src = rhs + j * nc;
+      if (!dev) {
+        HIPCHK(hipMemcpyAsync(h->d_src, rhs + j * nc, nc * sizeof(double), hipMemcpyHostToDevice, s));
+        R.src = h->d_src;
+      }
+      R.flux = flux + j * nf;
+      R.pressure = pressure + j * nc;
+      R.fl = dev ? R.flux : h->d_flux;
+      R.pr = dev ? R.pressure : h->d_pres;
+      k_blk_get<<<nblk(nGm), 256, 0, s>>>(nGm, j, B.xu, h->xu);
+      k_blk_get<<<nblk(nGm), 256, 0, s>>>(nGm, j, B.u0, h->u0);
+      k_blk_get<<<nblk(N), 256, 0, s>>>(N, j, B.xp, h->xp);
+      k_axpby<<<nblk(nGm), 256, 0, s>>>(nGm, 1.0, h->u0, 1.0, h->xu, h->uG);
+      post_correct(h);
+    }
+    HIPCHK(hipStreamSynchronize(s));
+  }
+  // statistics of the block's last source
+  const int jl = k - 1;
+  const int iters = fs.nupd[jl];
+  std::vector<double> ah((size_t)(iters + 1) * BK), bh((size_t)(iters + 1) * BK);
+  if (iters > 0) {
+    GateShared g(g_gate);
+    HIPCHK(hipMemcpy(ah.data(), B.alpha_h, (size_t)iters * BK * sizeof(double), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(bh.data(), B.beta_h, (size_t)iters * BK * sizeof(double), hipMemcpyDeviceToHost));
+  }
+  std::vector<double> a(iters), b(iters > 0 ? iters - 1 : 0);
+  for (int t = 0; t < iters; ++t) a[t] = ah[(size_t)t * BK + jl];
+  for (int t = 0; t + 1 < iters; ++t) b[t] = bh[(size_t)t * BK + jl];
+  double lmin = 1, lmax = 1;
+  h->stats.kappa = lanczos_kappa(a, b, &lmin, &lmax);
+  h->stats.lambda_min = lmin;
+  h->stats.lambda_max = lmax;
+  float pcg_ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&pcg_ms, h->ev0, h->ev1));
+  h->stats.it = iters;
+  h->stats.converged = fs.converged[jl];
+  h->stats.relres = fs.relres[jl];
+  h->stats.t_pcg_ms = pcg_ms;
+  h->stats.t_solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  int rc = BDDC_OK;
+  for (int j = 0; j < k; ++j) {
+    if (its) its[j] = fs.nupd[j];
+    if (fs.fail[j]) rc = BDDC_EBREAKDOWN;
+    else if (!fs.converged[j] && rc == BDDC_OK) rc = BDDC_ENOCONV;
+  }
+  return rc;
 }
 
 void apply_options(bddc_problem *h, const bddc_options *opt) {
@@ -1505,6 +1781,40 @@ int bddc_solve_batch(bddc_handle h, int32_t nrhs, const double *rhs, double rtol
       if (iterations) iterations[k] = h->stats.it;
       if (rc == BDDC_ENOCONV) rc_all = BDDC_ENOCONV;
     }
+    if (rc_all == BDDC_ENOCONV) g_last_error = "maximum number of CG iterations reached for a right-hand side";
+    return rc_all;
+  });
+}
+
+int bddc_solve_block(bddc_handle h, int32_t nrhs, const double *rhs, double rtol, double *flux, double *pressure,
+                     uint32_t flags, int32_t *iterations) {
+  return guarded([&]() -> int {
+    if (!h || nrhs < 0 || (nrhs > 0 && (!rhs || !flux || !pressure))) throw Error{BDDC_EINVAL, "bad argument"};
+    if (flags & (BDDC_STEP1_ONLY | BDDC_STEP12_ONLY))
+      throw Error{BDDC_EINVAL, "the block solve runs whole solves (no step flags)"};
+    if (!(rtol > 0.0)) throw Error{BDDC_EINVAL, "rtol must be > 0"};
+    const int64_t nc = h->L.ncells, nf = h->L.nfaces_all;
+    int rc_all = BDDC_OK;
+    if (h->L.N <= 1 || h->L.nGamma == 0) {
+      // no interface: nothing to iterate on, the solves are direct
+      for (int32_t k = 0; k < nrhs; ++k) {
+        const int rc = do_solve(h, rhs + k * nc, rtol, flux + k * nf, pressure + k * nc, flags);
+        if (iterations) iterations[k] = h->stats.it;
+        if (rc != BDDC_OK) rc_all = rc;
+      }
+      return rc_all;
+    }
+    {
+      GateShared g(g_gate);
+      block_setup(h);
+    }
+    for (int32_t b0 = 0; b0 < nrhs; b0 += BK) {
+      const int k = std::min<int32_t>(BK, nrhs - b0);
+      const int rc = solve_block_of(h, k, rhs + b0 * nc, rtol, flux + b0 * nf, pressure + b0 * nc, flags,
+                                    iterations ? iterations + b0 : nullptr);
+      if (rc == BDDC_EBREAKDOWN || (rc == BDDC_ENOCONV && rc_all == BDDC_OK)) rc_all = rc;
+    }
+    if (rc_all == BDDC_EBREAKDOWN) g_last_error = "CG breakdown (p^T S p <= 0 or not finite) for a right-hand side";
     if (rc_all == BDDC_ENOCONV) g_last_error = "maximum number of CG iterations reached for a right-hand side";
     return rc_all;
   });
@@ -1751,6 +2061,13 @@ int bddc_time_kernel(bddc_handle h, int32_t which, int32_t reps, double *avg_ms,
       *bytes = h->stats.bytes_prec;
       return BDDC_OK;
     }
+    if (which >= BDDC_K_BLOCK_SCHUR && which <= BDDC_K_BLOCK_PRECOND_FULL && !h->blk.ready)
+      throw Error{BDDC_EINVAL, "no block solve has run on this handle"};
+    if (which == BDDC_K_BLOCK_PRECOND_FULL) {
+      *avg_ms = time_graph_ms(h, reps, [&] { launch_precond_blk(h, nullptr); }, "the block preconditioner");
+      *bytes = h->stats.bytes_prec_block;
+      return BDDC_OK;
+    }
     GateShared g(g_gate);
     const Layout &L = h->L;
     hipStream_t s = h->stream;
@@ -1761,8 +2078,13 @@ int bddc_time_kernel(bddc_handle h, int32_t which, int32_t reps, double *avg_ms,
     const double totG = (double)L.g_off[N];
     const double sT = h->precision == BDDC_MIXED ? 4.0 : 8.0;
     double b = 0.0;
+    const BlockWs &B = h->blk;
     auto launch = [&]() {
-      if (which == BDDC_K_SCHUR_APPLY)
+      if (which == BDDC_K_BLOCK_SCHUR)
+        k_blk_symv<double><<<N, B.symv_threads, B.symv_shm, s>>>(h->g, h->Spk, h->d_pk, B.pu, 1.0, nullptr, B.yloc, nullptr);
+      else if (which == BDDC_K_BLOCK_PRECOND_APPLY)
+        k_blk_symv<double><<<N, B.symv_threads, B.symv_shm, s>>>(h->g, h->T64, h->d_pk, B.ru, 0.5, h->lw, B.yloc, nullptr);
+      else if (which == BDDC_K_SCHUR_APPLY)
         k_symv<double><<<N, SYMV_THREADS, symv_shm(L), s>>>(h->g, h->Spk, h->d_pk, h->pu, 1.0, nullptr, h->yloc, nullptr, nullptr, 0);
       else if (h->precision == BDDC_MIXED)
         k_symv<float><<<N, SYMV_THREADS, symv_shm(L), s>>>(h->g, h->T32, h->d_pk, h->ru, 0.5, h->lw, h->yloc, nullptr, nullptr, 0);
@@ -1774,6 +2096,10 @@ int bddc_time_kernel(bddc_handle h, int32_t which, int32_t reps, double *avg_ms,
       b = pk * 8.0 + totG * (4.0 + 8.0) + totG * 8.0;
     else if (which == BDDC_K_PRECOND_APPLY)
       b = pk * sT + totG * (4.0 + 8.0) + totG * 8.0;
+    else if (which == BDDC_K_BLOCK_SCHUR)
+      b = pk * 8.0 + totG * (4.0 + 8.0 * BK) + totG * 8.0 * BK;
+    else if (which == BDDC_K_BLOCK_PRECOND_APPLY)
+      b = pk * 8.0 + totG * (4.0 + 8.0 * BK) + totG * 8.0 * BK;
     else
       throw Error{BDDC_EINVAL, "unknown kernel"};
     launch();

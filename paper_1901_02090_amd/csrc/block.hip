@@ -1,0 +1,734 @@
+// Block form of step 3 (Algorithm "BDDC method"): the CG of eqs.
+// corr-reduced-1/2 for BK right-hand sides at once.  Every column keeps its
+// own CG scalars and stopping test, so each column runs the iteration of a
+// single solve (to rounding: the block kernels add in another order), while
+// one pass over the local operators S^i and T^i, the bases Psi^i, the swept
+// coarse factor and S_t^{-1} serves all BK columns.  The local operators and
+// bases are applied as 16 x 16 tiles on the FP64 matrix cores (a tile against
+// the block's 16 columns), the coarse sweeps by the column tasks of front.hip.
+//
+// Layout: every vector (interface, local, coarse, the coarse sweeps' work
+// vectors) keeps the BK values of an entry together ([n][BK]).
+//
+// Reductions are deterministic: a block writes one partial per column, a
+// consumer adds the partials of a column in a fixed order.
+#include <vector>
+
+#include "common.hpp"
+#include "dense.hpp"
+
+namespace bddc {
+
+constexpr int BK = 16;   // right-hand sides per block (the N of a 16 x 16 x 4 MFMA)
+
+// Device arrays of the block CG (allocated at the first block solve).
+struct BlockWs {
+  bool ready = false;
+  int4 *task = nullptr;                      // coarse sweep tasks (k_blk_nd_fwd / k_blk_nd_bwd)
+  std::vector<int> tf_off, tb_lo, tb_hi;     // forward tasks of level h, backward tasks of level h
+  double *ru = nullptr, *zu = nullptr, *pu = nullptr, *xu = nullptr, *qu = nullptr, *u0 = nullptr;  // [nGamma][BK]
+  double *yloc = nullptr, *wloc = nullptr;   // [sum nG][BK]
+  double *pp = nullptr, *xp = nullptr;       // [N][BK]
+  double *bc = nullptr, *cy = nullptr, *csol = nullptr;   // [nk][BK]
+  double *S0 = nullptr, *S1 = nullptr;       // [v_off[nfr]][BK]
+  double *XB = nullptr;                      // [b_off[nfr]][BK]
+  double *tt = nullptr;                      // [nt][BK]
+  double *part_g = nullptr, *part_r = nullptr, *part_z = nullptr;   // [PART_BLOCKS][BK]
+  double *alpha_h = nullptr, *beta_h = nullptr;                     // [max_it + 2][BK]
+  struct CgBlockState *st = nullptr;
+  size_t symv_shm = 0, psi_shm = 0, corr_shm = 0, fwd_shm = 0;
+  int symv_threads = 256;                    // k_blk_symv: 8 waves when one workgroup fills a CU's LDS
+};
+
+struct CgBlockState {
+  double rho[BK];        // r.z of the current iteration
+  double alpha[BK], beta[BK];
+  double r0sq[BK], relres[BK];
+  double rtol2;
+  int it;                // block iterations completed
+  int maxit;
+  int done;              // every column has stopped
+  int nupd[BK];          // x / r updates applied to each column
+  int cdone[BK];         // the column has stopped
+  int converged[BK], fail[BK];
+};
+
+// ---- per-column reductions ----------------------------------------------------
+// Thread t of a 256-thread block holds v for column t % BK; the block's BK
+// column sums go to part[blockIdx.x * BK + j].
+__device__ __forceinline__ void col_partial(double v, double *part, double *red) {
+  const int t = threadIdx.x;
+  red[t] = v;
+  __syncthreads();
+  if (t < BK) {
+    double s = 0.0;
+    for (int q = 0; q < 256 / BK; ++q) s += red[q * BK + t];
+    part[(int64_t)blockIdx.x * BK + t] = s;
+  }
+  __syncthreads();
+}
+
+// Column totals of np partials part[p * BK + j] into tot[j] (LDS); called by
+// one whole 256-thread block.
+__device__ __forceinline__ void col_sums(const double *__restrict__ part, int np, double *red, double *tot) {
+  const int t = threadIdx.x, j = t & (BK - 1);
+  double s = 0.0;
+  for (int p = t / BK; p < np; p += 256 / BK) s += part[(int64_t)p * BK + j];
+  red[t] = s;
+  __syncthreads();
+  if (t < BK) {
+    double v = 0.0;
+    for (int q = 0; q < 256 / BK; ++q) v += red[q * BK + t];
+    tot[t] = v;
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ bool blk_done(const CgBlockState *st) { return st && st->done; }
+
+// ---- CG scalars (one block of 256 threads each) ----------------------------------
+// Start: ||r_0||^2 per column; zero columns (padding of a partial block) stop at once.
+__global__ __launch_bounds__(256) void k_blk_init(CgBlockState *st, const double *__restrict__ rpart, int np,
+                                                  double rtol, int maxit) {
+  __shared__ double red[256], tot[BK];
+  col_sums(rpart, np, red, tot);
+  const int t = threadIdx.x;
+  if (t < BK) {
+    const double r0 = tot[t];
+    st->r0sq[t] = r0;
+    st->relres[t] = r0 > 0.0 ? 1.0 : 0.0;
+    st->nupd[t] = 0;
+    st->alpha[t] = st->beta[t] = 0.0;
+    st->fail[t] = isfinite(r0) ? 0 : 1;
+    st->converged[t] = (r0 == 0.0) ? 1 : 0;
+    st->cdone[t] = (r0 > 0.0 && isfinite(r0)) ? 0 : 1;
+  }
+  __syncthreads();
+  if (t == 0) {
+    st->rtol2 = rtol * rtol;
+    st->it = 0;
+    st->maxit = maxit;
+    int all = 1;
+    for (int j = 0; j < BK; ++j) all &= st->cdone[j];
+    st->done = all;
+  }
+}
+
+// First r.z: rho, and beta = 0 so that the p update gives p = z.
+__global__ __launch_bounds__(256) void k_blk_rho(CgBlockState *st, const double *__restrict__ zpart, int np) {
+  __shared__ double red[256], tot[BK];
+  col_sums(zpart, np, red, tot);
+  if (threadIdx.x < BK) {
+    st->rho[threadIdx.x] = tot[threadIdx.x];
+    st->beta[threadIdx.x] = 0.0;
+  }
+}
+
+// alpha = rho / (p.q) per running column; a column whose p.q is not positive
+// and finite stops (breakdown).
+__global__ __launch_bounds__(256) void k_blk_alpha(CgBlockState *st, const double *__restrict__ gpart, int np,
+                                                   double *__restrict__ alpha_h) {
+  __shared__ double red[256], tot[BK];
+  if (st->done) return;
+  col_sums(gpart, np, red, tot);
+  const int t = threadIdx.x;
+  if (t < BK) {
+    double a = 0.0;
+    if (!st->cdone[t]) {
+      const double gam = tot[t];
+      if (gam > 0.0 && isfinite(gam)) {
+        a = st->rho[t] / gam;
+      } else {
+        st->fail[t] = 1;
+        st->cdone[t] = 1;
+      }
+    }
+    st->alpha[t] = a;
+    alpha_h[(int64_t)st->it * BK + t] = a;
+  }
+  __syncthreads();
+  if (t == 0) {
+    int all = 1;
+    for (int j = 0; j < BK; ++j) all &= st->cdone[j];
+    st->done = all;
+  }
+}
+
+// Stopping test after the x / r update, per running column.
+__global__ __launch_bounds__(256) void k_blk_test(CgBlockState *st, const double *__restrict__ rpart, int np) {
+  __shared__ double red[256], tot[BK];
+  if (st->done) return;
+  col_sums(rpart, np, red, tot);
+  const int t = threadIdx.x;
+  if (t < BK && !st->cdone[t]) {
+    const double rn2 = tot[t];
+    const bool conv = rn2 <= st->rtol2 * st->r0sq[t];
+    const bool cap = st->nupd[t] >= st->maxit;
+    st->relres[t] = st->r0sq[t] > 0.0 ? sqrt(rn2 / st->r0sq[t]) : 0.0;
+    if (conv || cap || !isfinite(rn2)) {
+      st->cdone[t] = 1;
+      st->converged[t] = conv ? 1 : 0;
+      if (!isfinite(rn2)) st->fail[t] = 1;
+    }
+  }
+  __syncthreads();
+  if (t == 0) {
+    int all = 1;
+    for (int j = 0; j < BK; ++j) all &= st->cdone[j];
+    st->done = all;
+  }
+}
+
+// beta = rho' / rho per running column (0 for stopped ones, whose p is then
+// just z and is not used again); the block iteration is complete.
+__global__ __launch_bounds__(256) void k_blk_beta(CgBlockState *st, const double *__restrict__ zpart, int np,
+                                                  double *__restrict__ beta_h) {
+  __shared__ double red[256], tot[BK];
+  if (st->done) return;
+  col_sums(zpart, np, red, tot);
+  const int t = threadIdx.x;
+  if (t < BK) {
+    double b = 0.0;
+    if (!st->cdone[t]) {
+      b = tot[t] / st->rho[t];
+      st->rho[t] = tot[t];
+    }
+    st->beta[t] = b;
+    beta_h[(int64_t)st->it * BK + t] = b;
+  }
+  __syncthreads();
+  if (t == 0) st->it += 1;
+}
+
+// ---- CG vector kernels (grid-stride over the n * BK entries: a thread keeps
+// the column threadIdx.x % BK) ------------------------------------------------------
+__global__ __launch_bounds__(256) void k_blk_fill(int64_t n, double *x, double v, const CgBlockState *st) {
+  if (blk_done(st)) return;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) x[e] = v;
+}
+
+__global__ __launch_bounds__(256) void k_blk_norm2(int64_t n, const double *__restrict__ x, double *part) {
+  __shared__ double red[256];
+  double v = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n * BK; e += (int64_t)gridDim.x * 256)
+    v = fma(x[e], x[e], v);
+  col_partial(v, part, red);
+}
+
+// q = assembled local products + B_0^T x_p; partials of p.q
+__global__ __launch_bounds__(256) void k_blk_assemble(DevGeom g, const double *__restrict__ yloc,
+                                                      const double *__restrict__ xp,
+                                                      const double *__restrict__ dscale,
+                                                      const double *__restrict__ pu, double *__restrict__ q,
+                                                      double *part, const CgBlockState *st) {
+  __shared__ double red[256];
+  if (blk_done(st)) return;
+  const int j = threadIdx.x & (BK - 1);
+  double v = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < (int64_t)g.nGamma * BK;
+       e += (int64_t)gridDim.x * 256) {
+    const int gi = (int)(e / BK);
+    const int sm = g.sub_minus[gi], sp = g.sub_plus[gi];
+    const double b0 = -dscale[sm] * xp[(int64_t)sm * BK + j] + dscale[sp] * xp[(int64_t)sp * BK + j];
+    const double qq = yloc[(int64_t)g.own_minus[gi] * BK + j] + yloc[(int64_t)g.own_plus[gi] * BK + j] + b0;
+    q[e] = qq;
+    v = fma(pu[e], qq, v);
+  }
+  col_partial(v, part, red);
+}
+
+// x += alpha p, r -= alpha q (running columns); partials of r.r
+__global__ __launch_bounds__(256) void k_blk_update_xr(int nGamma, int N, const double *__restrict__ pu,
+                                                       const double *__restrict__ q, const double *__restrict__ pp,
+                                                       double *xu, double *ru, double *xp, double *rpart,
+                                                       CgBlockState *st) {
+  __shared__ double red[256];
+  if (st->done) return;
+  const int j = threadIdx.x & (BK - 1);
+  const bool run = !st->cdone[j];
+  const double a = st->alpha[j];
+  double v = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < (int64_t)nGamma * BK; e += (int64_t)gridDim.x * 256) {
+    double r = ru[e];
+    if (run) {
+      xu[e] = fma(a, pu[e], xu[e]);
+      r = fma(-a, q[e], r);
+      ru[e] = r;
+    }
+    v = fma(r, r, v);
+  }
+  if (blockIdx.x == 0 && run) {
+    for (int64_t e = threadIdx.x; e < (int64_t)N * BK; e += 256) xp[e] = fma(a, pp[e], xp[e]);
+  }
+  col_partial(v, rpart, red);   // ends with a barrier: every thread has read cdone
+  if (blockIdx.x == 0 && threadIdx.x < BK && !st->cdone[threadIdx.x]) st->nupd[threadIdx.x] += 1;
+}
+
+// p = z + beta p (flux and coarse pressure, z_p from the coarse solution)
+__global__ __launch_bounds__(256) void k_blk_update_p(int nGamma, int N, const int *__restrict__ pidx,
+                                                      const double *__restrict__ zu, const double *__restrict__ csolb,
+                                                      double *pu, double *pp, const CgBlockState *st) {
+  if (st->done) return;
+  const int j = threadIdx.x & (BK - 1);
+  const double b = st->beta[j];
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < (int64_t)nGamma * BK; e += (int64_t)gridDim.x * 256)
+    pu[e] = fma(b, pu[e], zu[e]);
+  if (blockIdx.x == 0) {
+    for (int64_t e = threadIdx.x; e < (int64_t)N * BK; e += 256) {
+      const int k = (int)(e / BK);
+      const double zp = pidx[k] >= 0 ? csolb[(int64_t)pidx[k] * BK + j] : 0.0;
+      pp[e] = fma(b, pp[e], zp);
+    }
+  }
+}
+
+// column j of a block vector <-> a single vector
+__global__ void k_blk_put(int64_t n, int j, const double *__restrict__ x, double *__restrict__ xb) {
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (k < n) xb[k * BK + j] = x[k];
+}
+__global__ void k_blk_get(int64_t n, int j, const double *__restrict__ xb, double *__restrict__ x) {
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (k < n) x[k] = xb[k * BK + j];
+}
+
+// ---- local operators on the matrix cores ---------------------------------------
+// M(r, c) of a symmetric matrix in the group-aligned packed lower storage,
+// which holds the entries r >= c (the rest of a diagonal 4 x 4 block is zero
+// padding): an entry above the diagonal is read from its mirror image.
+template <typename TS>
+__device__ __forceinline__ double sym_entry(const TS *__restrict__ M, int n, int r, int c) {
+  return (r >= c) ? (double)M[gp_index(n, r, c)] : (double)M[gp_index(n, c, r)];
+}
+
+// Four consecutive entries of a packed column (16-byte aligned: column
+// segments start at multiples of four entries), widened to FP64.
+__device__ __forceinline__ void load4(const float *p, double *o) {
+  const f32x4 v = *reinterpret_cast<const f32x4 *>(p);
+  o[0] = v[0]; o[1] = v[1]; o[2] = v[2]; o[3] = v[3];
+}
+__device__ __forceinline__ void load4(const double *p, double *o) {
+  const f64x2 v0 = *reinterpret_cast<const f64x2 *>(p), v1 = *reinterpret_cast<const f64x2 *>(p + 2);
+  o[0] = v0[0]; o[1] = v0[1]; o[2] = v1[0]; o[3] = v1[1];
+}
+
+// Y^i = M^i (w * R_i X) for the BK columns, M^i in packed storage (S^i, or T^i
+// of the preconditioner; FP32 entries are widened).  One workgroup of W = 4
+// or 8 waves per subdomain (grid-stride); w * R_i X is staged in LDS ([16
+// nb][BK], zero padded).  Wave w forms the 64-row blocks w, w + W, ... of Y^i from the
+// whole block row of the symmetric M^i, 16 columns at a time, on the FP64
+// matrix cores (v_mfma_f64_16x16x4f64: A(i, k) from lane i + 16 k, B(k, j)
+// from lane j + 16 k, C(4 q + lane / 16, lane % 16) in register q).  Four
+// accumulators u = 0..3 hold the rows 64 I + 4 i + u, and step s of a
+// 16-column tile J takes the columns 16 J + 4 k + s, so that every lane loads
+// four consecutive stored entries at once: four rows of one column left of the
+// diagonal (feeding the four accumulators), four rows of a mirror column right
+// of it (feeding the four steps); tiles that cross the diagonal are read entry
+// by entry.  M^i is read twice, both times once per block of BK columns.
+constexpr int BLK_SYMV_WAVES = 8;   // at most
+
+template <typename TS>
+__global__ __launch_bounds__(64 * BLK_SYMV_WAVES) void k_blk_symv(DevGeom g, const TS *__restrict__ M,
+                                                                  const int64_t *__restrict__ pk,
+                                                                  const double *__restrict__ X, double xscale,
+                                                                  const double *__restrict__ xw,
+                                                                  double *__restrict__ yloc, const CgBlockState *st) {
+  extern __shared__ double xs[];
+  if (blk_done(st)) return;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  for (int i = blockIdx.x; i < g.N; i += gridDim.x) {
+    const int n = g.nG[i], nb = (n + 15) >> 4, np = 4 * ((n + 3) / 4);
+    const int64_t go = g.g_off[i];
+    for (int e = tid; e < nb * 16 * BK; e += blockDim.x) {
+      const int r = e / BK, j = e % BK;
+      xs[e] = (r < n) ? (xw ? xw[go + r] : xscale) * X[(int64_t)g.Rmap[go + r] * BK + j] : 0.0;
+    }
+    __syncthreads();
+    const TS *Mi = M + pk[i];
+    for (int I = wv; 64 * I < n; I += (int)(blockDim.x >> 6)) {
+      f64x4 acc[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u] = f64x4{0.0, 0.0, 0.0, 0.0};
+      const int r0 = 64 * I + 4 * li;   // this lane's rows r0 + u (accumulator u)
+      for (int J = 0; J < nb; ++J) {
+        const int cl = 16 * J + 4 * lk;   // this lane's columns cl + s (step s)
+        double b[4];
+#pragma unroll
+        for (int s2 = 0; s2 < 4; ++s2) b[s2] = xs[(cl + s2) * BK + li];
+        const bool left = 16 * J + 15 <= 64 * I, right = 16 * J >= 64 * I + 64;
+        if (left || right) {
+          // four 16-byte loads: left of the diagonal load k is rows r0 .. r0 + 3
+          // of column cl + k (one entry per accumulator), right of it rows
+          // cl .. cl + 3 of the mirror column r0 + k (one entry per step)
+          double a[4][4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            a[k][0] = a[k][1] = a[k][2] = a[k][3] = 0.0;
+            if (left ? (r0 < np) : (r0 + k < n && cl < np))
+              load4(Mi + (left ? gp_index(n, r0, cl + k) : gp_index(n, cl, r0 + k)), a[k]);
+          }
+          if (left) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+#pragma unroll
+              for (int u = 0; u < 4; ++u) acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[k][u], b[k], acc[u], 0, 0, 0);
+          } else {
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+#pragma unroll
+              for (int s2 = 0; s2 < 4; ++s2)
+                acc[k] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[k][s2], b[s2], acc[k], 0, 0, 0);
+          }
+        } else {
+          // the tile crosses the diagonal: entry by entry
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int s2 = 0; s2 < 4; ++s2) {
+              const int r = r0 + u, c = cl + s2;
+              const double a = (r < n && c < n) ? sym_entry(Mi, n, r, c) : 0.0;
+              acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[s2], acc[u], 0, 0, 0);
+            }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int row = 64 * I + 16 * q + 4 * lk + u;
+          if (row < n) yloc[(go + row) * BK + li] = acc[u][q];
+        }
+    }
+    __syncthreads();   // LDS is reused by the next subdomain
+  }
+}
+
+// g^i = Psi^{iT} (w * R_i X) for the BK columns, added into the coarse
+// right-hand sides b at the coarse dofs: as in the
+// single-column kernel, a face's coarse dof gets the pieces of its two
+// subdomains onto zero, the same sum in either order.  The waves split the
+// 16-row blocks of Psi^i, C(i, j) = sum_k Psi(k, 16 K + i) X(k, j) on the
+// matrix cores (A(i, k) from lane i + 16 k: four consecutive rows of one column
+// per lane quad), and their four partial tiles are added in LDS, wave after
+// wave (a fixed order in 2 KB, so that X of interfaces up to 1,232 dofs fits).
+template <typename TS>
+__global__ __launch_bounds__(256) void k_blk_psi_apply(DevGeom g, const TS *__restrict__ Psi,
+                                                       const int64_t *__restrict__ psi_off,
+                                                       const int *__restrict__ sub_coff,
+                                                       const int *__restrict__ sub_cmap, const double *__restrict__ X,
+                                                       double xscale, const double *__restrict__ xw,
+                                                       double *__restrict__ b, const CgBlockState *st) {
+  extern __shared__ double sh[];
+  if (blk_done(st)) return;
+  const int i = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int n = g.nG[i], nb = (n + 15) >> 4, ldp = ld4(n);
+  const int64_t go = g.g_off[i];
+  double *xs = sh, *red = sh + nb * 16 * BK;   // red: one 16 x 16 tile
+  for (int e = tid; e < nb * 16 * BK; e += 256) {
+    const int r = e / BK, j = e % BK;
+    xs[e] = (r < n) ? (xw ? xw[go + r] : xscale) * X[(int64_t)g.Rmap[go + r] * BK + j] : 0.0;
+  }
+  __syncthreads();
+  const int c0 = sub_coff[i], nci = sub_coff[i + 1] - c0;
+  const TS *P = Psi + psi_off[i];
+  for (int K = 0; 16 * K < nci; ++K) {
+    f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+    const int c = 16 * K + li;
+    for (int R = wv; R < nb; R += 4) {
+      double a[4];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int r = 16 * R + 4 * s + lk;
+        a[s] = (c < nci && r < n) ? (double)P[(int64_t)c * ldp + r] : 0.0;
+      }
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], xs[(16 * R + 4 * s + lk) * BK + li], acc, 0, 0, 0);
+    }
+    for (int w = 0; w < 4; ++w) {
+      if (wv == w) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) red[q * 64 + lane] = (w == 0 ? 0.0 : red[q * 64 + lane]) + acc[q];
+      }
+      __syncthreads();
+    }
+    {
+      const int q = tid >> 6, l = tid & 63;
+      const int cc = 16 * K + 4 * q + (l >> 4), j = l & 15;
+      if (cc < nci) atomicAdd(b + (int64_t)sub_cmap[c0 + cc] * BK + j, red[q * 64 + l]);
+    }
+    __syncthreads();
+  }
+}
+
+// W^i = Psi^i alpha^(i) for the BK columns (alpha gathered from the coarse
+// solutions into LDS, [nc^i][BK]); wave w forms the 16-row blocks w, w + 4, ...
+// (A(i, k) = Psi(16 R + i, 16 K + 4 s + k): 16 consecutive rows of a column
+// per 16 lanes).
+template <typename TS>
+__global__ __launch_bounds__(256) void k_blk_psi_correct(DevGeom g, DevCoarse cs, const TS *__restrict__ Psi,
+                                                         const int64_t *__restrict__ psi_off,
+                                                         const double *__restrict__ csolb,
+                                                         double *__restrict__ wloc, const CgBlockState *st) {
+  extern __shared__ double al[];
+  if (blk_done(st)) return;
+  const int i = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int n = g.nG[i], nb = (n + 15) >> 4, ldp = ld4(n);
+  const int64_t go = g.g_off[i];
+  const int c0 = cs.sub_coff[i], nci = cs.sub_coff[i + 1] - c0, ncb = (nci + 15) >> 4;
+  for (int e = tid; e < ncb * 16 * BK; e += 256) {
+    const int c = e / BK, j = e % BK;
+    al[e] = (c < nci) ? csolb[(int64_t)cs.sub_cmap[c0 + c] * BK + j] : 0.0;
+  }
+  __syncthreads();
+  const TS *P = Psi + psi_off[i];
+  for (int R = wv; R < nb; R += 4) {
+    f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+    const int r = 16 * R + li;
+    for (int K = 0; K < ncb; ++K) {
+      double a[4];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int c = 16 * K + 4 * s + lk;
+        a[s] = (r < n && c < nci) ? (double)P[(int64_t)c * ldp + r] : 0.0;
+      }
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], al[(16 * K + 4 * s + lk) * BK + li], acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int row = 16 * R + 4 * q + lk;
+      if (row < n) wloc[(go + row) * BK + li] = acc[q];
+    }
+  }
+}
+
+// z = E (y + w) per column (multiplicity or stiffness weights), then each
+// face's total set to its zero-net-flux coarse dof; partials of r.z.  One
+// face per wave (lanes: column lane % 16, every fourth dof from lane / 16).
+__global__ __launch_bounds__(256) void k_blk_average(DevGeom g, DevCoarse cs, const double *__restrict__ wloc,
+                                                     const double *__restrict__ yloc,
+                                                     const double *__restrict__ csolb,
+                                                     double *__restrict__ z, const double *__restrict__ r,
+                                                     double *part, const CgBlockState *st) {
+  __shared__ double red[256];
+  if (blk_done(st)) return;
+  const int lane = threadIdx.x & 63, j = lane & 15, lk = lane >> 4;
+  double v = 0.0;
+  for (int f = blockIdx.x * 4 + (threadIdx.x >> 6); f < g.nF; f += gridDim.x * 4) {
+    const int n = g.f_n[f];
+    const int64_t base = g.g_off[g.f_minus[f]] + g.f_loffm[f];
+    const bool sw = g.fw_minus != nullptr;
+    const double wm = sw ? g.fw_minus[f] : 0.5, wp = sw ? g.fw_plus[f] : 0.5;
+    double tsum = 0.0;
+    for (int a = lk; a < n; a += 4) {
+      const int64_t km = (base + a) * BK + j, kp = (int64_t)g.own_plus[g.Rmap[base + a]] * BK + j;
+      tsum += wm * (yloc[km] + wloc[km]) + wp * (yloc[kp] + wloc[kp]);
+    }
+    tsum += __shfl_xor(tsum, 16, 64);
+    tsum += __shfl_xor(tsum, 32, 64);
+    const double corr = (csolb[(int64_t)cs.face_cofs[f] * BK + j] - tsum) / n;
+    for (int a = lk; a < n; a += 4) {
+      const int gi = g.Rmap[base + a];
+      const int64_t km = (base + a) * BK + j, kp = (int64_t)g.own_plus[gi] * BK + j;
+      const double wsm = yloc[km] + wloc[km], wsp = yloc[kp] + wloc[kp];
+      const double zz = (sw ? wm * wsm + wp * wsp : 0.5 * (wsm + wsp)) + corr;
+      z[(int64_t)gi * BK + j] = zz;
+      v = fma(r[(int64_t)gi * BK + j], zz, v);
+    }
+  }
+  col_partial(v, part, red);
+}
+
+// ---- coarse sweeps ---------------------------------------------------------------
+// The sweeps of coarse.hip for the BK columns, with the coarse vectors
+// interleaved ([dof][BK], like the interface vectors).  A task is 64 rows
+// (forward) or 64 columns (backward) of one front, a 16-row (16-column) block
+// per wave, on the matrix cores: each entry of R is read once per block of BK
+// columns.  Task descriptor, three int4: {first row / column, n, m, first
+// dof}, {v_off, b_off, child slot, 0}, {r_off low, r_off high, 0, 0}.
+constexpr int BLK_SWEEP_ROWS = 64;
+
+// Forward: t_p = b_P + S0_p[P] + S1_p[P] staged in LDS ([n][BK]); rows r < n
+// of R = [L_PP^{-1}; L_BP L_PP^{-1}] (packed lower triangle, then m full rows)
+// give z_P[r], rows n + k push w_p[k] = S0_p[B] + S1_p[B] - row . t_p into
+// the parent's slot array.
+__global__ __launch_bounds__(256) void k_blk_nd_fwd(int t0, const int4 *__restrict__ task,
+                                                    const double *__restrict__ FR, const int *__restrict__ wdst,
+                                                    const double *__restrict__ b, double *S0, double *S1,
+                                                    double *__restrict__ z, const CgBlockState *st) {
+  extern __shared__ double tl[];
+  const int4 *td = task + 3 * (int64_t)(t0 + blockIdx.x);
+  const int4 d0 = td[0], d1 = td[1], d2 = td[2];
+  if (blk_done(st)) return;
+  const int j0 = d0.x, n = d0.y, m = d0.z, fst = d0.w, vo = d1.x, bo = d1.y, slot = d1.z;
+  const int64_t ro = (int64_t)(((uint64_t)(uint32_t)d2.y << 32) | (uint32_t)d2.x);
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, li = lane & 15, lk = lane >> 4;
+  const int n4 = (n + 3) & ~3;
+  for (int e = tid; e < n4 * BK; e += 256) {
+    const int c = e / BK, j = e % BK;
+    tl[e] = c < n ? (b[(int64_t)(fst + c) * BK + j] + S0[(int64_t)(vo + c) * BK + j]) + S1[(int64_t)(vo + c) * BK + j]
+                  : 0.0;
+  }
+  __syncthreads();
+  const int rb = j0 + 16 * wv;
+  if (rb >= n + m) return;
+  const int r = rb + li;
+  const double *row;
+  int len;
+  if (r < n) {
+    row = FR + ro + (int64_t)r * (r + 1) / 2;
+    len = r + 1;
+  } else {
+    row = FR + ro + (int64_t)n * (n + 1) / 2 + (int64_t)(r - n) * n;
+    len = r < n + m ? n : 0;
+  }
+  const int kend = min(n4, (rb + 16 < n) ? ((rb + 16 + 3) & ~3) : n4);   // rows below n stop at their diagonal
+  f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+  for (int k0 = 0; k0 < kend; k0 += 4) {
+    const int k = k0 + lk;
+    const double a = k < len ? row[k] : 0.0;
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, tl[k * BK + li], acc, 0, 0, 0);
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int rr = rb + 4 * q + lk;
+    if (rr < n) {
+      z[(int64_t)(fst + rr) * BK + li] = acc[q];
+    } else if (rr < n + m) {
+      const double base = S0[(int64_t)(vo + rr) * BK + li] + S1[(int64_t)(vo + rr) * BK + li];
+      (slot ? S1 : S0)[(int64_t)wdst[bo + (rr - n)] * BK + li] = base - acc[q];
+    }
+  }
+}
+
+// Backward: columns c of the packed lower trapezoid BC (column c holds rows
+// c .. n + m - 1): x_c = sum_rho BC(rho, c) in(rho), in = s z on the own dofs
+// and -x_B on the B part; each x[d] is also stored into every B vector that
+// holds d.  in is read from the (L2 resident) vectors, four rows of BK per step.
+__global__ __launch_bounds__(256) void k_blk_nd_bwd(int t0, const int4 *__restrict__ task,
+                                                    const double *__restrict__ BC, const double *__restrict__ z,
+                                                    const double *__restrict__ sg, const int *__restrict__ xsc_off,
+                                                    const int *__restrict__ xsc, double *XB, double *__restrict__ x,
+                                                    const CgBlockState *st) {
+  const int4 *td = task + 3 * (int64_t)(t0 + blockIdx.x);
+  const int4 d0 = td[0], d1 = td[1], d2 = td[2];
+  if (blk_done(st)) return;
+  const int c0 = d0.x, n = d0.y, m = d0.z, fst = d0.w, bo = d1.y;
+  const int64_t ro = (int64_t)(((uint64_t)(uint32_t)d2.y << 32) | (uint32_t)d2.x);
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, li = lane & 15, lk = lane >> 4;
+  const int cb = c0 + 16 * wv;
+  if (cb >= n) return;
+  const int f = n + m, c = cb + li;
+  const double *col = BC + ro + (int64_t)c * f - (int64_t)c * (c - 1) / 2 - c;   // col[rho], rho >= c
+  f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+  const int rho0 = cb & ~3;
+#pragma unroll 4
+  for (int k0 = rho0; k0 < f; k0 += 4) {
+    const int rho = k0 + lk;
+    const double a = (c < n && rho >= c && rho < f) ? col[rho] : 0.0;
+    double in = 0.0;
+    if (rho < n) in = sg[fst + rho] * z[(int64_t)(fst + rho) * BK + li];
+    else if (rho < f) in = -XB[(int64_t)(bo + rho - n) * BK + li];
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, in, acc, 0, 0, 0);
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int cc = cb + 4 * q + lk;
+    if (cc < n) {
+      const int d = fst + cc;
+      x[(int64_t)d * BK + li] = acc[q];
+      for (int p = xsc_off[d]; p < xsc_off[d + 1]; ++p) XB[(int64_t)xsc[p] * BK + li] = acc[q];
+    }
+  }
+}
+
+// ---- dense top block of the coarse solve ------------------------------------------
+// t_t[t][j] = b_j[d0 + t] + the updates the swept fronts pushed for that dof
+__global__ __launch_bounds__(256) void k_blk_top_gather(int nt, int d0, const int *__restrict__ tg_off,
+                                                        const int *__restrict__ tg, const double *__restrict__ b,
+                                                        const double *__restrict__ S0, const double *__restrict__ S1,
+                                                        double *__restrict__ tt, const CgBlockState *st) {
+  if (blk_done(st)) return;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)nt * BK) return;
+  const int t = (int)(e / BK), j = (int)(e % BK);
+  double v = b[(int64_t)(d0 + t) * BK + j];
+  for (int q = tg_off[t]; q < tg_off[t + 1]; ++q) v += S0[(int64_t)tg[q] * BK + j] + S1[(int64_t)tg[q] * BK + j];
+  tt[e] = v;
+}
+
+// x_t = S_t^{-1} t_t for the rows [16 blockIdx.x, 16 blockIdx.x + 16) and the
+// BK columns: eight waves split the columns of S_t^{-1} (row major, ld),
+// A(i, k) = S_t^{-1}(16 I + i, k0 + 4 s + k) (four consecutive entries of a row
+// per lane quad), B(k, j) = t_t(k0 + 4 s + k, j), eight steps of loads in
+// flight per lane; the partial tiles meet in LDS in a fixed order.  Each x[d]
+// is also stored into every B vector holding d (for the backward sweeps of
+// the levels below).
+constexpr int TOP_GEMM_WAVES = 8;
+
+__global__ __launch_bounds__(64 * TOP_GEMM_WAVES) void k_blk_top_gemm(int nt, int ld, const double *__restrict__ Kt,
+                                                                      const double *__restrict__ tt, int d0,
+                                                                      const int *__restrict__ xsc_off,
+                                                                      const int *__restrict__ xsc,
+                                                                      double *__restrict__ XB,
+                                                                      double *__restrict__ x,
+                                                                      const CgBlockState *st) {
+  __shared__ double red[TOP_GEMM_WAVES * 256];
+  if (blk_done(st)) return;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int r = 16 * blockIdx.x + li;
+  const int nk4 = (nt + 3) / 4, per = (nk4 + TOP_GEMM_WAVES - 1) / TOP_GEMM_WAVES;
+  const int s0 = wv * per, s1 = min(nk4, s0 + per);
+  f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+  const double *row = Kt + (int64_t)min(r, nt - 1) * ld;
+  for (int s = s0; s < s1; s += 8) {
+    double a[8], bv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int k = 4 * (s + u) + lk;
+      const bool ok = s + u < s1 && k < nt;
+      a[u] = (ok && r < nt) ? row[k] : 0.0;
+      bv[u] = ok ? tt[(int64_t)k * BK + li] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], bv[u], acc, 0, 0, 0);
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) red[wv * 256 + q * 64 + lane] = acc[q];
+  __syncthreads();
+  if (tid >= 256) return;
+  const int q = tid >> 6, l = tid & 63;
+  double v = 0.0;
+#pragma unroll
+  for (int w = 0; w < TOP_GEMM_WAVES; ++w) v += red[w * 256 + q * 64 + l];
+  const int rr = 16 * blockIdx.x + 4 * q + (l >> 4), j = l & 15;
+  if (rr < nt) {
+    const int d = d0 + rr;
+    x[(int64_t)d * BK + j] = v;
+    for (int p = xsc_off[d]; p < xsc_off[d + 1]; ++p) XB[(int64_t)xsc[p] * BK + j] = v;
+  }
+}
+
+template __global__ void k_blk_symv<double>(DevGeom, const double *, const int64_t *, const double *, double,
+                                            const double *, double *, const CgBlockState *);
+template __global__ void k_blk_symv<float>(DevGeom, const float *, const int64_t *, const double *, double,
+                                           const double *, double *, const CgBlockState *);
+template __global__ void k_blk_psi_apply<double>(DevGeom, const double *, const int64_t *, const int *, const int *,
+                                                 const double *, double, const double *, double *,
+                                                 const CgBlockState *);
+template __global__ void k_blk_psi_apply<float>(DevGeom, const float *, const int64_t *, const int *, const int *,
+                                                const double *, double, const double *, double *,
+                                                const CgBlockState *);
+template __global__ void k_blk_psi_correct<double>(DevGeom, DevCoarse, const double *, const int64_t *,
+                                                   const double *, double *, const CgBlockState *);
+template __global__ void k_blk_psi_correct<float>(DevGeom, DevCoarse, const float *, const int64_t *, const double *,
+                                                  double *, const CgBlockState *);
+
+}  // namespace bddc

@@ -144,17 +144,21 @@ __global__ __launch_bounds__(256) void k_front_schur(DevFronts fd, const int4 *_
                                   sgn + fd.first[p]);
 }
 
-// Columns of S_t^{-1} (setup of the dense top block): the forward and backward
-// sweep tasks of coarse.hip for TOP_NC unit right-hand sides at once, so that
-// each entry of R is read once per TOP_NC columns.  Every column's sums run in
-// the order of the single-column tasks (same results).
+// Several right-hand sides of the coarse solve at once (the columns of
+// S_t^{-1} at setup, the block CG's coarse solves): the forward and backward
+// sweep tasks of coarse.hip for TOP_NC columns per workgroup, so that each
+// entry of R is read once per TOP_NC columns.  Every column's sums run in the
+// order of the single-column tasks (same results).  Columns are stored one
+// after the other (strides sk, sv, sb); done: optional stop flag.
 constexpr int TOP_NC = 4;
 
 __global__ __launch_bounds__(256) void k_top_fwd_cols(int t0, DevSweep sw, const double *__restrict__ FR,
                                                       const double *__restrict__ b, double *S0, double *S1,
-                                                      double *__restrict__ z, int64_t sk, int64_t sv, int ncols) {
+                                                      double *__restrict__ z, int64_t sk, int64_t sv, int ncols,
+                                                      const int *done) {
   const int4 *td = sw.task + 4 * (int64_t)(t0 + blockIdx.x);
   const int4 d0 = td[0], d1 = td[1], d2 = td[2];
+  if (done && *done) return;
   const int c0 = blockIdx.y * TOP_NC, nq = min(TOP_NC, ncols - c0);
   const int g = d0.z, n = d0.w, m = d1.x, fst = d1.y, vo = d1.z, bo = d1.w;
   const int64_t ro = (int64_t)(((uint64_t)(uint32_t)d2.y << 32) | (uint32_t)d2.x);
@@ -209,9 +213,10 @@ __global__ __launch_bounds__(256) void k_top_fwd_cols(int t0, DevSweep sw, const
 __global__ __launch_bounds__(256) void k_top_bwd_cols(int t0, DevSweep sw, const double *__restrict__ BC,
                                                       const double *__restrict__ z, const double *__restrict__ sg,
                                                       double *XB, double *__restrict__ x, int64_t sk, int64_t sb,
-                                                      int ncols) {
+                                                      int ncols, const int *done) {
   const int4 *td = sw.task + 4 * (int64_t)(t0 + blockIdx.x);
   const int4 d0 = td[0], d1 = td[1], d2 = td[2];
+  if (done && *done) return;
   const int c0 = blockIdx.y * TOP_NC, nq = min(TOP_NC, ncols - c0);
   const int g = d0.z, n = d0.w, m = d1.x, fst = d1.y, bo = d1.w;
   const int64_t ro = (int64_t)(((uint64_t)(uint32_t)d2.y << 32) | (uint32_t)d2.x);
