@@ -265,30 +265,36 @@ SERVE_DESC = ("Poisson stream (mean 50 requests/s, seeded) of independent solves
               "wells, tau off or 10, rtol 1e-8; setup and solve per request")
 
 
-def serve_stream(precision, requests, arrivals, max_active=4, setup_workers=2):
-    """Submit `requests` at their arrival times (s from start) and wait for all."""
+def serve_stream(precision, requests, arrivals, max_active=4, setup_workers=2, sources=None, keys=None):
+    """Submit `requests` at their arrival times (s from start) and wait for all
+    (sources / keys: per request, in place of the request's own source / 0)."""
     from paper_1901_02090_amd import Server
     srv = Server(precision=precision, max_active=max_active, setup_workers=setup_workers)
     try:
         tickets = []
         t0 = time.perf_counter()
-        for pr, ta in zip(requests, arrivals):
+        for k, (pr, ta) in enumerate(zip(requests, arrivals)):
             dt = ta - (time.perf_counter() - t0)
             if dt > 0:
                 time.sleep(dt)
-            tickets.append(srv.submit(pr.n, pr.h, pr.perm, pr.cuts, pr.source, tau=pr.tau, rtol=pr.rtol))
-        its, conv = [], 0
+            src = pr.source if sources is None else sources[k]
+            key = 0 if keys is None else keys[k]
+            tickets.append(srv.submit(pr.n, pr.h, pr.perm, pr.cuts, src, tau=pr.tau, rtol=pr.rtol, key=key))
+        its, conv, batch, reused = [], 0, [], 0
         for t in tickets:
             _, _, st = srv.result(t)
             its.append(st["it"])
             conv += st["converged"]
+            batch.append(st["batch"])
+            reused += st["reused"]
         wall = time.perf_counter() - t0
         ss = srv.stats()
     finally:
         srv.close()
     return {"solves_per_s": ss["solves_per_s"], "p50_ms": ss["p50_ms"], "p99_ms": ss["p99_ms"],
             "completed": ss["completed"], "converged": conv, "wall_s": wall, "peak_active": ss["peak_active"],
-            "peak_bytes": ss["peak_bytes"], "mean_iterations": float(np.mean(its))}
+            "peak_bytes": ss["peak_bytes"], "mean_iterations": float(np.mean(its)),
+            "mean_batch": float(np.mean(batch)), "max_batch": int(max(batch)), "reused": int(reused)}
 
 
 def serving(n_req, rate=50.0, seed=0):
@@ -299,6 +305,29 @@ def serving(n_req, rate=50.0, seed=0):
            "setup_workers": 2, "dims": {"2d": sum(r.dim == 2 for r in reqs), "3d": sum(r.dim == 3 for r in reqs)}}
     for prec in ("fp64", "mixed"):
         out[prec] = serve_stream(prec, reqs, arr)
+    return out
+
+
+SERVE_KEYED_DESC = ("Poisson stream (mean {rate:g} requests/s, seeded) over {np} resident problems (2D 32x125, 45x127, "
+                    "55x80 and a 60x220x17 slab, channelised fields, tau 10, rtol 1e-8), each request its own seeded "
+                    "wells: with problem keys the problem is set up once and the waiting requests of a key are "
+                    "solved together (bddc_solve_block); without keys every request sets its problem up")
+
+
+def serving_keyed(n_req, rate=200.0, seed=1):
+    """The same problems requested again and again: keyed (resident, batched) against unkeyed."""
+    import workloads as W
+    base = [W.serving_request(sd) for sd in (6, 11, 12, 7)]
+    rng = np.random.default_rng(seed)
+    pick = rng.integers(0, len(base), n_req)
+    reqs = [base[p] for p in pick]
+    srcs = [W.seeded_wells(base[p].n, rng) for p in pick]
+    arr = W.poisson_arrivals(rate, n_req, seed)
+    out = {"workload": SERVE_KEYED_DESC.format(rate=rate, np=len(base)), "requests": n_req,
+           "arrival_rate_per_s": rate, "max_active": 4, "setup_workers": 2}
+    for prec in ("fp64", "mixed"):
+        out[prec] = {"keyed": serve_stream(prec, reqs, arr, sources=srcs, keys=[int(p) + 1 for p in pick]),
+                     "unkeyed": serve_stream(prec, reqs, arr, sources=srcs)}
     return out
 
 
@@ -347,6 +376,71 @@ def kernels_only(pr, reps):
                       "copy_bytes": COPY_BYTES, "reps": reps}), flush=True)
 
 
+BLOCK_DESC = ("the same 60x220x85 field cut into uneven boxes (seeded cut planes, widths 4..16 cells; 1,260 "
+              "subdomains, interfaces up to 1,224 dofs), tau=5, {k} seeded well placements solved together "
+              "(bddc_solve_block: blocks of 16 sources per CG iteration), rtol 1e-8")
+FP64_MFMA_PEAK_TFS = 78.6
+
+
+def block_batch(nsrc):
+    """Several sources on one resident problem: the block CG against one solve
+    after the other (both device pointers), with the block kernels' rooflines."""
+    import torch
+    import workloads as W
+    from paper_1901_02090_amd import Solver
+    from paper_1901_02090_amd.bddc import K_BLOCK_SCHUR, K_BLOCK_PRECOND_FULL
+    full = W.reservoir_3d(nz=85, seed=0, tau=5.0)
+    cuts = W.seeded_cuts(full.n, 4, 16, 0)
+    srcs = np.stack([W.seeded_wells(full.n, np.random.default_rng(100 + k)) for k in range(nsrc)])
+    t0 = time.perf_counter()
+    s = Solver(full.n, full.h, full.perm, cuts, tau=5.0, precision="mixed", max_it=3000)
+    setup_s = time.perf_counter() - t0
+    try:
+        d_src = torch.tensor(srcs, dtype=torch.float64, device="cuda")
+        d_f = torch.empty((nsrc, s.n_faces_all), dtype=torch.float64, device="cuda")
+        d_p = torch.empty((nsrc, s.n_cells), dtype=torch.float64, device="cuda")
+        s.solve_block_device(nsrc, d_src.data_ptr(), 1e-8, d_f.data_ptr(), d_p.data_ptr())   # first call allocates
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        its_b = s.solve_block_device(nsrc, d_src.data_ptr(), 1e-8, d_f.data_ptr(), d_p.data_ptr())
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t
+        st = s.stats()
+        fb = d_f.cpu().numpy()
+        t = time.perf_counter()
+        its_1 = []
+        for k in range(nsrc):
+            s.solve_device(d_src[k].data_ptr(), 1e-8, d_f[k].data_ptr(), d_p[k].data_ptr())
+            its_1.append(s.stats()["it"])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter() - t
+        f1 = d_f.cpu().numpy()
+        err = max(float(np.linalg.norm(fb[k] - f1[k]) / np.linalg.norm(f1[k])) for k in range(nsrc))
+        ms_s, by_s = s.time_kernel(K_BLOCK_SCHUR, 20)
+        ms_p, by_p = s.time_kernel(K_BLOCK_PRECOND_FULL, 16)
+        fl = st["flops_block_local"]
+    finally:
+        s.close()
+    ach = by_s / (ms_s * 1e-3) / 1e9
+    tfs = fl / (ms_s * 1e-3) / 1e12
+    return {"workload": BLOCK_DESC.format(k=nsrc), "n_sub": int(st["n_sub"]), "setup_ms": setup_s * 1e3,
+            "solves_per_s": nsrc / tb, "ms": tb * 1e3,
+            "one_by_one": {"solves_per_s": nsrc / t1, "ms": t1 * 1e3, "precision": "mixed"},
+            "speedup": t1 / tb, "iterations": [int(its_b.min()), int(its_b.max())],
+            "iterations_equal_one_by_one": bool((np.array(its_1) == its_b).all()),
+            "max_flux_relerr_vs_one_by_one": err,
+            "dtype": "f64",
+            "roofline_block_schur": {
+                "kernel": "k_blk_symv<double> (S^i against 16 columns, 64 x 16 tiles on v_mfma_f64_16x16x4f64)",
+                "avg_launch_us": ms_s * 1e3, "bytes_per_launch": by_s, "flops_per_launch": fl,
+                "hbm": {"achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS},
+                "mfma": {"achieved": tfs, "peak": FP64_MFMA_PEAK_TFS, "unit": "TFLOP/s",
+                         "frac": tfs / FP64_MFMA_PEAK_TFS},
+                "note": "bytes count each packed entry once; the kernel reads the mirror half a second time"},
+            "block_precond_apply": {"avg_us": ms_p * 1e3, "bytes": by_p,
+                                    "achieved_gbs": by_p / (ms_p * 1e-3) / 1e9}}
+
+
 def main():
     faulthandler.enable()
     ap = argparse.ArgumentParser(description=__doc__)
@@ -359,6 +453,9 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=48,
                     help="requests of a served Poisson stream (mean 50/s) through bddc_server_* in both forms "
                          "(0: not run)")
+    ap.add_argument("--block-sources", type=int, default=32,
+                    help="sources of the block-solve workload (uneven boxes, tau 5), solved together and one by "
+                         "one (0: not run)")
     ap.add_argument("--kernels-only", action="store_true",
                     help="set up the mixed form, solve once, launch the S^i and T^i apply kernels alone, the "
                          "whole preconditioner, and a plain device copy of known size (for scaling hardware "
@@ -454,6 +551,8 @@ def main():
         "roofline": roof,
         "precond_apply": prec,
     }
+    if args.block_sources > 0:
+        out["batch"] = block_batch(args.block_sources)
     if args.serve_requests > 0:
         # The server's handles take device memory with the library's own
         # hipMalloc: its setup workers and driver are native threads, and the
@@ -466,6 +565,7 @@ def main():
             set_allocator()
             torch.cuda.empty_cache()
         out["serving"] = dict(serving(args.serve_requests), allocator="hipMalloc")
+        out["serving_resident"] = dict(serving_keyed(64), allocator="hipMalloc")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pr, args.cpu_seconds, st["it"])
     print(json.dumps(out), flush=True)

@@ -377,6 +377,19 @@ int bddc_estimate_bytes(const bddc_grid *g, const bddc_partition *part, double t
  * the requests' kernels overlap on the device, and a request that finishes
  * frees its memory and slot for the next.  Every request's arithmetic is that
  * of bddc_solve on its own handle: its result does not depend on the mix.
+ *
+ * Resident problems and batched solves: requests that carry the same nonzero
+ * problem_key name one problem (the caller promises equal permeability; the
+ * server checks grid, partition and tau, and the source's compatibility at
+ * submission, BDDC_EINVAL otherwise).  The first
+ * one is admitted and set up like any request; its problem then stays
+ * resident (its bytes count against mem_cap) and later requests of the key
+ * skip the setup.  The requests of a key that are waiting together (up to 16,
+ * equal rtol) are solved as one block of bddc_solve_block: one pass over the
+ * problem's operators per CG iteration serves all of them, and each result
+ * equals its own single solve to rounding.  An idle resident problem is
+ * released when a queued request needs its memory, or at
+ * bddc_server_destroy.
  * ------------------------------------------------------------------------ */
 typedef struct bddc_server *bddc_server_handle;
 
@@ -396,7 +409,8 @@ typedef struct {
   double tau;             /* as for bddc_setup                              */
   const double *rhs;      /* [n_cells] cell sources summing to 0; copied     */
   double rtol;            /* > 0                                            */
-  int32_t max_it;         /* <= 0: 10000                                    */
+  int32_t max_it;         /* <= 0: 10000 (a keyed problem keeps its first)  */
+  uint64_t problem_key;   /* 0: an independent problem; else see above      */
 } bddc_request;
 
 typedef struct {
@@ -411,6 +425,8 @@ typedef struct {
   double est_bytes;       /* admission estimate                             */
   double device_bytes;    /* bytes the problem held while solving           */
   double peak_bytes;      /* high-water mark during its setup               */
+  int32_t batch;          /* sources solved together with it (1: alone)     */
+  int32_t reused;         /* 1: its problem was resident (no setup)         */
 } bddc_request_stats;
 
 typedef struct {

@@ -67,14 +67,16 @@ class ServerOptions(C.Structure):
 
 class Request(C.Structure):
     _fields_ = [("grid", Grid), ("perm", C.POINTER(C.c_double)), ("part", Partition), ("tau", C.c_double),
-                ("rhs", C.POINTER(C.c_double)), ("rtol", C.c_double), ("max_it", C.c_int32)]
+                ("rhs", C.POINTER(C.c_double)), ("rtol", C.c_double), ("max_it", C.c_int32),
+                ("problem_key", C.c_uint64)]
 
 
 class RequestStats(C.Structure):
     _fields_ = [("status", C.c_int32), ("it", C.c_int32), ("converged", C.c_int32), ("relres", C.c_double),
                 ("kappa", C.c_double), ("n_sub", C.c_int32), ("n_coarse", C.c_int32), ("queue_ms", C.c_double),
                 ("setup_ms", C.c_double), ("solve_ms", C.c_double), ("latency_ms", C.c_double),
-                ("est_bytes", C.c_double), ("device_bytes", C.c_double), ("peak_bytes", C.c_double)]
+                ("est_bytes", C.c_double), ("device_bytes", C.c_double), ("peak_bytes", C.c_double),
+                ("batch", C.c_int32), ("reused", C.c_int32)]
 
 
 class ServerStats(C.Structure):
@@ -421,12 +423,13 @@ class Server:
         _check(lib, lib.bddc_server_create(C.byref(opt), C.byref(self.h)))
         self._sizes = {}
 
-    def submit(self, n, h, perm, cuts, source, tau=math.inf, rtol=1e-8, max_it=10000):
-        """Queue one problem; returns its ticket at once (inputs are copied)."""
+    def submit(self, n, h, perm, cuts, source, tau=math.inf, rtol=1e-8, max_it=10000, key=0):
+        """Queue one problem; returns its ticket at once (inputs are copied).  key: nonzero for a
+        problem that stays resident and is shared (and its solves batched) by the requests of that key."""
         g, part, keep = _grid_part(n, h, cuts)
         perm = np.ascontiguousarray(perm, dtype=np.float64).reshape(-1)
         src = np.ascontiguousarray(source, dtype=np.float64).reshape(-1)
-        req = Request(g, _dptr(perm), part, _tau(tau), _dptr(src), float(rtol), int(max_it))
+        req = Request(g, _dptr(perm), part, _tau(tau), _dptr(src), float(rtol), int(max_it), int(key))
         t = C.c_uint64()
         _check(self.lib, self.lib.bddc_server_submit(self.h, C.byref(req), C.byref(t)))
         dim = len(n)

@@ -1532,10 +1532,11 @@ void launch_iteration_blk(bddc_problem *h) {
 
 // Sources [0, k) of one block: steps 1-2 and the reduced right-hand side of
 // each (the single-source kernels), the block CG, and the post-correction of
-// each.  its[j] receives each source's CG iterations.  Returns the worst
-// status of the block.
+// each.  its[j], conv[j], relres[j] (each may be null) receive each source's
+// CG iterations, convergence flag and final relative residual.  Returns the
+// worst status of the block.
 int solve_block_of(bddc_problem *h, int k, const double *rhs, double rtol, double *flux, double *pressure,
-                   uint32_t flags, int32_t *its) {
+                   uint32_t flags, int32_t *its, int32_t *conv = nullptr, double *relres = nullptr) {
   const Layout &L = h->L;
   BlockWs &B = h->blk;
   const int N = L.N, nGm = L.nGamma;
@@ -1632,10 +1633,37 @@ int solve_block_of(bddc_problem *h, int k, const double *rhs, double rtol, doubl
   int rc = BDDC_OK;
   for (int j = 0; j < k; ++j) {
     if (its) its[j] = fs.nupd[j];
+    if (conv) conv[j] = fs.converged[j];
+    if (relres) relres[j] = fs.relres[j];
     if (fs.fail[j]) rc = BDDC_EBREAKDOWN;
     else if (!fs.converged[j] && rc == BDDC_OK) rc = BDDC_ENOCONV;
   }
   return rc;
+}
+
+// Up to BK sources on one handle (host buffers), for the request server: the
+// block CG, or single solves where there is no interface to iterate on.
+int block_solve_host(bddc_problem *h, int k, const double *rhs, double rtol, double *flux, double *pressure,
+                     int32_t *its, int32_t *conv, double *relres) {
+  if (k <= 0) return BDDC_OK;
+  if (k > BK) throw Error{BDDC_EINVAL, "at most 16 sources per block"};
+  const int64_t nc = h->L.ncells, nf = h->L.nfaces_all;
+  if (h->L.N <= 1 || h->L.nGamma == 0) {
+    int rc_all = BDDC_OK;
+    for (int j = 0; j < k; ++j) {
+      const int rc = do_solve(h, rhs + j * nc, rtol, flux + j * nf, pressure + j * nc, 0);
+      its[j] = h->stats.it;
+      conv[j] = h->stats.converged;
+      relres[j] = h->stats.relres;
+      if (rc != BDDC_OK) rc_all = rc;
+    }
+    return rc_all;
+  }
+  {
+    GateShared g(g_gate);
+    block_setup(h);
+  }
+  return solve_block_of(h, k, rhs, rtol, flux, pressure, 0, its, conv, relres);
 }
 
 void apply_options(bddc_problem *h, const bddc_options *opt) {

@@ -8,7 +8,13 @@
 //   driver         keeps up to two captured chunks of CG iterations in flight
 //                  for every solving request, reads each chunk's state when it
 //                  lands (event queries, no blocking), finishes converged
-//                  requests, destroys their handles and admits the next ones.
+//                  requests, destroys their handles and admits the next ones;
+//                  it also releases the idle resident problems that admission
+//                  evicted.
+// Requests with a problem key share one resident problem: the first sets it
+// up (a setup worker), and from then on the waiting requests of the key are
+// solved in blocks of up to 16 by a worker (bddc_solve_block's kernels), one
+// block after another, while the problem stays resident.
 // Requests of different sizes therefore overlap on the device: the kernels of
 // several CG chunks and of a setup run at once on different streams.  A
 // handle is touched by one thread at a time (its worker, then the driver).
@@ -47,8 +53,13 @@ Layout build_layout(const bddc_grid *gr, const bddc_partition *part) {
 }
 
 // Sum of the device arrays do_setup and the solve allocate, all taken as held
-// at once (the setup workspaces released along the way included).
-double estimate_bytes(const bddc_grid *gr, const bddc_partition *part, double tau, const bddc_options *opt) {
+// at once (the setup workspaces released along the way included); with
+// block_vectors, also those of the block CG (16 columns of every CG vector,
+// at most 10,000 iterations of coefficient history).
+constexpr int SRV_BLOCK = 16;
+
+double estimate_bytes(const bddc_grid *gr, const bddc_partition *part, double tau, const bddc_options *opt,
+                      bool block_vectors) {
   const Layout L = build_layout(gr, part);
   const int N = L.N, nF = L.nF, dim = L.dim;
   const bool allc = opt && (opt->flags & BDDC_ALL_CONSTRAINED);
@@ -104,6 +115,12 @@ double estimate_bytes(const bddc_grid *gr, const bddc_partition *part, double ta
       const double ld = (P.nt + 1) & ~1, cols = std::min(P.nt, TOP_BATCH);
       b += 8.0 * P.nt * ld + 8.0 * cols * (3 * nk + 2 * nv + std::max(nb, 1.0)) + 4.0 * (double)P.tg.size();
     }
+    if (block_vectors)
+      b += 8.0 * SRV_BLOCK * (3 * nk + 2 * nv + nb + P.nt) + 4.0 * 12.0 * 2.0 * (nv / 64.0 + 2.0 * nfr);
+  }
+  if (block_vectors) {
+    const int maxit = opt && opt->max_it > 0 ? opt->max_it : 10000;
+    b += 8.0 * SRV_BLOCK * (6.0 * L.nGamma + 2.0 * totG + 2.0 * N + 3.0 * 512 + 2.0 * (maxit + 2)) + 4096.0;
   }
   // CG and output vectors
   b += 8.0 * (7.0 * L.nGamma + 2.0 * N + 2.0 * totG + sum_nci + 6.0 * (double)L.ncells + (double)L.nfaces_all +
@@ -121,6 +138,8 @@ double ms_between(sclock::time_point a, sclock::time_point b) {
 
 namespace bddc {
 
+struct Resident;
+
 struct SrvRequest {
   uint64_t id = 0;
   bddc_grid grid{};
@@ -132,6 +151,8 @@ struct SrvRequest {
   double est = 0.0, held = 0.0;   // admission estimate; bytes counted against the cap now
   enum State { QUEUED, SETUP, SOLVING, DONE } state = QUEUED;
   bddc_problem *h = nullptr;
+  Resident *res = nullptr;        // keyed: the shared problem
+  bool reused = false;            // keyed and not the one that set it up
   int status = BDDC_OK;
   std::string err;
   bddc_request_stats st{};
@@ -147,6 +168,22 @@ struct SrvRequest {
   }
 };
 
+// A problem shared by the requests of one key: set up once, resident until
+// evicted or the server is destroyed.  busy: a worker owns it (setting it up
+// or solving blocks); ready: set up.
+struct Resident {
+  uint64_t key = 0;
+  bddc_grid grid{};
+  int32_t nsub[3] = {1, 1, 1};
+  std::vector<int32_t> cuts[3];
+  double tau = 0.0;
+  bddc_problem *h = nullptr;
+  bool ready = false, busy = true;
+  double held = 0.0;                   // bytes counted against the cap once set up
+  std::deque<SrvRequest *> pending;    // waiting to be solved
+  sclock::time_point last_use;
+};
+
 }  // namespace bddc
 
 struct bddc_server {
@@ -159,6 +196,9 @@ struct bddc_server {
   std::deque<SrvRequest *> to_setup;   // admitted, waiting for a worker
   std::vector<SrvRequest *> ready;     // set up, handed to the driver
   std::unordered_map<uint64_t, std::unique_ptr<SrvRequest>> reqs;
+  std::unordered_map<uint64_t, std::unique_ptr<Resident>> residents;   // by problem key
+  std::deque<Resident *> batch_jobs;   // ready residents with waiting requests, no worker on them
+  std::vector<std::unique_ptr<Resident>> evicted;   // released by the driver (outside the lock)
   uint64_t next_id = 1;
   double committed = 0.0, peak_committed = 0.0;
   int admitted = 0, peak_admitted = 0, in_setup = 0;
@@ -171,11 +211,25 @@ struct bddc_server {
   std::vector<std::thread> workers;
 
   // Under mu: admit from the head of the queue while a slot is free and the
-  // estimate fits next to what is held.
+  // estimate fits next to what is held; when it does not fit, the idle
+  // resident problem used longest ago is evicted (the driver frees it).
   void admit_locked() {
     while (!queue.empty() && admitted < opt.max_active) {
       SrvRequest *r = queue.front();
-      if (committed + r->est > cap) break;
+      if (committed + r->est > cap) {
+        Resident *lru = nullptr;
+        for (auto &kv : residents) {
+          Resident *q = kv.second.get();
+          if (q->ready && !q->busy && q->pending.empty() && (!lru || q->last_use < lru->last_use)) lru = q;
+        }
+        if (lru) {
+          auto it = residents.find(lru->key);
+          evicted.push_back(std::move(it->second));
+          residents.erase(it);
+          cv_drive.notify_one();
+        }
+        break;
+      }
       queue.pop_front();
       r->t_admit = sclock::now();
       r->held = r->est;
@@ -193,6 +247,12 @@ struct bddc_server {
     committed -= r->held;
     r->held = 0.0;
     --admitted;
+    complete_locked(r);
+    admit_locked();
+  }
+
+  // Under mu: a request is done (its statistics, the latency record).
+  void complete_locked(SrvRequest *r) {
     r->state = SrvRequest::DONE;
     r->t_done = sclock::now();
     r->st.status = r->status;
@@ -207,7 +267,6 @@ struct bddc_server {
       ++n_failed;
     }
     cv_done.notify_all();
-    admit_locked();
   }
 
   void fail(SrvRequest *r, int code, const std::string &msg) {
@@ -219,14 +278,29 @@ struct bddc_server {
     (void)hipSetDevice(device);
     for (;;) {
       SrvRequest *r = nullptr;
+      Resident *job = nullptr;
       {
         std::unique_lock<std::mutex> lk(mu);
-        cv_setup.wait(lk, [&] { return stopping || !to_setup.empty(); });
-        if (to_setup.empty()) return;
-        r = to_setup.front();
-        to_setup.pop_front();
-        r->state = SrvRequest::SETUP;
-        ++in_setup;
+        cv_setup.wait(lk, [&] { return stopping || !to_setup.empty() || !batch_jobs.empty(); });
+        if (!batch_jobs.empty()) {
+          job = batch_jobs.front();
+          batch_jobs.pop_front();
+        } else if (!to_setup.empty()) {
+          r = to_setup.front();
+          to_setup.pop_front();
+          r->state = SrvRequest::SETUP;
+          ++in_setup;
+        } else {
+          return;
+        }
+      }
+      if (job) {
+        run_batches(job);
+        continue;
+      }
+      if (r->res) {
+        setup_resident(r);
+        continue;
       }
       bool ok = false;
       try {
@@ -279,6 +353,140 @@ struct bddc_server {
     }
   }
 
+  // The first request of a key: set the shared problem up, then solve the
+  // waiting requests of the key (this one included) in blocks.
+  void setup_resident(SrvRequest *r) {
+    Resident *res = r->res;
+    bddc_problem *h = nullptr;
+    try {
+      bddc_options o{};
+      o.precision = opt.precision;
+      o.max_it = r->max_it;
+      o.flags = opt.flags;
+      const bddc_partition part = r->partition();
+      h = make_problem(&r->grid, r->perm.data(), &part, r->tau, &o);
+      r->st.setup_ms = h->stats.t_setup_ms;
+      r->st.peak_bytes = h->peak_bytes;
+    } catch (const Error &e) {
+      fail(r, e.code, e.msg);
+    } catch (const std::bad_alloc &) {
+      fail(r, BDDC_ENOMEM, "host out of memory");
+    } catch (const std::exception &e) {
+      fail(r, BDDC_EDEVICE, e.what());
+    }
+    r->t_setup_end = sclock::now();
+    r->perm.clear();
+    r->perm.shrink_to_fit();
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      --in_setup;
+      if (h) {
+        // the problem's bytes move from the request to the resident problem,
+        // and the request's slot frees up
+        // (it keeps the estimate, which holds the block vectors of its first block solve)
+        res->h = h;
+        res->held = std::max(r->held, h->device_bytes);
+        committed += res->held - r->held;
+        peak_committed = std::max(peak_committed, committed);
+        r->held = 0.0;
+        --admitted;
+        res->ready = true;
+        admit_locked();
+      } else {
+        // every request of the key fails with the setup
+        for (SrvRequest *q : res->pending)
+          if (q != r) {
+            q->status = r->status;
+            q->err = r->err;
+            complete_locked(q);
+          }
+        res->pending.clear();
+        r->res = nullptr;
+        residents.erase(res->key);
+        retire_locked(r);
+        return;
+      }
+    }
+    run_batches(res);
+  }
+
+  // Solve the waiting requests of a ready resident problem in blocks of up to
+  // 16 with equal rtol, until none is left; then the problem is idle.
+  void run_batches(Resident *res) {
+    bddc_problem *h = res->h;
+    const int64_t nc = h->L.ncells, nf = h->L.nfaces_all;
+    for (;;) {
+      std::vector<SrvRequest *> b;
+      double rtol = 0.0;
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        if (res->pending.empty()) {
+          res->busy = false;
+          res->last_use = sclock::now();
+          admit_locked();
+          return;
+        }
+        rtol = res->pending.front()->rtol;
+        for (auto it = res->pending.begin(); it != res->pending.end() && (int)b.size() < 16;) {
+          if ((*it)->rtol == rtol) {
+            b.push_back(*it);
+            it = res->pending.erase(it);
+          } else {
+            ++it;
+          }
+        }
+        for (SrvRequest *q : b) q->state = SrvRequest::SOLVING;
+      }
+      const int k = (int)b.size();
+      std::vector<double> rhs((size_t)k * nc), fl((size_t)k * nf, 0.0), pr((size_t)k * nc, 0.0), rel(k, 0.0);
+      std::vector<int32_t> its(k, 0), conv(k, 0);
+      for (int j = 0; j < k; ++j) std::copy(b[j]->rhs.begin(), b[j]->rhs.end(), rhs.begin() + (size_t)j * nc);
+      int rc = BDDC_OK;
+      std::string err;
+      try {
+        rc = block_solve_host(h, k, rhs.data(), rtol, fl.data(), pr.data(), its.data(), conv.data(), rel.data());
+        if (rc != BDDC_OK) err = rc == BDDC_ENOCONV ? "maximum number of CG iterations reached" : "CG breakdown";
+      } catch (const Error &e) {
+        rc = e.code;
+        err = e.msg;
+      } catch (const std::exception &e) {
+        rc = BDDC_EDEVICE;
+        err = e.what();
+      }
+      std::lock_guard<std::mutex> lk(mu);
+      // the first block solve allocates the block vectors (counted in the estimate)
+      if (h->device_bytes > res->held) {
+        committed += h->device_bytes - res->held;
+        res->held = h->device_bytes;
+        peak_committed = std::max(peak_committed, committed);
+      }
+      const bool solved = rc == BDDC_OK || rc == BDDC_ENOCONV || rc == BDDC_EBREAKDOWN;
+      for (int j = 0; j < k; ++j) {
+        SrvRequest *q = b[j];
+        if (solved) {
+          q->flux.assign(fl.begin() + (size_t)j * nf, fl.begin() + (size_t)(j + 1) * nf);
+          q->pres.assign(pr.begin() + (size_t)j * nc, pr.begin() + (size_t)(j + 1) * nc);
+          q->status = conv[j] ? BDDC_OK : (rc == BDDC_EBREAKDOWN ? BDDC_EBREAKDOWN : BDDC_ENOCONV);
+          if (q->status != BDDC_OK) q->err = err;
+        } else {
+          q->status = rc;
+          q->err = err;
+        }
+        q->st.it = its[j];
+        q->st.converged = conv[j];
+        q->st.relres = rel[j];
+        q->st.kappa = j == k - 1 ? h->stats.kappa : 0.0;
+        q->st.n_sub = h->L.N;
+        q->st.n_coarse = h->ncu + h->L.N;
+        q->st.est_bytes = q->est;
+        q->st.device_bytes = res->held;
+        q->st.batch = k;
+        q->st.reused = q->reused ? 1 : 0;
+        complete_locked(q);
+      }
+    }
+  }
+
   // Advance one solving request without blocking on the device; true when it
   // has left (finished or failed).
   bool advance(SrvRequest *r, bool &progressed) {
@@ -310,6 +518,7 @@ struct bddc_server {
     r->st.n_sub = h->L.N;
     r->st.n_coarse = h->ncu + h->L.N;
     r->st.est_bytes = r->est;
+    r->st.batch = 1;
     r->h = nullptr;
     {
       GateShared g(g_gate);
@@ -320,16 +529,38 @@ struct bddc_server {
     return true;
   }
 
+  // Free the handles of the evicted resident problems (HIP calls outside the
+  // lock), then count their bytes as free.
+  void release_evicted() {
+    std::vector<std::unique_ptr<Resident>> ev;
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      if (evicted.empty()) return;
+      ev.swap(evicted);
+    }
+    double freed = 0.0;
+    for (auto &q : ev) {
+      freed += q->held;
+      GateShared g(g_gate);
+      delete q->h;
+      q->h = nullptr;
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    committed -= freed;
+    admit_locked();
+  }
+
   void driver_loop() {
     (void)hipSetDevice(device);
     std::vector<SrvRequest *> act;
     for (;;) {
+      release_evicted();
       {
         std::unique_lock<std::mutex> lk(mu);
         act.insert(act.end(), ready.begin(), ready.end());
         ready.clear();
         if (act.empty()) {
-          if (stopping && to_setup.empty() && in_setup == 0) return;
+          if (stopping && to_setup.empty() && in_setup == 0 && evicted.empty()) return;
           cv_drive.wait_for(lk, std::chrono::milliseconds(2));
           continue;
         }
@@ -357,7 +588,7 @@ int bddc_estimate_bytes(const bddc_grid *g, const bddc_partition *part, double t
                         double *bytes) {
   return guarded([&]() -> int {
     if (!bytes) throw Error{BDDC_EINVAL, "null argument"};
-    *bytes = estimate_bytes(g, part, tau, opt);
+    *bytes = estimate_bytes(g, part, tau, opt, false);
     return BDDC_OK;
   });
 }
@@ -394,7 +625,8 @@ int bddc_server_submit(bddc_server_handle s, const bddc_request *req, uint64_t *
     bddc_options o{};
     o.precision = s->opt.precision;
     o.flags = s->opt.flags;
-    r->est = estimate_bytes(&req->grid, &req->part, req->tau, &o);   // validates grid and partition
+    // validates grid and partition; a keyed problem's estimate holds its block vectors too
+    r->est = estimate_bytes(&req->grid, &req->part, req->tau, &o, req->problem_key != 0);
     if (r->est > s->cap) throw Error{BDDC_ENOMEM, "request estimate exceeds the server's memory cap"};
     const Layout L = build_layout(&req->grid, &req->part);
     r->grid = req->grid;
@@ -408,17 +640,70 @@ int bddc_server_submit(bddc_server_handle s, const bddc_request *req, uint64_t *
     r->rtol = req->rtol;
     r->max_it = req->max_it;
     r->t_submit = sclock::now();
+    const uint64_t key = req->problem_key;
+    if (key) {
+      // a keyed request is solved in a block with others: its source is
+      // checked here, so that a bad one fails alone
+      double sum = 0.0, asum = 0.0;
+      for (double v : r->rhs) {
+        if (!std::isfinite(v)) throw Error{BDDC_EINVAL, "source must be finite"};
+        sum += v;
+        asum += std::fabs(v);
+      }
+      if (std::fabs(sum) > 1e-12 * asum) throw Error{BDDC_EINVAL, "source must sum to zero (no-flow compatibility)"};
+    }
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->stopping) throw Error{BDDC_EINVAL, "server is shutting down"};
-    r->id = s->next_id++;
-    *ticket = r->id;
+    Resident *res = nullptr;
+    if (key) {
+      auto it = s->residents.find(key);
+      if (it != s->residents.end()) {
+        res = it->second.get();
+        bool same = res->grid.dim == r->grid.dim && res->tau == r->tau;
+        for (int d = 0; d < 3 && same; ++d)
+          same = res->grid.n[d] == r->grid.n[d] && res->grid.h[d] == r->grid.h[d] && res->nsub[d] == r->nsub[d] &&
+                 res->cuts[d] == r->cuts[d];
+        if (!same) throw Error{BDDC_EINVAL, "request differs from the resident problem of its key"};
+      }
+    }
+    SrvRequest *rp = r.get();
+    rp->id = s->next_id++;
+    *ticket = rp->id;
     if (!s->any_submit) {
       s->any_submit = true;
-      s->t_first = r->t_submit;
+      s->t_first = rp->t_submit;
     }
     ++s->n_submitted;
-    s->queue.push_back(r.get());
-    s->reqs[r->id] = std::move(r);
+    s->reqs[rp->id] = std::move(r);
+    if (res) {
+      // the problem is resident (or being set up): wait for the next block
+      rp->res = res;
+      rp->reused = true;
+      rp->t_admit = rp->t_setup_end = rp->t_submit;
+      rp->perm.clear();
+      rp->perm.shrink_to_fit();
+      res->pending.push_back(rp);
+      if (res->ready && !res->busy) {
+        res->busy = true;
+        s->batch_jobs.push_back(res);
+        s->cv_setup.notify_one();
+      }
+    } else {
+      if (key) {
+        auto nr = std::make_unique<Resident>();
+        nr->key = key;
+        nr->grid = rp->grid;
+        nr->tau = rp->tau;
+        for (int d = 0; d < 3; ++d) {
+          nr->nsub[d] = rp->nsub[d];
+          nr->cuts[d] = rp->cuts[d];
+        }
+        rp->res = nr.get();
+        nr->pending.push_back(rp);
+        s->residents[key] = std::move(nr);
+      }
+      s->queue.push_back(rp);
+    }
     s->admit_locked();
     return BDDC_OK;
   });
@@ -493,6 +778,17 @@ int bddc_server_destroy(bddc_server_handle s) {
         r->status = BDDC_EINVAL;
         r->err = "server destroyed before admission";
         r->state = SrvRequest::DONE;
+        if (r->res) {
+          // the key's problem will not be set up: its waiting requests go too
+          for (SrvRequest *q : r->res->pending)
+            if (q != r) {
+              q->status = BDDC_EINVAL;
+              q->err = "server destroyed before admission";
+              q->state = SrvRequest::DONE;
+            }
+          s->residents.erase(r->res->key);
+          r->res = nullptr;
+        }
       }
       s->queue.clear();
       s->cv_setup.notify_all();
@@ -505,6 +801,11 @@ int bddc_server_destroy(bddc_server_handle s) {
       s->cv_drive.notify_all();
     }
     s->driver.join();
+    for (auto &kv : s->residents) {
+      GateShared g(g_gate);
+      delete kv.second->h;
+      kv.second->h = nullptr;
+    }
     delete s;
     return BDDC_OK;
   });

@@ -9,9 +9,13 @@
 //   cap_factor:    mem_cap = cap_factor * the largest estimate (0: unlimited)
 //   mode 0:        submit every request at random small intervals, poll all, check
 //   mode 1:        submit every request, destroy the server at once (drops the queue)
+//   mode 2:        keyed requests: every request five times under one key (its own
+//                  source each time) beside unkeyed copies, poll all, check outputs,
+//                  batches and that resident problems are released at destroy
 #include <stdint.h>
 #include <stdio.h>
 
+#include <algorithm>
 #include <atomic>
 #include <cstring>
 #include <mutex>
@@ -106,6 +110,8 @@ struct bddc_problem {
   int ncu = 0;
   // stand-in state
   int target = 1;
+  bool block_ready = false;
+  double est = 0.0;
   std::vector<sclock_t::time_point> land;
   const double *rhs = nullptr;
   double *flux = nullptr, *pres = nullptr;
@@ -140,7 +146,8 @@ int guarded(F &&fn) {
   }
 }
 
-double estimate_bytes(const bddc_grid *gr, const bddc_partition *part, double tau, const bddc_options *opt);
+double estimate_bytes(const bddc_grid *gr, const bddc_partition *part, double tau, const bddc_options *opt,
+                      bool block_vectors);
 
 void sleep_us(double us) { std::this_thread::sleep_for(std::chrono::duration<double, std::micro>(us)); }
 
@@ -163,7 +170,8 @@ bddc_problem *make_problem(const bddc_grid *g, const double *perm, const bddc_pa
     for (int64_t c = 0; c < h->L.ncells * h->L.dim; ++c)
       if (!(perm[c] > 0.0)) throw Error{BDDC_EINVAL, "permeability must be finite and > 0"};
     if (perm[0] == 7777.0) throw Error{BDDC_EFACTOR, "stand-in factorization failure"};
-    const double est = estimate_bytes(g, part, tau, opt);
+    const double est = estimate_bytes(g, part, tau, opt, true);
+    h->est = est;
     h->rng.seed((uint64_t)h->L.ncells * 1000003u + (uint64_t)h->L.N);
     std::uniform_real_distribution<double> u(0.0, 1.0);
     h->device_bytes = est * (0.5 + 0.5 * u(h->rng));
@@ -221,6 +229,39 @@ int solve_poll(bddc_problem *h, bool wait) {
   return 1;
 }
 
+// Block solve stand-in: every source checked, a random solve time, the same
+// outputs per source as solve_finish; the first call "allocates" block vectors.
+int block_solve_host(bddc_problem *h, int k, const double *rhs, double rtol, double *flux, double *pressure,
+                     int32_t *its, int32_t *conv, double *relres) {
+  GateShared g(g_gate);
+  if (k <= 0 || k > 16 || !(rtol > 0.0)) throw Error{BDDC_EINVAL, "bad block"};
+  const int64_t nc = h->L.ncells, nf = h->L.nfaces_all;
+  for (int j = 0; j < k; ++j) {
+    double sum = 0.0, asum = 0.0;
+    for (int64_t c = 0; c < nc; ++c) {
+      sum += rhs[j * nc + c];
+      asum += std::fabs(rhs[j * nc + c]);
+    }
+    if (std::fabs(sum) > 1e-12 * asum) throw Error{BDDC_EINVAL, "source must sum to zero"};
+  }
+  if (!h->block_ready) {
+    h->take(1024);
+    h->device_bytes = std::min(h->device_bytes * 1.1, h->est);
+    h->block_ready = true;
+  }
+  std::uniform_real_distribution<double> u(100.0, 1500.0);
+  sleep_us(u(h->rng));
+  for (int j = 0; j < k; ++j) {
+    for (int64_t f = 0; f < nf; ++f) flux[j * nf + f] = (double)f + (double)nc;
+    for (int64_t c = 0; c < nc; ++c) pressure[j * nc + c] = 2.0 * rhs[j * nc + c];
+    its[j] = 8;
+    conv[j] = 1;
+    relres[j] = 0.0;
+  }
+  h->stats.it = 8;
+  return BDDC_OK;
+}
+
 // Outputs that name the request: flux[j] = j + ncells, pressure = 2 * source.
 int solve_finish(bddc_problem *h) {
   auto &R = h->run;
@@ -257,6 +298,7 @@ struct Req {
   double tau = 0.0;
   std::vector<double> perm, rhs;
   bool fail = false;
+  uint64_t key = 0;
 };
 
 static bool read_requests(const char *path, std::vector<Req> &out) {
@@ -310,6 +352,27 @@ int main(int argc, char **argv) {
       reqs[k].fail = true;
     }
   }
+  if (mode == 2) {
+    // every request five times under its own key (the copies get their own
+    // sources, failing setups fail the whole key) and once more unkeyed
+    std::vector<Req> kr;
+    for (size_t k = 0; k < reqs.size(); ++k) {
+      for (int c = 0; c < 5; ++c) {
+        // (a keyed source must sum to zero at submission: every copy gets a valid one)
+        Req q = reqs[k];
+        q.key = 1 + k;
+        const int64_t nc = (int64_t)q.rhs.size();
+        std::fill(q.rhs.begin(), q.rhs.end(), 0.0);
+        q.rhs[(c * 7) % nc] += 1.0 + c;
+        q.rhs[nc - 1 - (c * 3) % nc] -= 1.0 + c;
+        q.fail = q.perm[0] == 7777.0;
+        kr.push_back(q);
+      }
+      kr.push_back(reqs[k]);
+    }
+    std::shuffle(kr.begin(), kr.end(), rng);
+    reqs.swap(kr);
+  }
   double est_max = 0.0;
   std::vector<double> est(reqs.size());
   for (size_t k = 0; k < reqs.size(); ++k) {
@@ -337,6 +400,7 @@ int main(int argc, char **argv) {
     rq.tau = reqs[k].tau;
     rq.rhs = reqs[k].rhs.data();
     rq.rtol = 1e-8;
+    rq.problem_key = reqs[k].key;
     if (bddc_server_submit(s, &rq, &tick[k]) != BDDC_OK) {
       printf("FAIL submit %zu: %s\n", k, g_last_error.c_str());
       return 1;
@@ -348,7 +412,7 @@ int main(int argc, char **argv) {
     printf("OK destroyed with %zu requests in flight, %d handles left\n", reqs.size(), g_live.load());
     return 0;
   }
-  int bad = 0, busy = 0, failed = 0;
+  int bad = 0, busy = 0, failed = 0, batched = 0, reused = 0;
   for (size_t k = 0; k < reqs.size(); ++k) {
     const Req &r = reqs[k];
     const int64_t nc = (int64_t)r.g.n[0] * r.g.n[1] * r.g.n[2];
@@ -390,10 +454,17 @@ int main(int argc, char **argv) {
         ++bad;
         break;
       }
-    if (st.est_bytes != est[k] || st.latency_ms < st.queue_ms) {
+    bddc_options eo{};
+    eo.precision = BDDC_MIXED;
+    const bddc_partition rp = part_of(r);
+    const double e = r.key ? estimate_bytes(&r.g, &rp, r.tau, &eo, true) : est[k];
+    if (st.est_bytes != e || st.latency_ms < st.queue_ms || st.batch < 1 || st.batch > 16 ||
+        (r.key == 0 && (st.batch != 1 || st.reused))) {
       printf("FAIL request %zu stats\n", k);
       ++bad;
     }
+    if (st.batch > 1) ++batched;
+    if (st.reused) ++reused;
   }
   bddc_server_stats_t ss{};
   bddc_server_stats(s, &ss);
@@ -401,11 +472,13 @@ int main(int argc, char **argv) {
     ++bad;
   if (ss.peak_active > max_active) ++bad;
   if (capf > 0 && ss.peak_bytes > so.mem_cap) ++bad;
+  if (mode == 2 && reused == 0) ++bad;
   bddc_server_destroy(s);
   if (g_live.load() != 0) ++bad;
-  printf("%s requests %zu failed %d busy-at-first-poll %d peak_active %d peak %.3g of cap %.3g, p50 %.2f ms p99 %.2f ms\n",
-         bad ? "FAIL" : "OK", reqs.size(), failed, busy, ss.peak_active, ss.peak_bytes, ss.mem_cap, ss.p50_ms,
-         ss.p99_ms);
+  printf("%s requests %zu failed %d busy-at-first-poll %d batched %d reused %d peak_active %d peak %.3g of cap %.3g, "
+         "p50 %.2f ms p99 %.2f ms\n",
+         bad ? "FAIL" : "OK", reqs.size(), failed, busy, batched, reused, ss.peak_active, ss.peak_bytes, ss.mem_cap,
+         ss.p50_ms, ss.p99_ms);
   return bad ? 1 : 0;
 }
 #endif  // SERVER_MOCK_LIB

@@ -117,3 +117,48 @@ def test_admission_by_memory():
     ss = srv.stats()
     assert ss["failed"] == 1 and ss["completed"] == 2
     srv.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-8), ("mixed", 1e-6)])
+def test_keyed_requests_share_a_resident_problem_and_batch(prec, tol):
+    """Requests under one problem key: the first sets the problem up, the
+    rest find it resident (no setup) and the ones waiting together are solved
+    in one block; every result must equal its own single solve (FP64 1e-8
+    with equal iterations, mixed 1e-6 within +-1), beside unkeyed requests in
+    the mix."""
+    Server, Solver = _gpu()
+    pr = W.serving_request(6)     # 32 x 125, tau 10
+    rtol = pr.rtol
+    rng = np.random.default_rng(5)
+    srcs = [W.seeded_wells(pr.n, rng) for _ in range(9)]
+    s = Solver(pr.n, pr.h, pr.perm, pr.cuts, tau=pr.tau, precision=prec)
+    ref = []
+    for src in srcs:
+        u, p = s.solve(src, rtol=rtol)
+        ref.append((u, p, s.stats()["it"]))
+    s.close()
+    srv = Server(precision=prec, max_active=3, setup_workers=2)
+    other = _submit_all(srv, [1, 4])
+    tk = [srv.submit(pr.n, pr.h, pr.perm, pr.cuts, src, tau=pr.tau, rtol=rtol, key=42) for src in srcs]
+    out = [srv.result(t) for t in tk]
+    for sd, t in other:
+        srv.result(t)
+    # a second wave finds the problem resident
+    tk2 = [srv.submit(pr.n, pr.h, pr.perm, pr.cuts, src, tau=pr.tau, rtol=rtol, key=42) for src in srcs[:3]]
+    out2 = [srv.result(t) for t in tk2]
+    with pytest.raises(Exception):
+        bad = W.serving_request(1)
+        srv.submit(bad.n, bad.h, bad.perm, bad.cuts, bad.source, tau=bad.tau, rtol=bad.rtol, key=42)
+    srv.close()
+    batches = []
+    for k, (u, p, st) in enumerate(out + out2):
+        ua, pa, ita = ref[k % 9] if k < 9 else ref[k - 9]
+        eu = np.linalg.norm(u - ua) / np.linalg.norm(ua)
+        ep = np.linalg.norm(p - pa) / np.linalg.norm(pa)
+        batches.append(st["batch"])
+        _say(f"{prec} keyed request {k}: batch {st['batch']}, reused {st['reused']}, it {st['it']} (alone {ita}), "
+             f"setup {st['setup_ms']:.1f} ms, latency {st['latency_ms']:.1f} ms, flux {eu:.1e}, pressure {ep:.1e}")
+        assert eu <= tol and ep <= tol
+        assert abs(st["it"] - ita) <= (0 if prec == "fp64" else 1)
+    assert sum(st["reused"] for _, _, st in out) == 8 and all(st["reused"] for _, _, st in out2)
+    assert max(batches) > 1

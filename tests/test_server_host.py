@@ -76,6 +76,7 @@ def test_server_scheduler_under_sanitizers(request, geometry, kind, cap):
     exe = request.getfixturevalue(kind)
     _run(exe, geometry, 4, 2, cap, 1, 0)          # serve all, check every ticket
     _run(exe, geometry, 3, 1, cap, 2, 1)          # destroy with the queue full
+    _run(exe, geometry, 3, 2, cap, 3, 2)          # keyed problems: resident, solved in blocks
 
 
 def _build_lib(tmp_path_factory, flags, name):
