@@ -310,8 +310,8 @@ def serving(n_req, rate=50.0, seed=0):
 
 SERVE_KEYED_DESC = ("Poisson stream (mean {rate:g} requests/s, seeded) over {np} resident problems (2D 32x125, 45x127, "
                     "55x80 and a 60x220x17 slab, channelised fields, tau 10, rtol 1e-8), each request its own seeded "
-                    "wells: with problem keys the problem is set up once and the waiting requests of a key are "
-                    "solved together (bddc_solve_block); without keys every request sets its problem up")
+                    "wells, under problem keys: each problem is set up once and the waiting requests of a key are "
+                    "solved together (bddc_solve_block)")
 
 
 def serving_keyed(n_req, rate=200.0, seed=1):
@@ -326,9 +326,28 @@ def serving_keyed(n_req, rate=200.0, seed=1):
     out = {"workload": SERVE_KEYED_DESC.format(rate=rate, np=len(base)), "requests": n_req,
            "arrival_rate_per_s": rate, "max_active": 4, "setup_workers": 2}
     for prec in ("fp64", "mixed"):
-        out[prec] = {"keyed": serve_stream(prec, reqs, arr, sources=srcs, keys=[int(p) + 1 for p in pick]),
-                     "unkeyed": serve_stream(prec, reqs, arr, sources=srcs)}
+        out[prec] = serve_stream(prec, reqs, arr, sources=srcs, keys=[int(p) + 1 for p in pick])
     return out
+
+
+def serving_child(n_req, timeout_s=600):
+    """Both serving streams in a child process, started before this process
+    touches the GPU (and done before it does), so that a failure there leaves
+    the rest of the bench line intact; returns (serving, serving_resident) or
+    error records."""
+    import subprocess
+    cmd = [sys.executable, os.path.abspath(__file__), "--serving-only", str(n_req)]
+    try:
+        res = subprocess.run(cmd, capture_output=True, text=True, timeout=timeout_s)
+    except subprocess.TimeoutExpired:
+        err = {"error": f"serving child exceeded {timeout_s} s"}
+        return err, err
+    lines = [ln for ln in res.stdout.splitlines() if ln.startswith("{")]
+    if res.returncode != 0 or not lines:
+        err = {"error": f"serving child exited with status {res.returncode}", "stderr_tail": res.stderr[-600:]}
+        return err, err
+    d = json.loads(lines[-1])
+    return d["serving"], d["serving_resident"]
 
 
 def copy_rate(reps=20):
@@ -453,6 +472,7 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=48,
                     help="requests of a served Poisson stream (mean 50/s) through bddc_server_* in both forms "
                          "(0: not run)")
+    ap.add_argument("--serving-only", type=int, default=0, help=argparse.SUPPRESS)
     ap.add_argument("--block-sources", type=int, default=32,
                     help="sources of the block-solve workload (uneven boxes, tau 5), solved together and one by "
                          "one (0: not run)")
@@ -471,6 +491,19 @@ def main():
               "(--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
 
+    if args.serving_only > 0:
+        # child of serving_child: the library's own hipMalloc, both streams
+        print(json.dumps({"serving": dict(serving(args.serving_only), allocator="hipMalloc"),
+                          "serving_resident": dict(serving_keyed(64), allocator="hipMalloc")}), flush=True)
+        return
+    srv_out = None
+    if args.serve_requests > 0 and not args.kernels_only:
+        # The serving streams run first, in a child process with the library's
+        # own hipMalloc: two runs of independent-problem streams (one with
+        # torch's allocator, one at 200 requests/s over repeated problems with
+        # hipMalloc) ended in a host segmentation fault whose cause is not
+        # known; a failure there must not take the rest of this line with it.
+        srv_out = serving_child(args.serve_requests)
     if args.alloc == "torch":
         import torch
         from paper_1901_02090_amd import set_allocator
@@ -553,19 +586,8 @@ def main():
     }
     if args.block_sources > 0:
         out["batch"] = block_batch(args.block_sources)
-    if args.serve_requests > 0:
-        # The server's handles take device memory with the library's own
-        # hipMalloc: its setup workers and driver are native threads, and the
-        # one run whose handles allocated through torch's caching allocator
-        # (ctypes callbacks into Python from those threads) ended in a host
-        # segmentation fault whose cause is not known.
-        if args.alloc == "torch":
-            import torch
-            from paper_1901_02090_amd import set_allocator
-            set_allocator()
-            torch.cuda.empty_cache()
-        out["serving"] = dict(serving(args.serve_requests), allocator="hipMalloc")
-        out["serving_resident"] = dict(serving_keyed(64), allocator="hipMalloc")
+    if srv_out is not None:
+        out["serving"], out["serving_resident"] = srv_out
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pr, args.cpu_seconds, st["it"])
     print(json.dumps(out), flush=True)
