@@ -357,56 +357,6 @@ void setup_dense_top(bddc_problem *h, hipStream_t s) {
                     (4.0 + 16.0) * (double)P.tg.size() + 16.0 * nt;
 }
 
-// Jacobi stage of the face eigenproblems.  Faces whose reduced matrix and
-// eigenvector matrix fit in one workgroup's LDS (16 m^2 bytes) run in classes
-// of equal capacity, so that small faces share a CU; the rest rotate in the
-// workspace.  Largest class first.
-void launch_face_jacobi(bddc_problem *h, const Layout &L, const DevGeom &g, double *fws, const int64_t *foff,
-                        hipStream_t s) {
-  static const int caps[] = {16, 32, 50, 64, 80, 100, 128};
-  constexpr int ncap = (int)(sizeof(caps) / sizeof(caps[0]));
-  int dev = 0, maxlds = 0;
-  HIPCHK(hipGetDevice(&dev));
-  HIPCHK(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-  hipFuncAttributes fa{};
-  HIPCHK(hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(&k_face_jacobi<true>)));
-  auto lds_bytes = [](int cap) { return (int64_t)16 * cap * cap; };
-  std::vector<std::vector<int>> cls(ncap + 1);   // cls[ncap]: in the workspace
-  for (int f = 0; f < L.nF; ++f) {
-    const int m = L.f_n[f] - 1;
-    if (m <= 0) continue;
-    int c = 0;
-    while (c < ncap && caps[c] < m) ++c;
-    if (c == ncap || lds_bytes(caps[c]) + (int64_t)fa.sharedSizeBytes > maxlds) c = ncap;
-    cls[c].push_back(f);
-  }
-  std::vector<int> list;
-  std::vector<int> start(ncap + 2, 0);
-  for (int c = 0; c <= ncap; ++c) {
-    start[c] = (int)list.size();
-    list.insert(list.end(), cls[c].begin(), cls[c].end());
-  }
-  start[ncap + 1] = (int)list.size();
-  if (list.empty()) return;
-  int *d_list = h->upload(list);
-  for (int c = ncap; c >= 0; --c) {
-    const int cnt = start[c + 1] - start[c];
-    if (cnt == 0) continue;
-    bool in_lds = c < ncap;
-    if (in_lds && lds_bytes(caps[c]) > 65536 &&
-        hipFuncSetAttribute(reinterpret_cast<const void *>(&k_face_jacobi<true>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes(caps[c])) != hipSuccess) {
-      (void)hipGetLastError();
-      in_lds = false;
-    }
-    if (in_lds)
-      k_face_jacobi<true><<<cnt, 256, (size_t)lds_bytes(caps[c]), s>>>(g, fws, foff, d_list + start[c]);
-    else
-      k_face_jacobi<false><<<cnt, 256, 0, s>>>(g, fws, foff, d_list + start[c]);
-    HIPCHK(hipGetLastError());
-  }
-}
-
 void do_setup(bddc_problem *h, const bddc_grid *gr, const double *perm, const bddc_partition *part) {
   Layout &L = h->L;
   {
@@ -612,7 +562,7 @@ void do_setup(bddc_problem *h, const bddc_grid *gr, const double *perm, const bd
     }
     HIPCHK(hipGetLastError());
     if (!allc && !ms) {
-      launch_face_jacobi(h, L, g, d_fws, d_foff, s);
+      k_face_eig<<<nF, 256, 0, s>>>(g, d_fws, d_foff, h->tau);
       k_face_rows<<<nF, 256, 0, s>>>(g, d_fws, d_foff, h->tau, d_eig, d_eoff, d_k, d_om, d_rows, d_roff);
       HIPCHK(hipGetLastError());
     }

@@ -416,210 +416,4 @@ __device__ __forceinline__ double wg_sum(double v, double *red) {
   return s;
 }
 
-// Cyclic Jacobi eigensolver for a symmetric n x n matrix A (n <= 256) with a
-// parallel round-robin pair ordering.  On exit A is diagonal (eigenvalues on
-// the diagonal) and V holds the eigenvectors as columns.  `pairs` is a shared
-// buffer of at least 3 * 128 doubles + 256 ints.
-__device__ __forceinline__ void wg_jacobi(int n, double *A, int lda, double *V, int ldv, double *shared,
-                                 int *perm, int max_sweeps = 40) {
-  const int tid = threadIdx.x;
-  double *cs = shared;          // cos per pair
-  double *sn = shared + 128;    // sin per pair
-  double *red = shared + 256;   // reduction scratch (4)
-  wg_set_identity(n, V, ldv);
-  const int m = (n + 1) & ~1;   // even number of players (n odd: one bye)
-  const int npair = m / 2;
-  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-    // convergence: off-diagonal mass vs diagonal mass
-    double off = 0.0, dia = 0.0;
-    for (int e = tid; e < n * n; e += WG) {
-      const int i = e % n, j = e / n;
-      const double a = A[i + (size_t)j * lda];
-      if (i == j) dia += a * a; else off += a * a;
-    }
-    off = wg_sum(off, red);
-    dia = wg_sum(dia, red);
-    if (off <= 1e-30 * dia || off == 0.0) break;
-    for (int round = 0; round < m - 1; ++round) {
-      // round-robin schedule: player 0 fixed, others rotate
-      if (tid < m) {
-        int p;
-        if (tid == 0) p = 0;
-        else p = 1 + ((tid - 1 + round) % (m - 1));
-        perm[tid] = p;
-      }
-      __syncthreads();
-      if (tid < npair) {
-        int p = perm[tid], q = perm[m - 1 - tid];
-        if (p > q) { const int t = p; p = q; q = t; }
-        double c = 1.0, s = 0.0;
-        if (q < n) {
-          const double apq = A[p + (size_t)q * lda];
-          if (apq != 0.0) {
-            const double app = A[p + (size_t)p * lda], aqq = A[q + (size_t)q * lda];
-            const double theta = (aqq - app) / (2.0 * apq);
-            const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-            c = 1.0 / sqrt(t * t + 1.0);
-            s = t * c;
-          }
-        }
-        cs[tid] = c;
-        sn[tid] = s;
-      }
-      __syncthreads();
-      // rows: A <- J^T A
-      for (int e = tid; e < npair * n; e += WG) {
-        const int t = e % npair, k = e / npair;
-        int p = perm[t], q = perm[m - 1 - t];
-        if (p > q) { const int x = p; p = q; q = x; }
-        if (q >= n) continue;
-        const double c = cs[t], s = sn[t];
-        const double ap = A[p + (size_t)k * lda], aq = A[q + (size_t)k * lda];
-        A[p + (size_t)k * lda] = c * ap - s * aq;
-        A[q + (size_t)k * lda] = s * ap + c * aq;
-      }
-      __syncthreads();
-      // columns: A <- A J, V <- V J
-      for (int e = tid; e < npair * n; e += WG) {
-        const int t = e % npair, k = e / npair;
-        int p = perm[t], q = perm[m - 1 - t];
-        if (p > q) { const int x = p; p = q; q = x; }
-        if (q >= n) continue;
-        const double c = cs[t], s = sn[t];
-        const double ap = A[k + (size_t)p * lda], aq = A[k + (size_t)q * lda];
-        A[k + (size_t)p * lda] = c * ap - s * aq;
-        A[k + (size_t)q * lda] = s * ap + c * aq;
-        const double vp = V[k + (size_t)p * ldv], vq = V[k + (size_t)q * ldv];
-        V[k + (size_t)p * ldv] = c * vp - s * vq;
-        V[k + (size_t)q * ldv] = s * vp + c * vq;
-      }
-      __syncthreads();
-    }
-  }
-}
-
-// The same cyclic Jacobi iteration (ordering, rotations, convergence test)
-// with A and V (both n x n, ld n, n <= 128) in LDS.  A round's row and column
-// rotations are applied in one pass over the disjoint 2 x 2 blocks that the
-// round's pairs cut out of A, so a round needs two barriers.  Lane t of every
-// wave owns row pair t (its indices and rotation stay in registers) and wave
-// w takes the column pairs w, w + 4, ..., four blocks at a time.  cs, sn
-// (doubles) and pp, qq (ints) are LDS arrays of at least 64 entries, red 4
-// doubles.
-__device__ __forceinline__ void jac_block(const double *A, int n, int pt, int qt, bool rq, int pu, int qu,
-                                          double (&v)[4]) {
-  const bool cq = qu < n;
-  v[0] = A[pt + pu * n];
-  v[1] = cq ? A[pt + qu * n] : 0.0;
-  v[2] = rq ? A[qt + pu * n] : 0.0;
-  v[3] = (rq && cq) ? A[qt + qu * n] : 0.0;
-}
-
-__device__ __forceinline__ void jac_rotate_store(double *A, int n, int pt, int qt, bool rq, double ct, double st,
-                                                 int pu, int qu, double cu, double su, const double (&v)[4]) {
-  const bool cq = qu < n;
-  const double a1 = ct * v[0] - st * v[2], c1 = st * v[0] + ct * v[2];
-  const double b1 = ct * v[1] - st * v[3], d1 = st * v[1] + ct * v[3];
-  A[pt + pu * n] = cu * a1 - su * b1;
-  if (cq) A[pt + qu * n] = su * a1 + cu * b1;
-  if (rq) A[qt + pu * n] = cu * c1 - su * d1;
-  if (rq && cq) A[qt + qu * n] = su * c1 + cu * d1;
-}
-
-__device__ __forceinline__ void wg_jacobi_lds(int n, double *A, double *V, double *cs, double *sn, int *pp,
-                                              int *qq, double *red, int max_sweeps = 40) {
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  constexpr int NW = WG / 64;
-  for (int j = wv; j < n; j += NW)
-    for (int i = lane; i < n; i += 64) V[i + j * n] = (i == j) ? 1.0 : 0.0;
-  __syncthreads();
-  const int m = (n + 1) & ~1;   // even number of players (n odd: one bye)
-  const int npair = m / 2;      // <= 64
-  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-    double off = 0.0, dia = 0.0;
-    for (int j = wv; j < n; j += NW)
-      for (int i = lane; i < n; i += 64) {
-        const double a = A[i + j * n];
-        if (i == j) dia += a * a; else off += a * a;
-      }
-    off = wg_sum(off, red);
-    dia = wg_sum(dia, red);
-    if (off <= 1e-30 * dia || off == 0.0) break;
-    for (int round = 0; round < m - 1; ++round) {
-      if (tid < npair) {
-        // round-robin: position 0 holds player 0, the others rotate
-        const int b = m - 1 - tid;
-        int p = (tid == 0) ? 0 : 1 + (tid - 1 + round) % (m - 1);
-        int q = 1 + (b - 1 + round) % (m - 1);
-        if (p > q) { const int t = p; p = q; q = t; }
-        double c = 1.0, s = 0.0;
-        if (q < n) {
-          const double apq = A[p + q * n];
-          if (apq != 0.0) {
-            const double app = A[p + p * n], aqq = A[q + q * n];
-            const double theta = (aqq - app) / (2.0 * apq);
-            const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-            c = 1.0 / sqrt(t * t + 1.0);
-            s = t * c;
-          }
-        }
-        cs[tid] = c;
-        sn[tid] = s;
-        pp[tid] = p;
-        qq[tid] = q;
-      }
-      __syncthreads();
-      // A <- J^T A J on the block of rows {p_t, q_t} and columns {p_u, q_u};
-      // U column pairs at a time, all loads before any store (the blocks are
-      // disjoint)
-      constexpr int U = 4;
-      if (lane < npair) {
-        const int pt = pp[lane], qt = qq[lane];
-        const bool rq = qt < n;
-        const double ct = cs[lane], st = sn[lane];
-        for (int u0 = wv; u0 < npair; u0 += U * NW) {
-          int pu[U], qu[U];
-          double cu[U], su[U], v[U][4];
-#pragma unroll
-          for (int j = 0; j < U; ++j) {
-            const int u = min(u0 + j * NW, npair - 1);
-            pu[j] = pp[u]; qu[j] = qq[u]; cu[j] = cs[u]; su[j] = sn[u];
-          }
-#pragma unroll
-          for (int j = 0; j < U; ++j)
-            if (u0 + j * NW < npair) jac_block(A, n, pt, qt, rq, pu[j], qu[j], v[j]);
-#pragma unroll
-          for (int j = 0; j < U; ++j)
-            if (u0 + j * NW < npair) jac_rotate_store(A, n, pt, qt, rq, ct, st, pu[j], qu[j], cu[j], su[j], v[j]);
-        }
-      }
-      // V <- V J, U column pairs at a time
-      for (int u0 = wv; u0 < npair; u0 += U * NW) {
-        int pu[U], qu[U];
-        double cu[U], su[U];
-        bool ok[U];
-#pragma unroll
-        for (int j = 0; j < U; ++j) {
-          const int u = min(u0 + j * NW, npair - 1);
-          pu[j] = pp[u]; qu[j] = qq[u]; cu[j] = cs[u]; su[j] = sn[u];
-          ok[j] = (u0 + j * NW < npair) && qu[j] < n;
-        }
-        for (int k = lane; k < n; k += 64) {
-          double vp[U], vq[U];
-#pragma unroll
-          for (int j = 0; j < U; ++j)
-            if (ok[j]) { vp[j] = V[k + pu[j] * n]; vq[j] = V[k + qu[j] * n]; }
-#pragma unroll
-          for (int j = 0; j < U; ++j)
-            if (ok[j]) {
-              V[k + pu[j] * n] = cu[j] * vp[j] - su[j] * vq[j];
-              V[k + qu[j] * n] = su[j] * vp[j] + cu[j] * vq[j];
-            }
-        }
-      }
-      __syncthreads();
-    }
-  }
-}
-
 }  // namespace bddc

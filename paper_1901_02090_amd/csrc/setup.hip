@@ -293,9 +293,9 @@ __global__ __launch_bounds__(256, 2) void k_schur_factor(DevGeom g, SetupWs ws, 
 //
 // The work is split in three launches that pass everything through the face's
 // workspace: k_face_reduce forms the reduced m x m matrix C = L^{-1} Xr L^{-T}
-// (into U; L, the Cholesky factor of Yr, stays in T1), k_face_jacobi
-// diagonalises it (eigenvalues onto the diagonal of U, eigenvectors into T2)
-// and k_face_rows selects the eigenvalues above tau and builds the rows.
+// (into U; L, the Cholesky factor of Yr, stays in T1), k_face_eig finds its
+// eigenvalues (onto the diagonal of U) and the eigenvectors of those above tau
+// (into T2), and k_face_rows selects them and builds the rows.
 __global__ __launch_bounds__(256, 2) void k_face_reduce(DevGeom g, SetupWs ws, double *fbase,
                                                      const int64_t *foff, int all_constrained,
                                                      double *eig_out, const int64_t *eig_off, int *kout,
@@ -508,33 +508,246 @@ __global__ __launch_bounds__(256) void k_ms_weight(DevGeom g, const double *__re
   for (int c = threadIdx.x; c < nc; c += WG) wsrc[lcg[c]] = well ? src[lcg[c]] / s : 0.0;
 }
 
-// Jacobi stage for the faces listed in `faces`.  IN_LDS: C and its eigenvector
-// matrix are held in dynamic LDS (16 m^2 bytes, m <= 128), the matrix C in U
-// is left untouched apart from its diagonal; otherwise the rotations work in
-// the workspace.
-template <bool IN_LDS>
-__global__ __launch_bounds__(256) void k_face_jacobi(DevGeom g, double *fbase, const int64_t *foff,
-                                                     const int *faces) {
-  const int f = faces[blockIdx.x];
+// Symmetric eigenproblem of a face's reduced matrix C (m x m, m <= 255, in U
+// with leading dimension m, full storage): Householder reduction to a
+// tridiagonal T = Q^T C Q (reflector k: v stored below the diagonal of column
+// k, beta_k in LDS), every eigenvalue of T by bisection on its Sturm sequence
+// (thread t finds the t-th smallest), the eigenvectors of those above tau by
+// inverse iteration on T (three steps from distinct starting vectors, a
+// partially pivoted tridiagonal LU each), orthogonalised within clusters of
+// close eigenvalues, and carried back through the reflectors.  Out: the
+// eigenvalues on the diagonal of U, the eigenvectors of those above tau in
+// the matching columns of T2 (leading dimension m); XH and YF of the face
+// workspace are scratch.  One workgroup per face.
+constexpr int EIG_MAX = 256;
+
+// Sturm count: eigenvalues of the tridiagonal (d, e) below x.
+__device__ __forceinline__ int sturm_below(int m, const double *d, const double *e, double x, double pivmin) {
+  int c = 0;
+  double q = d[0] - x;
+  if (fabs(q) < pivmin) q = -pivmin;
+  if (q < 0.0) ++c;
+  for (int i = 1; i < m; ++i) {
+    q = d[i] - x - e[i - 1] * e[i - 1] / q;
+    if (fabs(q) < pivmin) q = -pivmin;
+    if (q < 0.0) ++c;
+  }
+  return c;
+}
+
+__global__ __launch_bounds__(256) void k_face_eig(DevGeom g, double *fbase, const int64_t *foff, double tau) {
+  __shared__ double d[EIG_MAX], e[EIG_MAX], bet[EIG_MAX], lam[EIG_MAX], vs[EIG_MAX], ws[EIG_MAX];
+  __shared__ double red[8];
+  const int f = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int n = g.f_n[f], m = n - 1;
   if (m <= 0) return;
   double *w = fbase + foff[f];
-  double *T2 = w + 4 * n * n, *U = w + 5 * n * n;
-  if constexpr (IN_LDS) {
-    extern __shared__ double sh[];
-    __shared__ double cs[128], sn[128], red[8];
-    __shared__ int pp[128], qq[128];
-    double *A = sh, *V = sh + m * m;
-    for (int e = threadIdx.x; e < m * m; e += WG) A[e] = U[e];
-    __syncthreads();
-    wg_jacobi_lds(m, A, V, cs, sn, pp, qq, red);
-    for (int t = threadIdx.x; t < m; t += WG) U[t + (size_t)t * m] = A[t + t * m];
-    for (int e = threadIdx.x; e < m * m; e += WG) T2[e] = V[e];
-  } else {
-    __shared__ double jac[512];
-    __shared__ int perm[256];
-    wg_jacobi(m, U, m, T2, m, jac, perm);
+  double *XH = w + (size_t)n * n, *T2 = w + 4 * (size_t)n * n, *U = w + 5 * (size_t)n * n;
+  double *A = U;
+  // the two triangles of C, formed separately, are averaged
+  for (int64_t q = tid; q < (int64_t)m * m; q += 256) {
+    const int i = (int)(q % m), j = (int)(q / m);
+    if (i > j) {
+      const double a = 0.5 * (A[i + (size_t)j * m] + A[j + (size_t)i * m]);
+      A[i + (size_t)j * m] = a;
+      A[j + (size_t)i * m] = a;
+    }
   }
+  __syncthreads();
+  // --- Householder reduction (lower): column k below the diagonal -> beta, v
+  for (int k = 0; k + 2 < m; ++k) {
+    const int L = m - k - 1;
+    double *col = A + (size_t)k * m + (k + 1);
+    double s2 = 0.0;
+    for (int i = tid; i < L; i += 256) {
+      const double x = col[i];
+      vs[i] = x;
+      if (i > 0) s2 += x * x;
+    }
+    s2 = wg_sum(s2, red);   // (barrier inside: vs visible)
+    const double x0 = col[0];   // (vs[0] becomes v0 below, in thread 0)
+    double beta = 0.0, alpha = x0;
+    if (s2 > 0.0) {
+      const double mu = sqrt(x0 * x0 + s2);
+      alpha = x0 <= 0.0 ? mu : -mu;
+      const double v0 = x0 - alpha;
+      beta = 2.0 / (v0 * v0 + s2);
+      if (tid == 0) vs[0] = v0;
+    }
+    if (tid == 0) {
+      d[k] = A[(size_t)k * m + k];
+      e[k] = alpha;
+      bet[k] = beta;
+    }
+    __syncthreads();
+    if (beta == 0.0) continue;
+    for (int i = tid; i < L; i += 256) col[i] = vs[i];   // the reflector, for the back transformation
+    // p = beta A22 v (A22 symmetric: column i of A22 against v), a wave per column
+    double *A22 = A + (size_t)(k + 1) * m + (k + 1);
+    for (int i = wv; i < L; i += 4) {
+      const double *ci = A22 + (size_t)i * m;
+      double a = 0.0;
+      for (int j = lane; j < L; j += 64) a = fma(ci[j], vs[j], a);
+      for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
+      if (lane == 0) ws[i] = beta * a;
+    }
+    __syncthreads();
+    double pv = 0.0;
+    for (int i = tid; i < L; i += 256) pv += ws[i] * vs[i];
+    const double K = 0.5 * beta * wg_sum(pv, red);
+    for (int i = tid; i < L; i += 256) ws[i] -= K * vs[i];
+    __syncthreads();
+    // A22 -= v w^T + w v^T
+    for (int64_t q = tid; q < (int64_t)L * L; q += 256) {
+      const int i = (int)(q % L), j = (int)(q / L);
+      A22[i + (size_t)j * m] -= vs[i] * ws[j] + ws[i] * vs[j];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const int k0 = m >= 2 ? m - 2 : 0;
+    if (m >= 2) {
+      d[k0] = A[(size_t)k0 * m + k0];
+      e[k0] = A[(size_t)k0 * m + k0 + 1];
+      bet[k0] = 0.0;
+    }
+    d[m - 1] = A[(size_t)(m - 1) * m + (m - 1)];
+    e[m - 1] = 0.0;
+  }
+  __syncthreads();
+  // --- eigenvalues: bisection, thread t the t-th smallest (ascending)
+  double lo = 0.0, hi = 0.0, tnorm = 0.0;
+  for (int i = 0; i < m; ++i) {
+    const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < m ? fabs(e[i]) : 0.0);
+    lo = i == 0 ? d[i] - r : fmin(lo, d[i] - r);
+    hi = i == 0 ? d[i] + r : fmax(hi, d[i] + r);
+  }
+  tnorm = fmax(fabs(lo), fabs(hi));
+  const double eps = 2.220446049250313e-16;
+  // smallest pivot allowed in the Sturm counts: the safe minimum times max(1, e_i^2)
+  double emax2 = 1.0;
+  for (int i = 0; i + 1 < m; ++i) emax2 = fmax(emax2, e[i] * e[i]);
+  const double pivmin = 2.2250738585072014e-308 * emax2;
+  for (int t = tid; t < m; t += 256) {
+    double a = lo - eps * tnorm - pivmin, b = hi + eps * tnorm + pivmin;
+    for (int it = 0; it < 200; ++it) {
+      const double mid = 0.5 * (a + b);
+      if (mid <= a || mid >= b || (b - a) <= 2.0 * eps * fmax(fabs(a), fabs(b)) + pivmin) break;
+      if (sturm_below(m, d, e, mid, pivmin) > t) b = mid;
+      else a = mid;
+    }
+    lam[t] = 0.5 * (a + b);
+  }
+  __syncthreads();
+  // --- eigenvectors of the eigenvalues above tau: lam[t0 .. m)
+  int t0 = m;
+  for (int t = 0; t < m; ++t)
+    if (lam[t] > tau) { t0 = t; break; }
+  const int k = m - t0;
+  if (k > 0) {
+    // per vector: the upper factor (u0, u1, u2) of the pivoted LU, 3m doubles of scratch
+    const int per = (int)std::min<int64_t>(k, (2 * (int64_t)n * n) / (3 * (int64_t)m));
+    for (int b0 = 0; b0 < k; b0 += per) {
+      for (int jj = tid; jj < per && b0 + jj < k; jj += 256) {
+        const int t = t0 + b0 + jj;
+        double *y = T2 + (size_t)t * m;
+        double *u0 = XH + (size_t)jj * 3 * m, *u1 = u0 + m, *u2 = u1 + m;
+        // distinct starting vectors (their components in a cluster differ)
+        for (int i = 0; i < m; ++i) y[i] = 1.0 + 0.5 * sin(0.7 * (double)(i + 1) * (double)(t + 1));
+        const double shift = lam[t] + eps * tnorm;
+        for (int step = 0; step < 3; ++step) {
+          // LU of T - shift I with row interchanges, applied to y on the fly
+          double a = d[0] - shift, bb = m > 1 ? e[0] : 0.0, cc = 0.0;
+          double rhs = y[0];
+          for (int i = 0; i + 1 < m; ++i) {
+            // rows i (a, bb, cc) and i + 1 (e[i], d[i+1] - shift, e[i+1])
+            const double l0 = e[i], l1 = d[i + 1] - shift, l2 = i + 2 < m ? e[i + 1] : 0.0;
+            double r1 = y[i + 1];
+            if (fabs(l0) > fabs(a)) {
+              // swap rows i and i + 1
+              const double mlt = a / l0;
+              u0[i] = l0;
+              u1[i] = l1;
+              u2[i] = l2;
+              const double nb = bb - mlt * l1, nc = cc - mlt * l2;
+              const double ry = rhs - mlt * r1;
+              y[i] = r1;
+              a = nb;
+              bb = nc;
+              cc = 0.0;
+              rhs = ry;
+            } else {
+              const double mlt = a != 0.0 ? l0 / a : 0.0;
+              u0[i] = a;
+              u1[i] = bb;
+              u2[i] = cc;
+              y[i] = rhs;
+              a = l1 - mlt * bb;
+              bb = l2 - mlt * cc;
+              cc = 0.0;
+              rhs = r1 - mlt * rhs;
+            }
+          }
+          u0[m - 1] = a;
+          y[m - 1] = rhs;
+          // back substitution with tiny pivots replaced
+          const double tiny = eps * tnorm + pivmin;
+          double s = 0.0;
+          for (int i = m - 1; i >= 0; --i) {
+            double piv = u0[i];
+            if (fabs(piv) < tiny) piv = piv < 0.0 ? -tiny : tiny;
+            double v = y[i];
+            if (i + 1 < m) v -= u1[i] * y[i + 1];
+            if (i + 2 < m) v -= u2[i] * y[i + 2];
+            v /= piv;
+            y[i] = v;
+            s = fmax(s, fabs(v));
+          }
+          const double sc = s > 0.0 ? 1.0 / s : 1.0;
+          for (int i = 0; i < m; ++i) y[i] *= sc;
+        }
+      }
+      __syncthreads();
+    }
+    // orthonormalise within clusters of close eigenvalues (twice), normalise the rest
+    const double gap = 1e-3 * tnorm;
+    int c0 = t0;
+    for (int t = t0; t < m; ++t) {
+      if (t > t0 && lam[t] - lam[t - 1] > gap) c0 = t;
+      double *yt = T2 + (size_t)t * m;
+      for (int pass = 0; pass < 2; ++pass)
+        for (int q = c0; q < t; ++q) {
+          const double *yq = T2 + (size_t)q * m;
+          double dot = 0.0;
+          for (int i = tid; i < m; i += 256) dot += yq[i] * yt[i];
+          dot = wg_sum(dot, red);
+          for (int i = tid; i < m; i += 256) yt[i] -= dot * yq[i];
+          __syncthreads();
+        }
+      double nr = 0.0;
+      for (int i = tid; i < m; i += 256) nr += yt[i] * yt[i];
+      nr = sqrt(wg_sum(nr, red));
+      for (int i = tid; i < m; i += 256) yt[i] /= nr;
+      __syncthreads();
+    }
+    // back transformation y <- H_0 ... H_{m-3} y, a wave per vector
+    for (int t = t0 + wv; t < m; t += 4) {
+      double *y = T2 + (size_t)t * m;
+      for (int r = m - 3; r >= 0; --r) {
+        const double br = bet[r];
+        if (br == 0.0) continue;
+        const double *v = A + (size_t)r * m + (r + 1);
+        const int L = m - r - 1;
+        double a = 0.0;
+        for (int i = lane; i < L; i += 64) a = fma(v[i], y[r + 1 + i], a);
+        for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
+        a *= br;
+        for (int i = lane; i < L; i += 64) y[r + 1 + i] -= a * v[i];
+      }
+    }
+    __syncthreads();
+  }
+  for (int t = tid; t < m; t += 256) U[(size_t)t * m + t] = lam[t];
 }
 
 __global__ __launch_bounds__(256) void k_face_rows(DevGeom g, double *fbase, const int64_t *foff, double tau,
