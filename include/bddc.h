@@ -130,6 +130,12 @@ typedef struct {
                             the net outflow through the boundary instead of
                             zero, and the boundary entries of the flux
                             output carry them.  Read during bddc_setup only */
+  int32_t coarse_subtree; /* the bottom levels 0 .. coarse_subtree - 1 of the
+                            coarse tree (below the dense top block) are swept
+                            by one launch per direction, one workgroup per
+                            subtree (0: the library's default; < 0: one
+                            launch per level).  BDDC_AUTOTUNE times 0 .. 6
+                            levels and keeps the fastest                   */
 } bddc_options;
 
 typedef struct {
@@ -168,6 +174,12 @@ typedef struct {
                                apply (16 columns; 0 before a block solve)      */
   double flops_block_local; /* 2 * 16 * sum n_Gamma^i^2: the flops of one block
                                product with S^i or T^i (16 columns)             */
+  int32_t sweep_subtree_levels; /* coarse sweeps: levels 0 .. this - 1 are swept
+                               by one launch per direction, one workgroup per
+                               bottom subtree (0: one launch per level)        */
+  int32_t reserved0;
+  double tune_subtree_ms[7];/* coarse solve with bottom subtrees of 0 .. 6
+                               levels (0 where not timed)                       */
 } bddc_stats_t;
 
 /*

@@ -43,7 +43,7 @@ class Partition(C.Structure):
 class Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("max_it", C.c_int32), ("flags", C.c_uint32), ("coarse_leaf", C.c_int32),
                 ("coarse_top", C.c_int32), ("t_workgroups", C.c_int32), ("ms_source", C.POINTER(C.c_double)),
-                ("bflux", C.POINTER(C.c_double))]
+                ("bflux", C.POINTER(C.c_double)), ("coarse_subtree", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -57,7 +57,8 @@ class Stats(C.Structure):
                 ("device_bytes", C.c_double), ("sweep_wide4", C.c_int32), ("sweep_wide16", C.c_int32),
                 ("t_workgroups", C.c_int32), ("t_tune_ms", C.c_double), ("tune_coarse_ms", C.c_double * 4),
                 ("tune_precond_ms", C.c_double * 4), ("bytes_prec_block", C.c_double),
-                ("flops_block_local", C.c_double)]
+                ("flops_block_local", C.c_double), ("sweep_subtree_levels", C.c_int32), ("reserved0", C.c_int32),
+                ("tune_subtree_ms", C.c_double * 7)]
 
 
 class ServerOptions(C.Structure):
@@ -233,7 +234,7 @@ class Solver:
 
     def __init__(self, n, h, perm, cuts, tau=math.inf, precision="fp64", max_it=10000, all_constrained=False,
                  coarse_leaf=0, coarse_top=0, t_workgroups=0, multiscale=False,
-                 scaling="multiplicity", ms_source=None, autotune=False, bflux=None):
+                 scaling="multiplicity", ms_source=None, autotune=False, bflux=None, coarse_subtree=0):
         """ms_source: with multiscale=True, the cell-integrated well source that
         shapes the multiscale sources of the subdomains holding a well.
         bflux: [n_faces_all] prescribed normal fluxes of the boundary faces
@@ -246,6 +247,7 @@ class Solver:
                       (BDDC_MULTISCALE if multiscale else 0) | _scaling_flag(scaling) |
                       (BDDC_AUTOTUNE if autotune else 0),
                       int(coarse_leaf), int(coarse_top), int(t_workgroups))
+        opt.coarse_subtree = int(coarse_subtree)
         ms = None
         if ms_source is not None:
             ms = np.ascontiguousarray(ms_source, dtype=np.float64).reshape(-1)

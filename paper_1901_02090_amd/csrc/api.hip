@@ -71,6 +71,8 @@ static_assert(sizeof(CgState) <= 32 * sizeof(double), "CG state exceeds its scra
 static __device__ __align__(256) double scratch[NOALLOC_DOUBLES];
 
 constexpr int MAX_DEVICES = 64;
+constexpr int SUB_CANDS = 7;   // autotuner: bottom-subtree depths -1 (none) .. 5
+constexpr int SUB_DEFAULT_LEVELS = -1;   // levels swept by bottom subtrees without the autotuner (< 0: none)
 std::mutex g_scratch_mu;
 void *g_scratch_ptr[MAX_DEVICES] = {};
 
@@ -116,6 +118,7 @@ struct bddc_problem {
   uint32_t flags = 0;
   int coarse_leaf = 0;
   int coarse_top = 0;
+  int coarse_sub = 0;                             // bottom-subtree levels (0: default, < 0: none)
   int t_grid = 0;                                 // workgroups of the T^i launch beside the coarse solve
   int n_cu = 0;                                   // compute units of the device
   double tau = 0.0;
@@ -153,9 +156,12 @@ struct bddc_problem {
   double *Kt = nullptr, *ctt = nullptr;           // dense top block: S_t^{-1} (nt x top_ld), t_t
   int *tg_off = nullptr, *tg = nullptr;           // gather map of t_t
   int top_ld = 0;
+  int *d_sph = nullptr;                           // bottom-subtree sweeps (nd_subtrees): phase offsets,
+  const int4 *d_stask = nullptr;                  // task copies
   bool longl = false;                             // a subdomain extent exceeds SHORTLINE cells
   bool mc_staged = true;                          // the line kernels' coefficient copies fit in LDS
   double tune_coarse_ms[4] = {0, 0, 0, 0};        // autotuner: coarse solve per sweep width candidate
+  double tune_sub_ms[SUB_CANDS] = {};              // autotuner: coarse solve per bottom-subtree depth
   double tune_precond_ms[4] = {0, 0, 0, 0};       // autotuner: preconditioner per T^i grid candidate
   double coarse_bytes = 0.0;
   int64_t *d_pk = nullptr, *d_psi_off = nullptr, *d_Xoff = nullptr, *d_gamma_face = nullptr;
@@ -302,6 +308,21 @@ void check_coarse_ptrs(const bddc_problem *h) {
 
 void fill(bddc_problem *h, double *x, int64_t n, double v) {
   if (n > 0) k_fill<<<nblk(n), 256, 0, h->stream>>>(n, x, v);
+}
+
+// Bottom-subtree sweeps of levels [0, lv] (lv < 0: none; nd_subtrees caps lv
+// below the dense top block): host lists and their device copies.  The
+// stream must be idle (the lists are replaced).
+void set_subtrees(bddc_problem *h, int lv) {
+  NdPlan &P = h->nd;
+  nd_subtrees(P, lv);
+  if (h->d_sph) h->release(h->d_sph);
+  if (h->d_stask) h->release((void *)h->d_stask);
+  h->d_sph = nullptr;
+  h->d_stask = nullptr;
+  if (P.sub_lv < 0) return;
+  h->d_sph = h->upload(P.sph);
+  h->d_stask = (const int4 *)h->upload(P.stask);
 }
 
 // Dense top block of the coarse solve (nd_dense_top): S_t^{-1} column by
@@ -733,6 +754,7 @@ void do_setup(bddc_problem *h, const bddc_grid *gr, const double *perm, const bd
     // streamed per coarse solve: R twice (rows forward, columns backward)
     h->coarse_bytes = 2.0 * 8.0 * (double)P.r_off[nfr];
     setup_dense_top(h, s);
+    set_subtrees(h, (h->coarse_sub == 0 ? SUB_DEFAULT_LEVELS : h->coarse_sub) - 1);
   }
 
   const int nGm = L.nGamma;
@@ -827,7 +849,13 @@ void launch_coarse_solve(bddc_problem *h, hipStream_t s, const int *done) {
   const NdPlan &P = h->nd;
   if (h->nk == 0) return;
   check_coarse_ptrs(h);
-  for (int lv = 0; lv < P.top; ++lv) {
+  // levels [0, sl] by bottom subtrees, one launch per direction
+  const int sl = P.sub_lv;
+  if (sl >= 0 && (!h->d_sph || !h->d_stask)) throw Error{BDDC_EDEVICE, "subtree sweep lists not uploaded"};
+  if (sl >= 0)
+    k_nd_fwd_sub<<<P.nsubt, SUB_THREADS, 0, s>>>(sl + 1, h->d_sph, h->d_stask, h->sw, h->FR, h->bc, h->cS0, h->cS1,
+                                                 h->cy, done);
+  for (int lv = sl + 1; lv < P.top; ++lv) {
     const int t0 = P.ftask_off[lv], nt = P.ftask_off[lv + 1] - t0;
     k_nd_fwd<<<nt, 256, 0, s>>>(t0, h->sw, h->FR, h->bc, h->cS0, h->cS1, h->cy, done);
   }
@@ -837,11 +865,15 @@ void launch_coarse_solve(bddc_problem *h, hipStream_t s, const int *done) {
     k_top_gemv<<<nblk(P.nt, TOP_ROWS_PER_WG), TOP_THREADS, (size_t)h->top_ld * sizeof(double), s>>>(
         P.nt, h->top_ld, h->Kt, h->ctt, d0, h->sw.xsc_off, h->sw.xsc, h->cXB, h->csol, h->bc, done);
   }
-  for (int lv = P.top - 1; lv >= 0; --lv) {
+  for (int lv = P.top - 1; lv > sl; --lv) {
     const int t0 = P.btask_lo[lv], nt = P.btask_hi[lv] - t0;
     k_nd_bwd<<<nt, 256, 0, s>>>(t0, h->sw, h->BC, h->cy, h->csgn, h->cXB, h->csol, h->bc, done);
   }
+  if (sl >= 0)
+    k_nd_bwd_sub<<<P.nsubt, SUB_THREADS, 0, s>>>(sl + 1, h->d_sph + (int64_t)P.nsubt * (sl + 2), h->d_stask, h->sw,
+                                                 h->BC, h->cy, h->csgn, h->cXB, h->csol, h->bc, done);
 }
+
 
 void launch_precond(bddc_problem *h, const double *r, double *z, double *zpart, bool check) {
   const Layout &L = h->L;
@@ -1049,6 +1081,12 @@ void autotune(bddc_problem *h) {
     HIPCHK(hipStreamSynchronize(h->stream));
     h->release((void *)h->sw.task);
     h->sw.task = (const int4 *)h->upload(P.task);
+    set_subtrees(h, P.sub_lv);   // nd_tasks rebuilt the subtree copies of the tasks
+  };
+  auto set_sub = [&](int lv) {
+    GateShared g(g_gate);
+    HIPCHK(hipStreamSynchronize(h->stream));
+    set_subtrees(h, lv);
   };
   if (h->nk > 0 && P.top > 0) {
     {
@@ -1066,6 +1104,21 @@ void autotune(bddc_problem *h) {
       if (ms < best) { best = ms; bi = c; }
     }
     if (bi != 3) set_tasks(cand[bi][0], cand[bi][1]);   // else the last candidate's tasks are in place
+    // bottom subtrees: levels [0, lv] in one launch per direction
+    const int lv0 = P.sub_lv;
+    best = 1e300;
+    int blv = lv0;
+    for (int c = 0; c < SUB_CANDS; ++c) {
+      const int lv = c - 1;
+      if (lv >= P.top) break;
+      set_sub(lv);
+      const double ms =
+          time_graph_ms(h, REPS, [&] { launch_coarse_solve(h, h->stream, nullptr); }, "the coarse solve");
+      h->tune_sub_ms[c] = ms;
+      if (ms < best) { best = ms; blv = lv; }
+      if (ms > 1.25 * best) break;   // deeper subtrees only serialise more of the wide fronts
+    }
+    set_sub(blv);
     GateShared g(g_gate);
     fill(h, h->bc, h->nk, 0.0);
   }
@@ -1623,6 +1676,7 @@ void apply_options(bddc_problem *h, const bddc_options *opt) {
     h->flags = opt->flags;
     h->coarse_leaf = opt->coarse_leaf;
     h->coarse_top = opt->coarse_top;
+    h->coarse_sub = opt->coarse_subtree;
     h->t_grid = opt->t_workgroups;
     h->ms_src = opt->ms_source;
     h->bflux_in = opt->bflux;
@@ -1831,6 +1885,9 @@ int bddc_stats(bddc_handle h, bddc_stats_t *out) {
       s.tune_coarse_ms[c] = h->tune_coarse_ms[c];
       s.tune_precond_ms[c] = h->tune_precond_ms[c];
     }
+    s.sweep_subtree_levels = h->nd.sub_lv + 1;
+    static_assert(SUB_CANDS == sizeof(s.tune_subtree_ms) / sizeof(double), "subtree candidates");
+    for (int c = 0; c < SUB_CANDS; ++c) s.tune_subtree_ms[c] = h->tune_sub_ms[c];
     *out = s;
     return BDDC_OK;
   });

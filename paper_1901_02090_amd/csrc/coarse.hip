@@ -45,14 +45,14 @@ __device__ __forceinline__ double group_reduce(double v, int g) {
 
 // Rows [d0.y, d0.y + 256/g) of one front, forward: each lane group of g
 // lanes forms one row of R against t_p; rows r < n give z_P[r], rows n + k
-// push w_p[k] into the parent's slot array of this front.  Called by the
-// whole workgroup.
+// push w_p[k] into the parent's slot array of this front.  Called by 256
+// lanes (tid = 0 .. 255, whole wavefronts).
 __device__ __forceinline__ void fwd_task(const int4 d0, const int4 d1, const int4 d2, const DevSweep &sw,
                                          const double *__restrict__ FR, const double *__restrict__ b, double *S0,
-                                         double *S1, double *z) {
+                                         double *S1, double *z, int tid) {
   const int g = d0.z, n = d0.w, m = d1.x, fst = d1.y, vo = d1.z, bo = d1.w;
   const int64_t ro = (int64_t)(((uint64_t)(uint32_t)d2.y << 32) | (uint32_t)d2.x);
-  const int lane = threadIdx.x & (g - 1), r = d0.y + threadIdx.x / g;
+  const int lane = tid & (g - 1), r = d0.y + tid / g;
   if (r >= n + m) return;            // whole lane groups leave together
   const double *row;
   int len;
@@ -90,14 +90,14 @@ __device__ __forceinline__ void fwd_task(const int4 d0, const int4 d1, const int
 // Columns [d0.y, d0.y + 256/g) of one front, backward; each x[d] is also
 // stored into every B vector that holds d (those of the fronts below), and
 // the right-hand side b[d], consumed by the forward sweep, is cleared for the
-// next solve.  Called by the whole workgroup.
+// next solve.  Called by 256 lanes (tid = 0 .. 255, whole wavefronts).
 __device__ __forceinline__ void bwd_task(const int4 d0, const int4 d1, const int4 d2, const DevSweep &sw,
                                          const double *__restrict__ BC, const double *z,
                                          const double *__restrict__ sg, double *XB, double *__restrict__ x,
-                                         double *__restrict__ b) {
+                                         double *__restrict__ b, int tid) {
   const int g = d0.z, n = d0.w, m = d1.x, fst = d1.y, bo = d1.w;
   const int64_t ro = (int64_t)(((uint64_t)(uint32_t)d2.y << 32) | (uint32_t)d2.x);
-  const int lane = threadIdx.x & (g - 1), c = d0.y + threadIdx.x / g;
+  const int lane = tid & (g - 1), c = d0.y + tid / g;
   const double *xb = XB + bo;
   if (c >= n) return;
   const int f = n + m, d = fst + c;
@@ -133,7 +133,7 @@ __global__ __launch_bounds__(256) void k_nd_fwd(int t0, DevSweep sw, const doubl
   const int4 *td = sw.task + 4 * (int64_t)(t0 + blockIdx.x);
   const int4 d0 = td[0], d1 = td[1], d2 = td[2];
   if (done && *done) return;
-  fwd_task(d0, d1, d2, sw, FR, b, S0, S1, z);
+  fwd_task(d0, d1, d2, sw, FR, b, S0, S1, z, threadIdx.x);
 }
 
 __global__ __launch_bounds__(256) void k_nd_bwd(int t0, DevSweep sw, const double *__restrict__ BC,
@@ -143,7 +143,55 @@ __global__ __launch_bounds__(256) void k_nd_bwd(int t0, DevSweep sw, const doubl
   const int4 *td = sw.task + 4 * (int64_t)(t0 + blockIdx.x);
   const int4 d0 = td[0], d1 = td[1], d2 = td[2];
   if (done && *done) return;
-  bwd_task(d0, d1, d2, sw, BC, z, sg, XB, x, b);
+  bwd_task(d0, d1, d2, sw, BC, z, sg, XB, x, b, threadIdx.x);
+}
+
+// Bottom subtrees (nd_subtrees), one per workgroup of SUB_Q x 256 lanes: the
+// subtree's phases (levels) in order, each phase's tasks dealt to the SUB_Q
+// groups of 256 lanes, with a workgroup barrier between phases.  What one
+// phase writes (the pushes into the parents' slot arrays forward, the x values
+// in the descendants' B vectors backward) is read by a later phase of the same
+// workgroup, so the barrier orders it; no level launch boundary is paid inside
+// the subtree.  ph: this subtree's nph + 1 phase offsets into the task copies.
+constexpr int SUB_Q = 4;
+constexpr int SUB_THREADS = 256 * SUB_Q;
+
+__global__ __launch_bounds__(SUB_THREADS) void k_nd_fwd_sub(int nph, const int *__restrict__ sph,
+                                                            const int4 *__restrict__ stask, DevSweep sw,
+                                                            const double *__restrict__ FR,
+                                                            const double *__restrict__ b, double *S0, double *S1,
+                                                            double *__restrict__ z, const int *done) {
+  if (done && *done) return;
+  const int *ph = sph + (int64_t)blockIdx.x * (nph + 1);
+  const int q = threadIdx.x >> 8, tid = threadIdx.x & 255;
+  for (int k = 0; k < nph; ++k) {
+    const int e = ph[k + 1];
+    for (int t = ph[k] + q; t < e; t += SUB_Q) {
+      const int4 *td = stask + 4 * (int64_t)t;
+      fwd_task(td[0], td[1], td[2], sw, FR, b, S0, S1, z, tid);
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(SUB_THREADS) void k_nd_bwd_sub(int nph, const int *__restrict__ sph,
+                                                            const int4 *__restrict__ stask, DevSweep sw,
+                                                            const double *__restrict__ BC,
+                                                            const double *__restrict__ z,
+                                                            const double *__restrict__ sg, double *XB,
+                                                            double *__restrict__ x, double *__restrict__ b,
+                                                            const int *done) {
+  if (done && *done) return;
+  const int *ph = sph + (int64_t)blockIdx.x * (nph + 1);
+  const int q = threadIdx.x >> 8, tid = threadIdx.x & 255;
+  for (int k = 0; k < nph; ++k) {
+    const int e = ph[k + 1];
+    for (int t = ph[k] + q; t < e; t += SUB_Q) {
+      const int4 *td = stask + 4 * (int64_t)t;
+      bwd_task(td[0], td[1], td[2], sw, BC, z, sg, XB, x, b, tid);
+    }
+    __syncthreads();
+  }
 }
 
 // ---- dense top block (nd_dense_top) ---------------------------------------------

@@ -66,6 +66,18 @@ struct NdPlan {
   int ntask = 0;
   std::vector<int> ftask_off;       // [H+1] forward tasks of level h
   std::vector<int> btask_lo, btask_hi;  // [H] backward tasks of level h
+  std::vector<int> ft_first, bt_first;  // [nfr] first forward / backward task of each front
+  // bottom subtrees (nd_subtrees): the fronts of levels [0, sub_lv] are swept
+  // in one launch per direction, one workgroup per subtree (a front of level
+  // <= sub_lv whose parent lies above sub_lv, with all its descendants) taking
+  // the subtree's levels one after the other.  stask holds copies of the
+  // subtrees' forward tasks, then of their backward tasks; subtree t's phase k
+  // (k = 0 .. sub_lv) is stask[sph[t (sub_lv + 2) + k], sph[t (sub_lv + 2) + k + 1])
+  // forward (level k), and the same at sph[nsubt (sub_lv + 2) + t (sub_lv + 2) + k]
+  // backward (level sub_lv - k).
+  int sub_lv = -1;                  // -1: every level has its own launches
+  int nsubt = 0;
+  std::vector<int> stask, sph;
   // dense top block (nd_dense_top): levels [top, H) are solved with the
   // explicit inverse of their Schur complement; their nt dofs are the last
   // ones, [lvl_dof[top], nk).  tg lists, for every top dof, the positions of
@@ -74,6 +86,8 @@ struct NdPlan {
   int nt = 0;
   std::vector<int> tg_off, tg;      // [nt+1], positions
 };
+
+inline void nd_subtrees(NdPlan &P, int lv);
 
 // Lane-group widths and the task list of the solve sweeps.  A row (forward)
 // or column (backward) of at most wide4 entries is handled by 4 lanes, of at
@@ -131,18 +145,91 @@ inline void nd_tasks(NdPlan &P, int wide4, int wide16) {
   P.ftask_off.assign(H + 1, 0);
   P.btask_lo.assign(H, 0);
   P.btask_hi.assign(H, 0);
+  P.ft_first.assign(nn, 0);
+  P.bt_first.assign(nn, 0);
   for (int h = 0; h < H; ++h) {
-    for (int r = P.lvl_off[h]; r < P.lvl_off[h + 1]; ++r)
+    for (int r = P.lvl_off[h]; r < P.lvl_off[h + 1]; ++r) {
+      P.ft_first[r] = (int)P.task.size() / 16;
       for (int j = 0; j < P.n[r] + P.m[r]; j += 256 / P.gf[r]) push(r, j, P.gf[r], 0);
+    }
     P.ftask_off[h + 1] = (int)P.task.size() / 16;
   }
   for (int h = H - 1; h >= 0; --h) {
     P.btask_lo[h] = (int)P.task.size() / 16;
-    for (int r = P.lvl_off[h]; r < P.lvl_off[h + 1]; ++r)
+    for (int r = P.lvl_off[h]; r < P.lvl_off[h + 1]; ++r) {
+      P.bt_first[r] = (int)P.task.size() / 16;
       for (int j = 0; j < P.n[r]; j += 256 / P.gb[r]) push(r, j, P.gb[r], 1);
+    }
     P.btask_hi[h] = (int)P.task.size() / 16;
   }
   P.ntask = (int)P.task.size() / 16;
+  nd_subtrees(P, P.sub_lv);   // the subtree lists copy the tasks just built
+}
+
+// Bottom subtrees of the sweeps: levels [0, lv] (at most the levels below the
+// dense top block) in one launch per direction.  Inside a subtree a front's
+// forward pushes go to its parent, which is in the subtree unless the front is
+// its root (then the parent is swept by a later launch), and its backward
+// values go to the B vectors of its descendants; so subtrees never read what
+// another one writes in the same launch.  Subtrees are listed largest first.
+// Call after nd_tasks and nd_dense_top; lv < 0 clears the subtree lists.
+inline void nd_subtrees(NdPlan &P, int lv) {
+  P.sub_lv = -1;
+  P.nsubt = 0;
+  P.stask.clear();
+  P.sph.clear();
+  lv = std::min(lv, P.top - 1);
+  if (lv < 0 || P.nfr == 0) return;
+  const int nn = P.nfr;
+  std::vector<int> level(nn, 0);
+  for (int h = 0; h < P.H; ++h)
+    for (int r = P.lvl_off[h]; r < P.lvl_off[h + 1]; ++r) level[r] = h;
+  auto ntask = [&](int r, int kind) {
+    const int per = 256 / (kind == 0 ? P.gf[r] : P.gb[r]);
+    return ((kind == 0 ? P.n[r] + P.m[r] : P.n[r]) + per - 1) / per;
+  };
+  // subtrees: fronts of each root by level; size = forward tasks
+  std::vector<std::vector<std::vector<int>>> sub;
+  std::vector<int64_t> size;
+  for (int r = 0; r < P.lvl_off[lv + 1]; ++r) {
+    const int p = P.parent[r];
+    if (p >= 0 && level[p] <= lv) continue;
+    std::vector<std::vector<int>> byl(lv + 1);
+    std::vector<int> stack{r};
+    int64_t sz = 0;
+    while (!stack.empty()) {
+      const int q = stack.back();
+      stack.pop_back();
+      byl[level[q]].push_back(q);
+      sz += ntask(q, 0);
+      for (int k = 0; k < 2; ++k)
+        if (P.ch[2 * q + k] >= 0) stack.push_back(P.ch[2 * q + k]);
+    }
+    for (auto &v : byl) std::sort(v.begin(), v.end());
+    sub.push_back(std::move(byl));
+    size.push_back(sz);
+  }
+  std::vector<int> order(sub.size());
+  for (size_t t = 0; t < order.size(); ++t) order[t] = (int)t;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return size[a] > size[b]; });
+  const int nt = (int)sub.size(), np = lv + 2;
+  P.sub_lv = lv;
+  P.nsubt = nt;
+  P.sph.assign(2 * (size_t)nt * np, 0);
+  auto copy = [&](int r, int kind) {
+    const int t0 = kind == 0 ? P.ft_first[r] : P.bt_first[r];
+    P.stask.insert(P.stask.end(), P.task.begin() + 16 * (int64_t)t0,
+                   P.task.begin() + 16 * (int64_t)(t0 + ntask(r, kind)));
+  };
+  for (int kind = 0; kind < 2; ++kind)
+    for (int t = 0; t < nt; ++t) {
+      int *ph = &P.sph[(size_t)kind * nt * np + (size_t)t * np];
+      for (int k = 0; k <= lv; ++k) {
+        ph[k] = (int)P.stask.size() / 16;
+        for (int r : sub[order[t]][kind == 0 ? k : lv - k]) copy(r, kind);
+      }
+      ph[lv + 1] = (int)P.stask.size() / 16;
+    }
 }
 
 // `leaf`: largest number of subdomains in a leaf box (>= 1).

@@ -49,6 +49,7 @@ int main(int argc, char **argv) {
   NdPlan P;
   nd_plan(L, fk, leaf, P);
   if (const char *e = getenv("ND_TOP")) nd_dense_top(P, atoi(e));   // dense top block of at most $ND_TOP dofs
+  if (const char *e = getenv("ND_SUB")) nd_subtrees(P, atoi(e));     // bottom subtrees of levels 0..$ND_SUB
   printf("N %d\nnF %d\nH %d\nnfr %d\nnk %d\n", L.N, L.nF, P.H, P.nfr, P.nk);
   dump("face_k", fk);
   dump("f_minus", L.f_minus);
@@ -80,6 +81,9 @@ int main(int argc, char **argv) {
   dump("ftask_off", P.ftask_off);
   dump("btask_lo", P.btask_lo);
   dump("btask_hi", P.btask_hi);
+  printf("sub_lv %d\nnsubt %d\n", P.sub_lv, P.nsubt);
+  dump("stask", P.stask);
+  dump("sph", P.sph);
   printf("top %d\nnt %d\n", P.top, P.nt);
   dump("tg_off", P.tg_off);
   dump("tg", P.tg);

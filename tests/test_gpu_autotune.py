@@ -52,6 +52,12 @@ def test_autotuned_solver_solves_as_the_default(prec, top):
     else:
         assert st["coarse_dense"] == 0 and all(t > 0 for t in st["tune_coarse_ms"])
         assert st["tune_coarse_ms"][k] == min(st["tune_coarse_ms"])
+        # bottom-subtree depths 0, 1, ... up to the swept levels, the fastest kept
+        ts = st["tune_subtree_ms"]
+        timed = [c for c in range(len(ts)) if ts[c] > 0]
+        assert timed == list(range(len(timed))) and len(timed) >= 2
+        assert ts[st["sweep_subtree_levels"]] == min(ts[c] for c in timed)
+        print(f"  subtree levels {st['sweep_subtree_levels']}: coarse {np.round(ts, 4)} ms", flush=True)
     assert 1 <= st["t_workgroups"] <= st["n_sub"]
     u, p = s.solve(pr.source, rtol=1e-8)
     st1 = s.stats()

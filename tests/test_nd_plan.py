@@ -36,14 +36,17 @@ def dumper(tmp_path_factory):
     return exe
 
 
-SCALARS = ("N", "nF", "H", "nfr", "nk", "top", "nt")
+SCALARS = ("N", "nF", "H", "nfr", "nk", "top", "nt", "sub_lv", "nsubt")
 
 
-def load(exe, args, top=None):
+def load(exe, args, top=None, sub=None):
     env = dict(os.environ)
     env.pop("ND_TOP", None)
+    env.pop("ND_SUB", None)
     if top is not None:
         env["ND_TOP"] = str(top)
+    if sub is not None:
+        env["ND_SUB"] = str(sub)
     out = subprocess.run([exe] + [str(a) for a in args], capture_output=True, text=True, check=True,
                          env=env).stdout
     d = {}
@@ -203,11 +206,47 @@ def check_tasks(P):
             assert d[12] == want and d[14] == -1
 
 
+def launch_order(P, lvl):
+    """(descriptor, subtree) in the order of the launches: with bottom
+    subtrees (levels 0..sub_lv), each subtree's forward phases, then the
+    forward levels above, the backward levels above, each subtree's backward
+    phases; subtree -1 marks a level-launch task.  The subtree copies must be
+    exactly the level tasks of levels <= sub_lv, phase k of a subtree holding
+    level k forward and level sub_lv - k backward."""
+    T = P["task"].reshape(-1, 16)
+    sl = P["sub_lv"]
+    if sl < 0:
+        assert P["nsubt"] == 0 and len(P["stask"]) == 0
+        return [(d, -1) for d in T]
+    assert sl < P["top"]
+    ns, npk = P["nsubt"], sl + 2
+    ST, sph = P["stask"].reshape(-1, 16), P["sph"]
+    assert len(sph) == 2 * ns * npk
+    fwd, bwd = [], []
+    for t in range(ns):
+        for k in range(sl + 1):
+            for i in range(sph[t * npk + k], sph[t * npk + k + 1]):
+                assert ST[i][11] == 0 and lvl[ST[i][0]] == k
+                fwd.append((ST[i], t))
+            for i in range(sph[(ns + t) * npk + k], sph[(ns + t) * npk + k + 1]):
+                assert ST[i][11] == 1 and lvl[ST[i][0]] == sl - k
+                bwd.append((ST[i], t))
+    low = [d for d in T if lvl[d[0]] <= sl]
+    key = lambda d: tuple(int(v) for v in d[:12])
+    assert sorted(map(key, low)) == sorted(map(key, [d for d, _ in fwd + bwd]))
+    above_f = [(d, -1) for d in T if d[11] == 0 and lvl[d[0]] > sl]
+    above_b = [(d, -1) for d in T if d[11] == 1 and lvl[d[0]] > sl]
+    return fwd + above_f + above_b + bwd
+
+
 def sweep(P, FR, BC, sg, b, K=None):
-    """The sweep tasks serialised in index order (what the level-by-level
-    kernels compute).  With a dense top block (P["top"] < H)
+    """The sweep tasks serialised in launch order (what the level-by-level
+    and subtree kernels compute).  With a dense top block (P["top"] < H)
     the tasks of the top levels are replaced by the gather of t_t and a dense
-    solve with the Schur complement of K on the top dofs."""
+    solve with the Schur complement of K on the top dofs.  A subtree task may
+    only push into (forward) or scatter into (backward) fronts of its own
+    subtree, or, forward from the subtree's root, into a front above the
+    subtree levels: subtrees of one launch never share data."""
     nfr, nk, H = P["nfr"], P["nk"], P["H"]
     top = P["top"]
     nv = P["v_off"][nfr]
@@ -244,8 +283,21 @@ def sweep(P, FR, BC, sg, b, K=None):
                 XB[P["xsc"][k]] = xt[jj]
         del bot
 
-    for d in T:
+    sub_of = {}
+    for d, t in launch_order(P, lvl):
+        if t >= 0:
+            sub_of.setdefault(int(d[0]), t)
+            assert sub_of[int(d[0])] == t, "front in two subtrees"
+    for d, tsub in launch_order(P, lvl):
         p, j, g, n, m, fst, vo, bo, rlo, rhi, slot, kind = (int(v) for v in d[:12])
+        if tsub >= 0 and kind == 0:
+            par = [q for q in range(nfr) if p in P["ch"][2 * q:2 * q + 2]]
+            if par and lvl[par[0]] <= P["sub_lv"]:
+                assert sub_of[par[0]] == tsub, "push into another subtree"
+        if tsub >= 0 and kind == 1:
+            for k in range(P["xsc_off"][fst + j], P["xsc_off"][min(fst + j + 256 // g, fst + n)]):
+                owner = int(np.searchsorted(P["b_off"], P["xsc"][k], side="right")) - 1
+                assert sub_of.get(owner) == tsub, "scatter into another subtree"
         if lvl[p] >= top:
             if kind == 1 and not topped:
                 top_solve()
@@ -313,7 +365,21 @@ CASES = [
 @pytest.mark.parametrize("top", [None, 40, 150, 100000], ids=["sweeps", "top40", "top150", "alldense"])
 @pytest.mark.parametrize("args", CASES, ids=lambda a: "x".join(map(str, a[4:7])) + f"_leaf{a[7]}")
 def test_plan_factor_and_sweeps_match_dense_solve(dumper, args, top):
-    P = load(dumper, args, top)
+    check_plan(dumper, args, top, None)
+
+
+@pytest.mark.parametrize("sub", [0, 2, 99], ids=["sub1", "sub3", "suball"])
+@pytest.mark.parametrize("top", [None, 150], ids=["sweeps", "top150"])
+@pytest.mark.parametrize("args", CASES, ids=lambda a: "x".join(map(str, a[4:7])) + f"_leaf{a[7]}")
+def test_subtree_sweeps_match_dense_solve(dumper, args, top, sub):
+    """Bottom levels 0..sub swept by subtrees (one workgroup each), the rest by level launches."""
+    P = check_plan(dumper, args, top, sub)
+    want = min(sub, P["top"] - 1)
+    assert P["sub_lv"] == (want if want >= 0 and P["nfr"] > 0 else -1)
+
+
+def check_plan(dumper, args, top, sub):
+    P = load(dumper, args, top, sub)
     if top is None:
         assert P["top"] == P["H"] and P["nt"] == 0
     else:
@@ -342,6 +408,7 @@ def test_plan_factor_and_sweeps_match_dense_solve(dumper, args, top):
     x = sweep(P, FR, BC, sg, b, K)
     ref = np.linalg.solve(K, b)
     assert np.linalg.norm(x - ref) / np.linalg.norm(ref) < 1e-10
+    return P
 
 
 def test_single_subdomain_has_no_coarse_dofs(dumper):
