@@ -568,12 +568,14 @@ def main():
         "autotune": {"sweep_widths": [st["sweep_wide4"], st["sweep_wide16"]], "t_workgroups": st["t_workgroups"],
                      "tune_ms": st["t_tune_ms"], "coarse_ms_per_width": st["tune_coarse_ms"],
                      "precond_ms_per_t_grid": st["tune_precond_ms"],
+                     "single_lane_rows_upto": st["sweep_wide1"],
+                     "coarse_ms_per_single_lane_limit": st["tune_wide1_ms"],
                      "subtree_levels": st["sweep_subtree_levels"],
                      "coarse_ms_per_subtree_levels": st["tune_subtree_ms"],
                      "note": "coarse sweeps timed with lane-group widths (8,32) (12,48) (24,96) (48,192), then "
-                             "with the bottom 0..6 levels swept by one launch per direction (a workgroup per "
-                             "subtree); preconditioner with T^i on n_cu/2, n_cu, 2 n_cu, N workgroups; all timed "
-                             "from graph replays"},
+                             "with single-lane rows up to 0, 8, 16, 32 entries, then with the bottom 0..6 levels "
+                             "swept by one launch per direction (a workgroup per subtree); preconditioner with T^i "
+                             "on n_cu/2, n_cu, 2 n_cu, N workgroups; all timed from graph replays"},
         "fp64": {"value": args.steps / r64["total_s"], "unit": "solves/s",
                  "ms_per_step": r64["total_s"] / args.steps * 1e3,
                  "latency_ms": {"p50": float(np.percentile(r64["lat"] * 1e3, 50)),

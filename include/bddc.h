@@ -136,6 +136,9 @@ typedef struct {
                             subtree (0: the library's default; < 0: one
                             launch per level).  BDDC_AUTOTUNE times 0 .. 6
                             levels and keeps the fastest                   */
+  int32_t sweep_single;   /* coarse sweeps: rows and columns of at most this
+                            many entries are taken by one lane each (0:
+                            none).  BDDC_AUTOTUNE times 0, 8, 16, 32        */
 } bddc_options;
 
 typedef struct {
@@ -177,9 +180,12 @@ typedef struct {
   int32_t sweep_subtree_levels; /* coarse sweeps: levels 0 .. this - 1 are swept
                                by one launch per direction, one workgroup per
                                bottom subtree (0: one launch per level)        */
-  int32_t reserved0;
+  int32_t sweep_wide1;      /* coarse sweeps: rows / columns up to this long take
+                               one lane (0: none)                               */
   double tune_subtree_ms[7];/* coarse solve with bottom subtrees of 0 .. 6
                                levels (0 where not timed)                       */
+  double tune_wide1_ms[4];  /* coarse solve with single-lane rows up to 0, 8,
+                               16, 32 entries (0 where not timed)               */
 } bddc_stats_t;
 
 /*

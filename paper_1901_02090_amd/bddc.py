@@ -43,7 +43,8 @@ class Partition(C.Structure):
 class Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("max_it", C.c_int32), ("flags", C.c_uint32), ("coarse_leaf", C.c_int32),
                 ("coarse_top", C.c_int32), ("t_workgroups", C.c_int32), ("ms_source", C.POINTER(C.c_double)),
-                ("bflux", C.POINTER(C.c_double)), ("coarse_subtree", C.c_int32)]
+                ("bflux", C.POINTER(C.c_double)), ("coarse_subtree", C.c_int32),
+                ("sweep_single", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -57,8 +58,8 @@ class Stats(C.Structure):
                 ("device_bytes", C.c_double), ("sweep_wide4", C.c_int32), ("sweep_wide16", C.c_int32),
                 ("t_workgroups", C.c_int32), ("t_tune_ms", C.c_double), ("tune_coarse_ms", C.c_double * 4),
                 ("tune_precond_ms", C.c_double * 4), ("bytes_prec_block", C.c_double),
-                ("flops_block_local", C.c_double), ("sweep_subtree_levels", C.c_int32), ("reserved0", C.c_int32),
-                ("tune_subtree_ms", C.c_double * 7)]
+                ("flops_block_local", C.c_double), ("sweep_subtree_levels", C.c_int32), ("sweep_wide1", C.c_int32),
+                ("tune_subtree_ms", C.c_double * 7), ("tune_wide1_ms", C.c_double * 4)]
 
 
 class ServerOptions(C.Structure):
@@ -234,7 +235,8 @@ class Solver:
 
     def __init__(self, n, h, perm, cuts, tau=math.inf, precision="fp64", max_it=10000, all_constrained=False,
                  coarse_leaf=0, coarse_top=0, t_workgroups=0, multiscale=False,
-                 scaling="multiplicity", ms_source=None, autotune=False, bflux=None, coarse_subtree=0):
+                 scaling="multiplicity", ms_source=None, autotune=False, bflux=None, coarse_subtree=0,
+                 sweep_single=0):
         """ms_source: with multiscale=True, the cell-integrated well source that
         shapes the multiscale sources of the subdomains holding a well.
         bflux: [n_faces_all] prescribed normal fluxes of the boundary faces
@@ -248,6 +250,7 @@ class Solver:
                       (BDDC_AUTOTUNE if autotune else 0),
                       int(coarse_leaf), int(coarse_top), int(t_workgroups))
         opt.coarse_subtree = int(coarse_subtree)
+        opt.sweep_single = int(sweep_single)
         ms = None
         if ms_source is not None:
             ms = np.ascontiguousarray(ms_source, dtype=np.float64).reshape(-1)

@@ -71,6 +71,7 @@ static_assert(sizeof(CgState) <= 32 * sizeof(double), "CG state exceeds its scra
 static __device__ __align__(256) double scratch[NOALLOC_DOUBLES];
 
 constexpr int MAX_DEVICES = 64;
+constexpr size_t SWEEP_STAGE_BYTES = 32768;   // level sweeps stage their task's input in LDS up to this size
 constexpr int SUB_CANDS = 7;   // autotuner: bottom-subtree depths -1 (none) .. 5
 constexpr int SUB_DEFAULT_LEVELS = -1;   // levels swept by bottom subtrees without the autotuner (< 0: none)
 std::mutex g_scratch_mu;
@@ -119,6 +120,7 @@ struct bddc_problem {
   int coarse_leaf = 0;
   int coarse_top = 0;
   int coarse_sub = 0;                             // bottom-subtree levels (0: default, < 0: none)
+  int sweep_single = 0;                           // single-lane sweep rows up to this length (0: none)
   int t_grid = 0;                                 // workgroups of the T^i launch beside the coarse solve
   int n_cu = 0;                                   // compute units of the device
   double tau = 0.0;
@@ -162,6 +164,7 @@ struct bddc_problem {
   bool mc_staged = true;                          // the line kernels' coefficient copies fit in LDS
   double tune_coarse_ms[4] = {0, 0, 0, 0};        // autotuner: coarse solve per sweep width candidate
   double tune_sub_ms[SUB_CANDS] = {};              // autotuner: coarse solve per bottom-subtree depth
+  double tune_w1_ms[4] = {};                       // autotuner: coarse solve per single-lane row limit
   double tune_precond_ms[4] = {0, 0, 0, 0};       // autotuner: preconditioner per T^i grid candidate
   double coarse_bytes = 0.0;
   int64_t *d_pk = nullptr, *d_psi_off = nullptr, *d_Xoff = nullptr, *d_gamma_face = nullptr;
@@ -605,6 +608,7 @@ void do_setup(bddc_problem *h, const bddc_grid *gr, const double *perm, const bd
   NdPlan &P = h->nd;
   try {
     nd_plan(L, h->face_k, h->coarse_leaf, P);
+    if (h->sweep_single > 0) nd_tasks(P, P.wide4, P.wide16, h->sweep_single);
   } catch (const std::logic_error &e) {
     throw Error{BDDC_EINVAL, std::string("coarse plan: ") + e.what()};
   }
@@ -857,7 +861,9 @@ void launch_coarse_solve(bddc_problem *h, hipStream_t s, const int *done) {
                                                  h->cy, done);
   for (int lv = sl + 1; lv < P.top; ++lv) {
     const int t0 = P.ftask_off[lv], nt = P.ftask_off[lv + 1] - t0;
-    k_nd_fwd<<<nt, 256, 0, s>>>(t0, h->sw, h->FR, h->bc, h->cS0, h->cS1, h->cy, done);
+    const size_t shm = (size_t)P.lvl_maxn[lv] * sizeof(double);
+    const int stage = shm <= SWEEP_STAGE_BYTES;
+    k_nd_fwd<<<nt, 256, stage ? shm : 0, s>>>(t0, h->sw, h->FR, h->bc, h->cS0, h->cS1, h->cy, done, stage);
   }
   if (P.nt > 0) {
     const int d0 = P.lvl_dof[P.top];
@@ -867,7 +873,9 @@ void launch_coarse_solve(bddc_problem *h, hipStream_t s, const int *done) {
   }
   for (int lv = P.top - 1; lv > sl; --lv) {
     const int t0 = P.btask_lo[lv], nt = P.btask_hi[lv] - t0;
-    k_nd_bwd<<<nt, 256, 0, s>>>(t0, h->sw, h->BC, h->cy, h->csgn, h->cXB, h->csol, h->bc, done);
+    const size_t shm = (size_t)P.lvl_maxnm[lv] * sizeof(double);
+    const int stage = shm <= SWEEP_STAGE_BYTES;
+    k_nd_bwd<<<nt, 256, stage ? shm : 0, s>>>(t0, h->sw, h->BC, h->cy, h->csgn, h->cXB, h->csol, h->bc, done, stage);
   }
   if (sl >= 0)
     k_nd_bwd_sub<<<P.nsubt, SUB_THREADS, 0, s>>>(sl + 1, h->d_sph + (int64_t)P.nsubt * (sl + 2), h->d_stask, h->sw,
@@ -1075,9 +1083,9 @@ void autotune(bddc_problem *h) {
   NdPlan &P = h->nd;
   const Layout &L = h->L;
   constexpr int REPS = 24;
-  auto set_tasks = [&](int c4, int c16) {
+  auto set_tasks = [&](int c4, int c16, int w1) {
     GateShared g(g_gate);
-    nd_tasks(P, c4, c16);
+    nd_tasks(P, c4, c16, w1);
     HIPCHK(hipStreamSynchronize(h->stream));
     h->release((void *)h->sw.task);
     h->sw.task = (const int4 *)h->upload(P.task);
@@ -1097,13 +1105,28 @@ void autotune(bddc_problem *h) {
     double best = 1e300;
     int bi = 0;
     for (int c = 0; c < 4; ++c) {
-      set_tasks(cand[c][0], cand[c][1]);
+      set_tasks(cand[c][0], cand[c][1], -1);
       const double ms =
           time_graph_ms(h, REPS, [&] { launch_coarse_solve(h, h->stream, nullptr); }, "the coarse solve");
       h->tune_coarse_ms[c] = ms;
       if (ms < best) { best = ms; bi = c; }
     }
-    if (bi != 3) set_tasks(cand[bi][0], cand[bi][1]);   // else the last candidate's tasks are in place
+    if (bi != 3) set_tasks(cand[bi][0], cand[bi][1], -1);   // else the last candidate's tasks are in place
+    // single-lane rows (and columns) up to w1 entries
+    {
+      static const int w1c[4] = {0, 8, 16, 32};
+      const int c4 = P.wide4, c16 = P.wide16;
+      best = 1e300;
+      int bw = 0;
+      for (int c = 0; c < 4; ++c) {
+        set_tasks(c4, c16, w1c[c]);
+        const double ms =
+            time_graph_ms(h, REPS, [&] { launch_coarse_solve(h, h->stream, nullptr); }, "the coarse solve");
+        h->tune_w1_ms[c] = ms;
+        if (ms < best) { best = ms; bw = c; }
+      }
+      if (bw != 3) set_tasks(c4, c16, w1c[bw]);
+    }
     // bottom subtrees: levels [0, lv] in one launch per direction
     const int lv0 = P.sub_lv;
     best = 1e300;
@@ -1677,11 +1700,13 @@ void apply_options(bddc_problem *h, const bddc_options *opt) {
     h->coarse_leaf = opt->coarse_leaf;
     h->coarse_top = opt->coarse_top;
     h->coarse_sub = opt->coarse_subtree;
+    h->sweep_single = opt->sweep_single;
     h->t_grid = opt->t_workgroups;
     h->ms_src = opt->ms_source;
     h->bflux_in = opt->bflux;
   }
   if (h->coarse_top > TOP_MAX_DOFS) throw Error{BDDC_EINVAL, "coarse_top above 8192"};
+  if (h->sweep_single < 0) throw Error{BDDC_EINVAL, "sweep_single must be >= 0"};
   if (h->precision != BDDC_FP64 && h->precision != BDDC_MIXED) throw Error{BDDC_EINVAL, "bad precision"};
 }
 
@@ -1886,6 +1911,8 @@ int bddc_stats(bddc_handle h, bddc_stats_t *out) {
       s.tune_precond_ms[c] = h->tune_precond_ms[c];
     }
     s.sweep_subtree_levels = h->nd.sub_lv + 1;
+    s.sweep_wide1 = h->nd.wide1;
+    for (int c = 0; c < 4; ++c) s.tune_wide1_ms[c] = h->tune_w1_ms[c];
     static_assert(SUB_CANDS == sizeof(s.tune_subtree_ms) / sizeof(double), "subtree candidates");
     for (int c = 0; c < SUB_CANDS; ++c) s.tune_subtree_ms[c] = h->tune_sub_ms[c];
     *out = s;

@@ -40,16 +40,21 @@ __device__ __forceinline__ double group_sum(double v) {
 __device__ __forceinline__ double group_reduce(double v, int g) {
   if (g == 64) return group_sum<64>(v);
   if (g == 16) return group_sum<16>(v);
-  return group_sum<4>(v);
+  if (g == 4) return group_sum<4>(v);
+  return v;
 }
 
 // Rows [d0.y, d0.y + 256/g) of one front, forward: each lane group of g
 // lanes forms one row of R against t_p; rows r < n give z_P[r], rows n + k
 // push w_p[k] into the parent's slot array of this front.  Called by 256
 // lanes (tid = 0 .. 255, whole wavefronts).
+// tl: t_p staged in LDS by the caller (the whole task's workgroup), or null:
+// each lane group forms the t_p entries it needs from b, S0 and S1 (the same
+// sums, so the same bits).  A single lane (g = 1) takes a row with eight
+// independent loads in flight.
 __device__ __forceinline__ void fwd_task(const int4 d0, const int4 d1, const int4 d2, const DevSweep &sw,
                                          const double *__restrict__ FR, const double *__restrict__ b, double *S0,
-                                         double *S1, double *z, int tid) {
+                                         double *S1, double *z, int tid, const double *tl = nullptr) {
   const int g = d0.z, n = d0.w, m = d1.x, fst = d1.y, vo = d1.z, bo = d1.w;
   const int64_t ro = (int64_t)(((uint64_t)(uint32_t)d2.y << 32) | (uint32_t)d2.x);
   const int lane = tid & (g - 1), r = d0.y + tid / g;
@@ -69,18 +74,31 @@ __device__ __forceinline__ void fwd_task(const int4 d0, const int4 d1, const int
     base = S0[vo + r] + S1[vo + r];
     dst = sw.wdst[bo + (r - n)];
   }
-  double a[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int c0 = lane; c0 < len; c0 += 4 * g) {
+  double s;
+  if (g == 1) {
+    double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int c0 = 0; c0 < len; c0 += 8) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int c = c0 + u * g;
-      if (c < len) {
-        const double t = (b[fst + c] + S0[vo + c]) + S1[vo + c];
-        a[u] = fma(row[c], t, a[u]);
+      for (int u = 0; u < 8; ++u) {
+        const int c = c0 + u;
+        if (c < len) a[u] = fma(row[c], tl ? tl[c] : (b[fst + c] + S0[vo + c]) + S1[vo + c], a[u]);
       }
     }
+    s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+  } else {
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int c0 = lane; c0 < len; c0 += 4 * g) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int c = c0 + u * g;
+        if (c < len) {
+          const double t = tl ? tl[c] : (b[fst + c] + S0[vo + c]) + S1[vo + c];
+          a[u] = fma(row[c], t, a[u]);
+        }
+      }
+    }
+    s = group_reduce((a[0] + a[1]) + (a[2] + a[3]), g);
   }
-  const double s = group_reduce((a[0] + a[1]) + (a[2] + a[3]), g);
   if (lane == 0) {
     if (r < n) z[fst + r] = s;
     else (d2.z ? S1 : S0)[dst] = base - s;
@@ -91,10 +109,12 @@ __device__ __forceinline__ void fwd_task(const int4 d0, const int4 d1, const int
 // stored into every B vector that holds d (those of the fronts below), and
 // the right-hand side b[d], consumed by the forward sweep, is cleared for the
 // next solve.  Called by 256 lanes (tid = 0 .. 255, whole wavefronts).
+// vl: the task's input staged in LDS by the caller (sg z over the front's own
+// dofs, then -x_B), or null: read from z, sg and XB as needed.
 __device__ __forceinline__ void bwd_task(const int4 d0, const int4 d1, const int4 d2, const DevSweep &sw,
                                          const double *__restrict__ BC, const double *z,
                                          const double *__restrict__ sg, double *XB, double *__restrict__ x,
-                                         double *__restrict__ b, int tid) {
+                                         double *__restrict__ b, int tid, const double *vl = nullptr) {
   const int g = d0.z, n = d0.w, m = d1.x, fst = d1.y, bo = d1.w;
   const int64_t ro = (int64_t)(((uint64_t)(uint32_t)d2.y << 32) | (uint32_t)d2.x);
   const int lane = tid & (g - 1), c = d0.y + tid / g;
@@ -110,7 +130,7 @@ __device__ __forceinline__ void bwd_task(const int4 d0, const int4 d1, const int
     for (int u = 0; u < 4; ++u) {
       const int q = q0 + u * g;
       if (q < len) {
-        const double in = q < nl ? sg[d + q] * z[d + q] : -xb[q - nl];
+        const double in = vl ? vl[c + q] : (q < nl ? sg[d + q] * z[d + q] : -xb[q - nl]);
         a[u] = fma(col[q], in, a[u]);
       }
     }
@@ -127,23 +147,47 @@ __device__ __forceinline__ void bwd_task(const int4 d0, const int4 d1, const int
 // per workgroup; kernel boundaries order the levels.  The task descriptor is
 // read before the CG stop flag, so that the two loads are in flight together
 // (a level is a few dependent memory round trips long).
+// With stage set, the level kernels stage the task's input vector in LDS
+// (dynamic, at least the largest n_p (forward) or n_p + m_p (backward) of the
+// level's fronts), so that each entry is loaded once per task rather than once
+// per row; the same sums and products, so the same bits.
 __global__ __launch_bounds__(256) void k_nd_fwd(int t0, DevSweep sw, const double *__restrict__ FR,
                                                 const double *__restrict__ b, double *S0, double *S1,
-                                                double *__restrict__ z, const int *done) {
+                                                double *__restrict__ z, const int *done, int stage) {
+  extern __shared__ double tl[];
   const int4 *td = sw.task + 4 * (int64_t)(t0 + blockIdx.x);
   const int4 d0 = td[0], d1 = td[1], d2 = td[2];
   if (done && *done) return;
-  fwd_task(d0, d1, d2, sw, FR, b, S0, S1, z, threadIdx.x);
+  if (!stage) {
+    fwd_task(d0, d1, d2, sw, FR, b, S0, S1, z, threadIdx.x);
+    return;
+  }
+  const int n = d0.w, fst = d1.y, vo = d1.z;
+  // rows [d0.y, d0.y + 256 / g) read t_p up to the last own row of the task
+  const int nt = min(n, d0.y + 256 / d0.z);
+  for (int c = threadIdx.x; c < nt; c += 256) tl[c] = (b[fst + c] + S0[vo + c]) + S1[vo + c];
+  __syncthreads();
+  fwd_task(d0, d1, d2, sw, FR, b, S0, S1, z, threadIdx.x, tl);
 }
 
 __global__ __launch_bounds__(256) void k_nd_bwd(int t0, DevSweep sw, const double *__restrict__ BC,
                                                 const double *__restrict__ z, const double *__restrict__ sg,
                                                 double *XB, double *__restrict__ x, double *__restrict__ b,
-                                                const int *done) {
+                                                const int *done, int stage) {
+  extern __shared__ double vl[];
   const int4 *td = sw.task + 4 * (int64_t)(t0 + blockIdx.x);
   const int4 d0 = td[0], d1 = td[1], d2 = td[2];
   if (done && *done) return;
-  bwd_task(d0, d1, d2, sw, BC, z, sg, XB, x, b, threadIdx.x);
+  if (!stage) {
+    bwd_task(d0, d1, d2, sw, BC, z, sg, XB, x, b, threadIdx.x);
+    return;
+  }
+  // columns c >= d0.y read sg z from dof c on, then -x_B
+  const int n = d0.w, m = d1.x, fst = d1.y, bo = d1.w, cl = d0.y;
+  for (int q = cl + threadIdx.x; q < n + m; q += 256)
+    vl[q] = q < n ? sg[fst + q] * z[fst + q] : -XB[bo + (q - n)];
+  __syncthreads();
+  bwd_task(d0, d1, d2, sw, BC, z, sg, XB, x, b, threadIdx.x, vl);
 }
 
 // Bottom subtrees (nd_subtrees), one per workgroup of SUB_Q x 256 lanes: the

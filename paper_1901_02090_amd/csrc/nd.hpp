@@ -56,7 +56,8 @@ struct NdPlan {
   // parents' B values into their children's B vectors
   std::vector<int> gf, gb;          // [nfr] group widths, forward rows / backward columns
   std::vector<int> parent;          // [nfr] parent front (-1: root)
-  int wide4 = 24, wide16 = 96;      // rows (columns) up to wide4 long take 4 lanes, up to wide16 16, else 64
+  int wide1 = 0, wide4 = 24, wide16 = 96;  // rows (columns) up to wide1 long take 1 lane, up to wide4 4,
+                                           // up to wide16 16, longer ones 64
   std::vector<int> cslot;           // [nfr]
   std::vector<int> wdst;            // [sum m] forward: position of w_c[k] in the parent's vectors
   std::vector<int> xsc_off, xsc;    // [nk+1], [sum m]: every B-vector position holding x[d]
@@ -67,6 +68,7 @@ struct NdPlan {
   std::vector<int> ftask_off;       // [H+1] forward tasks of level h
   std::vector<int> btask_lo, btask_hi;  // [H] backward tasks of level h
   std::vector<int> ft_first, bt_first;  // [nfr] first forward / backward task of each front
+  std::vector<int> lvl_maxn, lvl_maxnm;  // [H] largest n_p and n_p + m_p of the level's fronts
   // bottom subtrees (nd_subtrees): the fronts of levels [0, sub_lv] are swept
   // in one launch per direction, one workgroup per subtree (a front of level
   // <= sub_lv whose parent lies above sub_lv, with all its descendants) taking
@@ -90,16 +92,19 @@ struct NdPlan {
 inline void nd_subtrees(NdPlan &P, int lv);
 
 // Lane-group widths and the task list of the solve sweeps.  A row (forward)
-// or column (backward) of at most wide4 entries is handled by 4 lanes, of at
-// most wide16 by 16, longer ones by 64, so that short rows do not leave lanes
+// or column (backward) of at most wide1 entries is handled by one lane, of at
+// most wide4 by 4 lanes, of at most wide16 by 16, longer ones by 64 (wide1 = 0:
+// no single-lane class), so that short rows do not leave lanes
 // idle; a workgroup of 256 lanes takes 256 / g of them.  Called by nd_plan
 // with the defaults and again by the autotuner with other thresholds (the
 // factor and the dense top block do not depend on them).
-inline void nd_tasks(NdPlan &P, int wide4, int wide16) {
+inline void nd_tasks(NdPlan &P, int wide4, int wide16, int wide1 = -1) {
   const int nn = P.nfr, H = P.H;
+  if (wide1 >= 0) P.wide1 = wide1;   // < 0: keep
   P.wide4 = wide4;
   P.wide16 = wide16;
-  auto width = [&](int len) { return len <= wide4 ? 4 : (len <= wide16 ? 16 : 64); };
+  const int w1 = P.wide1;
+  auto width = [&](int len) { return len <= w1 ? 1 : (len <= wide4 ? 4 : (len <= wide16 ? 16 : 64)); };
   P.gf.assign(nn, 4);
   P.gb.assign(nn, 4);
   for (int r = 0; r < nn; ++r) {
@@ -145,6 +150,13 @@ inline void nd_tasks(NdPlan &P, int wide4, int wide16) {
   P.ftask_off.assign(H + 1, 0);
   P.btask_lo.assign(H, 0);
   P.btask_hi.assign(H, 0);
+  P.lvl_maxn.assign(H, 0);
+  P.lvl_maxnm.assign(H, 0);
+  for (int h = 0; h < H; ++h)
+    for (int r = P.lvl_off[h]; r < P.lvl_off[h + 1]; ++r) {
+      P.lvl_maxn[h] = std::max(P.lvl_maxn[h], P.n[r]);
+      P.lvl_maxnm[h] = std::max(P.lvl_maxnm[h], P.n[r] + P.m[r]);
+    }
   P.ft_first.assign(nn, 0);
   P.bt_first.assign(nn, 0);
   for (int h = 0; h < H; ++h) {

@@ -48,6 +48,7 @@ int main(int argc, char **argv) {
   }
   NdPlan P;
   nd_plan(L, fk, leaf, P);
+  if (const char *e = getenv("ND_W1")) nd_tasks(P, P.wide4, P.wide16, atoi(e));   // single-lane rows up to $ND_W1
   if (const char *e = getenv("ND_TOP")) nd_dense_top(P, atoi(e));   // dense top block of at most $ND_TOP dofs
   if (const char *e = getenv("ND_SUB")) nd_subtrees(P, atoi(e));     // bottom subtrees of levels 0..$ND_SUB
   printf("N %d\nnF %d\nH %d\nnfr %d\nnk %d\n", L.N, L.nF, P.H, P.nfr, P.nk);

@@ -58,6 +58,9 @@ def test_autotuned_solver_solves_as_the_default(prec, top):
         assert timed == list(range(len(timed))) and len(timed) >= 2
         assert ts[st["sweep_subtree_levels"]] == min(ts[c] for c in timed)
         print(f"  subtree levels {st['sweep_subtree_levels']}: coarse {np.round(ts, 4)} ms", flush=True)
+        tw = st["tune_wide1_ms"]
+        assert all(x > 0 for x in tw) and tw[[0, 8, 16, 32].index(st["sweep_wide1"])] == min(tw)
+        print(f"  single-lane rows up to {st['sweep_wide1']}: coarse {np.round(tw, 4)} ms", flush=True)
     assert 1 <= st["t_workgroups"] <= st["n_sub"]
     u, p = s.solve(pr.source, rtol=1e-8)
     st1 = s.stats()

@@ -39,10 +39,13 @@ def dumper(tmp_path_factory):
 SCALARS = ("N", "nF", "H", "nfr", "nk", "top", "nt", "sub_lv", "nsubt")
 
 
-def load(exe, args, top=None, sub=None):
+def load(exe, args, top=None, sub=None, w1=None):
     env = dict(os.environ)
     env.pop("ND_TOP", None)
     env.pop("ND_SUB", None)
+    env.pop("ND_W1", None)
+    if w1 is not None:
+        env["ND_W1"] = str(w1)
     if top is not None:
         env["ND_TOP"] = str(top)
     if sub is not None:
@@ -309,7 +312,7 @@ def sweep(P, FR, BC, sg, b, K=None):
         ro = (rhi & 0xffffffff) << 32 | (rlo & 0xffffffff)
         assert (n, m, fst, vo, bo, ro) == (P["n"][p], P["m"][p], P["first"][p], P["v_off"][p], P["b_off"][p],
                                            P["r_off"][p])
-        assert g in (4, 16, 64)
+        assert g in (1, 4, 16, 64)
         if kind == 0:
             assert slot == P["cslot"][p]
             t = b[fst:fst + n] + S[0][vo:vo + n] + S[1][vo:vo + n]
@@ -378,8 +381,17 @@ def test_subtree_sweeps_match_dense_solve(dumper, args, top, sub):
     assert P["sub_lv"] == (want if want >= 0 and P["nfr"] > 0 else -1)
 
 
-def check_plan(dumper, args, top, sub):
-    P = load(dumper, args, top, sub)
+@pytest.mark.parametrize("w1", [6, 1000], ids=["short1", "all1"])
+@pytest.mark.parametrize("args", CASES, ids=lambda a: "x".join(map(str, a[4:7])) + f"_leaf{a[7]}")
+def test_single_lane_rows_match_dense_solve(dumper, args, w1):
+    """Rows / columns up to w1 entries as tasks of 256 single-lane rows, with bottom subtrees and a top block."""
+    P = check_plan(dumper, args, 150, 2, w1)
+    for g, ln in zip(P["gf"], P["n"]):
+        assert (g == 1) == (ln <= w1)
+
+
+def check_plan(dumper, args, top, sub, w1=None):
+    P = load(dumper, args, top, sub, w1)
     if top is None:
         assert P["top"] == P["H"] and P["nt"] == 0
     else:
