@@ -575,7 +575,7 @@ def main():
                      "note": "coarse sweeps timed with lane-group widths (8,32) (12,48) (24,96) (48,192), then "
                              "with single-lane rows up to 0, 8, 16, 32 entries, then with the bottom 0..6 levels "
                              "swept by one launch per direction (a workgroup per subtree); preconditioner with T^i "
-                             "on n_cu/2, n_cu, 2 n_cu, N workgroups; all timed from graph replays"},
+                             "on 3 n_cu/4, n_cu, 2 n_cu, N workgroups; all timed from graph replays"},
         "fp64": {"value": args.steps / r64["total_s"], "unit": "solves/s",
                  "ms_per_step": r64["total_s"] / args.steps * 1e3,
                  "latency_ms": {"p50": float(np.percentile(r64["lat"] * 1e3, 50)),

@@ -171,7 +171,7 @@ typedef struct {
   double t_tune_ms;         /* wall time of the autotuner (0: not run)           */
   double tune_coarse_ms[4]; /* coarse solve with widths (8,32) (12,48) (24,96)
                                (48,192)                                         */
-  double tune_precond_ms[4];/* preconditioner with T^i on n_cu/2, n_cu, 2 n_cu, N
+  double tune_precond_ms[4];/* preconditioner with T^i on 3 n_cu/4, n_cu, 2 n_cu, N
                                workgroups (n_cu: compute units)                 */
   double bytes_prec_block;  /* algorithmic bytes of one block preconditioner
                                apply (16 columns; 0 before a block solve)      */

@@ -1150,7 +1150,7 @@ void autotune(bddc_problem *h) {
       GateShared g(g_gate);
       fill(h, h->ru, L.nGamma, 1.0);
     }
-    const int cand[] = {h->n_cu / 2, h->n_cu, 2 * h->n_cu, L.N};
+    const int cand[] = {3 * h->n_cu / 4, h->n_cu, 2 * h->n_cu, L.N};
     double best = 1e300;
     int bg = L.N;
     for (int c = 0; c < 4; ++c) {
@@ -1509,9 +1509,8 @@ void launch_precond_blk(bddc_problem *h, CgBlockState *st) {
   k_blk_psi_apply<double><<<N, 256, B.psi_shm, s>>>(h->g, h->Psi64, h->d_psi_off, h->cs.sub_coff, h->cs.sub_cmap,
                                                    B.ru, 0.5, h->lw, B.bc, st);
   HIPCHK(hipEventRecord(h->ev_fork, s));
-  HIPCHK(hipStreamWaitEvent(h->side, h->ev_fork, 0));
-  k_blk_symv<double><<<N, B.symv_threads, B.symv_shm, h->side>>>(h->g, h->T64, h->d_pk, B.ru, 0.5, h->lw, B.yloc, st);
-  HIPCHK(hipEventRecord(h->ev_join, h->side));
+  // the coarse chain before T^i, as in launch_precond (it keeps the queue of
+  // the node it depends on in a captured graph)
   if (h->nk > 0) {
     check_coarse_ptrs(h);
     for (int lv = 0; lv < P.top; ++lv) {
@@ -1533,6 +1532,9 @@ void launch_precond_blk(bddc_problem *h, CgBlockState *st) {
                                         st);
     }
   }
+  HIPCHK(hipStreamWaitEvent(h->side, h->ev_fork, 0));
+  k_blk_symv<double><<<N, B.symv_threads, B.symv_shm, h->side>>>(h->g, h->T64, h->d_pk, B.ru, 0.5, h->lw, B.yloc, st);
+  HIPCHK(hipEventRecord(h->ev_join, h->side));
   k_blk_psi_correct<double><<<N, 256, B.corr_shm, s>>>(h->g, h->cs, h->Psi64, h->d_psi_off, B.csol, B.wloc, st);
   HIPCHK(hipStreamWaitEvent(s, h->ev_join, 0));
   k_blk_average<<<face_blocks(L.nF), 256, 0, s>>>(h->g, h->cs, B.wloc, B.yloc, B.csol, B.zu, B.ru, B.part_z, st);

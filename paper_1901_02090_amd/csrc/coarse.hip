@@ -154,6 +154,7 @@ __device__ __forceinline__ void bwd_task(const int4 d0, const int4 d1, const int
 __global__ __launch_bounds__(256) void k_nd_fwd(int t0, DevSweep sw, const double *__restrict__ FR,
                                                 const double *__restrict__ b, double *S0, double *S1,
                                                 double *__restrict__ z, const int *done, int stage) {
+  __builtin_amdgcn_s_setprio(3);   // the coarse chain is the apply's critical path
   extern __shared__ double tl[];
   const int4 *td = sw.task + 4 * (int64_t)(t0 + blockIdx.x);
   const int4 d0 = td[0], d1 = td[1], d2 = td[2];
@@ -174,6 +175,7 @@ __global__ __launch_bounds__(256) void k_nd_bwd(int t0, DevSweep sw, const doubl
                                                 const double *__restrict__ z, const double *__restrict__ sg,
                                                 double *XB, double *__restrict__ x, double *__restrict__ b,
                                                 const int *done, int stage) {
+  __builtin_amdgcn_s_setprio(3);   // the coarse chain is the apply's critical path
   extern __shared__ double vl[];
   const int4 *td = sw.task + 4 * (int64_t)(t0 + blockIdx.x);
   const int4 d0 = td[0], d1 = td[1], d2 = td[2];
@@ -245,6 +247,7 @@ __global__ __launch_bounds__(256) void k_top_gather(int nt, int d0, const int *_
                                                     const int *__restrict__ tg, const double *__restrict__ b,
                                                     const double *__restrict__ S0, const double *__restrict__ S1,
                                                     double *__restrict__ tt, const int *done) {
+  __builtin_amdgcn_s_setprio(3);   // the coarse chain is the apply's critical path
   const int j = blockIdx.x * 256 + threadIdx.x;
   if (j >= nt) return;
   double v = b[d0 + j];
@@ -274,6 +277,7 @@ __global__ __launch_bounds__(TOP_THREADS) void k_top_gemv(int nt, int ld, const 
                                                           const int *__restrict__ xsc, double *__restrict__ XB,
                                                           double *__restrict__ x, double *__restrict__ b,
                                                           const int *done) {
+  __builtin_amdgcn_s_setprio(3);   // the coarse chain is the apply's critical path
   extern __shared__ double tl[];
   for (int j = threadIdx.x; j < ld; j += TOP_THREADS) tl[j] = j < nt ? tt[j] : 0.0;
   __syncthreads();
