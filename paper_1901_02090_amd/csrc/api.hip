@@ -72,6 +72,7 @@ static __device__ __align__(256) double scratch[NOALLOC_DOUBLES];
 
 constexpr int MAX_DEVICES = 64;
 constexpr size_t SWEEP_STAGE_BYTES = 32768;   // level sweeps stage their task's input in LDS up to this size
+constexpr size_t TOP_STAGE_BYTES = 65536;     // ... and the setup's column sweeps of the top block
 constexpr int SUB_CANDS = 7;   // autotuner: bottom-subtree depths -1 (none) .. 5
 constexpr int SUB_DEFAULT_LEVELS = -1;   // levels swept by bottom subtrees without the autotuner (< 0: none)
 std::mutex g_scratch_mu;
@@ -363,13 +364,17 @@ void setup_dense_top(bddc_problem *h, hipStream_t s) {
     k_top_unit<<<dim3(ub, nc), 256, 0, s>>>(j0, nt, d0, sk, v0, v1, sv, bb, S0b, S1b);
     for (int lv = P.top; lv < P.H; ++lv) {
       const int t0 = P.ftask_off[lv], ntk = P.ftask_off[lv + 1] - t0;
-      k_top_fwd_cols<<<dim3(ntk, (nc + TOP_NC - 1) / TOP_NC), 256, 0, s>>>(t0, h->sw, h->FR, bb, S0b, S1b, zb, sk,
-                                                                           sv, (int)nc, nullptr);
+      const size_t shm = (size_t)TOP_NC * P.lvl_maxn[lv] * sizeof(double);
+      const int stage = shm <= TOP_STAGE_BYTES;
+      k_top_fwd_cols<<<dim3(ntk, (nc + TOP_NC - 1) / TOP_NC), 256, stage ? shm : 0, s>>>(
+          t0, h->sw, h->FR, bb, S0b, S1b, zb, sk, sv, (int)nc, nullptr, stage);
     }
     for (int lv = P.H - 1; lv >= P.top; --lv) {
       const int t0 = P.btask_lo[lv], ntk = P.btask_hi[lv] - t0;
-      k_top_bwd_cols<<<dim3(ntk, (nc + TOP_NC - 1) / TOP_NC), 256, 0, s>>>(t0, h->sw, h->BC, zb, h->csgn, XBb, xb,
-                                                                           sk, sb, (int)nc, nullptr);
+      const size_t shm = (size_t)TOP_NC * P.lvl_maxnm[lv] * sizeof(double);
+      const int stage = shm <= TOP_STAGE_BYTES;
+      k_top_bwd_cols<<<dim3(ntk, (nc + TOP_NC - 1) / TOP_NC), 256, stage ? shm : 0, s>>>(
+          t0, h->sw, h->BC, zb, h->csgn, XBb, xb, sk, sb, (int)nc, nullptr, stage);
     }
     k_top_store<<<dim3(nblk(h->top_ld), nc), 256, 0, s>>>(j0, nt, d0, h->top_ld, xb, sk, h->Kt);
     HIPCHK(hipGetLastError());

@@ -149,19 +149,33 @@ __global__ __launch_bounds__(256) void k_front_schur(DevFronts fd, const int4 *_
 // sweep tasks of coarse.hip for TOP_NC columns per workgroup, so that each
 // entry of R is read once per TOP_NC columns.  Every column's sums run in the
 // order of the single-column tasks (same results).  Columns are stored one
-// after the other (strides sk, sv, sb); done: optional stop flag.
+// after the other (strides sk, sv, sb); done: optional stop flag.  With stage
+// set, each task first stages its columns' inputs in LDS (dynamic: TOP_NC
+// times the level's largest n_p forward, n_p + m_p backward), so that the
+// lane groups do not reload them row after row (the same values).
 constexpr int TOP_NC = 4;
 
 __global__ __launch_bounds__(256) void k_top_fwd_cols(int t0, DevSweep sw, const double *__restrict__ FR,
                                                       const double *__restrict__ b, double *S0, double *S1,
                                                       double *__restrict__ z, int64_t sk, int64_t sv, int ncols,
-                                                      const int *done) {
+                                                      const int *done, int stage) {
+  extern __shared__ double tl[];   // with stage: t_p of the task's columns, [TOP_NC][nt]
   const int4 *td = sw.task + 4 * (int64_t)(t0 + blockIdx.x);
   const int4 d0 = td[0], d1 = td[1], d2 = td[2];
   if (done && *done) return;
   const int c0 = blockIdx.y * TOP_NC, nq = min(TOP_NC, ncols - c0);
   const int g = d0.z, n = d0.w, m = d1.x, fst = d1.y, vo = d1.z, bo = d1.w;
   const int64_t ro = (int64_t)(((uint64_t)(uint32_t)d2.y << 32) | (uint32_t)d2.x);
+  // the task's rows read t_p up to its last own row (all n with a B row)
+  const int nt = min(n, d0.y + 256 / g);
+  if (stage) {
+    for (int e = threadIdx.x; e < nq * nt; e += 256) {
+      const int q = e / nt, c = e - q * nt;
+      const int64_t o = c0 + q;
+      tl[e] = (b[o * sk + fst + c] + S0[o * sv + vo + c]) + S1[o * sv + vo + c];
+    }
+    __syncthreads();
+  }
   const int lane = threadIdx.x & (g - 1), r = d0.y + threadIdx.x / g;
   if (r >= n + m) return;            // whole lane groups leave together
   const double *row;
@@ -173,7 +187,7 @@ __global__ __launch_bounds__(256) void k_top_fwd_cols(int t0, DevSweep sw, const
     row = FR + ro + (int64_t)n * (n + 1) / 2 + (int64_t)(r - n) * n;
     len = n;
   }
-  double base[TOP_NC] = {0.0, 0.0, 0.0, 0.0};
+  double base[TOP_NC] = {};
   int dst = 0;
   if (r >= n && lane == 0) {
     for (int q = 0; q < nq; ++q) {
@@ -193,7 +207,7 @@ __global__ __launch_bounds__(256) void k_top_fwd_cols(int t0, DevSweep sw, const
         for (int q = 0; q < TOP_NC; ++q)
           if (q < nq) {
             const int64_t o = c0 + q;
-            const double t = (b[o * sk + fst + c] + S0[o * sv + vo + c]) + S1[o * sv + vo + c];
+            const double t = stage ? tl[q * nt + c] : (b[o * sk + fst + c] + S0[o * sv + vo + c]) + S1[o * sv + vo + c];
             a[q][u] = fma(rv, t, a[q][u]);
           }
       }
@@ -213,14 +227,25 @@ __global__ __launch_bounds__(256) void k_top_fwd_cols(int t0, DevSweep sw, const
 __global__ __launch_bounds__(256) void k_top_bwd_cols(int t0, DevSweep sw, const double *__restrict__ BC,
                                                       const double *__restrict__ z, const double *__restrict__ sg,
                                                       double *XB, double *__restrict__ x, int64_t sk, int64_t sb,
-                                                      int ncols, const int *done) {
+                                                      int ncols, const int *done, int stage) {
+  extern __shared__ double vl[];   // with stage: the task's inputs, [TOP_NC][n + m - first column]
   const int4 *td = sw.task + 4 * (int64_t)(t0 + blockIdx.x);
   const int4 d0 = td[0], d1 = td[1], d2 = td[2];
   if (done && *done) return;
   const int c0 = blockIdx.y * TOP_NC, nq = min(TOP_NC, ncols - c0);
   const int g = d0.z, n = d0.w, m = d1.x, fst = d1.y, bo = d1.w;
   const int64_t ro = (int64_t)(((uint64_t)(uint32_t)d2.y << 32) | (uint32_t)d2.x);
-  const int lane = threadIdx.x & (g - 1), c = d0.y + threadIdx.x / g;
+  // columns c >= cl read s z from own dof c on, then -x_B
+  const int cl = d0.y, W = n + m - cl;
+  if (stage) {
+    for (int e = threadIdx.x; e < nq * W; e += 256) {
+      const int k = e / W, q = cl + (e - k * W);
+      const int64_t o = c0 + k;
+      vl[e] = q < n ? sg[fst + q] * z[o * sk + fst + q] : -XB[o * sb + bo + (q - n)];
+    }
+    __syncthreads();
+  }
+  const int lane = threadIdx.x & (g - 1), c = cl + threadIdx.x / g;
   if (c >= n) return;
   const int f = n + m, d = fst + c;
   const int s0 = sw.xsc_off[d], s1 = sw.xsc_off[d + 1];
@@ -237,7 +262,8 @@ __global__ __launch_bounds__(256) void k_top_bwd_cols(int t0, DevSweep sw, const
         for (int k = 0; k < TOP_NC; ++k)
           if (k < nq) {
             const int64_t o = c0 + k;
-            const double in = q < nl ? sg[d + q] * z[o * sk + d + q] : -XB[o * sb + bo + (q - nl)];
+            const double in = stage ? vl[k * W + (c - cl) + q]
+                                    : (q < nl ? sg[d + q] * z[o * sk + d + q] : -XB[o * sb + bo + (q - nl)]);
             a[k][u] = fma(cv, in, a[k][u]);
           }
       }
