@@ -73,6 +73,7 @@ static __device__ __align__(256) double scratch[NOALLOC_DOUBLES];
 constexpr int MAX_DEVICES = 64;
 constexpr size_t SWEEP_STAGE_BYTES = 32768;   // level sweeps stage their task's input in LDS up to this size
 constexpr size_t TOP_STAGE_BYTES = 65536;     // ... and the setup's column sweeps of the top block
+constexpr int FRONT_SPLIT = 192;   // fronts with this many own dofs finish their factor over many workgroups
 constexpr int SUB_CANDS = 7;   // autotuner: bottom-subtree depths -1 (none) .. 5
 constexpr int SUB_DEFAULT_LEVELS = -1;   // levels swept by bottom subtrees without the autotuner (< 0: none)
 std::mutex g_scratch_mu;
@@ -743,20 +744,49 @@ void do_setup(bddc_problem *h, const bddc_grid *gr, const double *perm, const bd
       tl_off[lv + 1] = (int)(tl.size() / 4);
     }
     const int4 *d_tl = (const int4 *)h->upload(tl);
+    // fronts of at least FRONT_SPLIT own dofs: rows of L_BP (64 per item),
+    // inverse columns (KB per item), tiles of Q and packed columns (64 per
+    // item) over many workgroups
+    std::vector<int> si_off(P.H + 1, 0), sq_off(P.H + 1, 0), sp_off(P.H + 1, 0), sr_off(P.H + 1, 0);
+    std::vector<int> si, sq, sp, sr;
+    for (int lv = 0; lv < P.H; ++lv) {
+      for (int r = P.lvl_off[lv]; r < P.lvl_off[lv + 1]; ++r) {
+        if (P.n[r] < FRONT_SPLIT) continue;
+        for (int r0 = 0; r0 < P.m[r]; r0 += 64) sr.insert(sr.end(), {r, r0, 0, 0});
+        for (int c0 = 0; c0 < P.n[r]; c0 += KB) si.insert(si.end(), {r, c0, 0, 0});
+        for (int i0 = 0; i0 < P.m[r]; i0 += TILE)
+          for (int j0 = 0; j0 < P.n[r]; j0 += TILE) sq.insert(sq.end(), {r, i0, j0, 0});
+        for (int c0 = 0; c0 < P.n[r]; c0 += 64) sp.insert(sp.end(), {r, c0, 0, 0});
+      }
+      si_off[lv + 1] = (int)(si.size() / 4);
+      sq_off[lv + 1] = (int)(sq.size() / 4);
+      sp_off[lv + 1] = (int)(sp.size() / 4);
+      sr_off[lv + 1] = (int)(sr.size() / 4);
+    }
+    const int4 *d_si = (const int4 *)h->upload(si), *d_sq = (const int4 *)h->upload(sq),
+               *d_sp = (const int4 *)h->upload(sp), *d_sr = (const int4 *)h->upload(sr);
     for (int lv = 0; lv < P.H; ++lv) {
       const int f0 = P.lvl_off[lv], nf = P.lvl_off[lv + 1] - f0;
       k_front_factor<<<nf, 256, 0, s>>>(g, cs, fd, f0, cw.Ac, cw.ac_off, h->dscale, h->csgn, Fall, Wall, Qall,
-                                        h->FR, h->BC, h->d_err);
+                                        h->FR, h->BC, h->d_err, FRONT_SPLIT);
       HIPCHK(hipGetLastError());
+      const int nr = sr_off[lv + 1] - sr_off[lv];
+      if (nr > 0) k_front_rows<<<nr, 256, 0, s>>>(fd, d_sr + sr_off[lv], h->csgn, Fall);
       const int nt = tl_off[lv + 1] - tl_off[lv];
       if (nt > 0) {
         k_front_schur<<<nt, 256, 0, s>>>(fd, d_tl + tl_off[lv], h->csgn, Fall);
         HIPCHK(hipGetLastError());
       }
+      const int ni = si_off[lv + 1] - si_off[lv], nq = sq_off[lv + 1] - sq_off[lv], np = sp_off[lv + 1] - sp_off[lv];
+      if (ni > 0) k_front_inv<<<ni, 256, 0, s>>>(fd, d_si + si_off[lv], Fall, Wall);
+      if (nq > 0) k_front_q<<<nq, 256, 0, s>>>(fd, d_sq + sq_off[lv], Fall, Wall, Qall);
+      if (np > 0) k_front_pack<<<np, 256, 0, s>>>(fd, d_sp + sp_off[lv], Wall, Qall, h->FR, h->BC);
+      HIPCHK(hipGetLastError());
     }
     HIPCHK(hipStreamSynchronize(s));
     check_err(h, "the coarse problem");
     h->release((void *)d_tl);
+    for (const int4 *q : {d_si, d_sq, d_sp, d_sr}) h->release((void *)q);
     h->release(Fall);
     h->release(Wall);
     h->release(Qall);

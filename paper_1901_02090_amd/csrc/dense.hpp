@@ -280,6 +280,48 @@ __device__ __forceinline__ int wg_potrf(int n, double *A, int lda, double *lds, 
 // B <- L^{-1} B  (L lower triangular n x n, B n x nrhs).
 // lower_rhs: column c of B vanishes above row c (B = I, say), and so does the
 // same column of L^{-1} B; block k0 then only involves columns < k0 + NB.
+// Rows [ra, rb) (all >= n) of a partial signed factor whose leading n x n
+// block wg_potrf(n, A, lda, lds, s, n, true) has factored: the panel solves
+// and trailing updates that wg_potrf(n, A, lda, lds, s, nr, true) applies to
+// those rows, in the same blocks and order, so the rows receive the same
+// values.  Rows of different calls are independent (each update of a row
+// reads only that row and the factored leading columns).
+__device__ __forceinline__ void wg_potrf_rows(int n, double *A, int lda, double *lds, const double *s, int ra,
+                                              int rb) {
+  double *Lk = lds + 2 * KT * TILE;  // NB x NB
+  double *sk = Lk + NB * NB;         // NB signs
+  const int tid = threadIdx.x;
+  for (int kb0 = 0; kb0 < n; kb0 += KB) {
+    const int kb1 = min(kb0 + KB, n);
+    for (int k0 = kb0; k0 < kb1; k0 += NB) {
+      const int nb = min(NB, n - k0);
+      lds_load_lower_block(Lk, A, lda, k0, nb);
+      if (tid < NB) sk[tid] = (tid < nb && s) ? s[k0 + tid] : 1.0;
+      __syncthreads();
+      for (int r = ra + tid; r < rb; r += WG) {
+        double x[NB];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) x[j] = A[r + (size_t)(k0 + min(j, nb - 1)) * lda];
+        lds_lower_solve(Lk, x);
+        int ld = lda;
+        asm volatile("" : "+s"(ld) : : "memory");
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+          if (j < nb) A[r + (size_t)(k0 + j) * ld] = x[j] * sk[j];
+      }
+      __syncthreads();
+      const int r0 = k0 + nb;
+      if (r0 < kb1)
+        wg_gemm<false, true>(rb - ra, kb1 - r0, nb, -1.0, A + ra + (size_t)k0 * lda, lda, A + r0 + (size_t)k0 * lda,
+                             lda, 1.0, A + ra + (size_t)r0 * lda, lda, lds, sk);
+    }
+    if (kb1 < n)
+      wg_gemm<false, true>(rb - ra, n - kb1, kb1 - kb0, -1.0, A + ra + (size_t)kb0 * lda, lda,
+                           A + kb1 + (size_t)kb0 * lda, lda, 1.0, A + ra + (size_t)kb1 * lda, lda, lds,
+                           s ? s + kb0 : nullptr);
+  }
+}
+
 __device__ __forceinline__ void wg_trsm_lower(int n, int nrhs, const double *L, int ldl, double *B, int ldb,
                                      double *lds, bool lower_rhs = false) {
   double *Lk = lds + 2 * KT * TILE;

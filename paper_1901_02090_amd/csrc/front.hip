@@ -21,11 +21,14 @@ struct DevFronts {
 
 // Assemble, partially factor and invert the fronts [f0, f0 + gridDim.x) of one
 // level.  F, W (n x n), Q (m x n) are workspaces; FR / BC receive R.
+// Fronts with at least `split` own dofs (0: none) factor only their own block
+// here: L_BP, the inverse, Q and the packing are spread over many workgroups
+// by k_front_rows, k_front_inv, k_front_q and k_front_pack.
 __global__ __launch_bounds__(256, 2) void k_front_factor(DevGeom g, DevCoarse cs, DevFronts fd, int f0,
                                                       const double *__restrict__ Ac, const int64_t *__restrict__ ac_off,
                                                       const double *__restrict__ dscale,
                                                       const double *__restrict__ sgn, double *F, double *W,
-                                                      double *Q, double *FR, double *BC, int *err) {
+                                                      double *Q, double *FR, double *BC, int *err, int split) {
   __shared__ double lds[LDS_DOUBLES];
   const int p = f0 + blockIdx.x, tid = threadIdx.x;
   const int first = fd.first[p], n = fd.n[p], m = fd.m[p], f = n + m;
@@ -101,9 +104,12 @@ __global__ __launch_bounds__(256, 2) void k_front_factor(DevGeom g, DevCoarse cs
     __syncthreads();
   }
   // U = F_BB - L_BP s_P L_BP^T is left to k_front_schur (many workgroups)
-  if (wg_potrf(n, Fp, f, lds, sgn + first, f, true)) {
+  // a large front factors its own block here; k_front_rows forms L_BP
+  const bool big = split > 0 && n >= split;
+  if (wg_potrf(n, Fp, f, lds, sgn + first, big ? n : f, true)) {
     if (tid == 0) atomicOr(err, 64);
   }
+  if (big) return;
   double *Wp = W + fd.w_off[p];
   wg_set_identity(n, Wp, n);
   wg_trsm_lower(n, n, Fp, f, Wp, n, lds, true);
@@ -114,6 +120,79 @@ __global__ __launch_bounds__(256, 2) void k_front_factor(DevGeom g, DevCoarse cs
   const int64_t tri = (int64_t)n * (n + 1) / 2;
   // packing: wave per column c, lanes down the rows r >= c (then the m rows of Q)
   for (int c = wv; c < n; c += NW) {
+    double *Cc = C + (int64_t)c * f - (int64_t)c * (c - 1) / 2;
+    for (int r = c + lane; r < n; r += 64) {
+      const double v = Wp[r + (size_t)c * n];
+      R[(int64_t)r * (r + 1) / 2 + c] = v;
+      Cc[r - c] = v;
+    }
+    for (int k = lane; k < m; k += 64) {
+      const double v = Qp[k + (size_t)c * m];
+      R[tri + (int64_t)k * n + c] = v;
+      Cc[(n - c) + k] = v;
+    }
+  }
+}
+
+// The rest of k_front_factor for the large fronts, over many workgroups.
+// k_front_inv: columns [c0, c0 + KB) of W = L_PP^{-1} (item (front, c0)):
+// the rows above c0 are zero, the rest solve the trailing triangle against
+// the identity columns; with c0 a multiple of KB the blocks line up with those
+// of the single-workgroup solve, so every column sees the same operations.
+__global__ __launch_bounds__(256, 2) void k_front_inv(DevFronts fd, const int4 *__restrict__ items,
+                                                      const double *__restrict__ F, double *W) {
+  __shared__ double lds[LDS_DOUBLES];
+  const int4 it = items[blockIdx.x];
+  const int p = it.x, c0 = it.y;
+  const int n = fd.n[p], m = fd.m[p], f = n + m;
+  const int nc = min(KB, n - c0);
+  const double *Fp = F + fd.F_off[p];
+  double *Wp = W + fd.w_off[p];
+  for (int e = threadIdx.x; e < n * nc; e += WG) {
+    const int r = e % n, c = c0 + e / n;
+    Wp[r + (size_t)c * n] = (r == c) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  wg_trsm_lower(n - c0, nc, Fp + c0 + (size_t)c0 * f, f, Wp + c0 + (size_t)c0 * n, n, lds, true);
+}
+
+// k_front_rows: the B rows [n + r0, n + r0 + 64) of L_BP (item (front, r0)).
+__global__ __launch_bounds__(256, 2) void k_front_rows(DevFronts fd, const int4 *__restrict__ items,
+                                                       const double *__restrict__ sgn, double *F) {
+  __shared__ double lds[LDS_DOUBLES];
+  const int4 it = items[blockIdx.x];
+  const int p = it.x;
+  const int n = fd.n[p], m = fd.m[p], f = n + m;
+  const int ra = n + it.y, rb = min(ra + 64, f);
+  wg_potrf_rows(n, F + fd.F_off[p], f, lds, sgn + fd.first[p], ra, rb);
+}
+
+// k_front_q: one 64 x 64 tile (front, i0, j0) of Q = L_BP W (m x n).
+__global__ __launch_bounds__(256) void k_front_q(DevFronts fd, const int4 *__restrict__ tiles,
+                                                 const double *__restrict__ F, const double *__restrict__ W,
+                                                 double *Q) {
+  __shared__ double lds[2 * KT * TILE];
+  const int4 t = tiles[blockIdx.x];
+  const int p = t.x;
+  const int n = fd.n[p], m = fd.m[p], f = n + m;
+  const double *Fp = F + fd.F_off[p];
+  wg_gemm_tile<false, false>(t.y, t.z, m, n, n, 1.0, Fp + n, f, W + fd.w_off[p], n, 0.0, Q + fd.q_off[p], m, lds,
+                             nullptr);
+}
+
+// k_front_pack: columns [c0, c0 + 64) of R (item (front, c0)), packed as in
+// k_front_factor: a wave per column, lanes down the rows.
+__global__ __launch_bounds__(256) void k_front_pack(DevFronts fd, const int4 *__restrict__ items,
+                                                    const double *__restrict__ W, const double *__restrict__ Q,
+                                                    double *FR, double *BC) {
+  const int4 it = items[blockIdx.x];
+  const int p = it.x;
+  const int n = fd.n[p], m = fd.m[p], f = n + m;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const double *Wp = W + fd.w_off[p], *Qp = Q + fd.q_off[p];
+  double *R = FR + fd.r_off[p], *C = BC + fd.r_off[p];
+  const int64_t tri = (int64_t)n * (n + 1) / 2;
+  for (int c = it.y + wv; c < min(it.y + 64, n); c += 4) {
     double *Cc = C + (int64_t)c * f - (int64_t)c * (c - 1) / 2;
     for (int r = c + lane; r < n; r += 64) {
       const double v = Wp[r + (size_t)c * n];
