@@ -1117,7 +1117,7 @@ void autotune(bddc_problem *h) {
   const auto t0 = std::chrono::steady_clock::now();
   NdPlan &P = h->nd;
   const Layout &L = h->L;
-  constexpr int REPS = 24;
+  constexpr int REPS = 16;   // two timed replays of eight calls after a warm one
   auto set_tasks = [&](int c4, int c16, int w1) {
     GateShared g(g_gate);
     nd_tasks(P, c4, c16, w1);
