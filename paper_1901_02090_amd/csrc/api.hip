@@ -73,6 +73,8 @@ static __device__ __align__(256) double scratch[NOALLOC_DOUBLES];
 constexpr int MAX_DEVICES = 64;
 constexpr size_t SWEEP_STAGE_BYTES = 32768;   // level sweeps stage their task's input in LDS up to this size
 constexpr size_t TOP_STAGE_BYTES = 65536;     // ... and the setup's column sweeps of the top block
+constexpr int LS_SPLIT = 1024;     // subdomains with this many cells finish their local setup over many workgroups
+constexpr int LS_SPLIT_MAX = 8192; // (up to this many: the projection keeps z in 64 KB of LDS)
 constexpr int FRONT_SPLIT = 192;   // fronts with this many own dofs finish their factor over many workgroups
 constexpr int SUB_CANDS = 7;   // autotuner: bottom-subtree depths -1 (none) .. 5
 constexpr int SUB_DEFAULT_LEVELS = -1;   // levels swept by bottom subtrees without the autotuner (< 0: none)
@@ -518,8 +520,39 @@ void do_setup(bddc_problem *h, const bddc_grid *gr, const double *perm, const bd
   sw.pk = h->d_pk = h->upload(opk);
   sw.Spk = h->Spk = h->alloc<double>(pks);
   h->pk_h = opk;
-  LINE_LAUNCH(h->longl, k_local_setup, N, 256, 0, s, g, h->mcoef, sw, h->dscale, h->d_err);
+  LINE_LAUNCH(h->longl, k_local_setup, N, 256, 0, s, g, h->mcoef, sw, h->dscale, h->d_err, LS_SPLIT, LS_SPLIT_MAX);
   HIPCHK(hipGetLastError());
+  {
+    // subdomains of at least LS_SPLIT cells: steps 5-7 over many workgroups
+    std::vector<int> it_cols, it_tiles, it_sym;
+    int maxnc = 0;
+    for (int i = 0; i < N; ++i) {
+      const int nc = L.nc[i], nG = L.nG[i];
+      if (nc < LS_SPLIT || nc > LS_SPLIT_MAX) continue;
+      maxnc = std::max(maxnc, nc);
+      for (int c0 = 0; c0 < nG + 1; c0 += KB) it_cols.insert(it_cols.end(), {i, c0, 0, 0});
+      for (int c0 = 0; c0 < nc; c0 += KB) it_cols.insert(it_cols.end(), {i, c0, 1, 0});
+      for (int i0 = 0; i0 < nG; i0 += TILE)
+        for (int j0 = 0; j0 <= i0; j0 += TILE) it_tiles.insert(it_tiles.end(), {i, i0, 0, j0});
+      for (int i0 = 0; i0 < nc; i0 += TILE)
+        for (int j0 = 0; j0 <= i0; j0 += TILE) it_tiles.insert(it_tiles.end(), {i, i0, 1, j0});
+      for (int c0 = 0; c0 < nG; c0 += 64) it_sym.insert(it_sym.end(), {i, c0, 0, 0});
+      for (int c0 = 0; c0 < nc; c0 += 64) it_sym.insert(it_sym.end(), {i, c0, 1, 0});
+    }
+    if (!it_cols.empty()) {
+      const int4 *d_c = (const int4 *)h->upload(it_cols), *d_t = (const int4 *)h->upload(it_tiles),
+                 *d_y = (const int4 *)h->upload(it_sym);
+      const int nci = (int)it_cols.size() / 4;
+      k_ls_solve<<<nci, 256, 0, s>>>(g, sw, d_c);
+      // the projection needs each subdomain's whole last column of Y: a separate launch
+      k_ls_project<<<nci, 256, (size_t)maxnc * sizeof(double), s>>>(g, sw, d_c);
+      k_ls_gemm<<<(int)it_tiles.size() / 4, 256, 0, s>>>(g, sw, d_t);
+      k_ls_sym<<<(int)it_sym.size() / 4, 256, 0, s>>>(g, sw, d_y);
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipStreamSynchronize(s));
+      for (const int4 *q : {d_c, d_t, d_y}) h->release((void *)q);
+    }
+  }
   k_schur_factor<<<N, 256, 0, s>>>(g, sw, h->d_err);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s));

@@ -122,9 +122,14 @@ __global__ __launch_bounds__(64) void k_face_weights(DevGeom g, const double *__
 // ---------------------------------------------------------------------------
 // per-subdomain: d_i, P, H, S_A, L_P, S^i, X^i
 // ---------------------------------------------------------------------------
+// Subdomains of split .. split_max cells (split = 0: none) stop after the
+// Cholesky of P~ (step 4); k_ls_solve, k_ls_project, k_ls_gemm and k_ls_sym
+// finish them over many workgroups with the same operations per column and
+// per entry.
 template <int CAP>
 __global__ __launch_bounds__(256, 2) void k_local_setup(DevGeom g, const double *__restrict__ mcoef,
-                                                     SetupWs ws, double *dscale, int *err) {
+                                                     SetupWs ws, double *dscale, int *err, int split,
+                                                     int split_max) {
   __shared__ double lds[LDS_DOUBLES];
   __shared__ double red[8];
   const int i = blockIdx.x;
@@ -232,6 +237,7 @@ __global__ __launch_bounds__(256, 2) void k_local_setup(DevGeom g, const double 
   if (wg_potrf(nc, P, nc, lds)) {
     if (tid == 0) atomicOr(err, 2);
   }
+  if (split > 0 && nc >= split && nc <= split_max) return;
   // (5) Y = L_P^{-1} [H c]
   wg_trsm_lower(nc, nG + 1, P, nc, H, ldh, lds);
   double *zc = H + (size_t)nG * ldh;
@@ -252,6 +258,86 @@ __global__ __launch_bounds__(256, 2) void k_local_setup(DevGeom g, const double 
   wg_project_out(nc, zc, nc, V, nc);
   wg_gemm<true, false, true>(nc, nc, nc, 1.0, V, nc, V, nc, 0.0, X, nc, lds);
   wg_symmetrize_lower(nc, X, nc);
+}
+
+// Steps 5-7 of k_local_setup for the large subdomains, over many workgroups.
+// Items are (subdomain, first column or tile row, kind, tile column):
+//   k_ls_solve   kind 0: columns [c0, c0 + KB) of Y = L_P^{-1} [H c];
+//                kind 1: columns [c0, c0 + KB) of V = L_P^{-1} (identity
+//                right-hand side; c0 a multiple of KB, so the blocks line up
+//                with those of the one-workgroup solve);
+//   k_ls_project the same column blocks, Y' = (I - z z^T) Y (columns < nG) or
+//                V' = (I - z z^T) V, z = c / |c| from the last column of Y;
+//   k_ls_gemm    lower 64 x 64 tiles of S += Y'^T Y' (kind 0), X = V'^T V' (kind 1);
+//   k_ls_sym     columns [c0, c0 + 64) of S (kind 0) or X (kind 1) mirrored.
+__global__ __launch_bounds__(256, 2) void k_ls_solve(DevGeom g, SetupWs ws, const int4 *__restrict__ items) {
+  __shared__ double lds[LDS_DOUBLES];
+  const int4 it = items[blockIdx.x];
+  const int i = it.x, c0 = it.y, kind = it.z;
+  const int nc = g.nc[i], nG = g.nG[i];
+  const double *P = ws.base + ws.P[i];
+  if (kind == 0) {
+    double *H = ws.base + ws.H[i];
+    wg_trsm_lower(nc, min(KB, nG + 1 - c0), P, nc, H + (size_t)c0 * nc, nc, lds);
+  } else {
+    double *V = ws.base + ws.V[i];
+    const int ncol = min(KB, nc - c0);
+    for (int e = threadIdx.x; e < nc * ncol; e += WG) {
+      const int r = e % nc, c = c0 + e / nc;
+      V[r + (size_t)c * nc] = (r == c) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    wg_trsm_lower(nc - c0, ncol, P + c0 + (size_t)c0 * nc, nc, V + c0 + (size_t)c0 * nc, nc, lds, true);
+  }
+}
+
+// dynamic LDS: nc doubles (z)
+__global__ __launch_bounds__(256) void k_ls_project(DevGeom g, SetupWs ws, const int4 *__restrict__ items) {
+  extern __shared__ double zl[];
+  __shared__ double red[8];
+  const int4 it = items[blockIdx.x];
+  const int i = it.x, c0 = it.y, kind = it.z;
+  const int nc = g.nc[i], nG = g.nG[i];
+  double *H = ws.base + ws.H[i];
+  const double *zc = H + (size_t)nG * nc;
+  double zz = 0.0;
+  for (int a = threadIdx.x; a < nc; a += WG) zz += zc[a] * zc[a];
+  zz = wg_sum(zz, red);
+  const double zinv = 1.0 / sqrt(zz);
+  for (int a = threadIdx.x; a < nc; a += WG) zl[a] = zc[a] * zinv;
+  __syncthreads();
+  if (kind == 0) {
+    wg_project_out(nc, zl, min(KB, nG - c0), H + (size_t)c0 * nc, nc);
+  } else {
+    double *V = ws.base + ws.V[i];
+    wg_project_out(nc, zl, min(KB, nc - c0), V + (size_t)c0 * nc, nc);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_ls_gemm(DevGeom g, SetupWs ws, const int4 *__restrict__ items) {
+  __shared__ double lds[2 * KT * TILE];
+  const int4 it = items[blockIdx.x];
+  const int i = it.x, i0 = it.y, kind = it.z, j0 = it.w;
+  const int nc = g.nc[i], nG = g.nG[i];
+  if (kind == 0) {
+    const double *H = ws.base + ws.H[i];
+    wg_gemm_tile<true, false, true>(i0, j0, nG, nG, nc, 1.0, H, nc, H, nc, 1.0, ws.base + ws.S[i], nG, lds, nullptr);
+  } else {
+    const double *V = ws.base + ws.V[i];
+    wg_gemm_tile<true, false, true>(i0, j0, nc, nc, nc, 1.0, V, nc, V, nc, 0.0, ws.Xmat + ws.X[i], nc, lds, nullptr);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_ls_sym(DevGeom g, SetupWs ws, const int4 *__restrict__ items) {
+  const int4 it = items[blockIdx.x];
+  const int i = it.x, c0 = it.y, kind = it.z;
+  const int n = kind == 0 ? g.nG[i] : g.nc[i];
+  double *A = kind == 0 ? ws.base + ws.S[i] : ws.Xmat + ws.X[i];
+  const int c1 = min(c0 + 64, n);
+  for (int e = threadIdx.x; e < n * (c1 - c0); e += WG) {
+    const int r = e % n, c = c0 + e / n;
+    if (c > r) A[r + (size_t)c * n] = A[c + (size_t)r * n];
+  }
 }
 
 // Cholesky of S^i and W_S = L_S^{-1}; packed copy of S^i for the CG operator.
