@@ -525,11 +525,15 @@ void do_setup(bddc_problem *h, const bddc_grid *gr, const double *perm, const bd
   {
     // subdomains of at least LS_SPLIT cells: steps 5-7 over many workgroups
     std::vector<int> it_cols, it_tiles, it_sym;
+    std::vector<int64_t> woff(N, 0);
+    int64_t wsz = 0;
     int maxnc = 0;
     for (int i = 0; i < N; ++i) {
       const int nc = L.nc[i], nG = L.nG[i];
       if (nc < LS_SPLIT || nc > LS_SPLIT_MAX) continue;
       maxnc = std::max(maxnc, nc);
+      woff[i] = wsz;
+      wsz += nc;
       for (int c0 = 0; c0 < nG + 1; c0 += KB) it_cols.insert(it_cols.end(), {i, c0, 0, 0});
       for (int c0 = 0; c0 < nc; c0 += KB) it_cols.insert(it_cols.end(), {i, c0, 1, 0});
       for (int i0 = 0; i0 < nG; i0 += TILE)
@@ -542,15 +546,19 @@ void do_setup(bddc_problem *h, const bddc_grid *gr, const double *perm, const bd
     if (!it_cols.empty()) {
       const int4 *d_c = (const int4 *)h->upload(it_cols), *d_t = (const int4 *)h->upload(it_tiles),
                  *d_y = (const int4 *)h->upload(it_sym);
+      const int64_t *d_woff = h->upload(woff);
+      double *d_w = h->alloc<double>(wsz);
       const int nci = (int)it_cols.size() / 4;
       k_ls_solve<<<nci, 256, 0, s>>>(g, sw, d_c);
       // the projection needs each subdomain's whole last column of Y: a separate launch
-      k_ls_project<<<nci, 256, (size_t)maxnc * sizeof(double), s>>>(g, sw, d_c);
-      k_ls_gemm<<<(int)it_tiles.size() / 4, 256, 0, s>>>(g, sw, d_t);
+      k_ls_project<<<nci, 256, (size_t)maxnc * sizeof(double), s>>>(g, sw, d_c, d_woff, d_w);
+      k_ls_gemm<<<(int)it_tiles.size() / 4, 256, 0, s>>>(g, sw, d_t, d_woff, d_w);
       k_ls_sym<<<(int)it_sym.size() / 4, 256, 0, s>>>(g, sw, d_y);
       HIPCHK(hipGetLastError());
       HIPCHK(hipStreamSynchronize(s));
       for (const int4 *q : {d_c, d_t, d_y}) h->release((void *)q);
+      h->release((void *)d_woff);
+      h->release(d_w);
     }
   }
   k_schur_factor<<<N, 256, 0, s>>>(g, sw, h->d_err);

@@ -27,11 +27,13 @@ constexpr int LDS_DOUBLES = 2 * KT * TILE + NB * NB + 2 * NB + 2;
 // j + 16 k, and leaves C(4 r + lane / 16, lane % 16) in result register r.
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
+// r1 (may be null): a rank-one term subtracted from the result,
+// C(i, j) = ... - r1[i] r1[j].
 template <bool TA, bool TB, bool LOWER = false>
 __device__ __forceinline__ void wg_gemm_tile(int i0, int j0, int m, int n, int k, double alpha,
                                              const double *__restrict__ A, int lda, const double *__restrict__ B,
                                              int ldb, double beta, double *C, int ldc, double *lds,
-                                             const double *kscale) {
+                                             const double *kscale, const double *r1 = nullptr) {
   double *As = lds;              // As[kk * TILE + i] = op(A)(i0 + i, k0 + kk)
   double *Bs = lds + KT * TILE;  // Bs[kk * TILE + j] = op(B)(k0 + kk, j0 + j)
   const int tid = threadIdx.x;
@@ -110,7 +112,8 @@ __device__ __forceinline__ void wg_gemm_tile(int i0, int j0, int m, int n, int k
         if (LOWER && gj > gi) continue;
         double *dst = C + gi + (size_t)gj * ldc;
         const double v = acc[bi][bj][r];
-        *dst = (beta == 0.0) ? alpha * v : fma(alpha, v, beta * (*dst));
+        const double o = (beta == 0.0) ? alpha * v : fma(alpha, v, beta * (*dst));
+        *dst = r1 ? fma(-r1[gi], r1[gj], o) : o;
       }
 }
 

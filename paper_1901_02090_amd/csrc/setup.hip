@@ -266,9 +266,12 @@ __global__ __launch_bounds__(256, 2) void k_local_setup(DevGeom g, const double 
 //                kind 1: columns [c0, c0 + KB) of V = L_P^{-1} (identity
 //                right-hand side; c0 a multiple of KB, so the blocks line up
 //                with those of the one-workgroup solve);
-//   k_ls_project the same column blocks, Y' = (I - z z^T) Y (columns < nG) or
-//                V' = (I - z z^T) V, z = c / |c| from the last column of Y;
-//   k_ls_gemm    lower 64 x 64 tiles of S += Y'^T Y' (kind 0), X = V'^T V' (kind 1);
+//   k_ls_project the same column blocks, Y' = (I - z z^T) Y (columns < nG),
+//                z = c / |c| from the last column of Y; or w = V^T z (kind 1);
+//   k_ls_gemm    lower 64 x 64 tiles of S += Y'^T Y' (kind 0) and of
+//                X = V'^T V' = V^T V - w w^T (kind 1, V' = (I - z z^T) V and
+//                |z| = 1): V is lower triangular, so tile (i0, j0 <= i0)
+//                sums over k >= i0 only;
 //   k_ls_sym     columns [c0, c0 + 64) of S (kind 0) or X (kind 1) mirrored.
 __global__ __launch_bounds__(256, 2) void k_ls_solve(DevGeom g, SetupWs ws, const int4 *__restrict__ items) {
   __shared__ double lds[LDS_DOUBLES];
@@ -291,8 +294,9 @@ __global__ __launch_bounds__(256, 2) void k_ls_solve(DevGeom g, SetupWs ws, cons
   }
 }
 
-// dynamic LDS: nc doubles (z)
-__global__ __launch_bounds__(256) void k_ls_project(DevGeom g, SetupWs ws, const int4 *__restrict__ items) {
+// dynamic LDS: nc doubles (z); w at woff[i] in wbuf
+__global__ __launch_bounds__(256) void k_ls_project(DevGeom g, SetupWs ws, const int4 *__restrict__ items,
+                                                    const int64_t *__restrict__ woff, double *wbuf) {
   extern __shared__ double zl[];
   __shared__ double red[8];
   const int4 it = items[blockIdx.x];
@@ -309,12 +313,20 @@ __global__ __launch_bounds__(256) void k_ls_project(DevGeom g, SetupWs ws, const
   if (kind == 0) {
     wg_project_out(nc, zl, min(KB, nG - c0), H + (size_t)c0 * nc, nc);
   } else {
-    double *V = ws.base + ws.V[i];
-    wg_project_out(nc, zl, min(KB, nc - c0), V + (size_t)c0 * nc, nc);
+    // w[c] = sum over k >= c of V(k, c) z[k], a wave per column
+    const double *V = ws.base + ws.V[i];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int c = c0 + wv; c < min(c0 + KB, nc); c += WG / 64) {
+      double d = 0.0;
+      for (int k = c + lane; k < nc; k += 64) d = fma(V[k + (size_t)c * nc], zl[k], d);
+      for (int o = 32; o > 0; o >>= 1) d += __shfl_xor(d, o, 64);
+      if (lane == 0) wbuf[woff[i] + c] = d;
+    }
   }
 }
 
-__global__ __launch_bounds__(256) void k_ls_gemm(DevGeom g, SetupWs ws, const int4 *__restrict__ items) {
+__global__ __launch_bounds__(256) void k_ls_gemm(DevGeom g, SetupWs ws, const int4 *__restrict__ items,
+                                                 const int64_t *__restrict__ woff, const double *__restrict__ wbuf) {
   __shared__ double lds[2 * KT * TILE];
   const int4 it = items[blockIdx.x];
   const int i = it.x, i0 = it.y, kind = it.z, j0 = it.w;
@@ -323,8 +335,10 @@ __global__ __launch_bounds__(256) void k_ls_gemm(DevGeom g, SetupWs ws, const in
     const double *H = ws.base + ws.H[i];
     wg_gemm_tile<true, false, true>(i0, j0, nG, nG, nc, 1.0, H, nc, H, nc, 1.0, ws.base + ws.S[i], nG, lds, nullptr);
   } else {
-    const double *V = ws.base + ws.V[i];
-    wg_gemm_tile<true, false, true>(i0, j0, nc, nc, nc, 1.0, V, nc, V, nc, 0.0, ws.Xmat + ws.X[i], nc, lds, nullptr);
+    // rows k >= i0 of V: V + i0 shifts the summation index
+    const double *V = ws.base + ws.V[i] + i0;
+    wg_gemm_tile<true, false, true>(i0, j0, nc, nc, nc - i0, 1.0, V, nc, V, nc, 0.0, ws.Xmat + ws.X[i], nc, lds,
+                                    nullptr, wbuf + woff[i]);
   }
 }
 
