@@ -534,8 +534,8 @@ void do_setup(bddc_problem *h, const bddc_grid *gr, const double *perm, const bd
       maxnc = std::max(maxnc, nc);
       woff[i] = wsz;
       wsz += nc;
-      for (int c0 = 0; c0 < nG + 1; c0 += KB) it_cols.insert(it_cols.end(), {i, c0, 0, 0});
-      for (int c0 = 0; c0 < nc; c0 += KB) it_cols.insert(it_cols.end(), {i, c0, 1, 0});
+      for (int c0 = 0; c0 < nG + 1; c0 += LS_COLS) it_cols.insert(it_cols.end(), {i, c0, 0, 0});
+      for (int c0 = 0; c0 < nc; c0 += LS_COLS) it_cols.insert(it_cols.end(), {i, c0, 1, 0});
       for (int i0 = 0; i0 < nG; i0 += TILE)
         for (int j0 = 0; j0 <= i0; j0 += TILE) it_tiles.insert(it_tiles.end(), {i, i0, 0, j0});
       for (int i0 = 0; i0 < nc; i0 += TILE)

@@ -124,8 +124,8 @@ __global__ __launch_bounds__(64) void k_face_weights(DevGeom g, const double *__
 // ---------------------------------------------------------------------------
 // Subdomains of split .. split_max cells (split = 0: none) stop after the
 // Cholesky of P~ (step 4); k_ls_solve, k_ls_project, k_ls_gemm and k_ls_sym
-// finish them over many workgroups with the same operations per column and
-// per entry.
+// finish steps 5-7 over many workgroups (the same quantities, summed in
+// another order: X^i through the rank-one form below).
 template <int CAP>
 __global__ __launch_bounds__(256, 2) void k_local_setup(DevGeom g, const double *__restrict__ mcoef,
                                                      SetupWs ws, double *dscale, int *err, int split,
@@ -252,20 +252,35 @@ __global__ __launch_bounds__(256, 2) void k_local_setup(DevGeom g, const double 
   // (6) S = S_A + Y'^T Y'
   wg_gemm<true, false, true>(nG, nG, nc, 1.0, H, ldh, H, ldh, 1.0, S, nG, lds);
   wg_symmetrize_lower(nG, S, nG);
-  // (7) X = V'^T V' with V' = (I - z z^T) L_P^{-1}
+  // (7) X = V'^T V' with V' = (I - z z^T) V, V = L_P^{-1}: as |z| = 1,
+  // X = V^T V - w w^T with w = V^T z, and V is lower triangular, so the
+  // lower tile (i0, j0) sums over k >= i0 only.  w goes into the first column
+  // of P, whose factor is not read again.
   wg_set_identity(nc, V, nc);
   wg_trsm_lower(nc, nc, P, nc, V, nc, lds, true);
-  wg_project_out(nc, zc, nc, V, nc);
-  wg_gemm<true, false, true>(nc, nc, nc, 1.0, V, nc, V, nc, 0.0, X, nc, lds);
+  {
+    const int lane = tid & 63, wv = tid >> 6;
+    for (int c = wv; c < nc; c += WG / 64) {
+      double d = 0.0;
+      for (int k = c + lane; k < nc; k += 64) d = fma(V[k + (size_t)c * nc], zc[k], d);
+      for (int o = 32; o > 0; o >>= 1) d += __shfl_xor(d, o, 64);
+      if (lane == 0) P[c] = d;
+    }
+    __syncthreads();
+  }
+  for (int i0 = 0; i0 < nc; i0 += TILE)
+    for (int j0 = 0; j0 <= i0; j0 += TILE)
+      wg_gemm_tile<true, false, true>(i0, j0, nc, nc, nc - i0, 1.0, V + i0, nc, V + i0, nc, 0.0, X, nc, lds,
+                                      nullptr, P);
+  __syncthreads();
   wg_symmetrize_lower(nc, X, nc);
 }
 
 // Steps 5-7 of k_local_setup for the large subdomains, over many workgroups.
 // Items are (subdomain, first column or tile row, kind, tile column):
-//   k_ls_solve   kind 0: columns [c0, c0 + KB) of Y = L_P^{-1} [H c];
-//                kind 1: columns [c0, c0 + KB) of V = L_P^{-1} (identity
-//                right-hand side; c0 a multiple of KB, so the blocks line up
-//                with those of the one-workgroup solve);
+//   k_ls_solve   kind 0: columns [c0, c0 + LS_COLS) of Y = L_P^{-1} [H c];
+//                kind 1: columns [c0, c0 + LS_COLS) of V = L_P^{-1} (identity
+//                right-hand side: the rows above c0 stay zero);
 //   k_ls_project the same column blocks, Y' = (I - z z^T) Y (columns < nG),
 //                z = c / |c| from the last column of Y; or w = V^T z (kind 1);
 //   k_ls_gemm    lower 64 x 64 tiles of S += Y'^T Y' (kind 0) and of
@@ -273,6 +288,8 @@ __global__ __launch_bounds__(256, 2) void k_local_setup(DevGeom g, const double 
 //                |z| = 1): V is lower triangular, so tile (i0, j0 <= i0)
 //                sums over k >= i0 only;
 //   k_ls_sym     columns [c0, c0 + 64) of S (kind 0) or X (kind 1) mirrored.
+constexpr int LS_COLS = 64;   // columns per item of k_ls_solve / k_ls_project
+
 __global__ __launch_bounds__(256, 2) void k_ls_solve(DevGeom g, SetupWs ws, const int4 *__restrict__ items) {
   __shared__ double lds[LDS_DOUBLES];
   const int4 it = items[blockIdx.x];
@@ -281,10 +298,10 @@ __global__ __launch_bounds__(256, 2) void k_ls_solve(DevGeom g, SetupWs ws, cons
   const double *P = ws.base + ws.P[i];
   if (kind == 0) {
     double *H = ws.base + ws.H[i];
-    wg_trsm_lower(nc, min(KB, nG + 1 - c0), P, nc, H + (size_t)c0 * nc, nc, lds);
+    wg_trsm_lower(nc, min(LS_COLS, nG + 1 - c0), P, nc, H + (size_t)c0 * nc, nc, lds);
   } else {
     double *V = ws.base + ws.V[i];
-    const int ncol = min(KB, nc - c0);
+    const int ncol = min(LS_COLS, nc - c0);
     for (int e = threadIdx.x; e < nc * ncol; e += WG) {
       const int r = e % nc, c = c0 + e / nc;
       V[r + (size_t)c * nc] = (r == c) ? 1.0 : 0.0;
@@ -311,12 +328,12 @@ __global__ __launch_bounds__(256) void k_ls_project(DevGeom g, SetupWs ws, const
   for (int a = threadIdx.x; a < nc; a += WG) zl[a] = zc[a] * zinv;
   __syncthreads();
   if (kind == 0) {
-    wg_project_out(nc, zl, min(KB, nG - c0), H + (size_t)c0 * nc, nc);
+    if (c0 < nG) wg_project_out(nc, zl, min(LS_COLS, nG - c0), H + (size_t)c0 * nc, nc);
   } else {
     // w[c] = sum over k >= c of V(k, c) z[k], a wave per column
     const double *V = ws.base + ws.V[i];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int c = c0 + wv; c < min(c0 + KB, nc); c += WG / 64) {
+    for (int c = c0 + wv; c < min(c0 + LS_COLS, nc); c += WG / 64) {
       double d = 0.0;
       for (int k = c + lane; k < nc; k += 64) d = fma(V[k + (size_t)c * nc], zl[k], d);
       for (int o = 32; o > 0; o >>= 1) d += __shfl_xor(d, o, 64);
