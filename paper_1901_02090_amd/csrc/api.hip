@@ -544,6 +544,43 @@ void do_setup(bddc_problem *h, const bddc_grid *gr, const double *perm, const bd
       for (int c0 = 0; c0 < nc; c0 += 64) it_sym.insert(it_sym.end(), {i, c0, 1, 0});
     }
     if (!it_cols.empty()) {
+      // blocked Cholesky of P~, super-block by super-block (TILE = 64-row panels and tiles)
+      std::vector<int> big;
+      for (int i = 0; i < N; ++i)
+        if (L.nc[i] >= LS_SPLIT && L.nc[i] <= LS_SPLIT_MAX) big.push_back(i);
+      const int nbig = (int)big.size();
+      const int *d_big = h->upload(big);
+      std::vector<int> poff, uoff;   // per step: nbig + 1 prefix sums each
+      std::vector<int> npan, nupd;
+      const int nsteps = (maxnc + KB - 1) / KB;
+      for (int st = 0; st < nsteps; ++st) {
+        const int k1 = st * KB + KB;
+        int pa = 0, up = 0;
+        for (int b = 0; b < nbig; ++b) {
+          poff.push_back(pa);
+          uoff.push_back(up);
+          const int M = L.nc[big[b]] - k1;
+          if (M > 0) {
+            const int q = (M + TILE - 1) / TILE;
+            pa += q;
+            up += q * (q + 1) / 2;
+          }
+        }
+        poff.push_back(pa);
+        uoff.push_back(up);
+        npan.push_back(pa);
+        nupd.push_back(up);
+      }
+      const int *d_poff = h->upload(poff), *d_uoff = h->upload(uoff);
+      for (int st = 0; st < nsteps; ++st) {
+        const int k0 = st * KB;
+        k_pchol_diag<<<nbig, 256, 0, s>>>(g, sw, d_big, k0, h->d_err);
+        if (npan[st] > 0)
+          k_pchol_panel<<<npan[st], 256, 0, s>>>(g, sw, d_big, nbig, d_poff + (size_t)st * (nbig + 1), k0);
+        if (nupd[st] > 0)
+          k_pchol_update<<<nupd[st], 256, 0, s>>>(g, sw, d_big, nbig, d_uoff + (size_t)st * (nbig + 1), k0);
+      }
+      HIPCHK(hipGetLastError());
       const int4 *d_c = (const int4 *)h->upload(it_cols), *d_t = (const int4 *)h->upload(it_tiles),
                  *d_y = (const int4 *)h->upload(it_sym);
       const int64_t *d_woff = h->upload(woff);
@@ -557,6 +594,7 @@ void do_setup(bddc_problem *h, const bddc_grid *gr, const double *perm, const bd
       HIPCHK(hipGetLastError());
       HIPCHK(hipStreamSynchronize(s));
       for (const int4 *q : {d_c, d_t, d_y}) h->release((void *)q);
+      for (const int *q : {d_big, d_poff, d_uoff}) h->release((void *)q);
       h->release((void *)d_woff);
       h->release(d_w);
     }

@@ -122,10 +122,11 @@ __global__ __launch_bounds__(64) void k_face_weights(DevGeom g, const double *__
 // ---------------------------------------------------------------------------
 // per-subdomain: d_i, P, H, S_A, L_P, S^i, X^i
 // ---------------------------------------------------------------------------
-// Subdomains of split .. split_max cells (split = 0: none) stop after the
-// Cholesky of P~ (step 4); k_ls_solve, k_ls_project, k_ls_gemm and k_ls_sym
-// finish steps 5-7 over many workgroups (the same quantities, summed in
-// another order: X^i through the rank-one form below).
+// Subdomains of split .. split_max cells (split = 0: none) stop before the
+// Cholesky of P~ (step 4): k_pchol_diag / _panel / _update factor P~ by
+// blocks over many workgroups, then k_ls_solve, k_ls_project, k_ls_gemm and
+// k_ls_sym finish steps 5-7 (the same quantities, summed in another order:
+// X^i through the rank-one form below).
 template <int CAP>
 __global__ __launch_bounds__(256, 2) void k_local_setup(DevGeom g, const double *__restrict__ mcoef,
                                                      SetupWs ws, double *dscale, int *err, int split,
@@ -234,10 +235,10 @@ __global__ __launch_bounds__(256, 2) void k_local_setup(DevGeom g, const double 
   const double shift = (tr > 0.0) ? tr / ((double)nc * nc) : 1.0;
   for (int e = tid; e < nc * nc; e += WG) P[e] += shift;
   __syncthreads();
+  if (split > 0 && nc >= split && nc <= split_max) return;   // factored by k_pchol_*
   if (wg_potrf(nc, P, nc, lds)) {
     if (tid == 0) atomicOr(err, 2);
   }
-  if (split > 0 && nc >= split && nc <= split_max) return;
   // (5) Y = L_P^{-1} [H c]
   wg_trsm_lower(nc, nG + 1, P, nc, H, ldh, lds);
   double *zc = H + (size_t)nG * ldh;
@@ -288,6 +289,64 @@ __global__ __launch_bounds__(256, 2) void k_local_setup(DevGeom g, const double 
 //                |z| = 1): V is lower triangular, so tile (i0, j0 <= i0)
 //                sums over k >= i0 only;
 //   k_ls_sym     columns [c0, c0 + 64) of S (kind 0) or X (kind 1) mirrored.
+// Right-looking blocked Cholesky of P~ for the large subdomains, one step per
+// super-block [k0, k1 = k0 + KB) (all large subdomains at once; `big` lists
+// them): k_pchol_diag factors the diagonal block, k_pchol_panel the rows
+// below it in blocks of 64 (wg_potrf_rows), k_pchol_update the lower 64 x 64
+// tiles of the trailing matrix.  These are the operations wg_potrf applies
+// per super-block (panel solves and the super-block's own updates, then its
+// delayed trailing update), so every entry gets the same values.  Item
+// offsets per large subdomain: off[b] .. off[b + 1] (prefix sums).
+__device__ __forceinline__ int find_item(const int *__restrict__ off, int nb, int x) {
+  int lo = 0, hi = nb;   // largest b with off[b] <= x
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (off[mid] <= x) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(256, 2) void k_pchol_diag(DevGeom g, SetupWs ws, const int *__restrict__ big, int k0,
+                                                       int *err) {
+  __shared__ double lds[LDS_DOUBLES];
+  const int i = big[blockIdx.x];
+  const int nc = g.nc[i];
+  if (nc <= k0) return;
+  double *P = ws.base + ws.P[i];
+  const int nb = min(KB, nc - k0);
+  if (wg_potrf(nb, P + k0 + (size_t)k0 * nc, nc, lds)) {
+    if (threadIdx.x == 0) atomicOr(err, 2);
+  }
+}
+
+__global__ __launch_bounds__(256, 2) void k_pchol_panel(DevGeom g, SetupWs ws, const int *__restrict__ big, int nbig,
+                                                        const int *__restrict__ off, int k0) {
+  __shared__ double lds[LDS_DOUBLES];
+  const int b = find_item(off, nbig, blockIdx.x);
+  const int i = big[b];
+  const int nc = g.nc[i], k1 = k0 + KB;
+  const int ra = k1 + 64 * (blockIdx.x - off[b]), rb = min(ra + 64, nc);
+  wg_potrf_rows(KB, ws.base + ws.P[i] + k0 + (size_t)k0 * nc, nc, lds, nullptr, ra - k0, rb - k0);
+}
+
+__global__ __launch_bounds__(256) void k_pchol_update(DevGeom g, SetupWs ws, const int *__restrict__ big, int nbig,
+                                                      const int *__restrict__ off, int k0) {
+  __shared__ double lds[2 * KT * TILE];
+  const int b = find_item(off, nbig, blockIdx.x);
+  const int i = big[b];
+  const int nc = g.nc[i], k1 = k0 + KB, M = nc - k1;
+  // lower tile t -> (ti, tj), tj <= ti, t = ti (ti + 1) / 2 + tj
+  const int t = blockIdx.x - off[b];
+  int ti = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+  while (ti * (ti + 1) / 2 > t) --ti;
+  const int tj = t - ti * (ti + 1) / 2;
+  double *P = ws.base + ws.P[i];
+  const double *X = P + k1 + (size_t)k0 * nc;
+  wg_gemm_tile<false, true, true>(64 * ti, 64 * tj, M, M, KB, -1.0, X, nc, X, nc, 1.0, P + k1 + (size_t)k1 * nc, nc,
+                                  lds, nullptr);
+}
+
 constexpr int LS_COLS = 64;   // columns per item of k_ls_solve / k_ls_project
 
 __global__ __launch_bounds__(256, 2) void k_ls_solve(DevGeom g, SetupWs ws, const int4 *__restrict__ items) {
