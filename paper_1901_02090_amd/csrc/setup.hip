@@ -1018,7 +1018,8 @@ __global__ __launch_bounds__(256) void k_face_rows(DevGeom g, double *fbase, con
 // With S = L L^T, W = L^{-1} and the constraint rows C of the subdomain:
 // V = W C^T = Q R,  Psi = S^{-1} C^T (C S^{-1} C^T)^{-1} = W^T Q R^{-T},
 // A_c^i = (C S^{-1} C^T)^{-1} = R^{-1} R^{-T},
-// T = S^{-1} - Psi C S^{-1} = W'^T W' with W' = (I - Q Q^T) W.
+// T = S^{-1} - Psi C S^{-1} = W'^T W' with W' = (I - Q Q^T) W, formed as
+// W^T W - (Q^T W)^T (Q^T W).
 struct CoarseLocalWs {
   double *base;
   const int64_t *off;     // per subdomain workspace offset
@@ -1152,10 +1153,16 @@ __global__ __launch_bounds__(256) void k_coarse_local(DevGeom g, SetupWs ws, Dev
   }
   __syncthreads();
   wg_gemm<false, true>(nci, nci, nci, 1.0, Rinv, nci, Rinv, nci, 0.0, Ac, nci, lds);
-  // W' = W - Q (Q^T W);  T = W'^T W'
+  // T = W'^T W' with W' = (I - Q Q^T) W = W^T W - M1^T M1, M1 = Q^T W (Q has
+  // orthonormal columns).  W = L_S^{-1} is lower triangular, so the lower
+  // tile (i0, j0) of W^T W sums over k >= i0 only.
   wg_gemm<true, false>(nci, nG, nG, 1.0, Q, nG, W, nG, 0.0, M1, nci, lds);
-  wg_gemm<false, false>(nG, nG, nci, -1.0, Q, nG, M1, nci, 1.0, W, nG, lds);
-  wg_gemm<true, false, true>(nG, nG, nG, 1.0, W, nG, W, nG, 0.0, Tfull, nG, lds);
+  for (int i0 = 0; i0 < nG; i0 += TILE)
+    for (int j0 = 0; j0 <= i0; j0 += TILE)
+      wg_gemm_tile<true, false, true>(i0, j0, nG, nG, nG - i0, 1.0, W + i0, nG, W + i0, nG, 0.0, Tfull, nG, lds,
+                                      nullptr);
+  __syncthreads();
+  wg_gemm<true, false, true>(nG, nG, nci, -1.0, M1, nci, M1, nci, 1.0, Tfull, nG, lds);
   const int64_t po = cw.pk[i];
   for (int64_t e = tid; e < gp_size(nG); e += WG) {
     cw.t64[po + e] = 0.0;
