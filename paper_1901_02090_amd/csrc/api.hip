@@ -192,6 +192,7 @@ struct bddc_problem {
   struct Run {
     bool dev = false, eager = false;
     const double *src = nullptr;
+    const double *lsrc = nullptr;                 // source of the local problems (src, plus H_b g)
     double *fl = nullptr, *pr = nullptr;          // device outputs
     double *flux = nullptr, *pressure = nullptr;  // caller's outputs (host unless dev)
     int chunks = 0, checked = 0;                  // chunks launched / whose state was read
@@ -1297,10 +1298,11 @@ void autotune(bddc_problem *h) {
 // bddc_solve runs them back to back with one chunk in flight.
 bool solve_needs_cg(const bddc_problem *h) { return h->L.N > 1 && h->run.upto == 0; }
 
-// start_cg = false stops after the reduced right-hand side f* (in ru), for
-// the block CG, which starts its iterations from several of them.
+// upto_u0 stops after step 1 (u0, and R.lsrc set), for the block CG, which
+// forms the reduced right-hand sides f* of several sources at once and starts
+// its iterations from them.
 void solve_begin_launch(bddc_problem *h, const double *rhs, double rtol, double *flux, double *pressure,
-                        uint32_t flags, bool start_cg = true) {
+                        uint32_t flags, bool upto_u0 = false) {
   const Layout &L = h->L;
   hipStream_t s = h->stream;
   const int N = L.N, nF = L.nF, nGm = L.nGamma;
@@ -1339,6 +1341,7 @@ void solve_begin_launch(bddc_problem *h, const double *rhs, double rtol, double 
     k_axpby<<<nblk(L.ncells), 256, 0, s>>>((int)L.ncells, 1.0, R.src, 1.0, h->d_hb, h->d_srcb);
     src = h->d_srcb;
   }
+  R.lsrc = src;
   // step 1: coarse solve with (0, D F_0), u0 = E Psi alpha
   fill(h, h->bc, h->nk, 0.0);
   k_step1_rhs<<<N, 256, 0, s>>>(h->g, h->cs.pidx, src, h->dscale, h->bc);
@@ -1347,9 +1350,9 @@ void solve_begin_launch(bddc_problem *h, const double *rhs, double rtol, double 
                                           nullptr);
   k_average_balance<<<face_blocks(nF), 256, 0, s>>>(h->g, h->cs, h->wloc, nullptr, h->csol, h->u0, nullptr, nullptr,
                                                     nullptr);
-  if (R.upto) {
+  if (R.upto || upto_u0) {
     // u_0 or u^*: the post-correction with x = 0 continues u_0 into the interiors
-    fill(h, h->xp, N, 0.0);
+    if (R.upto) fill(h, h->xp, N, 0.0);
     HIPCHK(hipGetLastError());
     return;
   }
@@ -1358,7 +1361,6 @@ void solve_begin_launch(bddc_problem *h, const double *rhs, double rtol, double 
   LINE_LAUNCH_S(h->longl, h->mc_staged, k_source_term, N, 256, source_shm(L, h->mc_staged), s, h->g, h->mcoef,
                 h->Xmat, h->d_Xoff, src, h->wloc);
   k_fstar<<<nblk(nGm), 256, 0, s>>>(h->g, h->yloc, h->wloc, h->d_sb, h->ru);
-  if (!start_cg) return;
   fill(h, h->xu, nGm, 0.0);
   fill(h, h->xp, N, 0.0);
   k_norm2_partial<<<vec_blocks(nGm), 256, 0, s>>>(nGm, h->ru, h->cgw.part_r);
@@ -1420,7 +1422,23 @@ int solve_poll(bddc_problem *h, bool wait) {
 // Post-correction of Algorithm "BDDC method": the interior fluxes and
 // pressures of every subdomain from the final interface flux uG and the
 // source (local Dirichlet problems), into the run's outputs (enqueued only).
-void post_correct(bddc_problem *h) {
+// In three parts, so that the block solve can multiply the right-hand sides of
+// all its sources by X^i at once: the pressure right-hand side (rec_y), its
+// product with X^i (rec_p), and the fluxes, pressures and output copies.
+void post_correct_rhs(bddc_problem *h) {
+  const Layout &L = h->L;
+  auto &R = h->run;
+  // step 1 alone continues u_0 with zero source
+  const double *rsrc = R.src;
+  if (R.upto == 1) {
+    fill(h, h->d_zero_src, L.ncells, 0.0);
+    rsrc = h->d_zero_src;
+  }
+  LINE_LAUNCH_S(h->longl, h->mc_staged, k_recover_rhs, L.N, 256, recover_shm(L, h->mc_staged), h->stream, h->g,
+                h->mcoef, rsrc, h->uG, h->rec_y);
+}
+
+void post_correct_out(bddc_problem *h) {
   const Layout &L = h->L;
   hipStream_t s = h->stream;
   const int N = L.N, nGm = L.nGamma;
@@ -1432,18 +1450,8 @@ void post_correct(bddc_problem *h) {
     fill(h, fl, L.nfaces_all, 0.0);
   if (nGm > 0) k_scatter_iface<<<nblk(nGm), 256, 0, s>>>(nGm, h->d_gamma_face, h->uG, fl);
   if (N == 1) fill(h, h->xp, 1, 0.0);
-  // step 1 alone continues u_0 with zero source
-  const double *rsrc = R.src;
-  if (R.upto == 1) {
-    fill(h, h->d_zero_src, L.ncells, 0.0);
-    rsrc = h->d_zero_src;
-  }
-  const size_t rec_shm = recover_shm(L, h->mc_staged);
-  LINE_LAUNCH_S(h->longl, h->mc_staged, k_recover_rhs, N, 256, rec_shm, s, h->g, h->mcoef, rsrc, h->uG, h->rec_y);
-  k_recover_xgemv<<<dim3(N, nblk(L.maxC)), 256, (size_t)L.maxC * sizeof(double), s>>>(h->g, h->Xmat, h->d_Xoff,
-                                                                                       h->rec_y, h->rec_p);
-  LINE_LAUNCH_S(h->longl, h->mc_staged, k_recover_flux, N, 256, rec_shm, s, h->g, h->mcoef, h->uG, h->rec_p, h->xp,
-                h->dscale, fl, pr);
+  LINE_LAUNCH_S(h->longl, h->mc_staged, k_recover_flux, N, 256, recover_shm(L, h->mc_staged), s, h->g, h->mcoef,
+                h->uG, h->rec_p, h->xp, h->dscale, fl, pr);
   k_sum_partial<<<256, 256, 0, s>>>(L.ncells, pr, h->cgw.part_p);
   k_sub_mean<<<256, 256, 0, s>>>(L.ncells, pr, h->cgw.part_p, 256);
   HIPCHK(hipGetLastError());
@@ -1451,6 +1459,14 @@ void post_correct(bddc_problem *h) {
     HIPCHK(hipMemcpyAsync(R.flux, fl, L.nfaces_all * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(R.pressure, pr, L.ncells * sizeof(double), hipMemcpyDeviceToHost, s));
   }
+}
+
+void post_correct(bddc_problem *h) {
+  const Layout &L = h->L;
+  post_correct_rhs(h);
+  k_recover_xgemv<<<dim3(L.N, nblk(L.maxC)), 256, (size_t)L.maxC * sizeof(double), h->stream>>>(
+      h->g, h->Xmat, h->d_Xoff, h->rec_y, h->rec_p);
+  post_correct_out(h);
 }
 
 int solve_finish_locked(bddc_problem *h);
@@ -1590,6 +1606,8 @@ void block_setup(bddc_problem *h) {
   B.S1 = h->alloc<double>(nv * BK);
   B.XB = h->alloc<double>(nbv * BK);
   B.tt = h->alloc<double>((int64_t)std::max(P.nt, 1) * BK);
+  B.cA = h->alloc<double>(L.ncells * BK);
+  B.cB = h->alloc<double>(L.ncells * BK);
   B.part_g = h->alloc<double>((int64_t)PART_BLOCKS * BK);
   B.part_r = h->alloc<double>((int64_t)PART_BLOCKS * BK);
   B.part_z = h->alloc<double>((int64_t)PART_BLOCKS * BK);
@@ -1672,9 +1690,10 @@ void launch_iteration_blk(bddc_problem *h) {
   k_blk_update_p<<<gv, 256, 0, s>>>(nGm, N, h->cs.pidx, B.zu, B.csol, B.pu, B.pp, st);
 }
 
-// Sources [0, k) of one block: steps 1-2 and the reduced right-hand side of
-// each (the single-source kernels), the block CG, and the post-correction of
-// each.  its[j], conv[j], relres[j] (each may be null) receive each source's
+// Sources [0, k) of one block: step 1 of each (the single-source kernels),
+// the reduced right-hand sides f* of all k at once (one pass over S^i and one
+// over X^i), the block CG, and the post-correction (one pass over X^i for the
+// k pressure right-hand sides, then the fluxes of each).  its[j], conv[j], relres[j] (each may be null) receive each source's
 // CG iterations, convergence flag and final relative residual.  Returns the
 // worst status of the block.
 int solve_block_of(bddc_problem *h, int k, const double *rhs, double rtol, double *flux, double *pressure,
@@ -1689,12 +1708,22 @@ int solve_block_of(bddc_problem *h, int k, const double *rhs, double rtol, doubl
   {
     GateShared g(g_gate);
     hipStream_t s = h->stream;
-    fill(h, B.ru, nGm * BK, 0.0);
+    // columns k .. BK-1 (a partial block) stay zero: their f* is zero and
+    // the block CG stops them at once
+    fill(h, B.u0, nGm * BK, 0.0);
+    if (k < BK) fill(h, B.cA, nc * BK, 0.0);
     for (int j = 0; j < k; ++j) {
-      solve_begin_launch(h, rhs + j * nc, rtol, flux + j * nf, pressure + j * nc, flags, false);
-      k_blk_put<<<nblk(nGm), 256, 0, s>>>(nGm, j, h->ru, B.ru);
+      solve_begin_launch(h, rhs + j * nc, rtol, flux + j * nf, pressure + j * nc, flags, true);
       k_blk_put<<<nblk(nGm), 256, 0, s>>>(nGm, j, h->u0, B.u0);
+      k_blk_src_put<<<nblk(nc), 256, 0, s>>>(nc, j, h->g.lcell_global, h->run.lsrc, B.cA);
     }
+    // f* = -S u0 + H^T X F for the block's columns
+    k_blk_symv<double><<<N, B.symv_threads, B.symv_shm, s>>>(h->g, h->Spk, h->d_pk, B.u0, 1.0, nullptr, B.yloc,
+                                                             nullptr);
+    k_blk_xgemm<<<dim3(N, nblk(L.maxC)), 256, 0, s>>>(h->g, h->Xmat, h->d_Xoff, B.cA, B.cB);
+    LINE_LAUNCH_S(h->longl, h->mc_staged, k_blk_source_lines, N, 256, source_shm(L, h->mc_staged), s, h->g,
+                  h->mcoef, B.cB, B.wloc);
+    k_blk_fstar<<<nblk(nGm * BK), 256, 0, s>>>(h->g, B.yloc, B.wloc, h->d_sb, B.ru);
     for (double *v : {B.xu, B.pu}) fill(h, v, nGm * BK, 0.0);
     for (double *v : {B.xp, B.pp}) fill(h, v, (int64_t)N * BK, 0.0);
     k_blk_norm2<<<gv, 256, 0, s>>>(nGm, B.ru, B.part_r);
@@ -1726,26 +1755,37 @@ int solve_block_of(bddc_problem *h, int k, const double *rhs, double rtol, doubl
       if (fs.done) break;
     }
     HIPCHK(hipEventRecord(h->ev1, s));
-    // post-correction source by source
+    // post-correction: the pressure right-hand sides of all sources, one
+    // X^i pass for all of them, then each source's fluxes and pressures
     auto &R = h->run;
-    for (int j = 0; j < k; ++j) {
+    auto set_source = [&](int j) {
       R = bddc_problem::Run();
       R.t0 = t0;
       R.dev = dev;
       R.src = rhs + j * nc;
-      if (!dev) {
-        HIPCHK(hipMemcpyAsync(h->d_src, rhs + j * nc, nc * sizeof(double), hipMemcpyHostToDevice, s));
-        R.src = h->d_src;
-      }
       R.flux = flux + j * nf;
       R.pressure = pressure + j * nc;
       R.fl = dev ? R.flux : h->d_flux;
       R.pr = dev ? R.pressure : h->d_pres;
       k_blk_get<<<nblk(nGm), 256, 0, s>>>(nGm, j, B.xu, h->xu);
       k_blk_get<<<nblk(nGm), 256, 0, s>>>(nGm, j, B.u0, h->u0);
-      k_blk_get<<<nblk(N), 256, 0, s>>>(N, j, B.xp, h->xp);
       k_axpby<<<nblk(nGm), 256, 0, s>>>(nGm, 1.0, h->u0, 1.0, h->xu, h->uG);
-      post_correct(h);
+    };
+    for (int j = 0; j < k; ++j) {   // (columns k .. BK-1 of the products are not read)
+      set_source(j);
+      if (!dev) {
+        HIPCHK(hipMemcpyAsync(h->d_src, rhs + j * nc, nc * sizeof(double), hipMemcpyHostToDevice, s));
+        R.src = h->d_src;
+      }
+      post_correct_rhs(h);
+      k_blk_put<<<nblk(nc), 256, 0, s>>>(nc, j, h->rec_y, B.cA);
+    }
+    k_blk_xgemm<<<dim3(N, nblk(L.maxC)), 256, 0, s>>>(h->g, h->Xmat, h->d_Xoff, B.cA, B.cB);
+    for (int j = 0; j < k; ++j) {
+      set_source(j);
+      k_blk_get<<<nblk(N), 256, 0, s>>>(N, j, B.xp, h->xp);
+      k_blk_get<<<nblk(nc), 256, 0, s>>>(nc, j, B.cB, h->rec_p);
+      post_correct_out(h);
     }
     HIPCHK(hipStreamSynchronize(s));
   }

@@ -33,6 +33,7 @@ struct BlockWs {
   double *S0 = nullptr, *S1 = nullptr;       // [v_off[nfr]][BK]
   double *XB = nullptr;                      // [b_off[nfr]][BK]
   double *tt = nullptr;                      // [nt][BK]
+  double *cA = nullptr, *cB = nullptr;       // [sum nc][BK]: local cell loads, their X^i products
   double *part_g = nullptr, *part_r = nullptr, *part_z = nullptr;   // [PART_BLOCKS][BK]
   double *alpha_h = nullptr, *beta_h = nullptr;                     // [max_it + 2][BK]
   struct CgBlockState *st = nullptr;
@@ -290,6 +291,135 @@ __global__ void k_blk_put(int64_t n, int j, const double *__restrict__ x, double
 __global__ void k_blk_get(int64_t n, int j, const double *__restrict__ xb, double *__restrict__ x) {
   const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (k < n) x[k] = xb[k * BK + j];
+}
+
+// ---- the local interior problems of the block's sources --------------------------
+// Column j of the block's local cell loads: F[e][j] = -f[cell of local cell e]
+// (the sign of the single-source kernel's F^i), e over all subdomains' local
+// cells (the subdomains' local cell order).
+__global__ void k_blk_src_put(int64_t ncells, int j, const int *__restrict__ lcell_global,
+                              const double *__restrict__ src, double *__restrict__ F) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e < ncells) F[e * BK + j] = -src[lcell_global[e]];
+}
+
+// P^i = X^i Y^i for the BK columns of a block, X^i = V'^T V' the symmetric
+// pressure operator of subdomain i's interior problem in full column-major
+// storage (nc x nc), Y and P in [local cell][BK].  The serial kernels read X^i once per
+// source; here one pass over X^i serves all BK sources, as a 16-column product
+// on the FP64 matrix cores (v_mfma_f64_16x16x4f64, the lane layout of
+// k_blk_symv).  Workgroup (i, y) owns the 256 rows 256 y .. 256 y + 255 of
+// subdomain i, wave w the 64 rows R0 = 256 y + 64 w ..; accumulator u holds
+// the rows R0 + 16 u + (lane % 16), so that each load instruction reads 128
+// contiguous bytes of four columns.  Y^i is staged in LDS XG_CK rows at a
+// time (zero padded to whole 16-row tiles).
+constexpr int XG_CK = 128;
+
+__global__ __launch_bounds__(256) void k_blk_xgemm(DevGeom g, const double *__restrict__ Xmat,
+                                                   const int64_t *__restrict__ Xoff, const double *__restrict__ Y,
+                                                   double *__restrict__ P) {
+  __shared__ double ys[XG_CK * BK];
+  const int i = blockIdx.x, nc = g.nc[i];
+  const int rb = (int)blockIdx.y * 256;
+  if (rb >= nc) return;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int64_t co = g.cell_off[i];
+  const double *Xi = Xmat + Xoff[i];
+  const double *Yi = Y + co * BK;
+  const int R0 = rb + 64 * wv;
+  f64x4 acc[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) acc[u] = f64x4{0.0, 0.0, 0.0, 0.0};
+  for (int c0 = 0; c0 < nc; c0 += XG_CK) {
+    const int ck = min(XG_CK, nc - c0);
+    __syncthreads();   // the previous chunk has been used
+    for (int e = tid; e < XG_CK * BK; e += 256) ys[e] = (e < ck * BK) ? Yi[(int64_t)c0 * BK + e] : 0.0;
+    __syncthreads();
+    if (R0 >= nc) continue;   // the wave still takes part in the barriers
+    for (int J = 0; 16 * J < ck; ++J) {
+      const int cl = 16 * J + 4 * lk;   // this lane's chunk columns cl + k (step k)
+      double a[4][4], b[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        b[k] = ys[(cl + k) * BK + li];
+        const int c = c0 + cl + k;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int r = R0 + 16 * u + li;
+          a[k][u] = (r < nc && c < nc) ? __builtin_nontemporal_load(Xi + (int64_t)c * nc + r) : 0.0;
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[k][u], b[k], acc[u], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int row = R0 + 16 * u + 4 * q + lk;
+      if (row < nc) P[(co + row) * BK + li] = acc[u][q];
+    }
+}
+
+// h^i = H^{iT} X^i F^i for the BK columns (the line part of k_source_term,
+// from XF = X^i F^i of k_blk_xgemm): thread pairs (interface dof t, column j),
+// j fastest, so that 16 neighbouring threads solve the same line for the 16
+// columns and read XF coalesced.  h in [sum nG][BK].
+template <int CAP, bool STAGED>
+__global__ __launch_bounds__(256) void k_blk_source_lines(DevGeom g, const double *__restrict__ mcoef,
+                                                          const double *__restrict__ XF, double *__restrict__ hloc) {
+  extern __shared__ double mc[];
+  const int i = blockIdx.x, tid = threadIdx.x;
+  const int nc = g.nc[i], nG = g.nG[i];
+  const int64_t go = g.g_off[i];
+  const int *lcg = g.lcell_global + g.cell_off[i];
+  const double *ys = XF + g.cell_off[i] * BK;
+  if (STAGED) {
+    stage_mcoef(nc, lcg, mcoef, mc);
+    __syncthreads();
+  }
+  int ext[3], st[3];
+  for (int d = 0; d < 3; ++d) ext[d] = g.ext[3 * i + d];
+  st[0] = 1; st[1] = ext[0]; st[2] = ext[0] * ext[1];
+  for (int e = tid; e < nG * BK; e += 256) {
+    const int t = e / BK, j = e % BK;
+    const int64_t fl = go + t;
+    const int d = g.lg_dir[fl], lc = g.lg_cell[fl], end = g.lg_end[fl];
+    const int n = ext[d];
+    const int cd = (lc / st[d]) % n;
+    const int s0 = lc - cd * st[d];
+    int ms;
+    const double *m = line_coef<STAGED>(g, mc, mcoef, lcg, s0, d, st, ms);
+    double y[CAP + 1];
+    const int eidx = end ? n - 1 : 0;
+    double v = (end ? -1.0 : 1.0) * ys[(s0 + eidx * st[d]) * BK + j];
+    if (n >= 2) {
+      y[0] = 0.0;
+      for (int q = 1; q <= n - 1; ++q) y[q] = ys[(s0 + q * st[d]) * BK + j] - ys[(s0 + (q - 1) * st[d]) * BK + j];
+      line_solve_s<CAP>(n, m, ms, y);
+      const int adj = end ? n - 1 : 1;
+      v -= (m[eidx * ms] / 6.0) * y[adj];
+    }
+    hloc[fl * BK + j] = v;
+  }
+}
+
+// f* of eq. (reduced right-hand side) for the BK columns: -assembled S u0 +
+// assembled h (+ the boundary-flux load sb, shared by all sources; may be null).
+__global__ void k_blk_fstar(DevGeom g, const double *__restrict__ yloc, const double *__restrict__ hloc,
+                            const double *__restrict__ sb, double *__restrict__ r) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)g.nGamma * BK) return;
+  const int64_t gi = e / BK;
+  const int j = (int)(e % BK);
+  const int64_t a = g.own_minus[gi], b = g.own_plus[gi];
+  double v = -(yloc[a * BK + j] + yloc[b * BK + j]) + hloc[a * BK + j] + hloc[b * BK + j];
+  if (sb) v += sb[a] + sb[b];
+  r[e] = v;
 }
 
 // ---- local operators on the matrix cores ---------------------------------------
