@@ -1557,9 +1557,7 @@ void block_setup(bddc_problem *h) {
   int maxnc = 0;
   for (int i = 0; i < N; ++i) maxnc = std::max(maxnc, h->sub_coff_h[i + 1] - h->sub_coff_h[i]);
   const size_t nbmax = (size_t)(L.maxG + 15) / 16;
-  B.symv_shm = nbmax * 16 * BK * sizeof(double);
-  B.psi_shm = B.symv_shm + 256 * sizeof(double);
-  B.symv_threads = 2 * B.symv_shm > (size_t)lds_max ? 64 * BLK_SYMV_WAVES : 256;
+  B.psi_shm = nbmax * 16 * BK * sizeof(double) + 256 * sizeof(double);
   B.corr_shm = (size_t)((maxnc + 15) / 16) * 16 * BK * sizeof(double);
   // coarse sweep tasks of the swept levels: 64 rows / columns of a front each
   int maxn = 0;
@@ -1587,7 +1585,7 @@ void block_setup(bddc_problem *h) {
     B.tb_hi[lv] = (int)tk.size() / 12;
   }
   B.fwd_shm = (size_t)((maxn + 3) & ~3) * BK * sizeof(double);
-  if (std::max({B.symv_shm, B.psi_shm, B.corr_shm, B.fwd_shm}) > (size_t)lds_max)
+  if (std::max({B.psi_shm, B.corr_shm, B.fwd_shm}) > (size_t)lds_max)
     throw Error{BDDC_EINVAL, "a subdomain interface, coarse basis or coarse front is too large for the block "
                              "kernels' LDS"};
   const int64_t nG = L.nGamma, totG = L.g_off[N];
@@ -1621,6 +1619,9 @@ void block_setup(bddc_problem *h) {
   HIPCHK(hipStreamSynchronize(h->stream));
   B.ready = true;
 }
+
+// k_blk_symv's grid: one wave per 64-row block of the largest interface
+inline dim3 blk_symv_grid(const Layout &L) { return dim3(L.N, nblk(L.maxG, 64 * BLK_SYMV_WAVES)); }
 
 // grid of the block vector kernels (they leave one partial per block)
 inline int blk_vec_blocks(int64_t n) { return (int)std::min<int64_t>(nblk(n * BK), PART_BLOCKS); }
@@ -1665,7 +1666,7 @@ void launch_precond_blk(bddc_problem *h, CgBlockState *st) {
     }
   }
   HIPCHK(hipStreamWaitEvent(h->side, h->ev_fork, 0));
-  k_blk_symv<double><<<N, B.symv_threads, B.symv_shm, h->side>>>(h->g, h->T64, h->d_pk, B.ru, 0.5, h->lw, B.yloc, st);
+  k_blk_symv<double><<<blk_symv_grid(L), 64 * BLK_SYMV_WAVES, 0, h->side>>>(h->g, h->T64, h->d_pk, B.ru, 0.5, h->lw, B.yloc, st);
   HIPCHK(hipEventRecord(h->ev_join, h->side));
   k_blk_psi_correct<double><<<N, 256, B.corr_shm, s>>>(h->g, h->cs, h->Psi64, h->d_psi_off, B.csol, B.wloc, st);
   HIPCHK(hipStreamWaitEvent(s, h->ev_join, 0));
@@ -1680,7 +1681,7 @@ void launch_iteration_blk(bddc_problem *h) {
   const int N = L.N, nGm = L.nGamma;
   const int gv = blk_vec_blocks(nGm);
   CgBlockState *st = B.st;
-  k_blk_symv<double><<<N, B.symv_threads, B.symv_shm, s>>>(h->g, h->Spk, h->d_pk, B.pu, 1.0, nullptr, B.yloc, st);
+  k_blk_symv<double><<<blk_symv_grid(L), 64 * BLK_SYMV_WAVES, 0, s>>>(h->g, h->Spk, h->d_pk, B.pu, 1.0, nullptr, B.yloc, st);
   k_blk_assemble<<<gv, 256, 0, s>>>(h->g, B.yloc, B.pp, h->dscale, B.pu, B.qu, B.part_g, st);
   k_blk_alpha<<<1, 256, 0, s>>>(st, B.part_g, gv, B.alpha_h);
   k_blk_update_xr<<<gv, 256, 0, s>>>(nGm, N, B.pu, B.qu, B.pp, B.xu, B.ru, B.xp, B.part_r, st);
@@ -1718,7 +1719,7 @@ int solve_block_of(bddc_problem *h, int k, const double *rhs, double rtol, doubl
       k_blk_src_put<<<nblk(nc), 256, 0, s>>>(nc, j, h->g.lcell_global, h->run.lsrc, B.cA);
     }
     // f* = -S u0 + H^T X F for the block's columns
-    k_blk_symv<double><<<N, B.symv_threads, B.symv_shm, s>>>(h->g, h->Spk, h->d_pk, B.u0, 1.0, nullptr, B.yloc,
+    k_blk_symv<double><<<blk_symv_grid(L), 64 * BLK_SYMV_WAVES, 0, s>>>(h->g, h->Spk, h->d_pk, B.u0, 1.0, nullptr, B.yloc,
                                                              nullptr);
     k_blk_xgemm<<<dim3(N, nblk(L.maxC)), 256, 0, s>>>(h->g, h->Xmat, h->d_Xoff, B.cA, B.cB);
     LINE_LAUNCH_S(h->longl, h->mc_staged, k_blk_source_lines, N, 256, source_shm(L, h->mc_staged), s, h->g,
@@ -2299,9 +2300,9 @@ int bddc_time_kernel(bddc_handle h, int32_t which, int32_t reps, double *avg_ms,
     const BlockWs &B = h->blk;
     auto launch = [&]() {
       if (which == BDDC_K_BLOCK_SCHUR)
-        k_blk_symv<double><<<N, B.symv_threads, B.symv_shm, s>>>(h->g, h->Spk, h->d_pk, B.pu, 1.0, nullptr, B.yloc, nullptr);
+        k_blk_symv<double><<<blk_symv_grid(L), 64 * BLK_SYMV_WAVES, 0, s>>>(h->g, h->Spk, h->d_pk, B.pu, 1.0, nullptr, B.yloc, nullptr);
       else if (which == BDDC_K_BLOCK_PRECOND_APPLY)
-        k_blk_symv<double><<<N, B.symv_threads, B.symv_shm, s>>>(h->g, h->T64, h->d_pk, B.ru, 0.5, h->lw, B.yloc, nullptr);
+        k_blk_symv<double><<<blk_symv_grid(L), 64 * BLK_SYMV_WAVES, 0, s>>>(h->g, h->T64, h->d_pk, B.ru, 0.5, h->lw, B.yloc, nullptr);
       else if (which == BDDC_K_SCHUR_APPLY)
         k_symv<double><<<N, SYMV_THREADS, symv_shm(L), s>>>(h->g, h->Spk, h->d_pk, h->pu, 1.0, nullptr, h->yloc, nullptr, nullptr, 0);
       else if (h->precision == BDDC_MIXED)

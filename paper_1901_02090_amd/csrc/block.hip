@@ -37,8 +37,7 @@ struct BlockWs {
   double *part_g = nullptr, *part_r = nullptr, *part_z = nullptr;   // [PART_BLOCKS][BK]
   double *alpha_h = nullptr, *beta_h = nullptr;                     // [max_it + 2][BK]
   struct CgBlockState *st = nullptr;
-  size_t symv_shm = 0, psi_shm = 0, corr_shm = 0, fwd_shm = 0;
-  int symv_threads = 256;                    // k_blk_symv: 8 waves when one workgroup fills a CU's LDS
+  size_t psi_shm = 0, corr_shm = 0, fwd_shm = 0;
 };
 
 struct CgBlockState {
@@ -312,8 +311,9 @@ __global__ void k_blk_src_put(int64_t ncells, int j, const int *__restrict__ lce
 // subdomain i, wave w the 64 rows R0 = 256 y + 64 w ..; accumulator u holds
 // the rows R0 + 16 u + (lane % 16), so that each load instruction reads 128
 // contiguous bytes of four columns.  Y^i is staged in LDS XG_CK rows at a
-// time (zero padded to whole 16-row tiles).
-constexpr int XG_CK = 128;
+// time (zero padded to whole 16-row tiles), and each wave issues the loads
+// of its next tile before the MFMAs of the current one.
+constexpr int XG_CK = 256;
 
 __global__ __launch_bounds__(256) void k_blk_xgemm(DevGeom g, const double *__restrict__ Xmat,
                                                    const int64_t *__restrict__ Xoff, const double *__restrict__ Y,
@@ -331,29 +331,52 @@ __global__ __launch_bounds__(256) void k_blk_xgemm(DevGeom g, const double *__re
   f64x4 acc[4];
 #pragma unroll
   for (int u = 0; u < 4; ++u) acc[u] = f64x4{0.0, 0.0, 0.0, 0.0};
+  // tile J of the chunk at column c0: this lane's columns c0 + 16 J + 4 lk + k
+  // (step k).  Every lane loads, past the edge from a clamped address: a row
+  // past the edge is never stored, and a column past it meets the zero
+  // padding of Y^i (the entries of X^i are finite).  No load sits in a
+  // branch, so the wait before a tile's MFMAs need not cover the next tile's
+  // loads, which are issued first (after a chunk's last tile: the next
+  // chunk's first).
+  auto load_tile = [&](int c0, int J, double (&a)[4][4]) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int c = c0 + 16 * J + 4 * lk + k;
+      const int64_t cb = (int64_t)(c < nc ? c : 0) * nc;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int r = R0 + 16 * u + li;
+        a[k][u] = __builtin_nontemporal_load(Xi + cb + (r < nc ? r : 0));
+      }
+    }
+  };
+  double a[4][4], an[4][4];
+  if (R0 < nc) load_tile(0, 0, a);
+  static_assert(XG_CK % 32 == 0, "tiles are taken in pairs");
   for (int c0 = 0; c0 < nc; c0 += XG_CK) {
     const int ck = min(XG_CK, nc - c0);
     __syncthreads();   // the previous chunk has been used
     for (int e = tid; e < XG_CK * BK; e += 256) ys[e] = (e < ck * BK) ? Yi[(int64_t)c0 * BK + e] : 0.0;
     __syncthreads();
     if (R0 >= nc) continue;   // the wave still takes part in the barriers
-    for (int J = 0; 16 * J < ck; ++J) {
-      const int cl = 16 * J + 4 * lk;   // this lane's chunk columns cl + k (step k)
-      double a[4][4], b[4];
+    // tile J from cur, the loads of tile J + 1 into nxt first
+    auto step = [&](int J, const double (&cur)[4][4], double (&nxt)[4][4]) {
+      load_tile(c0, J + 1, nxt);
+      const int cl = 16 * J + 4 * lk;
+      double b[4];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        b[k] = ys[(cl + k) * BK + li];
-        const int c = c0 + cl + k;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int r = R0 + 16 * u + li;
-          a[k][u] = (r < nc && c < nc) ? __builtin_nontemporal_load(Xi + (int64_t)c * nc + r) : 0.0;
-        }
-      }
+      for (int k = 0; k < 4; ++k) b[k] = ys[(cl + k) * BK + li];
 #pragma unroll
       for (int k = 0; k < 4; ++k)
 #pragma unroll
-        for (int u = 0; u < 4; ++u) acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[k][u], b[k], acc[u], 0, 0, 0);
+        for (int u = 0; u < 4; ++u) acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(cur[k][u], b[k], acc[u], 0, 0, 0);
+    };
+    // tiles in pairs (a, then an), so that no copy waits on loads in flight;
+    // an odd count ends with a tile past the edge (its staged Y rows are zero)
+    const int nt = (((ck + 15) >> 4) + 1) & ~1;
+    for (int J = 0; J < nt; J += 2) {
+      step(J, a, an);
+      step(J + 1, an, a);
     }
   }
 #pragma unroll
@@ -423,14 +446,6 @@ __global__ void k_blk_fstar(DevGeom g, const double *__restrict__ yloc, const do
 }
 
 // ---- local operators on the matrix cores ---------------------------------------
-// M(r, c) of a symmetric matrix in the group-aligned packed lower storage,
-// which holds the entries r >= c (the rest of a diagonal 4 x 4 block is zero
-// padding): an entry above the diagonal is read from its mirror image.
-template <typename TS>
-__device__ __forceinline__ double sym_entry(const TS *__restrict__ M, int n, int r, int c) {
-  return (r >= c) ? (double)M[gp_index(n, r, c)] : (double)M[gp_index(n, c, r)];
-}
-
 // Four consecutive entries of a packed column (16-byte aligned: column
 // segments start at multiples of four entries), widened to FP64.
 __device__ __forceinline__ void load4(const float *p, double *o) {
@@ -443,19 +458,27 @@ __device__ __forceinline__ void load4(const double *p, double *o) {
 }
 
 // Y^i = M^i (w * R_i X) for the BK columns, M^i in packed storage (S^i, or T^i
-// of the preconditioner; FP32 entries are widened).  One workgroup of W = 4
-// or 8 waves per subdomain (grid-stride); w * R_i X is staged in LDS ([16
-// nb][BK], zero padded).  Wave w forms the 64-row blocks w, w + W, ... of Y^i from the
-// whole block row of the symmetric M^i, 16 columns at a time, on the FP64
-// matrix cores (v_mfma_f64_16x16x4f64: A(i, k) from lane i + 16 k, B(k, j)
-// from lane j + 16 k, C(4 q + lane / 16, lane % 16) in register q).  Four
-// accumulators u = 0..3 hold the rows 64 I + 4 i + u, and step s of a
-// 16-column tile J takes the columns 16 J + 4 k + s, so that every lane loads
-// four consecutive stored entries at once: four rows of one column left of the
-// diagonal (feeding the four accumulators), four rows of a mirror column right
-// of it (feeding the four steps); tiles that cross the diagonal are read entry
-// by entry.  M^i is read twice, both times once per block of BK columns.
-constexpr int BLK_SYMV_WAVES = 8;   // at most
+// of the preconditioner; FP32 entries are widened).  Workgroup (i, y) of
+// BLK_SYMV_WAVES waves covers the rows 64 W y .. of subdomain i, one 64-row
+// block I per wave, so a large interface is spread over several workgroups
+// and CUs; w * R_i X is staged in LDS SYMV_CJ 16-row tiles at a time (32 KB
+// whatever the interface size, so that several workgroups share a CU).  Wave
+// I forms its rows of Y^i from the whole block row of the symmetric M^i, 16
+// columns at a time, on the FP64 matrix cores (v_mfma_f64_16x16x4f64: A(i, k)
+// from lane i + 16 k, B(k, j) from lane j + 16 k, C(4 q + lane / 16, lane %
+// 16) in register q).  Four accumulators u = 0..3 hold the rows 64 I + 4 i +
+// u, and step k of a 16-column tile J takes the columns cl + k, cl = 16 J + 4
+// (lane / 16): a lane needs the 4 x 4 block M(r0 + u, cl + k), r0 = 64 I + 4
+// i.  Every lane reads four consecutive stored entries per k: at or below the
+// diagonal (r0 >= cl) the rows r0 .. r0 + 3 of the columns cl + k, above it the
+// rows cl .. cl + 3 of the mirror columns r0 + k, which hold the transpose of
+// the block; the 4 x 4 diagonal blocks (r0 = cl) take their upper half from
+// their own lower half.  So every tile, left of, across or right of the
+// diagonal, issues the same loads, and each wave issues the loads of its next
+// tile before the MFMAs of the current one.  M^i is read twice (as rows and
+// as mirror columns), both times once per block of BK columns.
+constexpr int BLK_SYMV_WAVES = 4;
+constexpr int SYMV_CJ = 16;
 
 template <typename TS>
 __global__ __launch_bounds__(64 * BLK_SYMV_WAVES) void k_blk_symv(DevGeom g, const TS *__restrict__ M,
@@ -463,75 +486,78 @@ __global__ __launch_bounds__(64 * BLK_SYMV_WAVES) void k_blk_symv(DevGeom g, con
                                                                   const double *__restrict__ X, double xscale,
                                                                   const double *__restrict__ xw,
                                                                   double *__restrict__ yloc, const CgBlockState *st) {
-  extern __shared__ double xs[];
+  __shared__ double xs[SYMV_CJ * 16 * BK];
   if (blk_done(st)) return;
+  const int i = blockIdx.x;
+  const int n = g.nG[i], nb = (n + 15) >> 4, np = 4 * ((n + 3) / 4);
+  if (64 * BLK_SYMV_WAVES * (int)blockIdx.y >= n) return;   // whole workgroup past the interface
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  for (int i = blockIdx.x; i < g.N; i += gridDim.x) {
-    const int n = g.nG[i], nb = (n + 15) >> 4, np = 4 * ((n + 3) / 4);
-    const int64_t go = g.g_off[i];
-    for (int e = tid; e < nb * 16 * BK; e += blockDim.x) {
-      const int r = e / BK, j = e % BK;
+  const int I = BLK_SYMV_WAVES * (int)blockIdx.y + wv;   // this wave's 64-row block
+  const bool live = 64 * I < n;
+  const int64_t go = g.g_off[i];
+  const TS *Mi = M + pk[i];
+  f64x4 acc[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) acc[u] = f64x4{0.0, 0.0, 0.0, 0.0};
+  const int r0 = 64 * I + 4 * li;   // this lane's rows r0 + u (accumulator u)
+  // t[k][s]: the stored entries of tile J.  Past the edge (also in the tile
+  // past the last, J = nb) a lane reads the matrix's first entries instead: a
+  // row past the edge is never stored, and a column past it meets the zero
+  // padding of the staged X (the stored entries are finite).  No load sits in
+  // a branch, so the wait before a tile's MFMAs need not cover the next
+  // tile's loads.
+  auto load_tile = [&](int J, double (&t)[4][4]) {
+    const int cl = 16 * J + 4 * lk;
+    const bool ok = r0 < np && cl < np, low = r0 >= cl;
+    const int rr = ok ? (low ? r0 : cl) : 0, cb = ok ? (low ? cl : r0) : 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) load4(Mi + gp_index(n, rr, cb + k), t[k]);
+  };
+  double t[4][4], tn[4][4];
+  if (live) load_tile(0, t);
+  static_assert(SYMV_CJ % 2 == 0, "tiles are taken in pairs");
+  for (int J0 = 0; J0 < nb; J0 += SYMV_CJ) {
+    __syncthreads();   // the previous chunk has been used
+    for (int e = tid; e < SYMV_CJ * 16 * BK; e += 64 * BLK_SYMV_WAVES) {
+      const int r = 16 * J0 + e / BK, j = e % BK;
       xs[e] = (r < n) ? (xw ? xw[go + r] : xscale) * X[(int64_t)g.Rmap[go + r] * BK + j] : 0.0;
     }
     __syncthreads();
-    const TS *Mi = M + pk[i];
-    for (int I = wv; 64 * I < n; I += (int)(blockDim.x >> 6)) {
-      f64x4 acc[4];
+    if (!live) continue;   // the wave still takes part in the barriers
+    // tile J from cur, the loads of tile J + 1 into nxt first
+    auto step = [&](int J, const double (&cur)[4][4], double (&nxt)[4][4]) {
+      load_tile(J + 1, nxt);
+      const int cl = 16 * J + 4 * lk;
+      double b[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) acc[u] = f64x4{0.0, 0.0, 0.0, 0.0};
-      const int r0 = 64 * I + 4 * li;   // this lane's rows r0 + u (accumulator u)
-      for (int J = 0; J < nb; ++J) {
-        const int cl = 16 * J + 4 * lk;   // this lane's columns cl + s (step s)
-        double b[4];
+      for (int k = 0; k < 4; ++k) b[k] = xs[(cl - 16 * J0 + k) * BK + li];
+      // M(r0 + u, cl + k): cur[k][u] at or below the diagonal, cur[u][k] above
 #pragma unroll
-        for (int s2 = 0; s2 < 4; ++s2) b[s2] = xs[(cl + s2) * BK + li];
-        const bool left = 16 * J + 15 <= 64 * I, right = 16 * J >= 64 * I + 64;
-        if (left || right) {
-          // four 16-byte loads: left of the diagonal load k is rows r0 .. r0 + 3
-          // of column cl + k (one entry per accumulator), right of it rows
-          // cl .. cl + 3 of the mirror column r0 + k (one entry per step)
-          double a[4][4];
+      for (int k = 0; k < 4; ++k)
 #pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            a[k][0] = a[k][1] = a[k][2] = a[k][3] = 0.0;
-            if (left ? (r0 < np) : (r0 + k < n && cl < np))
-              load4(Mi + (left ? gp_index(n, r0, cl + k) : gp_index(n, cl, r0 + k)), a[k]);
-          }
-          if (left) {
-#pragma unroll
-            for (int k = 0; k < 4; ++k)
-#pragma unroll
-              for (int u = 0; u < 4; ++u) acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[k][u], b[k], acc[u], 0, 0, 0);
-          } else {
-#pragma unroll
-            for (int k = 0; k < 4; ++k)
-#pragma unroll
-              for (int s2 = 0; s2 < 4; ++s2)
-                acc[k] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[k][s2], b[s2], acc[k], 0, 0, 0);
-          }
-        } else {
-          // the tile crosses the diagonal: entry by entry
-#pragma unroll
-          for (int u = 0; u < 4; ++u)
-#pragma unroll
-            for (int s2 = 0; s2 < 4; ++s2) {
-              const int r = r0 + u, c = cl + s2;
-              const double a = (r < n && c < n) ? sym_entry(Mi, n, r, c) : 0.0;
-              acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[s2], acc[u], 0, 0, 0);
-            }
+        for (int u = 0; u < 4; ++u) {
+          const bool lower = r0 > cl || (r0 == cl && u >= k);
+          acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(lower ? cur[k][u] : cur[u][k], b[k], acc[u], 0, 0, 0);
         }
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int row = 64 * I + 16 * q + 4 * lk + u;
-          if (row < n) yloc[(go + row) * BK + li] = acc[u][q];
-        }
+    };
+    // tiles in pairs (t, then tn), so that no copy waits on loads in flight;
+    // an odd count ends with the tile past the last (J = nb, inside the
+    // chunk's LDS: its staged X rows are zero)
+    const int J1 = J0 + ((min(nb, J0 + SYMV_CJ) - J0 + 1) & ~1);
+    for (int J = J0; J < J1; J += 2) {
+      step(J, t, tn);
+      step(J + 1, tn, t);
     }
-    __syncthreads();   // LDS is reused by the next subdomain
   }
+  if (!live) return;
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int row = 64 * I + 16 * q + 4 * lk + u;
+      if (row < n) yloc[(go + row) * BK + li] = acc[u][q];
+    }
 }
 
 // g^i = Psi^{iT} (w * R_i X) for the BK columns, added into the coarse
