@@ -1560,7 +1560,6 @@ void block_setup(bddc_problem *h) {
   B.psi_shm = nbmax * 16 * BK * sizeof(double) + 256 * sizeof(double);
   B.corr_shm = (size_t)((maxnc + 15) / 16) * 16 * BK * sizeof(double);
   // coarse sweep tasks of the swept levels: 64 rows / columns of a front each
-  int maxn = 0;
   std::vector<int> tk;
   auto push = [&](int r, int j0) {
     const int64_t ro = P.r_off[r];
@@ -1573,7 +1572,6 @@ void block_setup(bddc_problem *h) {
   B.tb_hi.assign(P.top, 0);
   for (int lv = 0; lv < P.top; ++lv) {
     for (int r = P.lvl_off[lv]; r < P.lvl_off[lv + 1]; ++r) {
-      maxn = std::max(maxn, P.n[r]);
       for (int j0 = 0; j0 < P.n[r] + P.m[r]; j0 += BLK_SWEEP_ROWS) push(r, j0);
     }
     B.tf_off[lv + 1] = (int)tk.size() / 12;
@@ -1584,9 +1582,8 @@ void block_setup(bddc_problem *h) {
       for (int c0 = 0; c0 < P.n[r]; c0 += BLK_SWEEP_ROWS) push(r, c0);
     B.tb_hi[lv] = (int)tk.size() / 12;
   }
-  B.fwd_shm = (size_t)((maxn + 3) & ~3) * BK * sizeof(double);
-  if (std::max({B.psi_shm, B.corr_shm, B.fwd_shm}) > (size_t)lds_max)
-    throw Error{BDDC_EINVAL, "a subdomain interface, coarse basis or coarse front is too large for the block "
+  if (std::max(B.psi_shm, B.corr_shm) > (size_t)lds_max)
+    throw Error{BDDC_EINVAL, "a subdomain interface or coarse basis is too large for the block "
                              "kernels' LDS"};
   const int64_t nG = L.nGamma, totG = L.g_off[N];
   const int64_t nk = std::max(h->nk, 1), nv = std::max<int64_t>(P.v_off[P.nfr], 1),
@@ -1649,7 +1646,7 @@ void launch_precond_blk(bddc_problem *h, CgBlockState *st) {
     for (int lv = 0; lv < P.top; ++lv) {
       const int t0 = B.tf_off[lv], nt = B.tf_off[lv + 1] - t0;
       if (nt > 0)
-        k_blk_nd_fwd<<<nt, 256, B.fwd_shm, s>>>(t0, B.task, h->FR, h->sw.wdst, B.bc, B.S0, B.S1, B.cy, st);
+        k_blk_nd_fwd<<<nt, 256, 0, s>>>(t0, B.task, h->FR, h->sw.wdst, B.bc, B.S0, B.S1, B.cy, st);
     }
     if (P.nt > 0) {
       const int d0 = P.lvl_dof[P.top];

@@ -37,7 +37,7 @@ struct BlockWs {
   double *part_g = nullptr, *part_r = nullptr, *part_z = nullptr;   // [PART_BLOCKS][BK]
   double *alpha_h = nullptr, *beta_h = nullptr;                     // [max_it + 2][BK]
   struct CgBlockState *st = nullptr;
-  size_t psi_shm = 0, corr_shm = 0, fwd_shm = 0;
+  size_t psi_shm = 0, corr_shm = 0;
 };
 
 struct CgBlockState {
@@ -709,56 +709,108 @@ __global__ __launch_bounds__(256) void k_blk_average(DevGeom g, DevCoarse cs, co
 // dof}, {v_off, b_off, child slot, 0}, {r_off low, r_off high, 0, 0}.
 constexpr int BLK_SWEEP_ROWS = 64;
 
-// Forward: t_p = b_P + S0_p[P] + S1_p[P] staged in LDS ([n][BK]); rows r < n
-// of R = [L_PP^{-1}; L_BP L_PP^{-1}] (packed lower triangle, then m full rows)
-// give z_P[r], rows n + k push w_p[k] = S0_p[B] + S1_p[B] - row . t_p into
-// the parent's slot array.
+// Forward: t_p = b_P + S0_p[P] + S1_p[P]; rows r < n of R = [L_PP^{-1};
+// L_BP L_PP^{-1}] (packed lower triangle, then m full rows) give z_P[r], rows
+// n + k push w_p[k] = S0_p[B] + S1_p[B] - row . t_p into the parent's slot
+// array.  t_p is staged in LDS FWD_KC entries at a time (32 KB whatever the
+// front size: a level holding one large front among many small ones keeps
+// several workgroups per CU), and the four waves split each chunk's k range:
+// wave w forms the partial products of all 64 rows of the task over its
+// quarter, four 16-row blocks as independent MFMA chains, and the partials
+// are added in LDS in wave order (in the chunk's space).
+constexpr int FWD_KC = 256;
+constexpr int FWD_SHM_DOUBLES = FWD_KC * BK;   // = 4 waves x 64 rows x BK partials
+
 __global__ __launch_bounds__(256) void k_blk_nd_fwd(int t0, const int4 *__restrict__ task,
                                                     const double *__restrict__ FR, const int *__restrict__ wdst,
                                                     const double *__restrict__ b, double *S0, double *S1,
                                                     double *__restrict__ z, const CgBlockState *st) {
-  extern __shared__ double tl[];
+  __shared__ double tl[FWD_SHM_DOUBLES];
   const int4 *td = task + 3 * (int64_t)(t0 + blockIdx.x);
   const int4 d0 = td[0], d1 = td[1], d2 = td[2];
   if (blk_done(st)) return;
   const int j0 = d0.x, n = d0.y, m = d0.z, fst = d0.w, vo = d1.x, bo = d1.y, slot = d1.z;
   const int64_t ro = (int64_t)(((uint64_t)(uint32_t)d2.y << 32) | (uint32_t)d2.x);
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, li = lane & 15, lk = lane >> 4;
+  const int tid = threadIdx.x, lane = tid & 63, li = lane & 15, lk = lane >> 4;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);   // (wave-uniform loop bounds)
   const int n4 = (n + 3) & ~3;
-  for (int e = tid; e < n4 * BK; e += 256) {
-    const int c = e / BK, j = e % BK;
-    tl[e] = c < n ? (b[(int64_t)(fst + c) * BK + j] + S0[(int64_t)(vo + c) * BK + j]) + S1[(int64_t)(vo + c) * BK + j]
-                  : 0.0;
-  }
-  __syncthreads();
-  const int rb = j0 + 16 * wv;
-  if (rb >= n + m) return;
-  const int r = rb + li;
-  const double *row;
-  int len;
-  if (r < n) {
-    row = FR + ro + (int64_t)r * (r + 1) / 2;
-    len = r + 1;
-  } else {
-    row = FR + ro + (int64_t)n * (n + 1) / 2 + (int64_t)(r - n) * n;
-    len = r < n + m ? n : 0;
-  }
-  const int kend = min(n4, (rb + 16 < n) ? ((rb + 16 + 3) & ~3) : n4);   // rows below n stop at their diagonal
-  f64x4 acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
-  for (int k0 = 0; k0 < kend; k0 += 4) {
-    const int k = k0 + lk;
-    const double a = k < len ? row[k] : 0.0;
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, tl[k * BK + li], acc, 0, 0, 0);
-  }
+  // the task's rows j0 + 16 u + li (u = 0..3); rows below n stop at their
+  // diagonal, rows past the front have none.  No load sits in a branch (the
+  // compiler would wait on each one): past a row's end a lane reads a
+  // clamped entry and multiplies it by 0 (the factor's entries are finite).
+  const double *row[4];
+  int len[4], lmax[4];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int rr = rb + 4 * q + lk;
+  for (int u = 0; u < 4; ++u) {
+    const int r = j0 + 16 * u + li;
+    if (r < n) {
+      row[u] = FR + ro + (int64_t)r * (r + 1) / 2;
+      len[u] = r + 1;
+    } else if (r < n + m) {
+      row[u] = FR + ro + (int64_t)n * (n + 1) / 2 + (int64_t)(r - n) * n;
+      len[u] = n;
+    } else {
+      row[u] = FR + ro;
+      len[u] = 0;
+    }
+    lmax[u] = len[u] > 0 ? len[u] - 1 : 0;
+  }
+  const int kmax = (j0 + 64 < n) ? min(n4, (j0 + 64 + 3) & ~3) : n4;
+  f64x4 ac[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) ac[u] = f64x4{0.0, 0.0, 0.0, 0.0};
+  for (int c0 = 0; c0 < kmax; c0 += FWD_KC) {
+    const int ck = min(FWD_KC, kmax - c0);
+    __syncthreads();   // the previous chunk has been used
+    // (padding rows c >= n read row n - 1 and are multiplied by 0)
+#pragma unroll 8
+    for (int e = tid; e < ck * BK; e += 256) {
+      const int c = c0 + e / BK, j = e % BK, cc = min(c, n - 1);
+      tl[e] = ((b[(int64_t)(fst + cc) * BK + j] + S0[(int64_t)(vo + cc) * BK + j]) + S1[(int64_t)(vo + cc) * BK + j]) *
+              (c < n ? 1.0 : 0.0);
+    }
+    __syncthreads();
+    // wave w: chunk entries 64 w .. 64 w + 63, 32 loads per lane in flight
+    const int kw0 = min(ck, 64 * wv), kw1 = min(ck, kw0 + 64);
+    int k0 = kw0;
+    for (; k0 + 32 <= kw1; k0 += 32) {
+      double a[8][4], bv[8];
+#pragma unroll
+      for (int h = 0; h < 8; ++h) {
+        const int kl = k0 + 4 * h + lk, k = c0 + kl;
+        bv[h] = tl[kl * BK + li];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) a[h][u] = row[u][min(k, lmax[u])] * (k < len[u] ? 1.0 : 0.0);
+      }
+#pragma unroll
+      for (int h = 0; h < 8; ++h)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) ac[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[h][u], bv[h], ac[u], 0, 0, 0);
+    }
+    for (; k0 < kw1; k0 += 4) {
+      const int kl = k0 + lk, k = c0 + kl;
+      const double bk = tl[kl * BK + li];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        ac[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(row[u][min(k, lmax[u])] * (k < len[u] ? 1.0 : 0.0), bk, ac[u],
+                                                     0, 0, 0);
+    }
+  }
+  __syncthreads();   // the last chunk has been used: its space takes the partials
+  double *red = tl;
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) red[(wv * 64 + 16 * u + 4 * q + lk) * BK + li] = ac[u][q];
+  __syncthreads();
+  for (int e = tid; e < 64 * BK; e += 256) {
+    const int rl = e / BK, j = e % BK, rr = j0 + rl;
+    const double v = ((red[rl * BK + j] + red[(64 + rl) * BK + j]) + red[(128 + rl) * BK + j]) + red[(192 + rl) * BK + j];
     if (rr < n) {
-      z[(int64_t)(fst + rr) * BK + li] = acc[q];
+      z[(int64_t)(fst + rr) * BK + j] = v;
     } else if (rr < n + m) {
-      const double base = S0[(int64_t)(vo + rr) * BK + li] + S1[(int64_t)(vo + rr) * BK + li];
-      (slot ? S1 : S0)[(int64_t)wdst[bo + (rr - n)] * BK + li] = base - acc[q];
+      const double base = S0[(int64_t)(vo + rr) * BK + j] + S1[(int64_t)(vo + rr) * BK + j];
+      (slot ? S1 : S0)[(int64_t)wdst[bo + (rr - n)] * BK + j] = base - v;
     }
   }
 }
@@ -777,22 +829,46 @@ __global__ __launch_bounds__(256) void k_blk_nd_bwd(int t0, const int4 *__restri
   if (blk_done(st)) return;
   const int c0 = d0.x, n = d0.y, m = d0.z, fst = d0.w, bo = d1.y;
   const int64_t ro = (int64_t)(((uint64_t)(uint32_t)d2.y << 32) | (uint32_t)d2.x);
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, li = lane & 15, lk = lane >> 4;
+  const int tid = threadIdx.x, lane = tid & 63, li = lane & 15, lk = lane >> 4;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);   // (wave-uniform loop bounds)
   const int cb = c0 + 16 * wv;
   if (cb >= n) return;
   const int f = n + m, c = cb + li;
-  const double *col = BC + ro + (int64_t)c * f - (int64_t)c * (c - 1) / 2 - c;   // col[rho], rho >= c
-  f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+  const bool cv = c < n;
+  // col[rho], rho >= c (a column past the front: the front's first entry)
+  const double *col = cv ? BC + ro + (int64_t)c * f - (int64_t)c * (c - 1) / 2 - c : BC + ro;
+  const int rlo = cv ? c : 0;
+  // Four independent MFMA chains, added at the end, each lane issuing its
+  // loads first.  No load is guarded by a branch (the compiler would wait on
+  // each one): outside its range a lane reads a clamped entry and multiplies
+  // it by 0 (the factor's entries and the vectors are finite).
+  auto term = [&](int k0q, double &a, double &in) {
+    const int rho = k0q + lk;
+    const bool ia = cv && rho >= c && rho < f;
+    a = col[ia ? rho : rlo] * (ia ? 1.0 : 0.0);
+    const int rz = min(rho, n - 1);
+    const int64_t rx = m > 0 ? bo + min(max(rho - n, 0), m - 1) : 0;
+    in = sg[fst + rz] * z[(int64_t)(fst + rz) * BK + li] * (rho < n ? 1.0 : 0.0) -
+         XB[rx * BK + li] * ((rho >= n && rho < f) ? 1.0 : 0.0);
+  };
+  f64x4 ac[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) ac[q] = f64x4{0.0, 0.0, 0.0, 0.0};
   const int rho0 = cb & ~3;
-#pragma unroll 4
-  for (int k0 = rho0; k0 < f; k0 += 4) {
-    const int rho = k0 + lk;
-    const double a = (c < n && rho >= c && rho < f) ? col[rho] : 0.0;
-    double in = 0.0;
-    if (rho < n) in = sg[fst + rho] * z[(int64_t)(fst + rho) * BK + li];
-    else if (rho < f) in = -XB[(int64_t)(bo + rho - n) * BK + li];
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, in, acc, 0, 0, 0);
+  int k0 = rho0;
+  for (; k0 + 16 <= f; k0 += 16) {
+    double a[4], in[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) term(k0 + 4 * q, a[q], in[q]);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) ac[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], in[q], ac[q], 0, 0, 0);
   }
+  for (; k0 < f; k0 += 4) {
+    double a, in;
+    term(k0, a, in);
+    ac[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, in, ac[0], 0, 0, 0);
+  }
+  const f64x4 acc = (ac[0] + ac[1]) + (ac[2] + ac[3]);
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int cc = cb + 4 * q + lk;
