@@ -818,12 +818,17 @@ __global__ __launch_bounds__(256) void k_blk_nd_fwd(int t0, const int4 *__restri
 // Backward: columns c of the packed lower trapezoid BC (column c holds rows
 // c .. n + m - 1): x_c = sum_rho BC(rho, c) in(rho), in = s z on the own dofs
 // and -x_B on the B part; each x[d] is also stored into every B vector that
-// holds d.  in is read from the (L2 resident) vectors, four rows of BK per step.
+// holds d.  The four waves split the task's rho range (the top levels hold
+// few, large fronts): wave w forms the partial sums of all 64 columns of the
+// task over its quarter, four 16-column blocks as independent MFMA chains
+// sharing each step's in(rho), and the partials are added in LDS in wave
+// order.  in is read from the (L2 resident) vectors.
 __global__ __launch_bounds__(256) void k_blk_nd_bwd(int t0, const int4 *__restrict__ task,
                                                     const double *__restrict__ BC, const double *__restrict__ z,
                                                     const double *__restrict__ sg, const int *__restrict__ xsc_off,
                                                     const int *__restrict__ xsc, double *XB, double *__restrict__ x,
                                                     const CgBlockState *st) {
+  __shared__ double red[4 * 64 * BK];
   const int4 *td = task + 3 * (int64_t)(t0 + blockIdx.x);
   const int4 d0 = td[0], d1 = td[1], d2 = td[2];
   if (blk_done(st)) return;
@@ -831,52 +836,73 @@ __global__ __launch_bounds__(256) void k_blk_nd_bwd(int t0, const int4 *__restri
   const int64_t ro = (int64_t)(((uint64_t)(uint32_t)d2.y << 32) | (uint32_t)d2.x);
   const int tid = threadIdx.x, lane = tid & 63, li = lane & 15, lk = lane >> 4;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);   // (wave-uniform loop bounds)
-  const int cb = c0 + 16 * wv;
-  if (cb >= n) return;
-  const int f = n + m, c = cb + li;
-  const bool cv = c < n;
-  // col[rho], rho >= c (a column past the front: the front's first entry)
-  const double *col = cv ? BC + ro + (int64_t)c * f - (int64_t)c * (c - 1) / 2 - c : BC + ro;
-  const int rlo = cv ? c : 0;
-  // Four independent MFMA chains, added at the end, each lane issuing its
-  // loads first.  No load is guarded by a branch (the compiler would wait on
-  // each one): outside its range a lane reads a clamped entry and multiplies
-  // it by 0 (the factor's entries and the vectors are finite).
-  auto term = [&](int k0q, double &a, double &in) {
-    const int rho = k0q + lk;
-    const bool ia = cv && rho >= c && rho < f;
-    a = col[ia ? rho : rlo] * (ia ? 1.0 : 0.0);
+  const int f = n + m;
+  // this lane's columns c0 + 16 u + li; col[u][rho], rho >= c (a column past
+  // the front: the front's first entry).  No load sits in a branch (the
+  // compiler would wait on each one): outside its range a lane reads a clamped
+  // entry and multiplies it by 0 (the factor's entries and the vectors are
+  // finite).
+  const double *col[4];
+  int cu[4], rlo[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int c = c0 + 16 * u + li;
+    cu[u] = c < n ? c : f;   // a column past the front takes no rows
+    col[u] = c < n ? BC + ro + (int64_t)c * f - (int64_t)c * (c - 1) / 2 - c : BC + ro;
+    rlo[u] = c < n ? c : 0;
+  }
+  const int rho0 = c0 & ~3;
+  const int qr = 4 * ((f - rho0 + 15) / 16);   // per wave, a multiple of 4
+  const int rw0 = min(f, rho0 + wv * qr), rw1 = min(f, rw0 + qr);
+  auto in_of = [&](int rho) {
     const int rz = min(rho, n - 1);
     const int64_t rx = m > 0 ? bo + min(max(rho - n, 0), m - 1) : 0;
-    in = sg[fst + rz] * z[(int64_t)(fst + rz) * BK + li] * (rho < n ? 1.0 : 0.0) -
-         XB[rx * BK + li] * ((rho >= n && rho < f) ? 1.0 : 0.0);
+    return sg[fst + rz] * z[(int64_t)(fst + rz) * BK + li] * (rho < n ? 1.0 : 0.0) -
+           XB[rx * BK + li] * ((rho >= n && rho < f) ? 1.0 : 0.0);
   };
   f64x4 ac[4];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) ac[q] = f64x4{0.0, 0.0, 0.0, 0.0};
-  const int rho0 = cb & ~3;
-  int k0 = rho0;
-  for (; k0 + 16 <= f; k0 += 16) {
-    double a[4], in[4];
+  for (int u = 0; u < 4; ++u) ac[u] = f64x4{0.0, 0.0, 0.0, 0.0};
+  int k0 = rw0;
+  for (; k0 + 16 <= rw1; k0 += 16) {
+    double a[4][4], in[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) term(k0 + 4 * q, a[q], in[q]);
+    for (int h = 0; h < 4; ++h) {
+      const int rho = k0 + 4 * h + lk;
+      in[h] = in_of(rho);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) ac[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], in[q], ac[q], 0, 0, 0);
-  }
-  for (; k0 < f; k0 += 4) {
-    double a, in;
-    term(k0, a, in);
-    ac[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, in, ac[0], 0, 0, 0);
-  }
-  const f64x4 acc = (ac[0] + ac[1]) + (ac[2] + ac[3]);
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int cc = cb + 4 * q + lk;
-    if (cc < n) {
-      const int d = fst + cc;
-      x[(int64_t)d * BK + li] = acc[q];
-      for (int p = xsc_off[d]; p < xsc_off[d + 1]; ++p) XB[(int64_t)xsc[p] * BK + li] = acc[q];
+      for (int u = 0; u < 4; ++u) {
+        const bool ia = rho >= cu[u] && rho < f;
+        a[h][u] = col[u][ia ? rho : rlo[u]] * (ia ? 1.0 : 0.0);
+      }
     }
+#pragma unroll
+    for (int h = 0; h < 4; ++h)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) ac[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[h][u], in[h], ac[u], 0, 0, 0);
+  }
+  for (; k0 < rw1; k0 += 4) {
+    const int rho = k0 + lk;
+    const double inr = in_of(rho);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const bool ia = rho >= cu[u] && rho < f;
+      ac[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(col[u][ia ? rho : rlo[u]] * (ia ? 1.0 : 0.0), inr, ac[u], 0, 0,
+                                                   0);
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) red[(wv * 64 + 16 * u + 4 * q + lk) * BK + li] = ac[u][q];
+  __syncthreads();
+  for (int e = tid; e < 64 * BK; e += 256) {
+    const int cl = e / BK, j = e % BK, cc = c0 + cl;
+    if (cc >= n) continue;
+    const double v = ((red[cl * BK + j] + red[(64 + cl) * BK + j]) + red[(128 + cl) * BK + j]) + red[(192 + cl) * BK + j];
+    const int d = fst + cc;
+    x[(int64_t)d * BK + j] = v;
+    for (int p = xsc_off[d]; p < xsc_off[d + 1]; ++p) XB[(int64_t)xsc[p] * BK + j] = v;
   }
 }
 
