@@ -577,7 +577,8 @@ __global__ __launch_bounds__(256) void k_blk_psi_apply(DevGeom g, const TS *__re
                                                        double *__restrict__ b, const CgBlockState *st) {
   extern __shared__ double sh[];
   if (blk_done(st)) return;
-  const int i = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int i = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);   // (wave-uniform loop bounds)
   const int li = lane & 15, lk = lane >> 4;
   const int n = g.nG[i], nb = (n + 15) >> 4, ldp = ld4(n);
   const int64_t go = g.g_off[i];
@@ -590,19 +591,39 @@ __global__ __launch_bounds__(256) void k_blk_psi_apply(DevGeom g, const TS *__re
   const int c0 = sub_coff[i], nci = sub_coff[i + 1] - c0;
   const TS *P = Psi + psi_off[i];
   for (int K = 0; 16 * K < nci; ++K) {
-    f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+    // Two independent MFMA chains, eight loads issued at once.  No load sits
+    // in a branch (the compiler would wait on each one): an entry past the
+    // edge is read from the basis's first entry instead; a row past the
+    // interface meets the zero padding of xs, a column past the subdomain's
+    // coarse dofs is never stored.
+    f64x4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
     const int c = 16 * K + li;
-    for (int R = wv; R < nb; R += 4) {
-      double a[4];
+    const int64_t cb = (int64_t)(c < nci ? c : 0) * ldp;
+    auto ld = [&](int R, int s) {
+      const int r = 16 * R + 4 * s + lk;
+      return (double)P[(c < nci && r < n) ? cb + r : 0];
+    };
+    int R = wv;
+    for (; R + 4 < nb; R += 8) {
+      double a[8];
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
-        const int r = 16 * R + 4 * s + lk;
-        a[s] = (c < nci && r < n) ? (double)P[(int64_t)c * ldp + r] : 0.0;
+        a[s] = ld(R, s);
+        a[4 + s] = ld(R + 4, s);
       }
 #pragma unroll
-      for (int s = 0; s < 4; ++s)
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], xs[(16 * R + 4 * s + lk) * BK + li], acc, 0, 0, 0);
+      for (int s = 0; s < 4; ++s) {
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], xs[(16 * R + 4 * s + lk) * BK + li], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[4 + s], xs[(16 * (R + 4) + 4 * s + lk) * BK + li], acc1, 0, 0,
+                                                    0);
+      }
     }
+    for (; R < nb; R += 4) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(ld(R, s), xs[(16 * R + 4 * s + lk) * BK + li], acc0, 0, 0, 0);
+    }
+    const f64x4 acc = acc0 + acc1;
     for (int w = 0; w < 4; ++w) {
       if (wv == w) {
 #pragma unroll
