@@ -663,19 +663,38 @@ __global__ __launch_bounds__(256) void k_blk_psi_correct(DevGeom g, DevCoarse cs
   __syncthreads();
   const TS *P = Psi + psi_off[i];
   for (int R = wv; R < nb; R += 4) {
-    f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+    // Two independent MFMA chains, eight loads issued at once.  No load sits
+    // in a branch (the compiler would wait on each one): an entry past the
+    // edge is read from the basis's first entry instead; a column past the
+    // subdomain's coarse dofs meets the zero padding of al, a row past the
+    // interface is never stored.
+    f64x4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
     const int r = 16 * R + li;
-    for (int K = 0; K < ncb; ++K) {
-      double a[4];
+    auto ld = [&](int K, int s) {
+      const int c = 16 * K + 4 * s + lk;
+      return (double)P[(r < n && c < nci) ? (int64_t)c * ldp + r : 0];
+    };
+    int K = 0;
+    for (; K + 1 < ncb; K += 2) {
+      double a[8];
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
-        const int c = 16 * K + 4 * s + lk;
-        a[s] = (r < n && c < nci) ? (double)P[(int64_t)c * ldp + r] : 0.0;
+        a[s] = ld(K, s);
+        a[4 + s] = ld(K + 1, s);
       }
 #pragma unroll
-      for (int s = 0; s < 4; ++s)
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], al[(16 * K + 4 * s + lk) * BK + li], acc, 0, 0, 0);
+      for (int s = 0; s < 4; ++s) {
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], al[(16 * K + 4 * s + lk) * BK + li], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[4 + s], al[(16 * (K + 1) + 4 * s + lk) * BK + li], acc1, 0, 0,
+                                                    0);
+      }
     }
+    for (; K < ncb; ++K) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(ld(K, s), al[(16 * K + 4 * s + lk) * BK + li], acc0, 0, 0, 0);
+    }
+    const f64x4 acc = acc0 + acc1;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int row = 16 * R + 4 * q + lk;
