@@ -1663,7 +1663,11 @@ void launch_precond_blk(bddc_problem *h, CgBlockState *st) {
     }
   }
   HIPCHK(hipStreamWaitEvent(h->side, h->ev_fork, 0));
-  k_blk_symv<double><<<blk_symv_grid(L), 64 * BLK_SYMV_WAVES, 0, h->side>>>(h->g, h->T64, h->d_pk, B.ru, 0.5, h->lw, B.yloc, st);
+  // T^i beside the coarse chain on about two workgroups per CU (the kernel
+  // loops over the subdomains), leaving room for the chain's small launches
+  const int tgy = (int)nblk(L.maxG, 64 * BLK_SYMV_WAVES);
+  const dim3 tgrid(std::min(L.N, std::max(2 * h->n_cu / tgy, 1)), tgy);
+  k_blk_symv<double><<<tgrid, 64 * BLK_SYMV_WAVES, 0, h->side>>>(h->g, h->T64, h->d_pk, B.ru, 0.5, h->lw, B.yloc, st);
   HIPCHK(hipEventRecord(h->ev_join, h->side));
   k_blk_psi_correct<double><<<N, 256, B.corr_shm, s>>>(h->g, h->cs, h->Psi64, h->d_psi_off, B.csol, B.wloc, st);
   HIPCHK(hipStreamWaitEvent(s, h->ev_join, 0));

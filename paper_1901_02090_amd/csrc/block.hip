@@ -488,9 +488,11 @@ __global__ __launch_bounds__(64 * BLK_SYMV_WAVES) void k_blk_symv(DevGeom g, con
                                                                   double *__restrict__ yloc, const CgBlockState *st) {
   __shared__ double xs[SYMV_CJ * 16 * BK];
   if (blk_done(st)) return;
-  const int i = blockIdx.x;
+  // subdomains i = blockIdx.x, + gridDim.x, ... (a grid narrower than N
+  // leaves CUs to the work beside it)
+  for (int i = blockIdx.x; i < g.N; i += gridDim.x) {
   const int n = g.nG[i], nb = (n + 15) >> 4, np = 4 * ((n + 3) / 4);
-  if (64 * BLK_SYMV_WAVES * (int)blockIdx.y >= n) return;   // whole workgroup past the interface
+  if (64 * BLK_SYMV_WAVES * (int)blockIdx.y >= n) continue;   // whole workgroup past the interface
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int I = BLK_SYMV_WAVES * (int)blockIdx.y + wv;   // this wave's 64-row block
@@ -550,14 +552,16 @@ __global__ __launch_bounds__(64 * BLK_SYMV_WAVES) void k_blk_symv(DevGeom g, con
       step(J + 1, tn, t);
     }
   }
-  if (!live) return;
+  if (live) {
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < 4; ++u)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int row = 64 * I + 16 * q + 4 * lk + u;
-      if (row < n) yloc[(go + row) * BK + li] = acc[u][q];
-    }
+      for (int q = 0; q < 4; ++q) {
+        const int row = 64 * I + 16 * q + 4 * lk + u;
+        if (row < n) yloc[(go + row) * BK + li] = acc[u][q];
+      }
+  }
+  }
 }
 
 // g^i = Psi^{iT} (w * R_i X) for the BK columns, added into the coarse
