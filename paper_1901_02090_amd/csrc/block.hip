@@ -724,21 +724,52 @@ __global__ __launch_bounds__(256) void k_blk_average(DevGeom g, DevCoarse cs, co
     const int64_t base = g.g_off[g.f_minus[f]] + g.f_loffm[f];
     const bool sw = g.fw_minus != nullptr;
     const double wm = sw ? g.fw_minus[f] : 0.5, wp = sw ? g.fw_plus[f] : 0.5;
+    // four steps' loads (each a chain Rmap -> own_plus -> values) issued
+    // together, added in the order of one step at a time
     double tsum = 0.0;
-    for (int a = lk; a < n; a += 4) {
+    int a = lk;
+    for (; a + 12 < n; a += 16) {
+      double vm[4], vp[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t km = (base + a + 4 * u) * BK + j, kp = (int64_t)g.own_plus[g.Rmap[base + a + 4 * u]] * BK + j;
+        vm[u] = yloc[km] + wloc[km];
+        vp[u] = yloc[kp] + wloc[kp];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) tsum += wm * vm[u] + wp * vp[u];
+    }
+    for (; a < n; a += 4) {
       const int64_t km = (base + a) * BK + j, kp = (int64_t)g.own_plus[g.Rmap[base + a]] * BK + j;
       tsum += wm * (yloc[km] + wloc[km]) + wp * (yloc[kp] + wloc[kp]);
     }
     tsum += __shfl_xor(tsum, 16, 64);
     tsum += __shfl_xor(tsum, 32, 64);
     const double corr = (csolb[(int64_t)cs.face_cofs[f] * BK + j] - tsum) / n;
-    for (int a = lk; a < n; a += 4) {
-      const int gi = g.Rmap[base + a];
-      const int64_t km = (base + a) * BK + j, kp = (int64_t)g.own_plus[gi] * BK + j;
-      const double wsm = yloc[km] + wloc[km], wsp = yloc[kp] + wloc[kp];
+    auto put = [&](int gi, double wsm, double wsp, double rr) {
       const double zz = (sw ? wm * wsm + wp * wsp : 0.5 * (wsm + wsp)) + corr;
       z[(int64_t)gi * BK + j] = zz;
-      v = fma(r[(int64_t)gi * BK + j], zz, v);
+      v = fma(rr, zz, v);
+    };
+    a = lk;
+    for (; a + 12 < n; a += 16) {
+      int gi[4];
+      double sm[4], sp[4], rv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        gi[u] = g.Rmap[base + a + 4 * u];
+        const int64_t km = (base + a + 4 * u) * BK + j, kp = (int64_t)g.own_plus[gi[u]] * BK + j;
+        sm[u] = yloc[km] + wloc[km];
+        sp[u] = yloc[kp] + wloc[kp];
+        rv[u] = r[(int64_t)gi[u] * BK + j];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) put(gi[u], sm[u], sp[u], rv[u]);
+    }
+    for (; a < n; a += 4) {
+      const int gi = g.Rmap[base + a];
+      const int64_t km = (base + a) * BK + j, kp = (int64_t)g.own_plus[gi] * BK + j;
+      put(gi, yloc[km] + wloc[km], yloc[kp] + wloc[kp], r[(int64_t)gi * BK + j]);
     }
   }
   col_partial(v, part, red);
